@@ -1,0 +1,159 @@
+"""Pins of the oracle's curve order and partition (bit-exact index work)."""
+import functools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle.grid import Grid
+from oracle.sfc import sfc_order, morton_keys
+from oracle import partition as part
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_zorder_golden_3x3():
+    rows = [list(map(int, l.split())) for l in open(os.path.join(GOLD, "zorder_l2x2.txt"))
+            if l.strip() and not l.startswith("#")]
+    g = Grid(levels=(2, 2))
+    sfc_index, pos = sfc_order(g)
+    keys = morton_keys(g)
+    assert list(sfc_index) == [r[3] for r in rows]
+    assert [int(keys[r[3]]) for r in rows] == [r[2] for r in rows]
+
+
+def _less_msb(a, b):
+    """True if the highest set bit of a is below that of b (a < b and a < a^b)."""
+    return a < b and a < (a ^ b)
+
+
+def _zcmp(p, q):
+    """Z-order comparison of two coordinate tuples without building keys: the
+    dimension whose coordinates differ in the most significant bit decides;
+    on a tie in bit level the higher dimension wins (it sits higher in the key)."""
+    msd = len(p) - 1
+    for dim in range(len(p) - 2, -1, -1):
+        if _less_msb(p[msd] ^ q[msd], p[dim] ^ q[dim]):
+            msd = dim
+    return (p[msd] > q[msd]) - (p[msd] < q[msd])
+
+
+@pytest.mark.parametrize("levels", [(3, 3), (4, 2), (2, 3, 4), (3, 1, 2, 2), (1, 5)])
+def test_zorder_matches_comparator_sort(levels):
+    """Key interleave + argsort agrees with a comparator sort on scaled coordinates."""
+    g = Grid(levels=levels)
+    nres = max(levels)
+    K = g.coords()
+    pts = [tuple(int(K[i, j]) << (nres - levels[j]) for j in range(g.d)) for i in range(g.N)]
+    order = sorted(range(g.N), key=functools.cmp_to_key(lambda a, b: _zcmp(pts[a], pts[b])))
+    sfc_index, pos = sfc_order(g)
+    assert list(sfc_index) == order
+    assert np.array_equal(pos[sfc_index], np.arange(g.N))
+
+
+def test_zorder_1d_and_reduced_is_identity():
+    for g in [Grid(npts=[1000]), Grid(levels=(7,)), Grid(levels=(6, 1, 1, 1))]:
+        sfc_index, _ = sfc_order(g)
+        assert np.array_equal(sfc_index, np.arange(g.N))
+
+
+def test_key_width_limit():
+    with pytest.raises(OverflowError):
+        sfc_order(Grid(levels=(11,) * 6))   # 66 key bits
+
+
+CASES = [(961, 8, Fraction(1, 4)), (100, 7, Fraction(1, 2)), (101, 7, Fraction(3, 2)),
+         (50, 3, Fraction(1, 1)), (17, 5, Fraction(2, 5)), (64, 4, Fraction(5, 2)),
+         (30, 2, Fraction(1, 2)), (9, 9, Fraction(1, 3)), (1000, 13, Fraction(7, 8)),
+         (23, 4, Fraction(0)), (40, 1, Fraction(1, 2))]
+
+
+@pytest.mark.parametrize("N,P,gamma", CASES)
+def test_overlap_closed_form(N, P, gamma):
+    """(ta_i, N_i) from the set union of eq. (enlarge) against the closed form
+    len = sum_{|k|<=F} ~N_{i+k} + ceil(eta ~N_{i-F-1}) + floor(eta ~N_{i+F+1})."""
+    sizes = part.piece_sizes(N, P)
+    starts = part.piece_starts(N, P)
+    assert sizes.sum() == N and sizes.max() - sizes.min() <= 1
+    assert list(sizes) == sorted(sizes, reverse=True)
+    F = math.floor(gamma)
+    eta = gamma - F
+    for i, S in enumerate(part.overlap_sets(N, P, gamma)):
+        ta, Ni, order = part.cyclic_range(S, N)
+        nl = math.ceil(eta * int(sizes[(i - F - 1) % P]))
+        nr = math.floor(eta * int(sizes[(i + F + 1) % P]))
+        ln = sum(int(sizes[(i + k) % P]) for k in range(-F, F + 1)) + nl + nr
+        if ln >= N:
+            assert (ta, Ni) == (0, N)
+        else:
+            assert Ni == ln
+            assert ta == (int(starts[(i - F) % P]) - nl) % N
+        assert set(order.tolist()) == set(S.tolist())
+
+
+@pytest.mark.parametrize("N,P", [(97, 7), (256, 8), (1000, 12), (33, 5), (64, 16)])
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_lemma_uniform_multiplicity(N, P, n):
+    """Lemma (Sec. 3.4): gamma = n/2, n <= P-1 gives multiplicity 2 gamma + 1
+    at every point and omega_i = 1/(2 gamma + 1)."""
+    if n > P - 1:
+        pytest.skip("lemma needs n <= P-1")
+    sets = part.overlap_sets(N, P, Fraction(n, 2))
+    m = part.multiplicity(sets, N)
+    assert np.all(m == n + 1)
+    assert np.allclose(part.omega(sets, m), 1.0 / (n + 1))
+
+
+@pytest.mark.parametrize("N,P,gamma", CASES)
+def test_partition_of_unity(N, P, gamma):
+    """eq. (pum) with D_i from eq. (Di): sum_i R_i^T D_i R_i = I."""
+    sets = part.overlap_sets(N, P, gamma)
+    m = part.multiplicity(sets, N)
+    acc = np.zeros(N)
+    for S, w in zip(sets, part.point_weights(sets, m)):
+        acc[S] += w
+    assert np.allclose(acc, 1.0)
+    om = part.omega(sets, m)
+    assert np.all(om <= 1.0) and np.all(om > 0)
+
+
+def test_omega_is_one_when_a_point_is_uncovered_by_others():
+    """gamma < 1/2 leaves points owned by one subdomain, so omega_i = 1."""
+    sets = part.overlap_sets(961, 8, Fraction(1, 4))
+    m = part.multiplicity(sets, 961)
+    assert np.all(part.omega(sets, m) == 1.0)
+
+
+@pytest.mark.parametrize("N,P,q", [(961, 8, 4), (248031, 256, 32), (100, 7, 3), (50, 5, 10)])
+def test_coarse_blocks(N, P, q):
+    """eq. (restr): blocks tile every piece, sizes differ by at most one with
+    the larger ones first, and R_0 has exactly one 1 per column."""
+    blocks = part.coarse_blocks(N, P, q)
+    starts = part.piece_starts(N, P)
+    sizes = part.piece_sizes(N, P)
+    assert len(blocks) == q * P
+    for i in range(P):
+        bl = blocks[i * q:(i + 1) * q]
+        assert bl[0][0] == starts[i]
+        assert sum(b[1] for b in bl) == sizes[i]
+        sz = [b[1] for b in bl]
+        assert max(sz) - min(sz) <= 1 and sz == sorted(sz, reverse=True)
+        for a, b in zip(bl, bl[1:]):
+            assert a[0] + a[1] == b[0]
+    if N <= 1000:
+        R0 = part.restriction_R0(N, P, q).toarray()
+        assert np.all(R0.sum(axis=0) == 1)
+
+
+def test_coarse_rule_values():
+    """q = 2^(floor(log2(N/P)) - 4): N/P = 2^S gives 2^(S-4) (Sec. 4.1); capped at N0 <= 16384."""
+    assert part.coarse_rule_q(256 * 64, 64) == 16
+    assert part.coarse_rule_q(1024 * 8, 8) == 64
+    assert part.coarse_rule_q(961, 8) == 4
+    assert part.coarse_rule_q(248031, 256) == 32
+    assert part.coarse_rule_q(252105, 512) == 16
+    assert part.coarse_rule_q(8258175, 4096) == 4      # rule gives 64, cap 16384/4096
+    assert part.coarse_rule_q(6885, 16) == 16 and part.coarse_rule_q(11025, 16) == 32
+    assert part.coarse_rule_q(20, 8) == 1
