@@ -1,0 +1,171 @@
+/*
+ * sfcdd.h - C ABI of the space-filling-curve two-level overlapping Schwarz
+ * solver (Griebel, Schweitzer, Troska: "A dimension-oblivious domain
+ * decomposition method based on space-filling curves") for MI355X (gfx950).
+ *
+ * The library solves A x = b (Sec. 3.1, eq. LES) for the assembled
+ * (2d+1)-point finite-difference matrix of -sum_j a_j d^2u/dx_j^2 = f on
+ * [0,1]^d with homogeneous Dirichlet data, on the anisotropic grid of level
+ * vector l (N = prod_j (2^{l_j} - 1) unknowns, eq. dof), preconditioned by
+ * the two-level Schwarz operator built from P contiguous, cyclically
+ * overlapping pieces of the Z-order curve (Sec. 3.3, Alg. 1-3).
+ *
+ * Conventions shared by every entry point
+ *  - Memory.  The library allocates no device memory.  The caller queries
+ *    sfcdd_workspace_size, allocates one device buffer of that size (any
+ *    allocator; 256-byte alignment) and passes it to sfcdd_setup; the buffer
+ *    must stay alive and untouched until sfcdd_destroy.  Vectors passed to the
+ *    compute calls are caller-owned device buffers of N doubles.  The context
+ *    owns only host memory.
+ *  - Streams.  All device work is enqueued on the HIP stream given to
+ *    sfcdd_setup (NULL = the default stream).  sfcdd_apply_precond and
+ *    sfcdd_matvec are asynchronous; sfcdd_setup and sfcdd_solve return after
+ *    their work is complete (they synchronise the stream).
+ *  - Vector order.  Vectors are in natural order (first coordinate fastest,
+ *    point k -> sum_j (k_j - 1) prod_{i<j} n_i) unless params.layout = 1, in
+ *    which case they are in curve order (entry p = point sfc_index[p]).
+ *  - Errors.  Every call returns an sfcdd_status; nothing aborts and no
+ *    exception crosses the ABI.  A message for the last failure is available
+ *    from sfcdd_last_error(ctx) (or sfcdd_last_error(NULL) for failures before
+ *    a context exists).  A failed call leaves output buffers unspecified.
+ *  - Threads.  A context may be used from one host thread at a time.
+ */
+#ifndef SFCDD_H
+#define SFCDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfcdd_ctx sfcdd_ctx;
+
+typedef enum {
+  SFCDD_OK = 0,
+  SFCDD_EINVAL = -1,     /* invalid argument (null pointer, out-of-range size) */
+  SFCDD_ENOMEM = -2,     /* workspace too small / host allocation failed       */
+  SFCDD_EDEVICE = -3,    /* a HIP runtime call failed                          */
+  SFCDD_ENOTCONV = -4,   /* solve reached max_iter before rtol                 */
+  SFCDD_EOVERFLOW = -5,  /* N >= 2^31, or d * max_j l_j > 64 key bits          */
+  SFCDD_ENOTSPD = -6     /* a local or coarse matrix was not positive definite */
+} sfcdd_status;
+
+enum { SFCDD_WEIGHT_NONE = 0, SFCDD_WEIGHT_OMEGA = 1 };
+enum { SFCDD_ADDITIVE = 0, SFCDD_BALANCED = 1 };
+enum { SFCDD_FP64 = 0, SFCDD_FP32 = 1 };
+enum { SFCDD_LOCAL_CHOLESKY = 0, SFCDD_LOCAL_INVERSE = 1 };
+enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
+
+typedef struct {
+  int32_t d;                 /* dimension, 1 <= d <= 16                                */
+  const int32_t* level;      /* host, length d: level l_j >= 1 (n_j = 2^l_j - 1), or   */
+  const int32_t* npts;       /* host, length d: explicit n_j >= 1 (h_j = 1/(n_j+1));    */
+                             /*   exactly one of level / npts is non-NULL              */
+  const double* coeff;       /* host, length d: a_j > 0, NULL = all 1                  */
+  int32_t P;                 /* number of subdomains, 1 <= P <= N                      */
+  int64_t gamma_num;         /* overlap gamma = gamma_num / gamma_den >= 0 (eq. enlarge) */
+  int64_t gamma_den;         /*   gamma_den >= 1                                       */
+  int32_t q;                 /* coarse unknowns per subdomain (eq. restr), 1..floor(N/P);
+                                0 = 2^(floor(log2(N/P)) - 4), capped at qP <= 16384    */
+  int32_t weighting;         /* SFCDD_WEIGHT_NONE or SFCDD_WEIGHT_OMEGA (eq. omegai)   */
+  int32_t variant;           /* SFCDD_ADDITIVE (eq. addSW) or SFCDD_BALANCED (eq. balSW) */
+  int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves  */
+  int32_t local_solver;      /* SFCDD_LOCAL_CHOLESKY: forward/backward substitution
+                                with the Cholesky factor; SFCDD_LOCAL_INVERSE: the
+                                explicit inverse formed from it, applied as a
+                                symmetric matrix-vector product                        */
+  int32_t layout;            /* 0 natural order, 1 curve order                          */
+} sfcdd_params;
+
+typedef struct {
+  int32_t iterations;        /* outer iterations taken                                 */
+  int32_t restarts;          /* residual replacements (iterative refinement steps)     */
+  double rel_residual;       /* ||b - A x||_2 / ||b||_2, recomputed at exit            */
+  double xi;                 /* Richardson damping used (0 for CG)                     */
+  double lambda_min;         /* Lanczos estimates of the extreme eigenvalues of        */
+  double lambda_max;         /*   C^{-1} A (Richardson with xi <= 0 only)              */
+} sfcdd_solve_info;
+
+typedef struct {
+  int64_t N;                 /* unknowns                                               */
+  int32_t P, q, N0;          /* subdomains, coarse points per subdomain, coarse size   */
+  int32_t max_Ni, min_Ni;    /* largest / smallest overlapping subdomain               */
+  int32_t tile;              /* tile edge of the packed factor layout                  */
+  int64_t sum_Ni;            /* sum_i N_i                                              */
+  int64_t factor_bytes;      /* bytes of all subdomain factor tiles                    */
+  int64_t factor_algo_bytes; /* sum_i N_i (N_i + 1) / 2 * sizeof(factor element)      */
+  int64_t coarse_bytes;      /* bytes of the coarse operator tiles                     */
+  double setup_ms[6];        /* sfc rank, neighbours, assembly, factor, coarse, total  */
+} sfcdd_info;
+
+/* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1
+ * inputs d, l, P, gamma, q).  Validates the parameters: EINVAL for sizes out
+ * of range, EOVERFLOW when N >= 2^31 or d * max_j l_j > 64. */
+sfcdd_status sfcdd_workspace_size(const sfcdd_params* params, size_t* bytes);
+
+/* Setup phase (Alg. 1): curve order of the grid points, disjoint pieces
+ * (eq. sloc), overlapping subdomains (eq. enlarge, cyclic), weights
+ * (eq. omegai), coarse blocks and A_0 = R_0 A R_0^T (eqs. restr, csm), and a
+ * Cholesky factorisation of every A_i = R_i A R_i^T and of A_0 (factor once,
+ * Sec. 3.1).  workspace_dev: device buffer of at least the queried size;
+ * hip_stream: hipStream_t or NULL.  On success *out receives a new context.
+ * ENOTSPD if a factorisation breaks down. */
+sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t bytes,
+                         void* hip_stream, sfcdd_ctx** out);
+
+/* h = C^{-1} g (Alg. 2; balanced form eq. balSW when variant = BALANCED).
+ * g_dev, h_dev: device, N doubles each, may not alias.  Asynchronous. */
+sfcdd_status sfcdd_apply_precond(sfcdd_ctx* ctx, const double* g_dev, double* h_dev);
+
+/* y = A x with the (2d+1)-point FD matrix.  Device, N doubles each, no alias. */
+sfcdd_status sfcdd_matvec(sfcdd_ctx* ctx, const double* x_dev, double* y_dev);
+
+/* Solve A x = b (Alg. 3 / preconditioned CG, Sec. 3.3).  b_dev: device, N
+ * doubles.  x_dev: device, N doubles, initial guess on entry (zero it for
+ * x0 = 0), solution on exit; may not alias b_dev.  Stops when the relative
+ * residual ||b - A x||_2 / ||b||_2 <= rtol (checked on the recursive residual
+ * and confirmed on the true residual, restarting from the current x when they
+ * disagree), or after max_iter iterations (ENOTCONV).
+ * method: SFCDD_PCG, SFCDD_FCG (flexible CG, beta = z'(r_new - r_old)/z'r_old,
+ * for the FP32-factor preconditioner) or SFCDD_RICHARDSON (x += xi C^{-1} r;
+ * xi <= 0 estimates xi = 2/(lmin + lmax) from 30 Lanczos steps).
+ * info: host, may be NULL. */
+sfcdd_status sfcdd_solve(sfcdd_ctx* ctx, const double* b_dev, double* x_dev, double rtol,
+                         int32_t max_iter, int32_t method, double xi, sfcdd_solve_info* info);
+
+/* Coefficient part of the adjoint gradient of J(u) with A(a) u = f:
+ * grad_a[j] = -lambda^T (dA/da_j) u = -(1/h_j^2) sum_k lambda_k (2 u_k - u_{k-e_j}
+ * - u_{k+e_j}) (Sec. 4 model problem with alpha = diag(a_j)).  lambda_dev, u_dev:
+ * device, N doubles; grad_a_host: host, d doubles.  Synchronous. */
+sfcdd_status sfcdd_grad_coeff(sfcdd_ctx* ctx, const double* lambda_dev, const double* u_dev,
+                              double* grad_a_host);
+
+/* Copies the partition to host arrays (each may be NULL): sfc_index[N]
+ * (natural index of curve position p), ta[P] (first curve position of
+ * Omega_i), Ni[P] (its size; Omega_i = {(ta_i + s) mod N : s < N_i}), omega[P]
+ * (eq. omegai weight actually applied), q_out (coarse points per subdomain). */
+sfcdd_status sfcdd_get_partition(sfcdd_ctx* ctx, int32_t* sfc_index_host, int64_t* ta_host,
+                                 int64_t* Ni_host, double* omega_host, int32_t* q_out);
+
+/* The same partition computed on the host alone, before any setup (no GPU
+ * needed): ta[P], Ni[P], omega[P] and q_out as in sfcdd_get_partition, each
+ * may be NULL.  Validation and error codes as sfcdd_workspace_size. */
+sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, int64_t* Ni_host,
+                                  double* omega_host, int32_t* q_out);
+
+/* Sizes and setup timings of a context. */
+sfcdd_status sfcdd_get_info(sfcdd_ctx* ctx, sfcdd_info* info);
+
+/* Releases the context's host memory.  The workspace may be freed afterwards. */
+sfcdd_status sfcdd_destroy(sfcdd_ctx* ctx);
+
+/* Message describing the last failure on ctx (or of a call without a context
+ * when ctx is NULL).  Valid until the next call on the same context. */
+const char* sfcdd_last_error(const sfcdd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFCDD_H */

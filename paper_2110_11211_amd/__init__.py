@@ -1,0 +1,265 @@
+"""MI355X-native SFC two-level overlapping Schwarz solver.
+
+Thin ctypes binding of the C ABI in include/sfcdd.h (libsfcdd.so, built for
+gfx950 by `build_lib.build()`).  The binding only marshals arguments: every
+step of setup, preconditioner application and solve runs in the library's HIP
+kernels.  PyTorch provides device memory (the workspace and the vectors) and
+the stream.  There is no CPU fallback: if the library cannot be loaded the
+import of `lib()` raises.
+
+Method: Griebel, Schweitzer, Troska, "A dimension-oblivious domain
+decomposition method based on space-filling curves" (Sec. 3.3, Alg. 1-3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from fractions import Fraction
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfcdd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EOVERFLOW, ENOTSPD = 0, -1, -2, -3, -4, -5, -6
+_STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTCONV: "ENOTCONV",
+           EOVERFLOW: "EOVERFLOW", ENOTSPD: "ENOTSPD"}
+WEIGHTING = {"none": 0, "omega": 1}
+VARIANT = {"additive": 0, "balanced": 1}
+FACTOR_DTYPE = {"fp64": 0, "fp32": 1}
+LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
+METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}
+LAYOUT = {"natural": 0, "sfc": 1}
+
+EXPORTS = ["sfcdd_workspace_size", "sfcdd_setup", "sfcdd_apply_precond", "sfcdd_matvec",
+           "sfcdd_solve", "sfcdd_grad_coeff", "sfcdd_get_partition", "sfcdd_partition_host",
+           "sfcdd_get_info", "sfcdd_destroy", "sfcdd_last_error"]
+
+
+class SfcddError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("level", ctypes.POINTER(ctypes.c_int32)),
+                ("npts", ctypes.POINTER(ctypes.c_int32)), ("coeff", ctypes.POINTER(ctypes.c_double)),
+                ("P", ctypes.c_int32), ("gamma_num", ctypes.c_int64), ("gamma_den", ctypes.c_int64),
+                ("q", ctypes.c_int32), ("weighting", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("factor_dtype", ctypes.c_int32), ("local_solver", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("xi", ctypes.c_double),
+                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("P", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("N0", ctypes.c_int32), ("max_Ni", ctypes.c_int32), ("min_Ni", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("sum_Ni", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
+                ("factor_algo_bytes", ctypes.c_int64), ("coarse_bytes", ctypes.c_int64),
+                ("setup_ms", ctypes.c_double * 6)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded C-ABI library; builds it first if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from .build_lib import build
+        build()
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.sfcdd_workspace_size.argtypes = [P(Params), P(ctypes.c_size_t)]
+    L.sfcdd_setup.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(vp)]
+    L.sfcdd_apply_precond.argtypes = [vp, vp, vp]
+    L.sfcdd_matvec.argtypes = [vp, vp, vp]
+    L.sfcdd_solve.argtypes = [vp, vp, vp, dbl, i32, i32, dbl, P(SolveInfo)]
+    L.sfcdd_grad_coeff.argtypes = [vp, vp, vp, P(dbl)]
+    L.sfcdd_get_partition.argtypes = [vp, P(i32), P(i64), P(i64), P(dbl), P(i32)]
+    L.sfcdd_partition_host.argtypes = [P(Params), P(i64), P(i64), P(dbl), P(i32)]
+    L.sfcdd_get_info.argtypes = [vp, P(Info)]
+    L.sfcdd_destroy.argtypes = [vp]
+    L.sfcdd_last_error.argtypes = [vp]
+    L.sfcdd_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, ctx=None):
+    if st != OK:
+        msg = lib().sfcdd_last_error(ctx)
+        raise SfcddError(st, msg.decode() if msg else "")
+
+
+def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q=0,
+                weighting="omega", variant="balanced", factor_dtype="fp64",
+                local_solver="cholesky", layout="natural"):
+    """Builds the sfcdd_params struct; returns (struct, keepalive)."""
+    g = Fraction(gamma)
+    d = len(levels) if levels is not None else len(npts)
+    keep = []
+    prm = Params()
+    prm.d = d
+    if levels is not None:
+        arr = (ctypes.c_int32 * d)(*[int(v) for v in levels])
+        keep.append(arr)
+        prm.level = arr
+    if npts is not None:
+        arr = (ctypes.c_int32 * d)(*[int(v) for v in npts])
+        keep.append(arr)
+        prm.npts = arr
+    if coeff is not None:
+        arr = (ctypes.c_double * d)(*[float(v) for v in coeff])
+        keep.append(arr)
+        prm.coeff = arr
+    prm.P = int(P)
+    prm.gamma_num = g.numerator
+    prm.gamma_den = g.denominator
+    prm.q = int(q)
+    prm.weighting = WEIGHTING[weighting]
+    prm.variant = VARIANT[variant]
+    prm.factor_dtype = FACTOR_DTYPE[factor_dtype]
+    prm.local_solver = LOCAL_SOLVER[local_solver]
+    prm.layout = LAYOUT[layout]
+    return prm, keep
+
+
+def workspace_size(**kw) -> int:
+    prm, keep = make_params(**kw)
+    n = ctypes.c_size_t()
+    _check(lib().sfcdd_workspace_size(ctypes.byref(prm), ctypes.byref(n)))
+    return int(n.value)
+
+
+def partition_host(**kw):
+    """(ta, Ni, omega, q) of the decomposition, computed on the host only."""
+    import numpy as np
+    prm, keep = make_params(**kw)
+    Pn = prm.P
+    ta = (ctypes.c_int64 * Pn)()
+    Ni = (ctypes.c_int64 * Pn)()
+    om = (ctypes.c_double * Pn)()
+    q = ctypes.c_int32()
+    _check(lib().sfcdd_partition_host(ctypes.byref(prm), ta, Ni, om, ctypes.byref(q)))
+    return np.array(ta[:], dtype=np.int64), np.array(Ni[:], dtype=np.int64), np.array(om[:]), int(q.value)
+
+
+class SFCSchwarz:
+    """One set-up solver context: grid, partition, factors, coarse operator.
+
+    All vectors are float64 torch tensors of length N on the context's device,
+    in natural order (first coordinate fastest) unless layout="sfc".  Work is
+    enqueued on the torch stream current at construction.
+    """
+
+    def __init__(self, levels: Optional[Sequence[int]] = None, npts: Optional[Sequence[int]] = None,
+                 coeff: Optional[Sequence[float]] = None, P: int = 1, gamma=Fraction(1, 2), q: int = 0,
+                 weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
+                 local_solver: str = "cholesky", layout: str = "natural", device="cuda:0"):
+        import torch
+        self._torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("SFCSchwarz needs a ROCm GPU device")
+        self.kw = dict(levels=levels, npts=npts, coeff=coeff, P=P, gamma=gamma, q=q, weighting=weighting,
+                       variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
+                       layout=layout)
+        prm, self._keep = make_params(**self.kw)
+        n = ctypes.c_size_t()
+        _check(lib().sfcdd_workspace_size(ctypes.byref(prm), ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            ctx = ctypes.c_void_p()
+            _check(lib().sfcdd_setup(ctypes.byref(prm), ctypes.c_void_p(self.ws.data_ptr()),
+                                     self.workspace_bytes + 256, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(ctx)), None if not ctx.value else ctx)
+        self.ctx = ctx
+        inf = Info()
+        _check(lib().sfcdd_get_info(self.ctx, ctypes.byref(inf)), self.ctx)
+        self.N = int(inf.N)
+        self.d = prm.d
+        self._info = inf
+
+    # -- helpers -----------------------------------------------------------
+    def _vec(self, t, name):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
+                or t.numel() != self.N or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor of {self.N} entries on {self.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def info(self) -> dict:
+        i = self._info
+        return {k: (list(getattr(i, k)) if k == "setup_ms" else getattr(i, k)) for k, _ in Info._fields_}
+
+    # -- operators ---------------------------------------------------------
+    def apply(self, g, out=None):
+        """h = C^{-1} g (Alg. 2 / eq. balSW)."""
+        torch = self._torch
+        h = torch.empty_like(g) if out is None else out
+        _check(lib().sfcdd_apply_precond(self.ctx, self._vec(g, "g"), self._vec(h, "h")), self.ctx)
+        return h
+
+    def matvec(self, x, out=None):
+        torch = self._torch
+        y = torch.empty_like(x) if out is None else out
+        _check(lib().sfcdd_matvec(self.ctx, self._vec(x, "x"), self._vec(y, "y")), self.ctx)
+        return y
+
+    def solve(self, b, x0=None, rtol=1e-9, max_iter=1000, method="pcg", xi=0.0, check=True):
+        """x with A x = b to relative residual rtol; returns (x, info dict)."""
+        torch = self._torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        inf = SolveInfo()
+        st = lib().sfcdd_solve(self.ctx, self._vec(b, "b"), self._vec(x, "x"), float(rtol), int(max_iter),
+                               METHOD[method], float(xi), ctypes.byref(inf))
+        if check:
+            _check(st, self.ctx)
+        info = {k: getattr(inf, k) for k, _ in SolveInfo._fields_}
+        info["status"] = st
+        return x, info
+
+    def grad_coeff(self, lam, u):
+        """dJ/da_j = -lam^T (dA/da_j) u (host list of d floats)."""
+        out = (ctypes.c_double * self.d)()
+        _check(lib().sfcdd_grad_coeff(self.ctx, self._vec(lam, "lam"), self._vec(u, "u"), out), self.ctx)
+        return [float(v) for v in out]
+
+    def partition(self) -> dict:
+        import numpy as np
+        Pn = self.kw["P"]
+        sfc = (ctypes.c_int32 * self.N)()
+        ta = (ctypes.c_int64 * Pn)()
+        Ni = (ctypes.c_int64 * Pn)()
+        om = (ctypes.c_double * Pn)()
+        q = ctypes.c_int32()
+        _check(lib().sfcdd_get_partition(self.ctx, sfc, ta, Ni, om, ctypes.byref(q)), self.ctx)
+        return {"sfc_index": np.ctypeslib.as_array(sfc).astype(np.int64), "ta": np.array(ta[:]),
+                "Ni": np.array(Ni[:]), "omega": np.array(om[:]), "q": int(q.value)}
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().sfcdd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+from .autograd import PoissonSolve, solve_poisson  # noqa: E402,F401

@@ -1,0 +1,598 @@
+// Per-iteration operators: stencil SpMV in curve order, the subdomain solves
+// of the Schwarz operator (Alg. 2), the weighted scatter-add, the coarse
+// restriction / prolongation, BLAS-1 with deterministic two-stage reductions.
+#include "common.h"
+#include "kernels.h"
+
+namespace sfcdd {
+
+// ---------------------------------------------------------------------------
+// SpMV with the (2d+1)-point FD matrix, vectors in curve order (Alg. 3 A x).
+// MODE 0: y = A x.  MODE 1: y = A x, partials of x . y.  MODE 2: y = b - A x,
+// partials of y . y.  The reductions use a fixed grid of RED_BLOCKS blocks.
+template <int MODE>
+__global__ __launch_bounds__(RED_THREADS) void k_spmv(GridDesc g, const int32_t* __restrict__ nbr,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ y,
+                                                      const double* __restrict__ b,
+                                                      double* __restrict__ partials) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  const int64_t N = g.N;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const double xp = x[p];
+    double v = g.diag * xp;
+    for (int j = 0; j < g.d; ++j) {
+      const int32_t m = nbr[(2 * j) * N + p];
+      const int32_t q = nbr[(2 * j + 1) * N + p];
+      double s = 0.0;
+      if (m >= 0) s += x[m];
+      if (q >= 0) s += x[q];
+      v -= g.c[j] * s;
+    }
+    if (MODE == 2) v = b[p] - v;
+    y[p] = v;
+    if (MODE == 1) acc += xp * v;
+    if (MODE == 2) acc += v * v;
+  }
+  if (MODE != 0) {
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+void launch_spmv(const GridDesc& g, const int32_t* nbr, const double* x, double* y, const double* b,
+                 double* partials, const double* dotv, hipStream_t s) {
+  if (b) {
+    hipLaunchKernelGGL(k_spmv<2>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, g, nbr, x, y, b,
+                       partials);
+  } else if (partials) {
+    hipLaunchKernelGGL(k_spmv<1>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, g, nbr, x, y, b,
+                       partials);
+  } else {
+    const int64_t nb = (g.N + RED_THREADS - 1) / RED_THREADS;
+    hipLaunchKernelGGL(k_spmv<0>, dim3((unsigned)(nb < 65535 * 16 ? nb : 65535 * 16)),
+                       dim3(RED_THREADS), 0, s, g, nbr, x, y, b, partials);
+  }
+  (void)dotv;
+}
+
+// ---------------------------------------------------------------------------
+// Subdomain solves d_i = A_i^{-1} R_i w by forward and backward substitution
+// with the packed tiled Cholesky factor (Sec. 3.1: factor once, then only
+// forward/backward steps; Alg. 2 first two steps).  One workgroup per
+// subdomain; R_i w (a cyclic contiguous curve range) is staged in LDS.
+// Diagonal tiles hold L_II^{-1}, so every step is a tile matrix-vector product.
+// Each wave streams whole 16-byte-per-lane row groups of the tiles.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+template <typename T>
+__device__ __forceinline__ T dotv(const typename Vec16<T>::type& a, const T* b);
+template <>
+__device__ __forceinline__ float dotv<float>(const float4& a, const float* b) {
+  const float4 y = *reinterpret_cast<const float4*>(b);
+  return a.x * y.x + a.y * y.y + a.z * y.z + a.w * y.w;
+}
+template <>
+__device__ __forceinline__ double dotv<double>(const double2& a, const double* b) {
+  const double2 y = *reinterpret_cast<const double2*>(b);
+  return a.x * y.x + a.y * y.y;
+}
+template <typename T>
+__device__ __forceinline__ void axpyv(T* acc, const typename Vec16<T>::type& a, T s);
+template <>
+__device__ __forceinline__ void axpyv<float>(float* acc, const float4& a, float s) {
+  acc[0] += a.x * s; acc[1] += a.y * s; acc[2] += a.z * s; acc[3] += a.w * s;
+}
+template <>
+__device__ __forceinline__ void axpyv<double>(double* acc, const double2& a, double s) {
+  acc[0] += a.x * s; acc[1] += a.y * s;
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
+    int64_t N, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
+    const int32_t* __restrict__ nt, const int64_t* __restrict__ off,
+    const int64_t* __restrict__ doff, const T* __restrict__ fac, const double* __restrict__ w,
+    double* __restrict__ dbuf) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VEC = Vec16<T>::n;          // elements per lane per load
+  constexpr int LPR = TS / VEC;             // lanes per tile row
+  constexpr int RPI = 64 / LPR;             // rows per wave load
+  constexpr int NGRP = TS / RPI;            // row groups per tile
+  const int b = blockIdx.x;
+  const int ntb = nt[b], n = Ni[b];
+  const int64_t t0 = ta[b];
+  extern __shared__ unsigned char smem_raw[];
+  T* y = reinterpret_cast<T*>(smem_raw);    // ntb * TS
+  T* sS = y + ntb * TS;                     // TS
+  T* red = sS + TS;                         // W * TS
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int lrow = lane / LPR, c0 = (lane % LPR) * VEC;
+  const T* F = fac + off[b] * TS2;
+
+  for (int s = tid; s < ntb * TS; s += W * 64) {
+    T v = T(0);
+    if (s < n) {
+      int64_t p = t0 + s;
+      if (p >= N) p -= N;
+      v = (T)w[p];
+    }
+    y[s] = v;
+  }
+  __syncthreads();
+
+  // forward: y_I <- L_II^{-1} (g_I - sum_{J<I} L_IJ y_J)
+  for (int I = 0; I < ntb; ++I) {
+    const T* rowI = F + tri_index(I, 0) * TS2;
+    for (int grp = wv; grp < NGRP; grp += W) {
+      const int r = grp * RPI + lrow;
+      T acc = T(0);
+#pragma unroll 4
+      for (int J = 0; J < I; ++J) {
+        const V v = *reinterpret_cast<const V*>(rowI + (int64_t)J * TS2 + r * TS + c0);
+        acc += dotv<T>(v, y + J * TS + c0);
+      }
+      for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if ((lane % LPR) == 0) sS[r] = y[I * TS + r] - acc;
+    }
+    __syncthreads();
+    const T* D = rowI + (int64_t)I * TS2;
+    for (int grp = wv; grp < NGRP; grp += W) {
+      const int r = grp * RPI + lrow;
+      const V v = *reinterpret_cast<const V*>(D + r * TS + c0);
+      T acc = dotv<T>(v, sS + c0);
+      for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if ((lane % LPR) == 0) y[I * TS + r] = acc;
+    }
+    __syncthreads();
+  }
+
+  // backward: x_I <- L_II^{-T} (y_I - sum_{K>I} L_KI^T x_K), x overwrites y
+  for (int I = ntb - 1; I >= 0; --I) {
+    T accv[VEC];
+    for (int e = 0; e < VEC; ++e) accv[e] = T(0);
+    for (int grp = wv; grp < NGRP; grp += W) {
+      const int r = grp * RPI + lrow;
+#pragma unroll 4
+      for (int K = I + 1; K < ntb; ++K) {
+        const V v = *reinterpret_cast<const V*>(F + tri_index(K, I) * TS2 + r * TS + c0);
+        axpyv<T>(accv, v, y[K * TS + r]);
+      }
+    }
+    for (int e = 0; e < VEC; ++e)
+      for (int o = LPR; o < 64; o <<= 1) accv[e] += __shfl_xor(accv[e], o, 64);
+    if (lane < LPR)
+      for (int e = 0; e < VEC; ++e) red[wv * TS + c0 + e] = accv[e];
+    __syncthreads();
+    if (tid < TS) {
+      T s = y[I * TS + tid];
+      for (int q = 0; q < W; ++q) s -= red[q * TS + tid];
+      sS[tid] = s;
+    }
+    __syncthreads();
+    for (int e = 0; e < VEC; ++e) accv[e] = T(0);
+    const T* D = F + tri_index(I, I) * TS2;
+    for (int grp = wv; grp < NGRP; grp += W) {
+      const int r = grp * RPI + lrow;
+      const V v = *reinterpret_cast<const V*>(D + r * TS + c0);
+      axpyv<T>(accv, v, sS[r]);
+    }
+    for (int e = 0; e < VEC; ++e)
+      for (int o = LPR; o < 64; o <<= 1) accv[e] += __shfl_xor(accv[e], o, 64);
+    if (lane < LPR)
+      for (int e = 0; e < VEC; ++e) red[wv * TS + c0 + e] = accv[e];
+    __syncthreads();
+    if (tid < TS) {
+      T s = T(0);
+      for (int q = 0; q < W; ++q) s += red[q * TS + tid];
+      y[I * TS + tid] = s;
+    }
+    __syncthreads();
+  }
+
+  double* out = dbuf + doff[b];
+  for (int s = tid; s < n; s += W * 64) out[s] = (double)y[s];
+}
+
+constexpr int TRSV_WAVES = 16;
+
+template <typename T>
+void launch_schwarz_trsv(int P, int64_t N, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                         const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
+                         const double* w, double* dbuf, hipStream_t s) {
+  const size_t sh = ((size_t)max_nt * TS + TS + (size_t)TRSV_WAVES * TS) * sizeof(T);
+  hipLaunchKernelGGL((k_schwarz_trsv<T, TRSV_WAVES>), dim3(P), dim3(TRSV_WAVES * 64), sh, s, N, ta,
+                     Ni, nt, off, doff, fac, w, dbuf);
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric matrix-vector product with a packed lower-tiled symmetric matrix
+// (an explicit inverse), one workgroup per stored tile, no atomics:
+// part[b][I][J] = M_IJ x_J and, for I != J, part[b][J][I] = M_IJ^T x_I;
+// y_I = sum_K part[b][I][K] is formed by k_symv_reduce in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_symv_tiles(BatchMeta bm, const T* __restrict__ M,
+                                                             const T* __restrict__ xloc,
+                                                             T* __restrict__ part) {
+  const int b = blockIdx.y;
+  const int ntb = bm.nt[b];
+  const int64_t t = blockIdx.x;
+  if (t >= (int64_t)ntb * (ntb + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+  while ((int64_t)I * (I + 1) / 2 > t) --I;
+  const int J = (int)(t - (int64_t)I * (I + 1) / 2);
+  __shared__ T sM[TS * LDS_S];
+  __shared__ T sx[2 * TS];
+  stage_tile(sM, M + (bm.off[b] + t) * TS2);
+  const T* xb = xloc + bm.xoff[b];
+  if (threadIdx.x < TS) sx[threadIdx.x] = xb[J * TS + threadIdx.x];
+  else if (threadIdx.x < 2 * TS) sx[threadIdx.x] = xb[I * TS + threadIdx.x - TS];
+  __syncthreads();
+  T* pb = part + bm.poff[b];
+  const int tid = threadIdx.x;
+  if (tid < TS) {
+    T acc = T(0);
+    for (int c = 0; c < TS; ++c) acc += sM[tid * LDS_S + c] * sx[c];
+    pb[((int64_t)I * ntb + J) * TS + tid] = acc;
+  } else if (tid < 2 * TS && I != J) {
+    const int c = tid - TS;
+    T acc = T(0);
+    for (int r = 0; r < TS; ++r) acc += sM[r * LDS_S + c] * sx[TS + r];
+    pb[((int64_t)J * ntb + I) * TS + c] = acc;
+  }
+}
+
+template <typename T>
+void launch_symv_tiles(int nb, int max_nt, const BatchMeta& bm, const T* M, const T* xloc, T* part,
+                       hipStream_t s) {
+  const int ntiles = max_nt * (max_nt + 1) / 2;
+  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(ntiles, nb), dim3(TILE_THREADS), 0, s, bm, M, xloc, part);
+}
+
+// out[b][s] = sum_K part[b][s/TS][K][s%TS] for s < n_b (fixed order over K).
+template <typename T>
+__global__ void k_symv_reduce(BatchMeta bm, const int32_t* __restrict__ n, const int64_t* __restrict__ doff,
+                              const T* __restrict__ part, double* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int ntb = bm.nt[b];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n[b]) return;
+  const int I = s / TS, r = s % TS;
+  const T* pb = part + bm.poff[b] + (int64_t)I * ntb * TS + r;
+  T acc = T(0);
+  for (int K = 0; K < ntb; ++K) acc += pb[(int64_t)K * TS];
+  out[doff[b] + s] = (double)acc;
+}
+
+template <typename T>
+void launch_symv_reduce(int nb, int max_n, const BatchMeta& bm, const int32_t* n,
+                        const int64_t* doff, const T* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_symv_reduce<T>, dim3((max_n + 255) / 256, nb), dim3(256), 0, s, bm, n, doff,
+                     part, out);
+}
+
+// xloc[b][s] = R_b w (cyclic curve range from ta_b) for s < N_b, 0 up to nt_b*TS.
+template <typename T>
+__global__ void k_gather_local(int64_t N, BatchMeta bm, const int32_t* __restrict__ ta,
+                               const int32_t* __restrict__ Ni, const double* __restrict__ w,
+                               T* __restrict__ xloc) {
+  const int b = blockIdx.y;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= bm.nt[b] * TS) return;
+  T v = T(0);
+  if (s < Ni[b]) {
+    int64_t p = (int64_t)ta[b] + s;
+    if (p >= N) p -= N;
+    v = (T)w[p];
+  }
+  xloc[bm.xoff[b] + s] = v;
+}
+
+template <typename T>
+void launch_gather_local(int nb, int64_t N, int max_nt, const BatchMeta& bm, const int32_t* ta,
+                         const int32_t* Ni, const double* w, T* xloc, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_local<T>, dim3((max_nt * TS + 255) / 256, nb), dim3(256), 0, s, N, bm,
+                     ta, Ni, w, xloc);
+}
+
+#define INST(T)                                                                                    \
+  template void launch_schwarz_trsv<T>(int, int64_t, const int32_t*, const int32_t*,               \
+                                       const int32_t*, const int64_t*, const int64_t*, int,        \
+                                       const T*, const double*, double*, hipStream_t);             \
+  template void launch_symv_tiles<T>(int, int, const BatchMeta&, const T*, const T*, T*,           \
+                                     hipStream_t);                                                 \
+  template void launch_symv_reduce<T>(int, int, const BatchMeta&, const int32_t*, const int64_t*,  \
+                                      const T*, double*, hipStream_t);                             \
+  template void launch_gather_local<T>(int, int64_t, int, const BatchMeta&, const int32_t*,        \
+                                       const int32_t*, const double*, T*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+// ---------------------------------------------------------------------------
+// h[p] = sum over subdomains i containing p of omega_i d_i[(p - ta_i) mod N]
+// (Alg. 2 last step, eq. w1levprec with D_i = omega_i I), in gather form with
+// a fixed order over i: deterministic, no floating-point atomics.  Only
+// pieces k-F-1 .. k+F+1 around p's piece k can contain p.
+__global__ void k_scatter(GridDesc g, PartDesc pd, const int32_t* __restrict__ ta,
+                          const int32_t* __restrict__ Ni, const int64_t* __restrict__ doff,
+                          const double* __restrict__ omega, const double* __restrict__ dbuf,
+                          double* __restrict__ h) {
+  const int64_t N = g.N;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    const int k = piece_of(p, pd.base, pd.rem);
+    for (int c = 0; c < pd.ncand; ++c) {
+      int i = (pd.ncand >= pd.P) ? c : k - (pd.F + 1) + c;
+      i %= pd.P;
+      if (i < 0) i += pd.P;
+      int64_t o = p - ta[i];
+      if (o < 0) o += N;
+      if (o < Ni[i]) acc += omega[i] * dbuf[doff[i] + o];
+    }
+    h[p] = acc;
+  }
+}
+
+void launch_scatter(const GridDesc& g, const PartDesc& pd, const int32_t* ta, const int32_t* Ni,
+                    const int64_t* doff, const double* omega, const double* dbuf, double* h,
+                    hipStream_t s) {
+  const int64_t nb = (g.N + 255) / 256;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)(nb < 1048576 ? nb : 1048576)), dim3(256), 0, s, g,
+                     pd, ta, Ni, doff, omega, dbuf, h);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse restriction c0 = R_0 v (eq. restr): block (i, m) is a contiguous
+// curve range; one wave per coarse unknown.
+__device__ __forceinline__ void block_range(int I, const PartDesc& pd, int64_t* start, int64_t* size) {
+  const int i = I / pd.q, m = I % pd.q;
+  const int64_t sz = pd.base + (i < pd.rem ? 1 : 0);
+  const int64_t qb = sz / pd.q, qr = sz % pd.q;
+  *start = piece_start(i, pd.base, pd.rem) + (m < qr ? m * (qb + 1) : qr * (qb + 1) + (m - qr) * qb);
+  *size = qb + (m < qr ? 1 : 0);
+}
+
+__global__ void k_restrict(PartDesc pd, const double* __restrict__ v, double* __restrict__ c0) {
+  const int I = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= pd.N0) return;
+  int64_t st, sz;
+  block_range(I, pd, &st, &sz);
+  double acc = 0.0;
+  for (int64_t e = lane; e < sz; e += 64) acc += v[st + e];
+  acc = wave_sum(acc);
+  if (lane == 0) c0[I] = acc;
+}
+
+void launch_restrict(const PartDesc& pd, const double* v, double* c0, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3((pd.N0 + 3) / 4), dim3(256), 0, s, pd, v, c0);
+}
+
+__device__ __forceinline__ int coarse_block_of(int64_t p, const PartDesc& pd) {
+  const int i = piece_of(p, pd.base, pd.rem);
+  const int64_t o = p - piece_start(i, pd.base, pd.rem);
+  const int64_t sz = pd.base + (i < pd.rem ? 1 : 0);
+  const int64_t qb = sz / pd.q, qr = sz % pd.q;
+  const int64_t big = qr * (qb + 1);
+  const int m = o < big ? (int)(o / (qb + 1)) : (int)(qr + (o - big) / qb);
+  return i * pd.q + m;
+}
+
+// Prolongation R_0^T d0 fused with the final vector combinations.
+template <int MODE>
+__global__ void k_combine(int64_t N, PartDesc pd, const double* __restrict__ d0,
+                          const double* __restrict__ a, const double* __restrict__ b,
+                          double* __restrict__ out) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const double t = d0[coarse_block_of(p, pd)];
+    if (MODE == COMB_PROLONG) out[p] = t;
+    if (MODE == COMB_ADD_PROLONG) out[p] = a[p] + t;
+    if (MODE == COMB_BAL_FINAL) out[p] = a[p] - t + b[p];
+  }
+}
+
+void launch_combine(const GridDesc& g, const PartDesc& pd, int mode, const double* d0,
+                    const double* a, const double* b, double* out, hipStream_t s) {
+  const int64_t nb0 = (g.N + 255) / 256;
+  const dim3 grid((unsigned)(nb0 < 1048576 ? nb0 : 1048576));
+  if (mode == COMB_PROLONG)
+    hipLaunchKernelGGL(k_combine<COMB_PROLONG>, grid, dim3(256), 0, s, g.N, pd, d0, a, b, out);
+  else if (mode == COMB_ADD_PROLONG)
+    hipLaunchKernelGGL(k_combine<COMB_ADD_PROLONG>, grid, dim3(256), 0, s, g.N, pd, d0, a, b, out);
+  else
+    hipLaunchKernelGGL(k_combine<COMB_BAL_FINAL>, grid, dim3(256), 0, s, g.N, pd, d0, a, b, out);
+}
+
+// ---------------------------------------------------------------------------
+// BLAS-1 with deterministic two-stage reductions (fixed grid, fixed order).
+__global__ __launch_bounds__(RED_THREADS) void k_dot(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ c,
+                                                     double* __restrict__ partials) {
+  __shared__ double sh[16];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double ai = a[i];
+    s0 += ai * b[i];
+    if (c) s1 += ai * c[i];
+  }
+  const double r0 = block_sum(s0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r0;
+  if (c) {
+    const double r1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) partials[RED_BLOCKS + blockIdx.x] = r1;
+  }
+}
+
+void launch_dot(int64_t n, const double* a, const double* b, const double* c, double* partials,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, a, b, c, partials);
+}
+
+// Second reduction stage plus the scalar recurrences of CG.
+__global__ __launch_bounds__(RED_THREADS) void k_finalize(int mode, const double* __restrict__ partials,
+                                                          double* __restrict__ S) {
+  __shared__ double sh[16];
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x) {
+    s0 += partials[i];
+    if (mode == FIN_RZ_NEXT_FLEX) s1 += partials[RED_BLOCKS + i];
+  }
+  const double r0 = block_sum(s0, sh);
+  const double r1 = (mode == FIN_RZ_NEXT_FLEX) ? block_sum(s1, sh) : 0.0;
+  if (threadIdx.x == 0) {
+    switch (mode) {
+      case FIN_PQ_ALPHA: S[S_PQ] = r0; S[S_ALPHA] = S[S_RZ] / r0; break;
+      case FIN_RR: S[S_RR] = r0; break;
+      case FIN_RZ_INIT: S[S_RZ] = r0; break;
+      case FIN_RZ_NEXT: S[S_BETA] = r0 / S[S_RZ]; S[S_RZ] = r0; break;
+      case FIN_RZ_NEXT_FLEX: S[S_BETA] = -S[S_ALPHA] * r1 / S[S_RZ]; S[S_RZ] = r0; break;
+      case FIN_BB: S[S_BB] = r0; break;
+    }
+  }
+}
+
+void launch_finalize(int mode, const double* partials, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, mode, partials, scal);
+}
+
+// x += alpha p, r -= alpha q, partials of r . r.
+__global__ __launch_bounds__(RED_THREADS) void k_update_xr(int64_t n, const double* __restrict__ S,
+                                                           double* __restrict__ x,
+                                                           double* __restrict__ r,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q,
+                                                           double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const double alpha = S[S_ALPHA];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_update_xr(int64_t n, const double* scal, double* x, double* r, const double* p,
+                      const double* q, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, scal, x, r, p, q,
+                     partials);
+}
+
+__global__ void k_update_p(int64_t n, const double* __restrict__ S, double* __restrict__ p,
+                           const double* __restrict__ z) {
+  const double beta = S[S_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+void launch_update_p(int64_t n, const double* scal, double* p, const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(2048), dim3(256), 0, s, n, scal, p, z);
+}
+
+// x += S[slot] * z
+__global__ void k_axpy_scal(int64_t n, const double* __restrict__ S, int slot,
+                            double* __restrict__ x, const double* __restrict__ z) {
+  const double a = S[slot];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += a * z[i];
+}
+
+void launch_axpy_scal(int64_t n, const double* scal, int slot, double* x, const double* z,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_scal, dim3(2048), dim3(256), 0, s, n, scal, slot, x, z);
+}
+
+// gather: out[p] = in[idx[p]];  scatter: out[idx[p]] = in[p].
+__global__ void k_permute(int64_t n, const int32_t* __restrict__ idx, const double* __restrict__ in,
+                          double* __restrict__ out, int gather) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    if (gather) out[p] = in[idx[p]];
+    else out[idx[p]] = in[p];
+  }
+}
+
+void launch_permute(int64_t n, const int32_t* idx, const double* in, double* out, int gather,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_permute, dim3(2048), dim3(256), 0, s, n, idx, in, out, gather);
+}
+
+__global__ void k_copy(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, n, a, b);
+}
+__global__ void k_zero(int64_t n, double* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0.0;
+}
+void launch_zero(int64_t n, double* a, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, n, a);
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient gradient partial sums, natural order (regular stencil):
+// partials[j][blk] = sum_k lam_k (2 u_k - u_{k-e_j} - u_{k+e_j}).
+__global__ __launch_bounds__(RED_THREADS) void k_grad_coeff(GridDesc g, const double* __restrict__ lam,
+                                                            const double* __restrict__ u,
+                                                            double* __restrict__ partials) {
+  __shared__ double sh[16];
+  double acc[MAXD];
+  for (int j = 0; j < MAXD; ++j) acc[j] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.N;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double lk = lam[k], uk = u[k];
+    for (int j = 0; j < g.d; ++j) {
+      const int64_t kj = (k / g.stride[j]) % g.n[j];
+      double v = 2.0 * uk;
+      if (kj > 0) v -= u[k - g.stride[j]];
+      if (kj < g.n[j] - 1) v -= u[k + g.stride[j]];
+      acc[j] += lk * v;
+    }
+  }
+  for (int j = 0; j < g.d; ++j) {
+    const double s = block_sum(acc[j], sh);
+    if (threadIdx.x == 0) partials[j * RED_BLOCKS + blockIdx.x] = s;
+  }
+}
+
+void launch_grad_coeff(const GridDesc& g, const double* lam, const double* u, double* partials,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_coeff, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, g, lam, u, partials);
+}
+
+__global__ void k_finalize_vec(int nvals, const double* __restrict__ partials, double* __restrict__ out) {
+  __shared__ double sh[16];
+  for (int j = 0; j < nvals; ++j) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x) s += partials[j * RED_BLOCKS + i];
+    const double r = block_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = r;
+  }
+}
+
+void launch_finalize_vec(int nvals, const double* partials, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_vec, dim3(1), dim3(RED_THREADS), 0, s, nvals, partials, out);
+}
+
+}  // namespace sfcdd

@@ -1,0 +1,151 @@
+// Device-side building blocks shared by the sfcdd kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfcdd {
+
+// Edge of the square tiles of the packed lower-triangular factor layout.
+constexpr int TS = 64;
+constexpr int TS2 = TS * TS;
+// Row stride (elements) of a tile staged in LDS; odd to spread LDS banks.
+constexpr int LDS_S = TS + 1;
+// Workgroup size of the tile kernels: 4 waves, each owning a 32x32 quadrant.
+constexpr int TILE_THREADS = 256;
+// Blocks used by the first stage of the deterministic two-stage reductions.
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<float> {
+  typedef f32x4 type;
+  // row within a 16x16 block of register r of lane group g = lane / 16
+  __device__ __forceinline__ static int row(int g, int r) { return 4 * g + r; }
+};
+template <> struct Acc<double> {
+  typedef f64x4 type;
+  __device__ __forceinline__ static int row(int g, int r) { return 4 * r + g; }
+};
+
+// One 16x16x4 MFMA step: c += a(16x4) * b(4x16).  Lane l supplies
+// a[l%16][l/16] and b[l/16][l%16].  Lane l, register r of c holds
+// C[4*(l/16) + r][l%16] for the f32 instruction and C[4*r + l/16][l%16] for
+// the f64 one (both measured on gfx950).
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Index of lower tile (I, J), J <= I, in row-major packed tile order.
+__device__ __host__ __forceinline__ int64_t tri_index(int I, int J) {
+  return (int64_t)I * (I + 1) / 2 + J;
+}
+
+// Copies a row-major TS x TS tile from global memory into LDS (stride LDS_S).
+template <typename T>
+__device__ __forceinline__ void stage_tile(T* __restrict__ lds, const T* __restrict__ g) {
+  for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
+    lds[(e / TS) * LDS_S + (e % TS)] = g[e];
+  }
+}
+
+// Accumulator of one wave: 2x2 blocks of 16x16 covering a 32x32 quadrant of
+// the 64x64 output tile.  Quadrant of wave w: rows 32*(w/2), cols 32*(w%2).
+template <typename T> struct TileAcc {
+  typename Acc<T>::type c[2][2];
+  __device__ __forceinline__ void zero() {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int r = 0; r < 4; ++r) c[a][b][r] = T(0);
+  }
+  // Row / column of register r of block (a, b) for this lane.
+  __device__ __forceinline__ static int row(int a, int r) {
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    return 32 * (w >> 1) + 16 * a + Acc<T>::row(l >> 4, r);
+  }
+  __device__ __forceinline__ static int col(int b) {
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    return 32 * (w & 1) + 16 * b + (l & 15);
+  }
+  __device__ __forceinline__ void load(const T* __restrict__ g) {  // row-major global tile
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int r = 0; r < 4; ++r) c[a][b][r] = g[row(a, r) * TS + col(b)];
+  }
+  __device__ __forceinline__ void store(T* __restrict__ g) const {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int r = 0; r < 4; ++r) g[row(a, r) * TS + col(b)] = c[a][b][r];
+  }
+  __device__ __forceinline__ void store_lds(T* __restrict__ s) const {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int r = 0; r < 4; ++r) s[row(a, r) * LDS_S + col(b)] = c[a][b][r];
+  }
+};
+
+// acc += sign * opA(A) * opB(B) for LDS tiles A, B (stride LDS_S).
+// TA: A is read transposed (math A[i][k] = sA[k][i]); TB: B is read
+// transposed (math B[k][j] = sB[j][k]).
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void tile_mma(TileAcc<T>& acc, const T* __restrict__ sA,
+                                         const T* __restrict__ sB, T sign) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i0 = 32 * (w >> 1), j0 = 32 * (w & 1);
+  const int li = l & 15, lk = l >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < TS; k0 += 4) {
+    const int k = k0 + lk;
+    T a[2], b[2];
+    for (int m = 0; m < 2; ++m) {
+      const int i = i0 + 16 * m + li;
+      a[m] = sign * (TA ? sA[k * LDS_S + i] : sA[i * LDS_S + k]);
+    }
+    for (int n = 0; n < 2; ++n) {
+      const int j = j0 + 16 * n + li;
+      b[n] = TB ? sB[j * LDS_S + k] : sB[k * LDS_S + j];
+    }
+    for (int m = 0; m < 2; ++m)
+      for (int n = 0; n < 2; ++n) acc.c[m][n] = mfma16(a[m], b[n], acc.c[m][n]);
+  }
+}
+
+// Wave-level sum (all 64 lanes receive the result).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-level sum for blockDim.x <= 1024; result valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh /* >= 16 */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  T r = T(0);
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Piece (disjoint subdomain) containing curve position p, for P pieces of
+// sizes floor(N/P)+1 (first N mod P) and floor(N/P).
+__device__ __host__ __forceinline__ int piece_of(int64_t p, int64_t base, int64_t rem) {
+  const int64_t big = rem * (base + 1);
+  return p < big ? (int)(p / (base + 1)) : (int)(rem + (p - big) / base);
+}
+__device__ __host__ __forceinline__ int64_t piece_start(int i, int64_t base, int64_t rem) {
+  return (int64_t)i * base + (i < rem ? i : rem);
+}
+
+}  // namespace sfcdd

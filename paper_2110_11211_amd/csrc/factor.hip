@@ -1,0 +1,245 @@
+// Batched dense Cholesky factorisation of the subdomain matrices and of the
+// coarse matrix (factor once, Sec. 3.1), on packed lower 64x64 tiles with
+// MFMA tile products.  Left-looking over tile columns J: one launch factors
+// the diagonal tiles (J, J) of every matrix of the batch, a second one
+// finishes the sub-diagonal tiles (I, J), I > J.  The diagonal tiles keep the
+// INVERSE of the diagonal Cholesky block, L_JJ^{-1}, so that both the panel
+// update and the substitution sweeps are tile products.
+#include "common.h"
+#include "kernels.h"
+
+namespace sfcdd {
+
+// Unblocked Cholesky of the lower part of a TS x TS LDS tile followed by the
+// inversion of the factor: on exit sX holds L^{-1} (lower), sC is clobbered.
+// A non-positive pivot sets *status to -6 and is replaced by 1.
+template <typename T>
+__device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < TS; ++k) {
+    __syncthreads();
+    if (tid < TS) {
+      T piv = sC[k * LDS_S + k];
+      if (!(piv > T(0))) {
+        if (tid == 0) atomicExch(status, -6);
+        piv = T(1);
+      }
+      const T dk = sqrt(piv);
+      if (tid >= k) sC[tid * LDS_S + k] = (tid == k) ? dk : sC[tid * LDS_S + k] / dk;
+    }
+    __syncthreads();
+    // trailing update of the lower triangle below row k
+    const int m = TS - 1 - k;
+    for (int e = tid; e < m * m; e += TILE_THREADS) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) sC[i * LDS_S + j] -= sC[i * LDS_S + k] * sC[j * LDS_S + k];
+    }
+  }
+  __syncthreads();
+  // X = L^{-1}: thread c solves L x = e_c by forward substitution.
+  if (tid < TS) {
+    const int c = tid;
+    for (int i = 0; i < TS; ++i) {
+      T v;
+      if (i < c) {
+        v = T(0);
+      } else {
+        T s = (i == c) ? T(1) : T(0);
+        for (int k = c; k < i; ++k) s -= sC[i * LDS_S + k] * sX[k * LDS_S + c];
+        v = s / sC[i * LDS_S + i];
+      }
+      sX[i * LDS_S + c] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, const int32_t* __restrict__ nt,
+                                                             const int64_t* __restrict__ off,
+                                                             T* __restrict__ fac,
+                                                             int32_t* __restrict__ status) {
+  const int b = blockIdx.x;
+  if (J >= nt[b]) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  T* F = fac + off[b] * TS2;
+  TileAcc<T> acc;
+  acc.load(F + tri_index(J, J) * TS2);
+  for (int K = 0; K < J; ++K) {
+    stage_tile(sA, F + tri_index(J, K) * TS2);
+    __syncthreads();
+    tile_mma<T, false, true>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
+    __syncthreads();
+  }
+  acc.store_lds(sA);
+  potrf_inv_tile(sA, sB, status);
+  T* D = F + tri_index(J, J) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
+    const int i = e / TS, j = e % TS;
+    D[e] = j <= i ? sB[i * LDS_S + j] : T(0);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, const int32_t* __restrict__ nt,
+                                                              const int64_t* __restrict__ off,
+                                                              T* __restrict__ fac) {
+  const int b = blockIdx.y;
+  const int I = J + 1 + blockIdx.x;
+  if (I >= nt[b]) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  T* F = fac + off[b] * TS2;
+  TileAcc<T> acc;
+  acc.load(F + tri_index(I, J) * TS2);
+  for (int K = 0; K < J; ++K) {
+    stage_tile(sA, F + tri_index(I, K) * TS2);
+    stage_tile(sB, F + tri_index(J, K) * TS2);
+    __syncthreads();
+    tile_mma<T, false, true>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+    __syncthreads();
+  }
+  acc.store_lds(sA);
+  stage_tile(sB, F + tri_index(J, J) * TS2);      // L_JJ^{-1}
+  __syncthreads();
+  TileAcc<T> out;
+  out.zero();
+  tile_mma<T, false, true>(out, sA, sB, T(1));     // L_IJ = A_IJ L_JJ^{-T}
+  out.store(F + tri_index(I, J) * TS2);
+}
+
+// The FP64 tile kernels stage two 64x65 double tiles (66.5 KB of LDS), above
+// the default 64 KB dynamic limit: raise it once per kernel.
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+void launch_potrf_diag(int J, int nb, const int32_t* nt, const int64_t* off, T* fac,
+                       int32_t* status, hipStream_t s) {
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, nt, off, fac, status);
+}
+template <typename T>
+void launch_potrf_panel(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac,
+                        hipStream_t s) {
+  if (max_nt - 1 - J <= 0) return;
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_potrf_panel<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, nt,
+                     off, fac);
+}
+
+// Column J of X = L^{-1} from the columns right of it (X L = I):
+// X_JJ = L_JJ^{-1};  X_IJ = -(sum_{K=J+1..I} X_IK L_KJ) L_JJ^{-1}, I > J.
+// L holds off-diagonal factor tiles and inverted diagonal tiles, so
+// X_II L_IJ uses the stored diagonal tile of row I directly.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_col(int J, const int32_t* __restrict__ nt,
+                                                            const int64_t* __restrict__ off,
+                                                            const T* __restrict__ L,
+                                                            T* __restrict__ X) {
+  const int b = blockIdx.y;
+  const int I = J + blockIdx.x;
+  if (I >= nt[b]) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  const T* Lb = L + off[b] * TS2;
+  T* Xb = X + off[b] * TS2;
+  if (I == J) {
+    const T* src = Lb + tri_index(J, J) * TS2;
+    T* dst = Xb + tri_index(J, J) * TS2;
+    for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) dst[e] = src[e];
+    return;
+  }
+  TileAcc<T> acc;
+  acc.zero();
+  for (int K = J + 1; K <= I; ++K) {
+    stage_tile(sA, Xb + tri_index(I, K) * TS2);
+    stage_tile(sB, Lb + tri_index(K, J) * TS2);
+    __syncthreads();
+    tile_mma<T, false, false>(acc, sA, sB, T(1));
+    __syncthreads();
+  }
+  acc.store_lds(sA);
+  stage_tile(sB, Lb + tri_index(J, J) * TS2);
+  __syncthreads();
+  TileAcc<T> out;
+  out.zero();
+  tile_mma<T, false, false>(out, sA, sB, T(-1));
+  out.store(Xb + tri_index(I, J) * TS2);
+}
+
+template <typename T>
+void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
+                      const T* L, T* X, hipStream_t s) {
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_trtri_col<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_trtri_col<T>, dim3(max_nt - J, nb), dim3(TILE_THREADS), sh, s, J, nt, off, L,
+                     X);
+}
+
+// M = X^T X = A^{-1} from X = L^{-1}:  M_IJ = sum_{K >= I} X_KI^T X_KJ, I >= J.
+// Diagonal tiles are written in full (both triangles).
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restrict__ nt,
+                                                        const int64_t* __restrict__ off,
+                                                        const T* __restrict__ X,
+                                                        T* __restrict__ M) {
+  const int b = blockIdx.y;
+  const int ntb = nt[b];
+  const int64_t t = blockIdx.x;
+  if (t >= (int64_t)ntb * (ntb + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+  while ((int64_t)I * (I + 1) / 2 > t) --I;
+  const int J = (int)(t - (int64_t)I * (I + 1) / 2);
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  const T* Xb = X + off[b] * TS2;
+  TileAcc<T> acc;
+  acc.zero();
+  for (int K = I; K < ntb; ++K) {
+    stage_tile(sA, Xb + tri_index(K, I) * TS2);
+    stage_tile(sB, Xb + tri_index(K, J) * TS2);
+    __syncthreads();
+    tile_mma<T, true, false>(acc, sA, sB, T(1));
+    __syncthreads();
+  }
+  acc.store(M + off[b] * TS2 + tri_index(I, J) * TS2);
+}
+
+template <typename T>
+void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* X, T* M,
+                  hipStream_t s) {
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_lauum<T>, sh), true);
+  (void)once;
+  const int ntiles = max_nt * (max_nt + 1) / 2;
+  hipLaunchKernelGGL(k_lauum<T>, dim3(ntiles, nb), dim3(TILE_THREADS), sh, s, nt, off, X, M);
+}
+
+#define INST(T)                                                                                    \
+  template void launch_potrf_diag<T>(int, int, const int32_t*, const int64_t*, T*, int32_t*,        \
+                                     hipStream_t);                                                 \
+  template void launch_potrf_panel<T>(int, int, int, const int32_t*, const int64_t*, T*,           \
+                                      hipStream_t);                                                \
+  template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
+                                    hipStream_t);                                                  \
+  template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace sfcdd

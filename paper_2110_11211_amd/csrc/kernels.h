@@ -1,0 +1,129 @@
+// Host-callable launchers of the sfcdd device kernels (internal interface).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfcdd {
+
+constexpr int MAXD = 16;
+
+// Grid geometry passed by value to the kernels.
+struct GridDesc {
+  int d;
+  int nres;                 // curve resolution bits
+  int64_t N;
+  int n[MAXD];              // interior points per dimension
+  int shift[MAXD];          // coordinate scaling to the finest resolution
+  int64_t stride[MAXD];     // natural-order strides (first coordinate fastest)
+  double c[MAXD];           // a_j / h_j^2
+  double inv_h2[MAXD];      // 1 / h_j^2
+  double diag;              // sum_j 2 c_j
+};
+
+// Partition geometry passed by value.
+struct PartDesc {
+  int P, q, N0;
+  int64_t base, rem;        // piece sizes floor(N/P) (+1 for the first rem)
+  int F;                    // floor(gamma)
+  int ncand;                // subdomains that may cover a piece's points
+};
+
+// ---- setup ------------------------------------------------------------
+void launch_sfc_rank(const GridDesc& g, int32_t* pos, int32_t* sfc_index, hipStream_t s);
+void launch_build_nbr(const GridDesc& g, const int32_t* pos, const int32_t* sfc_index,
+                      int32_t* nbr, hipStream_t s);
+template <typename T>
+void launch_assemble_local(const GridDesc& g, int P, const int32_t* ta, const int32_t* Ni,
+                           const int32_t* nt, const int64_t* fac_off, const int32_t* nbr,
+                           int max_nt, T* fac, hipStream_t s);
+void launch_coarse_counts(const GridDesc& g, const PartDesc& pd, int j, const int32_t* nbr,
+                          int32_t* cnt, hipStream_t s);
+void launch_coarse_accumulate(int64_t ntiles_elems, double cj, const int32_t* cnt, double* A0,
+                              hipStream_t s);
+void launch_coarse_pad(int N0, int nt0, double* A0, hipStream_t s);
+
+// ---- batched tiled Cholesky, inversion ----------------------------------
+template <typename T>
+void launch_potrf_diag(int J, int nb, const int32_t* nt, const int64_t* off, T* fac,
+                       int32_t* status, hipStream_t s);
+template <typename T>
+void launch_potrf_panel(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac,
+                        hipStream_t s);
+template <typename T>
+void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
+                      const T* L, T* X, hipStream_t s);
+template <typename T>
+void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* X, T* M,
+                  hipStream_t s);
+
+// ---- per-iteration operators ---------------------------------------------
+void launch_spmv(const GridDesc& g, const int32_t* nbr, const double* x, double* y,
+                 const double* b /* y = b - A x when non-null */, double* partials /* dot */,
+                 const double* dotv /* partial sums of dotv . y when non-null */, hipStream_t s);
+template <typename T>
+void launch_schwarz_trsv(int P, int64_t N, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                         const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
+                         const double* w, double* dbuf, hipStream_t s);
+// Per-matrix offsets of a batch of packed tiled matrices: tile count nt,
+// first tile, first element of the padded local vector, first partial.
+struct BatchMeta {
+  const int32_t* nt;
+  const int64_t* off;
+  const int64_t* xoff;
+  const int64_t* poff;
+};
+template <typename T>
+void launch_symv_tiles(int nb, int max_nt, const BatchMeta& bm, const T* M, const T* xloc, T* part,
+                       hipStream_t s);
+template <typename T>
+void launch_symv_reduce(int nb, int max_n, const BatchMeta& bm, const int32_t* n,
+                        const int64_t* doff, const T* part, double* out, hipStream_t s);
+template <typename T>
+void launch_gather_local(int nb, int64_t N, int max_nt, const BatchMeta& bm, const int32_t* ta,
+                         const int32_t* Ni, const double* w, T* xloc, hipStream_t s);
+void launch_scatter(const GridDesc& g, const PartDesc& pd, const int32_t* ta, const int32_t* Ni,
+                    const int64_t* doff, const double* omega, const double* dbuf, double* h,
+                    hipStream_t s);
+void launch_restrict(const PartDesc& pd, const double* v, double* c0, hipStream_t s);
+// h = y + (prolong d0) ... see apply.hip for the exact combination modes
+void launch_combine(const GridDesc& g, const PartDesc& pd, int mode, const double* d0,
+                    const double* a, const double* b, double* out, hipStream_t s);
+
+// ---- BLAS-1 and scalars ---------------------------------------------------
+void launch_dot(int64_t n, const double* a, const double* b, const double* c, double* partials,
+                hipStream_t s);
+void launch_finalize(int mode, const double* partials, double* scal, hipStream_t s);
+void launch_update_xr(int64_t n, const double* scal, double* x, double* r, const double* p,
+                      const double* q, double* partials, hipStream_t s);
+void launch_update_p(int64_t n, const double* scal, double* p, const double* z, hipStream_t s);
+void launch_axpy_scal(int64_t n, const double* scal, int slot, double* x, const double* z,
+                      hipStream_t s);
+void launch_permute(int64_t n, const int32_t* idx, const double* in, double* out, int gather,
+                    hipStream_t s);
+void launch_grad_coeff(const GridDesc& g, const double* lam, const double* u, double* partials,
+                       hipStream_t s);
+void launch_finalize_vec(int nvals, const double* partials, double* out, hipStream_t s);
+void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
+void launch_zero(int64_t n, double* a, hipStream_t s);
+
+// Scalar slots of the solver's device scalar array.
+enum {
+  S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZQ, S_BB, S_XI, S_TMP, S_COUNT = 16
+};
+// Finalize modes.
+enum {
+  FIN_PQ_ALPHA = 0,   // S_PQ = sum; S_ALPHA = S_RZ / S_PQ
+  FIN_RR,             // S_RR = sum
+  FIN_RZ_INIT,        // S_RZ = sum
+  FIN_RZ_NEXT,        // rz = sum; S_BETA = rz / S_RZ; S_RZ = rz
+  FIN_RZ_NEXT_FLEX,   // rz = sum0, zq = sum1; S_BETA = -S_ALPHA zq / S_RZ; S_RZ = rz
+  FIN_BB              // S_BB = sum
+};
+// Combine modes of launch_combine.
+enum {
+  COMB_PROLONG = 0,          // out = R0^T d0
+  COMB_ADD_PROLONG,          // out = a + R0^T d0
+  COMB_BAL_FINAL             // out = a - R0^T d0 + b      (y - F A y + F g)
+};
+
+}  // namespace sfcdd

@@ -1,0 +1,178 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: index and partition work bit-exact; FP64 operators within 1e-12
+(relative 2-norm, well above the ~1e-15 rounding of either side and far
+below any plausible indexing or sign error); FP32-factor operators within
+2e-4 (tens of FP32 ulps amplified by the local condition numbers, which stay
+below ~1e3 at these sizes); solutions within 1e-9 of the exact DST-I solution
+(solved to rtol 1e-12)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+from seeded_inputs import uniform_pm1, workloads
+from oracle.grid import Grid
+from oracle.schwarz import OracleSchwarz
+from oracle import exact, solvers
+from oracle import grad as ograd
+from oracle.sfc import sfc_order
+
+from gpu_common import DEV, dvec, host, relerr, announce
+
+pytestmark = pytest.mark.gpu
+
+import paper_2110_11211_amd as m
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-4
+
+SMALL = [  # levels, P, gamma
+    ((5, 5), 8, Fraction(1, 4)),       # the d=2 workload
+    ((4, 3), 5, Fraction(1, 2)),
+    ((3, 4, 2), 7, Fraction(3, 4)),
+    ((6,), 4, Fraction(1, 1)),
+    ((3, 3), 3, Fraction(5, 2)),       # every subdomain is the whole grid
+    ((4, 4), 6, Fraction(0)),          # no overlap
+    ((2, 3, 2, 2), 9, Fraction(1, 3)),
+    ((7, 2), 11, Fraction(1, 2)),      # ragged subdomains (N_i not multiples of 64)
+]
+
+
+def _solver(levels, P, gamma, **kw):
+    return m.SFCSchwarz(levels=levels, P=P, gamma=gamma, **kw)
+
+
+@pytest.mark.parametrize("levels,P,gamma", SMALL)
+def test_sfc_index_and_partition_bit_exact(levels, P, gamma):
+    announce("partition", levels, P, gamma)
+    S = _solver(levels, P, gamma)
+    part = S.partition()
+    O = OracleSchwarz(Grid(levels=levels), P, gamma, factor=False)
+    assert np.array_equal(part["sfc_index"], O.sfc_index)
+    assert np.array_equal(part["ta"], O.ta) and np.array_equal(part["Ni"], O.Ni)
+    assert np.array_equal(part["omega"], O.omega) and part["q"] == O.q
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+def test_sfc_index_full_size(name):
+    w = workloads()[name]
+    announce("sfc_index", name)
+    S = _solver(w.levels[0], w.P, w.gamma, factor_dtype="fp32")
+    sfc = S.partition()["sfc_index"]
+    ref, _ = sfc_order(Grid(levels=w.levels[0]))
+    assert np.array_equal(sfc, ref)
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("levels,P,gamma", SMALL[:4])
+def test_matvec(levels, P, gamma):
+    announce("matvec", levels, P, gamma)
+    g = Grid(levels=levels, coeff=[0.5 + j for j in range(len(levels))])
+    S = m.SFCSchwarz(levels=levels, coeff=g.a, P=P, gamma=gamma)
+    x = uniform_pm1(3, g.N)
+    y = host(S.matvec(dvec(x)))
+    assert relerr(y, g.matrix() @ x) <= FP64_TOL
+
+
+VARIANTS = [("balanced", "omega"), ("additive", "omega"), ("additive", "none"), ("balanced", "none")]
+
+
+@pytest.mark.parametrize("local", ["cholesky", "inverse"])
+@pytest.mark.parametrize("variant,weighting", VARIANTS)
+@pytest.mark.parametrize("levels,P,gamma", SMALL)
+def test_apply_fp64(levels, P, gamma, variant, weighting, local):
+    announce("apply64", levels, P, gamma, variant, weighting, local)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma, weighting=weighting, variant=variant)
+    S = _solver(levels, P, gamma, weighting=weighting, variant=variant, local_solver=local)
+    r = uniform_pm1(7, g.N)
+    h = host(S.apply(dvec(r)))
+    assert relerr(h, O.apply(r)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("local", ["cholesky", "inverse"])
+@pytest.mark.parametrize("levels,P,gamma", SMALL)
+def test_apply_fp32_factors(levels, P, gamma, local):
+    announce("apply32", levels, P, gamma, local)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma)
+    S = _solver(levels, P, gamma, factor_dtype="fp32", local_solver=local)
+    r = uniform_pm1(8, g.N)
+    h = host(S.apply(dvec(r)))
+    assert relerr(h, O.apply(r)) <= FP32_TOL
+
+
+def test_apply_sfc_layout_and_determinism():
+    levels, P, gamma = (5, 4, 3), 13, Fraction(1, 2)
+    announce("layout", levels)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma)
+    S = _solver(levels, P, gamma, layout="sfc")
+    r = uniform_pm1(9, g.N)
+    rs = r[O.sfc_index]
+    h1 = host(S.apply(dvec(rs)))
+    h2 = host(S.apply(dvec(rs)))
+    assert np.array_equal(h1, h2)                     # no atomics: bitwise reproducible
+    assert relerr(h1, O.apply_s(rs)) <= FP64_TOL
+
+
+def test_pcg_c1_iterations_and_solution():
+    w = workloads()["c1"]
+    announce("pcg c1")
+    g = Grid(levels=w.levels[0])
+    O = OracleSchwarz(g, w.P, w.gamma)
+    f = w.rhs()
+    _, it_o, _ = solvers.pcg(O.A_nat, f, O.apply, rtol=w.rtol)
+    S = _solver(w.levels[0], w.P, w.gamma)
+    x, info = S.solve(dvec(f), rtol=w.rtol)
+    assert abs(info["iterations"] - it_o) <= 1
+    assert info["rel_residual"] <= w.rtol
+    xs = exact.solve(g, f)
+    assert relerr(host(x), xs) <= 1e-8
+
+
+@pytest.mark.parametrize("fdtype,local,method", [("fp64", "cholesky", "pcg"), ("fp64", "inverse", "pcg"),
+                                                 ("fp32", "cholesky", "fcg"), ("fp32", "inverse", "fcg")])
+@pytest.mark.parametrize("levels,P,gamma", [((5, 5), 8, Fraction(1, 4)), ((4, 3, 3), 10, Fraction(1, 2)),
+                                            ((3, 2, 2, 3), 6, Fraction(1, 4))])
+def test_solve_matches_exact(levels, P, gamma, fdtype, local, method):
+    announce("solve", levels, P, gamma, fdtype, local, method)
+    g = Grid(levels=levels)
+    f = uniform_pm1(4, g.N)
+    S = _solver(levels, P, gamma, factor_dtype=fdtype, local_solver=local)
+    x, info = S.solve(dvec(f), rtol=1e-12, method=method)
+    assert relerr(host(x), exact.solve(g, f)) <= 1e-9
+
+
+def test_richardson_fixed_xi_matches_oracle_count():
+    levels, P, gamma = (4, 4), 6, Fraction(1, 2)
+    announce("richardson")
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma)
+    lmin, lmax = solvers.dense_spectrum(O.A_nat.toarray(), O.dense_preconditioner())
+    xi, _ = solvers.optimal_damping(lmin, lmax)
+    f = uniform_pm1(5, g.N)
+    _, it_o = solvers.richardson(O.A_nat, f, O.apply, xi, rtol=1e-8)
+    S = _solver(levels, P, gamma)
+    x, info = S.solve(dvec(f), rtol=1e-8, method="richardson", xi=xi, max_iter=5000)
+    assert abs(info["iterations"] - it_o) <= 1
+    x2, info2 = S.solve(dvec(f), rtol=1e-8, method="richardson", xi=0.0, max_iter=5000)
+    assert abs(info2["lambda_max"] - lmax) <= 1e-3 * lmax
+    assert info2["iterations"] <= 1.5 * it_o + 2
+    assert relerr(host(x2), exact.solve(g, f)) <= 1e-6
+
+
+def test_grad_coeff_matches_oracle():
+    levels, coeff = (4, 3, 3), (0.3, 2.0, 5.0)
+    announce("grad")
+    g = Grid(levels=levels, coeff=coeff)
+    u = uniform_pm1(1, g.N)
+    lam = uniform_pm1(2, g.N)
+    S = m.SFCSchwarz(levels=levels, coeff=coeff, P=4, gamma=Fraction(1, 2))
+    ga = S.grad_coeff(dvec(lam), dvec(u))
+    ref = [-(g.inv_h2[j]) * float(lam @ (g.second_difference(j) @ u)) for j in range(g.d)]
+    assert np.allclose(ga, ref, rtol=1e-12, atol=0)

@@ -1,0 +1,97 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared entry
+point, validates its parameters, and its host-side partition (eqs. sloc,
+enlarge, omegai, q rule) equals the oracle's bit for bit."""
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import paper_2110_11211_amd as m
+from seeded_inputs import workloads
+from oracle.grid import Grid
+from oracle import partition as part
+from oracle.schwarz import OracleSchwarz
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sfcdd.h")
+
+
+def test_library_exports_every_declared_symbol():
+    names = re.findall(r"\b(sfcdd_[a-z_]+)\s*\(", open(HDR).read())
+    names = sorted(set(names))
+    assert len(names) >= 11
+    L = m.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(m.EXPORTS) == set(names)
+
+
+def _oracle_partition(levels, P, gamma, weighting="omega"):
+    g = Grid(levels=levels)
+    sets = part.overlap_sets(g.N, P, gamma)
+    rng = [part.cyclic_range(S, g.N) for S in sets]
+    mult = part.multiplicity(sets, g.N)
+    om = part.omega(sets, mult) if weighting == "omega" else np.ones(P)
+    return (np.array([r[0] for r in rng]), np.array([r[1] for r in rng]), om,
+            part.coarse_rule_q(g.N, P))
+
+
+@pytest.mark.parametrize("levels,P,gamma", [
+    ((5, 5), 8, Fraction(1, 4)), ((7, 6, 5), 256, Fraction(1, 2)),
+    ((3, 3, 3, 3, 3, 4), 512, Fraction(1, 4)), ((4, 3), 5, Fraction(3, 2)), ((3,), 7, Fraction(5, 2)),
+    ((4, 4), 9, Fraction(2, 3)), ((2, 2, 2), 27, Fraction(0)), ((6, 2), 100, Fraction(7, 3)),
+    ((5, 4, 3), 13, Fraction(1, 7)), ((3, 3), 2, Fraction(1, 2)), ((4,), 15, Fraction(1))])
+def test_partition_host_matches_oracle(levels, P, gamma):
+    ta, Ni, om, q = m.partition_host(levels=levels, P=P, gamma=gamma)
+    ota, oNi, oom, oq = _oracle_partition(levels, P, gamma)
+    assert np.array_equal(ta, ota) and np.array_equal(Ni, oNi)
+    assert np.array_equal(om, oom) and q == oq
+
+
+def test_partition_host_ct_layer():
+    w = workloads()["c4"]
+    for lv in w.levels[::7]:
+        ta, Ni, om, q = m.partition_host(levels=lv, P=w.P, gamma=w.gamma)
+        ota, oNi, oom, oq = _oracle_partition(lv, w.P, w.gamma)
+        assert np.array_equal(ta, ota) and np.array_equal(Ni, oNi)
+        assert np.array_equal(om, oom) and q == oq
+
+
+@pytest.mark.slow
+def test_partition_host_large_grid():
+    w = workloads()["c5"]
+    ta, Ni, om, q = m.partition_host(levels=w.levels[0], P=w.P, gamma=w.gamma)
+    ota, oNi, oom, oq = _oracle_partition(w.levels[0], w.P, w.gamma)
+    assert np.array_equal(ta, ota) and np.array_equal(Ni, oNi)
+    assert np.array_equal(om, oom) and q == oq == 4
+    assert Ni.min() == 2520 and Ni.max() == 2522
+
+
+def test_partition_host_weighting_none_and_explicit_q():
+    ta, Ni, om, q = m.partition_host(levels=(5, 5), P=8, gamma=Fraction(1, 2), weighting="none", q=3)
+    assert np.all(om == 1.0) and q == 3
+
+
+def test_partition_host_1d_npts():
+    ta, Ni, om, q = m.partition_host(npts=[256 * 16], P=16, gamma=Fraction(1, 2), q=16)
+    S = OracleSchwarz(Grid(npts=[256 * 16]), 16, Fraction(1, 2), q=16, factor=False)
+    assert np.array_equal(ta, S.ta) and np.array_equal(Ni, S.Ni) and np.allclose(om, 0.5)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(levels=(3, 3), P=0), m.EINVAL), (dict(levels=(3, 3), P=50), m.EINVAL),
+    (dict(levels=(3, 3), P=4, gamma=Fraction(-1, 2)), m.EINVAL),
+    (dict(levels=(3, 3), P=4, q=20), m.EINVAL), (dict(levels=(11,) * 6, P=4), m.EOVERFLOW),
+    (dict(levels=(16, 16), P=4), m.EOVERFLOW), (dict(levels=(0, 3), P=4), m.EINVAL),
+    (dict(levels=(3, 3), P=4, coeff=(1.0, -1.0)), m.EINVAL)])
+def test_invalid_parameters(kw, code):
+    with pytest.raises(m.SfcddError) as e:
+        m.workspace_size(**kw)
+    assert e.value.status == code
+
+
+def test_workspace_grows_with_factor_precision():
+    a = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp32")
+    b = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp64")
+    assert b > a > 1.9e9
