@@ -1,0 +1,233 @@
+"""Benchmark: time to a 1e-9 solve on the d=3 level (7,6,5) grid, one MI355X.
+
+Workload (synthetic, seeded): N = 127*63*31 = 248,031 unknowns, 7-point FD
+Laplacian, f iid U[-1,1) from splitmix64 seed 2, Z-order curve, P = 256
+subdomains, gamma = 1/2 (100% overlap), q = 32 (N0 = 8192), omega-weighted
+balanced two-level Schwarz preconditioner, outer PCG (flexible CG with FP32
+factors) in FP64 to a relative residual of 1e-9.
+
+One step = the whole hot path on a fresh right-hand side: setup (curve order,
+partition, neighbour table, local assembly, batched Cholesky of the 256 local
+matrices, coarse matrix and its inverse) + the outer solve.  The headline is
+the FP32-factor path; the all-FP64 path is timed beside it.  Inputs are
+resident in HBM before the timed region; the workspace is allocated once.
+
+Prints one JSON line (see the design notes for the field definitions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--local", default="cholesky", choices=["cholesky", "inverse"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=12, help="subdomains in the CPU oracle sample")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + steps of the headline path only (for rocprofv3)")
+    return ap.parse_args()
+
+
+def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_kernel=True):
+    """Times `steps` full setup+solve passes; returns a dict of measurements."""
+    import torch
+    import paper_2110_11211_amd as m
+    kw = dict(levels=list(w.levels[0]), P=w.P, gamma=w.gamma, factor_dtype=fdtype, local_solver=local)
+    nbytes = m.workspace_size(**kw)
+    key = (fdtype, local)
+    if key not in ws_cache:
+        ws_cache.clear()
+        torch.cuda.empty_cache()
+        ws_cache[key] = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda:0")
+    ws = ws_cache[key]
+    method = "fcg" if fdtype == "fp32" else "pcg"
+    times, setups, solves, iters = [], [], [], []
+    x = None
+    ktimes = None
+    S = None
+    for k in range(warmup + steps):
+        timed = k >= warmup
+        if S is not None:
+            S.close()
+            S = None
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        S = m.SFCSchwarz(device="cuda:0", workspace=ws, **kw)
+        e1.record()
+        if timed and prof_kernel:
+            S.set_profiling(True)
+        x, info = S.solve(f_dev, rtol=w.rtol, max_iter=500, method=method)
+        e2.record()
+        torch.cuda.synchronize()
+        if timed:
+            times.append(e0.elapsed_time(e2))
+            setups.append(e0.elapsed_time(e1))
+            solves.append(e1.elapsed_time(e2))
+            iters.append(info["iterations"])
+            if prof_kernel:
+                kt = {kk: S.kernel_time(kk) for kk in ("local_solve", "scatter", "spmv", "coarse")}
+                ktimes = kt if ktimes is None else {kk: (ktimes[kk][0] + kt[kk][0], ktimes[kk][1] + kt[kk][1])
+                                                   for kk in kt}
+                S.set_profiling(False)
+    sinfo = S.info()
+    S.close()
+    return {"ms": sorted(times)[len(times) // 2], "ms_min": min(times), "setup_ms": sorted(setups)[len(setups) // 2],
+            "solve_ms": sorted(solves)[len(solves) // 2], "iterations": iters[-1], "info": sinfo,
+            "kernels": ktimes, "x": x, "rel_residual": info["rel_residual"], "restarts": info["restarts"]}
+
+
+def cpu_baseline(w, iterations, nsample):
+    """The oracle (plain FP64 NumPy/SciPy, untuned) on a bounded sample of the
+    same workload, extrapolated to one full setup + solve."""
+    import numpy as np
+    import scipy.linalg as sla
+    from oracle.grid import Grid
+    from oracle.schwarz import OracleSchwarz
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    g = Grid(levels=w.levels[0])
+    t = time.perf_counter()
+    O = OracleSchwarz(g, w.P, w.gamma, factor=False)       # index work, A, A_0 (full)
+    t_index = time.perf_counter() - t
+    t = time.perf_counter()
+    coarse = sla.cho_factor(O.A0, lower=True)                # full coarse factorisation
+    t_coarse = time.perf_counter() - t
+    idx = np.linspace(0, w.P - 1, nsample).astype(int)
+    t = time.perf_counter()
+    facs = {i: sla.cho_factor(O.local_matrix(i), lower=True) for i in idx}
+    t_fac = (time.perf_counter() - t) / nsample
+    f = w.rhs()
+    gs = O.to_s(f)
+    t = time.perf_counter()
+    for i in idx:
+        sla.cho_solve(facs[i], gs[O.orders[i]])
+    t_loc = (time.perf_counter() - t) / nsample
+    t = time.perf_counter()
+    for _ in range(4):
+        sla.cho_solve(coarse, O.R0 @ gs)
+    t_csolve = (time.perf_counter() - t) / 4
+    t = time.perf_counter()
+    for _ in range(6):
+        O.A @ gs
+    t_spmv = (time.perf_counter() - t) / 6
+    setup = t_index + t_coarse + w.P * t_fac
+    per_iter = w.P * t_loc + 2 * t_csolve + 3 * t_spmv
+    total_ms = 1e3 * (setup + iterations * per_iter)
+    return {"value": total_ms, "unit": "ms", "cores": int(cores), "kind": "oracle",
+            "sample": f"{nsample} of {w.P} local Cholesky factorisations and solves timed and scaled by "
+                      f"{w.P}; index work, coarse factorisation, coarse solves and SpMV timed in full; "
+                      f"{iterations} balanced-PCG iterations (the GPU FP64 count)",
+            "setup_s": setup, "per_iteration_s": per_iter}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+              f"(the solver's sharding across GPUs is design-only).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2110_11211_amd as m
+    from seeded_inputs import workloads
+    m.lib()
+    w = workloads()["c2"]
+    f_dev = torch.tensor(w.rhs(), dtype=torch.float64, device="cuda:0")
+    ws_cache = {}
+    head = run_path(w, f_dev, "fp32", args.local, args.steps, args.warmup, ws_cache)
+    if args.profile_only:
+        print(json.dumps({"profile_only": True, "ms": head["ms"]}), flush=True)
+        return
+    f64 = None
+    if not args.skip_fp64:
+        f64 = run_path(w, f_dev, "fp64", args.local, max(2, args.steps // 2), args.warmup, ws_cache)
+    ws_cache.clear()
+
+    # accuracy of the headline solution against the exact DST-I solution
+    from oracle.grid import Grid
+    from oracle import exact
+    xs = exact.solve(Grid(levels=w.levels[0]), w.rhs())
+    xh = head["x"].cpu().numpy()
+    err = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
+
+    info = head["info"]
+    es = 4
+    sumN = info["sum_Ni"]
+    N = info["N"]
+    d = len(w.levels[0])
+    if args.local == "cholesky":
+        local_bytes = 2 * info["factor_algo_bytes"] + 16 * sumN     # two sweeps over the triangle
+    else:
+        local_bytes = info["factor_algo_bytes"] + 16 * sumN         # one pass over the inverse
+    ms_local, n_local = head["kernels"]["local_solve"]
+    avg_local = ms_local / max(n_local, 1)
+    ms_spmv, n_spmv = head["kernels"]["spmv"]
+    avg_spmv = ms_spmv / max(n_spmv, 1)
+    spmv_bytes = (16 + 8 * d) * N
+    gbs_local = local_bytes / (avg_local * 1e-3) / 1e9
+    gbs_spmv = spmv_bytes / (avg_spmv * 1e-3) / 1e9
+    # the dominant kernel class over a whole step
+    solve_local_ms = ms_local / args.steps
+    factor_ms = info["setup_ms"][3]
+    nt = [(n + 63) // 64 for n in [info["max_Ni"]]]
+    roofline = {"kernel": "k_schwarz_trsv (FP32 factors)" if args.local == "cholesky" else "k_symv_tiles (FP32 inverse)",
+                "bound": "hbm", "achieved": round(gbs_local, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs_local / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": avg_local, "algorithmic_bytes_per_launch": local_bytes,
+                "local_solve_ms_per_step": solve_local_ms, "factor_ms_per_step": factor_ms}
+    out = {
+        "metric": "time-to-1e-9 solve & GB/s of SpMV+Schwarz: FP32-precond vs FP64, 1 GPU",
+        "value": round(head["ms"], 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 local factors/solves, f64 outer", "data": "synthetic",
+        "config": {"workload": w.name, "levels": list(w.levels[0]), "N": N, "P": w.P,
+                   "gamma": str(w.gamma), "q": info["q"], "N0": info["N0"], "rtol": w.rtol,
+                   "variant": "balanced", "weighting": "omega", "local_solver": args.local,
+                   "outer": "flexible CG (fp32) / PCG (fp64)"},
+        "headline": {"setup_ms": round(head["setup_ms"], 3), "solve_ms": round(head["solve_ms"], 3),
+                     "ms_min": round(head["ms_min"], 3), "iterations": head["iterations"],
+                     "restarts": head["restarts"], "rel_residual": head["rel_residual"],
+                     "rel_error_vs_exact": err, "setup_phases_ms": info["setup_ms"]},
+        "gbps": {"schwarz_local_solve": round(gbs_local, 1), "spmv": round(gbs_spmv, 1),
+                 "local_solve_avg_ms": avg_local, "spmv_avg_ms": avg_spmv},
+        "roofline": roofline,
+    }
+    if f64 is not None:
+        i64 = f64["info"]
+        ms64, n64 = f64["kernels"]["local_solve"]
+        b64 = (2 * i64["factor_algo_bytes"] if args.local == "cholesky" else i64["factor_algo_bytes"]) + 16 * sumN
+        out["fp64"] = {"ms": round(f64["ms"], 3), "setup_ms": round(f64["setup_ms"], 3),
+                       "solve_ms": round(f64["solve_ms"], 3), "iterations": f64["iterations"],
+                       "local_solve_gbps": round(b64 / (ms64 / max(n64, 1) * 1e-3) / 1e9, 1),
+                       "setup_phases_ms": i64["setup_ms"]}
+        out["speedup_fp32_vs_fp64"] = round(f64["ms"] / head["ms"], 3)
+    if not args.no_cpu_baseline:
+        iters = f64["iterations"] if f64 is not None else head["iterations"]
+        out["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

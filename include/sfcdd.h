@@ -155,6 +155,22 @@ sfcdd_status sfcdd_get_partition(sfcdd_ctx* ctx, int32_t* sfc_index_host, int64_
 sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, int64_t* Ni_host,
                                   double* omega_host, int32_t* q_out);
 
+/* Kernel classes timed by the profiling counters. */
+enum { SFCDD_K_LOCAL_SOLVE = 0, SFCDD_K_SCATTER = 1, SFCDD_K_SPMV = 2, SFCDD_K_COARSE = 3,
+       SFCDD_K_COUNT = 4 };
+
+/* Turns per-kernel timing on (1) or off (0) and clears the counters.  When on,
+ * every launch of a timed kernel class is bracketed by HIP events on the
+ * context's stream; the elapsed times are accumulated whenever the library
+ * synchronises (end of sfcdd_solve) or on sfcdd_get_kernel_time.  Adds a few
+ * microseconds per launch. */
+sfcdd_status sfcdd_set_profiling(sfcdd_ctx* ctx, int32_t on);
+
+/* Accumulated device time (ms) and launch count of kernel class `kind`
+ * (SFCDD_K_*) since profiling was enabled.  Synchronises the stream. */
+sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* ctx, int32_t kind, double* total_ms,
+                                   int64_t* launches);
+
 /* Sizes and setup timings of a context. */
 sfcdd_status sfcdd_get_info(sfcdd_ctx* ctx, sfcdd_info* info);
 

@@ -32,7 +32,9 @@ LAYOUT = {"natural": 0, "sfc": 1}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_setup", "sfcdd_apply_precond", "sfcdd_matvec",
            "sfcdd_solve", "sfcdd_grad_coeff", "sfcdd_get_partition", "sfcdd_partition_host",
-           "sfcdd_get_info", "sfcdd_destroy", "sfcdd_last_error"]
+           "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_destroy",
+           "sfcdd_last_error"]
+KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
 
 
 class SfcddError(RuntimeError):
@@ -87,6 +89,8 @@ def lib() -> ctypes.CDLL:
     L.sfcdd_get_partition.argtypes = [vp, P(i32), P(i64), P(i64), P(dbl), P(i32)]
     L.sfcdd_partition_host.argtypes = [P(Params), P(i64), P(i64), P(dbl), P(i32)]
     L.sfcdd_get_info.argtypes = [vp, P(Info)]
+    L.sfcdd_set_profiling.argtypes = [vp, i32]
+    L.sfcdd_get_kernel_time.argtypes = [vp, i32, P(dbl), P(i64)]
     L.sfcdd_destroy.argtypes = [vp]
     L.sfcdd_last_error.argtypes = [vp]
     L.sfcdd_last_error.restype = ctypes.c_char_p
@@ -166,7 +170,8 @@ class SFCSchwarz:
     def __init__(self, levels: Optional[Sequence[int]] = None, npts: Optional[Sequence[int]] = None,
                  coeff: Optional[Sequence[float]] = None, P: int = 1, gamma=Fraction(1, 2), q: int = 0,
                  weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
-                 local_solver: str = "cholesky", layout: str = "natural", device="cuda:0"):
+                 local_solver: str = "cholesky", layout: str = "natural", device="cuda:0",
+                 workspace=None):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -181,7 +186,12 @@ class SFCSchwarz:
         self.workspace_bytes = int(n.value)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            if workspace is not None:
+                if workspace.device != self.device or workspace.numel() < self.workspace_bytes + 256:
+                    raise ValueError("workspace tensor too small or on the wrong device")
+                self.ws = workspace
+            else:
+                self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
             ctx = ctypes.c_void_p()
             _check(lib().sfcdd_setup(ctypes.byref(prm), ctypes.c_void_p(self.ws.data_ptr()),
                                      self.workspace_bytes + 256, ctypes.c_void_p(self.stream.cuda_stream),
@@ -237,6 +247,17 @@ class SFCSchwarz:
         out = (ctypes.c_double * self.d)()
         _check(lib().sfcdd_grad_coeff(self.ctx, self._vec(lam, "lam"), self._vec(u, "u"), out), self.ctx)
         return [float(v) for v in out]
+
+    def set_profiling(self, on: bool = True):
+        _check(lib().sfcdd_set_profiling(self.ctx, 1 if on else 0), self.ctx)
+
+    def kernel_time(self, kind: str):
+        """(total ms, launches) of a timed kernel class since profiling was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().sfcdd_get_kernel_time(self.ctx, KERNELS[kind], ctypes.byref(ms), ctypes.byref(n)),
+               self.ctx)
+        return float(ms.value), int(n.value)
 
     def partition(self) -> dict:
         import numpy as np

@@ -80,6 +80,13 @@ struct sfcdd_ctx {
   double* host_scal = nullptr;  // pinned
   std::string err;
   sfcdd_info info{};
+  // per-kernel profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+  double k_ms[SFCDD_K_COUNT] = {};
+  int64_t k_n[SFCDD_K_COUNT] = {};
 };
 
 #define FAIL(ctx, code, ...)                                   \
@@ -97,6 +104,43 @@ struct sfcdd_ctx {
   } while (0)
 
 namespace {
+
+// Event pair around one timed launch (no-op unless profiling is on).
+struct ProfScope {
+  sfcdd_ctx* c;
+  int kind;
+  size_t idx = SIZE_MAX;
+  ProfScope(sfcdd_ctx* c_, int kind_) : c(c_), kind(kind_) {
+    if (!c->prof) return;
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->ev_pool.push_back(e);
+        c->ev_kind.push_back(0);
+      }
+    }
+    idx = c->ev_used;
+    c->ev_used += 2;
+    c->ev_kind[idx] = kind;
+    (void)hipEventRecord(c->ev_pool[idx], c->stream);
+  }
+  ~ProfScope() {
+    if (idx != SIZE_MAX) (void)hipEventRecord(c->ev_pool[idx + 1], c->stream);
+  }
+};
+
+// Folds the recorded event pairs into the per-kernel totals (stream must be idle).
+void prof_collect(sfcdd_ctx* c) {
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]) == hipSuccess) {
+      c->k_ms[c->ev_kind[i]] += ms;
+      c->k_n[c->ev_kind[i]] += 1;
+    }
+  }
+  c->ev_used = 0;
+}
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -405,6 +449,7 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
 
 // F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then d0 = A_0^{-1} c0.
 void coarse_solve(sfcdd_ctx* c, const double* v) {
+  ProfScope ps(c, SFCDD_K_COARSE);
   BatchMeta bm{c->c_nt, c->c_off, c->c_xoff, c->c_poff};
   launch_restrict(c->pd, v, c->c0, c->stream);
   launch_symv_tiles<double>(1, c->nt0, bm, c->A0, c->c0, c->cpart, c->stream);
@@ -414,6 +459,8 @@ void coarse_solve(sfcdd_ctx* c, const double* v) {
 // y = sum_i R_i^T omega_i A_i^{-1} R_i w (eq. w1levprec).
 void fine_apply(sfcdd_ctx* c, const double* w, double* y) {
   const hipStream_t s = c->stream;
+  {
+  ProfScope ps(c, SFCDD_K_LOCAL_SOLVE);
   if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
     if (c->fdtype == SFCDD_FP32)
       launch_schwarz_trsv<float>(c->P, c->g.N, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff,
@@ -437,7 +484,14 @@ void fine_apply(sfcdd_ctx* c, const double* w, double* y) {
                                  c->dbuf, s);
     }
   }
+  }
+  ProfScope ps(c, SFCDD_K_SCATTER);
   launch_scatter(c->g, c->pd, c->d_ta, c->d_Ni, c->d_doff, c->d_omega, c->dbuf, y, s);
+}
+
+void spmv(sfcdd_ctx* c, const double* x, double* y, const double* b, double* partials) {
+  ProfScope ps(c, SFCDD_K_SPMV);
+  launch_spmv(c->g, c->nbr, x, y, b, partials, nullptr, c->stream);
 }
 
 // h = C^{-1} g in curve order (Alg. 2; balanced form eq. balSW).
@@ -447,9 +501,9 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h) {
     double *t = c->vec[V_T], *w = c->vec[V_W], *y = c->vec[V_Y], *v = c->vec[V_V];
     coarse_solve(c, g);                                               // d0 = A0^{-1} R0 g
     launch_combine(c->g, c->pd, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
-    launch_spmv(c->g, c->nbr, t, w, g, c->partials, nullptr, s);     // w = g - A t = G g
+    spmv(c, t, w, g, c->partials);                                    // w = g - A t = G g
     fine_apply(c, w, y);                                              // y = C1^{-1} G g
-    launch_spmv(c->g, c->nbr, y, v, nullptr, nullptr, nullptr, s);   // v = A y
+    spmv(c, y, v, nullptr, nullptr);                                  // v = A y
     coarse_solve(c, v);                                               // d0 = A0^{-1} R0 A y
     launch_combine(c->g, c->pd, COMB_BAL_FINAL, c->d0, y, t, h, s);  // h = y - F A y + F g
   } else {
@@ -714,7 +768,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       launch_dot(N, r, q, nullptr, c->partials, s);
       launch_finalize(FIN_RZ_INIT, c->partials, c->scal, s);
       for (int k = 0; k < 30; ++k) {
-        launch_spmv(c->g, c->nbr, p, tmp, nullptr, c->partials, p, s);
+        spmv(c, p, tmp, nullptr, c->partials);
         launch_finalize(FIN_PQ_ALPHA, c->partials, c->scal, s);
         launch_update_xr(N, c->scal, z, r, p, tmp, c->partials, s);
         double a_k;
@@ -746,7 +800,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     hx[0] = xi;
     HIPCHK(c, hipMemcpyAsync(c->scal + S_XI, hx, 8, hipMemcpyHostToDevice, s));
     for (;;) {
-      launch_spmv(c->g, c->nbr, x, r, b, c->partials, nullptr, s);
+      spmv(c, x, r, b, c->partials);
       launch_finalize(FIN_RR, c->partials, c->scal, s);
       if ((st = read_scal(c, S_RR, &rr))) return st;
       if (rr <= tol2) { conv = true; break; }
@@ -760,7 +814,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     bool fresh = true;
     while (true) {
       if (fresh) {
-        launch_spmv(c->g, c->nbr, x, r, b, c->partials, nullptr, s);
+        spmv(c, x, r, b, c->partials);
         launch_finalize(FIN_RR, c->partials, c->scal, s);
         if ((st = read_scal(c, S_RR, &rr))) return st;
         if (rr <= tol2) { conv = true; break; }
@@ -771,7 +825,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         launch_copy(N, z, p, s);
         fresh = false;
       }
-      launch_spmv(c->g, c->nbr, p, q, nullptr, c->partials, p, s);
+      spmv(c, p, q, nullptr, c->partials);
       launch_finalize(FIN_PQ_ALPHA, c->partials, c->scal, s);
       launch_update_xr(N, c->scal, x, r, p, q, c->partials, s);
       launch_finalize(FIN_RR, c->partials, c->scal, s);
@@ -780,7 +834,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       if (!std::isfinite(rr)) FAIL(c, SFCDD_ENOTCONV, "residual is not finite");
       if (rr <= tol2 || it >= max_iter) {
         // confirm on the true residual; restart from x when they disagree
-        launch_spmv(c->g, c->nbr, x, tmp, b, c->partials, nullptr, s);
+        spmv(c, x, tmp, b, c->partials);
         launch_finalize(FIN_RR, c->partials, c->scal, s);
         if ((st = read_scal(c, S_RR, &rr))) return st;
         if (rr <= tol2) { conv = true; break; }
@@ -798,6 +852,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   if (c->layout == 1) launch_copy(N, x, x_io, s);
   else launch_permute(N, c->sfc_index, x, x_io, 0, s);
   HIPCHK(c, hipStreamSynchronize(s));
+  prof_collect(c);
   inf.iterations = it;
   inf.restarts = restarts;
   inf.rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
@@ -859,6 +914,28 @@ sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, 
   return SFCDD_OK;
 }
 
+sfcdd_status sfcdd_set_profiling(sfcdd_ctx* c, int32_t on) {
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ev_used = 0;
+  for (int k = 0; k < SFCDD_K_COUNT; ++k) {
+    c->k_ms[k] = 0.0;
+    c->k_n[k] = 0;
+  }
+  c->prof = on != 0;
+  return SFCDD_OK;
+}
+
+sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* c, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  if (kind < 0 || kind >= SFCDD_K_COUNT) FAIL(c, SFCDD_EINVAL, "kind = %d", kind);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if (total_ms) *total_ms = c->k_ms[kind];
+  if (launches) *launches = c->k_n[kind];
+  return SFCDD_OK;
+}
+
 sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
   if (!c || !info) FAIL(c, SFCDD_EINVAL, "NULL argument");
   *info = c->info;
@@ -868,6 +945,7 @@ sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
 sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (!c) return SFCDD_OK;
   if (c->host_scal) (void)hipHostFree(c->host_scal);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return SFCDD_OK;
 }
