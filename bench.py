@@ -212,6 +212,8 @@ def main():
                      "rel_error_vs_exact": err, "setup_phases_ms": info["setup_ms"]},
         "gbps": {"schwarz_local_solve": round(gbs_local, 1), "spmv": round(gbs_spmv, 1),
                  "local_solve_avg_ms": avg_local, "spmv_avg_ms": avg_spmv},
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in head["kernels"].items()},
+        "kernel_launches_per_step": {k: v[1] // args.steps for k, v in head["kernels"].items()},
         "roofline": roofline,
     }
     if f64 is not None:

@@ -54,8 +54,11 @@ __device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
   __syncthreads();
 }
 
+// left != 0: left-looking (the tile first receives -sum_{K<J} L_JK L_JK^T);
+// left == 0: right-looking (the trailing updates were already applied).
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, const int32_t* __restrict__ nt,
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left,
+                                                             const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
                                                              int32_t* __restrict__ status) {
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, const int32_
   T* F = fac + off[b] * TS2;
   TileAcc<T> acc;
   acc.load(F + tri_index(J, J) * TS2);
-  for (int K = 0; K < J; ++K) {
+  for (int K = 0; K < (left ? J : 0); ++K) {
     stage_tile(sA, F + tri_index(J, K) * TS2);
     __syncthreads();
     tile_mma<T, false, true>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
@@ -83,7 +86,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, const int32_
 }
 
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, const int32_t* __restrict__ nt,
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left,
+                                                              const int32_t* __restrict__ nt,
                                                               const int64_t* __restrict__ off,
                                                               T* __restrict__ fac) {
   const int b = blockIdx.y;
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, const int32
   T* F = fac + off[b] * TS2;
   TileAcc<T> acc;
   acc.load(F + tri_index(I, J) * TS2);
-  for (int K = 0; K < J; ++K) {
+  for (int K = 0; K < (left ? J : 0); ++K) {
     stage_tile(sA, F + tri_index(I, K) * TS2);
     stage_tile(sB, F + tri_index(J, K) * TS2);
     __syncthreads();
@@ -120,22 +124,151 @@ static void allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename T>
-void launch_potrf_diag(int J, int nb, const int32_t* nt, const int64_t* off, T* fac,
+void launch_potrf_diag(int J, int left, int nb, const int32_t* nt, const int64_t* off, T* fac,
                        int32_t* status, hipStream_t s) {
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
   static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, nt, off, fac, status);
+  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, left, nt, off, fac,
+                     status);
 }
 template <typename T>
-void launch_potrf_panel(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac,
-                        hipStream_t s) {
+void launch_potrf_panel(int J, int left, int nb, int max_nt, const int32_t* nt, const int64_t* off,
+                        T* fac, hipStream_t s) {
   if (max_nt - 1 - J <= 0) return;
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
   static bool once = (allow_lds(k_potrf_panel<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, nt,
+  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, left,
+                     nt, off, fac);
+}
+
+// Triangle index t -> (a, b), b <= a.
+__device__ __forceinline__ void tri_decode(int64_t t, int* a, int* b) {
+  int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+  while ((int64_t)I * (I + 1) / 2 > t) --I;
+  *a = I;
+  *b = (int)(t - (int64_t)I * (I + 1) / 2);
+}
+
+// Right-looking trailing update after column K: A_IJ -= L_IK L_JK^T for
+// K < J <= I (one workgroup per trailing tile, all in parallel).
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_update(int K, const int32_t* __restrict__ nt,
+                                                               const int64_t* __restrict__ off,
+                                                               T* __restrict__ fac) {
+  const int b = blockIdx.y;
+  int a, c;
+  tri_decode(blockIdx.x, &a, &c);
+  const int I = K + 1 + a, J = K + 1 + c;
+  if (I >= nt[b]) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  T* F = fac + off[b] * TS2;
+  TileAcc<T> acc;
+  acc.load(F + tri_index(I, J) * TS2);
+  stage_tile(sA, F + tri_index(I, K) * TS2);
+  stage_tile(sB, F + tri_index(J, K) * TS2);
+  __syncthreads();
+  tile_mma<T, false, true>(acc, sA, sB, T(-1));
+  acc.store(F + tri_index(I, J) * TS2);
+}
+
+template <typename T>
+void launch_potrf_update(int K, int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac,
+                         hipStream_t s) {
+  const int m = max_nt - 1 - K;
+  if (m <= 0) return;
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_potrf_update<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_potrf_update<T>, dim3(m * (m + 1) / 2, nb), dim3(TILE_THREADS), sh, s, K, nt,
                      off, fac);
+}
+
+// X = L^{-1} right-looking, for matrices too few to fill the GPU by batch:
+// X starts as the identity; step K makes row K final, X_KJ = L_KK^{-1} X_KJ
+// (J <= K), then removes it from the rows below, X_IJ -= L_IK X_KJ (I > K).
+template <typename T>
+__global__ void k_identity_tiles(const int32_t* __restrict__ nt, const int64_t* __restrict__ off,
+                                 T* __restrict__ X) {
+  const int b = blockIdx.y;
+  const int ntb = nt[b];
+  const int64_t ntiles = (int64_t)ntb * (ntb + 1) / 2;
+  T* Xb = X + off[b] * TS2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * TS2;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e / TS2;
+    int a, c;
+    tri_decode(t, &a, &c);
+    const int r = (int)((e % TS2) / TS), q = (int)(e % TS);
+    Xb[e] = (a == c && r == q) ? T(1) : T(0);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_row(int K, const int32_t* __restrict__ nt,
+                                                            const int64_t* __restrict__ off,
+                                                            const T* __restrict__ L,
+                                                            T* __restrict__ X) {
+  const int b = blockIdx.y;
+  const int J = blockIdx.x;
+  if (K >= nt[b] || J > K) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  const T* Lb = L + off[b] * TS2;
+  T* Xb = X + off[b] * TS2;
+  stage_tile(sA, Lb + tri_index(K, K) * TS2);
+  stage_tile(sB, Xb + tri_index(K, J) * TS2);
+  __syncthreads();
+  TileAcc<T> acc;
+  acc.zero();
+  tile_mma<T, false, false>(acc, sA, sB, T(1));
+  __syncthreads();
+  acc.store(Xb + tri_index(K, J) * TS2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_update(int K, const int32_t* __restrict__ nt,
+                                                               const int64_t* __restrict__ off,
+                                                               const T* __restrict__ L,
+                                                               T* __restrict__ X) {
+  const int b = blockIdx.y;
+  const int ntb = nt[b];
+  const int I = K + 1 + (int)(blockIdx.x / (K + 1));
+  const int J = (int)(blockIdx.x % (K + 1));
+  if (I >= ntb) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  const T* Lb = L + off[b] * TS2;
+  T* Xb = X + off[b] * TS2;
+  TileAcc<T> acc;
+  acc.load(Xb + tri_index(I, J) * TS2);
+  stage_tile(sA, Lb + tri_index(I, K) * TS2);
+  stage_tile(sB, Xb + tri_index(K, J) * TS2);
+  __syncthreads();
+  tile_mma<T, false, false>(acc, sA, sB, T(-1));
+  acc.store(Xb + tri_index(I, J) * TS2);
+}
+
+template <typename T>
+void launch_trtri_rl(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* L, T* X,
+                     hipStream_t s) {
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_trtri_row<T>, sh), allow_lds(k_trtri_update<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_identity_tiles<T>, dim3(1024, nb), dim3(256), 0, s, nt, off, X);
+  for (int K = 0; K < max_nt; ++K) {
+    hipLaunchKernelGGL(k_trtri_row<T>, dim3(K + 1, nb), dim3(TILE_THREADS), sh, s, K, nt, off, L, X);
+    const int m = max_nt - 1 - K;
+    if (m > 0)
+      hipLaunchKernelGGL(k_trtri_update<T>, dim3(m * (K + 1), nb), dim3(TILE_THREADS), sh, s, K, nt,
+                         off, L, X);
+  }
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -231,10 +364,14 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 }
 
 #define INST(T)                                                                                    \
-  template void launch_potrf_diag<T>(int, int, const int32_t*, const int64_t*, T*, int32_t*,        \
+  template void launch_potrf_diag<T>(int, int, int, const int32_t*, const int64_t*, T*, int32_t*,   \
                                      hipStream_t);                                                 \
-  template void launch_potrf_panel<T>(int, int, int, const int32_t*, const int64_t*, T*,           \
+  template void launch_potrf_panel<T>(int, int, int, int, const int32_t*, const int64_t*, T*,      \
                                       hipStream_t);                                                \
+  template void launch_potrf_update<T>(int, int, int, const int32_t*, const int64_t*, T*,          \
+                                       hipStream_t);                                               \
+  template void launch_trtri_rl<T>(int, int, const int32_t*, const int64_t*, const T*, T*,         \
+                                   hipStream_t);                                                   \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t);

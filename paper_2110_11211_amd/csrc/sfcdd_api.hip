@@ -434,15 +434,24 @@ void bind(sfcdd_ctx* c) {
 
 // Batched left-looking tiled Cholesky of nb packed matrices (+ optional
 // inversion into M = A^{-1} via X = L^{-1}, M = X^T X).
+// Left-looking when the batch alone fills the GPU (each workgroup keeps its
+// output tile in registers across the K loop); right-looking when there are
+// too few matrices, so that every tile update of a step runs in parallel.
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, int32_t* status, hipStream_t s) {
+  const bool left = (int64_t)nb * max_nt >= 1024;
   for (int J = 0; J < max_nt; ++J) {
-    launch_potrf_diag<T>(J, nb, nt, off, fac, status, s);
-    launch_potrf_panel<T>(J, nb, max_nt, nt, off, fac, s);
+    launch_potrf_diag<T>(J, left ? 1 : 0, nb, nt, off, fac, status, s);
+    launch_potrf_panel<T>(J, left ? 1 : 0, nb, max_nt, nt, off, fac, s);
+    if (!left) launch_potrf_update<T>(J, nb, max_nt, nt, off, fac, s);
   }
   if (invert) {
-    for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
+    if (left) {
+      for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
+    } else {
+      launch_trtri_rl<T>(nb, max_nt, nt, off, fac, X, s);
+    }
     launch_lauum<T>(nb, max_nt, nt, off, X, fac, s);
   }
 }

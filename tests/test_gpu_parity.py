@@ -176,3 +176,71 @@ def test_grad_coeff_matches_oracle():
     ga = S.grad_coeff(dvec(lam), dvec(u))
     ref = [-(g.inv_h2[j]) * float(lam @ (g.second_difference(j) @ u)) for j in range(g.d)]
     assert np.allclose(ga, ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("fdtype,local", [("fp64", "cholesky"), ("fp32", "cholesky"), ("fp64", "inverse"),
+                                          ("fp32", "inverse")])
+def test_apply_batched_left_looking_size(fdtype, local):
+    """128 subdomains of ~950 points (15 tiles): the batched left-looking
+    factorisation path, ragged last tiles."""
+    levels, P, gamma = (6, 5, 5), 128, Fraction(1, 2)
+    announce("apply-left", fdtype, local)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma)
+    S = _solver(levels, P, gamma, factor_dtype=fdtype, local_solver=local)
+    r = uniform_pm1(12, g.N)
+    h = host(S.apply(dvec(r)))
+    assert relerr(h, O.apply(r)) <= (FP64_TOL if fdtype == "fp64" else FP32_TOL)
+
+
+def _coarse_vector(N, P, q, seed):
+    """R_0^T c for random c (curve order), from the eq. (restr) blocks."""
+    from oracle import partition as part
+    c = uniform_pm1(seed, q * P)
+    v = np.empty(N)
+    for I, (s, sz) in enumerate(part.coarse_blocks(N, P, q)):
+        v[s:s + sz] = c[I]
+    return v
+
+
+@pytest.mark.parametrize("name,fdtype", [("c2", "fp32"), ("c2", "fp64"), ("c5", "fp32")])
+def test_full_size_solution_and_operator_properties(name, fdtype):
+    """Workloads at full size in the benchmark's launch configuration: the
+    solve against the exact DST-I solution, and properties of C^{-1} that hold
+    at any size: symmetry u^T C^{-1} v = v^T C^{-1} u, and the balanced
+    operator's identity on the coarse space, C^{-1} A R_0^T c = R_0^T c."""
+    w = workloads()[name]
+    announce("full-size", name, fdtype)
+    g = Grid(levels=w.levels[0])
+    S = _solver(w.levels[0], w.P, w.gamma, factor_dtype=fdtype, layout="sfc")
+    f = w.rhs()
+    sfc = S.partition()["sfc_index"]
+    method = "fcg" if fdtype == "fp32" else "pcg"
+    xs_sfc, info = S.solve(dvec(f[sfc]), rtol=1e-12, method=method, max_iter=600)
+    x = np.empty(g.N)
+    x[sfc] = host(xs_sfc)
+    assert relerr(x, exact.solve(g, f)) <= 1e-9
+    u = dvec(uniform_pm1(21, g.N))
+    v = dvec(uniform_pm1(22, g.N))
+    a = float(torch.dot(u, S.apply(v)))
+    b = float(torch.dot(v, S.apply(u)))
+    assert abs(a - b) <= (1e-12 if fdtype == "fp64" else 1e-5) * abs(a)
+    q = S.partition()["q"]
+    cv = dvec(_coarse_vector(g.N, w.P, q, 23))
+    back = S.apply(S.matvec(cv))
+    assert relerr(host(back), host(cv)) <= (1e-10 if fdtype == "fp64" else 1e-5)
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+
+
+def test_full_size_apply_c2_matches_oracle():
+    """One preconditioner application at the d=3 workload's full size (256
+    subdomains of ~1937 points, FP64 factors) against the oracle."""
+    w = workloads()["c2"]
+    announce("full-size apply c2")
+    g = Grid(levels=w.levels[0])
+    O = OracleSchwarz(g, w.P, w.gamma)
+    S = _solver(w.levels[0], w.P, w.gamma)
+    r = uniform_pm1(31, g.N)
+    assert relerr(host(S.apply(dvec(r))), O.apply(r)) <= FP64_TOL
