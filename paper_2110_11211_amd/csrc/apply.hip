@@ -218,6 +218,8 @@ template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_symv_tiles(BatchMeta bm, const T* __restrict__ M,
                                                              const T* __restrict__ xloc,
                                                              T* __restrict__ part) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VEC = Vec16<T>::n;
   const int b = blockIdx.y;
   const int ntb = bm.nt[b];
   const int64_t t = blockIdx.x;
@@ -228,22 +230,33 @@ __global__ __launch_bounds__(TILE_THREADS) void k_symv_tiles(BatchMeta bm, const
   const int J = (int)(t - (int64_t)I * (I + 1) / 2);
   __shared__ T sM[TS * LDS_S];
   __shared__ T sx[2 * TS];
-  stage_tile(sM, M + (bm.off[b] + t) * TS2);
+  const V* src = reinterpret_cast<const V*>(M + (bm.off[b] + t) * TS2);
+  for (int e = threadIdx.x; e < TS2 / VEC; e += TILE_THREADS) {
+    const V v = src[e];
+    const int r = (e * VEC) / TS, c = (e * VEC) % TS;
+    const T* pv = reinterpret_cast<const T*>(&v);
+    for (int q = 0; q < VEC; ++q) sM[r * LDS_S + c + q] = pv[q];
+  }
   const T* xb = xloc + bm.xoff[b];
   if (threadIdx.x < TS) sx[threadIdx.x] = xb[J * TS + threadIdx.x];
   else if (threadIdx.x < 2 * TS) sx[threadIdx.x] = xb[I * TS + threadIdx.x - TS];
   __syncthreads();
   T* pb = part + bm.poff[b];
-  const int tid = threadIdx.x;
-  if (tid < TS) {
-    T acc = T(0);
-    for (int c = 0; c < TS; ++c) acc += sM[tid * LDS_S + c] * sx[c];
-    pb[((int64_t)I * ntb + J) * TS + tid] = acc;
-  } else if (tid < 2 * TS && I != J) {
-    const int c = tid - TS;
-    T acc = T(0);
-    for (int r = 0; r < TS; ++r) acc += sM[r * LDS_S + c] * sx[TS + r];
-    pb[((int64_t)J * ntb + I) * TS + c] = acc;
+  const int tid = threadIdx.x, rc = tid >> 2, qq = tid & 3;
+  // row product: rows rc, columns 16 qq .. 16 qq + 15
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc += sM[rc * LDS_S + 16 * qq + k] * sx[16 * qq + k];
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (qq == 0) pb[((int64_t)I * ntb + J) * TS + rc] = acc;
+  if (I != J) {  // transposed product: column rc, rows 16 qq .. 16 qq + 15
+    T acc2 = T(0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc2 += sM[(16 * qq + k) * LDS_S + rc] * sx[TS + 16 * qq + k];
+    acc2 += __shfl_xor(acc2, 1, 64);
+    acc2 += __shfl_xor(acc2, 2, 64);
+    if (qq == 0) pb[((int64_t)J * ntb + I) * TS + rc] = acc2;
   }
 }
 
@@ -254,26 +267,38 @@ void launch_symv_tiles(int nb, int max_nt, const BatchMeta& bm, const T* M, cons
   hipLaunchKernelGGL(k_symv_tiles<T>, dim3(ntiles, nb), dim3(TILE_THREADS), 0, s, bm, M, xloc, part);
 }
 
-// out[b][s] = sum_K part[b][s/TS][K][s%TS] for s < n_b (fixed order over K).
+// out[b][I TS + r] = sum_K part[b][I][K][r] for I TS + r < n_b, fixed order:
+// one workgroup per tile row, four interleaved partial sums over K.
 template <typename T>
-__global__ void k_symv_reduce(BatchMeta bm, const int32_t* __restrict__ n, const int64_t* __restrict__ doff,
-                              const T* __restrict__ part, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_symv_reduce(BatchMeta bm, const int32_t* __restrict__ n,
+                                                     const int64_t* __restrict__ doff,
+                                                     const T* __restrict__ part,
+                                                     double* __restrict__ out) {
   const int b = blockIdx.y;
   const int ntb = bm.nt[b];
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n[b]) return;
-  const int I = s / TS, r = s % TS;
+  const int I = blockIdx.x;
+  if (I >= ntb) return;
+  __shared__ T red[4 * TS];
+  const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;
   const T* pb = part + bm.poff[b] + (int64_t)I * ntb * TS + r;
   T acc = T(0);
-  for (int K = 0; K < ntb; ++K) acc += pb[(int64_t)K * TS];
-  out[doff[b] + s] = (double)acc;
+  for (int K = kq; K < ntb; K += 4) acc += pb[(int64_t)K * TS];
+  red[kq * TS + r] = acc;
+  __syncthreads();
+  if (threadIdx.x < TS) {
+    const int sidx = I * TS + r;
+    if (sidx < n[b]) {
+      const T v = (red[r] + red[TS + r]) + (red[2 * TS + r] + red[3 * TS + r]);
+      out[doff[b] + sidx] = (double)v;
+    }
+  }
 }
 
 template <typename T>
 void launch_symv_reduce(int nb, int max_n, const BatchMeta& bm, const int32_t* n,
                         const int64_t* doff, const T* part, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_symv_reduce<T>, dim3((max_n + 255) / 256, nb), dim3(256), 0, s, bm, n, doff,
-                     part, out);
+  const int max_nt = (max_n + TS - 1) / TS;
+  hipLaunchKernelGGL(k_symv_reduce<T>, dim3(max_nt, nb), dim3(256), 0, s, bm, n, doff, part, out);
 }
 
 // xloc[b][s] = R_b w (cyclic curve range from ta_b) for s < N_b, 0 up to nt_b*TS.

@@ -10,46 +10,60 @@
 
 namespace sfcdd {
 
-// Unblocked Cholesky of the lower part of a TS x TS LDS tile followed by the
-// inversion of the factor: on exit sX holds L^{-1} (lower), sC is clobbered.
+// Broadcast of lane `src` (wave-uniform) to every lane through an SGPR.
+__device__ __forceinline__ float bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Unblocked Cholesky of a TS x TS LDS tile followed by the inversion of the
+// factor, both done by the first wave alone with no workgroup barrier inside
+// (a single wave issues its LDS operations in program order).
+// Factoring: lane i owns row i of the tile in LDS; at step k every lane reads
+// the pivot and column k by broadcast.  Inverting: lane c keeps column c of
+// X = L^{-1} in registers and sweeps the columns of L left to right.
+// On exit sX holds L^{-1} (lower, zeros above) and sC holds L (lower).
 // A non-positive pivot sets *status to -6 and is replaced by 1.
 template <typename T>
 __device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < TS; ++k) {
-    __syncthreads();
-    if (tid < TS) {
+  __syncthreads();
+  if (threadIdx.x < TS) {
+    const int i = threadIdx.x;
+    for (int k = 0; k < TS; ++k) {
       T piv = sC[k * LDS_S + k];
       if (!(piv > T(0))) {
-        if (tid == 0) atomicExch(status, -6);
+        if (i == k) atomicExch(status, -6);
         piv = T(1);
       }
       const T dk = sqrt(piv);
-      if (tid >= k) sC[tid * LDS_S + k] = (tid == k) ? dk : sC[tid * LDS_S + k] / dk;
-    }
-    __syncthreads();
-    // trailing update of the lower triangle below row k
-    const int m = TS - 1 - k;
-    for (int e = tid; e < m * m; e += TILE_THREADS) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) sC[i * LDS_S + j] -= sC[i * LDS_S + k] * sC[j * LDS_S + k];
-    }
-  }
-  __syncthreads();
-  // X = L^{-1}: thread c solves L x = e_c by forward substitution.
-  if (tid < TS) {
-    const int c = tid;
-    for (int i = 0; i < TS; ++i) {
-      T v;
-      if (i < c) {
-        v = T(0);
-      } else {
-        T s = (i == c) ? T(1) : T(0);
-        for (int k = c; k < i; ++k) s -= sC[i * LDS_S + k] * sX[k * LDS_S + c];
-        v = s / sC[i * LDS_S + i];
+      T l = T(0);
+      if (i > k) {
+        l = sC[i * LDS_S + k] / dk;
+        sC[i * LDS_S + k] = l;
       }
-      sX[i * LDS_S + c] = v;
+      if (i == k) sC[k * LDS_S + k] = dk;
+#pragma unroll 8
+      for (int j = k + 1; j <= i; ++j) sC[i * LDS_S + j] -= l * sC[j * LDS_S + k];
     }
+    const int c = threadIdx.x;
+    T b[TS];
+#pragma unroll
+    for (int r = 0; r < TS; ++r) b[r] = (r == c) ? T(1) : T(0);
+#pragma unroll
+    for (int k = 0; k < TS; ++k) {
+      __asm__ volatile("" ::: "memory");
+      const T xk = b[k] / sC[k * LDS_S + k];
+      b[k] = xk;
+#pragma unroll
+      for (int r = k + 1; r < TS; ++r) b[r] -= sC[r * LDS_S + k] * xk;
+    }
+#pragma unroll
+    for (int r = 0; r < TS; ++r) sX[r * LDS_S + c] = b[r];
   }
   __syncthreads();
 }
