@@ -97,7 +97,9 @@ typedef struct {
   int64_t factor_bytes;      /* bytes of all subdomain factor tiles                    */
   int64_t factor_algo_bytes; /* sum_i N_i (N_i + 1) / 2 * sizeof(factor element)      */
   int64_t coarse_bytes;      /* bytes of the coarse operator tiles                     */
-  double setup_ms[6];        /* sfc rank, neighbours, assembly, factor, coarse, total  */
+  double setup_ms[6];        /* sfc rank, neighbours, assembly, subdomain factorisation,
+                                coarse setup (runs concurrently with the factorisation),
+                                total                                                  */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1

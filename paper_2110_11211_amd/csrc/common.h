@@ -12,6 +12,8 @@ constexpr int TS2 = TS * TS;
 constexpr int LDS_S = TS + 1;
 // Workgroup size of the tile kernels: 4 waves, each owning a 32x32 quadrant.
 constexpr int TILE_THREADS = 256;
+// K-chunk length of the split-K tile updates used for single matrices.
+constexpr int SPLITK = 8;
 // Blocks used by the first stage of the deterministic two-stage reductions.
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
@@ -54,6 +56,30 @@ __device__ __forceinline__ void stage_tile(T* __restrict__ lds, const T* __restr
   }
 }
 
+// One row-major TS x TS tile held in registers across the workgroup (16-byte
+// vector loads, TS2 / TILE_THREADS elements per thread): the prefetch buffer
+// that lets the next tiles load from memory while MFMA works on LDS.
+template <typename T> struct TileRegs {
+  static constexpr int VEC = 16 / sizeof(T);
+  static constexpr int NV = TS2 / (TILE_THREADS * VEC);
+  typedef T V __attribute__((ext_vector_type(VEC)));
+  V v[NV];
+  __device__ __forceinline__ void load(const T* __restrict__ g) {
+    const V* gv = reinterpret_cast<const V*>(g);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = gv[threadIdx.x + q * TILE_THREADS];
+  }
+  __device__ __forceinline__ void store_lds(T* __restrict__ lds) const {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = (threadIdx.x + q * TILE_THREADS) * VEC;
+      T* dst = lds + (e / TS) * LDS_S + (e % TS);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) dst[c] = v[q][c];
+    }
+  }
+};
+
 // Accumulator of one wave: 2x2 blocks of 16x16 covering a 32x32 quadrant of
 // the 64x64 output tile.  Quadrant of wave w: rows 32*(w/2), cols 32*(w%2).
 template <typename T> struct TileAcc {
@@ -76,6 +102,11 @@ template <typename T> struct TileAcc {
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b)
         for (int r = 0; r < 4; ++r) c[a][b][r] = g[row(a, r) * TS + col(b)];
+  }
+  __device__ __forceinline__ void sub(const T* __restrict__ g) {  // acc -= row-major tile
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int r = 0; r < 4; ++r) c[a][b][r] -= g[row(a, r) * TS + col(b)];
   }
   __device__ __forceinline__ void store(T* __restrict__ g) const {
     for (int a = 0; a < 2; ++a)

@@ -30,10 +30,11 @@ __device__ __forceinline__ double bcast(double v, int src) {
 // On exit sX holds L^{-1} (lower, zeros above) and sC holds L (lower).
 // A non-positive pivot sets *status to -6 and is replaced by 1.
 template <typename T>
-__device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
+__device__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
   __syncthreads();
   if (threadIdx.x < TS) {
     const int i = threadIdx.x;
+    T* __restrict__ col = sX;  // column k of L for the update; sX is written only at the end
     for (int k = 0; k < TS; ++k) {
       T piv = sC[k * LDS_S + k];
       if (!(piv > T(0))) {
@@ -41,14 +42,13 @@ __device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
         piv = T(1);
       }
       const T dk = sqrt(piv);
-      T l = T(0);
-      if (i > k) {
-        l = sC[i * LDS_S + k] / dk;
-        sC[i * LDS_S + k] = l;
-      }
-      if (i == k) sC[k * LDS_S + k] = dk;
+      const T rdk = T(1) / dk;
+      const T l = (i > k) ? sC[i * LDS_S + k] * rdk : (i == k ? dk : T(0));
+      if (i >= k) sC[i * LDS_S + k] = l;
+      col[i] = l;
 #pragma unroll 8
-      for (int j = k + 1; j <= i; ++j) sC[i * LDS_S + j] -= l * sC[j * LDS_S + k];
+      for (int j = k + 1; j < TS; ++j)
+        if (j <= i) sC[i * LDS_S + j] -= l * col[j];
     }
     const int c = threadIdx.x;
     T b[TS];
@@ -57,7 +57,7 @@ __device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
 #pragma unroll
     for (int k = 0; k < TS; ++k) {
       __asm__ volatile("" ::: "memory");
-      const T xk = b[k] / sC[k * LDS_S + k];
+      const T xk = b[k] * (T(1) / sC[k * LDS_S + k]);
       b[k] = xk;
 #pragma unroll
       for (int r = k + 1; r < TS; ++r) b[r] -= sC[r * LDS_S + k] * xk;
@@ -68,10 +68,12 @@ __device__ void potrf_inv_tile(T* sC, T* sX, int32_t* status) {
   __syncthreads();
 }
 
-// left != 0: left-looking (the tile first receives -sum_{K<J} L_JK L_JK^T);
-// left == 0: right-looking (the trailing updates were already applied).
+// left != 0: left-looking, the tile first receives -sum_{K<J} L_JK L_JK^T
+// in this workgroup.  nparts > 0 (single matrix, split-K): that update was
+// precomputed as nparts partial tiles part[I][c] by k_potrf_partial.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left,
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left, int nparts, int maxc,
+                                                             const T* __restrict__ part,
                                                              const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
@@ -84,12 +86,18 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left,
   T* F = fac + off[b] * TS2;
   TileAcc<T> acc;
   acc.load(F + tri_index(J, J) * TS2);
-  for (int K = 0; K < (left ? J : 0); ++K) {
-    stage_tile(sA, F + tri_index(J, K) * TS2);
+  for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
+  const int nk = left ? J : 0;
+  TileRegs<T> ra;
+  if (nk > 0) ra.load(F + tri_index(J, 0) * TS2);
+  for (int K = 0; K < nk; ++K) {
     __syncthreads();
+    ra.store_lds(sA);
+    __syncthreads();
+    if (K + 1 < nk) ra.load(F + tri_index(J, K + 1) * TS2);
     tile_mma<T, false, true>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
-    __syncthreads();
   }
+  __syncthreads();
   acc.store_lds(sA);
   potrf_inv_tile(sA, sB, status);
   T* D = F + tri_index(J, J) * TS2;
@@ -100,7 +108,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left,
 }
 
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left,
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left, int nparts, int maxc,
+                                                              const T* __restrict__ part,
                                                               const int32_t* __restrict__ nt,
                                                               const int64_t* __restrict__ off,
                                                               T* __restrict__ fac) {
@@ -113,13 +122,25 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left,
   T* F = fac + off[b] * TS2;
   TileAcc<T> acc;
   acc.load(F + tri_index(I, J) * TS2);
-  for (int K = 0; K < (left ? J : 0); ++K) {
-    stage_tile(sA, F + tri_index(I, K) * TS2);
-    stage_tile(sB, F + tri_index(J, K) * TS2);
-    __syncthreads();
-    tile_mma<T, false, true>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
-    __syncthreads();
+  for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);
+  const int nk = left ? J : 0;
+  TileRegs<T> ra, rb;
+  if (nk > 0) {
+    ra.load(F + tri_index(I, 0) * TS2);
+    rb.load(F + tri_index(J, 0) * TS2);
   }
+  for (int K = 0; K < nk; ++K) {
+    __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 < nk) {
+      ra.load(F + tri_index(I, K + 1) * TS2);
+      rb.load(F + tri_index(J, K + 1) * TS2);
+    }
+    tile_mma<T, false, true>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+  }
+  __syncthreads();
   acc.store_lds(sA);
   stage_tile(sB, F + tri_index(J, J) * TS2);      // L_JJ^{-1}
   __syncthreads();
@@ -138,151 +159,74 @@ static void allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename T>
-void launch_potrf_diag(int J, int left, int nb, const int32_t* nt, const int64_t* off, T* fac,
-                       int32_t* status, hipStream_t s) {
+void launch_potrf_diag(int J, int left, int nparts, int maxc, const T* part, int nb,
+                       const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
+                       hipStream_t s) {
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
   static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, left, nt, off, fac,
-                     status);
+  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, left, nparts, maxc,
+                     part, nt, off, fac, status);
 }
 template <typename T>
-void launch_potrf_panel(int J, int left, int nb, int max_nt, const int32_t* nt, const int64_t* off,
-                        T* fac, hipStream_t s) {
+void launch_potrf_panel(int J, int left, int nparts, int maxc, const T* part, int nb, int max_nt,
+                        const int32_t* nt, const int64_t* off, T* fac, hipStream_t s) {
   if (max_nt - 1 - J <= 0) return;
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
   static bool once = (allow_lds(k_potrf_panel<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, left,
-                     nt, off, fac);
+                     nparts, maxc, part, nt, off, fac);
 }
 
-// Triangle index t -> (a, b), b <= a.
-__device__ __forceinline__ void tri_decode(int64_t t, int* a, int* b) {
-  int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
-  while ((int64_t)I * (I + 1) / 2 > t) --I;
-  *a = I;
-  *b = (int)(t - (int64_t)I * (I + 1) / 2);
-}
-
-// Right-looking trailing update after column K: A_IJ -= L_IK L_JK^T for
-// K < J <= I (one workgroup per trailing tile, all in parallel).
+// Split-K update of column J of one matrix (batch 1): workgroup (x, c)
+// computes part[I][c] = sum_{K in chunk c} L_IK L_JK^T for I = J + x, chunk
+// c = [c SPLITK, (c + 1) SPLITK) intersected with [0, J).  Many workgroups per
+// column instead of one long K loop per tile.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_update(int K, const int32_t* __restrict__ nt,
-                                                               const int64_t* __restrict__ off,
-                                                               T* __restrict__ fac) {
-  const int b = blockIdx.y;
-  int a, c;
-  tri_decode(blockIdx.x, &a, &c);
-  const int I = K + 1 + a, J = K + 1 + c;
-  if (I >= nt[b]) return;
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_partial(int J, int maxc,
+                                                                const int32_t* __restrict__ nt,
+                                                                const int64_t* __restrict__ off,
+                                                                const T* __restrict__ fac,
+                                                                T* __restrict__ part) {
+  const int I = J + blockIdx.x;
+  const int c = blockIdx.y;
+  if (I >= nt[0]) return;
+  const int k0 = c * SPLITK, k1 = min(J, k0 + SPLITK);
   extern __shared__ unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
-  T* F = fac + off[b] * TS2;
-  TileAcc<T> acc;
-  acc.load(F + tri_index(I, J) * TS2);
-  stage_tile(sA, F + tri_index(I, K) * TS2);
-  stage_tile(sB, F + tri_index(J, K) * TS2);
-  __syncthreads();
-  tile_mma<T, false, true>(acc, sA, sB, T(-1));
-  acc.store(F + tri_index(I, J) * TS2);
-}
-
-template <typename T>
-void launch_potrf_update(int K, int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac,
-                         hipStream_t s) {
-  const int m = max_nt - 1 - K;
-  if (m <= 0) return;
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
-  static bool once = (allow_lds(k_potrf_update<T>, sh), true);
-  (void)once;
-  hipLaunchKernelGGL(k_potrf_update<T>, dim3(m * (m + 1) / 2, nb), dim3(TILE_THREADS), sh, s, K, nt,
-                     off, fac);
-}
-
-// X = L^{-1} right-looking, for matrices too few to fill the GPU by batch:
-// X starts as the identity; step K makes row K final, X_KJ = L_KK^{-1} X_KJ
-// (J <= K), then removes it from the rows below, X_IJ -= L_IK X_KJ (I > K).
-template <typename T>
-__global__ void k_identity_tiles(const int32_t* __restrict__ nt, const int64_t* __restrict__ off,
-                                 T* __restrict__ X) {
-  const int b = blockIdx.y;
-  const int ntb = nt[b];
-  const int64_t ntiles = (int64_t)ntb * (ntb + 1) / 2;
-  T* Xb = X + off[b] * TS2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * TS2;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t t = e / TS2;
-    int a, c;
-    tri_decode(t, &a, &c);
-    const int r = (int)((e % TS2) / TS), q = (int)(e % TS);
-    Xb[e] = (a == c && r == q) ? T(1) : T(0);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_trtri_row(int K, const int32_t* __restrict__ nt,
-                                                            const int64_t* __restrict__ off,
-                                                            const T* __restrict__ L,
-                                                            T* __restrict__ X) {
-  const int b = blockIdx.y;
-  const int J = blockIdx.x;
-  if (K >= nt[b] || J > K) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
-  const T* Lb = L + off[b] * TS2;
-  T* Xb = X + off[b] * TS2;
-  stage_tile(sA, Lb + tri_index(K, K) * TS2);
-  stage_tile(sB, Xb + tri_index(K, J) * TS2);
-  __syncthreads();
+  const T* F = fac + off[0] * TS2;
   TileAcc<T> acc;
   acc.zero();
-  tile_mma<T, false, false>(acc, sA, sB, T(1));
-  __syncthreads();
-  acc.store(Xb + tri_index(K, J) * TS2);
-}
-
-template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_trtri_update(int K, const int32_t* __restrict__ nt,
-                                                               const int64_t* __restrict__ off,
-                                                               const T* __restrict__ L,
-                                                               T* __restrict__ X) {
-  const int b = blockIdx.y;
-  const int ntb = nt[b];
-  const int I = K + 1 + (int)(blockIdx.x / (K + 1));
-  const int J = (int)(blockIdx.x % (K + 1));
-  if (I >= ntb) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
-  const T* Lb = L + off[b] * TS2;
-  T* Xb = X + off[b] * TS2;
-  TileAcc<T> acc;
-  acc.load(Xb + tri_index(I, J) * TS2);
-  stage_tile(sA, Lb + tri_index(I, K) * TS2);
-  stage_tile(sB, Xb + tri_index(K, J) * TS2);
-  __syncthreads();
-  tile_mma<T, false, false>(acc, sA, sB, T(-1));
-  acc.store(Xb + tri_index(I, J) * TS2);
-}
-
-template <typename T>
-void launch_trtri_rl(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* L, T* X,
-                     hipStream_t s) {
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
-  static bool once = (allow_lds(k_trtri_row<T>, sh), allow_lds(k_trtri_update<T>, sh), true);
-  (void)once;
-  hipLaunchKernelGGL(k_identity_tiles<T>, dim3(1024, nb), dim3(256), 0, s, nt, off, X);
-  for (int K = 0; K < max_nt; ++K) {
-    hipLaunchKernelGGL(k_trtri_row<T>, dim3(K + 1, nb), dim3(TILE_THREADS), sh, s, K, nt, off, L, X);
-    const int m = max_nt - 1 - K;
-    if (m > 0)
-      hipLaunchKernelGGL(k_trtri_update<T>, dim3(m * (K + 1), nb), dim3(TILE_THREADS), sh, s, K, nt,
-                         off, L, X);
+  TileRegs<T> ra, rb;
+  ra.load(F + tri_index(I, k0) * TS2);
+  rb.load(F + tri_index(J, k0) * TS2);
+  for (int K = k0; K < k1; ++K) {
+    __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 < k1) {
+      ra.load(F + tri_index(I, K + 1) * TS2);
+      rb.load(F + tri_index(J, K + 1) * TS2);
+    }
+    tile_mma<T, false, true>(acc, sA, sB, T(1));
   }
+  acc.store(part + ((int64_t)I * maxc + c) * TS2);
+}
+
+template <typename T>
+void launch_potrf_partial(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
+                          const T* fac, T* part, hipStream_t s) {
+  const int nc = (J + SPLITK - 1) / SPLITK;
+  if (nc == 0) return;
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_potrf_partial<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_potrf_partial<T>, dim3(max_nt - J, nc), dim3(TILE_THREADS), sh, s, J, maxc,
+                     nt, off, fac, part);
+  (void)maxc;
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -310,13 +254,21 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_col(int J, const int32_t
   }
   TileAcc<T> acc;
   acc.zero();
+  TileRegs<T> ra, rb;
+  ra.load(Xb + tri_index(I, J + 1) * TS2);
+  rb.load(Lb + tri_index(J + 1, J) * TS2);
   for (int K = J + 1; K <= I; ++K) {
-    stage_tile(sA, Xb + tri_index(I, K) * TS2);
-    stage_tile(sB, Lb + tri_index(K, J) * TS2);
     __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 <= I) {
+      ra.load(Xb + tri_index(I, K + 1) * TS2);
+      rb.load(Lb + tri_index(K + 1, J) * TS2);
+    }
     tile_mma<T, false, false>(acc, sA, sB, T(1));
-    __syncthreads();
   }
+  __syncthreads();
   acc.store_lds(sA);
   stage_tile(sB, Lb + tri_index(J, J) * TS2);
   __syncthreads();
@@ -334,6 +286,92 @@ void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_
   (void)once;
   hipLaunchKernelGGL(k_trtri_col<T>, dim3(max_nt - J, nb), dim3(TILE_THREADS), sh, s, J, nt, off, L,
                      X);
+}
+
+// Split-K form of the column step above for one matrix (batch 1):
+// k_trtri_partial computes part[I][c] = sum_{K in chunk c} X_IK L_KJ over the
+// chunks c of [J+1, I]; k_trtri_finish sums them and applies -L_JJ^{-1}.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_partial(int J, int maxc,
+                                                                const int32_t* __restrict__ nt,
+                                                                const int64_t* __restrict__ off,
+                                                                const T* __restrict__ L,
+                                                                const T* __restrict__ X,
+                                                                T* __restrict__ part) {
+  const int I = J + 1 + blockIdx.x;
+  const int c = blockIdx.y;
+  const int k0 = J + 1 + c * SPLITK;
+  if (I >= nt[0] || k0 > I) return;
+  const int k1 = min(I + 1, k0 + SPLITK);
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  const T* Lb = L + off[0] * TS2;
+  const T* Xb = X + off[0] * TS2;
+  TileAcc<T> acc;
+  acc.zero();
+  TileRegs<T> ra, rb;
+  ra.load(Xb + tri_index(I, k0) * TS2);
+  rb.load(Lb + tri_index(k0, J) * TS2);
+  for (int K = k0; K < k1; ++K) {
+    __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 < k1) {
+      ra.load(Xb + tri_index(I, K + 1) * TS2);
+      rb.load(Lb + tri_index(K + 1, J) * TS2);
+    }
+    tile_mma<T, false, false>(acc, sA, sB, T(1));
+  }
+  acc.store(part + ((int64_t)I * maxc + c) * TS2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_finish(int J, int maxc,
+                                                               const int32_t* __restrict__ nt,
+                                                               const int64_t* __restrict__ off,
+                                                               const T* __restrict__ L,
+                                                               T* __restrict__ X,
+                                                               const T* __restrict__ part) {
+  const int I = J + blockIdx.x;
+  if (I >= nt[0]) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  const T* Lb = L + off[0] * TS2;
+  T* Xb = X + off[0] * TS2;
+  if (I == J) {
+    const T* src = Lb + tri_index(J, J) * TS2;
+    T* dst = Xb + tri_index(J, J) * TS2;
+    for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) dst[e] = src[e];
+    return;
+  }
+  TileAcc<T> acc;
+  acc.zero();
+  const int np = (I - J + SPLITK - 1) / SPLITK;
+  for (int c = 0; c < np; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);  // acc = -sum
+  acc.store_lds(sA);
+  stage_tile(sB, Lb + tri_index(J, J) * TS2);
+  __syncthreads();
+  TileAcc<T> out;
+  out.zero();
+  tile_mma<T, false, false>(out, sA, sB, T(1));
+  out.store(Xb + tri_index(I, J) * TS2);
+}
+
+template <typename T>
+void launch_trtri_splitk(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
+                         const T* L, T* X, T* part, hipStream_t s) {
+  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  static bool once = (allow_lds(k_trtri_partial<T>, sh), allow_lds(k_trtri_finish<T>, sh), true);
+  (void)once;
+  const int m = max_nt - 1 - J;
+  if (m > 0)
+    hipLaunchKernelGGL(k_trtri_partial<T>, dim3(m, (m + SPLITK - 1) / SPLITK), dim3(TILE_THREADS), sh,
+                       s, J, maxc, nt, off, L, X, part);
+  hipLaunchKernelGGL(k_trtri_finish<T>, dim3(max_nt - J), dim3(TILE_THREADS), sh, s, J, maxc, nt, off,
+                     L, X, part);
 }
 
 // M = X^T X = A^{-1} from X = L^{-1}:  M_IJ = sum_{K >= I} X_KI^T X_KJ, I >= J.
@@ -357,12 +395,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restric
   const T* Xb = X + off[b] * TS2;
   TileAcc<T> acc;
   acc.zero();
+  TileRegs<T> ra, rb;
+  ra.load(Xb + tri_index(I, I) * TS2);
+  rb.load(Xb + tri_index(I, J) * TS2);
   for (int K = I; K < ntb; ++K) {
-    stage_tile(sA, Xb + tri_index(K, I) * TS2);
-    stage_tile(sB, Xb + tri_index(K, J) * TS2);
     __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 < ntb) {
+      ra.load(Xb + tri_index(K + 1, I) * TS2);
+      rb.load(Xb + tri_index(K + 1, J) * TS2);
+    }
     tile_mma<T, true, false>(acc, sA, sB, T(1));
-    __syncthreads();
   }
   acc.store(M + off[b] * TS2 + tri_index(I, J) * TS2);
 }
@@ -378,14 +423,14 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 }
 
 #define INST(T)                                                                                    \
-  template void launch_potrf_diag<T>(int, int, int, const int32_t*, const int64_t*, T*, int32_t*,   \
-                                     hipStream_t);                                                 \
-  template void launch_potrf_panel<T>(int, int, int, int, const int32_t*, const int64_t*, T*,      \
-                                      hipStream_t);                                                \
-  template void launch_potrf_update<T>(int, int, int, const int32_t*, const int64_t*, T*,          \
-                                       hipStream_t);                                               \
-  template void launch_trtri_rl<T>(int, int, const int32_t*, const int64_t*, const T*, T*,         \
-                                   hipStream_t);                                                   \
+  template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
+                                     const int64_t*, T*, int32_t*, hipStream_t);                   \
+  template void launch_potrf_panel<T>(int, int, int, int, const T*, int, int, const int32_t*,      \
+                                      const int64_t*, T*, hipStream_t);                            \
+  template void launch_potrf_partial<T>(int, int, int, const int32_t*, const int64_t*, const T*,  \
+                                        T*, hipStream_t);                                          \
+  template void launch_trtri_splitk<T>(int, int, int, const int32_t*, const int64_t*, const T*,   \
+                                       T*, T*, hipStream_t);                                       \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t);

@@ -44,17 +44,18 @@ void launch_coarse_pad(int N0, int nt0, double* A0, hipStream_t s);
 
 // ---- batched tiled Cholesky, inversion ----------------------------------
 template <typename T>
-void launch_potrf_diag(int J, int left, int nb, const int32_t* nt, const int64_t* off, T* fac,
-                       int32_t* status, hipStream_t s);
+void launch_potrf_diag(int J, int left, int nparts, int maxc, const T* part, int nb,
+                       const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
+                       hipStream_t s);
 template <typename T>
-void launch_potrf_panel(int J, int left, int nb, int max_nt, const int32_t* nt, const int64_t* off,
-                        T* fac, hipStream_t s);
+void launch_potrf_panel(int J, int left, int nparts, int maxc, const T* part, int nb, int max_nt,
+                        const int32_t* nt, const int64_t* off, T* fac, hipStream_t s);
 template <typename T>
-void launch_potrf_update(int K, int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac,
-                         hipStream_t s);
+void launch_potrf_partial(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
+                          const T* fac, T* part, hipStream_t s);
 template <typename T>
-void launch_trtri_rl(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* L, T* X,
-                     hipStream_t s);
+void launch_trtri_splitk(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
+                         const T* L, T* X, T* part, hipStream_t s);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);

@@ -51,6 +51,7 @@ struct sfcdd_ctx {
   GridDesc g{};
   PartDesc pd{};
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // internal, default priority: coarse setup overlaps the fine factorisation
   // host partition
   std::vector<int32_t> ta, Ni, nt;
   std::vector<int64_t> off, doff, xoff, poff;
@@ -61,7 +62,7 @@ struct sfcdd_ctx {
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff, r_omega, r_fac,
       r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cmeta, r_dbuf, r_vec, r_partials,
-      r_scal, r_status, r_gout;
+      r_scal, r_status, r_gout, r_cpartk;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // convenience device pointers
@@ -71,6 +72,7 @@ struct sfcdd_ctx {
   double* d_omega = nullptr;
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
+  double* cpartk = nullptr;  // split-K partial tiles of the coarse factorisation
   int32_t *c_nt = nullptr, *c_n = nullptr;
   int64_t *c_off = nullptr, *c_xoff = nullptr, *c_poff = nullptr, *c_doff = nullptr;
   double* dbuf = nullptr;
@@ -380,6 +382,7 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
   c->r_d0 = pl.take((size_t)c->nt0 * TS * 8);
   c->r_cpart = pl.take((size_t)c->nt0 * c->nt0 * TS * 8);
   c->r_cmeta = pl.take(64);
+  c->r_cpartk = pl.take((size_t)c->nt0 * ((c->nt0 + SPLITK - 1) / SPLITK) * TS2 * 8);
   c->r_dbuf = pl.take((size_t)c->sum_Ni * 8);
   c->r_vec = pl.take((size_t)NVEC * (((size_t)N * 8 + 255) & ~size_t(255)));
   c->r_partials = pl.take((size_t)MAXD * RED_BLOCKS * 8);
@@ -415,6 +418,7 @@ void bind(sfcdd_ctx* c) {
   c->c0 = at<double>(c, c->r_c0);
   c->d0 = at<double>(c, c->r_d0);
   c->cpart = at<double>(c, c->r_cpart);
+  c->cpartk = at<double>(c, c->r_cpartk);
   unsigned char* cm = c->ws + c->r_cmeta.off;
   c->c_off = reinterpret_cast<int64_t*>(cm);       // 0
   c->c_xoff = reinterpret_cast<int64_t*>(cm + 8);  // 0
@@ -434,23 +438,28 @@ void bind(sfcdd_ctx* c) {
 
 // Batched left-looking tiled Cholesky of nb packed matrices (+ optional
 // inversion into M = A^{-1} via X = L^{-1}, M = X^T X).
-// Left-looking when the batch alone fills the GPU (each workgroup keeps its
-// output tile in registers across the K loop); right-looking when there are
-// too few matrices, so that every tile update of a step runs in parallel.
+// Batched left-looking factorisation: each workgroup keeps its output tile in
+// registers across the K loop.  A single matrix (part != nullptr) uses the
+// split-K form instead, so that every column step runs on many workgroups.
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
-                  bool invert, int32_t* status, hipStream_t s) {
-  const bool left = (int64_t)nb * max_nt >= 1024;
+                  bool invert, int32_t* status, T* part, hipStream_t s) {
+  const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   for (int J = 0; J < max_nt; ++J) {
-    launch_potrf_diag<T>(J, left ? 1 : 0, nb, nt, off, fac, status, s);
-    launch_potrf_panel<T>(J, left ? 1 : 0, nb, max_nt, nt, off, fac, s);
-    if (!left) launch_potrf_update<T>(J, nb, max_nt, nt, off, fac, s);
+    if (part) {
+      launch_potrf_partial<T>(J, max_nt, maxc, nt, off, fac, part, s);
+      const int np = (J + SPLITK - 1) / SPLITK;
+      launch_potrf_diag<T>(J, 0, np, maxc, part, 1, nt, off, fac, status, s);
+      launch_potrf_panel<T>(J, 0, np, maxc, part, 1, max_nt, nt, off, fac, s);
+    } else {
+      launch_potrf_diag<T>(J, 1, 0, 0, (const T*)nullptr, nb, nt, off, fac, status, s);
+      launch_potrf_panel<T>(J, 1, 0, 0, (const T*)nullptr, nb, max_nt, nt, off, fac, s);
+    }
   }
   if (invert) {
-    if (left) {
-      for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
-    } else {
-      launch_trtri_rl<T>(nb, max_nt, nt, off, fac, X, s);
+    for (int J = max_nt - 1; J >= 0; --J) {
+      if (part) launch_trtri_splitk<T>(J, max_nt, maxc, nt, off, fac, X, part, s);
+      else launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
     }
     launch_lauum<T>(nb, max_nt, nt, off, X, fac, s);
   }
@@ -641,6 +650,38 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   launch_build_nbr(c->g, c->pos, c->sfc_index, c->nbr, s);
   HIPCHK(c, hipEventRecord(ev[2], s));
 
+  // The coarse setup (one matrix, latency-bound right-looking steps) runs on
+  // an internal stream forked from the caller's, concurrently with the
+  // batched subdomain factorisation; both join before setup returns.
+  hipEvent_t fork, join;
+  HIPCHK(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  HIPCHK(c, hipEventRecord(fork, s));
+  HIPCHK(c, hipStreamWaitEvent(c->side, fork, 0));
+  hipEvent_t cev0, cev1;
+  HIPCHK(c, hipEventCreate(&cev0));
+  HIPCHK(c, hipEventCreate(&cev1));
+  {
+    const hipStream_t cs = c->side;
+    HIPCHK(c, hipEventRecord(cev0, cs));
+    // coarse matrix A_0 = R_0 A R_0^T = sum_j c_j E_j (eq. csm), then A_0^{-1}
+    HIPCHK(c, hipMemsetAsync(c->A0, 0, c->r_A0.bytes, cs));
+    HIPCHK(c, hipMemsetAsync(c->c0, 0, c->r_c0.bytes, cs));
+    const int64_t ctiles_elems = (int64_t)c->nt0 * (c->nt0 + 1) / 2 * TS2;
+    for (int j = 0; j < c->d; ++j) {
+      HIPCHK(c, hipMemsetAsync(c->X0, 0, (size_t)ctiles_elems * 4, cs));
+      launch_coarse_counts(c->g, c->pd, j, c->nbr, (int32_t*)c->X0, cs);
+      launch_coarse_accumulate(ctiles_elems, c->g.c[j], (const int32_t*)c->X0, c->A0, cs);
+    }
+    launch_coarse_pad(c->N0, c->nt0, c->A0, cs);
+    factor_batch<double>(1, c->nt0, c->c_nt, c->c_off, c->A0, c->X0, true, c->status + 1,
+                         c->cpartk, cs);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(cev1, cs));
+    HIPCHK(c, hipEventRecord(join, cs));
+  }
+
   // local matrices A_i = R_i A R_i^T
   HIPCHK(c, hipMemsetAsync(c->fac, 0, c->r_fac.bytes, s));
   if (c->fdtype == SFCDD_FP32)
@@ -656,33 +697,27 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(P, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv,
-                        c->status, s);
+                        c->status, (float*)nullptr, s);
   else
     factor_batch<double>(P, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv,
-                         c->status, s);
+                         c->status, (double*)nullptr, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
-
-  // coarse matrix A_0 = R_0 A R_0^T = sum_j c_j E_j (eq. csm), then A_0^{-1}
-  HIPCHK(c, hipMemsetAsync(c->A0, 0, c->r_A0.bytes, s));
-  HIPCHK(c, hipMemsetAsync(c->c0, 0, c->r_c0.bytes, s));
-  const int64_t ctiles_elems = (int64_t)c->nt0 * (c->nt0 + 1) / 2 * TS2;
-  for (int j = 0; j < c->d; ++j) {
-    HIPCHK(c, hipMemsetAsync(c->X0, 0, (size_t)ctiles_elems * 4, s));
-    launch_coarse_counts(c->g, c->pd, j, c->nbr, (int32_t*)c->X0, s);
-    launch_coarse_accumulate(ctiles_elems, c->g.c[j], (const int32_t*)c->X0, c->A0, s);
-  }
-  launch_coarse_pad(c->N0, c->nt0, c->A0, s);
-  factor_batch<double>(1, c->nt0, c->c_nt, c->c_off, c->A0, c->X0, true, c->status, s);
-  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamWaitEvent(s, join, 0));
   HIPCHK(c, hipEventRecord(ev[5], s));
   HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, hipStreamSynchronize(c->side));
 
   float ms[5];
-  for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+  for (int k = 0; k < 4; ++k) HIPCHK(c, hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+  HIPCHK(c, hipEventElapsedTime(&ms[4], cev0, cev1));  // coarse setup (overlapped)
   float tot;
   HIPCHK(c, hipEventElapsedTime(&tot, ev[0], ev[5]));
   for (auto& e : ev) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(cev0);
+  (void)hipEventDestroy(cev1);
+  (void)hipEventDestroy(fork);
+  (void)hipEventDestroy(join);
   sfcdd_info& I = c->info;
   I.N = c->g.N;
   I.P = c->P;
@@ -701,9 +736,10 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   for (int k = 0; k < 5; ++k) I.setup_ms[k] = ms[k];
   I.setup_ms[5] = tot;
 
-  int32_t stat = 0;
-  HIPCHK(c, hipMemcpy(&stat, c->status, 4, hipMemcpyDeviceToHost));
-  if (stat != 0) FAIL(c, SFCDD_ENOTSPD, "a local or coarse matrix is not positive definite");
+  int32_t stat[2] = {0, 0};
+  HIPCHK(c, hipMemcpy(stat, c->status, 8, hipMemcpyDeviceToHost));
+  if (stat[0] != 0) FAIL(c, SFCDD_ENOTSPD, "a local matrix is not positive definite");
+  if (stat[1] != 0) FAIL(c, SFCDD_ENOTSPD, "the coarse matrix is not positive definite");
   return SFCDD_OK;
 }
 
@@ -955,6 +991,7 @@ sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (!c) return SFCDD_OK;
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
   return SFCDD_OK;
 }
