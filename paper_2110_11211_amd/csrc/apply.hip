@@ -106,7 +106,7 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   const int b = blockIdx.x;
   const int ntb = nt[b], n = Ni[b];
   const int64_t t0 = ta[b];
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* y = reinterpret_cast<T*>(smem_raw);    // ntb * TS
   T* sS = y + ntb * TS;                     // TS
   T* red = sS + TS;                         // W * TS

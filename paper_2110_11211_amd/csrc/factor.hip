@@ -21,51 +21,148 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Unblocked Cholesky of a TS x TS LDS tile followed by the inversion of the
-// factor, both done by the first wave alone with no workgroup barrier inside
-// (a single wave issues its LDS operations in program order).
-// Factoring: lane i owns row i of the tile in LDS; at step k every lane reads
-// the pivot and column k by broadcast.  Inverting: lane c keeps column c of
-// X = L^{-1} in registers and sweeps the columns of L left to right.
-// On exit sX holds L^{-1} (lower, zeros above) and sC holds L (lower).
+// Row stride of the LDS buffers of the diagonal-tile factorisation: 16-byte
+// aligned rows whose 16-byte chunks fall in distinct bank groups for 8
+// consecutive rows (66 doubles, 68 floats).
+template <typename T> struct Pstride { static constexpr int v = (sizeof(T) == 8) ? 66 : 68; };
+
+constexpr int DB = 16;         // block edge inside the diagonal tile
+constexpr int NDB = TS / DB;   // blocks per tile edge
+
+// Cholesky factor and inverse of one DB x DB diagonal block at (o, o) of sC,
+// by lanes 0..DB-1 of the first wave alone (one wave issues its LDS
+// operations in program order, so no barrier is needed inside):
+// factoring, lane i owns block row i; inverting, lane c owns column c of the
+// inverse, written to dinv (row-major DB x DB, lower).
+template <typename T>
+__device__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv,
+                             T* __restrict__ colbuf, int32_t* status) {
+  constexpr int PS = Pstride<T>::v;
+  const int i = threadIdx.x;
+  if (i >= DB) return;
+  for (int k = 0; k < DB; ++k) {
+    T piv = sC[(o + k) * PS + o + k];
+    if (!(piv > T(0))) {
+      if (i == k) atomicExch(status, -6);
+      piv = T(1);
+    }
+    const T dk = sqrt(piv);
+    const T rdk = T(1) / dk;
+    const T l = (i > k) ? sC[(o + i) * PS + o + k] * rdk : (i == k ? dk : T(0));
+    if (i >= k) sC[(o + i) * PS + o + k] = l;
+    colbuf[i] = (i > k) ? l : T(0);
+#pragma unroll
+    for (int j = 0; j < DB; ++j)
+      if (j > k) sC[(o + i) * PS + o + j] -= l * colbuf[j];
+  }
+  // inverse of the DB x DB lower factor, column c per lane
+  const int c = i;
+  T x[DB];
+#pragma unroll
+  for (int r = 0; r < DB; ++r) x[r] = (r == c) ? T(1) : T(0);
+#pragma unroll
+  for (int k = 0; k < DB; ++k) {
+    x[k] = x[k] / sC[(o + k) * PS + o + k];
+#pragma unroll
+    for (int r = k + 1; r < DB; ++r) x[r] -= sC[(o + r) * PS + o + k] * x[k];
+  }
+#pragma unroll
+  for (int r = 0; r < DB; ++r) dinv[r * DB + c] = x[r];
+}
+
+// Cholesky factorisation and inversion of a TS x TS LDS tile (stride
+// Pstride, lower part read), blocked by DB: the DB x DB diagonal blocks are
+// factored and inverted by one wave, the panels, trailing updates and the
+// off-diagonal blocks of the inverse by the whole workgroup.
+// On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).
 // A non-positive pivot sets *status to -6 and is replaced by 1.
 template <typename T>
-__device__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
+__device__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, T* __restrict__ dinv,
+                               T* __restrict__ colbuf, int32_t* status) {
+  constexpr int PS = Pstride<T>::v;
+  const int tid = threadIdx.x;
   __syncthreads();
-  if (threadIdx.x < TS) {
-    const int i = threadIdx.x;
-    T* __restrict__ col = sX;  // column k of L for the update; sX is written only at the end
-    for (int k = 0; k < TS; ++k) {
-      T piv = sC[k * LDS_S + k];
-      if (!(piv > T(0))) {
-        if (i == k) atomicExch(status, -6);
-        piv = T(1);
+  for (int bk = 0; bk < NDB; ++bk) {
+    const int o = bk * DB;
+    factor_block(sC, o, dinv + bk * DB * DB, colbuf, status);
+    __syncthreads();
+    // panel: L[r][o..o+DB) = C[r][o..o+DB) Dinv^T for rows below the block
+    const int nrow = TS - o - DB;
+    T pv[(TS - DB) * DB / TILE_THREADS];
+    const T* Di = dinv + bk * DB * DB;
+#pragma unroll
+    for (int q = 0; q < (TS - DB) * DB / TILE_THREADS; ++q) {
+      const int t = tid + q * TILE_THREADS;
+      pv[q] = T(0);
+      if (t < nrow * DB) {
+        const int r = o + DB + t / DB, cc = t % DB;
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < DB; ++m) acc += sC[r * PS + o + m] * Di[cc * DB + m];
+        pv[q] = acc;
       }
-      const T dk = sqrt(piv);
-      const T rdk = T(1) / dk;
-      const T l = (i > k) ? sC[i * LDS_S + k] * rdk : (i == k ? dk : T(0));
-      if (i >= k) sC[i * LDS_S + k] = l;
-      col[i] = l;
-#pragma unroll 8
-      for (int j = k + 1; j < TS; ++j)
-        if (j <= i) sC[i * LDS_S + j] -= l * col[j];
     }
-    const int c = threadIdx.x;
-    T b[TS];
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < TS; ++r) b[r] = (r == c) ? T(1) : T(0);
-#pragma unroll
-    for (int k = 0; k < TS; ++k) {
-      __asm__ volatile("" ::: "memory");
-      const T xk = b[k] * (T(1) / sC[k * LDS_S + k]);
-      b[k] = xk;
-#pragma unroll
-      for (int r = k + 1; r < TS; ++r) b[r] -= sC[r * LDS_S + k] * xk;
+    for (int q = 0; q < (TS - DB) * DB / TILE_THREADS; ++q) {
+      const int t = tid + q * TILE_THREADS;
+      if (t < nrow * DB) sC[(o + DB + t / DB) * PS + o + t % DB] = pv[q];
     }
+    __syncthreads();
+    // trailing update of the lower part below and right of the block:
+    // C[i][j] -= sum_m L[i][o+m] L[j][o+m] for o+DB <= j <= i
+    const int m0 = o + DB;
+    const int span = TS - m0;
+    for (int e = tid; e < span * span; e += TILE_THREADS) {
+      const int i = m0 + e / span, j = m0 + e % span;
+      if (j > i) continue;
+      T acc = T(0);
 #pragma unroll
-    for (int r = 0; r < TS; ++r) sX[r * LDS_S + c] = b[r];
+      for (int m = 0; m < DB; ++m) acc += sC[i * PS + o + m] * sC[j * PS + o + m];
+      sC[i * PS + j] -= acc;
+    }
+    __syncthreads();
+  }
+  // X = L^{-1} by block rows: X_II = Dinv_I,
+  // X_IJ = -Dinv_I sum_{K=J}^{I-1} L_IK X_KJ for J < I.
+  for (int e = tid; e < TS * TS; e += TILE_THREADS) {
+    const int r = e / TS, cc = e % TS;
+    const int I = r / DB, J = cc / DB;
+    sX[r * PS + cc] = (I == J) ? dinv[I * DB * DB + (r % DB) * DB + (cc % DB)] : T(0);
   }
   __syncthreads();
+  T* tmp = sC;  // upper part of sC is free: tmp block (I, J) stored at rows of J, columns of I
+  for (int I = 1; I < NDB; ++I) {
+    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ for J < I, one element per thread
+    for (int e = tid; e < I * DB * DB; e += TILE_THREADS) {
+      const int J = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
+      T acc = T(0);
+      for (int K = J; K < I; ++K) {
+#pragma unroll
+        for (int m = 0; m < DB; ++m)
+          acc += sC[(I * DB + r) * PS + K * DB + m] * sX[(K * DB + m) * PS + J * DB + cc];
+      }
+      tmp[(J * DB + cc) * PS + I * DB + r] = acc;  // transposed into the free upper part
+    }
+    __syncthreads();
+    for (int e = tid; e < I * DB * DB; e += TILE_THREADS) {
+      const int J = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
+      T acc = T(0);
+#pragma unroll
+      for (int m = 0; m < DB; ++m)
+        acc += dinv[I * DB * DB + r * DB + m] * tmp[(J * DB + cc) * PS + I * DB + m];
+      sX[(I * DB + r) * PS + J * DB + cc] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+// LDS of the diagonal kernel: two Pstride tiles (C, X), the DB x DB block
+// inverses and a column buffer.  The GEMM staging (two LDS_S tiles) fits in
+// the same space.
+template <typename T>
+constexpr size_t diag_lds_bytes() {
+  return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + TS) * sizeof(T);
 }
 
 // left != 0: left-looking, the tile first receives -sum_{K<J} L_JK L_JK^T
@@ -80,9 +177,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left, in
                                                              int32_t* __restrict__ status) {
   const int b = blockIdx.x;
   if (J >= nt[b]) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
   T* F = fac + off[b] * TS2;
   TileAcc<T> acc;
   acc.load(F + tri_index(J, J) * TS2);
@@ -98,12 +194,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left, in
     tile_mma<T, false, true>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
   }
   __syncthreads();
-  acc.store_lds(sA);
-  potrf_inv_tile(sA, sB, status);
+  constexpr int PS = Pstride<T>::v;
+  T* sC = reinterpret_cast<T*>(smem_raw);
+  T* sX = sC + TS * PS;
+  T* dinv = sX + TS * PS;
+  T* colbuf = dinv + NDB * DB * DB;
+  for (int a = 0; a < 2; ++a)
+    for (int b2 = 0; b2 < 2; ++b2)
+      for (int r = 0; r < 4; ++r) sC[TileAcc<T>::row(a, r) * PS + TileAcc<T>::col(b2)] = acc.c[a][b2][r];
+  potrf_inv_tile(sC, sX, dinv, colbuf, status);
   T* D = F + tri_index(J, J) * TS2;
   for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
     const int i = e / TS, j = e % TS;
-    D[e] = j <= i ? sB[i * LDS_S + j] : T(0);
+    D[e] = j <= i ? sX[i * PS + j] : T(0);
   }
 }
 
@@ -116,7 +219,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left, i
   const int b = blockIdx.y;
   const int I = J + 1 + blockIdx.x;
   if (I >= nt[b]) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
   T* F = fac + off[b] * TS2;
@@ -162,7 +265,7 @@ template <typename T>
 void launch_potrf_diag(int J, int left, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s) {
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  const size_t sh = diag_lds_bytes<T>();
   static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, left, nparts, maxc,
@@ -193,7 +296,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_partial(int J, int maxc,
   const int c = blockIdx.y;
   if (I >= nt[0]) return;
   const int k0 = c * SPLITK, k1 = min(J, k0 + SPLITK);
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
   const T* F = fac + off[0] * TS2;
@@ -241,7 +344,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_col(int J, const int32_t
   const int b = blockIdx.y;
   const int I = J + blockIdx.x;
   if (I >= nt[b]) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
   const T* Lb = L + off[b] * TS2;
@@ -303,7 +406,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_partial(int J, int maxc,
   const int k0 = J + 1 + c * SPLITK;
   if (I >= nt[0] || k0 > I) return;
   const int k1 = min(I + 1, k0 + SPLITK);
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
   const T* Lb = L + off[0] * TS2;
@@ -336,7 +439,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_finish(int J, int maxc,
                                                                const T* __restrict__ part) {
   const int I = J + blockIdx.x;
   if (I >= nt[0]) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
   const T* Lb = L + off[0] * TS2;
@@ -389,7 +492,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restric
   while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
   while ((int64_t)I * (I + 1) / 2 > t) --I;
   const int J = (int)(t - (int64_t)I * (I + 1) / 2);
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
   const T* Xb = X + off[b] * TS2;
