@@ -100,12 +100,18 @@ typedef struct {
   double setup_ms[6];        /* sfc rank, neighbours, assembly, subdomain factorisation,
                                 coarse setup (runs concurrently with the factorisation),
                                 total                                                  */
+  int32_t ngrids;            /* grids in the context (1 unless set up as a batch)      */
+  int32_t trsv_waves;        /* waves per workgroup of the substitution kernel          */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1
  * inputs d, l, P, gamma, q).  Validates the parameters: EINVAL for sizes out
  * of range, EOVERFLOW when N >= 2^31 or d * max_j l_j > 64. */
 sfcdd_status sfcdd_workspace_size(const sfcdd_params* params, size_t* bytes);
+
+/* Workspace bytes for a batch of ngrids independent grids (params[ngrids]);
+ * see sfcdd_setup_batch. */
+sfcdd_status sfcdd_workspace_size_batch(int32_t ngrids, const sfcdd_params* params, size_t* bytes);
 
 /* Setup phase (Alg. 1): curve order of the grid points, disjoint pieces
  * (eq. sloc), overlapping subdomains (eq. enlarge, cyclic), weights
@@ -116,6 +122,21 @@ sfcdd_status sfcdd_workspace_size(const sfcdd_params* params, size_t* bytes);
  * ENOTSPD if a factorisation breaks down. */
 sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t bytes,
                          void* hip_stream, sfcdd_ctx** out);
+
+/* Setup of a batch of ngrids (1..65535) independent subproblems, e.g. all
+ * subgrids of one layer of the combination technique (Sec. 2, eq. combi; the
+ * subproblems are independent and solved in parallel), in one context: every
+ * setup phase and every operator of the solve runs as one launch over all
+ * grids.  params[ngrids] may differ in d, levels, coefficients, P, gamma and q;
+ * weighting, variant, factor_dtype, local_solver and layout must agree.
+ * Vectors of a batch context concatenate the grids in order: grid k owns the
+ * entries [sum_{k'<k} N_k', sum_{k'<=k} N_k').  sfcdd_solve then solves all
+ * grids, each to its own relative residual ||b_k - A_k x_k|| / ||b_k|| <= rtol
+ * (converged grids stop iterating); info reports the largest iteration count
+ * and residual, sfcdd_get_batch_stats the per-grid ones.  sfcdd_grad_coeff is
+ * not available for batches (EINVAL). */
+sfcdd_status sfcdd_setup_batch(int32_t ngrids, const sfcdd_params* params, void* workspace_dev,
+                               size_t bytes, void* hip_stream, sfcdd_ctx** out);
 
 /* h = C^{-1} g (Alg. 2; balanced form eq. balSW when variant = BALANCED).
  * g_dev, h_dev: device, N doubles each, may not alias.  Asynchronous. */
@@ -144,12 +165,26 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* ctx, const double* b_dev, double* x_dev, dou
 sfcdd_status sfcdd_grad_coeff(sfcdd_ctx* ctx, const double* lambda_dev, const double* u_dev,
                               double* grad_a_host);
 
-/* Copies the partition to host arrays (each may be NULL): sfc_index[N]
+/* Copies the partition of grid `grid` (0 for a single-grid context) to host
+ * arrays (each may be NULL), in the grid's own numbering: sfc_index[N]
  * (natural index of curve position p), ta[P] (first curve position of
  * Omega_i), Ni[P] (its size; Omega_i = {(ta_i + s) mod N : s < N_i}), omega[P]
  * (eq. omegai weight actually applied), q_out (coarse points per subdomain). */
-sfcdd_status sfcdd_get_partition(sfcdd_ctx* ctx, int32_t* sfc_index_host, int64_t* ta_host,
-                                 int64_t* Ni_host, double* omega_host, int32_t* q_out);
+sfcdd_status sfcdd_get_partition(sfcdd_ctx* ctx, int32_t grid, int32_t* sfc_index_host,
+                                 int64_t* ta_host, int64_t* Ni_host, double* omega_host,
+                                 int32_t* q_out);
+
+/* Per-grid outer iteration counts and final relative residuals of the last
+ * sfcdd_solve (host arrays of ngrids entries, each may be NULL). */
+sfcdd_status sfcdd_get_batch_stats(sfcdd_ctx* ctx, int32_t* iterations, double* rel_residual);
+
+/* Autotuner of the subdomain-solve kernel: times the substitution sweeps with
+ * 4, 8 and 16 waves per workgroup on the context's own factors (repeats runs
+ * each, events on the context's stream), keeps the fastest for all later
+ * applications, and returns its time per application in *best_ms (may be
+ * NULL).  With the explicit-inverse local solver there is nothing to tune and
+ * only the time is measured.  Synchronous. */
+sfcdd_status sfcdd_autotune(sfcdd_ctx* ctx, int32_t repeats, double* best_ms);
 
 /* The same partition computed on the host alone, before any setup (no GPU
  * needed): ta[P], Ni[P], omega[P] and q_out as in sfcdd_get_partition, each

@@ -30,8 +30,9 @@ LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
 METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}
 LAYOUT = {"natural": 0, "sfc": 1}
 
-EXPORTS = ["sfcdd_workspace_size", "sfcdd_setup", "sfcdd_apply_precond", "sfcdd_matvec",
-           "sfcdd_solve", "sfcdd_grad_coeff", "sfcdd_get_partition", "sfcdd_partition_host",
+EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
+           "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
+           "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
            "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_destroy",
            "sfcdd_last_error"]
 KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
@@ -63,7 +64,8 @@ class Info(ctypes.Structure):
                 ("N0", ctypes.c_int32), ("max_Ni", ctypes.c_int32), ("min_Ni", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("sum_Ni", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("factor_algo_bytes", ctypes.c_int64), ("coarse_bytes", ctypes.c_int64),
-                ("setup_ms", ctypes.c_double * 6)]
+                ("setup_ms", ctypes.c_double * 6), ("ngrids", ctypes.c_int32),
+                ("trsv_waves", ctypes.c_int32)]
 
 
 _lib = None
@@ -81,12 +83,16 @@ def lib() -> ctypes.CDLL:
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
     L.sfcdd_workspace_size.argtypes = [P(Params), P(ctypes.c_size_t)]
+    L.sfcdd_workspace_size_batch.argtypes = [i32, P(Params), P(ctypes.c_size_t)]
     L.sfcdd_setup.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(vp)]
+    L.sfcdd_setup_batch.argtypes = [i32, P(Params), vp, ctypes.c_size_t, vp, P(vp)]
+    L.sfcdd_get_batch_stats.argtypes = [vp, P(i32), P(dbl)]
+    L.sfcdd_autotune.argtypes = [vp, i32, P(dbl)]
     L.sfcdd_apply_precond.argtypes = [vp, vp, vp]
     L.sfcdd_matvec.argtypes = [vp, vp, vp]
     L.sfcdd_solve.argtypes = [vp, vp, vp, dbl, i32, i32, dbl, P(SolveInfo)]
     L.sfcdd_grad_coeff.argtypes = [vp, vp, vp, P(dbl)]
-    L.sfcdd_get_partition.argtypes = [vp, P(i32), P(i64), P(i64), P(dbl), P(i32)]
+    L.sfcdd_get_partition.argtypes = [vp, i32, P(i32), P(i64), P(i64), P(dbl), P(i32)]
     L.sfcdd_partition_host.argtypes = [P(Params), P(i64), P(i64), P(dbl), P(i32)]
     L.sfcdd_get_info.argtypes = [vp, P(Info)]
     L.sfcdd_set_profiling.argtypes = [vp, i32]
@@ -267,7 +273,7 @@ class SFCSchwarz:
         Ni = (ctypes.c_int64 * Pn)()
         om = (ctypes.c_double * Pn)()
         q = ctypes.c_int32()
-        _check(lib().sfcdd_get_partition(self.ctx, sfc, ta, Ni, om, ctypes.byref(q)), self.ctx)
+        _check(lib().sfcdd_get_partition(self.ctx, 0, sfc, ta, Ni, om, ctypes.byref(q)), self.ctx)
         return {"sfc_index": np.ctypeslib.as_array(sfc).astype(np.int64), "ta": np.array(ta[:]),
                 "Ni": np.array(Ni[:]), "omega": np.array(om[:]), "q": int(q.value)}
 
@@ -282,5 +288,102 @@ class SFCSchwarz:
         except Exception:
             pass
 
+
+class SFCSchwarzBatch(SFCSchwarz):
+    """Many independent grids in one context (e.g. one layer of the
+    combination technique): every setup phase and solver operator runs as one
+    launch over all grids.  `grids` is a list of dicts with the per-grid keys
+    levels / npts, coeff, P, gamma, q; the other options are shared.  Vectors
+    concatenate the grids in order (see `offsets`)."""
+
+    def __init__(self, grids, weighting: str = "omega", variant: str = "balanced",
+                 factor_dtype: str = "fp64", local_solver: str = "cholesky", layout: str = "natural",
+                 device="cuda:0", workspace=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("SFCSchwarzBatch needs a ROCm GPU device")
+        G = len(grids)
+        arr = (Params * G)()
+        self._keep = []
+        for k, gk in enumerate(grids):
+            prm, keep = make_params(levels=gk.get("levels"), npts=gk.get("npts"), coeff=gk.get("coeff"),
+                                    P=gk["P"], gamma=gk.get("gamma", Fraction(1, 2)), q=gk.get("q", 0),
+                                    weighting=weighting, variant=variant, factor_dtype=factor_dtype,
+                                    local_solver=local_solver, layout=layout)
+            arr[k] = prm
+            self._keep.append(keep)
+        self._arr = arr
+        self.kw = dict(P=sum(g["P"] for g in grids), weighting=weighting, variant=variant,
+                       factor_dtype=factor_dtype, local_solver=local_solver, layout=layout)
+        n = ctypes.c_size_t()
+        _check(lib().sfcdd_workspace_size_batch(G, arr, ctypes.byref(n)))
+        self.workspace_bytes = int(n.value)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            if workspace is not None:
+                if workspace.device != self.device or workspace.numel() < self.workspace_bytes + 256:
+                    raise ValueError("workspace tensor too small or on the wrong device")
+                self.ws = workspace
+            else:
+                self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            ctx = ctypes.c_void_p()
+            st = lib().sfcdd_setup_batch(G, arr, ctypes.c_void_p(self.ws.data_ptr()), self.workspace_bytes + 256,
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+            _check(st, None if not ctx.value else ctx)
+        self.ctx = ctx
+        inf = Info()
+        _check(lib().sfcdd_get_info(self.ctx, ctypes.byref(inf)), self.ctx)
+        self.N = int(inf.N)
+        self.G = G
+        self.d = None
+        self._info = inf
+        sizes = []
+        for gk in grids:
+            nn = [(1 << l) - 1 for l in gk["levels"]] if gk.get("levels") is not None else list(gk["npts"])
+            sizes.append(int(__import__("numpy").prod(nn)))
+        self.sizes = sizes
+        self.offsets = [0]
+        for v in sizes:
+            self.offsets.append(self.offsets[-1] + v)
+
+    def split(self, v):
+        """Per-grid views of a concatenated vector."""
+        return [v[self.offsets[k]:self.offsets[k + 1]] for k in range(self.G)]
+
+    def batch_stats(self):
+        """(iterations, relative residuals) per grid of the last solve."""
+        its = (ctypes.c_int32 * self.G)()
+        res = (ctypes.c_double * self.G)()
+        _check(lib().sfcdd_get_batch_stats(self.ctx, its, res), self.ctx)
+        return list(its), list(res)
+
+    def partition(self, grid: int = 0) -> dict:
+        import numpy as np
+        Pn = self._arr[grid].P
+        Ng = self.sizes[grid]
+        sfc = (ctypes.c_int32 * Ng)()
+        ta = (ctypes.c_int64 * Pn)()
+        Ni = (ctypes.c_int64 * Pn)()
+        om = (ctypes.c_double * Pn)()
+        q = ctypes.c_int32()
+        _check(lib().sfcdd_get_partition(self.ctx, grid, sfc, ta, Ni, om, ctypes.byref(q)), self.ctx)
+        return {"sfc_index": np.ctypeslib.as_array(sfc).astype(np.int64), "ta": np.array(ta[:]),
+                "Ni": np.array(Ni[:]), "omega": np.array(om[:]), "q": int(q.value)}
+
+
+def _autotune(self, repeats: int = 5):
+    """Picks the fastest subdomain-solve launch shape on this context's own
+    factors; returns the time per application (ms)."""
+    ms = ctypes.c_double()
+    _check(lib().sfcdd_autotune(self.ctx, int(repeats), ctypes.byref(ms)), self.ctx)
+    inf = Info()
+    _check(lib().sfcdd_get_info(self.ctx, ctypes.byref(inf)), self.ctx)
+    self._info = inf
+    return float(ms.value)
+
+
+SFCSchwarz.autotune = _autotune
 
 from .autograd import PoissonSolve, solve_poisson  # noqa: E402,F401

@@ -8,28 +8,40 @@ namespace sfcdd {
 
 // ---------------------------------------------------------------------------
 // SpMV with the (2d+1)-point FD matrix, vectors in curve order (Alg. 3 A x).
-// MODE 0: y = A x.  MODE 1: y = A x, partials of x . y.  MODE 2: y = b - A x,
-// partials of y . y.  The reductions use a fixed grid of RED_BLOCKS blocks.
+// MODE 0: y = A x over the whole batch.  MODE 1: y = A x with per-grid
+// partials of x . y.  MODE 2: y = b - A x with per-grid partials of y . y.
+// Reductions: block (x, g) covers grid g only; partials[g * rbx + x]; the
+// grid of blocks is fixed, so the sums are deterministic.
 template <int MODE>
-__global__ __launch_bounds__(RED_THREADS) void k_spmv(GridDesc g, const int32_t* __restrict__ nbr,
+__global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __restrict__ nbr,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const double* __restrict__ b,
                                                       double* __restrict__ partials) {
   __shared__ double sh[16];
   double acc = 0.0;
-  const int64_t N = g.N;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+  const int64_t Nt = B.Ntot;
+  int64_t start, hi;
+  if (MODE == 0) {
+    start = 0;
+    hi = Nt;
+  } else {
+    const GridDesc& g = B.grids[blockIdx.y];
+    start = g.goff;
+    hi = g.goff + g.N;
+  }
+  for (int64_t p = start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi;
        p += (int64_t)gridDim.x * blockDim.x) {
+    const GridDesc& g = B.grids[MODE == 0 ? grid_of(B, B.gid, p) : (int)blockIdx.y];
     const double xp = x[p];
     double v = g.diag * xp;
     for (int j = 0; j < g.d; ++j) {
-      const int32_t m = nbr[(2 * j) * N + p];
-      const int32_t q = nbr[(2 * j + 1) * N + p];
-      double s = 0.0;
-      if (m >= 0) s += x[m];
-      if (q >= 0) s += x[q];
-      v -= g.c[j] * s;
+      const int32_t m = nbr[(2 * j) * Nt + p];
+      const int32_t q = nbr[(2 * j + 1) * Nt + p];
+      double sj = 0.0;
+      if (m >= 0) sj += x[m];
+      if (q >= 0) sj += x[q];
+      v -= g.c[j] * sj;
     }
     if (MODE == 2) v = b[p] - v;
     y[p] = v;
@@ -37,25 +49,24 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(GridDesc g, const int32_t*
     if (MODE == 2) acc += v * v;
   }
   if (MODE != 0) {
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    const double sm = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sm;
   }
 }
 
-void launch_spmv(const GridDesc& g, const int32_t* nbr, const double* x, double* y, const double* b,
-                 double* partials, const double* dotv, hipStream_t s) {
-  if (b) {
-    hipLaunchKernelGGL(k_spmv<2>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, g, nbr, x, y, b,
+void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
+                 const double* b, double* partials, hipStream_t s) {
+  if (mode == 2) {
+    hipLaunchKernelGGL(k_spmv<2>, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
                        partials);
-  } else if (partials) {
-    hipLaunchKernelGGL(k_spmv<1>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, g, nbr, x, y, b,
+  } else if (mode == 1) {
+    hipLaunchKernelGGL(k_spmv<1>, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
                        partials);
   } else {
-    const int64_t nb = (g.N + RED_THREADS - 1) / RED_THREADS;
+    const int64_t nb = (B.Ntot + RED_THREADS - 1) / RED_THREADS;
     hipLaunchKernelGGL(k_spmv<0>, dim3((unsigned)(nb < 65535 * 16 ? nb : 65535 * 16)),
-                       dim3(RED_THREADS), 0, s, g, nbr, x, y, b, partials);
+                       dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
   }
-  (void)dotv;
 }
 
 // ---------------------------------------------------------------------------
@@ -94,7 +105,7 @@ __device__ __forceinline__ void axpyv<double>(double* acc, const double2& a, dou
 
 template <typename T, int W>
 __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
-    int64_t N, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
+    Batch B, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
     const int32_t* __restrict__ nt, const int64_t* __restrict__ off,
     const int64_t* __restrict__ doff, const T* __restrict__ fac, const double* __restrict__ w,
     double* __restrict__ dbuf) {
@@ -106,6 +117,9 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   const int b = blockIdx.x;
   const int ntb = nt[b], n = Ni[b];
   const int64_t t0 = ta[b];
+  const GridDesc& g = B.grids[grid_of(B, B.sgid, b)];
+  const int64_t N = g.N;
+  const double* __restrict__ wg = w + g.goff;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* y = reinterpret_cast<T*>(smem_raw);    // ntb * TS
   T* sS = y + ntb * TS;                     // TS
@@ -119,7 +133,7 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     if (s < n) {
       int64_t p = t0 + s;
       if (p >= N) p -= N;
-      v = (T)w[p];
+      v = (T)wg[p];
     }
     y[s] = v;
   }
@@ -198,15 +212,23 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   for (int s = tid; s < n; s += W * 64) out[s] = (double)y[s];
 }
 
-constexpr int TRSV_WAVES = 16;
+// Waves per workgroup of the substitution kernel: 4, 8 or 16 (a tuning knob).
+template <typename T, int W>
+static void trsv_w(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                   const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
+                   const double* w, double* dbuf, hipStream_t s) {
+  const size_t sh = ((size_t)max_nt * TS + TS + (size_t)W * TS) * sizeof(T);
+  hipLaunchKernelGGL((k_schwarz_trsv<T, W>), dim3(B.Ptot), dim3(W * 64), sh, s, B, ta, Ni, nt, off,
+                     doff, fac, w, dbuf);
+}
 
 template <typename T>
-void launch_schwarz_trsv(int P, int64_t N, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                         const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
-                         const double* w, double* dbuf, hipStream_t s) {
-  const size_t sh = ((size_t)max_nt * TS + TS + (size_t)TRSV_WAVES * TS) * sizeof(T);
-  hipLaunchKernelGGL((k_schwarz_trsv<T, TRSV_WAVES>), dim3(P), dim3(TRSV_WAVES * 64), sh, s, N, ta,
-                     Ni, nt, off, doff, fac, w, dbuf);
+void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                         const int64_t* off, const int64_t* doff, int max_nt, int waves,
+                         const T* fac, const double* w, double* dbuf, hipStream_t s) {
+  if (waves <= 4) trsv_w<T, 4>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, s);
+  else if (waves <= 8) trsv_w<T, 8>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, s);
+  else trsv_w<T, 16>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -303,37 +325,38 @@ void launch_symv_reduce(int nb, int max_n, const BatchMeta& bm, const int32_t* n
 
 // xloc[b][s] = R_b w (cyclic curve range from ta_b) for s < N_b, 0 up to nt_b*TS.
 template <typename T>
-__global__ void k_gather_local(int64_t N, BatchMeta bm, const int32_t* __restrict__ ta,
+__global__ void k_gather_local(Batch B, BatchMeta bm, const int32_t* __restrict__ ta,
                                const int32_t* __restrict__ Ni, const double* __restrict__ w,
                                T* __restrict__ xloc) {
   const int b = blockIdx.y;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= bm.nt[b] * TS) return;
+  const GridDesc& g = B.grids[grid_of(B, B.sgid, b)];
   T v = T(0);
   if (s < Ni[b]) {
     int64_t p = (int64_t)ta[b] + s;
-    if (p >= N) p -= N;
-    v = (T)w[p];
+    if (p >= g.N) p -= g.N;
+    v = (T)w[g.goff + p];
   }
   xloc[bm.xoff[b] + s] = v;
 }
 
 template <typename T>
-void launch_gather_local(int nb, int64_t N, int max_nt, const BatchMeta& bm, const int32_t* ta,
+void launch_gather_local(const Batch& B, int max_nt, const BatchMeta& bm, const int32_t* ta,
                          const int32_t* Ni, const double* w, T* xloc, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_local<T>, dim3((max_nt * TS + 255) / 256, nb), dim3(256), 0, s, N, bm,
-                     ta, Ni, w, xloc);
+  hipLaunchKernelGGL(k_gather_local<T>, dim3((max_nt * TS + 255) / 256, B.Ptot), dim3(256), 0, s, B,
+                     bm, ta, Ni, w, xloc);
 }
 
 #define INST(T)                                                                                    \
-  template void launch_schwarz_trsv<T>(int, int64_t, const int32_t*, const int32_t*,               \
-                                       const int32_t*, const int64_t*, const int64_t*, int,        \
+  template void launch_schwarz_trsv<T>(const Batch&, const int32_t*, const int32_t*,              \
+                                       const int32_t*, const int64_t*, const int64_t*, int, int,   \
                                        const T*, const double*, double*, hipStream_t);             \
   template void launch_symv_tiles<T>(int, int, const BatchMeta&, const T*, const T*, T*,           \
                                      hipStream_t);                                                 \
   template void launch_symv_reduce<T>(int, int, const BatchMeta&, const int32_t*, const int64_t*,  \
                                       const T*, double*, hipStream_t);                             \
-  template void launch_gather_local<T>(int, int64_t, int, const BatchMeta&, const int32_t*,        \
+  template void launch_gather_local<T>(const Batch&, int, const BatchMeta&, const int32_t*,        \
                                        const int32_t*, const double*, T*, hipStream_t);
 INST(float)
 INST(double)
@@ -344,137 +367,151 @@ INST(double)
 // (Alg. 2 last step, eq. w1levprec with D_i = omega_i I), in gather form with
 // a fixed order over i: deterministic, no floating-point atomics.  Only
 // pieces k-F-1 .. k+F+1 around p's piece k can contain p.
-__global__ void k_scatter(GridDesc g, PartDesc pd, const int32_t* __restrict__ ta,
-                          const int32_t* __restrict__ Ni, const int64_t* __restrict__ doff,
-                          const double* __restrict__ omega, const double* __restrict__ dbuf,
-                          double* __restrict__ h) {
-  const int64_t N = g.N;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+__global__ void k_scatter(Batch B, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
+                          const int64_t* __restrict__ doff, const double* __restrict__ omega,
+                          const double* __restrict__ dbuf, double* __restrict__ h) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B.Ntot;
        p += (int64_t)gridDim.x * blockDim.x) {
+    const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
+    const int64_t N = g.N;
+    const int64_t pl = p - g.goff;
     double acc = 0.0;
-    const int k = piece_of(p, pd.base, pd.rem);
-    for (int c = 0; c < pd.ncand; ++c) {
-      int i = (pd.ncand >= pd.P) ? c : k - (pd.F + 1) + c;
-      i %= pd.P;
-      if (i < 0) i += pd.P;
-      int64_t o = p - ta[i];
+    const int k = piece_of(pl, g.base, g.rem);
+    for (int c = 0; c < g.ncand; ++c) {
+      int i = (g.ncand >= g.P) ? c : k - (g.F + 1) + c;
+      i %= g.P;
+      if (i < 0) i += g.P;
+      const int ig = g.soff + i;
+      int64_t o = pl - ta[ig];
       if (o < 0) o += N;
-      if (o < Ni[i]) acc += omega[i] * dbuf[doff[i] + o];
+      if (o < Ni[ig]) acc += omega[ig] * dbuf[doff[ig] + o];
     }
     h[p] = acc;
   }
 }
 
-void launch_scatter(const GridDesc& g, const PartDesc& pd, const int32_t* ta, const int32_t* Ni,
-                    const int64_t* doff, const double* omega, const double* dbuf, double* h,
-                    hipStream_t s) {
-  const int64_t nb = (g.N + 255) / 256;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)(nb < 1048576 ? nb : 1048576)), dim3(256), 0, s, g,
-                     pd, ta, Ni, doff, omega, dbuf, h);
+void launch_scatter(const Batch& B, const int32_t* ta, const int32_t* Ni, const int64_t* doff,
+                    const double* omega, const double* dbuf, double* h, hipStream_t s) {
+  const int64_t nb = (B.Ntot + 255) / 256;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)(nb < 1048576 ? nb : 1048576)), dim3(256), 0, s, B,
+                     ta, Ni, doff, omega, dbuf, h);
 }
 
 // ---------------------------------------------------------------------------
 // Coarse restriction c0 = R_0 v (eq. restr): block (i, m) is a contiguous
-// curve range; one wave per coarse unknown.
-__device__ __forceinline__ void block_range(int I, const PartDesc& pd, int64_t* start, int64_t* size) {
-  const int i = I / pd.q, m = I % pd.q;
-  const int64_t sz = pd.base + (i < pd.rem ? 1 : 0);
-  const int64_t qb = sz / pd.q, qr = sz % pd.q;
-  *start = piece_start(i, pd.base, pd.rem) + (m < qr ? m * (qb + 1) : qr * (qb + 1) + (m - qr) * qb);
+// curve range; one wave per coarse unknown.  c0 is stored per grid padded to
+// whole tiles (offset c0pad).
+__device__ __forceinline__ void block_range(int I, const GridDesc& g, int64_t* start, int64_t* size) {
+  const int i = I / g.q, m = I % g.q;
+  const int64_t sz = g.base + (i < g.rem ? 1 : 0);
+  const int64_t qb = sz / g.q, qr = sz % g.q;
+  *start = piece_start(i, g.base, g.rem) + (m < qr ? m * (qb + 1) : qr * (qb + 1) + (m - qr) * qb);
   *size = qb + (m < qr ? 1 : 0);
 }
 
-__global__ void k_restrict(PartDesc pd, const double* __restrict__ v, double* __restrict__ c0) {
-  const int I = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__global__ void k_restrict(Batch B, const double* __restrict__ v, double* __restrict__ c0) {
+  const int64_t Ig = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (I >= pd.N0) return;
+  if (Ig >= B.N0tot) return;
+  const GridDesc& g = B.grids[grid_of(B, B.cgid, Ig)];
+  const int I = (int)(Ig - g.c0off);
   int64_t st, sz;
-  block_range(I, pd, &st, &sz);
+  block_range(I, g, &st, &sz);
+  const double* vg = v + g.goff + st;
   double acc = 0.0;
-  for (int64_t e = lane; e < sz; e += 64) acc += v[st + e];
+  for (int64_t e = lane; e < sz; e += 64) acc += vg[e];
   acc = wave_sum(acc);
-  if (lane == 0) c0[I] = acc;
+  if (lane == 0) c0[g.c0pad + I] = acc;
 }
 
-void launch_restrict(const PartDesc& pd, const double* v, double* c0, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3((pd.N0 + 3) / 4), dim3(256), 0, s, pd, v, c0);
+void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((B.N0tot + 3) / 4)), dim3(256), 0, s, B, v, c0);
 }
 
-__device__ __forceinline__ int coarse_block_of(int64_t p, const PartDesc& pd) {
-  const int i = piece_of(p, pd.base, pd.rem);
-  const int64_t o = p - piece_start(i, pd.base, pd.rem);
-  const int64_t sz = pd.base + (i < pd.rem ? 1 : 0);
-  const int64_t qb = sz / pd.q, qr = sz % pd.q;
+__device__ __forceinline__ int coarse_block_of(int64_t p, const GridDesc& g) {
+  const int i = piece_of(p, g.base, g.rem);
+  const int64_t o = p - piece_start(i, g.base, g.rem);
+  const int64_t sz = g.base + (i < g.rem ? 1 : 0);
+  const int64_t qb = sz / g.q, qr = sz % g.q;
   const int64_t big = qr * (qb + 1);
   const int m = o < big ? (int)(o / (qb + 1)) : (int)(qr + (o - big) / qb);
-  return i * pd.q + m;
+  return i * g.q + m;
 }
 
 // Prolongation R_0^T d0 fused with the final vector combinations.
 template <int MODE>
-__global__ void k_combine(int64_t N, PartDesc pd, const double* __restrict__ d0,
-                          const double* __restrict__ a, const double* __restrict__ b,
-                          double* __restrict__ out) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+__global__ void k_combine(Batch B, const double* __restrict__ d0, const double* __restrict__ a,
+                          const double* __restrict__ b, double* __restrict__ out) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B.Ntot;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const double t = d0[coarse_block_of(p, pd)];
+    const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
+    const double t = d0[g.c0off + coarse_block_of(p - g.goff, g)];
     if (MODE == COMB_PROLONG) out[p] = t;
     if (MODE == COMB_ADD_PROLONG) out[p] = a[p] + t;
     if (MODE == COMB_BAL_FINAL) out[p] = a[p] - t + b[p];
   }
 }
 
-void launch_combine(const GridDesc& g, const PartDesc& pd, int mode, const double* d0,
-                    const double* a, const double* b, double* out, hipStream_t s) {
-  const int64_t nb0 = (g.N + 255) / 256;
+void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
+                    double* out, hipStream_t s) {
+  const int64_t nb0 = (B.Ntot + 255) / 256;
   const dim3 grid((unsigned)(nb0 < 1048576 ? nb0 : 1048576));
   if (mode == COMB_PROLONG)
-    hipLaunchKernelGGL(k_combine<COMB_PROLONG>, grid, dim3(256), 0, s, g.N, pd, d0, a, b, out);
+    hipLaunchKernelGGL(k_combine<COMB_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
   else if (mode == COMB_ADD_PROLONG)
-    hipLaunchKernelGGL(k_combine<COMB_ADD_PROLONG>, grid, dim3(256), 0, s, g.N, pd, d0, a, b, out);
+    hipLaunchKernelGGL(k_combine<COMB_ADD_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
   else
-    hipLaunchKernelGGL(k_combine<COMB_BAL_FINAL>, grid, dim3(256), 0, s, g.N, pd, d0, a, b, out);
+    hipLaunchKernelGGL(k_combine<COMB_BAL_FINAL>, grid, dim3(256), 0, s, B, d0, a, b, out);
 }
 
 // ---------------------------------------------------------------------------
-// BLAS-1 with deterministic two-stage reductions (fixed grid, fixed order).
-__global__ __launch_bounds__(RED_THREADS) void k_dot(int64_t n, const double* __restrict__ a,
+// BLAS-1 with deterministic two-stage per-grid reductions: block (x, g) sums
+// its share of grid g into partials[g * rbx + x] (second sum at + G * rbx);
+// k_finalize (one block per grid) sums them in a fixed order.
+__global__ __launch_bounds__(RED_THREADS) void k_dot(Batch B, const double* __restrict__ a,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ c,
                                                      double* __restrict__ partials) {
   __shared__ double sh[16];
+  const GridDesc& g = B.grids[blockIdx.y];
   double s0 = 0.0, s1 = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  for (int64_t i = g.goff + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.goff + g.N;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double ai = a[i];
     s0 += ai * b[i];
     if (c) s1 += ai * c[i];
   }
+  const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const double r0 = block_sum(s0, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = r0;
+  if (threadIdx.x == 0) partials[slot] = r0;
   if (c) {
     const double r1 = block_sum(s1, sh);
-    if (threadIdx.x == 0) partials[RED_BLOCKS + blockIdx.x] = r1;
+    if (threadIdx.x == 0) partials[(int64_t)B.G * gridDim.x + slot] = r1;
   }
 }
 
-void launch_dot(int64_t n, const double* a, const double* b, const double* c, double* partials,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, a, b, c, partials);
+void launch_dot(const Batch& B, const double* a, const double* b, const double* c,
+                double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, a, b, c, partials);
 }
 
-// Second reduction stage plus the scalar recurrences of CG.
-__global__ __launch_bounds__(RED_THREADS) void k_finalize(int mode, const double* __restrict__ partials,
-                                                          double* __restrict__ S) {
+// Second reduction stage plus the scalar recurrences of CG, one block per grid.
+__global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
+                                                          const double* __restrict__ partials,
+                                                          double* __restrict__ Sall) {
   __shared__ double sh[16];
+  const int gi = blockIdx.x;
+  const double* pp = partials + (int64_t)gi * B.rbx;
+  const double* pp2 = partials + (int64_t)B.G * B.rbx + (int64_t)gi * B.rbx;
   double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < RED_BLOCKS; i += blockDim.x) {
-    s0 += partials[i];
-    if (mode == FIN_RZ_NEXT_FLEX) s1 += partials[RED_BLOCKS + i];
+  for (int i = threadIdx.x; i < B.rbx; i += blockDim.x) {
+    s0 += pp[i];
+    if (mode == FIN_RZ_NEXT_FLEX) s1 += pp2[i];
   }
   const double r0 = block_sum(s0, sh);
   const double r1 = (mode == FIN_RZ_NEXT_FLEX) ? block_sum(s1, sh) : 0.0;
   if (threadIdx.x == 0) {
+    double* S = Sall + (int64_t)gi * S_COUNT;
     switch (mode) {
       case FIN_PQ_ALPHA: S[S_PQ] = r0; S[S_ALPHA] = S[S_RZ] / r0; break;
       case FIN_RR: S[S_RR] = r0; break;
@@ -486,61 +523,78 @@ __global__ __launch_bounds__(RED_THREADS) void k_finalize(int mode, const double
   }
 }
 
-void launch_finalize(int mode, const double* partials, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, mode, partials, scal);
+void launch_finalize(const Batch& B, int mode, const double* partials, double* scal,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(B.G), dim3(RED_THREADS), 0, s, B, mode, partials, scal);
 }
 
-// x += alpha p, r -= alpha q, partials of r . r.
-__global__ __launch_bounds__(RED_THREADS) void k_update_xr(int64_t n, const double* __restrict__ S,
+// x += alpha_g p, r -= alpha_g q on active grids; per-grid partials of r . r.
+__global__ __launch_bounds__(RED_THREADS) void k_update_xr(Batch B, const double* __restrict__ Sall,
+                                                           const int32_t* __restrict__ active,
                                                            double* __restrict__ x,
                                                            double* __restrict__ r,
                                                            const double* __restrict__ p,
                                                            const double* __restrict__ q,
                                                            double* __restrict__ partials) {
   __shared__ double sh[16];
-  const double alpha = S[S_ALPHA];
+  const int gi = blockIdx.y;
+  const GridDesc& g = B.grids[gi];
+  const bool act = active[gi] != 0;
+  const double alpha = Sall[(int64_t)gi * S_COUNT + S_ALPHA];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  for (int64_t i = g.goff + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.goff + g.N;
        i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
+    double ri = r[i];
+    if (act) {
+      x[i] += alpha * p[i];
+      ri -= alpha * q[i];
+      r[i] = ri;
+    }
     acc += ri * ri;
   }
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  const double sm = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[(int64_t)gi * gridDim.x + blockIdx.x] = sm;
 }
 
-void launch_update_xr(int64_t n, const double* scal, double* x, double* r, const double* p,
-                      const double* q, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_xr, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, scal, x, r, p, q,
-                     partials);
-}
-
-__global__ void k_update_p(int64_t n, const double* __restrict__ S, double* __restrict__ p,
-                           const double* __restrict__ z) {
-  const double beta = S[S_BETA];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
-}
-
-void launch_update_p(int64_t n, const double* scal, double* p, const double* z, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(2048), dim3(256), 0, s, n, scal, p, z);
-}
-
-// x += S[slot] * z
-__global__ void k_axpy_scal(int64_t n, const double* __restrict__ S, int slot,
-                            double* __restrict__ x, const double* __restrict__ z) {
-  const double a = S[slot];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    x[i] += a * z[i];
-}
-
-void launch_axpy_scal(int64_t n, const double* scal, int slot, double* x, const double* z,
+void launch_update_xr(const Batch& B, const double* scal, const int32_t* active, double* x,
+                      double* r, const double* p, const double* q, double* partials,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_scal, dim3(2048), dim3(256), 0, s, n, scal, slot, x, z);
+  hipLaunchKernelGGL(k_update_xr, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, scal, active, x, r,
+                     p, q, partials);
+}
+
+__global__ void k_update_p(Batch B, const double* __restrict__ Sall,
+                           const int32_t* __restrict__ active, double* __restrict__ p,
+                           const double* __restrict__ z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.Ntot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int gi = grid_of(B, B.gid, i);
+    const int a = active[gi];
+    if (!a) continue;
+    p[i] = (a == 2) ? z[i] : z[i] + Sall[(int64_t)gi * S_COUNT + S_BETA] * p[i];  // 2: restarted
+  }
+}
+
+void launch_update_p(const Batch& B, const double* scal, const int32_t* active, double* p,
+                     const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(2048), dim3(256), 0, s, B, scal, active, p, z);
+}
+
+// x += S_g[slot] z on active grids
+__global__ void k_axpy_scal(Batch B, const double* __restrict__ Sall, int slot,
+                            const int32_t* __restrict__ active, double* __restrict__ x,
+                            const double* __restrict__ z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.Ntot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int gi = grid_of(B, B.gid, i);
+    if (!active[gi]) continue;
+    x[i] += Sall[(int64_t)gi * S_COUNT + slot] * z[i];
+  }
+}
+
+void launch_axpy_scal(const Batch& B, const double* scal, int slot, const int32_t* active,
+                      double* x, const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_scal, dim3(2048), dim3(256), 0, s, B, scal, slot, active, x, z);
 }
 
 // gather: out[p] = in[idx[p]];  scatter: out[idx[p]] = in[p].

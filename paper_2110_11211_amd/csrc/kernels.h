@@ -1,4 +1,10 @@
 // Host-callable launchers of the sfcdd device kernels (internal interface).
+//
+// Every kernel works on a batch of G independent grids (G = 1 for a single
+// subproblem): vectors of all grids are concatenated, each grid owning the
+// entries [goff, goff + N); subdomains and coarse unknowns are numbered
+// globally in grid order.  A kernel finds the grid of an entry through the
+// per-entry grid id tables (not read when G == 1).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,7 +13,7 @@ namespace sfcdd {
 
 constexpr int MAXD = 16;
 
-// Grid geometry passed by value to the kernels.
+// Geometry, partition and batch placement of one grid.
 struct GridDesc {
   int d;
   int nres;                 // curve resolution bits
@@ -18,29 +24,61 @@ struct GridDesc {
   double c[MAXD];           // a_j / h_j^2
   double inv_h2[MAXD];      // 1 / h_j^2
   double diag;              // sum_j 2 c_j
-};
-
-// Partition geometry passed by value.
-struct PartDesc {
+  // partition
   int P, q, N0;
   int64_t base, rem;        // piece sizes floor(N/P) (+1 for the first rem)
   int F;                    // floor(gamma)
-  int ncand;                // subdomains that may cover a piece's points
+  int ncand;                // subdomains that may contain a point of a piece
+  // placement in the batch
+  int64_t goff;             // first vector entry
+  int soff;                 // first subdomain
+  int64_t c0off;            // first coarse unknown
+  int64_t c0pad;            // first entry of the tile-padded coarse vector
+  int nt0;                  // coarse tiles per edge
+};
+
+// Device view of a batch (passed by value).
+struct Batch {
+  const GridDesc* grids;
+  int G;
+  int dmax;                 // planes of the neighbour table
+  int64_t Ntot;             // sum of N
+  int Ptot;                 // sum of P
+  int64_t N0tot;            // sum of N0
+  const uint16_t* gid;      // grid of each vector entry
+  const uint16_t* sgid;     // grid of each subdomain
+  const uint16_t* cgid;     // grid of each coarse unknown
+  const uint16_t* ctgid;    // grid of each coarse tile
+  int rbx;                  // reduction blocks per grid
+};
+
+__device__ __forceinline__ int grid_of(const Batch& B, const uint16_t* ids, int64_t i) {
+  return B.G == 1 ? 0 : (int)ids[i];
+}
+
+// Per-matrix offsets of a batch of packed tiled matrices: tile count nt,
+// first tile, first element of the padded local vector, first partial.
+struct BatchMeta {
+  const int32_t* nt;
+  const int64_t* off;
+  const int64_t* xoff;
+  const int64_t* poff;
 };
 
 // ---- setup ------------------------------------------------------------
-void launch_sfc_rank(const GridDesc& g, int32_t* pos, int32_t* sfc_index, hipStream_t s);
-void launch_build_nbr(const GridDesc& g, const int32_t* pos, const int32_t* sfc_index,
-                      int32_t* nbr, hipStream_t s);
+void launch_sfc_rank(const Batch& B, int32_t* pos, int32_t* sfc_index, hipStream_t s);
+void launch_build_nbr(const Batch& B, const int32_t* pos, const int32_t* sfc_index, int32_t* nbr,
+                      hipStream_t s);
 template <typename T>
-void launch_assemble_local(const GridDesc& g, int P, const int32_t* ta, const int32_t* Ni,
-                           const int32_t* nt, const int64_t* fac_off, const int32_t* nbr,
-                           int max_nt, T* fac, hipStream_t s);
-void launch_coarse_counts(const GridDesc& g, const PartDesc& pd, int j, const int32_t* nbr,
+void launch_assemble_local(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                           const int64_t* fac_off, const int32_t* nbr, int max_nt, T* fac,
+                           hipStream_t s);
+void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
                           int32_t* cnt, hipStream_t s);
-void launch_coarse_accumulate(int64_t ntiles_elems, double cj, const int32_t* cnt, double* A0,
+void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
                               hipStream_t s);
-void launch_coarse_pad(int N0, int nt0, double* A0, hipStream_t s);
+void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, double* A0,
+                       hipStream_t s);
 
 // ---- batched tiled Cholesky, inversion ----------------------------------
 template <typename T>
@@ -64,21 +102,14 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
                   hipStream_t s);
 
 // ---- per-iteration operators ---------------------------------------------
-void launch_spmv(const GridDesc& g, const int32_t* nbr, const double* x, double* y,
-                 const double* b /* y = b - A x when non-null */, double* partials /* dot */,
-                 const double* dotv /* partial sums of dotv . y when non-null */, hipStream_t s);
+// mode 0: y = A x;  1: y = A x, per-grid partials of x.y;  2: y = b - A x,
+// per-grid partials of y.y.
+void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
+                 const double* b, double* partials, hipStream_t s);
 template <typename T>
-void launch_schwarz_trsv(int P, int64_t N, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                         const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
-                         const double* w, double* dbuf, hipStream_t s);
-// Per-matrix offsets of a batch of packed tiled matrices: tile count nt,
-// first tile, first element of the padded local vector, first partial.
-struct BatchMeta {
-  const int32_t* nt;
-  const int64_t* off;
-  const int64_t* xoff;
-  const int64_t* poff;
-};
+void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                         const int64_t* off, const int64_t* doff, int max_nt, int waves,
+                         const T* fac, const double* w, double* dbuf, hipStream_t s);
 template <typename T>
 void launch_symv_tiles(int nb, int max_nt, const BatchMeta& bm, const T* M, const T* xloc, T* part,
                        hipStream_t s);
@@ -86,25 +117,26 @@ template <typename T>
 void launch_symv_reduce(int nb, int max_n, const BatchMeta& bm, const int32_t* n,
                         const int64_t* doff, const T* part, double* out, hipStream_t s);
 template <typename T>
-void launch_gather_local(int nb, int64_t N, int max_nt, const BatchMeta& bm, const int32_t* ta,
+void launch_gather_local(const Batch& B, int max_nt, const BatchMeta& bm, const int32_t* ta,
                          const int32_t* Ni, const double* w, T* xloc, hipStream_t s);
-void launch_scatter(const GridDesc& g, const PartDesc& pd, const int32_t* ta, const int32_t* Ni,
-                    const int64_t* doff, const double* omega, const double* dbuf, double* h,
-                    hipStream_t s);
-void launch_restrict(const PartDesc& pd, const double* v, double* c0, hipStream_t s);
-// h = y + (prolong d0) ... see apply.hip for the exact combination modes
-void launch_combine(const GridDesc& g, const PartDesc& pd, int mode, const double* d0,
-                    const double* a, const double* b, double* out, hipStream_t s);
+void launch_scatter(const Batch& B, const int32_t* ta, const int32_t* Ni, const int64_t* doff,
+                    const double* omega, const double* dbuf, double* h, hipStream_t s);
+void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s);
+void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
+                    double* out, hipStream_t s);
 
-// ---- BLAS-1 and scalars ---------------------------------------------------
-void launch_dot(int64_t n, const double* a, const double* b, const double* c, double* partials,
-                hipStream_t s);
-void launch_finalize(int mode, const double* partials, double* scal, hipStream_t s);
-void launch_update_xr(int64_t n, const double* scal, double* x, double* r, const double* p,
-                      const double* q, double* partials, hipStream_t s);
-void launch_update_p(int64_t n, const double* scal, double* p, const double* z, hipStream_t s);
-void launch_axpy_scal(int64_t n, const double* scal, int slot, double* x, const double* z,
+// ---- BLAS-1 and scalars (per grid) -----------------------------------------
+void launch_dot(const Batch& B, const double* a, const double* b, const double* c,
+                double* partials, hipStream_t s);
+void launch_finalize(const Batch& B, int mode, const double* partials, double* scal,
+                     hipStream_t s);
+void launch_update_xr(const Batch& B, const double* scal, const int32_t* active, double* x,
+                      double* r, const double* p, const double* q, double* partials,
                       hipStream_t s);
+void launch_update_p(const Batch& B, const double* scal, const int32_t* active, double* p,
+                     const double* z, hipStream_t s);
+void launch_axpy_scal(const Batch& B, const double* scal, int slot, const int32_t* active,
+                      double* x, const double* z, hipStream_t s);
 void launch_permute(int64_t n, const int32_t* idx, const double* in, double* out, int gather,
                     hipStream_t s);
 void launch_grad_coeff(const GridDesc& g, const double* lam, const double* u, double* partials,
@@ -113,7 +145,7 @@ void launch_finalize_vec(int nvals, const double* partials, double* out, hipStre
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
 void launch_zero(int64_t n, double* a, hipStream_t s);
 
-// Scalar slots of the solver's device scalar array.
+// Scalar slots of the solver's per-grid device scalars S[g * S_COUNT + slot].
 enum {
   S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZQ, S_BB, S_XI, S_TMP, S_COUNT = 16
 };

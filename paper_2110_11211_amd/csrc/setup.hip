@@ -1,5 +1,5 @@
 // Setup-phase kernels (Alg. 1): curve order, neighbour table, local and
-// coarse assembly.
+// coarse assembly, for a batch of grids (one launch covers every grid).
 #include "common.h"
 #include "kernels.h"
 
@@ -20,9 +20,13 @@ __device__ __forceinline__ int64_t count_in(int64_t lo, int64_t hi, int n, int s
 // points that share K's prefix above it and have a 0 there; on a tensor grid
 // that count is a product over dimensions of interval counts, because a key
 // prefix fixes the top bits of every scaled coordinate.
-__global__ void k_sfc_rank(GridDesc g, int32_t* __restrict__ pos, int32_t* __restrict__ sfc_index) {
-  const int64_t nat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (nat >= g.N) return;
+// Entry idx of grid g: natural index idx - goff; writes pos[idx] and
+// sfc_index[goff + rank] as batch-global indices.
+__global__ void k_sfc_rank(Batch B, int32_t* __restrict__ pos, int32_t* __restrict__ sfc_index) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B.Ntot) return;
+  const GridDesc& g = B.grids[grid_of(B, B.gid, idx)];
+  const int64_t nat = idx - g.goff;
   int64_t C[MAXD];
   for (int j = 0; j < g.d; ++j) {
     const int64_t k = (nat / g.stride[j]) % g.n[j] + 1;
@@ -50,41 +54,51 @@ __global__ void k_sfc_rank(GridDesc g, int32_t* __restrict__ pos, int32_t* __res
       rank += cnt;
     }
   }
-  pos[nat] = (int32_t)rank;
-  if (rank < g.N) sfc_index[rank] = (int32_t)nat;
+  pos[idx] = (int32_t)(g.goff + rank);
+  if (rank < g.N) sfc_index[g.goff + rank] = (int32_t)idx;
 }
 
-void launch_sfc_rank(const GridDesc& g, int32_t* pos, int32_t* sfc_index, hipStream_t s) {
+void launch_sfc_rank(const Batch& B, int32_t* pos, int32_t* sfc_index, hipStream_t s) {
   const int th = 256;
-  hipLaunchKernelGGL(k_sfc_rank, dim3((g.N + th - 1) / th), dim3(th), 0, s, g, pos, sfc_index);
+  hipLaunchKernelGGL(k_sfc_rank, dim3((B.Ntot + th - 1) / th), dim3(th), 0, s, B, pos, sfc_index);
 }
 
 // Curve positions of the 2d stencil neighbours of every curve position
 // (Alg. 1: map to neighbouring points), -1 on the Dirichlet boundary.
-// Layout nbr[(2 j + side) * N + p], side 0 = minus, 1 = plus.
-__global__ void k_build_nbr(GridDesc g, const int32_t* __restrict__ pos,
+// Layout nbr[(2 j + side) * Ntot + p], side 0 = minus, 1 = plus; batch-global
+// positions.
+__global__ void k_build_nbr(Batch B, const int32_t* __restrict__ pos,
                             const int32_t* __restrict__ sfc_index, int32_t* __restrict__ nbr) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= g.N) return;
-  const int64_t nat = sfc_index[p];
-  for (int j = 0; j < g.d; ++j) {
-    const int64_t k = (nat / g.stride[j]) % g.n[j];
-    nbr[(2 * j) * g.N + p] = k > 0 ? pos[nat - g.stride[j]] : -1;
-    nbr[(2 * j + 1) * g.N + p] = k < g.n[j] - 1 ? pos[nat + g.stride[j]] : -1;
+  if (p >= B.Ntot) return;
+  const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
+  const int64_t nat = sfc_index[p];            // batch-global natural index
+  const int64_t loc = nat - g.goff;
+  for (int j = 0; j < B.dmax; ++j) {
+    int32_t m = -1, q = -1;
+    if (j < g.d) {
+      const int64_t k = (loc / g.stride[j]) % g.n[j];
+      if (k > 0) m = pos[nat - g.stride[j]];
+      if (k < g.n[j] - 1) q = pos[nat + g.stride[j]];
+    }
+    nbr[(2 * j) * B.Ntot + p] = m;
+    nbr[(2 * j + 1) * B.Ntot + p] = q;
   }
 }
 
-void launch_build_nbr(const GridDesc& g, const int32_t* pos, const int32_t* sfc_index,
-                      int32_t* nbr, hipStream_t s) {
+void launch_build_nbr(const Batch& B, const int32_t* pos, const int32_t* sfc_index, int32_t* nbr,
+                      hipStream_t s) {
   const int th = 256;
-  hipLaunchKernelGGL(k_build_nbr, dim3((g.N + th - 1) / th), dim3(th), 0, s, g, pos, sfc_index, nbr);
+  hipLaunchKernelGGL(k_build_nbr, dim3((B.Ntot + th - 1) / th), dim3(th), 0, s, B, pos, sfc_index,
+                     nbr);
 }
 
 // Local matrices A_i = R_i A R_i^T (Sec. 3.1) written as packed lower tiles:
-// row s of subdomain b is curve position (ta_b + s) mod N.  Rows past N_b are
-// padding with a unit diagonal.  The tiles must be zeroed beforehand.
+// row s of subdomain b (grid g) is curve position (ta_b + s) mod N of grid g.
+// Rows past N_b are padding with a unit diagonal.  The tiles must be zeroed
+// beforehand.
 template <typename T>
-__global__ void k_assemble_local(GridDesc g, const int32_t* __restrict__ ta,
+__global__ void k_assemble_local(Batch B, const int32_t* __restrict__ ta,
                                  const int32_t* __restrict__ Ni, const int32_t* __restrict__ nt,
                                  const int64_t* __restrict__ fac_off,
                                  const int32_t* __restrict__ nbr, T* __restrict__ fac) {
@@ -92,6 +106,7 @@ __global__ void k_assemble_local(GridDesc g, const int32_t* __restrict__ ta,
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int ntb = nt[b];
   if (s >= ntb * TS) return;
+  const GridDesc& g = B.grids[grid_of(B, B.sgid, b)];
   T* F = fac + fac_off[b] * TS2;
   const int I = s / TS, r = s % TS;
   const int n = Ni[b];
@@ -100,12 +115,12 @@ __global__ void k_assemble_local(GridDesc g, const int32_t* __restrict__ ta,
     return;
   }
   F[tri_index(I, I) * TS2 + r * TS + r] = (T)g.diag;
-  const int64_t p = ((int64_t)ta[b] + s) % g.N;
+  const int64_t p = g.goff + ((int64_t)ta[b] + s) % g.N;
   for (int j = 0; j < g.d; ++j) {
     for (int side = 0; side < 2; ++side) {
-      const int64_t q = nbr[(2 * j + side) * g.N + p];
+      const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
       if (q < 0) continue;
-      const int64_t t = ((q - ta[b]) % g.N + g.N) % g.N;
+      const int64_t t = ((q - g.goff - ta[b]) % g.N + g.N) % g.N;
       if (t < n && t < s) {
         const int J = (int)(t / TS), c = (int)(t % TS);
         F[tri_index(I, J) * TS2 + r * TS + c] = (T)(-g.c[j]);
@@ -115,81 +130,94 @@ __global__ void k_assemble_local(GridDesc g, const int32_t* __restrict__ ta,
 }
 
 template <typename T>
-void launch_assemble_local(const GridDesc& g, int P, const int32_t* ta, const int32_t* Ni,
-                           const int32_t* nt, const int64_t* fac_off, const int32_t* nbr,
-                           int max_nt, T* fac, hipStream_t s) {
+void launch_assemble_local(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
+                           const int64_t* fac_off, const int32_t* nbr, int max_nt, T* fac,
+                           hipStream_t s) {
   const int th = 256;
-  dim3 grid((max_nt * TS + th - 1) / th, P);
-  hipLaunchKernelGGL(k_assemble_local<T>, grid, dim3(th), 0, s, g, ta, Ni, nt, fac_off, nbr, fac);
+  dim3 grid((max_nt * TS + th - 1) / th, B.Ptot);
+  hipLaunchKernelGGL(k_assemble_local<T>, grid, dim3(th), 0, s, B, ta, Ni, nt, fac_off, nbr, fac);
 }
-template void launch_assemble_local<float>(const GridDesc&, int, const int32_t*, const int32_t*,
+template void launch_assemble_local<float>(const Batch&, const int32_t*, const int32_t*,
                                            const int32_t*, const int64_t*, const int32_t*, int,
                                            float*, hipStream_t);
-template void launch_assemble_local<double>(const GridDesc&, int, const int32_t*, const int32_t*,
+template void launch_assemble_local<double>(const Batch&, const int32_t*, const int32_t*,
                                             const int32_t*, const int64_t*, const int32_t*, int,
                                             double*, hipStream_t);
 
-// Coarse unknown (block) of curve position p: piece i and its m-th block of
-// eq. (restr), index i q + m.
-__device__ __forceinline__ int coarse_block(int64_t p, const PartDesc& pd) {
-  const int i = piece_of(p, pd.base, pd.rem);
-  const int64_t o = p - piece_start(i, pd.base, pd.rem);
-  const int64_t sz = pd.base + (i < pd.rem ? 1 : 0);
-  const int64_t qb = sz / pd.q, qr = sz % pd.q;
+// Coarse unknown (block) of local curve position p of grid g: piece i and its
+// m-th block of eq. (restr), local index i q + m.
+__device__ __forceinline__ int coarse_block(int64_t p, const GridDesc& g) {
+  const int i = piece_of(p, g.base, g.rem);
+  const int64_t o = p - piece_start(i, g.base, g.rem);
+  const int64_t sz = g.base + (i < g.rem ? 1 : 0);
+  const int64_t qb = sz / g.q, qr = sz % g.q;
   const int64_t big = qr * (qb + 1);
   const int m = o < big ? (int)(o / (qb + 1)) : (int)(qr + (o - big) / qb);
-  return i * pd.q + m;
+  return i * g.q + m;
 }
 
 // Integer coupling counts of dimension j between coarse blocks (eq. csm with
 // A = sum_j c_j L_j): cnt(I, J) = sum_{p in I, p' in J} (L_j)_{p p'} for
-// J <= I, accumulated with integer atomics into packed lower tiles.
-__global__ void k_coarse_counts(GridDesc g, PartDesc pd, int j, const int32_t* __restrict__ nbr,
-                                int32_t* __restrict__ cnt) {
+// J <= I, accumulated with integer atomics into the packed lower tiles of
+// each grid's coarse matrix (first tile ctile_off[g]).
+__global__ void k_coarse_counts(Batch B, int j, const int32_t* __restrict__ nbr,
+                                const int64_t* __restrict__ ctile_off, int32_t* __restrict__ cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= g.N) return;
-  const int I = coarse_block(p, pd);
-  atomicAdd(&cnt[tri_index(I / TS, I / TS) * TS2 + (I % TS) * TS + (I % TS)], 2);
+  if (p >= B.Ntot) return;
+  const int gi = grid_of(B, B.gid, p);
+  const GridDesc& g = B.grids[gi];
+  if (j >= g.d) return;
+  int32_t* C = cnt + ctile_off[gi] * TS2;
+  const int I = coarse_block(p - g.goff, g);
+  atomicAdd(&C[tri_index(I / TS, I / TS) * TS2 + (I % TS) * TS + (I % TS)], 2);
   for (int side = 0; side < 2; ++side) {
-    const int64_t q = nbr[(2 * j + side) * g.N + p];
+    const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
     if (q < 0) continue;
-    const int J = coarse_block(q, pd);
+    const int J = coarse_block(q - g.goff, g);
     if (J > I) continue;
-    atomicAdd(&cnt[tri_index(I / TS, J / TS) * TS2 + (I % TS) * TS + (J % TS)], -1);
+    atomicAdd(&C[tri_index(I / TS, J / TS) * TS2 + (I % TS) * TS + (J % TS)], -1);
   }
 }
 
-void launch_coarse_counts(const GridDesc& g, const PartDesc& pd, int j, const int32_t* nbr,
+void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
                           int32_t* cnt, hipStream_t s) {
   const int th = 256;
-  hipLaunchKernelGGL(k_coarse_counts, dim3((g.N + th - 1) / th), dim3(th), 0, s, g, pd, j, nbr, cnt);
+  hipLaunchKernelGGL(k_coarse_counts, dim3((B.Ntot + th - 1) / th), dim3(th), 0, s, B, j, nbr,
+                     ctile_off, cnt);
 }
 
-__global__ void k_coarse_accumulate(int64_t n, double cj, const int32_t* __restrict__ cnt,
+// A_0 += c_j E_j for every coarse tile element (the grid of a tile from ctgid).
+__global__ void k_coarse_accumulate(Batch B, int64_t n, int j, const int32_t* __restrict__ cnt,
                                     double* __restrict__ A0) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = cnt[e];
-    if (v) A0[e] += cj * (double)v;
+    if (v) {
+      const GridDesc& g = B.grids[grid_of(B, B.ctgid, e / TS2)];
+      if (j < g.d) A0[e] += g.c[j] * (double)v;
+    }
   }
 }
 
-void launch_coarse_accumulate(int64_t n, double cj, const int32_t* cnt, double* A0, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_accumulate, dim3(2048), dim3(256), 0, s, n, cj, cnt, A0);
+void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_accumulate, dim3(2048), dim3(256), 0, s, B, nelems, j, cnt, A0);
 }
 
-// Unit diagonal on the padding rows N0 .. nt0*TS-1 of the coarse matrix.
-__global__ void k_coarse_pad(int N0, int nt0, double* __restrict__ A0) {
-  const int r = N0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nt0 * TS) return;
+// Unit diagonal on the padding rows N0 .. nt0*TS-1 of each coarse matrix.
+__global__ void k_coarse_pad(Batch B, const int64_t* __restrict__ ctile_off, double* __restrict__ A0) {
+  const int gi = blockIdx.y;
+  const GridDesc& g = B.grids[gi];
+  const int r = g.N0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.nt0 * TS) return;
   const int I = r / TS;
-  A0[tri_index(I, I) * TS2 + (r % TS) * TS + (r % TS)] = 1.0;
+  A0[(ctile_off[gi] + tri_index(I, I)) * TS2 + (r % TS) * TS + (r % TS)] = 1.0;
 }
 
-void launch_coarse_pad(int N0, int nt0, double* A0, hipStream_t s) {
-  const int pad = nt0 * TS - N0;
-  if (pad <= 0) return;
-  hipLaunchKernelGGL(k_coarse_pad, dim3((pad + 63) / 64), dim3(64), 0, s, N0, nt0, A0);
+void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, double* A0,
+                       hipStream_t s) {
+  (void)max_nt0;
+  hipLaunchKernelGGL(k_coarse_pad, dim3(1, B.G), dim3(64), 0, s, B, ctile_off, A0);
 }
 
 }  // namespace sfcdd

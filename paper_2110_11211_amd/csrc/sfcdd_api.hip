@@ -1,6 +1,7 @@
 // Host side of the C ABI: validation, the closed-form partition, workspace
 // layout, and the orchestration of setup (Alg. 1), operator application
-// (Alg. 2, eqs. addSW / balSW) and the outer iterations (Alg. 3, PCG).
+// (Alg. 2, eqs. addSW / balSW) and the outer iterations (Alg. 3, PCG), for a
+// batch of independent grids (a single grid is the batch of one).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,48 +39,60 @@ struct Planner {
 
 enum { V_X = 0, V_R, V_Z, V_P, V_Q, V_T, V_W, V_Y, V_V, V_IN, V_OUT, V_B, V_TMP, NVEC };
 
+// One grid of the batch on the host.
+struct GridHost {
+  GridDesc desc{};
+  std::vector<double> coeff;
+  std::vector<int32_t> ta, Ni;
+  std::vector<double> omega;
+};
+
 }  // namespace
 
 struct sfcdd_ctx {
-  // parameters
-  int d = 0;
-  std::vector<int> levels, npts;
-  std::vector<double> coeff;
-  int P = 0, q = 0, N0 = 0;
-  int64_t gnum = 0, gden = 1;
+  int G = 0;
+  std::vector<GridHost> grid;
   int weighting = 1, variant = 1, fdtype = 0, local_solver = 0, layout = 0;
-  GridDesc g{};
-  PartDesc pd{};
+  int64_t Ntot = 0, N0tot = 0;
+  int Ptot = 0, dmax = 0, rbx = RED_BLOCKS;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // internal, default priority: coarse setup overlaps the fine factorisation
-  // host partition
+  // per-subdomain (batch-global) host tables
   std::vector<int32_t> ta, Ni, nt;
   std::vector<int64_t> off, doff, xoff, poff;
   std::vector<double> omega;
-  int max_nt = 0, max_Ni = 0, min_Ni = 0;
-  int64_t sum_Ni = 0, tiles = 0, parts = 0, xlen = 0;
-  int nt0 = 0;
+  std::vector<uint16_t> sgid;
+  // coarse matrices, one per grid
+  std::vector<int32_t> c_nt, c_n;
+  std::vector<int64_t> c_off, c_xoff, c_poff, c_doff;
+  int max_nt = 0, max_Ni = 0, min_Ni = 0, max_nt0 = 0, max_N0 = 0;
+  int64_t sum_Ni = 0, tiles = 0, parts = 0, xlen = 0, ctiles = 0, cparts = 0, c0len = 0;
+  int trsv_waves = 16;
   // workspace regions
-  Region r_sfc, r_pos, r_nbr, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff, r_omega, r_fac,
-      r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cmeta, r_dbuf, r_vec, r_partials,
-      r_scal, r_status, r_gout, r_cpartk;
+  Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
+      r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
+      r_cmeta, r_cgid, r_ctgid, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout;
   size_t total = 0;
   unsigned char* ws = nullptr;
-  // convenience device pointers
+  // device pointers
   int32_t *sfc_index = nullptr, *pos = nullptr, *nbr = nullptr;
+  uint16_t *gid = nullptr, *d_sgid = nullptr, *cgid = nullptr, *ctgid = nullptr;
+  GridDesc* d_grids = nullptr;
   int32_t *d_ta = nullptr, *d_Ni = nullptr, *d_nt = nullptr;
   int64_t *d_off = nullptr, *d_doff = nullptr, *d_xoff = nullptr, *d_poff = nullptr;
   double* d_omega = nullptr;
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
-  double* cpartk = nullptr;  // split-K partial tiles of the coarse factorisation
-  int32_t *c_nt = nullptr, *c_n = nullptr;
-  int64_t *c_off = nullptr, *c_xoff = nullptr, *c_poff = nullptr, *c_doff = nullptr;
+  double* cpartk = nullptr;  // split-K partial tiles of a single coarse factorisation
+  int32_t *dc_nt = nullptr, *dc_n = nullptr;
+  int64_t *dc_off = nullptr, *dc_xoff = nullptr, *dc_poff = nullptr, *dc_doff = nullptr;
   double* dbuf = nullptr;
   double* vec[NVEC] = {};
   double *partials = nullptr, *scal = nullptr, *gout = nullptr;
-  int32_t* status = nullptr;
-  double* host_scal = nullptr;  // pinned
+  int32_t *active = nullptr, *status = nullptr;
+  double* host_scal = nullptr;  // pinned, G * S_COUNT + G + 256 doubles
+  std::vector<int32_t> last_iters;
+  std::vector<double> last_relres;
   std::string err;
   sfcdd_info info{};
   // per-kernel profiling
@@ -89,6 +102,22 @@ struct sfcdd_ctx {
   size_t ev_used = 0;
   double k_ms[SFCDD_K_COUNT] = {};
   int64_t k_n[SFCDD_K_COUNT] = {};
+
+  Batch batch() const {
+    Batch B;
+    B.grids = d_grids;
+    B.G = G;
+    B.dmax = dmax;
+    B.Ntot = Ntot;
+    B.Ptot = Ptot;
+    B.N0tot = N0tot;
+    B.gid = gid;
+    B.sgid = d_sgid;
+    B.cgid = cgid;
+    B.ctgid = ctgid;
+    B.rbx = rbx;
+    return B;
+  }
 };
 
 #define FAIL(ctx, code, ...)                                   \
@@ -146,17 +175,20 @@ void prof_collect(sfcdd_ctx* c) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Parameter validation and the host partition (eqs. dof, sloc, enlarge,
-// omegai, restr).  Fills everything in ctx except device pointers.
-sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
-  if (!p) FAIL(c, SFCDD_EINVAL, "params is NULL");
-  if (p->d < 1 || p->d > MAXD) FAIL(c, SFCDD_EINVAL, "d = %d out of range 1..%d", p->d, MAXD);
-  if ((p->level == nullptr) == (p->npts == nullptr))
-    FAIL(c, SFCDD_EINVAL, "give exactly one of level / npts");
-  c->d = p->d;
-  c->levels.clear();
-  c->npts.clear();
-  GridDesc& g = c->g;
+// Validation and host partition of one grid (eqs. dof, sloc, enlarge, omegai,
+// restr).  err receives the message on failure.
+sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
+  char buf[512];
+#define GFAIL(code, ...)                     \
+  do {                                       \
+    snprintf(buf, sizeof(buf), __VA_ARGS__); \
+    err = buf;                               \
+    return code;                             \
+  } while (0)
+  if (!p) GFAIL(SFCDD_EINVAL, "params is NULL");
+  if (p->d < 1 || p->d > MAXD) GFAIL(SFCDD_EINVAL, "d = %d out of range 1..%d", p->d, MAXD);
+  if ((p->level == nullptr) == (p->npts == nullptr)) GFAIL(SFCDD_EINVAL, "give exactly one of level / npts");
+  GridDesc& g = h.desc;
   memset(&g, 0, sizeof(g));
   g.d = p->d;
   int nres = 0;
@@ -164,14 +196,12 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
     int n;
     if (p->level) {
       const int l = p->level[j];
-      if (l < 1 || l > 30) FAIL(c, SFCDD_EINVAL, "level[%d] = %d out of range 1..30", j, l);
-      c->levels.push_back(l);
+      if (l < 1 || l > 30) GFAIL(SFCDD_EINVAL, "level[%d] = %d out of range 1..30", j, l);
       n = (1 << l) - 1;
       nres = std::max(nres, l);
     } else {
       n = p->npts[j];
-      if (n < 1) FAIL(c, SFCDD_EINVAL, "npts[%d] = %d < 1", j, n);
-      c->npts.push_back(n);
+      if (n < 1) GFAIL(SFCDD_EINVAL, "npts[%d] = %d < 1", j, n);
     }
     g.n[j] = n;
   }
@@ -181,54 +211,43 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
     while ((int64_t(1) << nres) < (int64_t)mx + 1) ++nres;
     if (nres < 1) nres = 1;
   }
-  if ((int64_t)nres * p->d > 64)
-    FAIL(c, SFCDD_EOVERFLOW, "Morton key needs %d bits > 64", nres * p->d);
+  if ((int64_t)nres * p->d > 64) GFAIL(SFCDD_EOVERFLOW, "Morton key needs %d bits > 64", nres * p->d);
   g.nres = nres;
   int64_t N = 1;
   for (int j = 0; j < p->d; ++j) {
     g.stride[j] = N;
     N *= g.n[j];
-    if (N >= (int64_t(1) << 31)) FAIL(c, SFCDD_EOVERFLOW, "N >= 2^31");
+    if (N >= (int64_t(1) << 31)) GFAIL(SFCDD_EOVERFLOW, "N >= 2^31");
     g.shift[j] = p->level ? nres - p->level[j] : 0;
   }
   g.N = N;
-  c->coeff.assign(p->d, 1.0);
+  h.coeff.assign(p->d, 1.0);
   if (p->coeff)
     for (int j = 0; j < p->d; ++j) {
       if (!(p->coeff[j] > 0.0) || !std::isfinite(p->coeff[j]))
-        FAIL(c, SFCDD_EINVAL, "coeff[%d] must be positive and finite", j);
-      c->coeff[j] = p->coeff[j];
+        GFAIL(SFCDD_EINVAL, "coeff[%d] must be positive and finite", j);
+      h.coeff[j] = p->coeff[j];
     }
   double diag = 0.0;
   for (int j = 0; j < p->d; ++j) {
     const double ih2 = (double)((int64_t)(g.n[j] + 1) * (g.n[j] + 1));
     g.inv_h2[j] = ih2;
-    g.c[j] = c->coeff[j] * ih2;
+    g.c[j] = h.coeff[j] * ih2;
     diag += 2.0 * g.c[j];
   }
   g.diag = diag;
-
-  if (p->P < 1 || p->P > N) FAIL(c, SFCDD_EINVAL, "P = %d must satisfy 1 <= P <= N = %lld", p->P, (long long)N);
+  if (p->P < 1 || p->P > N) GFAIL(SFCDD_EINVAL, "P = %d must satisfy 1 <= P <= N = %lld", p->P, (long long)N);
   if (p->gamma_den < 1 || p->gamma_den > (int64_t(1) << 30) || p->gamma_num < 0)
-    FAIL(c, SFCDD_EINVAL, "gamma = %lld/%lld must be >= 0 with 1 <= den <= 2^30",
-         (long long)p->gamma_num, (long long)p->gamma_den);
+    GFAIL(SFCDD_EINVAL, "gamma = %lld/%lld must be >= 0 with 1 <= den <= 2^30",
+          (long long)p->gamma_num, (long long)p->gamma_den);
   if (p->weighting != SFCDD_WEIGHT_NONE && p->weighting != SFCDD_WEIGHT_OMEGA)
-    FAIL(c, SFCDD_EINVAL, "weighting = %d", p->weighting);
-  if (p->variant != SFCDD_ADDITIVE && p->variant != SFCDD_BALANCED)
-    FAIL(c, SFCDD_EINVAL, "variant = %d", p->variant);
+    GFAIL(SFCDD_EINVAL, "weighting = %d", p->weighting);
+  if (p->variant != SFCDD_ADDITIVE && p->variant != SFCDD_BALANCED) GFAIL(SFCDD_EINVAL, "variant = %d", p->variant);
   if (p->factor_dtype != SFCDD_FP64 && p->factor_dtype != SFCDD_FP32)
-    FAIL(c, SFCDD_EINVAL, "factor_dtype = %d", p->factor_dtype);
+    GFAIL(SFCDD_EINVAL, "factor_dtype = %d", p->factor_dtype);
   if (p->local_solver != SFCDD_LOCAL_CHOLESKY && p->local_solver != SFCDD_LOCAL_INVERSE)
-    FAIL(c, SFCDD_EINVAL, "local_solver = %d", p->local_solver);
-  if (p->layout != 0 && p->layout != 1) FAIL(c, SFCDD_EINVAL, "layout = %d", p->layout);
-  c->P = p->P;
-  c->gnum = p->gamma_num;
-  c->gden = p->gamma_den;
-  c->weighting = p->weighting;
-  c->variant = p->variant;
-  c->fdtype = p->factor_dtype;
-  c->local_solver = p->local_solver;
-  c->layout = p->layout;
+    GFAIL(SFCDD_EINVAL, "local_solver = %d", p->local_solver);
+  if (p->layout != 0 && p->layout != 1) GFAIL(SFCDD_EINVAL, "layout = %d", p->layout);
 
   const int P = p->P;
   const int64_t base = N / P, rem = N % P;
@@ -244,12 +263,14 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
     qq = std::min<int64_t>(qq, base);
     q = (int)std::max<int64_t>(1, qq);
   }
-  if (q < 1 || q > base) FAIL(c, SFCDD_EINVAL, "q = %d must satisfy 1 <= q <= floor(N/P) = %lld", q, (long long)base);
-  if ((int64_t)q * P > (int64_t(1) << 17))
-    FAIL(c, SFCDD_EINVAL, "coarse size qP = %lld exceeds 131072", (long long)q * P);
-  c->q = q;
-  c->N0 = q * P;
-  c->nt0 = (int)ceil_div(c->N0, TS);
+  if (q < 1 || q > base) GFAIL(SFCDD_EINVAL, "q = %d must satisfy 1 <= q <= floor(N/P) = %lld", q, (long long)base);
+  if ((int64_t)q * P > (int64_t(1) << 17)) GFAIL(SFCDD_EINVAL, "coarse size qP = %lld exceeds 131072", (long long)q * P);
+  g.P = P;
+  g.q = q;
+  g.N0 = q * P;
+  g.nt0 = (int)ceil_div(g.N0, TS);
+  g.base = base;
+  g.rem = rem;
 
   // overlapping subdomains, eq. (enlarge), cyclic closure
   const int64_t F = p->gamma_num / p->gamma_den;
@@ -264,8 +285,8 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
     if (i < 0) i += P;
     return piece_start((int)i, base, rem);
   };
-  c->ta.assign(P, 0);
-  c->Ni.assign(P, 0);
+  h.ta.assign(P, 0);
+  h.Ni.assign(P, 0);
   for (int i = 0; i < P; ++i) {
     int64_t len;
     int64_t nl = 0;
@@ -278,21 +299,23 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
       for (int64_t k = -F; k <= F; ++k) len += size_of(i + k);
     }
     if (len >= N) {
-      c->ta[i] = 0;
-      c->Ni[i] = (int32_t)N;
+      h.ta[i] = 0;
+      h.Ni[i] = (int32_t)N;
     } else {
       int64_t t = (start_of(i - F) - nl) % N;
       if (t < 0) t += N;
-      c->ta[i] = (int32_t)t;
-      c->Ni[i] = (int32_t)len;
+      h.ta[i] = (int32_t)t;
+      h.Ni[i] = (int32_t)len;
     }
   }
+  g.F = (int)std::min<int64_t>(F, P);
+  g.ncand = (int)std::min<int64_t>(P, 2 * F + 3);
   // multiplicities and omega_i = 1 / min_{p in Omega_i} m_p (eq. omegai)
-  c->omega.assign(P, 1.0);
-  if (c->weighting == SFCDD_WEIGHT_OMEGA) {
+  h.omega.assign(P, 1.0);
+  if (p->weighting == SFCDD_WEIGHT_OMEGA) {
     std::vector<int32_t> m(N + 1, 0);
     for (int i = 0; i < P; ++i) {
-      const int64_t a = c->ta[i], e = a + c->Ni[i];
+      const int64_t a = h.ta[i], e = a + h.Ni[i];
       if (e <= N) {
         m[a] += 1;
         m[e] -= 1;
@@ -306,87 +329,149 @@ sfcdd_status plan(sfcdd_ctx* c, const sfcdd_params* p) {
     for (int64_t k = 1; k < N; ++k) m[k] += m[k - 1];
     for (int i = 0; i < P; ++i) {
       int32_t mn = INT32_MAX;
-      const int64_t a = c->ta[i];
-      for (int64_t s = 0; s < c->Ni[i]; ++s) {
+      const int64_t a = h.ta[i];
+      for (int64_t s = 0; s < h.Ni[i]; ++s) {
         int64_t q2 = a + s;
         if (q2 >= N) q2 -= N;
         mn = std::min(mn, m[q2]);
       }
-      c->omega[i] = 1.0 / (double)mn;
+      h.omega[i] = 1.0 / (double)mn;
     }
   }
-  // tiles and offsets
-  c->nt.assign(P, 0);
-  c->off.assign(P, 0);
-  c->doff.assign(P, 0);
-  c->xoff.assign(P, 0);
-  c->poff.assign(P, 0);
-  int64_t toff = 0, dof = 0, xof = 0, pof = 0;
-  c->max_nt = 0;
-  c->max_Ni = 0;
-  c->min_Ni = INT32_MAX;
-  for (int i = 0; i < P; ++i) {
-    const int ntb = (int)ceil_div(c->Ni[i], TS);
-    c->nt[i] = ntb;
-    c->off[i] = toff;
-    c->doff[i] = dof;
-    c->xoff[i] = xof;
-    c->poff[i] = pof;
-    toff += (int64_t)ntb * (ntb + 1) / 2;
-    dof += c->Ni[i];
-    xof += (int64_t)ntb * TS;
-    pof += (int64_t)ntb * ntb * TS;
-    c->max_nt = std::max(c->max_nt, ntb);
-    c->max_Ni = std::max(c->max_Ni, c->Ni[i]);
-    c->min_Ni = std::min(c->min_Ni, c->Ni[i]);
+  for (int i = 0; i < P; ++i)
+    if ((int64_t)ceil_div(h.Ni[i], TS) * TS > 8192)
+      GFAIL(SFCDD_EINVAL, "subdomain N_i = %d exceeds 8192 points", h.Ni[i]);
+  return SFCDD_OK;
+#undef GFAIL
+}
+
+// Plans the whole batch: per-grid partitions, batch placement, workspace.
+sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
+  if (G < 1 || G > 65535) FAIL(c, SFCDD_EINVAL, "number of grids %d out of range 1..65535", G);
+  if (!params) FAIL(c, SFCDD_EINVAL, "params is NULL");
+  c->G = G;
+  c->grid.assign(G, GridHost());
+  for (int k = 0; k < G; ++k) {
+    std::string e;
+    const sfcdd_status st = plan_grid(c->grid[k], &params[k], e);
+    if (st != SFCDD_OK) {
+      if (G > 1) e = "grid " + std::to_string(k) + ": " + e;
+      FAIL(c, st, "%s", e.c_str());
+    }
+    if (params[k].weighting != params[0].weighting || params[k].variant != params[0].variant ||
+        params[k].factor_dtype != params[0].factor_dtype ||
+        params[k].local_solver != params[0].local_solver || params[k].layout != params[0].layout)
+      FAIL(c, SFCDD_EINVAL, "grid %d: weighting, variant, factor_dtype, local_solver and layout must "
+           "be the same for every grid of a batch", k);
   }
+  c->weighting = params[0].weighting;
+  c->variant = params[0].variant;
+  c->fdtype = params[0].factor_dtype;
+  c->local_solver = params[0].local_solver;
+  c->layout = params[0].layout;
+  // batch placement
+  int64_t goff = 0, c0off = 0, c0pad = 0;
+  int soff = 0;
+  c->dmax = 0;
+  c->ta.clear(); c->Ni.clear(); c->nt.clear(); c->off.clear(); c->doff.clear();
+  c->xoff.clear(); c->poff.clear(); c->omega.clear(); c->sgid.clear();
+  c->c_nt.clear(); c->c_n.clear(); c->c_off.clear(); c->c_xoff.clear(); c->c_poff.clear();
+  c->c_doff.clear();
+  int64_t toff = 0, dof = 0, xof = 0, pof = 0, ctoff = 0, cpof = 0;
+  c->max_nt = 0; c->max_Ni = 0; c->min_Ni = INT32_MAX; c->max_nt0 = 0; c->max_N0 = 0;
+  for (int k = 0; k < G; ++k) {
+    GridHost& h = c->grid[k];
+    GridDesc& g = h.desc;
+    g.goff = goff;
+    g.soff = soff;
+    g.c0off = c0off;
+    g.c0pad = c0pad;
+    goff += g.N;
+    soff += g.P;
+    c0off += g.N0;
+    c0pad += (int64_t)g.nt0 * TS;
+    c->dmax = std::max(c->dmax, g.d);
+    for (int i = 0; i < g.P; ++i) {
+      const int ntb = (int)ceil_div(h.Ni[i], TS);
+      c->ta.push_back(h.ta[i]);
+      c->Ni.push_back(h.Ni[i]);
+      c->nt.push_back(ntb);
+      c->off.push_back(toff);
+      c->doff.push_back(dof);
+      c->xoff.push_back(xof);
+      c->poff.push_back(pof);
+      c->omega.push_back(h.omega[i]);
+      c->sgid.push_back((uint16_t)k);
+      toff += (int64_t)ntb * (ntb + 1) / 2;
+      dof += h.Ni[i];
+      xof += (int64_t)ntb * TS;
+      pof += (int64_t)ntb * ntb * TS;
+      c->max_nt = std::max(c->max_nt, ntb);
+      c->max_Ni = std::max(c->max_Ni, h.Ni[i]);
+      c->min_Ni = std::min(c->min_Ni, h.Ni[i]);
+    }
+    c->c_nt.push_back(g.nt0);
+    c->c_n.push_back(g.N0);
+    c->c_off.push_back(ctoff);
+    c->c_xoff.push_back(g.c0pad);
+    c->c_poff.push_back(cpof);
+    c->c_doff.push_back(g.c0off);
+    ctoff += (int64_t)g.nt0 * (g.nt0 + 1) / 2;
+    cpof += (int64_t)g.nt0 * g.nt0 * TS;
+    c->max_nt0 = std::max(c->max_nt0, g.nt0);
+    c->max_N0 = std::max(c->max_N0, g.N0);
+  }
+  c->Ntot = goff;
+  if (c->Ntot >= (int64_t(1) << 31)) FAIL(c, SFCDD_EOVERFLOW, "total size of the batch >= 2^31");
+  c->Ptot = soff;
+  c->N0tot = c0off;
+  c->c0len = c0pad;
   c->tiles = toff;
   c->sum_Ni = dof;
   c->xlen = xof;
   c->parts = pof;
-  if (c->max_nt * TS > 8192)
-    FAIL(c, SFCDD_EINVAL, "largest subdomain N_i = %d exceeds 8192 points", c->max_Ni);
-
-  PartDesc& pdsc = c->pd;
-  pdsc.P = P;
-  pdsc.q = q;
-  pdsc.N0 = c->N0;
-  pdsc.base = base;
-  pdsc.rem = rem;
-  pdsc.F = (int)std::min<int64_t>(F, P);
-  pdsc.ncand = (int)std::min<int64_t>(P, 2 * F + 3);
+  c->ctiles = ctoff;
+  c->cparts = cpof;
+  c->rbx = G == 1 ? RED_BLOCKS : std::max(8, RED_BLOCKS / G);
 
   // workspace layout
   const size_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
-  const int64_t ct = (int64_t)c->nt0 * (c->nt0 + 1) / 2;
+  const int64_t Nt = c->Ntot;
+  const int Pt = c->Ptot;
   Planner pl;
-  c->r_sfc = pl.take(4 * N);
-  c->r_pos = pl.take(4 * N);
-  c->r_nbr = pl.take((size_t)8 * p->d * N);
-  c->r_ta = pl.take(4 * P);
-  c->r_Ni = pl.take(4 * P);
-  c->r_nt = pl.take(4 * P);
-  c->r_off = pl.take(8 * P);
-  c->r_doff = pl.take(8 * P);
-  c->r_xoff = pl.take(8 * P);
-  c->r_poff = pl.take(8 * P);
-  c->r_omega = pl.take(8 * P);
+  c->r_sfc = pl.take(4 * Nt);
+  c->r_pos = pl.take(4 * Nt);
+  c->r_nbr = pl.take((size_t)8 * c->dmax * Nt);
+  c->r_gid = pl.take(2 * Nt);
+  c->r_grids = pl.take(sizeof(GridDesc) * G);
+  c->r_ta = pl.take(4 * Pt);
+  c->r_Ni = pl.take(4 * Pt);
+  c->r_nt = pl.take(4 * Pt);
+  c->r_off = pl.take(8 * Pt);
+  c->r_doff = pl.take(8 * Pt);
+  c->r_xoff = pl.take(8 * Pt);
+  c->r_poff = pl.take(8 * Pt);
+  c->r_omega = pl.take(8 * Pt);
+  c->r_sgid = pl.take(2 * Pt);
   c->r_fac = pl.take((size_t)c->tiles * TS2 * es);
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   c->r_facX = pl.take(inv ? (size_t)c->tiles * TS2 * es : 0);
   c->r_xloc = pl.take(inv ? (size_t)c->xlen * es : 0);
   c->r_fpart = pl.take(inv ? (size_t)c->parts * es : 0);
-  c->r_A0 = pl.take((size_t)ct * TS2 * 8);
-  c->r_X0 = pl.take((size_t)ct * TS2 * 8);
-  c->r_c0 = pl.take((size_t)c->nt0 * TS * 8);
-  c->r_d0 = pl.take((size_t)c->nt0 * TS * 8);
-  c->r_cpart = pl.take((size_t)c->nt0 * c->nt0 * TS * 8);
-  c->r_cmeta = pl.take(64);
-  c->r_cpartk = pl.take((size_t)c->nt0 * ((c->nt0 + SPLITK - 1) / SPLITK) * TS2 * 8);
+  c->r_A0 = pl.take((size_t)c->ctiles * TS2 * 8);
+  c->r_X0 = pl.take((size_t)c->ctiles * TS2 * 8);
+  c->r_c0 = pl.take((size_t)c->c0len * 8);
+  c->r_d0 = pl.take((size_t)c->N0tot * 8);
+  c->r_cpart = pl.take((size_t)c->cparts * 8);
+  c->r_cpartk = pl.take(G == 1 ? (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) * TS2 * 8 : 0);
+  c->r_cmeta = pl.take((size_t)G * (4 * 8 + 2 * 4));
+  c->r_cgid = pl.take(2 * c->N0tot);
+  c->r_ctgid = pl.take(2 * c->ctiles);
   c->r_dbuf = pl.take((size_t)c->sum_Ni * 8);
-  c->r_vec = pl.take((size_t)NVEC * (((size_t)N * 8 + 255) & ~size_t(255)));
-  c->r_partials = pl.take((size_t)MAXD * RED_BLOCKS * 8);
-  c->r_scal = pl.take(S_COUNT * 8);
+  c->r_vec = pl.take((size_t)NVEC * (((size_t)Nt * 8 + 255) & ~size_t(255)));
+  c->r_partials = pl.take((size_t)8 * (2 * (size_t)G * c->rbx + (size_t)MAXD * RED_BLOCKS));
+  c->r_scal = pl.take((size_t)8 * G * S_COUNT);
+  c->r_active = pl.take((size_t)4 * G);
   c->r_status = pl.take(64);
   c->r_gout = pl.take(MAXD * 8);
   c->total = pl.top + 256;
@@ -401,6 +486,8 @@ void bind(sfcdd_ctx* c) {
   c->sfc_index = at<int32_t>(c, c->r_sfc);
   c->pos = at<int32_t>(c, c->r_pos);
   c->nbr = at<int32_t>(c, c->r_nbr);
+  c->gid = at<uint16_t>(c, c->r_gid);
+  c->d_grids = at<GridDesc>(c, c->r_grids);
   c->d_ta = at<int32_t>(c, c->r_ta);
   c->d_Ni = at<int32_t>(c, c->r_Ni);
   c->d_nt = at<int32_t>(c, c->r_nt);
@@ -409,6 +496,7 @@ void bind(sfcdd_ctx* c) {
   c->d_xoff = at<int64_t>(c, c->r_xoff);
   c->d_poff = at<int64_t>(c, c->r_poff);
   c->d_omega = at<double>(c, c->r_omega);
+  c->d_sgid = at<uint16_t>(c, c->r_sgid);
   c->fac = at<void>(c, c->r_fac);
   c->facX = at<void>(c, c->r_facX);
   c->xloc = at<void>(c, c->r_xloc);
@@ -420,24 +508,26 @@ void bind(sfcdd_ctx* c) {
   c->cpart = at<double>(c, c->r_cpart);
   c->cpartk = at<double>(c, c->r_cpartk);
   unsigned char* cm = c->ws + c->r_cmeta.off;
-  c->c_off = reinterpret_cast<int64_t*>(cm);       // 0
-  c->c_xoff = reinterpret_cast<int64_t*>(cm + 8);  // 0
-  c->c_poff = reinterpret_cast<int64_t*>(cm + 16); // 0
-  c->c_doff = reinterpret_cast<int64_t*>(cm + 24); // 0
-  c->c_nt = reinterpret_cast<int32_t*>(cm + 32);
-  c->c_n = reinterpret_cast<int32_t*>(cm + 36);
+  const int G = c->G;
+  c->dc_off = reinterpret_cast<int64_t*>(cm);
+  c->dc_xoff = c->dc_off + G;
+  c->dc_poff = c->dc_xoff + G;
+  c->dc_doff = c->dc_poff + G;
+  c->dc_nt = reinterpret_cast<int32_t*>(c->dc_doff + G);
+  c->dc_n = c->dc_nt + G;
+  c->cgid = at<uint16_t>(c, c->r_cgid);
+  c->ctgid = at<uint16_t>(c, c->r_ctgid);
   c->dbuf = at<double>(c, c->r_dbuf);
-  const size_t vstride = ((size_t)c->g.N * 8 + 255) & ~size_t(255);
+  const size_t vstride = ((size_t)c->Ntot * 8 + 255) & ~size_t(255);
   for (int k = 0; k < NVEC; ++k)
     c->vec[k] = reinterpret_cast<double*>(c->ws + c->r_vec.off + k * vstride);
   c->partials = at<double>(c, c->r_partials);
   c->scal = at<double>(c, c->r_scal);
+  c->active = at<int32_t>(c, c->r_active);
   c->status = at<int32_t>(c, c->r_status);
   c->gout = at<double>(c, c->r_gout);
 }
 
-// Batched left-looking tiled Cholesky of nb packed matrices (+ optional
-// inversion into M = A^{-1} via X = L^{-1}, M = X^T X).
 // Batched left-looking factorisation: each workgroup keeps its output tile in
 // registers across the K loop.  A single matrix (part != nullptr) uses the
 // split-K form instead, so that every column step runs on many workgroups.
@@ -465,76 +555,94 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
   }
 }
 
-// F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then d0 = A_0^{-1} c0.
+// F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then d0 = A_0^{-1} c0 (per grid).
 void coarse_solve(sfcdd_ctx* c, const double* v) {
   ProfScope ps(c, SFCDD_K_COARSE);
-  BatchMeta bm{c->c_nt, c->c_off, c->c_xoff, c->c_poff};
-  launch_restrict(c->pd, v, c->c0, c->stream);
-  launch_symv_tiles<double>(1, c->nt0, bm, c->A0, c->c0, c->cpart, c->stream);
-  launch_symv_reduce<double>(1, c->N0, bm, c->c_n, c->c_doff, c->cpart, c->d0, c->stream);
+  const Batch B = c->batch();
+  BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
+  launch_restrict(B, v, c->c0, c->stream);
+  launch_symv_tiles<double>(c->G, c->max_nt0, bm, c->A0, c->c0, c->cpart, c->stream);
+  launch_symv_reduce<double>(c->G, c->max_N0, bm, c->dc_n, c->dc_doff, c->cpart, c->d0, c->stream);
+}
+
+// Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
+void local_solves(sfcdd_ctx* c, const double* w, int waves) {
+  const hipStream_t s = c->stream;
+  const Batch B = c->batch();
+  if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
+    if (c->fdtype == SFCDD_FP32)
+      launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves,
+                                 (const float*)c->fac, w, c->dbuf, s);
+    else
+      launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves,
+                                  (const double*)c->fac, w, c->dbuf, s);
+  } else {
+    BatchMeta bm{c->d_nt, c->d_off, c->d_xoff, c->d_poff};
+    if (c->fdtype == SFCDD_FP32) {
+      launch_gather_local<float>(B, c->max_nt, bm, c->d_ta, c->d_Ni, w, (float*)c->xloc, s);
+      launch_symv_tiles<float>(c->Ptot, c->max_nt, bm, (const float*)c->fac, (const float*)c->xloc,
+                               (float*)c->fpart, s);
+      launch_symv_reduce<float>(c->Ptot, c->max_Ni, bm, c->d_Ni, c->d_doff, (const float*)c->fpart,
+                                c->dbuf, s);
+    } else {
+      launch_gather_local<double>(B, c->max_nt, bm, c->d_ta, c->d_Ni, w, (double*)c->xloc, s);
+      launch_symv_tiles<double>(c->Ptot, c->max_nt, bm, (const double*)c->fac, (const double*)c->xloc,
+                                (double*)c->fpart, s);
+      launch_symv_reduce<double>(c->Ptot, c->max_Ni, bm, c->d_Ni, c->d_doff, (const double*)c->fpart,
+                                 c->dbuf, s);
+    }
+  }
 }
 
 // y = sum_i R_i^T omega_i A_i^{-1} R_i w (eq. w1levprec).
 void fine_apply(sfcdd_ctx* c, const double* w, double* y) {
-  const hipStream_t s = c->stream;
   {
-  ProfScope ps(c, SFCDD_K_LOCAL_SOLVE);
-  if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
-    if (c->fdtype == SFCDD_FP32)
-      launch_schwarz_trsv<float>(c->P, c->g.N, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff,
-                                 c->max_nt, (const float*)c->fac, w, c->dbuf, s);
-    else
-      launch_schwarz_trsv<double>(c->P, c->g.N, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff,
-                                  c->max_nt, (const double*)c->fac, w, c->dbuf, s);
-  } else {
-    BatchMeta bm{c->d_nt, c->d_off, c->d_xoff, c->d_poff};
-    if (c->fdtype == SFCDD_FP32) {
-      launch_gather_local<float>(c->P, c->g.N, c->max_nt, bm, c->d_ta, c->d_Ni, w, (float*)c->xloc, s);
-      launch_symv_tiles<float>(c->P, c->max_nt, bm, (const float*)c->fac, (const float*)c->xloc,
-                               (float*)c->fpart, s);
-      launch_symv_reduce<float>(c->P, c->max_Ni, bm, c->d_Ni, c->d_doff, (const float*)c->fpart,
-                                c->dbuf, s);
-    } else {
-      launch_gather_local<double>(c->P, c->g.N, c->max_nt, bm, c->d_ta, c->d_Ni, w, (double*)c->xloc, s);
-      launch_symv_tiles<double>(c->P, c->max_nt, bm, (const double*)c->fac, (const double*)c->xloc,
-                                (double*)c->fpart, s);
-      launch_symv_reduce<double>(c->P, c->max_Ni, bm, c->d_Ni, c->d_doff, (const double*)c->fpart,
-                                 c->dbuf, s);
-    }
-  }
+    ProfScope ps(c, SFCDD_K_LOCAL_SOLVE);
+    local_solves(c, w, c->trsv_waves);
   }
   ProfScope ps(c, SFCDD_K_SCATTER);
-  launch_scatter(c->g, c->pd, c->d_ta, c->d_Ni, c->d_doff, c->d_omega, c->dbuf, y, s);
+  launch_scatter(c->batch(), c->d_ta, c->d_Ni, c->d_doff, c->d_omega, c->dbuf, y, c->stream);
 }
 
-void spmv(sfcdd_ctx* c, const double* x, double* y, const double* b, double* partials) {
+void spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, double* partials) {
   ProfScope ps(c, SFCDD_K_SPMV);
-  launch_spmv(c->g, c->nbr, x, y, b, partials, nullptr, c->stream);
+  launch_spmv(c->batch(), mode, c->nbr, x, y, b, partials, c->stream);
 }
 
 // h = C^{-1} g in curve order (Alg. 2; balanced form eq. balSW).
 void apply_s(sfcdd_ctx* c, const double* g, double* h) {
   const hipStream_t s = c->stream;
+  const Batch B = c->batch();
   if (c->variant == SFCDD_BALANCED) {
     double *t = c->vec[V_T], *w = c->vec[V_W], *y = c->vec[V_Y], *v = c->vec[V_V];
-    coarse_solve(c, g);                                               // d0 = A0^{-1} R0 g
-    launch_combine(c->g, c->pd, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
-    spmv(c, t, w, g, c->partials);                                    // w = g - A t = G g
-    fine_apply(c, w, y);                                              // y = C1^{-1} G g
-    spmv(c, y, v, nullptr, nullptr);                                  // v = A y
-    coarse_solve(c, v);                                               // d0 = A0^{-1} R0 A y
-    launch_combine(c->g, c->pd, COMB_BAL_FINAL, c->d0, y, t, h, s);  // h = y - F A y + F g
+    coarse_solve(c, g);                                         // d0 = A0^{-1} R0 g
+    launch_combine(B, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
+    spmv(c, 2, t, w, g, c->partials);                           // w = g - A t = G g
+    fine_apply(c, w, y);                                        // y = C1^{-1} G g
+    spmv(c, 0, y, v, nullptr, nullptr);                         // v = A y
+    coarse_solve(c, v);                                         // d0 = A0^{-1} R0 A y
+    launch_combine(B, COMB_BAL_FINAL, c->d0, y, t, h, s);      // h = y - F A y + F g
   } else {
     coarse_solve(c, g);
     fine_apply(c, g, h);
-    launch_combine(c->g, c->pd, COMB_ADD_PROLONG, c->d0, h, nullptr, h, s);
+    launch_combine(B, COMB_ADD_PROLONG, c->d0, h, nullptr, h, s);
   }
 }
 
-sfcdd_status read_scal(sfcdd_ctx* c, int slot, double* out) {
-  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal + slot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+// Copies the per-grid scalars to the pinned host buffer.
+sfcdd_status read_scal(sfcdd_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * c->G * S_COUNT,
+                           hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  *out = c->host_scal[0];
+  return SFCDD_OK;
+}
+double hs(sfcdd_ctx* c, int g, int slot) { return c->host_scal[(size_t)g * S_COUNT + slot]; }
+
+sfcdd_status write_active(sfcdd_ctx* c, const std::vector<int32_t>& act) {
+  int32_t* hb = reinterpret_cast<int32_t*>(c->host_scal + (size_t)c->G * S_COUNT);
+  for (int g = 0; g < c->G; ++g) hb[g] = act[g];
+  HIPCHK(c, hipMemcpyAsync(c->active, hb, 4 * c->G, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SFCDD_OK;
 }
 
@@ -572,111 +680,88 @@ void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b
   *lmax = kth(m - 1);
 }
 
-}  // namespace
-
-extern "C" {
-
-sfcdd_status sfcdd_workspace_size(const sfcdd_params* params, size_t* bytes) {
-  if (!bytes) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "bytes is NULL");
-  sfcdd_ctx tmp;
-  const sfcdd_status st = plan(&tmp, params);
-  if (st != SFCDD_OK) {
-    g_last_error = tmp.err;
-    return st;
-  }
-  *bytes = tmp.total;
-  return SFCDD_OK;
-}
-
-sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t bytes,
-                         void* hip_stream, sfcdd_ctx** out) {
-  if (!out) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!workspace_dev) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "workspace is NULL");
-  sfcdd_ctx* c = new (std::nothrow) sfcdd_ctx();
-  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_ENOMEM, "host allocation failed");
-  sfcdd_status st = plan(c, params);
-  if (st != SFCDD_OK) {
-    g_last_error = c->err;
-    delete c;
-    return st;
-  }
-  if (bytes < c->total) {
-    g_last_error = "workspace too small: need " + std::to_string(c->total) + " bytes";
-    delete c;
-    return SFCDD_ENOMEM;
-  }
-  // align the base
-  c->ws = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(workspace_dev) + 255) & ~uintptr_t(255));
-  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  bind(c);
-  if (hipHostMalloc((void**)&c->host_scal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    g_last_error = "hipHostMalloc failed";
-    delete c;
-    return SFCDD_EDEVICE;
-  }
-  *out = c;
+// Device setup of a planned context (Alg. 1).
+sfcdd_status setup_device(sfcdd_ctx* c) {
   const hipStream_t s = c->stream;
-  const int P = c->P;
+  const int G = c->G;
+  const int Pt = c->Ptot;
+  const Batch B = c->batch();
   hipEvent_t ev[6];
   for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
   HIPCHK(c, hipEventRecord(ev[0], s));
 
-  // tables
-  HIPCHK(c, hipMemcpyAsync(c->d_ta, c->ta.data(), 4 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_Ni, c->Ni.data(), 4 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_nt, c->nt.data(), 4 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_off, c->off.data(), 8 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_doff, c->doff.data(), 8 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_xoff, c->xoff.data(), 8 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_poff, c->poff.data(), 8 * P, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_omega, c->omega.data(), 8 * P, hipMemcpyHostToDevice, s));
-  {
-    static thread_local int64_t zeros[4] = {0, 0, 0, 0};
-    static thread_local int32_t cm[2];
-    cm[0] = c->nt0;
-    cm[1] = c->N0;
-    HIPCHK(c, hipMemcpyAsync(c->ws + c->r_cmeta.off, zeros, 32, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->c_nt, cm, 8, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+  // tables (host temporaries: synchronised before they go out of scope)
+  std::vector<GridDesc> gd(G);
+  for (int k = 0; k < G; ++k) gd[k] = c->grid[k].desc;
+  std::vector<uint16_t> gid, cgid, ctgid;
+  if (G > 1) {
+    gid.resize(c->Ntot);
+    cgid.resize(c->N0tot);
+    ctgid.resize(c->ctiles);
+    for (int k = 0; k < G; ++k) {
+      const GridDesc& g = gd[k];
+      std::fill(gid.begin() + g.goff, gid.begin() + g.goff + g.N, (uint16_t)k);
+      std::fill(cgid.begin() + g.c0off, cgid.begin() + g.c0off + g.N0, (uint16_t)k);
+      std::fill(ctgid.begin() + c->c_off[k],
+                ctgid.begin() + c->c_off[k] + (int64_t)g.nt0 * (g.nt0 + 1) / 2, (uint16_t)k);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->gid, gid.data(), 2 * c->Ntot, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->cgid, cgid.data(), 2 * c->N0tot, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->ctgid, ctgid.data(), 2 * c->ctiles, hipMemcpyHostToDevice, s));
   }
+  HIPCHK(c, hipMemcpyAsync(c->d_grids, gd.data(), sizeof(GridDesc) * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_ta, c->ta.data(), 4 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_Ni, c->Ni.data(), 4 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_nt, c->nt.data(), 4 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_off, c->off.data(), 8 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_doff, c->doff.data(), 8 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_xoff, c->xoff.data(), 8 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_poff, c->poff.data(), 8 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_omega, c->omega.data(), 8 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_sgid, c->sgid.data(), 2 * Pt, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_off, c->c_off.data(), 8 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_xoff, c->c_xoff.data(), 8 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_poff, c->c_poff.data(), 8 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_doff, c->c_doff.data(), 8 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_nt, c->c_nt.data(), 4 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_n, c->c_n.data(), 4 * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemsetAsync(c->status, 0, 64, s));
+  HIPCHK(c, hipStreamSynchronize(s));
 
   // curve order and neighbours (Alg. 1: sfc_index, neighbour map)
-  HIPCHK(c, hipMemsetAsync(c->sfc_index, 0, 4 * c->g.N, s));
-  launch_sfc_rank(c->g, c->pos, c->sfc_index, s);
+  HIPCHK(c, hipMemsetAsync(c->sfc_index, 0, 4 * c->Ntot, s));
+  launch_sfc_rank(B, c->pos, c->sfc_index, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[1], s));
-  launch_build_nbr(c->g, c->pos, c->sfc_index, c->nbr, s);
+  launch_build_nbr(B, c->pos, c->sfc_index, c->nbr, s);
   HIPCHK(c, hipEventRecord(ev[2], s));
 
-  // The coarse setup (one matrix, latency-bound right-looking steps) runs on
-  // an internal stream forked from the caller's, concurrently with the
-  // batched subdomain factorisation; both join before setup returns.
-  hipEvent_t fork, join;
+  // The coarse setup (small, latency-bound steps) runs on an internal stream
+  // forked from the caller's, concurrently with the batched subdomain
+  // factorisation; both join before setup returns.
+  hipEvent_t fork, join, cev0, cev1;
   HIPCHK(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
   HIPCHK(c, hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreate(&cev0));
+  HIPCHK(c, hipEventCreate(&cev1));
   if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   HIPCHK(c, hipEventRecord(fork, s));
   HIPCHK(c, hipStreamWaitEvent(c->side, fork, 0));
-  hipEvent_t cev0, cev1;
-  HIPCHK(c, hipEventCreate(&cev0));
-  HIPCHK(c, hipEventCreate(&cev1));
   {
     const hipStream_t cs = c->side;
     HIPCHK(c, hipEventRecord(cev0, cs));
-    // coarse matrix A_0 = R_0 A R_0^T = sum_j c_j E_j (eq. csm), then A_0^{-1}
+    // coarse matrices A_0 = R_0 A R_0^T = sum_j c_j E_j (eq. csm), then A_0^{-1}
     HIPCHK(c, hipMemsetAsync(c->A0, 0, c->r_A0.bytes, cs));
     HIPCHK(c, hipMemsetAsync(c->c0, 0, c->r_c0.bytes, cs));
-    const int64_t ctiles_elems = (int64_t)c->nt0 * (c->nt0 + 1) / 2 * TS2;
-    for (int j = 0; j < c->d; ++j) {
-      HIPCHK(c, hipMemsetAsync(c->X0, 0, (size_t)ctiles_elems * 4, cs));
-      launch_coarse_counts(c->g, c->pd, j, c->nbr, (int32_t*)c->X0, cs);
-      launch_coarse_accumulate(ctiles_elems, c->g.c[j], (const int32_t*)c->X0, c->A0, cs);
+    const int64_t celems = c->ctiles * TS2;
+    for (int j = 0; j < c->dmax; ++j) {
+      HIPCHK(c, hipMemsetAsync(c->X0, 0, (size_t)celems * 4, cs));
+      launch_coarse_counts(B, j, c->nbr, c->dc_off, (int32_t*)c->X0, cs);
+      launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
     }
-    launch_coarse_pad(c->N0, c->nt0, c->A0, cs);
-    factor_batch<double>(1, c->nt0, c->c_nt, c->c_off, c->A0, c->X0, true, c->status + 1,
-                         c->cpartk, cs);
+    launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
+    factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, c->status + 1,
+                         G == 1 ? c->cpartk : (double*)nullptr, cs);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
     HIPCHK(c, hipEventRecord(join, cs));
@@ -685,10 +770,10 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   // local matrices A_i = R_i A R_i^T
   HIPCHK(c, hipMemsetAsync(c->fac, 0, c->r_fac.bytes, s));
   if (c->fdtype == SFCDD_FP32)
-    launch_assemble_local<float>(c->g, P, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->nbr, c->max_nt,
+    launch_assemble_local<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->nbr, c->max_nt,
                                  (float*)c->fac, s);
   else
-    launch_assemble_local<double>(c->g, P, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->nbr, c->max_nt,
+    launch_assemble_local<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->nbr, c->max_nt,
                                   (double*)c->fac, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[3], s));
@@ -696,10 +781,10 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   // factor once (Sec. 3.1)
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   if (c->fdtype == SFCDD_FP32)
-    factor_batch<float>(P, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv,
+    factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv,
                         c->status, (float*)nullptr, s);
   else
-    factor_batch<double>(P, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv,
+    factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv,
                          c->status, (double*)nullptr, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
@@ -719,10 +804,10 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   (void)hipEventDestroy(fork);
   (void)hipEventDestroy(join);
   sfcdd_info& I = c->info;
-  I.N = c->g.N;
-  I.P = c->P;
-  I.q = c->q;
-  I.N0 = c->N0;
+  I.N = c->Ntot;
+  I.P = c->Ptot;
+  I.q = c->grid[0].desc.q;
+  I.N0 = (int32_t)c->N0tot;
   I.max_Ni = c->max_Ni;
   I.min_Ni = c->min_Ni;
   I.tile = TS;
@@ -730,23 +815,86 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
   const int64_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
   I.factor_bytes = c->tiles * TS2 * es;
   int64_t algo = 0;
-  for (int i = 0; i < P; ++i) algo += (int64_t)c->Ni[i] * (c->Ni[i] + 1) / 2;
+  for (int i = 0; i < Pt; ++i) algo += (int64_t)c->Ni[i] * (c->Ni[i] + 1) / 2;
   I.factor_algo_bytes = algo * es;
   I.coarse_bytes = (int64_t)c->r_A0.bytes;
   for (int k = 0; k < 5; ++k) I.setup_ms[k] = ms[k];
   I.setup_ms[5] = tot;
+  I.ngrids = G;
+  I.trsv_waves = c->trsv_waves;
 
   int32_t stat[2] = {0, 0};
   HIPCHK(c, hipMemcpy(stat, c->status, 8, hipMemcpyDeviceToHost));
   if (stat[0] != 0) FAIL(c, SFCDD_ENOTSPD, "a local matrix is not positive definite");
-  if (stat[1] != 0) FAIL(c, SFCDD_ENOTSPD, "the coarse matrix is not positive definite");
+  if (stat[1] != 0) FAIL(c, SFCDD_ENOTSPD, "a coarse matrix is not positive definite");
   return SFCDD_OK;
+}
+
+sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev, size_t bytes,
+                          void* hip_stream, sfcdd_ctx** out) {
+  if (!out) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!workspace_dev) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "workspace is NULL");
+  sfcdd_ctx* c = new (std::nothrow) sfcdd_ctx();
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_ENOMEM, "host allocation failed");
+  sfcdd_status st = plan(c, G, params);
+  if (st != SFCDD_OK) {
+    g_last_error = c->err;
+    delete c;
+    return st;
+  }
+  if (bytes < c->total) {
+    g_last_error = "workspace too small: need " + std::to_string(c->total) + " bytes";
+    delete c;
+    return SFCDD_ENOMEM;
+  }
+  c->ws = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(workspace_dev) + 255) & ~uintptr_t(255));
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  bind(c);
+  if (hipHostMalloc((void**)&c->host_scal, sizeof(double) * ((size_t)G * S_COUNT + (size_t)G + 256),
+                    hipHostMallocDefault) != hipSuccess) {
+    g_last_error = "hipHostMalloc failed";
+    delete c;
+    return SFCDD_EDEVICE;
+  }
+  *out = c;
+  return setup_device(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+sfcdd_status sfcdd_workspace_size_batch(int32_t ngrids, const sfcdd_params* params, size_t* bytes) {
+  if (!bytes) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "bytes is NULL");
+  sfcdd_ctx tmp;
+  const sfcdd_status st = plan(&tmp, ngrids, params);
+  if (st != SFCDD_OK) {
+    g_last_error = tmp.err;
+    return st;
+  }
+  *bytes = tmp.total;
+  return SFCDD_OK;
+}
+
+sfcdd_status sfcdd_workspace_size(const sfcdd_params* params, size_t* bytes) {
+  return sfcdd_workspace_size_batch(1, params, bytes);
+}
+
+sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t bytes,
+                         void* hip_stream, sfcdd_ctx** out) {
+  return setup_common(1, params, workspace_dev, bytes, hip_stream, out);
+}
+
+sfcdd_status sfcdd_setup_batch(int32_t ngrids, const sfcdd_params* params, void* workspace_dev,
+                               size_t bytes, void* hip_stream, sfcdd_ctx** out) {
+  return setup_common(ngrids, params, workspace_dev, bytes, hip_stream, out);
 }
 
 sfcdd_status sfcdd_apply_precond(sfcdd_ctx* c, const double* g, double* h) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
   if (!g || !h || g == h) FAIL(c, SFCDD_EINVAL, "g and h must be distinct non-NULL device vectors");
-  const int64_t N = c->g.N;
+  const int64_t N = c->Ntot;
   if (c->layout == 1) {
     apply_s(c, g, h);
   } else {
@@ -761,12 +909,12 @@ sfcdd_status sfcdd_apply_precond(sfcdd_ctx* c, const double* g, double* h) {
 sfcdd_status sfcdd_matvec(sfcdd_ctx* c, const double* x, double* y) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
   if (!x || !y || x == y) FAIL(c, SFCDD_EINVAL, "x and y must be distinct non-NULL device vectors");
-  const int64_t N = c->g.N;
+  const int64_t N = c->Ntot;
   if (c->layout == 1) {
-    launch_spmv(c->g, c->nbr, x, y, nullptr, nullptr, nullptr, c->stream);
+    spmv(c, 0, x, y, nullptr, nullptr);
   } else {
     launch_permute(N, c->sfc_index, x, c->vec[V_IN], 1, c->stream);
-    launch_spmv(c->g, c->nbr, c->vec[V_IN], c->vec[V_OUT], nullptr, nullptr, nullptr, c->stream);
+    spmv(c, 0, c->vec[V_IN], c->vec[V_OUT], nullptr, nullptr);
     launch_permute(N, c->sfc_index, c->vec[V_OUT], y, 0, c->stream);
   }
   HIPCHK(c, hipGetLastError());
@@ -781,7 +929,9 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   if (method != SFCDD_PCG && method != SFCDD_FCG && method != SFCDD_RICHARDSON)
     FAIL(c, SFCDD_EINVAL, "method = %d", method);
   const hipStream_t s = c->stream;
-  const int64_t N = c->g.N;
+  const int64_t N = c->Ntot;
+  const int G = c->G;
+  const Batch B = c->batch();
   double *x = c->vec[V_X], *r = c->vec[V_R], *z = c->vec[V_Z], *p = c->vec[V_P], *q = c->vec[V_Q],
          *b = c->vec[V_B], *tmp = c->vec[V_TMP];
   if (c->layout == 1) {
@@ -791,126 +941,202 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     launch_permute(N, c->sfc_index, b_in, b, 1, s);
     launch_permute(N, c->sfc_index, x_io, x, 1, s);
   }
-  launch_dot(N, b, b, nullptr, c->partials, s);
-  launch_finalize(FIN_BB, c->partials, c->scal, s);
-  double bb;
-  sfcdd_status st = read_scal(c, S_BB, &bb);
-  if (st) return st;
-  const double tol2 = rtol * rtol * bb;
+  launch_dot(B, b, b, nullptr, c->partials, s);
+  launch_finalize(B, FIN_BB, c->partials, c->scal, s);
+  sfcdd_status st;
+  if ((st = read_scal(c))) return st;
+  std::vector<double> tol2(G), bb(G), rr(G, 0.0);
+  for (int g = 0; g < G; ++g) {
+    bb[g] = hs(c, g, S_BB);
+    tol2[g] = rtol * rtol * bb[g];
+  }
+  std::vector<int32_t> act(G, 1), its(G, 0);
   sfcdd_solve_info inf{};
   int it = 0, restarts = 0;
-  bool conv = false;
-  double rr = 0.0;
+  auto n_active = [&]() {
+    int n = 0;
+    for (int g = 0; g < G; ++g) n += act[g] != 0;
+    return n;
+  };
+  auto read_rr = [&]() -> sfcdd_status {
+    sfcdd_status e = read_scal(c);
+    if (e) return e;
+    for (int g = 0; g < G; ++g) rr[g] = hs(c, g, S_RR);
+    return SFCDD_OK;
+  };
 
   if (method == SFCDD_RICHARDSON) {
+    std::vector<double> xig(G, xi);
     if (!(xi > 0.0)) {
-      // Lanczos estimate of the extreme eigenvalues of C^{-1}A from CG steps
-      std::vector<double> al, be;
-      launch_zero(N, z, s);  // z used as x of the estimation run
+      // Lanczos estimate of the extreme eigenvalues of C^{-1}A from CG steps (per grid)
+      std::vector<std::vector<double>> al(G), be(G);
+      std::vector<int32_t> ok(G, 1);
+      if ((st = write_active(c, ok))) return st;
+      launch_zero(N, z, s);  // z is the iterate of the estimation run
       launch_copy(N, b, r, s);
       apply_s(c, r, q);
       launch_copy(N, q, p, s);
-      launch_dot(N, r, q, nullptr, c->partials, s);
-      launch_finalize(FIN_RZ_INIT, c->partials, c->scal, s);
+      launch_dot(B, r, q, nullptr, c->partials, s);
+      launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, s);
       for (int k = 0; k < 30; ++k) {
-        spmv(c, p, tmp, nullptr, c->partials);
-        launch_finalize(FIN_PQ_ALPHA, c->partials, c->scal, s);
-        launch_update_xr(N, c->scal, z, r, p, tmp, c->partials, s);
-        double a_k;
-        if ((st = read_scal(c, S_ALPHA, &a_k))) return st;
-        if (!(a_k > 0.0) || !std::isfinite(a_k)) break;
-        al.push_back(a_k);
+        spmv(c, 1, p, tmp, nullptr, c->partials);
+        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, s);
+        launch_update_xr(B, c->scal, c->active, z, r, p, tmp, c->partials, s);
+        if ((st = read_scal(c))) return st;
+        for (int g = 0; g < G; ++g) {
+          const double a_k = hs(c, g, S_ALPHA);
+          if (ok[g] && a_k > 0.0 && std::isfinite(a_k)) al[g].push_back(a_k);
+          else ok[g] = 0;
+        }
         apply_s(c, r, q);
-        launch_dot(N, r, q, nullptr, c->partials, s);
-        launch_finalize(FIN_RZ_NEXT, c->partials, c->scal, s);
-        double b_k;
-        if ((st = read_scal(c, S_BETA, &b_k))) return st;
-        if (!(b_k > 0.0) || !std::isfinite(b_k)) break;
-        be.push_back(b_k);
-        launch_update_p(N, c->scal, p, q, s);
+        launch_dot(B, r, q, nullptr, c->partials, s);
+        launch_finalize(B, FIN_RZ_NEXT, c->partials, c->scal, s);
+        if ((st = read_scal(c))) return st;
+        for (int g = 0; g < G; ++g) {
+          const double b_k = hs(c, g, S_BETA);
+          if (ok[g] && b_k > 0.0 && std::isfinite(b_k)) be[g].push_back(b_k);
+          else ok[g] = 0;
+        }
+        if ((st = write_active(c, ok))) return st;
+        int nok = 0;
+        for (int g = 0; g < G; ++g) nok += ok[g];
+        if (nok == 0) break;
+        launch_update_p(B, c->scal, c->active, p, q, s);
       }
-      const int m = (int)al.size();
-      if (m == 0) FAIL(c, SFCDD_ENOTCONV, "Lanczos estimate failed");
-      std::vector<double> ta(m), tb(m > 1 ? m - 1 : 0);
-      for (int k = 0; k < m; ++k) ta[k] = 1.0 / al[k] + (k > 0 ? be[k - 1] / al[k - 1] : 0.0);
-      for (int k = 0; k + 1 < m; ++k) tb[k] = std::sqrt(be[k]) / al[k];
-      double lmin, lmax;
-      tridiag_extremes(ta, tb, &lmin, &lmax);
-      inf.lambda_min = lmin;
-      inf.lambda_max = lmax;
-      xi = 2.0 / (lmin + lmax);
+      for (int g = 0; g < G; ++g) {
+        const int m = (int)std::min(al[g].size(), be[g].size() + 1);
+        if (m == 0) FAIL(c, SFCDD_ENOTCONV, "Lanczos estimate failed for grid %d", g);
+        std::vector<double> ta(m), tb(m > 1 ? m - 1 : 0);
+        for (int k = 0; k < m; ++k) ta[k] = 1.0 / al[g][k] + (k > 0 ? be[g][k - 1] / al[g][k - 1] : 0.0);
+        for (int k = 0; k + 1 < m; ++k) tb[k] = std::sqrt(be[g][k]) / al[g][k];
+        double lmin, lmax;
+        tridiag_extremes(ta, tb, &lmin, &lmax);
+        if (g == 0) {
+          inf.lambda_min = lmin;
+          inf.lambda_max = lmax;
+        }
+        xig[g] = 2.0 / (lmin + lmax);
+      }
     }
-    inf.xi = xi;
-    double* hx = c->host_scal + 8;
-    hx[0] = xi;
-    HIPCHK(c, hipMemcpyAsync(c->scal + S_XI, hx, 8, hipMemcpyHostToDevice, s));
+    inf.xi = xig[0];
+    // damping per grid into S_XI (read-modify-write of the scalar array)
+    if ((st = read_scal(c))) return st;
+    for (int g = 0; g < G; ++g) c->host_scal[(size_t)g * S_COUNT + S_XI] = xig[g];
+    HIPCHK(c, hipMemcpyAsync(c->scal, c->host_scal, sizeof(double) * G * S_COUNT,
+                             hipMemcpyHostToDevice, s));
+    std::fill(act.begin(), act.end(), 1);
     for (;;) {
-      spmv(c, x, r, b, c->partials);
-      launch_finalize(FIN_RR, c->partials, c->scal, s);
-      if ((st = read_scal(c, S_RR, &rr))) return st;
-      if (rr <= tol2) { conv = true; break; }
-      if (it >= max_iter) break;
+      spmv(c, 2, x, r, b, c->partials);
+      launch_finalize(B, FIN_RR, c->partials, c->scal, s);
+      if ((st = read_rr())) return st;
+      for (int g = 0; g < G; ++g)
+        if (act[g] && rr[g] <= tol2[g]) act[g] = 0;
+      if (n_active() == 0 || it >= max_iter) break;
+      if ((st = write_active(c, act))) return st;
       apply_s(c, r, z);
-      launch_axpy_scal(N, c->scal, S_XI, x, z, s);
+      launch_axpy_scal(B, c->scal, S_XI, c->active, x, z, s);
       ++it;
+      for (int g = 0; g < G; ++g) its[g] += act[g] != 0;
     }
   } else {
     const bool flex = method == SFCDD_FCG;
-    bool fresh = true;
-    while (true) {
-      if (fresh) {
-        spmv(c, x, r, b, c->partials);
-        launch_finalize(FIN_RR, c->partials, c->scal, s);
-        if ((st = read_scal(c, S_RR, &rr))) return st;
-        if (rr <= tol2) { conv = true; break; }
-        if (it >= max_iter) break;
-        apply_s(c, r, z);
-        launch_dot(N, r, z, nullptr, c->partials, s);
-        launch_finalize(FIN_RZ_INIT, c->partials, c->scal, s);
-        launch_copy(N, z, p, s);
-        fresh = false;
-      }
-      spmv(c, p, q, nullptr, c->partials);
-      launch_finalize(FIN_PQ_ALPHA, c->partials, c->scal, s);
-      launch_update_xr(N, c->scal, x, r, p, q, c->partials, s);
-      launch_finalize(FIN_RR, c->partials, c->scal, s);
-      ++it;
-      if ((st = read_scal(c, S_RR, &rr))) return st;
-      if (!std::isfinite(rr)) FAIL(c, SFCDD_ENOTCONV, "residual is not finite");
-      if (rr <= tol2 || it >= max_iter) {
-        // confirm on the true residual; restart from x when they disagree
-        spmv(c, x, tmp, b, c->partials);
-        launch_finalize(FIN_RR, c->partials, c->scal, s);
-        if ((st = read_scal(c, S_RR, &rr))) return st;
-        if (rr <= tol2) { conv = true; break; }
-        if (it >= max_iter || restarts >= 8) break;
-        ++restarts;
-        fresh = true;
-        continue;
-      }
+    // r = b - A x, z = C^{-1} r, p = z
+    spmv(c, 2, x, r, b, c->partials);
+    launch_finalize(B, FIN_RR, c->partials, c->scal, s);
+    if ((st = read_rr())) return st;
+    for (int g = 0; g < G; ++g)
+      if (rr[g] <= tol2[g]) act[g] = 0;
+    if (n_active() > 0 && max_iter > 0) {
+      if ((st = write_active(c, act))) return st;
       apply_s(c, r, z);
-      launch_dot(N, z, r, flex ? q : nullptr, c->partials, s);
-      launch_finalize(flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT, c->partials, c->scal, s);
-      launch_update_p(N, c->scal, p, z, s);
+      launch_dot(B, r, z, nullptr, c->partials, s);
+      launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, s);
+      launch_copy(N, z, p, s);
+      while (true) {
+        spmv(c, 1, p, q, nullptr, c->partials);
+        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, s);
+        launch_update_xr(B, c->scal, c->active, x, r, p, q, c->partials, s);
+        launch_finalize(B, FIN_RR, c->partials, c->scal, s);
+        ++it;
+        for (int g = 0; g < G; ++g) its[g] += act[g] != 0;
+        if ((st = read_rr())) return st;
+        bool check = false;
+        for (int g = 0; g < G; ++g) {
+          if (!act[g]) continue;
+          if (!std::isfinite(rr[g])) FAIL(c, SFCDD_ENOTCONV, "residual of grid %d is not finite", g);
+          if (rr[g] <= tol2[g] || it >= max_iter) check = true;
+        }
+        if (check) {
+          // confirm on the true residual; a grid whose true residual is still
+          // too large restarts from its current x (residual replacement)
+          spmv(c, 2, x, tmp, b, c->partials);
+          launch_finalize(B, FIN_RR, c->partials, c->scal, s);
+          std::vector<double> rec = rr;
+          if ((st = read_rr())) return st;
+          for (int g = 0; g < G; ++g) {
+            if (!act[g]) continue;
+            if (rr[g] <= tol2[g]) {
+              act[g] = 0;
+            } else if (rec[g] <= tol2[g] && it < max_iter && restarts < 8 * G) {
+              const GridDesc& gd = c->grid[g].desc;
+              launch_copy(gd.N, tmp + gd.goff, r + gd.goff, s);
+              act[g] = 2;  // p = z at the next direction update
+              ++restarts;
+            }
+          }
+          if (it >= max_iter) break;
+        }
+        if (n_active() == 0) break;
+        if ((st = write_active(c, act))) return st;
+        apply_s(c, r, z);
+        launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
+        launch_finalize(B, flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT, c->partials, c->scal, s);
+        launch_update_p(B, c->scal, c->active, p, z, s);
+        for (int g = 0; g < G; ++g)
+          if (act[g] == 2) act[g] = 1;
+      }
     }
   }
   if (c->layout == 1) launch_copy(N, x, x_io, s);
   else launch_permute(N, c->sfc_index, x, x_io, 0, s);
   HIPCHK(c, hipStreamSynchronize(s));
   prof_collect(c);
-  inf.iterations = it;
+  c->last_iters = its;
+  c->last_relres.assign(G, 0.0);
+  bool conv = true;
+  double worst = 0.0;
+  int itmax = 0;
+  for (int g = 0; g < G; ++g) {
+    const double rel = bb[g] > 0 ? std::sqrt(rr[g] / bb[g]) : std::sqrt(rr[g]);
+    c->last_relres[g] = rel;
+    worst = std::max(worst, rel);
+    itmax = std::max(itmax, its[g]);
+    if (rr[g] > tol2[g]) conv = false;
+  }
+  inf.iterations = itmax;
   inf.restarts = restarts;
-  inf.rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+  inf.rel_residual = worst;
   if (info) *info = inf;
-  if (!conv) FAIL(c, SFCDD_ENOTCONV, "not converged after %d iterations (rel. residual %.3e)", it, inf.rel_residual);
+  if (!conv) FAIL(c, SFCDD_ENOTCONV, "not converged after %d iterations (rel. residual %.3e)", itmax, worst);
+  return SFCDD_OK;
+}
+
+sfcdd_status sfcdd_get_batch_stats(sfcdd_ctx* c, int32_t* iterations, double* rel_residual) {
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  for (int g = 0; g < c->G; ++g) {
+    if (iterations) iterations[g] = g < (int)c->last_iters.size() ? c->last_iters[g] : 0;
+    if (rel_residual) rel_residual[g] = g < (int)c->last_relres.size() ? c->last_relres[g] : 0.0;
+  }
   return SFCDD_OK;
 }
 
 sfcdd_status sfcdd_grad_coeff(sfcdd_ctx* c, const double* lam, const double* u, double* grad_a) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
   if (!lam || !u || !grad_a) FAIL(c, SFCDD_EINVAL, "NULL argument");
+  if (c->G != 1) FAIL(c, SFCDD_EINVAL, "the coefficient gradient is defined for a single grid");
   const hipStream_t s = c->stream;
-  const int64_t N = c->g.N;
+  const int64_t N = c->Ntot;
+  const GridDesc& g = c->grid[0].desc;
   const double *L = lam, *U = u;
   if (c->layout == 1) {  // to natural order
     launch_permute(N, c->sfc_index, lam, c->vec[V_IN], 0, s);
@@ -918,44 +1144,84 @@ sfcdd_status sfcdd_grad_coeff(sfcdd_ctx* c, const double* lam, const double* u, 
     L = c->vec[V_IN];
     U = c->vec[V_OUT];
   }
-  launch_grad_coeff(c->g, L, U, c->partials, s);
-  launch_finalize_vec(c->d, c->partials, c->gout, s);
-  HIPCHK(c, hipMemcpyAsync(c->host_scal + 16, c->gout, 8 * c->d, hipMemcpyDeviceToHost, s));
+  launch_grad_coeff(g, L, U, c->partials, s);
+  launch_finalize_vec(g.d, c->partials, c->gout, s);
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->gout, 8 * g.d, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  for (int j = 0; j < c->d; ++j) grad_a[j] = -c->g.inv_h2[j] * c->host_scal[16 + j];
+  for (int j = 0; j < g.d; ++j) grad_a[j] = -g.inv_h2[j] * c->host_scal[j];
   return SFCDD_OK;
 }
 
-sfcdd_status sfcdd_get_partition(sfcdd_ctx* c, int32_t* sfc_index_host, int64_t* ta_host,
-                                 int64_t* Ni_host, double* omega_host, int32_t* q_out) {
+sfcdd_status sfcdd_get_partition(sfcdd_ctx* c, int32_t grid, int32_t* sfc_index_host,
+                                 int64_t* ta_host, int64_t* Ni_host, double* omega_host,
+                                 int32_t* q_out) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  if (grid < 0 || grid >= c->G) FAIL(c, SFCDD_EINVAL, "grid %d out of range", grid);
+  const GridHost& h = c->grid[grid];
   if (sfc_index_host) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(sfc_index_host, c->sfc_index, 4 * c->g.N, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(sfc_index_host, c->sfc_index + h.desc.goff, 4 * h.desc.N, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < h.desc.N; ++k) sfc_index_host[k] -= (int32_t)h.desc.goff;
   }
-  for (int i = 0; i < c->P; ++i) {
-    if (ta_host) ta_host[i] = c->ta[i];
-    if (Ni_host) Ni_host[i] = c->Ni[i];
-    if (omega_host) omega_host[i] = c->omega[i];
+  for (int i = 0; i < h.desc.P; ++i) {
+    if (ta_host) ta_host[i] = h.ta[i];
+    if (Ni_host) Ni_host[i] = h.Ni[i];
+    if (omega_host) omega_host[i] = h.omega[i];
   }
-  if (q_out) *q_out = c->q;
+  if (q_out) *q_out = h.desc.q;
   return SFCDD_OK;
 }
 
 sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, int64_t* Ni_host,
                                   double* omega_host, int32_t* q_out) {
-  sfcdd_ctx tmp;
-  const sfcdd_status st = plan(&tmp, params);
+  GridHost h;
+  std::string e;
+  const sfcdd_status st = plan_grid(h, params, e);
   if (st != SFCDD_OK) {
-    g_last_error = tmp.err;
+    g_last_error = e;
     return st;
   }
-  for (int i = 0; i < tmp.P; ++i) {
-    if (ta_host) ta_host[i] = tmp.ta[i];
-    if (Ni_host) Ni_host[i] = tmp.Ni[i];
-    if (omega_host) omega_host[i] = tmp.omega[i];
+  for (int i = 0; i < h.desc.P; ++i) {
+    if (ta_host) ta_host[i] = h.ta[i];
+    if (Ni_host) Ni_host[i] = h.Ni[i];
+    if (omega_host) omega_host[i] = h.omega[i];
   }
-  if (q_out) *q_out = tmp.q;
+  if (q_out) *q_out = h.desc.q;
+  return SFCDD_OK;
+}
+
+sfcdd_status sfcdd_autotune(sfcdd_ctx* c, int32_t repeats, double* best_ms) {
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  if (repeats < 1) repeats = 3;
+  const hipStream_t s = c->stream;
+  hipEvent_t a, b;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  double* w = c->vec[V_TMP];
+  launch_zero(c->Ntot, w, s);
+  int best = c->trsv_waves;
+  double best_t = 1e300;
+  const int cand[3] = {4, 8, 16};
+  const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
+  for (int k = 0; k < ncand; ++k) {
+    local_solves(c, w, cand[k]);  // warm-up
+    HIPCHK(c, hipEventRecord(a, s));
+    for (int rpt = 0; rpt < repeats; ++rpt) local_solves(c, w, cand[k]);
+    HIPCHK(c, hipEventRecord(b, s));
+    HIPCHK(c, hipEventSynchronize(b));
+    float ms;
+    HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+    const double t = ms / repeats;
+    if (t < best_t) {
+      best_t = t;
+      best = cand[k];
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (ncand > 1) c->trsv_waves = best;
+  c->info.trsv_waves = c->trsv_waves;
+  if (best_ms) *best_ms = best_t;
   return SFCDD_OK;
 }
 
@@ -989,6 +1255,7 @@ sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
 
 sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (!c) return SFCDD_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->side) (void)hipStreamDestroy(c->side);

@@ -244,3 +244,61 @@ def test_full_size_apply_c2_matches_oracle():
     S = _solver(w.levels[0], w.P, w.gamma)
     r = uniform_pm1(31, g.N)
     assert relerr(host(S.apply(dvec(r))), O.apply(r)) <= FP64_TOL
+
+
+def test_batch_heterogeneous_grids_match_single_grid_oracle():
+    """A batch of grids of different dimension, size, coefficients, P, gamma
+    and q: every grid's block of the batched operator equals the oracle of
+    that grid alone, and the batched solve equals each grid's exact solution."""
+    grids = [dict(levels=(4, 3), P=5, gamma=Fraction(1, 2)),
+             dict(levels=(3, 2, 3), P=7, gamma=Fraction(1, 4), coeff=(0.5, 2.0, 1.5)),
+             dict(levels=(5,), P=3, gamma=Fraction(1, 1), q=4),
+             dict(levels=(2, 2, 2, 3), P=4, gamma=Fraction(3, 4))]
+    announce("batch heterogeneous")
+    for fdtype, method in (("fp64", "pcg"), ("fp32", "fcg")):
+        S = m.SFCSchwarzBatch(grids, factor_dtype=fdtype)
+        rhs, refs_apply, refs_x = [], [], []
+        for k, gk in enumerate(grids):
+            g = Grid(levels=gk["levels"], coeff=gk.get("coeff"))
+            O = OracleSchwarz(g, gk["P"], gk["gamma"], q=gk.get("q"))
+            part = S.partition(k)
+            assert np.array_equal(part["sfc_index"], O.sfc_index)
+            assert np.array_equal(part["ta"], O.ta) and np.array_equal(part["Ni"], O.Ni)
+            r = uniform_pm1(40 + k, g.N)
+            rhs.append(r)
+            refs_apply.append(O.apply(r))
+            refs_x.append(exact.solve(g, r))
+        rb = dvec(np.concatenate(rhs))
+        h = S.split(host(S.apply(rb)))
+        for k in range(len(grids)):
+            assert relerr(h[k], refs_apply[k]) <= (FP64_TOL if fdtype == "fp64" else FP32_TOL)
+        x, info = S.solve(rb, rtol=1e-12, method=method)
+        xs = S.split(host(x))
+        for k in range(len(grids)):
+            assert relerr(xs[k], refs_x[k]) <= 1e-9
+        its, res = S.batch_stats()
+        assert max(res) <= 1e-12 and info["iterations"] == max(its)
+
+
+@pytest.mark.parametrize("fdtype,method", [("fp32", "fcg"), ("fp64", "pcg")])
+def test_batch_ct_layer_84_grids(fdtype, method):
+    """The d=4 combination-technique layer |l|_1 = 14, l_j >= 2 (84 grids of
+    6,885 .. 11,025 points, P = 16 each, gamma = 1/4) solved as one batch:
+    each grid's solution matches its exact DST-I solution and its iteration
+    count equals that of the same grid solved alone."""
+    w = workloads()["c4"]
+    announce("batch ct", fdtype)
+    grids = [dict(levels=lv, P=w.P, gamma=w.gamma) for lv in w.levels]
+    S = m.SFCSchwarzBatch(grids, factor_dtype=fdtype)
+    S.autotune(3)
+    f = np.concatenate([w.rhs(g) for g in range(len(w.levels))])
+    x, info = S.solve(dvec(f), rtol=1e-12, method=method, max_iter=400)
+    xs = S.split(host(x))
+    its, _ = S.batch_stats()
+    for g in range(len(w.levels)):
+        ref = exact.solve(Grid(levels=w.levels[g]), w.rhs(g))
+        assert relerr(xs[g], ref) <= 1e-9, g
+    for g in (0, 41, 83):
+        Sg = _solver(w.levels[g], w.P, w.gamma, factor_dtype=fdtype)
+        _, ig = Sg.solve(dvec(w.rhs(g)), rtol=1e-12, method=method, max_iter=400)
+        assert abs(ig["iterations"] - its[g]) <= (0 if fdtype == "fp64" else 2), g
