@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the headline path only (for rocprofv3)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="with --profile-only: also copy a buffer of this many MiB three times "
+                         "(the reference kernel that scales the HBM byte counters)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 84-grid layer")
     return ap.parse_args()
 
 
@@ -93,6 +97,106 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_kernel=True)
     return {"ms": sorted(times)[len(times) // 2], "ms_min": min(times), "setup_ms": sorted(setups)[len(setups) // 2],
             "solve_ms": sorted(solves)[len(solves) // 2], "iterations": iters[-1], "info": sinfo,
             "kernels": ktimes, "x": x, "rel_residual": info["rel_residual"], "restarts": info["restarts"]}
+
+
+def source_digest():
+    """Digest of the sources of the substitution kernel: a stored HBM byte
+    count is only valid for the code it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("apply.hip", "common.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2110_11211_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_file):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_batch(w, fdtype, steps, warmup, sequential=False):
+    """The 84-grid combination-technique layer: setup (+ substitution-kernel
+    autotuning) + solve of every grid, either as one batched context or grid
+    after grid.  Returns (median ms, max iterations, solutions, waves)."""
+    import numpy as np
+    import torch
+    import paper_2110_11211_amd as m
+    grids = [dict(levels=list(lv), P=w.P, gamma=w.gamma) for lv in w.levels]
+    f = np.concatenate([w.rhs(g) for g in range(len(w.levels))])
+    f_dev = torch.tensor(f, dtype=torch.float64, device="cuda:0")
+    offs = np.concatenate([[0], np.cumsum([w.N(g) for g in range(len(w.levels))])])
+    method = "fcg" if fdtype == "fp32" else "pcg"
+    ws = None
+    times, iters, x, waves = [], 0, None, None
+    for k in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        if not sequential:
+            S = m.SFCSchwarzBatch(grids, factor_dtype=fdtype, workspace=ws)
+            ws = S.ws
+            S.autotune(2)
+            x, _ = S.solve(f_dev, rtol=w.rtol, method=method, max_iter=500)
+            its, _ = S.batch_stats()
+            waves = S.info()["trsv_waves"]
+            S.close()
+            iters = max(its)
+        else:
+            x = torch.empty_like(f_dev)
+            iters = 0
+            for g, gk in enumerate(grids):
+                Sg = m.SFCSchwarz(levels=gk["levels"], P=gk["P"], gamma=gk["gamma"], factor_dtype=fdtype)
+                xg, ig = Sg.solve(f_dev[offs[g]:offs[g + 1]], rtol=w.rtol, method=method, max_iter=500)
+                x[offs[g]:offs[g + 1]].copy_(xg)
+                iters = max(iters, ig["iterations"])
+                Sg.close()
+        t1.record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            times.append(t0.elapsed_time(t1))
+    return sorted(times)[len(times) // 2], iters, x.cpu().numpy(), waves, offs
+
+
+def ct_batch_report(steps, warmup):
+    import numpy as np
+    from seeded_inputs import workloads
+    from oracle.grid import Grid
+    from oracle import exact
+    w = workloads()["c4"]
+    b32, it32, x32, waves, offs = run_batch(w, "fp32", steps, warmup)
+    b64, it64, x64, _, _ = run_batch(w, "fp64", max(1, steps // 2), warmup)
+    s32, _, _, _, _ = run_batch(w, "fp32", 1, 1, sequential=True)
+    err32 = err64 = 0.0
+    for g in range(len(w.levels)):
+        ref = exact.solve(Grid(levels=w.levels[g]), w.rhs(g))
+        nr = np.linalg.norm(ref)
+        err32 = max(err32, float(np.linalg.norm(x32[offs[g]:offs[g + 1]] - ref) / nr))
+        err64 = max(err64, float(np.linalg.norm(x64[offs[g]:offs[g + 1]] - ref) / nr))
+    return {"workload": w.name, "grids": len(w.levels), "N_total": int(offs[-1]),
+            "batched_fp32_ms": round(b32, 3), "batched_fp64_ms": round(b64, 3),
+            "sequential_fp32_ms": round(s32, 3),
+            "speedup_batched_vs_sequential": round(s32 / b32, 3),
+            "speedup_fp32_vs_fp64": round(b64 / b32, 3),
+            "max_iterations_fp32": it32, "max_iterations_fp64": it64, "trsv_waves": waves,
+            "max_rel_error_vs_exact_fp32": err32, "max_rel_error_vs_exact_fp64": err64,
+            "note": "setup + autotune + solve of all 84 grids to 1e-9 per step"}
 
 
 def cpu_baseline(w, iterations, nsample):
@@ -158,7 +262,20 @@ def main():
     ws_cache = {}
     head = run_path(w, f_dev, "fp32", args.local, args.steps, args.warmup, ws_cache)
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms": head["ms"]}), flush=True)
+        ms_l, n_l = head["kernels"]["local_solve"]
+        out = {"profile_only": True, "ms": head["ms"], "local_solve_launches": n_l,
+               "local_solve_avg_ms": ms_l / max(n_l, 1)}
+        if args.copy_probe > 0:
+            ws_cache.clear()
+            n = args.copy_probe * (1 << 20) // 4
+            a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            out["copy_probe_bytes_read"] = 4 * n
+            out["copy_probe_bytes_written"] = 4 * n
+        print(json.dumps(out), flush=True)
         return
     f64 = None
     if not args.skip_fp64:
@@ -192,9 +309,11 @@ def main():
     solve_local_ms = ms_local / args.steps
     factor_ms = info["setup_ms"][3]
     nt = [(n + 63) // 64 for n in [info["max_Ni"]]]
+    traffic = stored_traffic("k_schwarz_trsv_fp32_d3_l7x6x5_P256_traffic.txt") \
+        if args.local == "cholesky" else None
     roofline = {"kernel": "k_schwarz_trsv (FP32 factors)" if args.local == "cholesky" else "k_symv_tiles (FP32 inverse)",
                 "bound": "hbm", "achieved": round(gbs_local, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs_local / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(gbs_local / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "avg_launch_ms": avg_local, "algorithmic_bytes_per_launch": local_bytes,
                 "local_solve_ms_per_step": solve_local_ms, "factor_ms_per_step": factor_ms}
     out = {
@@ -225,6 +344,15 @@ def main():
                        "local_solve_gbps": round(b64 / (ms64 / max(n64, 1) * 1e-3) / 1e9, 1),
                        "setup_phases_ms": i64["setup_ms"]}
         out["speedup_fp32_vs_fp64"] = round(f64["ms"] / head["ms"], 3)
+    # MFMA rate of the batched subdomain factorisation (sum N_i^3 / 3 flops)
+    _, Ni, _, _ = m.partition_host(levels=list(w.levels[0]), P=w.P, gamma=w.gamma)
+    fflops = float(np.sum(Ni.astype(np.float64) ** 3) / 3.0)
+    out["factor"] = {"flops": fflops, "ms": round(factor_ms, 3),
+                     "tflops": round(fflops / (factor_ms * 1e-3) / 1e12, 2), "peak_tflops": FP32_MFMA_PEAK_TFLOPS,
+                     "frac": round(fflops / (factor_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
+                     "note": "FP32 MFMA; runs concurrently with the coarse setup"}
+    if not args.no_batch:
+        out["ct_batch"] = ct_batch_report(max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         iters = f64["iterations"] if f64 is not None else head["iterations"]
         out["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_sample)
