@@ -139,16 +139,21 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   }
   __syncthreads();
 
+  // Rows at or past n are padding (unit diagonal, zero right-hand side, zero
+  // solution): their tile rows and columns are never read.  Chunks of the
+  // diagonal-tile inverses right of the diagonal are zero and not read either.
   // forward: y_I <- L_II^{-1} (g_I - sum_{J<I} L_IJ y_J)
   for (int I = 0; I < ntb; ++I) {
     const T* rowI = F + tri_index(I, 0) * TS2;
     for (int grp = wv; grp < NGRP; grp += W) {
       const int r = grp * RPI + lrow;
       T acc = T(0);
+      if (I * TS + r < n) {
 #pragma unroll 4
-      for (int J = 0; J < I; ++J) {
-        const V v = *reinterpret_cast<const V*>(rowI + (int64_t)J * TS2 + r * TS + c0);
-        acc += dotv<T>(v, y + J * TS + c0);
+        for (int J = 0; J < I; ++J) {
+          const V v = *reinterpret_cast<const V*>(rowI + (int64_t)J * TS2 + r * TS + c0);
+          acc += dotv<T>(v, y + J * TS + c0);
+        }
       }
       for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if ((lane % LPR) == 0) sS[r] = y[I * TS + r] - acc;
@@ -157,8 +162,11 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     const T* D = rowI + (int64_t)I * TS2;
     for (int grp = wv; grp < NGRP; grp += W) {
       const int r = grp * RPI + lrow;
-      const V v = *reinterpret_cast<const V*>(D + r * TS + c0);
-      T acc = dotv<T>(v, sS + c0);
+      T acc = T(0);
+      if (c0 <= r && I * TS + r < n) {
+        const V v = *reinterpret_cast<const V*>(D + r * TS + c0);
+        acc = dotv<T>(v, sS + c0);
+      }
       for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if ((lane % LPR) == 0) y[I * TS + r] = acc;
     }
@@ -171,10 +179,15 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     for (int e = 0; e < VEC; ++e) accv[e] = T(0);
     for (int grp = wv; grp < NGRP; grp += W) {
       const int r = grp * RPI + lrow;
+      const int Kend = ntb - 1;  // the last tile row may hold padding rows
 #pragma unroll 4
-      for (int K = I + 1; K < ntb; ++K) {
+      for (int K = I + 1; K < Kend; ++K) {
         const V v = *reinterpret_cast<const V*>(F + tri_index(K, I) * TS2 + r * TS + c0);
         axpyv<T>(accv, v, y[K * TS + r]);
+      }
+      if (I < Kend && Kend * TS + r < n) {
+        const V v = *reinterpret_cast<const V*>(F + tri_index(Kend, I) * TS2 + r * TS + c0);
+        axpyv<T>(accv, v, y[Kend * TS + r]);
       }
     }
     for (int e = 0; e < VEC; ++e)
@@ -192,8 +205,10 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     const T* D = F + tri_index(I, I) * TS2;
     for (int grp = wv; grp < NGRP; grp += W) {
       const int r = grp * RPI + lrow;
-      const V v = *reinterpret_cast<const V*>(D + r * TS + c0);
-      axpyv<T>(accv, v, sS[r]);
+      if (c0 <= r && I * TS + r < n) {
+        const V v = *reinterpret_cast<const V*>(D + r * TS + c0);
+        axpyv<T>(accv, v, sS[r]);
+      }
     }
     for (int e = 0; e < VEC; ++e)
       for (int o = LPR; o < 64; o <<= 1) accv[e] += __shfl_xor(accv[e], o, 64);

@@ -92,6 +92,9 @@ struct sfcdd_ctx {
   int32_t *active = nullptr, *status = nullptr;
   double* host_scal = nullptr;  // pinned, G * S_COUNT + G + 256 doubles
   std::vector<int32_t> last_iters;
+  // host copy of the device activity flags (valid after the first upload)
+  std::vector<int32_t> active_shadow;
+  bool active_valid = false, active_in_flight = false;
   std::vector<double> last_relres;
   std::string err;
   sfcdd_info info{};
@@ -634,15 +637,23 @@ sfcdd_status read_scal(sfcdd_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * c->G * S_COUNT,
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->active_in_flight = false;
   return SFCDD_OK;
 }
 double hs(sfcdd_ctx* c, int g, int slot) { return c->host_scal[(size_t)g * S_COUNT + slot]; }
 
+// Uploads the per-grid activity flags when they changed since the last
+// upload.  The copy is asynchronous; its pinned source is rewritten only after
+// a stream synchronisation has retired it.
 sfcdd_status write_active(sfcdd_ctx* c, const std::vector<int32_t>& act) {
+  if (c->active_valid && act == c->active_shadow) return SFCDD_OK;
+  if (c->active_in_flight) HIPCHK(c, hipStreamSynchronize(c->stream));
   int32_t* hb = reinterpret_cast<int32_t*>(c->host_scal + (size_t)c->G * S_COUNT);
   for (int g = 0; g < c->G; ++g) hb[g] = act[g];
   HIPCHK(c, hipMemcpyAsync(c->active, hb, 4 * c->G, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->active_in_flight = true;
+  c->active_shadow = act;
+  c->active_valid = true;
   return SFCDD_OK;
 }
 
