@@ -76,9 +76,6 @@ void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, 
 // subdomain; R_i w (a cyclic contiguous curve range) is staged in LDS.
 // Diagonal tiles hold L_II^{-1}, so every step is a tile matrix-vector product.
 // Each wave streams whole 16-byte-per-lane row groups of the tiles.
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
-template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
 
 template <typename T>
 __device__ __forceinline__ T dotv(const typename Vec16<T>::type& a, const T* b);

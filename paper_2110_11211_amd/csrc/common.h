@@ -43,6 +43,11 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// 16-byte vector of T (one load per lane).
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
 // Index of lower tile (I, J), J <= I, in row-major packed tile order.
 __device__ __host__ __forceinline__ int64_t tri_index(int I, int J) {
   return (int64_t)I * (I + 1) / 2 + J;

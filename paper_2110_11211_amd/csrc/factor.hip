@@ -165,11 +165,11 @@ constexpr size_t diag_lds_bytes() {
   return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + TS) * sizeof(T);
 }
 
-// left != 0: left-looking, the tile first receives -sum_{K<J} L_JK L_JK^T
-// in this workgroup.  nparts > 0 (single matrix, split-K): that update was
-// precomputed as nparts partial tiles part[I][c] by k_potrf_partial.
+// Left-looking: the tile first receives -sum_{K<J} L_JK L_JK^T.  The terms
+// K = kfrom .. J-1 are formed in this workgroup; the terms K < kfrom (single
+// matrix, split-K) were precomputed as nparts partial tiles part[I][c].
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left, int nparts, int maxc,
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, int nparts, int maxc,
                                                              const T* __restrict__ part,
                                                              const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
@@ -183,14 +183,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left, in
   TileAcc<T> acc;
   acc.load(F + tri_index(J, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
-  const int nk = left ? J : 0;
   TileRegs<T> ra;
-  if (nk > 0) ra.load(F + tri_index(J, 0) * TS2);
-  for (int K = 0; K < nk; ++K) {
+  if (kfrom < J) ra.load(F + tri_index(J, kfrom) * TS2);
+  for (int K = kfrom; K < J; ++K) {
     __syncthreads();
     ra.store_lds(sA);
     __syncthreads();
-    if (K + 1 < nk) ra.load(F + tri_index(J, K + 1) * TS2);
+    if (K + 1 < J) ra.load(F + tri_index(J, K + 1) * TS2);
     tile_mma<T, false, true>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
   }
   __syncthreads();
@@ -210,34 +209,25 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int left, in
   }
 }
 
+// Sub-diagonal tile (I, J): A_IJ - sum_{K<J} L_IK L_JK^T (terms K >= kfrom
+// here, the others from nparts partial tiles), times L_JJ^{-T}.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left, int nparts, int maxc,
-                                                              const T* __restrict__ part,
-                                                              const int32_t* __restrict__ nt,
-                                                              const int64_t* __restrict__ off,
-                                                              T* __restrict__ fac) {
-  const int b = blockIdx.y;
-  const int I = J + 1 + blockIdx.x;
-  if (I >= nt[b]) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
-  T* F = fac + off[b] * TS2;
+__device__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const T* __restrict__ part,
+                           T* __restrict__ F, T* sA, T* sB) {
   TileAcc<T> acc;
   acc.load(F + tri_index(I, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);
-  const int nk = left ? J : 0;
   TileRegs<T> ra, rb;
-  if (nk > 0) {
-    ra.load(F + tri_index(I, 0) * TS2);
-    rb.load(F + tri_index(J, 0) * TS2);
+  if (kfrom < J) {
+    ra.load(F + tri_index(I, kfrom) * TS2);
+    rb.load(F + tri_index(J, kfrom) * TS2);
   }
-  for (int K = 0; K < nk; ++K) {
+  for (int K = kfrom; K < J; ++K) {
     __syncthreads();
     ra.store_lds(sA);
     rb.store_lds(sB);
     __syncthreads();
-    if (K + 1 < nk) {
+    if (K + 1 < J) {
       ra.load(F + tri_index(I, K + 1) * TS2);
       rb.load(F + tri_index(J, K + 1) * TS2);
     }
@@ -253,6 +243,75 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int left, i
   out.store(F + tri_index(I, J) * TS2);
 }
 
+// Partial update of column Jn: part[I][c] = sum_{K = k0}^{k1 - 1} L_IK L_JnK^T.
+template <typename T>
+__device__ void partial_tile(int Jn, int I, int c, int k0, int k1, int maxc, const T* __restrict__ F,
+                             T* __restrict__ part, T* sA, T* sB) {
+  TileAcc<T> acc;
+  acc.zero();
+  TileRegs<T> ra, rb;
+  ra.load(F + tri_index(I, k0) * TS2);
+  rb.load(F + tri_index(Jn, k0) * TS2);
+  for (int K = k0; K < k1; ++K) {
+    __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 < k1) {
+      ra.load(F + tri_index(I, K + 1) * TS2);
+      rb.load(F + tri_index(Jn, K + 1) * TS2);
+    }
+    tile_mma<T, false, true>(acc, sA, sB, T(1));
+  }
+  acc.store(part + ((int64_t)I * maxc + c) * TS2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int kfrom, int nparts, int maxc,
+                                                              const T* __restrict__ part,
+                                                              const int32_t* __restrict__ nt,
+                                                              const int64_t* __restrict__ off,
+                                                              T* __restrict__ fac) {
+  const int b = blockIdx.y;
+  const int I = J + 1 + blockIdx.x;
+  if (I >= nt[b]) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  panel_tile<T>(J, I, kfrom, nparts, maxc, part, fac + off[b] * TS2, sA, sB);
+}
+
+// One matrix (batch of one), look-ahead step after the diagonal tile of
+// column J: the first workgroups form the split-K partial update of column
+// J + 1 from columns K < J (part_out[I][c], I > J, chunks of SPLITK columns),
+// the others finish the sub-diagonal tiles of column J (using the partials of
+// columns K < J - 1 in part_in and forming the K = J - 1 term themselves).
+// Column J + 1 then needs only its own K = J term.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, int nparts_in,
+                                                             const T* __restrict__ part_in,
+                                                             T* __restrict__ part_out, int nc_out,
+                                                             const int32_t* __restrict__ nt,
+                                                             const int64_t* __restrict__ off,
+                                                             T* __restrict__ fac) {
+  const int ntb = nt[0];
+  const int m = ntb - 1 - J;  // tiles below the diagonal in column J
+  if (m <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LDS_S;
+  T* F = fac + off[0] * TS2;
+  const int x = blockIdx.x;
+  if (x < m * nc_out) {
+    const int I = J + 1 + x % m, c = x / m;
+    const int k0 = c * SPLITK, k1 = min(J, k0 + SPLITK);
+    partial_tile<T>(J + 1, I, c, k0, k1, maxc, F, part_out, sA, sB);
+  } else if (x < m * nc_out + m) {
+    const int I = J + 1 + (x - m * nc_out);
+    panel_tile<T>(J, I, J > 0 ? J - 1 : 0, nparts_in, maxc, part_in, F, sA, sB);
+  }
+}
+
 // The FP64 tile kernels stage two 64x65 double tiles (66.5 KB of LDS), above
 // the default 64 KB dynamic limit: raise it once per kernel.
 template <typename K>
@@ -262,74 +321,36 @@ static void allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename T>
-void launch_potrf_diag(int J, int left, int nparts, int maxc, const T* part, int nb,
+void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s) {
   const size_t sh = diag_lds_bytes<T>();
   static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, left, nparts, maxc,
+  hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, kfrom, nparts, maxc,
                      part, nt, off, fac, status);
 }
 template <typename T>
-void launch_potrf_panel(int J, int left, int nparts, int maxc, const T* part, int nb, int max_nt,
+void launch_potrf_panel(int J, int kfrom, int nparts, int maxc, const T* part, int nb, int max_nt,
                         const int32_t* nt, const int64_t* off, T* fac, hipStream_t s) {
   if (max_nt - 1 - J <= 0) return;
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
   static bool once = (allow_lds(k_potrf_panel<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, left,
+  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, kfrom,
                      nparts, maxc, part, nt, off, fac);
 }
-
-// Split-K update of column J of one matrix (batch 1): workgroup (x, c)
-// computes part[I][c] = sum_{K in chunk c} L_IK L_JK^T for I = J + x, chunk
-// c = [c SPLITK, (c + 1) SPLITK) intersected with [0, J).  Many workgroups per
-// column instead of one long K loop per tile.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_partial(int J, int maxc,
-                                                                const int32_t* __restrict__ nt,
-                                                                const int64_t* __restrict__ off,
-                                                                const T* __restrict__ fac,
-                                                                T* __restrict__ part) {
-  const int I = J + blockIdx.x;
-  const int c = blockIdx.y;
-  if (I >= nt[0]) return;
-  const int k0 = c * SPLITK, k1 = min(J, k0 + SPLITK);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
-  const T* F = fac + off[0] * TS2;
-  TileAcc<T> acc;
-  acc.zero();
-  TileRegs<T> ra, rb;
-  ra.load(F + tri_index(I, k0) * TS2);
-  rb.load(F + tri_index(J, k0) * TS2);
-  for (int K = k0; K < k1; ++K) {
-    __syncthreads();
-    ra.store_lds(sA);
-    rb.store_lds(sB);
-    __syncthreads();
-    if (K + 1 < k1) {
-      ra.load(F + tri_index(I, K + 1) * TS2);
-      rb.load(F + tri_index(J, K + 1) * TS2);
-    }
-    tile_mma<T, false, true>(acc, sA, sB, T(1));
-  }
-  acc.store(part + ((int64_t)I * maxc + c) * TS2);
-}
-
-template <typename T>
-void launch_potrf_partial(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
-                          const T* fac, T* part, hipStream_t s) {
-  const int nc = (J + SPLITK - 1) / SPLITK;
-  if (nc == 0) return;
+void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part_in, T* part_out,
+                       const int32_t* nt, const int64_t* off, T* fac, hipStream_t s) {
+  const int m = max_nt - 1 - J;
+  if (m <= 0) return;
+  const int nc_out = (J + SPLITK - 1) / SPLITK;
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
-  static bool once = (allow_lds(k_potrf_partial<T>, sh), true);
+  static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_partial<T>, dim3(max_nt - J, nc), dim3(TILE_THREADS), sh, s, J, maxc,
-                     nt, off, fac, part);
-  (void)maxc;
+  hipLaunchKernelGGL(k_potrf_step<T>, dim3(m * nc_out + m), dim3(TILE_THREADS), sh, s, J, maxc,
+                     nparts_in, part_in, part_out, nc_out, nt, off, fac);
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -391,90 +412,117 @@ void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_
                      X);
 }
 
-// Split-K form of the column step above for one matrix (batch 1):
-// k_trtri_partial computes part[I][c] = sum_{K in chunk c} X_IK L_KJ over the
-// chunks c of [J+1, I]; k_trtri_finish sums them and applies -L_JJ^{-1}.
+// Recursive (level-by-level) triangular inversion X = L^{-1} for a batch of
+// matrices.  With the tile columns split into blocks of s tiles and the
+// blocks paired as (A, B) = ([2ps, 2ps+s), [2ps+s, 2ps+2s)), the block of X
+// below a pair's diagonal is X_BA = -X_BB L_BA X_AA, where X_AA and X_BB were
+// completed at the previous level (s/2).  Starting from the inverted diagonal
+// tiles (s = 1) and doubling s, every level is two independent batched tile
+// products: T = L_BA X_AA, then X_BA = -X_BB T.  log2(nt) levels instead of
+// nt dependent column steps.  T of matrix b occupies tiles toff[b] ..
+// toff[b] + ceil(nt^2 / 4): tile (ii, jj) of pair p is p s^2 + ii s + jj.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_trtri_partial(int J, int maxc,
-                                                                const int32_t* __restrict__ nt,
-                                                                const int64_t* __restrict__ off,
-                                                                const T* __restrict__ L,
-                                                                const T* __restrict__ X,
-                                                                T* __restrict__ part) {
-  const int I = J + 1 + blockIdx.x;
-  const int c = blockIdx.y;
-  const int k0 = J + 1 + c * SPLITK;
-  if (I >= nt[0] || k0 > I) return;
-  const int k1 = min(I + 1, k0 + SPLITK);
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_diag_copy(const int32_t* __restrict__ nt,
+                                                                  const int64_t* __restrict__ off,
+                                                                  const T* __restrict__ L,
+                                                                  T* __restrict__ X) {
+  const int b = blockIdx.y, k = blockIdx.x;
+  if (k >= nt[b]) return;
+  typedef typename Vec16<T>::type V;
+  constexpr int VEC = Vec16<T>::n;
+  const V* src = reinterpret_cast<const V*>(L + (off[b] + tri_index(k, k)) * TS2);
+  V* dst = reinterpret_cast<V*>(X + (off[b] + tri_index(k, k)) * TS2);
+  for (int e = threadIdx.x; e < TS2 / VEC; e += TILE_THREADS) dst[e] = src[e];
+}
+
+// T_ij = sum_{k = j}^{B0 - 1} L_ik X_kj for i in B, j in A.  Workgroups with
+// the longest sums (small jj) are dispatched first.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32_t* __restrict__ nt,
+                                                              const int64_t* __restrict__ off,
+                                                              const int64_t* __restrict__ toff,
+                                                              const T* __restrict__ L,
+                                                              const T* __restrict__ X,
+                                                              T* __restrict__ Tb) {
+  const int b = blockIdx.z, p = blockIdx.y;
+  const int jj = blockIdx.x / s, ii = blockIdx.x % s;
+  const int A0 = 2 * p * s, B0 = A0 + s;
+  const int i = B0 + ii, j = A0 + jj;
+  if (i >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
-  const T* Lb = L + off[0] * TS2;
-  const T* Xb = X + off[0] * TS2;
+  const T* Lb = L + off[b] * TS2;
+  const T* Xb = X + off[b] * TS2;
   TileAcc<T> acc;
   acc.zero();
   TileRegs<T> ra, rb;
-  ra.load(Xb + tri_index(I, k0) * TS2);
-  rb.load(Lb + tri_index(k0, J) * TS2);
-  for (int K = k0; K < k1; ++K) {
+  ra.load(Lb + tri_index(i, j) * TS2);
+  rb.load(Xb + tri_index(j, j) * TS2);
+  for (int k = j; k < B0; ++k) {
     __syncthreads();
     ra.store_lds(sA);
     rb.store_lds(sB);
     __syncthreads();
-    if (K + 1 < k1) {
-      ra.load(Xb + tri_index(I, K + 1) * TS2);
-      rb.load(Lb + tri_index(K + 1, J) * TS2);
+    if (k + 1 < B0) {
+      ra.load(Lb + tri_index(i, k + 1) * TS2);
+      rb.load(Xb + tri_index(k + 1, j) * TS2);
     }
     tile_mma<T, false, false>(acc, sA, sB, T(1));
   }
-  acc.store(part + ((int64_t)I * maxc + c) * TS2);
+  acc.store(Tb + (toff[b] + (int64_t)p * s * s + (int64_t)ii * s + jj) * TS2);
 }
 
+// X_ij = -sum_{k = B0}^{i} X_ik T_kj for i in B, j in A (longest sums, large
+// ii, first).
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_trtri_finish(int J, int maxc,
-                                                               const int32_t* __restrict__ nt,
-                                                               const int64_t* __restrict__ off,
-                                                               const T* __restrict__ L,
-                                                               T* __restrict__ X,
-                                                               const T* __restrict__ part) {
-  const int I = J + blockIdx.x;
-  if (I >= nt[0]) return;
+__global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32_t* __restrict__ nt,
+                                                              const int64_t* __restrict__ off,
+                                                              const int64_t* __restrict__ toff,
+                                                              const T* __restrict__ Tb,
+                                                              T* __restrict__ X) {
+  const int b = blockIdx.z, p = blockIdx.y;
+  const int ii = s - 1 - (int)(blockIdx.x / s), jj = blockIdx.x % s;
+  const int A0 = 2 * p * s, B0 = A0 + s;
+  const int i = B0 + ii, j = A0 + jj;
+  if (i >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LDS_S;
-  const T* Lb = L + off[0] * TS2;
-  T* Xb = X + off[0] * TS2;
-  if (I == J) {
-    const T* src = Lb + tri_index(J, J) * TS2;
-    T* dst = Xb + tri_index(J, J) * TS2;
-    for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) dst[e] = src[e];
-    return;
-  }
+  T* Xb = X + off[b] * TS2;
+  const T* Tp = Tb + (toff[b] + (int64_t)p * s * s + jj) * TS2;  // T_kj at Tp + (k - B0) s TS2
   TileAcc<T> acc;
   acc.zero();
-  const int np = (I - J + SPLITK - 1) / SPLITK;
-  for (int c = 0; c < np; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);  // acc = -sum
-  acc.store_lds(sA);
-  stage_tile(sB, Lb + tri_index(J, J) * TS2);
-  __syncthreads();
-  TileAcc<T> out;
-  out.zero();
-  tile_mma<T, false, false>(out, sA, sB, T(1));
-  out.store(Xb + tri_index(I, J) * TS2);
+  TileRegs<T> ra, rb;
+  ra.load(Xb + tri_index(i, B0) * TS2);
+  rb.load(Tp);
+  for (int k = B0; k <= i; ++k) {
+    __syncthreads();
+    ra.store_lds(sA);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (k + 1 <= i) {
+      ra.load(Xb + tri_index(i, k + 1) * TS2);
+      rb.load(Tp + (int64_t)(k + 1 - B0) * s * TS2);
+    }
+    tile_mma<T, false, false>(acc, sA, sB, T(-1));
+  }
+  acc.store(Xb + tri_index(i, j) * TS2);
 }
 
 template <typename T>
-void launch_trtri_splitk(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
-                         const T* L, T* X, T* part, hipStream_t s) {
+void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
+                      const T* L, T* X, T* Tb, hipStream_t st) {
   const size_t sh = 2 * TS * LDS_S * sizeof(T);
-  static bool once = (allow_lds(k_trtri_partial<T>, sh), allow_lds(k_trtri_finish<T>, sh), true);
+  static bool once = (allow_lds(k_trtri_rec_t<T>, sh), allow_lds(k_trtri_rec_x<T>, sh), true);
   (void)once;
-  const int m = max_nt - 1 - J;
-  if (m > 0)
-    hipLaunchKernelGGL(k_trtri_partial<T>, dim3(m, (m + SPLITK - 1) / SPLITK), dim3(TILE_THREADS), sh,
-                       s, J, maxc, nt, off, L, X, part);
-  hipLaunchKernelGGL(k_trtri_finish<T>, dim3(max_nt - J), dim3(TILE_THREADS), sh, s, J, maxc, nt, off,
-                     L, X, part);
+  hipLaunchKernelGGL(k_trtri_diag_copy<T>, dim3(max_nt, nb), dim3(TILE_THREADS), 0, st, nt, off, L, X);
+  for (int s = 1; s < max_nt; s *= 2) {
+    const int npairs = (max_nt + 2 * s - 1) / (2 * s);
+    const dim3 grid(s * s, npairs, nb);
+    hipLaunchKernelGGL(k_trtri_rec_t<T>, grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, L, X, Tb);
+    hipLaunchKernelGGL(k_trtri_rec_x<T>, grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X);
+  }
 }
 
 // M = X^T X = A^{-1} from X = L^{-1}:  M_IJ = sum_{K >= I} X_KI^T X_KJ, I >= J.
@@ -530,13 +578,13 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
   template void launch_potrf_panel<T>(int, int, int, int, const T*, int, int, const int32_t*,      \
                                       const int64_t*, T*, hipStream_t);                            \
-  template void launch_potrf_partial<T>(int, int, int, const int32_t*, const int64_t*, const T*,  \
-                                        T*, hipStream_t);                                          \
-  template void launch_trtri_splitk<T>(int, int, int, const int32_t*, const int64_t*, const T*,   \
-                                       T*, T*, hipStream_t);                                       \
+  template void launch_potrf_step<T>(int, int, int, int, const T*, T*, const int32_t*,             \
+                                     const int64_t*, T*, hipStream_t);                             \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
-  template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t);
+  template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \
+  template void launch_trtri_rec<T>(int, int, const int32_t*, const int64_t*, const int64_t*,     \
+                                    const T*, T*, T*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

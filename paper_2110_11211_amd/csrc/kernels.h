@@ -82,21 +82,21 @@ void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, do
 
 // ---- batched tiled Cholesky, inversion ----------------------------------
 template <typename T>
-void launch_potrf_diag(int J, int left, int nparts, int maxc, const T* part, int nb,
+void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s);
 template <typename T>
-void launch_potrf_panel(int J, int left, int nparts, int maxc, const T* part, int nb, int max_nt,
+void launch_potrf_panel(int J, int kfrom, int nparts, int maxc, const T* part, int nb, int max_nt,
                         const int32_t* nt, const int64_t* off, T* fac, hipStream_t s);
 template <typename T>
-void launch_potrf_partial(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
-                          const T* fac, T* part, hipStream_t s);
-template <typename T>
-void launch_trtri_splitk(int J, int max_nt, int maxc, const int32_t* nt, const int64_t* off,
-                         const T* L, T* X, T* part, hipStream_t s);
+void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part_in, T* part_out,
+                       const int32_t* nt, const int64_t* off, T* fac, hipStream_t s);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);
+template <typename T>
+void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
+                      const T* L, T* X, T* Tb, hipStream_t s);
 template <typename T>
 void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* X, T* M,
                   hipStream_t s);

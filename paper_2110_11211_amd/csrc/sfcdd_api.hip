@@ -64,9 +64,10 @@ struct sfcdd_ctx {
   std::vector<uint16_t> sgid;
   // coarse matrices, one per grid
   std::vector<int32_t> c_nt, c_n;
-  std::vector<int64_t> c_off, c_xoff, c_poff, c_doff;
+  std::vector<int64_t> c_off, c_xoff, c_poff, c_doff, c_toff;
   int max_nt = 0, max_Ni = 0, min_Ni = 0, max_nt0 = 0, max_N0 = 0;
   int64_t sum_Ni = 0, tiles = 0, parts = 0, xlen = 0, ctiles = 0, cparts = 0, c0len = 0;
+  int64_t ctinv = 0;  // tiles of the coarse inversion workspace (all grids)
   int trsv_waves = 16;
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
@@ -86,6 +87,7 @@ struct sfcdd_ctx {
   double* cpartk = nullptr;  // split-K partial tiles of a single coarse factorisation
   int32_t *dc_nt = nullptr, *dc_n = nullptr;
   int64_t *dc_off = nullptr, *dc_xoff = nullptr, *dc_poff = nullptr, *dc_doff = nullptr;
+  int64_t* dc_toff = nullptr;  // first tile of each coarse matrix's inversion workspace
   double* dbuf = nullptr;
   double* vec[NVEC] = {};
   double *partials = nullptr, *scal = nullptr, *gout = nullptr;
@@ -379,8 +381,8 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->ta.clear(); c->Ni.clear(); c->nt.clear(); c->off.clear(); c->doff.clear();
   c->xoff.clear(); c->poff.clear(); c->omega.clear(); c->sgid.clear();
   c->c_nt.clear(); c->c_n.clear(); c->c_off.clear(); c->c_xoff.clear(); c->c_poff.clear();
-  c->c_doff.clear();
-  int64_t toff = 0, dof = 0, xof = 0, pof = 0, ctoff = 0, cpof = 0;
+  c->c_doff.clear(); c->c_toff.clear();
+  int64_t toff = 0, dof = 0, xof = 0, pof = 0, ctoff = 0, cpof = 0, ctt = 0;
   c->max_nt = 0; c->max_Ni = 0; c->min_Ni = INT32_MAX; c->max_nt0 = 0; c->max_N0 = 0;
   for (int k = 0; k < G; ++k) {
     GridHost& h = c->grid[k];
@@ -419,6 +421,8 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     c->c_xoff.push_back(g.c0pad);
     c->c_poff.push_back(cpof);
     c->c_doff.push_back(g.c0off);
+    c->c_toff.push_back(ctt);
+    ctt += ((int64_t)g.nt0 * g.nt0 + 3) / 4;
     ctoff += (int64_t)g.nt0 * (g.nt0 + 1) / 2;
     cpof += (int64_t)g.nt0 * g.nt0 * TS;
     c->max_nt0 = std::max(c->max_nt0, g.nt0);
@@ -435,6 +439,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->parts = pof;
   c->ctiles = ctoff;
   c->cparts = cpof;
+  c->ctinv = ctt;
   c->rbx = G == 1 ? RED_BLOCKS : std::max(8, RED_BLOCKS / G);
 
   // workspace layout
@@ -466,8 +471,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_c0 = pl.take((size_t)c->c0len * 8);
   c->r_d0 = pl.take((size_t)c->N0tot * 8);
   c->r_cpart = pl.take((size_t)c->cparts * 8);
-  c->r_cpartk = pl.take(G == 1 ? (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) * TS2 * 8 : 0);
-  c->r_cmeta = pl.take((size_t)G * (4 * 8 + 2 * 4));
+  // split-K partials of the single-matrix factorisation (two buffers), later
+  // reused by the triangular inversion
+  const size_t kparts = G == 1 ? 2 * (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) : 0;
+  c->r_cpartk = pl.take(std::max(kparts, (size_t)c->ctinv) * TS2 * 8);
+  c->r_cmeta = pl.take((size_t)G * (5 * 8 + 2 * 4));
   c->r_cgid = pl.take(2 * c->N0tot);
   c->r_ctgid = pl.take(2 * c->ctiles);
   c->r_dbuf = pl.take((size_t)c->sum_Ni * 8);
@@ -516,7 +524,8 @@ void bind(sfcdd_ctx* c) {
   c->dc_xoff = c->dc_off + G;
   c->dc_poff = c->dc_xoff + G;
   c->dc_doff = c->dc_poff + G;
-  c->dc_nt = reinterpret_cast<int32_t*>(c->dc_doff + G);
+  c->dc_toff = c->dc_doff + G;
+  c->dc_nt = reinterpret_cast<int32_t*>(c->dc_toff + G);
   c->dc_n = c->dc_nt + G;
   c->cgid = at<uint16_t>(c, c->r_cgid);
   c->ctgid = at<uint16_t>(c, c->r_ctgid);
@@ -536,23 +545,29 @@ void bind(sfcdd_ctx* c) {
 // split-K form instead, so that every column step runs on many workgroups.
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
-                  bool invert, int32_t* status, T* part, hipStream_t s) {
+                  bool invert, int32_t* status, T* part, T* tbuf, const int64_t* toff,
+                  hipStream_t s) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
+  const int64_t half = (int64_t)max_nt * maxc * TS2;
   for (int J = 0; J < max_nt; ++J) {
     if (part) {
-      launch_potrf_partial<T>(J, max_nt, maxc, nt, off, fac, part, s);
-      const int np = (J + SPLITK - 1) / SPLITK;
-      launch_potrf_diag<T>(J, 0, np, maxc, part, 1, nt, off, fac, status, s);
-      launch_potrf_panel<T>(J, 0, np, maxc, part, 1, max_nt, nt, off, fac, s);
+      // one matrix: split-K partials of columns K < J - 1 (double-buffered),
+      // computed by the previous step concurrently with its panel
+      const int np = J > 1 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
+      T* pin = part + (J & 1) * half;
+      T* pout = part + ((J + 1) & 1) * half;
+      launch_potrf_diag<T>(J, J > 0 ? J - 1 : 0, np, maxc, pin, 1, nt, off, fac, status, s);
+      launch_potrf_step<T>(J, max_nt, maxc, np, pin, pout, nt, off, fac, s);
     } else {
-      launch_potrf_diag<T>(J, 1, 0, 0, (const T*)nullptr, nb, nt, off, fac, status, s);
-      launch_potrf_panel<T>(J, 1, 0, 0, (const T*)nullptr, nb, max_nt, nt, off, fac, s);
+      launch_potrf_diag<T>(J, 0, 0, 0, (const T*)nullptr, nb, nt, off, fac, status, s);
+      launch_potrf_panel<T>(J, 0, 0, 0, (const T*)nullptr, nb, max_nt, nt, off, fac, s);
     }
   }
   if (invert) {
-    for (int J = max_nt - 1; J >= 0; --J) {
-      if (part) launch_trtri_splitk<T>(J, max_nt, maxc, nt, off, fac, X, part, s);
-      else launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
+    if (tbuf) {
+      launch_trtri_rec<T>(nb, max_nt, nt, off, toff, fac, X, tbuf, s);
+    } else {
+      for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
     }
     launch_lauum<T>(nb, max_nt, nt, off, X, fac, s);
   }
@@ -734,6 +749,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->dc_xoff, c->c_xoff.data(), 8 * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->dc_poff, c->c_poff.data(), 8 * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->dc_doff, c->c_doff.data(), 8 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->dc_toff, c->c_toff.data(), 8 * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->dc_nt, c->c_nt.data(), 4 * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->dc_n, c->c_n.data(), 4 * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemsetAsync(c->status, 0, 64, s));
@@ -772,7 +788,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
     factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, c->status + 1,
-                         G == 1 ? c->cpartk : (double*)nullptr, cs);
+                         G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, cs);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
     HIPCHK(c, hipEventRecord(join, cs));
@@ -793,10 +809,10 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv,
-                        c->status, (float*)nullptr, s);
+                        c->status, (float*)nullptr, (float*)nullptr, nullptr, s);
   else
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv,
-                         c->status, (double*)nullptr, s);
+                         c->status, (double*)nullptr, (double*)nullptr, nullptr, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
   HIPCHK(c, hipStreamWaitEvent(s, join, 0));
