@@ -57,6 +57,9 @@ enum { SFCDD_ADDITIVE = 0, SFCDD_BALANCED = 1 };
 enum { SFCDD_FP64 = 0, SFCDD_FP32 = 1 };
 enum { SFCDD_LOCAL_CHOLESKY = 0, SFCDD_LOCAL_INVERSE = 1 };
 enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
+/* Flag OR-ed into the method of sfcdd_solve: start from x0 exactly as given
+ * and apply the full balanced operator every iteration (see sfcdd_solve). */
+enum { SFCDD_SOLVE_PLAIN_START = 256 };
 
 typedef struct {
   int32_t d;                 /* dimension, 1 <= d <= 16                                */
@@ -153,7 +156,13 @@ sfcdd_status sfcdd_matvec(sfcdd_ctx* ctx, const double* x_dev, double* y_dev);
  * disagree), or after max_iter iterations (ENOTCONV).
  * method: SFCDD_PCG, SFCDD_FCG (flexible CG, beta = z'(r_new - r_old)/z'r_old,
  * for the FP32-factor preconditioner) or SFCDD_RICHARDSON (x += xi C^{-1} r;
- * xi <= 0 estimates xi = 2/(lmin + lmax) from 30 Lanczos steps).
+ * xi <= 0 estimates xi = 2/(lmin + lmax) from 30 Lanczos steps on the residual
+ * of the start).
+ * Balanced variant (eq. balSW): unless SFCDD_SOLVE_PLAIN_START is OR-ed into
+ * method, the start is first corrected to x0 + F (b - A x0), F = R_0^T A_0^{-1}
+ * R_0.  Its residual, and every later one, satisfies R_0 r = 0, where the
+ * balanced operator reduces to (I - F A) C1^{-1}: one coarse solve per
+ * iteration instead of two, same iterates as the full operator from that start.
  * info: host, may be NULL. */
 sfcdd_status sfcdd_solve(sfcdd_ctx* ctx, const double* b_dev, double* x_dev, double rtol,
                          int32_t max_iter, int32_t method, double xi, sfcdd_solve_info* info);

@@ -124,6 +124,16 @@ class OracleSchwarz:
     def matvec(self, x: np.ndarray) -> np.ndarray:
         return self.A_nat @ x
 
+    def balancing_start(self, b: np.ndarray, x0: Optional[np.ndarray] = None) -> np.ndarray:
+        """x0 + F (b - A x0) in natural order: the coarse-corrected start of
+        the balanced iteration (F = R_0^T A_0^{-1} R_0, eq. balan).  Its
+        residual r satisfies R_0 r = R_0 b - A_0 A_0^{-1} R_0 b = 0 (for x0 = 0),
+        and since R_0 A C^{-1} r = R_0 r for the balanced C^{-1}, CG and
+        Richardson keep R_0 r_k = 0 from there on."""
+        x = np.zeros(self.N) if x0 is None else np.asarray(x0, dtype=np.float64)
+        r_s = self.to_s(b - self.A_nat @ x)
+        return x + self.from_s(self.coarse_s(r_s))
+
     def dense_preconditioner(self) -> np.ndarray:
         """C^{-1} as a dense matrix in natural order (tiny grids only)."""
         I = np.eye(self.N)

@@ -28,6 +28,7 @@ VARIANT = {"additive": 0, "balanced": 1}
 FACTOR_DTYPE = {"fp64": 0, "fp32": 1}
 LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
 METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}
+SOLVE_PLAIN_START = 256
 LAYOUT = {"natural": 0, "sfc": 1}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
@@ -235,13 +236,18 @@ class SFCSchwarz:
         _check(lib().sfcdd_matvec(self.ctx, self._vec(x, "x"), self._vec(y, "y")), self.ctx)
         return y
 
-    def solve(self, b, x0=None, rtol=1e-9, max_iter=1000, method="pcg", xi=0.0, check=True):
-        """x with A x = b to relative residual rtol; returns (x, info dict)."""
+    def solve(self, b, x0=None, rtol=1e-9, max_iter=1000, method="pcg", xi=0.0, check=True,
+              plain_start=False):
+        """x with A x = b to relative residual rtol; returns (x, info dict).
+        plain_start: balanced variant only, start from x0 as given and apply
+        the full balanced operator every iteration (otherwise the start is
+        coarse-corrected and each iteration needs one coarse solve)."""
         torch = self._torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         inf = SolveInfo()
+        code = METHOD[method] | (SOLVE_PLAIN_START if plain_start else 0)
         st = lib().sfcdd_solve(self.ctx, self._vec(b, "b"), self._vec(x, "x"), float(rtol), int(max_iter),
-                               METHOD[method], float(xi), ctypes.byref(inf))
+                               code, float(xi), ctypes.byref(inf))
         if check:
             _check(st, self.ctx)
         info = {k: getattr(inf, k) for k, _ in SolveInfo._fields_}

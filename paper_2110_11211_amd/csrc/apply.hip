@@ -461,6 +461,7 @@ __global__ void k_combine(Batch B, const double* __restrict__ d0, const double* 
     if (MODE == COMB_PROLONG) out[p] = t;
     if (MODE == COMB_ADD_PROLONG) out[p] = a[p] + t;
     if (MODE == COMB_BAL_FINAL) out[p] = a[p] - t + b[p];
+    if (MODE == COMB_SUB_PROLONG) out[p] = a[p] - t;
   }
 }
 
@@ -472,8 +473,130 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
     hipLaunchKernelGGL(k_combine<COMB_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
   else if (mode == COMB_ADD_PROLONG)
     hipLaunchKernelGGL(k_combine<COMB_ADD_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
-  else
+  else if (mode == COMB_BAL_FINAL)
     hipLaunchKernelGGL(k_combine<COMB_BAL_FINAL>, grid, dim3(256), 0, s, B, d0, a, b, out);
+  else
+    hipLaunchKernelGGL(k_combine<COMB_SUB_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
+}
+
+// ---------------------------------------------------------------------------
+// Triangular matrix-vector products with a packed lower-tiled FP64 matrix X
+// (the coarse operator keeps X = L_0^{-1}, so A_0^{-1} v = X^T (X v)).
+// Streamed straight from HBM with 16-byte loads, in chunks of TRMV_CH tiles
+// per workgroup; partial results per (tile, chunk) are summed by
+// k_trmv_reduce in a fixed order (no atomics).
+constexpr int TRMV_CH = 8;
+
+// Rows: part[I][c] = sum_{K in chunk c, K <= I} X_IK v_K.
+__global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const double* __restrict__ X,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ part) {
+  const int b = blockIdx.y, ntb = bm.nt[b];
+  const int I = blockIdx.x / nchx, c = blockIdx.x % nchx;
+  const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
+  const int k0 = c * TRMV_CH;
+  if (I >= ntb || c >= nch || k0 > I) return;
+  const int k1 = min(I + 1, k0 + TRMV_CH);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lrow = lane >> 5, c0 = (lane & 31) * 2;
+  const double* Xb = X + bm.off[b] * TS2;
+  const double* vb = v + bm.xoff[b];
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int K = k0; K < k1; ++K) {
+    const double2 vk = *reinterpret_cast<const double2*>(vb + K * TS + c0);
+    const double* tile = Xb + tri_index(I, K) * TS2;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = wv * 16 + q * 2 + lrow;
+      const double2 x = *reinterpret_cast<const double2*>(tile + r * TS + c0);
+      acc[q] += x.x * vk.x + x.y * vk.y;
+    }
+  }
+  double* pb = part + bm.poff[b] + ((int64_t)I * nch + c) * TS;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double a = acc[q];
+    for (int o = 16; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((lane & 31) == 0) pb[wv * 16 + q * 2 + lrow] = a;
+  }
+}
+
+// Columns: part[K][c] = sum_{I in chunk c of [K, nt)} X_IK^T y_I.
+__global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const double* __restrict__ X,
+                                                   const double* __restrict__ y,
+                                                   double* __restrict__ part) {
+  const int b = blockIdx.y, ntb = bm.nt[b];
+  const int K = blockIdx.x / nchx, c = blockIdx.x % nchx;
+  const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
+  const int i0 = K + c * TRMV_CH;
+  if (K >= ntb || c >= nch || i0 >= ntb) return;
+  const int i1 = min(ntb, i0 + TRMV_CH);
+  __shared__ double red[4 * TS];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lrow = lane >> 5, c0 = (lane & 31) * 2;
+  const double* Xb = X + bm.off[b] * TS2;
+  const double* yb = y + bm.xoff[b];
+  double a0 = 0.0, a1 = 0.0;
+  for (int I = i0; I < i1; ++I) {
+    const double* tile = Xb + tri_index(I, K) * TS2;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = wv * 16 + q * 2 + lrow;
+      const double2 x = *reinterpret_cast<const double2*>(tile + r * TS + c0);
+      const double yr = yb[I * TS + r];
+      a0 += x.x * yr;
+      a1 += x.y * yr;
+    }
+  }
+  a0 += __shfl_xor(a0, 32, 64);
+  a1 += __shfl_xor(a1, 32, 64);
+  if (lane < 32) {
+    red[wv * TS + c0] = a0;
+    red[wv * TS + c0 + 1] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x < TS) {
+    const int col = threadIdx.x;
+    const double sum = (red[col] + red[TS + col]) + (red[2 * TS + col] + red[3 * TS + col]);
+    part[bm.poff[b] + ((int64_t)K * nch + c) * TS + col] = sum;
+  }
+}
+
+// MODE 0 (after k_trmv_rows): out = tile-padded vector at xoff[b];
+// MODE 1 (after k_trmv_cols): out = unpadded vector at doff[b], n[b] entries.
+template <int MODE>
+__global__ __launch_bounds__(TS) void k_trmv_reduce(BatchMeta bm, const int32_t* __restrict__ n,
+                                                    const int64_t* __restrict__ doff,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  const int b = blockIdx.y, ntb = bm.nt[b];
+  const int T = blockIdx.x;
+  if (T >= ntb) return;
+  const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
+  const int nc = MODE == 0 ? T / TRMV_CH + 1 : (ntb - T + TRMV_CH - 1) / TRMV_CH;
+  const int r = threadIdx.x;
+  const double* pb = part + bm.poff[b] + (int64_t)T * nch * TS + r;
+  double acc = 0.0;
+  for (int c = 0; c < nc; ++c) acc += pb[(int64_t)c * TS];
+  if (MODE == 0) {
+    out[bm.xoff[b] + T * TS + r] = acc;
+  } else {
+    const int sidx = T * TS + r;
+    if (sidx < n[b]) out[doff[b] + sidx] = acc;
+  }
+}
+
+void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
+                         const int64_t* doff, const double* X, const double* v, double* ytmp,
+                         double* part, double* out, hipStream_t s) {
+  const int nchx = (max_nt + TRMV_CH - 1) / TRMV_CH;
+  const dim3 grid(max_nt * nchx, nb);
+  hipLaunchKernelGGL(k_trmv_rows, grid, dim3(256), 0, s, bm, nchx, X, v, part);
+  hipLaunchKernelGGL(k_trmv_reduce<0>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, ytmp);
+  hipLaunchKernelGGL(k_trmv_cols, grid, dim3(256), 0, s, bm, nchx, X, ytmp, part);
+  hipLaunchKernelGGL(k_trmv_reduce<1>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, out);
 }
 
 // ---------------------------------------------------------------------------

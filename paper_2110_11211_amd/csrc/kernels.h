@@ -122,6 +122,12 @@ void launch_gather_local(const Batch& B, int max_nt, const BatchMeta& bm, const 
 void launch_scatter(const Batch& B, const int32_t* ta, const int32_t* Ni, const int64_t* doff,
                     const double* omega, const double* dbuf, double* h, hipStream_t s);
 void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s);
+// out = X^T (X v) for packed lower-tiled FP64 X (the coarse operator X = L_0^{-1}):
+// v tile-padded at bm.xoff, ytmp the same layout, part the per-(tile, chunk)
+// partials at bm.poff, out unpadded at doff (n[b] entries).
+void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
+                         const int64_t* doff, const double* X, const double* v, double* ytmp,
+                         double* part, double* out, hipStream_t s);
 void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
                     double* out, hipStream_t s);
 
@@ -162,7 +168,8 @@ enum {
 enum {
   COMB_PROLONG = 0,          // out = R0^T d0
   COMB_ADD_PROLONG,          // out = a + R0^T d0
-  COMB_BAL_FINAL             // out = a - R0^T d0 + b      (y - F A y + F g)
+  COMB_BAL_FINAL,            // out = a - R0^T d0 + b      (y - F A y + F g)
+  COMB_SUB_PROLONG           // out = a - R0^T d0          (y - F A y)
 };
 
 }  // namespace sfcdd

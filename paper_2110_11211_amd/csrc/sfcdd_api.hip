@@ -72,7 +72,7 @@ struct sfcdd_ctx {
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
-      r_cmeta, r_cgid, r_ctgid, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout;
+      r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // device pointers
@@ -84,6 +84,7 @@ struct sfcdd_ctx {
   double* d_omega = nullptr;
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
+  double* cy = nullptr;  // tile-padded coarse vector X_0 R_0 v between the two products
   double* cpartk = nullptr;  // split-K partial tiles of a single coarse factorisation
   int32_t *dc_nt = nullptr, *dc_n = nullptr;
   int64_t *dc_off = nullptr, *dc_xoff = nullptr, *dc_poff = nullptr, *dc_doff = nullptr;
@@ -478,6 +479,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_cmeta = pl.take((size_t)G * (5 * 8 + 2 * 4));
   c->r_cgid = pl.take(2 * c->N0tot);
   c->r_ctgid = pl.take(2 * c->ctiles);
+  c->r_cy = pl.take((size_t)c->c0len * 8);
   c->r_dbuf = pl.take((size_t)c->sum_Ni * 8);
   c->r_vec = pl.take((size_t)NVEC * (((size_t)Nt * 8 + 255) & ~size_t(255)));
   c->r_partials = pl.take((size_t)8 * (2 * (size_t)G * c->rbx + (size_t)MAXD * RED_BLOCKS));
@@ -518,6 +520,7 @@ void bind(sfcdd_ctx* c) {
   c->d0 = at<double>(c, c->r_d0);
   c->cpart = at<double>(c, c->r_cpart);
   c->cpartk = at<double>(c, c->r_cpartk);
+  c->cy = at<double>(c, c->r_cy);
   unsigned char* cm = c->ws + c->r_cmeta.off;
   const int G = c->G;
   c->dc_off = reinterpret_cast<int64_t*>(cm);
@@ -545,8 +548,8 @@ void bind(sfcdd_ctx* c) {
 // split-K form instead, so that every column step runs on many workgroups.
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
-                  bool invert, int32_t* status, T* part, T* tbuf, const int64_t* toff,
-                  hipStream_t s) {
+                  bool invert, bool product, int32_t* status, T* part, T* tbuf,
+                  const int64_t* toff, hipStream_t s) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   const int64_t half = (int64_t)max_nt * maxc * TS2;
   for (int J = 0; J < max_nt; ++J) {
@@ -569,18 +572,19 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
     } else {
       for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
     }
-    launch_lauum<T>(nb, max_nt, nt, off, X, fac, s);
+    if (product) launch_lauum<T>(nb, max_nt, nt, off, X, fac, s);
   }
 }
 
-// F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then d0 = A_0^{-1} c0 (per grid).
+// F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then
+// d0 = A_0^{-1} c0 = X_0^T (X_0 c0) with X_0 = L_0^{-1} (per grid).
 void coarse_solve(sfcdd_ctx* c, const double* v) {
   ProfScope ps(c, SFCDD_K_COARSE);
   const Batch B = c->batch();
   BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
   launch_restrict(B, v, c->c0, c->stream);
-  launch_symv_tiles<double>(c->G, c->max_nt0, bm, c->A0, c->c0, c->cpart, c->stream);
-  launch_symv_reduce<double>(c->G, c->max_N0, bm, c->dc_n, c->dc_doff, c->cpart, c->d0, c->stream);
+  launch_coarse_apply(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart, c->d0,
+                      c->stream);
 }
 
 // Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
@@ -645,6 +649,19 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h) {
     fine_apply(c, g, h);
     launch_combine(B, COMB_ADD_PROLONG, c->d0, h, nullptr, h, s);
   }
+}
+
+// Balanced operator on a residual r with R_0 r = 0 (F r = 0): the terms
+// t = F r and A t of eq. balSW vanish, so h = y - F A y with y = C1^{-1} r.
+// PCG and Richardson keep R_0 r_k = 0 once the start is coarse-corrected,
+// because R_0 A C^{-1} r = R_0 r, so each iteration needs one coarse solve.
+void apply_s_proj(sfcdd_ctx* c, const double* r, double* h) {
+  const Batch B = c->batch();
+  double *y = c->vec[V_Y], *v = c->vec[V_V];
+  fine_apply(c, r, y);                                         // y = C1^{-1} r
+  spmv(c, 0, y, v, nullptr, nullptr);                          // v = A y
+  coarse_solve(c, v);                                          // d0 = A0^{-1} R0 A y
+  launch_combine(B, COMB_SUB_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y - F A y
 }
 
 // Copies the per-grid scalars to the pinned host buffer.
@@ -787,7 +804,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
-    factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, c->status + 1,
+    factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
                          G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, cs);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
@@ -808,10 +825,10 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   // factor once (Sec. 3.1)
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   if (c->fdtype == SFCDD_FP32)
-    factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv,
+    factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
                         c->status, (float*)nullptr, (float*)nullptr, nullptr, s);
   else
-    factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv,
+    factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
                          c->status, (double*)nullptr, (double*)nullptr, nullptr, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
@@ -953,8 +970,16 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
   if (!b_in || !x_io || b_in == x_io) FAIL(c, SFCDD_EINVAL, "b and x must be distinct non-NULL device vectors");
   if (!(rtol > 0.0) || max_iter < 0) FAIL(c, SFCDD_EINVAL, "need rtol > 0 and max_iter >= 0");
+  const bool plain = (method & SFCDD_SOLVE_PLAIN_START) != 0;
+  method &= ~SFCDD_SOLVE_PLAIN_START;
   if (method != SFCDD_PCG && method != SFCDD_FCG && method != SFCDD_RICHARDSON)
     FAIL(c, SFCDD_EINVAL, "method = %d", method);
+  // balanced form: coarse-corrected start, then one coarse solve per iteration
+  const bool proj = c->variant == SFCDD_BALANCED && !plain;
+  auto precond = [&](const double* g, double* h) {
+    if (proj) apply_s_proj(c, g, h);
+    else apply_s(c, g, h);
+  };
   const hipStream_t s = c->stream;
   const int64_t N = c->Ntot;
   const int G = c->G;
@@ -967,6 +992,12 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   } else {
     launch_permute(N, c->sfc_index, b_in, b, 1, s);
     launch_permute(N, c->sfc_index, x_io, x, 1, s);
+  }
+  if (proj) {
+    // x <- x + F (b - A x), so that R_0 (b - A x) = 0 (balancing start)
+    spmv(c, 2, x, tmp, b, c->partials);
+    coarse_solve(c, tmp);
+    launch_combine(B, COMB_ADD_PROLONG, c->d0, x, nullptr, x, s);
   }
   launch_dot(B, b, b, nullptr, c->partials, s);
   launch_finalize(B, FIN_BB, c->partials, c->scal, s);
@@ -999,9 +1030,9 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       std::vector<std::vector<double>> al(G), be(G);
       std::vector<int32_t> ok(G, 1);
       if ((st = write_active(c, ok))) return st;
-      launch_zero(N, z, s);  // z is the iterate of the estimation run
-      launch_copy(N, b, r, s);
-      apply_s(c, r, q);
+      launch_zero(N, z, s);  // z is the iterate of the estimation run (on the residual of x)
+      spmv(c, 2, x, r, b, c->partials);
+      precond(r, q);
       launch_copy(N, q, p, s);
       launch_dot(B, r, q, nullptr, c->partials, s);
       launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, s);
@@ -1015,7 +1046,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
           if (ok[g] && a_k > 0.0 && std::isfinite(a_k)) al[g].push_back(a_k);
           else ok[g] = 0;
         }
-        apply_s(c, r, q);
+        precond(r, q);
         launch_dot(B, r, q, nullptr, c->partials, s);
         launch_finalize(B, FIN_RZ_NEXT, c->partials, c->scal, s);
         if ((st = read_scal(c))) return st;
@@ -1060,7 +1091,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         if (act[g] && rr[g] <= tol2[g]) act[g] = 0;
       if (n_active() == 0 || it >= max_iter) break;
       if ((st = write_active(c, act))) return st;
-      apply_s(c, r, z);
+      precond(r, z);
       launch_axpy_scal(B, c->scal, S_XI, c->active, x, z, s);
       ++it;
       for (int g = 0; g < G; ++g) its[g] += act[g] != 0;
@@ -1075,7 +1106,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       if (rr[g] <= tol2[g]) act[g] = 0;
     if (n_active() > 0 && max_iter > 0) {
       if ((st = write_active(c, act))) return st;
-      apply_s(c, r, z);
+      precond(r, z);
       launch_dot(B, r, z, nullptr, c->partials, s);
       launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, s);
       launch_copy(N, z, p, s);
@@ -1115,7 +1146,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         }
         if (n_active() == 0) break;
         if ((st = write_active(c, act))) return st;
-        apply_s(c, r, z);
+        precond(r, z);
         launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
         launch_finalize(B, flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT, c->partials, c->scal, s);
         launch_update_p(B, c->scal, c->active, p, z, s);

@@ -120,15 +120,20 @@ def test_apply_sfc_layout_and_determinism():
     assert relerr(h1, O.apply_s(rs)) <= FP64_TOL
 
 
-def test_pcg_c1_iterations_and_solution():
+@pytest.mark.parametrize("plain", [False, True])
+def test_pcg_c1_iterations_and_solution(plain):
+    """Default: balancing start x0 = F b and one coarse solve per iteration;
+    plain: x0 = 0 and the full balanced operator.  Each against the oracle's
+    PCG from the same start."""
     w = workloads()["c1"]
-    announce("pcg c1")
+    announce("pcg c1", plain)
     g = Grid(levels=w.levels[0])
     O = OracleSchwarz(g, w.P, w.gamma)
     f = w.rhs()
-    _, it_o, _ = solvers.pcg(O.A_nat, f, O.apply, rtol=w.rtol)
+    x0 = None if plain else O.balancing_start(f)
+    _, it_o, _ = solvers.pcg(O.A_nat, f, O.apply, x0=x0, rtol=w.rtol)
     S = _solver(w.levels[0], w.P, w.gamma)
-    x, info = S.solve(dvec(f), rtol=w.rtol)
+    x, info = S.solve(dvec(f), rtol=w.rtol, plain_start=plain)
     assert abs(info["iterations"] - it_o) <= 1
     assert info["rel_residual"] <= w.rtol
     xs = exact.solve(g, f)
@@ -157,9 +162,12 @@ def test_richardson_fixed_xi_matches_oracle_count():
     xi, _ = solvers.optimal_damping(lmin, lmax)
     f = uniform_pm1(5, g.N)
     _, it_o = solvers.richardson(O.A_nat, f, O.apply, xi, rtol=1e-8)
+    _, it_b = solvers.richardson(O.A_nat, f, O.apply, xi, x0=O.balancing_start(f), rtol=1e-8)
     S = _solver(levels, P, gamma)
-    x, info = S.solve(dvec(f), rtol=1e-8, method="richardson", xi=xi, max_iter=5000)
+    x, info = S.solve(dvec(f), rtol=1e-8, method="richardson", xi=xi, max_iter=5000, plain_start=True)
     assert abs(info["iterations"] - it_o) <= 1
+    xb, infob = S.solve(dvec(f), rtol=1e-8, method="richardson", xi=xi, max_iter=5000)
+    assert abs(infob["iterations"] - it_b) <= 1
     x2, info2 = S.solve(dvec(f), rtol=1e-8, method="richardson", xi=0.0, max_iter=5000)
     assert abs(info2["lambda_max"] - lmax) <= 1e-3 * lmax
     assert info2["iterations"] <= 1.5 * it_o + 2

@@ -91,6 +91,27 @@ def test_balanced_is_identity_on_coarse_space(levels, P, gamma, q):
     assert np.allclose(S.apply(S.matvec(v)), v, atol=1e-11 * np.abs(v).max())
 
 
+@pytest.mark.parametrize("levels,P,gamma,q", SMALL)
+def test_balancing_start_keeps_residuals_in_kernel_of_R0(levels, P, gamma, q):
+    """From x_0 = F b the residual has R_0 r = 0, CG keeps it there, and on
+    such r the balanced operator equals (I - F A) C1^{-1} r (t = F r vanishes)."""
+    g = Grid(levels=levels)
+    S = OracleSchwarz(g, P, gamma, q=q, variant="balanced")
+    b = uniform_pm1(6, g.N)
+    nb = np.linalg.norm(S.R0 @ S.to_s(b))
+    x0 = S.balancing_start(b)
+    r0 = S.to_s(b - S.matvec(x0))
+    assert np.linalg.norm(S.R0 @ r0) <= 1e-12 * nb
+    x3, _, _ = solvers.pcg(S.A_nat, b, S.apply, x0=x0, rtol=1e-300, maxit=3)
+    r3 = S.to_s(b - S.matvec(x3))
+    assert np.linalg.norm(S.R0 @ r3) <= 1e-11 * nb
+    v = S.to_s(uniform_pm1(7, g.N))
+    r = v - S.A @ S.coarse_s(v)                      # R_0 r = 0
+    y = S.fine_s(r)
+    proj = y - S.coarse_s(S.A @ y)
+    assert np.allclose(S.apply_s(r), proj, atol=1e-12 * np.abs(proj).max())
+
+
 def test_single_subdomain_is_exact():
     """P = 1: the only subdomain is the whole grid, so C_bal^{-1} = A^{-1}
     (PCG converges in one step) and additive PCG needs at most two."""
