@@ -29,140 +29,146 @@ template <typename T> struct Pstride { static constexpr int v = (sizeof(T) == 8)
 constexpr int DB = 16;         // block edge inside the diagonal tile
 constexpr int NDB = TS / DB;   // blocks per tile edge
 
-// Cholesky factor and inverse of one DB x DB diagonal block at (o, o) of sC,
-// by lanes 0..DB-1 of the first wave alone (one wave issues its LDS
-// operations in program order, so no barrier is needed inside):
-// factoring, lane i owns block row i; inverting, lane c owns column c of the
-// inverse, written to dinv (row-major DB x DB, lower).
+// Cholesky factor and inverse of the DB x DB diagonal block at (o, o) of sC,
+// by the first wave, in registers: lane i < DB holds block row i; column k
+// of the factor is broadcast from lane k's registers (readlane), so the
+// serial chain has no LDS round trips.  Writes the factor back to the block
+// (upper part zero) and its inverse, row-major and lower, to dinv.
+// A non-positive pivot sets *status to -6 and is replaced by 1.
 template <typename T>
-__device__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv,
-                             T* __restrict__ colbuf, int32_t* status) {
+__device__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, int32_t* status) {
   constexpr int PS = Pstride<T>::v;
   const int i = threadIdx.x;
-  if (i >= DB) return;
+  const bool act = i < DB;
+  T a[DB];
+#pragma unroll
+  for (int j = 0; j < DB; ++j) a[j] = act ? sC[(o + i) * PS + o + j] : T(0);
+#pragma unroll
   for (int k = 0; k < DB; ++k) {
-    T piv = sC[(o + k) * PS + o + k];
+    T piv = bcast(a[k], k);
     if (!(piv > T(0))) {
       if (i == k) atomicExch(status, -6);
       piv = T(1);
     }
     const T dk = sqrt(piv);
     const T rdk = T(1) / dk;
-    const T l = (i > k) ? sC[(o + i) * PS + o + k] * rdk : (i == k ? dk : T(0));
-    if (i >= k) sC[(o + i) * PS + o + k] = l;
-    colbuf[i] = (i > k) ? l : T(0);
+    const T l = (i > k) ? a[k] * rdk : (i == k ? dk : T(0));
+    a[k] = l;
 #pragma unroll
-    for (int j = 0; j < DB; ++j)
-      if (j > k) sC[(o + i) * PS + o + j] -= l * colbuf[j];
+    for (int j = k + 1; j < DB; ++j) a[j] -= l * bcast(l, j);
   }
-  // inverse of the DB x DB lower factor, column c per lane
-  const int c = i;
+  // inverse by forward substitution, lane c owning column c
+  T dg = T(1);
+#pragma unroll
+  for (int j = 0; j < DB; ++j)
+    if (i == j) dg = a[j];
+  const T rinv = T(1) / dg;
   T x[DB];
 #pragma unroll
-  for (int r = 0; r < DB; ++r) x[r] = (r == c) ? T(1) : T(0);
+  for (int r = 0; r < DB; ++r) {
+    T sum = (r == i) ? T(1) : T(0);
 #pragma unroll
-  for (int k = 0; k < DB; ++k) {
-    x[k] = x[k] / sC[(o + k) * PS + o + k];
-#pragma unroll
-    for (int r = k + 1; r < DB; ++r) x[r] -= sC[(o + r) * PS + o + k] * x[k];
+    for (int k = 0; k < r; ++k) sum -= bcast(a[k], r) * x[k];
+    x[r] = sum * bcast(rinv, r);
   }
+  if (act) {
 #pragma unroll
-  for (int r = 0; r < DB; ++r) dinv[r * DB + c] = x[r];
+    for (int j = 0; j < DB; ++j) sC[(o + i) * PS + o + j] = a[j];
+#pragma unroll
+    for (int r = 0; r < DB; ++r) dinv[r * DB + i] = x[r];
+  }
+}
+
+// 16x16 blocks on MFMA, one wave (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] per k-step of 4).  c += X Y^T (X, Y row-major, 16 columns
+// read from k = 0).
+template <typename T>
+__device__ __forceinline__ void blk_abt(typename Acc<T>::type& c, const T* X, int ldx, const T* Y,
+                                        int ldy) {
+  const int m = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
+#pragma unroll
+  for (int st = 0; st < DB / 4; ++st) c = mfma16(X[m * ldx + 4 * st + kk], Y[m * ldy + 4 * st + kk], c);
+}
+// c += X Z (Z row-major).
+template <typename T>
+__device__ __forceinline__ void blk_ab(typename Acc<T>::type& c, const T* X, int ldx, const T* Z,
+                                       int ldz) {
+  const int m = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
+#pragma unroll
+  for (int st = 0; st < DB / 4; ++st) c = mfma16(X[m * ldx + 4 * st + kk], Z[(4 * st + kk) * ldz + m], c);
+}
+template <typename T>
+__device__ __forceinline__ void blk_store(const typename Acc<T>::type& c, T* D, int ld, T sign) {
+  const int g = (threadIdx.x >> 4) & 3, n = threadIdx.x & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) D[Acc<T>::row(g, r) * ld + n] = sign * c[r];
+}
+template <typename T>
+__device__ __forceinline__ void blk_sub(const typename Acc<T>::type& c, T* D, int ld) {
+  const int g = (threadIdx.x >> 4) & 3, n = threadIdx.x & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) D[Acc<T>::row(g, r) * ld + n] -= c[r];
+}
+template <typename T>
+__device__ __forceinline__ typename Acc<T>::type blk_zero() {
+  typename Acc<T>::type c;
+  c[0] = c[1] = c[2] = c[3] = T(0);
+  return c;
 }
 
 // Cholesky factorisation and inversion of a TS x TS LDS tile (stride
-// Pstride, lower part read), blocked by DB: the DB x DB diagonal blocks are
-// factored and inverted by one wave, the panels, trailing updates and the
-// off-diagonal blocks of the inverse by the whole workgroup.
+// Pstride, lower part read), blocked by DB, all by the first wave (one wave
+// issues its LDS operations in program order, so no barrier is needed
+// inside): register factorisation of each diagonal block, panel and trailing
+// updates as 16x16 MFMA block products, then the block rows of the inverse,
+// X_IJ = -L_II^{-1} sum_{K=J}^{I-1} L_IK X_KJ.
 // On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).
-// A non-positive pivot sets *status to -6 and is replaced by 1.
 template <typename T>
 __device__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, T* __restrict__ dinv,
-                               T* __restrict__ colbuf, int32_t* status) {
+                               T* __restrict__ tmp, int32_t* status) {
   constexpr int PS = Pstride<T>::v;
-  const int tid = threadIdx.x;
+  typedef typename Acc<T>::type AT;
   __syncthreads();
-  for (int bk = 0; bk < NDB; ++bk) {
-    const int o = bk * DB;
-    factor_block(sC, o, dinv + bk * DB * DB, colbuf, status);
-    __syncthreads();
-    // panel: L[r][o..o+DB) = C[r][o..o+DB) Dinv^T for rows below the block
-    const int nrow = TS - o - DB;
-    T pv[(TS - DB) * DB / TILE_THREADS];
-    const T* Di = dinv + bk * DB * DB;
-#pragma unroll
-    for (int q = 0; q < (TS - DB) * DB / TILE_THREADS; ++q) {
-      const int t = tid + q * TILE_THREADS;
-      pv[q] = T(0);
-      if (t < nrow * DB) {
-        const int r = o + DB + t / DB, cc = t % DB;
-        T acc = T(0);
-#pragma unroll
-        for (int m = 0; m < DB; ++m) acc += sC[r * PS + o + m] * Di[cc * DB + m];
-        pv[q] = acc;
+  if (threadIdx.x < 64) {
+    for (int bk = 0; bk < NDB; ++bk) {
+      const int o = bk * DB;
+      factor_block(sC, o, dinv + bk * DB * DB, status);
+      for (int rb = bk + 1; rb < NDB; ++rb) {      // L_rb,bk = C_rb,bk L_bk,bk^{-T}
+        AT c = blk_zero<T>();
+        blk_abt<T>(c, sC + rb * DB * PS + o, PS, dinv + bk * DB * DB, DB);
+        blk_store<T>(c, sC + rb * DB * PS + o, PS, T(1));
       }
+      for (int rb = bk + 1; rb < NDB; ++rb)        // C_rb,cb -= L_rb,bk L_cb,bk^T
+        for (int cb = bk + 1; cb <= rb; ++cb) {
+          AT u = blk_zero<T>();
+          blk_abt<T>(u, sC + rb * DB * PS + o, PS, sC + cb * DB * PS + o, PS);
+          blk_sub<T>(u, sC + rb * DB * PS + cb * DB, PS);
+        }
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < (TS - DB) * DB / TILE_THREADS; ++q) {
-      const int t = tid + q * TILE_THREADS;
-      if (t < nrow * DB) sC[(o + DB + t / DB) * PS + o + t % DB] = pv[q];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < NDB * DB * DB; e += 64) {  // X_II = L_II^{-1}
+      const int I = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
+      sX[(I * DB + r) * PS + I * DB + cc] = dinv[e];
     }
-    __syncthreads();
-    // trailing update of the lower part below and right of the block:
-    // C[i][j] -= sum_m L[i][o+m] L[j][o+m] for o+DB <= j <= i
-    const int m0 = o + DB;
-    const int span = TS - m0;
-    for (int e = tid; e < span * span; e += TILE_THREADS) {
-      const int i = m0 + e / span, j = m0 + e % span;
-      if (j > i) continue;
-      T acc = T(0);
-#pragma unroll
-      for (int m = 0; m < DB; ++m) acc += sC[i * PS + o + m] * sC[j * PS + o + m];
-      sC[i * PS + j] -= acc;
-    }
-    __syncthreads();
-  }
-  // X = L^{-1} by block rows: X_II = Dinv_I,
-  // X_IJ = -Dinv_I sum_{K=J}^{I-1} L_IK X_KJ for J < I.
-  for (int e = tid; e < TS * TS; e += TILE_THREADS) {
-    const int r = e / TS, cc = e % TS;
-    const int I = r / DB, J = cc / DB;
-    sX[r * PS + cc] = (I == J) ? dinv[I * DB * DB + (r % DB) * DB + (cc % DB)] : T(0);
+    for (int I = 1; I < NDB; ++I)
+      for (int J = 0; J < I; ++J) {
+        AT t = blk_zero<T>();
+        for (int K = J; K < I; ++K) blk_ab<T>(t, sC + I * DB * PS + K * DB, PS, sX + K * DB * PS + J * DB, PS);
+        blk_store<T>(t, tmp, DB, T(1));
+        AT xij = blk_zero<T>();
+        blk_ab<T>(xij, dinv + I * DB * DB, DB, tmp, DB);
+        blk_store<T>(xij, sX + I * DB * PS + J * DB, PS, T(-1));
+      }
   }
   __syncthreads();
-  T* tmp = sC;  // upper part of sC is free: tmp block (I, J) stored at rows of J, columns of I
-  for (int I = 1; I < NDB; ++I) {
-    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ for J < I, one element per thread
-    for (int e = tid; e < I * DB * DB; e += TILE_THREADS) {
-      const int J = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
-      T acc = T(0);
-      for (int K = J; K < I; ++K) {
-#pragma unroll
-        for (int m = 0; m < DB; ++m)
-          acc += sC[(I * DB + r) * PS + K * DB + m] * sX[(K * DB + m) * PS + J * DB + cc];
-      }
-      tmp[(J * DB + cc) * PS + I * DB + r] = acc;  // transposed into the free upper part
-    }
-    __syncthreads();
-    for (int e = tid; e < I * DB * DB; e += TILE_THREADS) {
-      const int J = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
-      T acc = T(0);
-#pragma unroll
-      for (int m = 0; m < DB; ++m)
-        acc += dinv[I * DB * DB + r * DB + m] * tmp[(J * DB + cc) * PS + I * DB + m];
-      sX[(I * DB + r) * PS + J * DB + cc] = -acc;
-    }
-    __syncthreads();
-  }
 }
 
 // LDS of the diagonal kernel: two Pstride tiles (C, X), the DB x DB block
-// inverses and a column buffer.  The GEMM staging (two LDS_S tiles) fits in
+// inverses and one DB x DB scratch block.  The GEMM staging (two LDS_S tiles) fits in
 // the same space.
 template <typename T>
 constexpr size_t diag_lds_bytes() {
-  return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + TS) * sizeof(T);
+  return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + DB * DB) * sizeof(T);
 }
 
 // Left-looking: the tile first receives -sum_{K<J} L_JK L_JK^T.  The terms
@@ -197,11 +203,11 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
   T* sC = reinterpret_cast<T*>(smem_raw);
   T* sX = sC + TS * PS;
   T* dinv = sX + TS * PS;
-  T* colbuf = dinv + NDB * DB * DB;
+  T* tmp = dinv + NDB * DB * DB;
   for (int a = 0; a < 2; ++a)
     for (int b2 = 0; b2 < 2; ++b2)
       for (int r = 0; r < 4; ++r) sC[TileAcc<T>::row(a, r) * PS + TileAcc<T>::col(b2)] = acc.c[a][b2][r];
-  potrf_inv_tile(sC, sX, dinv, colbuf, status);
+  potrf_inv_tile(sC, sX, dinv, tmp, status);
   T* D = F + tri_index(J, J) * TS2;
   for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
     const int i = e / TS, j = e % TS;
