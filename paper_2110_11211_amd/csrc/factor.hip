@@ -29,18 +29,30 @@ template <typename T> struct Pstride { static constexpr int v = (sizeof(T) == 8)
 constexpr int DB = 16;         // block edge inside the diagonal tile
 constexpr int NDB = TS / DB;   // blocks per tile edge
 
+// 1/sqrt(x) for x > 0: hardware estimate refined by one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+
 // Cholesky factor and inverse of the DB x DB diagonal block at (o, o) of sC,
-// by the first wave, in registers: lane i < DB holds block row i; column k
-// of the factor is broadcast from lane k's registers (readlane), so the
-// serial chain has no LDS round trips.  Writes the factor back to the block
-// (upper part zero) and its inverse, row-major and lower, to dinv.
-// A non-positive pivot sets *status to -6 and is replaced by 1.
+// by the first wave: lane i < DB holds block row i in registers; after each
+// pivot the new factor column is broadcast through the LDS buffer colbuf
+// (one write, same-address reads; one wave issues its LDS operations in
+// program order).  Writes the factor back to the block (upper part zero),
+// its inverse (row-major, lower) to dinv.  A non-positive pivot sets
+// *status to -6 and is replaced by 1.
 template <typename T>
-__device__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, int32_t* status) {
+__device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, T* __restrict__ colbuf,
+                             int32_t* status) {
   constexpr int PS = Pstride<T>::v;
   const int i = threadIdx.x;
   const bool act = i < DB;
-  T a[DB];
+  T a[DB], rd[DB];
 #pragma unroll
   for (int j = 0; j < DB; ++j) a[j] = act ? sC[(o + i) * PS + o + j] : T(0);
 #pragma unroll
@@ -50,52 +62,58 @@ __device__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, in
       if (i == k) atomicExch(status, -6);
       piv = T(1);
     }
-    const T dk = sqrt(piv);
-    const T rdk = T(1) / dk;
-    const T l = (i > k) ? a[k] * rdk : (i == k ? dk : T(0));
+    const T rs = rsqrt_nr(piv);
+    rd[k] = rs;
+    const T l = (i > k) ? a[k] * rs : (i == k ? piv * rs : T(0));
     a[k] = l;
+    if (k + 1 < DB) {
+      if (act) colbuf[i] = l;
 #pragma unroll
-    for (int j = k + 1; j < DB; ++j) a[j] -= l * bcast(l, j);
+      for (int j = k + 1; j < DB; ++j) a[j] -= l * colbuf[j];
+    }
   }
-  // inverse by forward substitution, lane c owning column c
-  T dg = T(1);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < DB; ++j)
-    if (i == j) dg = a[j];
-  const T rinv = T(1) / dg;
+    for (int j = 0; j < DB; ++j) sC[(o + i) * PS + o + j] = a[j];
+  }
+  // inverse by forward substitution, lane c owning column c; L_rk read back
+  // from the block (same address in every lane), 1/L_rr = rd[r]
   T x[DB];
 #pragma unroll
   for (int r = 0; r < DB; ++r) {
     T sum = (r == i) ? T(1) : T(0);
 #pragma unroll
-    for (int k = 0; k < r; ++k) sum -= bcast(a[k], r) * x[k];
-    x[r] = sum * bcast(rinv, r);
+    for (int k = 0; k < r; ++k) sum -= sC[(o + r) * PS + o + k] * x[k];
+    x[r] = sum * rd[r];
   }
   if (act) {
-#pragma unroll
-    for (int j = 0; j < DB; ++j) sC[(o + i) * PS + o + j] = a[j];
 #pragma unroll
     for (int r = 0; r < DB; ++r) dinv[r * DB + i] = x[r];
   }
 }
 
-// 16x16 blocks on MFMA, one wave (lane l supplies A[l%16][l/16] and
-// B[l/16][l%16] per k-step of 4).  c += X Y^T (X, Y row-major, 16 columns
-// read from k = 0).
+// 16x16 blocks on MFMA, one wave: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] per k-step of 4.  Operand fragments of a row-major block X:
+// fragment st of lane l is X[l%16][4 st + l/16] (the A operand of X, and the
+// B operand of X^T).
 template <typename T>
-__device__ __forceinline__ void blk_abt(typename Acc<T>::type& c, const T* X, int ldx, const T* Y,
-                                        int ldy) {
+__device__ __forceinline__ void frag_load(T (&f)[DB / 4], const T* X, int ld) {
   const int m = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
 #pragma unroll
-  for (int st = 0; st < DB / 4; ++st) c = mfma16(X[m * ldx + 4 * st + kk], Y[m * ldy + 4 * st + kk], c);
+  for (int st = 0; st < DB / 4; ++st) f[st] = X[m * ld + 4 * st + kk];
 }
-// c += X Z (Z row-major).
+// B operand of a row-major block Z (B = Z): Z[4 st + l/16][l%16].
 template <typename T>
-__device__ __forceinline__ void blk_ab(typename Acc<T>::type& c, const T* X, int ldx, const T* Z,
-                                       int ldz) {
+__device__ __forceinline__ void frag_load_b(T (&f)[DB / 4], const T* Z, int ld) {
   const int m = threadIdx.x & 15, kk = (threadIdx.x >> 4) & 3;
 #pragma unroll
-  for (int st = 0; st < DB / 4; ++st) c = mfma16(X[m * ldx + 4 * st + kk], Z[(4 * st + kk) * ldz + m], c);
+  for (int st = 0; st < DB / 4; ++st) f[st] = Z[(4 * st + kk) * ld + m];
+}
+template <typename T>
+__device__ __forceinline__ void frag_mma(typename Acc<T>::type& c, const T (&a)[DB / 4],
+                                         const T (&b)[DB / 4]) {
+#pragma unroll
+  for (int st = 0; st < DB / 4; ++st) c = mfma16(a[st], b[st], c);
 }
 template <typename T>
 __device__ __forceinline__ void blk_store(const typename Acc<T>::type& c, T* D, int ld, T sign) {
@@ -104,10 +122,10 @@ __device__ __forceinline__ void blk_store(const typename Acc<T>::type& c, T* D, 
   for (int r = 0; r < 4; ++r) D[Acc<T>::row(g, r) * ld + n] = sign * c[r];
 }
 template <typename T>
-__device__ __forceinline__ void blk_sub(const typename Acc<T>::type& c, T* D, int ld) {
+__device__ __forceinline__ void blk_load(typename Acc<T>::type& c, const T* D, int ld) {
   const int g = (threadIdx.x >> 4) & 3, n = threadIdx.x & 15;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) D[Acc<T>::row(g, r) * ld + n] -= c[r];
+  for (int r = 0; r < 4; ++r) c[r] = D[Acc<T>::row(g, r) * ld + n];
 }
 template <typename T>
 __device__ __forceinline__ typename Acc<T>::type blk_zero() {
@@ -116,59 +134,116 @@ __device__ __forceinline__ typename Acc<T>::type blk_zero() {
   return c;
 }
 
-// Cholesky factorisation and inversion of a TS x TS LDS tile (stride
-// Pstride, lower part read), blocked by DB, all by the first wave (one wave
-// issues its LDS operations in program order, so no barrier is needed
-// inside): register factorisation of each diagonal block, panel and trailing
-// updates as 16x16 MFMA block products, then the block rows of the inverse,
-// X_IJ = -L_II^{-1} sum_{K=J}^{I-1} L_IK X_KJ.
-// On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).
-template <typename T>
-__device__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, T* __restrict__ dinv,
-                               T* __restrict__ tmp, int32_t* status) {
+// One column block bk of the blocked factorisation (first wave): diagonal
+// block, panel L_rb,bk = C_rb,bk L_bk,bk^{-T} and trailing update
+// C_rb,cb -= L_rb,bk L_cb,bk^T, with independent block products issued
+// together.
+template <typename T, int bk>
+__device__ __forceinline__ void factor_column(T* __restrict__ sC, T* __restrict__ dinv,
+                                              T* __restrict__ colbuf, int32_t* status) {
+  constexpr int PS = Pstride<T>::v;
+  constexpr int o = bk * DB;
+  constexpr int nr = NDB - 1 - bk;  // blocks below the diagonal
+  typedef typename Acc<T>::type AT;
+  factor_block(sC, o, dinv + bk * DB * DB, colbuf, status);
+  if constexpr (nr > 0) {
+    T fd[DB / 4], fc[nr][DB / 4];
+    frag_load<T>(fd, dinv + bk * DB * DB, DB);                 // B = Dinv^T
+#pragma unroll
+    for (int q = 0; q < nr; ++q) frag_load<T>(fc[q], sC + (o + DB + q * DB) * PS + o, PS);
+    AT pc[nr];
+#pragma unroll
+    for (int q = 0; q < nr; ++q) {
+      pc[q] = blk_zero<T>();
+      frag_mma<T>(pc[q], fc[q], fd);
+    }
+#pragma unroll
+    for (int q = 0; q < nr; ++q) blk_store<T>(pc[q], sC + (o + DB + q * DB) * PS + o, PS, T(1));
+    T fl[nr][DB / 4];
+#pragma unroll
+    for (int q = 0; q < nr; ++q) frag_load<T>(fl[q], sC + (o + DB + q * DB) * PS + o, PS);
+#pragma unroll
+    for (int q = 0; q < nr; ++q)
+#pragma unroll
+      for (int u = 0; u <= q; ++u) {                              // block (rb, cb) = (bk+1+q, bk+1+u)
+        T* D = sC + (o + DB + q * DB) * PS + o + DB + u * DB;
+        AT cc;
+        blk_load<T>(cc, D, PS);
+        AT up = blk_zero<T>();
+        frag_mma<T>(up, fl[q], fl[u]);
+        cc -= up;
+        blk_store<T>(cc, D, PS, T(1));
+      }
+  }
+}
+
+// Block row I of X = L^{-1}: X_IJ = -L_II^{-1} sum_{K=J}^{I-1} L_IK X_KJ,
+// J < I (rows above already complete).
+template <typename T, int I>
+__device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restrict__ sX,
+                                            const T* __restrict__ dinv, T* __restrict__ tmp) {
   constexpr int PS = Pstride<T>::v;
   typedef typename Acc<T>::type AT;
+  AT t[I];
+#pragma unroll
+  for (int J = 0; J < I; ++J) t[J] = blk_zero<T>();
+#pragma unroll
+  for (int K = 0; K < I; ++K) {
+    T fa[DB / 4];
+    frag_load<T>(fa, sC + (I * DB) * PS + K * DB, PS);         // A = L_IK
+#pragma unroll
+    for (int J = 0; J <= K; ++J) {
+      T fb[DB / 4];
+      frag_load_b<T>(fb, sX + (K * DB) * PS + J * DB, PS);     // B = X_KJ
+      frag_mma<T>(t[J], fa, fb);
+    }
+  }
+  T fdi[DB / 4];
+  frag_load<T>(fdi, dinv + I * DB * DB, DB);                   // A = L_II^{-1}
+#pragma unroll
+  for (int J = 0; J < I; ++J) {
+    blk_store<T>(t[J], tmp + J * DB * DB, DB, T(1));
+    T fb[DB / 4];
+    frag_load_b<T>(fb, tmp + J * DB * DB, DB);
+    AT xij = blk_zero<T>();
+    frag_mma<T>(xij, fdi, fb);
+    blk_store<T>(xij, sX + (I * DB) * PS + J * DB, PS, T(-1));
+  }
+}
+
+// Cholesky factorisation and inversion of a TS x TS LDS tile (stride
+// Pstride, lower part read), blocked by DB, all by the first wave.
+// On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).
+// tmp: (NDB - 1) DB x DB blocks plus a DB column buffer.
+template <typename T>
+__device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, T* __restrict__ dinv,
+                               T* __restrict__ tmp, int32_t* status) {
+  constexpr int PS = Pstride<T>::v;
   __syncthreads();
   if (threadIdx.x < 64) {
-    for (int bk = 0; bk < NDB; ++bk) {
-      const int o = bk * DB;
-      factor_block(sC, o, dinv + bk * DB * DB, status);
-      for (int rb = bk + 1; rb < NDB; ++rb) {      // L_rb,bk = C_rb,bk L_bk,bk^{-T}
-        AT c = blk_zero<T>();
-        blk_abt<T>(c, sC + rb * DB * PS + o, PS, dinv + bk * DB * DB, DB);
-        blk_store<T>(c, sC + rb * DB * PS + o, PS, T(1));
-      }
-      for (int rb = bk + 1; rb < NDB; ++rb)        // C_rb,cb -= L_rb,bk L_cb,bk^T
-        for (int cb = bk + 1; cb <= rb; ++cb) {
-          AT u = blk_zero<T>();
-          blk_abt<T>(u, sC + rb * DB * PS + o, PS, sC + cb * DB * PS + o, PS);
-          blk_sub<T>(u, sC + rb * DB * PS + cb * DB, PS);
-        }
-    }
+    T* colbuf = tmp + (NDB - 1) * DB * DB;
+    factor_column<T, 0>(sC, dinv, colbuf, status);
+    factor_column<T, 1>(sC, dinv, colbuf, status);
+    factor_column<T, 2>(sC, dinv, colbuf, status);
+    factor_column<T, 3>(sC, dinv, colbuf, status);
     const int lane = threadIdx.x;
     for (int e = lane; e < NDB * DB * DB; e += 64) {  // X_II = L_II^{-1}
       const int I = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
       sX[(I * DB + r) * PS + I * DB + cc] = dinv[e];
     }
-    for (int I = 1; I < NDB; ++I)
-      for (int J = 0; J < I; ++J) {
-        AT t = blk_zero<T>();
-        for (int K = J; K < I; ++K) blk_ab<T>(t, sC + I * DB * PS + K * DB, PS, sX + K * DB * PS + J * DB, PS);
-        blk_store<T>(t, tmp, DB, T(1));
-        AT xij = blk_zero<T>();
-        blk_ab<T>(xij, dinv + I * DB * DB, DB, tmp, DB);
-        blk_store<T>(xij, sX + I * DB * PS + J * DB, PS, T(-1));
-      }
+    inverse_row<T, 1>(sC, sX, dinv, tmp);
+    inverse_row<T, 2>(sC, sX, dinv, tmp);
+    inverse_row<T, 3>(sC, sX, dinv, tmp);
   }
   __syncthreads();
 }
 
 // LDS of the diagonal kernel: two Pstride tiles (C, X), the DB x DB block
-// inverses and one DB x DB scratch block.  The GEMM staging (two LDS_S tiles) fits in
+// inverses, NDB - 1 scratch blocks and a column buffer.  The GEMM staging (two LDS_S tiles) fits in
 // the same space.
 template <typename T>
 constexpr size_t diag_lds_bytes() {
-  return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + DB * DB) * sizeof(T);
+  return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + (NDB - 1) * DB * DB + DB) * sizeof(T);
 }
 
 // Left-looking: the tile first receives -sum_{K<J} L_JK L_JK^T.  The terms
