@@ -40,12 +40,11 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
 }
 
 // Cholesky factor and inverse of the DB x DB diagonal block at (o, o) of sC,
-// by the first wave: lane i < DB holds block row i in registers; after each
-// pivot the new factor column is broadcast through the LDS buffer colbuf
-// (one write, same-address reads; one wave issues its LDS operations in
-// program order).  Writes the factor back to the block (upper part zero),
-// its inverse (row-major, lower) to dinv.  A non-positive pivot sets
-// *status to -6 and is replaced by 1.
+// by the first wave: lane i < DB holds block row i in registers, and the
+// factor column of each pivot is read from the pivot lane's registers
+// (readlane).  Writes the factor back to the block (upper part zero), its
+// inverse (row-major, lower) to dinv.  A non-positive pivot sets *status to
+// -6 and is replaced by 1.
 template <typename T>
 __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, T* __restrict__ colbuf,
                              int32_t* status) {
@@ -53,25 +52,31 @@ __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __res
   const int i = threadIdx.x;
   const bool act = i < DB;
   T a[DB], rd[DB];
+  // full symmetric row i from the lower triangle (the stored upper part is
+  // not meaningful)
 #pragma unroll
-  for (int j = 0; j < DB; ++j) a[j] = act ? sC[(o + i) * PS + o + j] : T(0);
+  for (int j = 0; j < DB; ++j)
+    a[j] = act ? (j <= i ? sC[(o + i) * PS + o + j] : sC[(o + j) * PS + o + i]) : T(0);
 #pragma unroll
   for (int k = 0; k < DB; ++k) {
+    // the trailing block stays symmetric (every lane updates its whole row),
+    // so column k below the pivot is row k right of it: lane k's registers
     T piv = bcast(a[k], k);
     if (!(piv > T(0))) {
       if (i == k) atomicExch(status, -6);
       piv = T(1);
     }
+    T colk[DB];
+#pragma unroll
+    for (int j = k + 1; j < DB; ++j) colk[j] = bcast(a[j], k);
     const T rs = rsqrt_nr(piv);
     rd[k] = rs;
     const T l = (i > k) ? a[k] * rs : (i == k ? piv * rs : T(0));
     a[k] = l;
-    if (k + 1 < DB) {
-      if (act) colbuf[i] = l;
 #pragma unroll
-      for (int j = k + 1; j < DB; ++j) a[j] -= l * colbuf[j];
-    }
+    for (int j = k + 1; j < DB; ++j) a[j] -= l * (colk[j] * rs);
   }
+  (void)colbuf;
   if (act) {
 #pragma unroll
     for (int j = 0; j < DB; ++j) sC[(o + i) * PS + o + j] = a[j];
