@@ -105,7 +105,7 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     Batch B, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
     const int32_t* __restrict__ nt, const int64_t* __restrict__ off,
     const int64_t* __restrict__ doff, const T* __restrict__ fac, const double* __restrict__ w,
-    double* __restrict__ dbuf) {
+    double* __restrict__ dbuf, const int32_t* __restrict__ active) {
   typedef typename Vec16<T>::type V;
   constexpr int VEC = Vec16<T>::n;          // elements per lane per load
   constexpr int LPR = TS / VEC;             // lanes per tile row
@@ -114,7 +114,9 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   const int b = blockIdx.x;
   const int ntb = nt[b], n = Ni[b];
   const int64_t t0 = ta[b];
-  const GridDesc& g = B.grids[grid_of(B, B.sgid, b)];
+  const int gi = grid_of(B, B.sgid, b);
+  if (active && !act_updating(active[gi])) return;
+  const GridDesc& g = B.grids[gi];
   const int64_t N = g.N;
   const double* __restrict__ wg = w + g.goff;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -228,19 +230,20 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
 template <typename T, int W>
 static void trsv_w(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
                    const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
-                   const double* w, double* dbuf, hipStream_t s) {
+                   const double* w, double* dbuf, const int32_t* active, hipStream_t s) {
   const size_t sh = ((size_t)max_nt * TS + TS + (size_t)W * TS) * sizeof(T);
   hipLaunchKernelGGL((k_schwarz_trsv<T, W>), dim3(B.Ptot), dim3(W * 64), sh, s, B, ta, Ni, nt, off,
-                     doff, fac, w, dbuf);
+                     doff, fac, w, dbuf, active);
 }
 
 template <typename T>
 void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
                          const int64_t* off, const int64_t* doff, int max_nt, int waves,
-                         const T* fac, const double* w, double* dbuf, hipStream_t s) {
-  if (waves <= 4) trsv_w<T, 4>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, s);
-  else if (waves <= 8) trsv_w<T, 8>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, s);
-  else trsv_w<T, 16>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, s);
+                         const T* fac, const double* w, double* dbuf, const int32_t* active,
+                         hipStream_t s) {
+  if (waves <= 4) trsv_w<T, 4>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, active, s);
+  else if (waves <= 8) trsv_w<T, 8>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, active, s);
+  else trsv_w<T, 16>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, active, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,7 +366,8 @@ void launch_gather_local(const Batch& B, int max_nt, const BatchMeta& bm, const 
 #define INST(T)                                                                                    \
   template void launch_schwarz_trsv<T>(const Batch&, const int32_t*, const int32_t*,              \
                                        const int32_t*, const int64_t*, const int64_t*, int, int,   \
-                                       const T*, const double*, double*, hipStream_t);             \
+                                       const T*, const double*, double*, const int32_t*,           \
+                                       hipStream_t);                                               \
   template void launch_symv_tiles<T>(int, int, const BatchMeta&, const T*, const T*, T*,           \
                                      hipStream_t);                                                 \
   template void launch_symv_reduce<T>(int, int, const BatchMeta&, const int32_t*, const int64_t*,  \
@@ -488,14 +492,15 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
 constexpr int TRMV_CH = 8;
 
 // Rows: part[I][c] = sum_{K in chunk c, K <= I} X_IK v_K.
-__global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const double* __restrict__ X,
+__global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
+                                                   const double* __restrict__ X,
                                                    const double* __restrict__ v,
                                                    double* __restrict__ part) {
   const int b = blockIdx.y, ntb = bm.nt[b];
   const int I = blockIdx.x / nchx, c = blockIdx.x % nchx;
   const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
   const int k0 = c * TRMV_CH;
-  if (I >= ntb || c >= nch || k0 > I) return;
+  if (I >= ntb || c >= nch || k0 > I || (active && !act_updating(active[b]))) return;
   const int k1 = min(I + 1, k0 + TRMV_CH);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane >> 5, c0 = (lane & 31) * 2;
@@ -524,14 +529,15 @@ __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const
 }
 
 // Columns: part[K][c] = sum_{I in chunk c of [K, nt)} X_IK^T y_I.
-__global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const double* __restrict__ X,
+__global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
+                                                   const double* __restrict__ X,
                                                    const double* __restrict__ y,
                                                    double* __restrict__ part) {
   const int b = blockIdx.y, ntb = bm.nt[b];
   const int K = blockIdx.x / nchx, c = blockIdx.x % nchx;
   const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
   const int i0 = K + c * TRMV_CH;
-  if (K >= ntb || c >= nch || i0 >= ntb) return;
+  if (K >= ntb || c >= nch || i0 >= ntb || (active && !act_updating(active[b]))) return;
   const int i1 = min(ntb, i0 + TRMV_CH);
   __shared__ double red[4 * TS];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -590,12 +596,12 @@ __global__ __launch_bounds__(TS) void k_trmv_reduce(BatchMeta bm, const int32_t*
 
 void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
                          const int64_t* doff, const double* X, const double* v, double* ytmp,
-                         double* part, double* out, hipStream_t s) {
+                         double* part, double* out, const int32_t* active, hipStream_t s) {
   const int nchx = (max_nt + TRMV_CH - 1) / TRMV_CH;
   const dim3 grid(max_nt * nchx, nb);
-  hipLaunchKernelGGL(k_trmv_rows, grid, dim3(256), 0, s, bm, nchx, X, v, part);
+  hipLaunchKernelGGL(k_trmv_rows, grid, dim3(256), 0, s, bm, nchx, active, X, v, part);
   hipLaunchKernelGGL(k_trmv_reduce<0>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, ytmp);
-  hipLaunchKernelGGL(k_trmv_cols, grid, dim3(256), 0, s, bm, nchx, X, ytmp, part);
+  hipLaunchKernelGGL(k_trmv_cols, grid, dim3(256), 0, s, bm, nchx, active, X, ytmp, part);
   hipLaunchKernelGGL(k_trmv_reduce<1>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, out);
 }
 
@@ -633,7 +639,8 @@ void launch_dot(const Batch& B, const double* a, const double* b, const double* 
 // Second reduction stage plus the scalar recurrences of CG, one block per grid.
 __global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
                                                           const double* __restrict__ partials,
-                                                          double* __restrict__ Sall) {
+                                                          double* __restrict__ Sall,
+                                                          int32_t* __restrict__ active) {
   __shared__ double sh[16];
   const int gi = blockIdx.x;
   const double* pp = partials + (int64_t)gi * B.rbx;
@@ -647,20 +654,38 @@ __global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
   const double r1 = (mode == FIN_RZ_NEXT_FLEX) ? block_sum(s1, sh) : 0.0;
   if (threadIdx.x == 0) {
     double* S = Sall + (int64_t)gi * S_COUNT;
+    const int f = active ? active[gi] : ACT_RUN;
+    const bool upd = act_updating(f);
     switch (mode) {
-      case FIN_PQ_ALPHA: S[S_PQ] = r0; S[S_ALPHA] = S[S_RZ] / r0; break;
+      case FIN_PQ_ALPHA:
+        if (upd) {
+          S[S_PQ] = r0;
+          S[S_ALPHA] = S[S_RZ] / r0;
+          if (active && f == ACT_RESTART) active[gi] = ACT_RUN;
+        }
+        break;
       case FIN_RR: S[S_RR] = r0; break;
-      case FIN_RZ_INIT: S[S_RZ] = r0; break;
-      case FIN_RZ_NEXT: S[S_BETA] = r0 / S[S_RZ]; S[S_RZ] = r0; break;
-      case FIN_RZ_NEXT_FLEX: S[S_BETA] = -S[S_ALPHA] * r1 / S[S_RZ]; S[S_RZ] = r0; break;
+      case FIN_RZ_INIT: if (upd) S[S_RZ] = r0; break;
+      case FIN_RZ_NEXT:
+        if (upd) { S[S_BETA] = r0 / S[S_RZ]; S[S_RZ] = r0; }
+        break;
+      case FIN_RZ_NEXT_FLEX:
+        if (upd) { S[S_BETA] = -S[S_ALPHA] * r1 / S[S_RZ]; S[S_RZ] = r0; }
+        break;
       case FIN_BB: S[S_BB] = r0; break;
+      case FIN_RR_CAND:
+      case FIN_RR_DONE:
+        S[S_RR] = r0;
+        if (active && upd && r0 <= S[S_TOL2]) active[gi] = (mode == FIN_RR_CAND) ? ACT_CAND : ACT_DONE;
+        break;
+      case FIN_TRR: S[S_TRR] = r0; break;
     }
   }
 }
 
 void launch_finalize(const Batch& B, int mode, const double* partials, double* scal,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(B.G), dim3(RED_THREADS), 0, s, B, mode, partials, scal);
+                     int32_t* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(B.G), dim3(RED_THREADS), 0, s, B, mode, partials, scal, active);
 }
 
 // x += alpha_g p, r -= alpha_g q on active grids; per-grid partials of r . r.
@@ -674,7 +699,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_update_xr(Batch B, const double
   __shared__ double sh[16];
   const int gi = blockIdx.y;
   const GridDesc& g = B.grids[gi];
-  const bool act = active[gi] != 0;
+  const bool act = act_updating(active[gi]);
   const double alpha = Sall[(int64_t)gi * S_COUNT + S_ALPHA];
   double acc = 0.0;
   for (int64_t i = g.goff + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.goff + g.N;
@@ -705,8 +730,8 @@ __global__ void k_update_p(Batch B, const double* __restrict__ Sall,
        i += (int64_t)gridDim.x * blockDim.x) {
     const int gi = grid_of(B, B.gid, i);
     const int a = active[gi];
-    if (!a) continue;
-    p[i] = (a == 2) ? z[i] : z[i] + Sall[(int64_t)gi * S_COUNT + S_BETA] * p[i];  // 2: restarted
+    if (a == ACT_RUN) p[i] = z[i] + Sall[(int64_t)gi * S_COUNT + S_BETA] * p[i];
+    else if (a == ACT_RESTART) p[i] = z[i];
   }
 }
 
@@ -722,7 +747,7 @@ __global__ void k_axpy_scal(Batch B, const double* __restrict__ Sall, int slot,
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.Ntot;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int gi = grid_of(B, B.gid, i);
-    if (!active[gi]) continue;
+    if (!act_updating(active[gi])) continue;
     x[i] += Sall[(int64_t)gi * S_COUNT + slot] * z[i];
   }
 }

@@ -106,10 +106,13 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 // per-grid partials of y.y.
 void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
                  const double* b, double* partials, hipStream_t s);
+// active (nullable): per-grid solver flags; subdomains of grids that are not
+// updating (flag not RUN or RESTART) are skipped.
 template <typename T>
 void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
                          const int64_t* off, const int64_t* doff, int max_nt, int waves,
-                         const T* fac, const double* w, double* dbuf, hipStream_t s);
+                         const T* fac, const double* w, double* dbuf, const int32_t* active,
+                         hipStream_t s);
 template <typename T>
 void launch_symv_tiles(int nb, int max_nt, const BatchMeta& bm, const T* M, const T* xloc, T* part,
                        hipStream_t s);
@@ -127,7 +130,7 @@ void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s)
 // partials at bm.poff, out unpadded at doff (n[b] entries).
 void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
                          const int64_t* doff, const double* X, const double* v, double* ytmp,
-                         double* part, double* out, hipStream_t s);
+                         double* part, double* out, const int32_t* active, hipStream_t s);
 void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
                     double* out, hipStream_t s);
 
@@ -135,7 +138,7 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
 void launch_dot(const Batch& B, const double* a, const double* b, const double* c,
                 double* partials, hipStream_t s);
 void launch_finalize(const Batch& B, int mode, const double* partials, double* scal,
-                     hipStream_t s);
+                     int32_t* active, hipStream_t s);
 void launch_update_xr(const Batch& B, const double* scal, const int32_t* active, double* x,
                       double* r, const double* p, const double* q, double* partials,
                       hipStream_t s);
@@ -153,16 +156,30 @@ void launch_zero(int64_t n, double* a, hipStream_t s);
 
 // Scalar slots of the solver's per-grid device scalars S[g * S_COUNT + slot].
 enum {
-  S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZQ, S_BB, S_XI, S_TMP, S_COUNT = 16
+  S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZQ, S_BB, S_XI, S_TMP, S_TOL2, S_TRR,
+  S_COUNT = 16
 };
-// Finalize modes.
+// Per-grid solver flags (device array `active`).
 enum {
-  FIN_PQ_ALPHA = 0,   // S_PQ = sum; S_ALPHA = S_RZ / S_PQ
+  ACT_DONE = 0,      // converged or stopped: no updates
+  ACT_RUN = 1,       // iterating
+  ACT_RESTART = 2,   // iterating, next direction p = z (becomes RUN at the next step size)
+  ACT_CAND = 3,      // recursive residual below tolerance, awaiting the true-residual check
+  ACT_SKIP = 4       // excluded from the current pass
+};
+__host__ __device__ __forceinline__ bool act_updating(int f) { return f == ACT_RUN || f == ACT_RESTART; }
+// Finalize modes.  With a flag array, the CG recurrences (PQ_ALPHA, RZ_*) are
+// applied to updating grids only.
+enum {
+  FIN_PQ_ALPHA = 0,   // S_PQ = sum; S_ALPHA = S_RZ / S_PQ; RESTART -> RUN
   FIN_RR,             // S_RR = sum
   FIN_RZ_INIT,        // S_RZ = sum
   FIN_RZ_NEXT,        // rz = sum; S_BETA = rz / S_RZ; S_RZ = rz
   FIN_RZ_NEXT_FLEX,   // rz = sum0, zq = sum1; S_BETA = -S_ALPHA zq / S_RZ; S_RZ = rz
-  FIN_BB              // S_BB = sum
+  FIN_BB,             // S_BB = sum
+  FIN_RR_CAND,        // S_RR = sum; updating grid with S_RR <= S_TOL2 -> CAND
+  FIN_RR_DONE,        // S_RR = sum; updating grid with S_RR <= S_TOL2 -> DONE
+  FIN_TRR             // S_TRR = sum
 };
 // Combine modes of launch_combine.
 enum {

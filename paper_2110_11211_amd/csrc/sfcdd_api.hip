@@ -95,6 +95,7 @@ struct sfcdd_ctx {
   int32_t *active = nullptr, *status = nullptr;
   double* host_scal = nullptr;  // pinned, G * S_COUNT + G + 256 doubles
   std::vector<int32_t> last_iters;
+  hipEvent_t ev_rb = nullptr;  // readback of the per-iteration scalars
   // host copy of the device activity flags (valid after the first upload)
   std::vector<int32_t> active_shadow;
   bool active_valid = false, active_in_flight = false;
@@ -578,26 +579,26 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
 
 // F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then
 // d0 = A_0^{-1} c0 = X_0^T (X_0 c0) with X_0 = L_0^{-1} (per grid).
-void coarse_solve(sfcdd_ctx* c, const double* v) {
+void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) {
   ProfScope ps(c, SFCDD_K_COARSE);
   const Batch B = c->batch();
   BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
   launch_restrict(B, v, c->c0, c->stream);
   launch_coarse_apply(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart, c->d0,
-                      c->stream);
+                      mask, c->stream);
 }
 
 // Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
-void local_solves(sfcdd_ctx* c, const double* w, int waves) {
+void local_solves(sfcdd_ctx* c, const double* w, int waves, const int32_t* mask = nullptr) {
   const hipStream_t s = c->stream;
   const Batch B = c->batch();
   if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
     if (c->fdtype == SFCDD_FP32)
       launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves,
-                                 (const float*)c->fac, w, c->dbuf, s);
+                                 (const float*)c->fac, w, c->dbuf, mask, s);
     else
       launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves,
-                                  (const double*)c->fac, w, c->dbuf, s);
+                                  (const double*)c->fac, w, c->dbuf, mask, s);
   } else {
     BatchMeta bm{c->d_nt, c->d_off, c->d_xoff, c->d_poff};
     if (c->fdtype == SFCDD_FP32) {
@@ -617,10 +618,10 @@ void local_solves(sfcdd_ctx* c, const double* w, int waves) {
 }
 
 // y = sum_i R_i^T omega_i A_i^{-1} R_i w (eq. w1levprec).
-void fine_apply(sfcdd_ctx* c, const double* w, double* y) {
+void fine_apply(sfcdd_ctx* c, const double* w, double* y, const int32_t* mask = nullptr) {
   {
     ProfScope ps(c, SFCDD_K_LOCAL_SOLVE);
-    local_solves(c, w, c->trsv_waves);
+    local_solves(c, w, c->trsv_waves, mask);
   }
   ProfScope ps(c, SFCDD_K_SCATTER);
   launch_scatter(c->batch(), c->d_ta, c->d_Ni, c->d_doff, c->d_omega, c->dbuf, y, c->stream);
@@ -632,21 +633,23 @@ void spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, d
 }
 
 // h = C^{-1} g in curve order (Alg. 2; balanced form eq. balSW).
-void apply_s(sfcdd_ctx* c, const double* g, double* h) {
+// mask (nullable): solver flags; grids that are not updating may skip the
+// subdomain and coarse solves (their output is then unspecified).
+void apply_s(sfcdd_ctx* c, const double* g, double* h, const int32_t* mask = nullptr) {
   const hipStream_t s = c->stream;
   const Batch B = c->batch();
   if (c->variant == SFCDD_BALANCED) {
     double *t = c->vec[V_T], *w = c->vec[V_W], *y = c->vec[V_Y], *v = c->vec[V_V];
-    coarse_solve(c, g);                                         // d0 = A0^{-1} R0 g
+    coarse_solve(c, g, mask);                                   // d0 = A0^{-1} R0 g
     launch_combine(B, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
     spmv(c, 2, t, w, g, c->partials);                           // w = g - A t = G g
-    fine_apply(c, w, y);                                        // y = C1^{-1} G g
+    fine_apply(c, w, y, mask);                                  // y = C1^{-1} G g
     spmv(c, 0, y, v, nullptr, nullptr);                         // v = A y
-    coarse_solve(c, v);                                         // d0 = A0^{-1} R0 A y
+    coarse_solve(c, v, mask);                                   // d0 = A0^{-1} R0 A y
     launch_combine(B, COMB_BAL_FINAL, c->d0, y, t, h, s);      // h = y - F A y + F g
   } else {
-    coarse_solve(c, g);
-    fine_apply(c, g, h);
+    coarse_solve(c, g, mask);
+    fine_apply(c, g, h, mask);
     launch_combine(B, COMB_ADD_PROLONG, c->d0, h, nullptr, h, s);
   }
 }
@@ -655,12 +658,12 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h) {
 // t = F r and A t of eq. balSW vanish, so h = y - F A y with y = C1^{-1} r.
 // PCG and Richardson keep R_0 r_k = 0 once the start is coarse-corrected,
 // because R_0 A C^{-1} r = R_0 r, so each iteration needs one coarse solve.
-void apply_s_proj(sfcdd_ctx* c, const double* r, double* h) {
+void apply_s_proj(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask = nullptr) {
   const Batch B = c->batch();
   double *y = c->vec[V_Y], *v = c->vec[V_V];
-  fine_apply(c, r, y);                                         // y = C1^{-1} r
+  fine_apply(c, r, y, mask);                                   // y = C1^{-1} r
   spmv(c, 0, y, v, nullptr, nullptr);                          // v = A y
-  coarse_solve(c, v);                                          // d0 = A0^{-1} R0 A y
+  coarse_solve(c, v, mask);                                    // d0 = A0^{-1} R0 A y
   launch_combine(B, COMB_SUB_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y - F A y
 }
 
@@ -901,6 +904,12 @@ sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev
     delete c;
     return SFCDD_EDEVICE;
   }
+  if (hipEventCreateWithFlags(&c->ev_rb, hipEventDisableTiming) != hipSuccess) {
+    g_last_error = "hipEventCreate failed";
+    (void)hipHostFree(c->host_scal);
+    delete c;
+    return SFCDD_EDEVICE;
+  }
   *out = c;
   return setup_device(c);
 }
@@ -976,9 +985,11 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     FAIL(c, SFCDD_EINVAL, "method = %d", method);
   // balanced form: coarse-corrected start, then one coarse solve per iteration
   const bool proj = c->variant == SFCDD_BALANCED && !plain;
+  // preconditioner inside the iteration: grids that are not updating skip
+  // their subdomain and coarse solves
   auto precond = [&](const double* g, double* h) {
-    if (proj) apply_s_proj(c, g, h);
-    else apply_s(c, g, h);
+    if (proj) apply_s_proj(c, g, h, c->active);
+    else apply_s(c, g, h, c->active);
   };
   const hipStream_t s = c->stream;
   const int64_t N = c->Ntot;
@@ -1000,7 +1011,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     launch_combine(B, COMB_ADD_PROLONG, c->d0, x, nullptr, x, s);
   }
   launch_dot(B, b, b, nullptr, c->partials, s);
-  launch_finalize(B, FIN_BB, c->partials, c->scal, s);
+  launch_finalize(B, FIN_BB, c->partials, c->scal, nullptr, s);
   sfcdd_status st;
   if ((st = read_scal(c))) return st;
   std::vector<double> tol2(G), bb(G), rr(G, 0.0);
@@ -1008,17 +1019,40 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     bb[g] = hs(c, g, S_BB);
     tol2[g] = rtol * rtol * bb[g];
   }
-  std::vector<int32_t> act(G, 1), its(G, 0);
+  std::vector<int32_t> flags(G, ACT_RUN), its(G, 0);
   sfcdd_solve_info inf{};
   int it = 0, restarts = 0;
-  auto n_active = [&]() {
+  auto n_updating = [&]() {
     int n = 0;
-    for (int g = 0; g < G; ++g) n += act[g] != 0;
+    for (int g = 0; g < G; ++g) n += act_updating(flags[g]);
     return n;
   };
   auto read_rr = [&]() -> sfcdd_status {
     sfcdd_status e = read_scal(c);
     if (e) return e;
+    for (int g = 0; g < G; ++g) rr[g] = hs(c, g, S_RR);
+    return SFCDD_OK;
+  };
+  // per-grid scalars written by the host (tolerances, Richardson damping):
+  // read-modify-write of the device scalar array, which read_scal just copied
+  auto upload_scal = [&]() -> sfcdd_status {
+    HIPCHK(c, hipMemcpyAsync(c->scal, c->host_scal, sizeof(double) * G * S_COUNT, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return SFCDD_OK;
+  };
+  // Asynchronous copy of the residual norms and flags of the step just
+  // enqueued; the host waits for it while the next preconditioner
+  // application (enqueued speculatively) runs.
+  int32_t* hflags = reinterpret_cast<int32_t*>(c->host_scal + (size_t)G * S_COUNT) + G;
+  auto enqueue_readback = [&]() -> sfcdd_status {
+    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * G * S_COUNT, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hflags, c->active, 4 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(c->ev_rb, s));
+    return SFCDD_OK;
+  };
+  auto wait_readback = [&]() -> sfcdd_status {
+    HIPCHK(c, hipEventSynchronize(c->ev_rb));
+    c->active_in_flight = false;
     for (int g = 0; g < G; ++g) rr[g] = hs(c, g, S_RR);
     return SFCDD_OK;
   };
@@ -1028,36 +1062,37 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     if (!(xi > 0.0)) {
       // Lanczos estimate of the extreme eigenvalues of C^{-1}A from CG steps (per grid)
       std::vector<std::vector<double>> al(G), be(G);
-      std::vector<int32_t> ok(G, 1);
+      std::vector<int32_t> ok(G, ACT_RUN);
       if ((st = write_active(c, ok))) return st;
       launch_zero(N, z, s);  // z is the iterate of the estimation run (on the residual of x)
       spmv(c, 2, x, r, b, c->partials);
       precond(r, q);
       launch_copy(N, q, p, s);
       launch_dot(B, r, q, nullptr, c->partials, s);
-      launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, s);
+      launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, c->active, s);
       for (int k = 0; k < 30; ++k) {
         spmv(c, 1, p, tmp, nullptr, c->partials);
-        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, s);
+        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s);
         launch_update_xr(B, c->scal, c->active, z, r, p, tmp, c->partials, s);
         if ((st = read_scal(c))) return st;
         for (int g = 0; g < G; ++g) {
           const double a_k = hs(c, g, S_ALPHA);
           if (ok[g] && a_k > 0.0 && std::isfinite(a_k)) al[g].push_back(a_k);
-          else ok[g] = 0;
+          else ok[g] = ACT_DONE;
         }
+        if ((st = write_active(c, ok))) return st;
         precond(r, q);
         launch_dot(B, r, q, nullptr, c->partials, s);
-        launch_finalize(B, FIN_RZ_NEXT, c->partials, c->scal, s);
+        launch_finalize(B, FIN_RZ_NEXT, c->partials, c->scal, c->active, s);
         if ((st = read_scal(c))) return st;
         for (int g = 0; g < G; ++g) {
           const double b_k = hs(c, g, S_BETA);
           if (ok[g] && b_k > 0.0 && std::isfinite(b_k)) be[g].push_back(b_k);
-          else ok[g] = 0;
+          else ok[g] = ACT_DONE;
         }
         if ((st = write_active(c, ok))) return st;
         int nok = 0;
-        for (int g = 0; g < G; ++g) nok += ok[g];
+        for (int g = 0; g < G; ++g) nok += ok[g] != ACT_DONE;
         if (nok == 0) break;
         launch_update_p(B, c->scal, c->active, p, q, s);
       }
@@ -1077,81 +1112,119 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       }
     }
     inf.xi = xig[0];
-    // damping per grid into S_XI (read-modify-write of the scalar array)
-    if ((st = read_scal(c))) return st;
-    for (int g = 0; g < G; ++g) c->host_scal[(size_t)g * S_COUNT + S_XI] = xig[g];
-    HIPCHK(c, hipMemcpyAsync(c->scal, c->host_scal, sizeof(double) * G * S_COUNT,
-                             hipMemcpyHostToDevice, s));
-    std::fill(act.begin(), act.end(), 1);
-    for (;;) {
-      spmv(c, 2, x, r, b, c->partials);
-      launch_finalize(B, FIN_RR, c->partials, c->scal, s);
-      if ((st = read_rr())) return st;
-      for (int g = 0; g < G; ++g)
-        if (act[g] && rr[g] <= tol2[g]) act[g] = 0;
-      if (n_active() == 0 || it >= max_iter) break;
-      if ((st = write_active(c, act))) return st;
+    // r = b - A x and its norm; damping and tolerances to the device
+    spmv(c, 2, x, r, b, c->partials);
+    launch_finalize(B, FIN_RR, c->partials, c->scal, nullptr, s);
+    if ((st = read_rr())) return st;
+    for (int g = 0; g < G; ++g) {
+      c->host_scal[(size_t)g * S_COUNT + S_XI] = xig[g];
+      c->host_scal[(size_t)g * S_COUNT + S_TOL2] = tol2[g];
+      flags[g] = rr[g] <= tol2[g] ? ACT_DONE : ACT_RUN;
+    }
+    if ((st = upload_scal())) return st;
+    if ((st = write_active(c, flags))) return st;
+    if (n_updating() > 0 && max_iter > 0) {
       precond(r, z);
-      launch_axpy_scal(B, c->scal, S_XI, c->active, x, z, s);
-      ++it;
-      for (int g = 0; g < G; ++g) its[g] += act[g] != 0;
+      for (;;) {
+        // x += xi C^{-1} r; r = b - A x; a grid below tolerance stops (DONE)
+        const std::vector<int32_t> before = flags;
+        launch_axpy_scal(B, c->scal, S_XI, c->active, x, z, s);
+        spmv(c, 2, x, r, b, c->partials);
+        launch_finalize(B, FIN_RR_DONE, c->partials, c->scal, c->active, s);
+        if ((st = enqueue_readback())) return st;
+        ++it;
+        if (it < max_iter) precond(r, z);  // next iteration's, speculatively
+        if ((st = wait_readback())) return st;
+        for (int g = 0; g < G; ++g) {
+          its[g] += act_updating(before[g]);
+          flags[g] = hflags[g];
+        }
+        c->active_shadow = flags;
+        if (n_updating() == 0 || it >= max_iter) break;
+      }
     }
   } else {
     const bool flex = method == SFCDD_FCG;
-    // r = b - A x, z = C^{-1} r, p = z
+    const int fin_rz = flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT;
+    // r = b - A x
     spmv(c, 2, x, r, b, c->partials);
-    launch_finalize(B, FIN_RR, c->partials, c->scal, s);
+    launch_finalize(B, FIN_RR, c->partials, c->scal, nullptr, s);
     if ((st = read_rr())) return st;
-    for (int g = 0; g < G; ++g)
-      if (rr[g] <= tol2[g]) act[g] = 0;
-    if (n_active() > 0 && max_iter > 0) {
-      if ((st = write_active(c, act))) return st;
+    for (int g = 0; g < G; ++g) {
+      c->host_scal[(size_t)g * S_COUNT + S_TOL2] = tol2[g];
+      flags[g] = rr[g] <= tol2[g] ? ACT_DONE : ACT_RUN;
+    }
+    if (n_updating() > 0 && max_iter > 0) {
+      if ((st = upload_scal())) return st;
+      if ((st = write_active(c, flags))) return st;
+      // z = C^{-1} r, p = z
       precond(r, z);
       launch_dot(B, r, z, nullptr, c->partials, s);
-      launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, s);
+      launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, c->active, s);
       launch_copy(N, z, p, s);
-      while (true) {
+      for (;;) {
+        // step: x += alpha p, r -= alpha q; a grid whose recursive residual is
+        // below tolerance is frozen (CAND) until its true residual is checked
+        const std::vector<int32_t> before = flags;
         spmv(c, 1, p, q, nullptr, c->partials);
-        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, s);
+        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s);
         launch_update_xr(B, c->scal, c->active, x, r, p, q, c->partials, s);
-        launch_finalize(B, FIN_RR, c->partials, c->scal, s);
+        launch_finalize(B, FIN_RR_CAND, c->partials, c->scal, c->active, s);
+        if ((st = enqueue_readback())) return st;
         ++it;
-        for (int g = 0; g < G; ++g) its[g] += act[g] != 0;
-        if ((st = read_rr())) return st;
+        if (it < max_iter) {
+          // next direction, enqueued before the host has seen the residuals
+          precond(r, z);
+          launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
+          launch_finalize(B, fin_rz, c->partials, c->scal, c->active, s);
+          launch_update_p(B, c->scal, c->active, p, z, s);
+        }
+        if ((st = wait_readback())) return st;
         bool check = false;
         for (int g = 0; g < G; ++g) {
-          if (!act[g]) continue;
-          if (!std::isfinite(rr[g])) FAIL(c, SFCDD_ENOTCONV, "residual of grid %d is not finite", g);
-          if (rr[g] <= tol2[g] || it >= max_iter) check = true;
+          its[g] += act_updating(before[g]);
+          flags[g] = hflags[g];
+          if (!std::isfinite(rr[g]) && act_updating(before[g]))
+            FAIL(c, SFCDD_ENOTCONV, "residual of grid %d is not finite", g);
+          if (flags[g] == ACT_CAND || (it >= max_iter && act_updating(flags[g]))) check = true;
         }
+        c->active_shadow = flags;
         if (check) {
           // confirm on the true residual; a grid whose true residual is still
           // too large restarts from its current x (residual replacement)
           spmv(c, 2, x, tmp, b, c->partials);
-          launch_finalize(B, FIN_RR, c->partials, c->scal, s);
-          std::vector<double> rec = rr;
-          if ((st = read_rr())) return st;
+          launch_finalize(B, FIN_TRR, c->partials, c->scal, nullptr, s);
+          if ((st = read_scal(c))) return st;
+          std::vector<int32_t> pass(G, ACT_SKIP);
+          bool any_restart = false;
           for (int g = 0; g < G; ++g) {
-            if (!act[g]) continue;
-            if (rr[g] <= tol2[g]) {
-              act[g] = 0;
-            } else if (rec[g] <= tol2[g] && it < max_iter && restarts < 8 * G) {
+            if (flags[g] != ACT_CAND && !(it >= max_iter && act_updating(flags[g]))) continue;
+            const double trr = hs(c, g, S_TRR);
+            rr[g] = trr;
+            if (trr <= tol2[g]) {
+              flags[g] = ACT_DONE;
+            } else if (flags[g] == ACT_CAND && it < max_iter && restarts < 8 * G) {
               const GridDesc& gd = c->grid[g].desc;
               launch_copy(gd.N, tmp + gd.goff, r + gd.goff, s);
-              act[g] = 2;  // p = z at the next direction update
+              flags[g] = ACT_RESTART;
+              pass[g] = ACT_RESTART;
+              any_restart = true;
               ++restarts;
+            } else {
+              flags[g] = ACT_DONE;  // max_iter reached
             }
           }
-          if (it >= max_iter) break;
+          if (any_restart) {
+            // z = C^{-1} r and p = z for the restarted grids only
+            if ((st = write_active(c, pass))) return st;
+            precond(r, z);
+            launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
+            launch_finalize(B, fin_rz, c->partials, c->scal, c->active, s);
+            launch_update_p(B, c->scal, c->active, p, z, s);
+          }
+          if ((st = write_active(c, flags))) return st;
         }
-        if (n_active() == 0) break;
-        if ((st = write_active(c, act))) return st;
-        precond(r, z);
-        launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
-        launch_finalize(B, flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT, c->partials, c->scal, s);
-        launch_update_p(B, c->scal, c->active, p, z, s);
-        for (int g = 0; g < G; ++g)
-          if (act[g] == 2) act[g] = 1;
+        if (n_updating() == 0 || it >= max_iter) break;
       }
     }
   }
@@ -1315,6 +1388,7 @@ sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (!c) return SFCDD_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
+  if (c->ev_rb) (void)hipEventDestroy(c->ev_rb);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
