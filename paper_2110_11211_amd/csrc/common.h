@@ -53,12 +53,22 @@ __device__ __host__ __forceinline__ int64_t tri_index(int I, int J) {
   return (int64_t)I * (I + 1) / 2 + J;
 }
 
-// Copies a row-major TS x TS tile from global memory into LDS (stride LDS_S).
+// Row stride (elements) of the tiles staged in LDS for the MFMA tile
+// products: 16-byte aligned rows, consecutive rows 16 bytes apart in the bank
+// space (68 floats, 66 doubles).
+template <typename T> struct LdsV { static constexpr int v = TS + 16 / (int)sizeof(T); };
+
+// Copies a row-major TS x TS tile from global memory into LDS (stride
+// LdsV), as is or transposed.
 template <typename T>
 __device__ __forceinline__ void stage_tile(T* __restrict__ lds, const T* __restrict__ g) {
-  for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
-    lds[(e / TS) * LDS_S + (e % TS)] = g[e];
-  }
+  constexpr int S = LdsV<T>::v;
+  for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) lds[(e / TS) * S + (e % TS)] = g[e];
+}
+template <typename T>
+__device__ __forceinline__ void stage_tile_t(T* __restrict__ lds, const T* __restrict__ g) {
+  constexpr int S = LdsV<T>::v;
+  for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) lds[(e % TS) * S + (e / TS)] = g[e];
 }
 
 // One row-major TS x TS tile held in registers across the workgroup (16-byte
@@ -74,13 +84,24 @@ template <typename T> struct TileRegs {
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = gv[threadIdx.x + q * TILE_THREADS];
   }
+  // as is (16-byte stores)
   __device__ __forceinline__ void store_lds(T* __restrict__ lds) const {
+    constexpr int S = LdsV<T>::v;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int e = (threadIdx.x + q * TILE_THREADS) * VEC;
-      T* dst = lds + (e / TS) * LDS_S + (e % TS);
+      *reinterpret_cast<V*>(lds + (e / TS) * S + (e % TS)) = v[q];
+    }
+  }
+  // transposed: LDS row c holds global column c
+  __device__ __forceinline__ void store_lds_t(T* __restrict__ lds) const {
+    constexpr int S = LdsV<T>::v;
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) dst[c] = v[q][c];
+    for (int q = 0; q < NV; ++q) {
+      const int e = (threadIdx.x + q * TILE_THREADS) * VEC;
+      const int r = e / TS, c0 = e % TS;
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) lds[(c0 + u) * S + r] = v[q][u];
     }
   }
 };
@@ -118,36 +139,55 @@ template <typename T> struct TileAcc {
       for (int b = 0; b < 2; ++b)
         for (int r = 0; r < 4; ++r) g[row(a, r) * TS + col(b)] = c[a][b][r];
   }
-  __device__ __forceinline__ void store_lds(T* __restrict__ s) const {
+  __device__ __forceinline__ void store_lds(T* __restrict__ s) const {  // row-major, stride LdsV
+    constexpr int S = LdsV<T>::v;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b)
-        for (int r = 0; r < 4; ++r) s[row(a, r) * LDS_S + col(b)] = c[a][b][r];
+        for (int r = 0; r < 4; ++r) s[row(a, r) * S + col(b)] = c[a][b][r];
   }
 };
 
-// acc += sign * opA(A) * opB(B) for LDS tiles A, B (stride LDS_S).
-// TA: A is read transposed (math A[i][k] = sA[k][i]); TB: B is read
-// transposed (math B[k][j] = sB[j][k]).
-template <typename T, bool TA, bool TB>
+// acc += sign * A Bt^T for LDS tiles sA[i][k] and sBt[j][k] (both
+// k-contiguous, stride LdsV).  Lane (li, lk) reads four consecutive k of its
+// rows with one vector load and feeds them to four MFMA steps: in group t,
+// step u, lane group lk covers k = 16 t + 4 lk + u, the same k for A and B,
+// so every k in 0..TS-1 is summed exactly once.
+// Four consecutive elements from a 16-byte aligned LDS address (16-byte loads).
+__device__ __forceinline__ void load4(float (&d)[4], const float* p) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+}
+__device__ __forceinline__ void load4(double (&d)[4], const double* p) {
+  const double2 v0 = *reinterpret_cast<const double2*>(p);
+  const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+  d[0] = v0.x; d[1] = v0.y; d[2] = v1.x; d[3] = v1.y;
+}
+
+template <typename T>
 __device__ __forceinline__ void tile_mma(TileAcc<T>& acc, const T* __restrict__ sA,
-                                         const T* __restrict__ sB, T sign) {
+                                         const T* __restrict__ sBt, T sign) {
+  constexpr int S = LdsV<T>::v;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int i0 = 32 * (w >> 1), j0 = 32 * (w & 1);
   const int li = l & 15, lk = l >> 4;
-#pragma unroll 4
-  for (int k0 = 0; k0 < TS; k0 += 4) {
-    const int k = k0 + lk;
-    T a[2], b[2];
+#pragma unroll
+  for (int t = 0; t < TS / 16; ++t) {
+    const int kb = 16 * t + 4 * lk;
+    T a[2][4], b[2][4];
+#pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const int i = i0 + 16 * m + li;
-      a[m] = sign * (TA ? sA[k * LDS_S + i] : sA[i * LDS_S + k]);
+      load4(a[m], sA + (i0 + 16 * m + li) * S + kb);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[m][u] *= sign;
     }
-    for (int n = 0; n < 2; ++n) {
-      const int j = j0 + 16 * n + li;
-      b[n] = TB ? sB[j * LDS_S + k] : sB[k * LDS_S + j];
-    }
-    for (int m = 0; m < 2; ++m)
-      for (int n = 0; n < 2; ++n) acc.c[m][n] = mfma16(a[m], b[n], acc.c[m][n]);
+#pragma unroll
+    for (int n = 0; n < 2; ++n) load4(b[n], sBt + (j0 + 16 * n + li) * S + kb);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc.c[m][n] = mfma16(a[m][u], b[n][u], acc.c[m][n]);
   }
 }
 

@@ -244,7 +244,7 @@ __device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict
 }
 
 // LDS of the diagonal kernel: two Pstride tiles (C, X), the DB x DB block
-// inverses, NDB - 1 scratch blocks and a column buffer.  The GEMM staging (two LDS_S tiles) fits in
+// inverses, NDB - 1 scratch blocks and a column buffer.  The GEMM staging (LdsV tiles, the same size) fits in
 // the same space.
 template <typename T>
 constexpr size_t diag_lds_bytes() {
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
     ra.store_lds(sA);
     __syncthreads();
     if (K + 1 < J) ra.load(F + tri_index(J, K + 1) * TS2);
-    tile_mma<T, false, true>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
+    tile_mma<T>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
   }
   __syncthreads();
   constexpr int PS = Pstride<T>::v;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
 // Sub-diagonal tile (I, J): A_IJ - sum_{K<J} L_IK L_JK^T (terms K >= kfrom
 // here, the others from nparts partial tiles), times L_JJ^{-T}.
 template <typename T>
-__device__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const T* __restrict__ part,
+__device__ __forceinline__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const T* __restrict__ part,
                            T* __restrict__ F, T* sA, T* sB) {
   TileAcc<T> acc;
   acc.load(F + tri_index(I, J) * TS2);
@@ -317,7 +317,7 @@ __device__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const 
       ra.load(F + tri_index(I, K + 1) * TS2);
       rb.load(F + tri_index(J, K + 1) * TS2);
     }
-    tile_mma<T, false, true>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+    tile_mma<T>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
   }
   __syncthreads();
   acc.store_lds(sA);
@@ -325,13 +325,13 @@ __device__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const 
   __syncthreads();
   TileAcc<T> out;
   out.zero();
-  tile_mma<T, false, true>(out, sA, sB, T(1));     // L_IJ = A_IJ L_JJ^{-T}
+  tile_mma<T>(out, sA, sB, T(1));     // L_IJ = A_IJ L_JJ^{-T}
   out.store(F + tri_index(I, J) * TS2);
 }
 
 // Partial update of column Jn: part[I][c] = sum_{K = k0}^{k1 - 1} L_IK L_JnK^T.
 template <typename T>
-__device__ void partial_tile(int Jn, int I, int c, int k0, int k1, int maxc, const T* __restrict__ F,
+__device__ __forceinline__ void partial_tile(int Jn, int I, int c, int k0, int k1, int maxc, const T* __restrict__ F,
                              T* __restrict__ part, T* sA, T* sB) {
   TileAcc<T> acc;
   acc.zero();
@@ -347,7 +347,7 @@ __device__ void partial_tile(int Jn, int I, int c, int k0, int k1, int maxc, con
       ra.load(F + tri_index(I, K + 1) * TS2);
       rb.load(F + tri_index(Jn, K + 1) * TS2);
     }
-    tile_mma<T, false, true>(acc, sA, sB, T(1));
+    tile_mma<T>(acc, sA, sB, T(1));
   }
   acc.store(part + ((int64_t)I * maxc + c) * TS2);
 }
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int kfrom, 
   if (I >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
+  T* sB = sA + TS * LdsV<T>::v;
   panel_tile<T>(J, I, kfrom, nparts, maxc, part, fac + off[b] * TS2, sA, sB);
 }
 
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, in
   if (m <= 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
+  T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[0] * TS2;
   const int x = blockIdx.x;
   if (x < m * nc_out) {
@@ -420,7 +420,7 @@ template <typename T>
 void launch_potrf_panel(int J, int kfrom, int nparts, int maxc, const T* part, int nb, int max_nt,
                         const int32_t* nt, const int64_t* off, T* fac, hipStream_t s) {
   if (max_nt - 1 - J <= 0) return;
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_potrf_panel<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, kfrom,
@@ -432,7 +432,7 @@ void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
   const int nc_out = (J + SPLITK - 1) / SPLITK;
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_step<T>, dim3(m * nc_out + m), dim3(TILE_THREADS), sh, s, J, maxc,
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_col(int J, const int32_t
   if (I >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
+  T* sB = sA + TS * LdsV<T>::v;
   const T* Lb = L + off[b] * TS2;
   T* Xb = X + off[b] * TS2;
   if (I == J) {
@@ -470,28 +470,28 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_col(int J, const int32_t
   for (int K = J + 1; K <= I; ++K) {
     __syncthreads();
     ra.store_lds(sA);
-    rb.store_lds(sB);
+    rb.store_lds_t(sB);
     __syncthreads();
     if (K + 1 <= I) {
       ra.load(Xb + tri_index(I, K + 1) * TS2);
       rb.load(Lb + tri_index(K + 1, J) * TS2);
     }
-    tile_mma<T, false, false>(acc, sA, sB, T(1));
+    tile_mma<T>(acc, sA, sB, T(1));                // acc += X_IK L_KJ
   }
   __syncthreads();
   acc.store_lds(sA);
-  stage_tile(sB, Lb + tri_index(J, J) * TS2);
+  stage_tile_t(sB, Lb + tri_index(J, J) * TS2);
   __syncthreads();
   TileAcc<T> out;
   out.zero();
-  tile_mma<T, false, false>(out, sA, sB, T(-1));
+  tile_mma<T>(out, sA, sB, T(-1));                 // X_IJ = -acc L_JJ^{-1}
   out.store(Xb + tri_index(I, J) * TS2);
 }
 
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s) {
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_trtri_col<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_trtri_col<T>, dim3(max_nt - J, nb), dim3(TILE_THREADS), sh, s, J, nt, off, L,
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32
   if (i >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
+  T* sB = sA + TS * LdsV<T>::v;
   const T* Lb = L + off[b] * TS2;
   const T* Xb = X + off[b] * TS2;
   TileAcc<T> acc;
@@ -548,13 +548,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32
   for (int k = j; k < B0; ++k) {
     __syncthreads();
     ra.store_lds(sA);
-    rb.store_lds(sB);
+    rb.store_lds_t(sB);
     __syncthreads();
     if (k + 1 < B0) {
       ra.load(Lb + tri_index(i, k + 1) * TS2);
       rb.load(Xb + tri_index(k + 1, j) * TS2);
     }
-    tile_mma<T, false, false>(acc, sA, sB, T(1));
+    tile_mma<T>(acc, sA, sB, T(1));                // T_ij += L_ik X_kj
   }
   acc.store(Tb + (toff[b] + (int64_t)p * s * s + (int64_t)ii * s + jj) * TS2);
 }
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
   if (i >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
+  T* sB = sA + TS * LdsV<T>::v;
   T* Xb = X + off[b] * TS2;
   const T* Tp = Tb + (toff[b] + (int64_t)p * s * s + jj) * TS2;  // T_kj at Tp + (k - B0) s TS2
   TileAcc<T> acc;
@@ -585,13 +585,13 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
   for (int k = B0; k <= i; ++k) {
     __syncthreads();
     ra.store_lds(sA);
-    rb.store_lds(sB);
+    rb.store_lds_t(sB);
     __syncthreads();
     if (k + 1 <= i) {
       ra.load(Xb + tri_index(i, k + 1) * TS2);
       rb.load(Tp + (int64_t)(k + 1 - B0) * s * TS2);
     }
-    tile_mma<T, false, false>(acc, sA, sB, T(-1));
+    tile_mma<T>(acc, sA, sB, T(-1));               // X_ij -= X_ik T_kj
   }
   acc.store(Xb + tri_index(i, j) * TS2);
 }
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
 template <typename T>
 void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
                       const T* L, T* X, T* Tb, hipStream_t st) {
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_trtri_rec_t<T>, sh), allow_lds(k_trtri_rec_x<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_trtri_diag_copy<T>, dim3(max_nt, nb), dim3(TILE_THREADS), 0, st, nt, off, L, X);
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restric
   const int J = (int)(t - (int64_t)I * (I + 1) / 2);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LDS_S;
+  T* sB = sA + TS * LdsV<T>::v;
   const T* Xb = X + off[b] * TS2;
   TileAcc<T> acc;
   acc.zero();
@@ -637,14 +637,14 @@ __global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restric
   rb.load(Xb + tri_index(I, J) * TS2);
   for (int K = I; K < ntb; ++K) {
     __syncthreads();
-    ra.store_lds(sA);
-    rb.store_lds(sB);
+    ra.store_lds_t(sA);
+    rb.store_lds_t(sB);
     __syncthreads();
     if (K + 1 < ntb) {
       ra.load(Xb + tri_index(K + 1, I) * TS2);
       rb.load(Xb + tri_index(K + 1, J) * TS2);
     }
-    tile_mma<T, true, false>(acc, sA, sB, T(1));
+    tile_mma<T>(acc, sA, sB, T(1));                // M_IJ += X_KI^T X_KJ
   }
   acc.store(M + off[b] * TS2 + tri_index(I, J) * TS2);
 }
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restric
 template <typename T>
 void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* X, T* M,
                   hipStream_t s) {
-  const size_t sh = 2 * TS * LDS_S * sizeof(T);
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_lauum<T>, sh), true);
   (void)once;
   const int ntiles = max_nt * (max_nt + 1) / 2;

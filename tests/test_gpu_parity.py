@@ -306,7 +306,10 @@ def test_batch_ct_layer_84_grids(fdtype, method):
     for g in range(len(w.levels)):
         ref = exact.solve(Grid(levels=w.levels[g]), w.rhs(g))
         assert relerr(xs[g], ref) <= 1e-9, g
+    # A single grid factors its coarse matrix with the split-K schedule, a
+    # batch with the batched one: the coarse factors round differently, which
+    # can move the step that crosses rtol = 1e-12 by one.
     for g in (0, 41, 83):
         Sg = _solver(w.levels[g], w.P, w.gamma, factor_dtype=fdtype)
         _, ig = Sg.solve(dvec(w.rhs(g)), rtol=1e-12, method=method, max_iter=400)
-        assert abs(ig["iterations"] - its[g]) <= (0 if fdtype == "fp64" else 2), g
+        assert abs(ig["iterations"] - its[g]) <= (1 if fdtype == "fp64" else 2), g
