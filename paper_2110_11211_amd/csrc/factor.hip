@@ -255,17 +255,10 @@ constexpr size_t diag_lds_bytes() {
 // K = kfrom .. J-1 are formed in this workgroup; the terms K < kfrom (single
 // matrix, split-K) were precomputed as nparts partial tiles part[I][c].
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, int nparts, int maxc,
-                                                             const T* __restrict__ part,
-                                                             const int32_t* __restrict__ nt,
-                                                             const int64_t* __restrict__ off,
-                                                             T* __restrict__ fac,
-                                                             int32_t* __restrict__ status) {
-  const int b = blockIdx.x;
-  if (J >= nt[b]) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc, const T* __restrict__ part,
+                                          T* __restrict__ F, int32_t* __restrict__ status,
+                                          unsigned char* smem_raw) {
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* F = fac + off[b] * TS2;
   TileAcc<T> acc;
   acc.load(F + tri_index(J, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
@@ -293,6 +286,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
     const int i = e / TS, j = e % TS;
     D[e] = j <= i ? sX[i * PS + j] : T(0);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, int nparts, int maxc,
+                                                             const T* __restrict__ part,
+                                                             const int32_t* __restrict__ nt,
+                                                             const int64_t* __restrict__ off,
+                                                             T* __restrict__ fac,
+                                                             int32_t* __restrict__ status) {
+  const int b = blockIdx.x;
+  if (J >= nt[b]) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  diag_tile<T>(J, kfrom, nparts, maxc, part, fac + off[b] * TS2, status, smem_raw);
 }
 
 // Sub-diagonal tile (I, J): A_IJ - sum_{K<J} L_IK L_JK^T (terms K >= kfrom
@@ -367,6 +373,31 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int kfrom, 
   panel_tile<T>(J, I, kfrom, nparts, maxc, part, fac + off[b] * TS2, sA, sB);
 }
 
+// Whole left-looking factorisation of one matrix per workgroup (batches of
+// many small matrices): column by column, the diagonal tile and then the
+// sub-diagonal tiles, all in this workgroup.  Tiles written here are read
+// back in later columns only by this workgroup, whose waves share one CU and
+// its vector L1: the workgroup-scope release/acquire of the barrier makes the
+// stores visible.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __restrict__ nt,
+                                                             const int64_t* __restrict__ off,
+                                                             T* __restrict__ fac,
+                                                             int32_t* __restrict__ status) {
+  const int b = blockIdx.x;
+  const int ntb = nt[b];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LdsV<T>::v;
+  T* F = fac + off[b] * TS2;
+  for (int J = 0; J < ntb; ++J) {
+    diag_tile<T>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
+    __syncthreads();
+    for (int I = J + 1; I < ntb; ++I) panel_tile<T>(J, I, 0, 0, 0, (const T*)nullptr, F, sA, sB);
+    __syncthreads();
+  }
+}
+
 // One matrix (batch of one), look-ahead step after the diagonal tile of
 // column J: the first workgroups form the split-K partial update of column
 // J + 1 from columns K < J (part_out[I][c], I > J, chunks of SPLITK columns),
@@ -425,6 +456,14 @@ void launch_potrf_panel(int J, int kfrom, int nparts, int maxc, const T* part, i
   (void)once;
   hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, kfrom,
                      nparts, maxc, part, nt, off, fac);
+}
+template <typename T>
+void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
+                       hipStream_t s) {
+  const size_t sh = diag_lds_bytes<T>();
+  static bool once = (allow_lds(k_potrf_full<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_potrf_full<T>, dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
 }
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part_in, T* part_out,
@@ -664,6 +703,8 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
   template void launch_potrf_panel<T>(int, int, int, int, const T*, int, int, const int32_t*,      \
                                       const int64_t*, T*, hipStream_t);                            \
+  template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*,            \
+                                     hipStream_t);                                                 \
   template void launch_potrf_step<T>(int, int, int, int, const T*, T*, const int32_t*,             \
                                      const int64_t*, T*, hipStream_t);                             \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \

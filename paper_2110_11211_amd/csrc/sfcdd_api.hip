@@ -553,18 +553,18 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
                   const int64_t* toff, hipStream_t s) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   const int64_t half = (int64_t)max_nt * maxc * TS2;
-  for (int J = 0; J < max_nt; ++J) {
-    if (part) {
-      // one matrix: split-K partials of columns K < J - 1 (double-buffered),
-      // computed by the previous step concurrently with its panel
+  if (!part) {
+    // batch: one workgroup factors a whole matrix
+    launch_potrf_full<T>(nb, nt, off, fac, status, s);
+  } else {
+    // one matrix: split-K partials of columns K < J - 1 (double-buffered),
+    // computed by the previous step concurrently with its panel
+    for (int J = 0; J < max_nt; ++J) {
       const int np = J > 1 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
       T* pin = part + (J & 1) * half;
       T* pout = part + ((J + 1) & 1) * half;
       launch_potrf_diag<T>(J, J > 0 ? J - 1 : 0, np, maxc, pin, 1, nt, off, fac, status, s);
       launch_potrf_step<T>(J, max_nt, maxc, np, pin, pout, nt, off, fac, s);
-    } else {
-      launch_potrf_diag<T>(J, 0, 0, 0, (const T*)nullptr, nb, nt, off, fac, status, s);
-      launch_potrf_panel<T>(J, 0, 0, 0, (const T*)nullptr, nb, max_nt, nt, off, fac, s);
     }
   }
   if (invert) {
