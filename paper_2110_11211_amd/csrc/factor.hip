@@ -1,10 +1,13 @@
 // Batched dense Cholesky factorisation of the subdomain matrices and of the
 // coarse matrix (factor once, Sec. 3.1), on packed lower 64x64 tiles with
-// MFMA tile products.  Left-looking over tile columns J: one launch factors
-// the diagonal tiles (J, J) of every matrix of the batch, a second one
-// finishes the sub-diagonal tiles (I, J), I > J.  The diagonal tiles keep the
-// INVERSE of the diagonal Cholesky block, L_JJ^{-1}, so that both the panel
-// update and the substitution sweeps are tile products.
+// MFMA tile products, left-looking over tile columns J.  A batch of matrices
+// is factored by one persistent workgroup per matrix; a single large matrix
+// by two launches per column (the diagonal tile, then its sub-diagonal tiles
+// beside the split-K partial update of the next column).  The diagonal tiles
+// keep the INVERSE of the diagonal Cholesky block, L_JJ^{-1}, so that both
+// the panel update and the substitution sweeps are tile products.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -254,7 +257,64 @@ constexpr size_t diag_lds_bytes() {
 // Left-looking: the tile first receives -sum_{K<J} L_JK L_JK^T.  The terms
 // K = kfrom .. J-1 are formed in this workgroup; the terms K < kfrom (single
 // matrix, split-K) were precomputed as nparts partial tiles part[I][c].
-template <typename T>
+// acc += sign * sum_{K = k0}^{k1 - 1} A_K B_K^T for row-major global tiles
+// A_K = pa(K), B_K = pb(K), with two LDS buffers of two tiles each at lds:
+// the tiles of step K + 1 are staged while the MFMAs of step K run, one
+// barrier per step.
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void gemm_loop_db(TileAcc<T>& acc, int k0, int k1, FA pa, FB pb, T* lds, T sign) {
+  constexpr int S = LdsV<T>::v;
+  if (k0 >= k1) return;
+  TileRegs<T> ra, rb;
+  ra.load(pa(k0));
+  rb.load(pb(k0));
+  __syncthreads();
+  ra.store_lds(lds);
+  rb.store_lds(lds + TS * S);
+  if (k0 + 1 < k1) {
+    ra.load(pa(k0 + 1));
+    rb.load(pb(k0 + 1));
+  }
+  __syncthreads();
+  for (int K = k0; K < k1; ++K) {
+    T* cur = lds + ((K - k0) & 1) * 2 * TS * S;
+    T* nxt = lds + (((K - k0) & 1) ^ 1) * 2 * TS * S;
+    if (K + 1 < k1) {
+      ra.store_lds(nxt);
+      rb.store_lds(nxt + TS * S);
+      if (K + 2 < k1) {
+        ra.load(pa(K + 2));
+        rb.load(pb(K + 2));
+      }
+    }
+    tile_mma<T>(acc, cur, cur + TS * S, sign);
+    __syncthreads();
+  }
+}
+// Same with A_K = B_K (acc += sign * sum A_K A_K^T), one tile per buffer.
+template <typename T, typename FA>
+__device__ __forceinline__ void syrk_loop_db(TileAcc<T>& acc, int k0, int k1, FA pa, T* lds, T sign) {
+  constexpr int S = LdsV<T>::v;
+  if (k0 >= k1) return;
+  TileRegs<T> ra;
+  ra.load(pa(k0));
+  __syncthreads();
+  ra.store_lds(lds);
+  if (k0 + 1 < k1) ra.load(pa(k0 + 1));
+  __syncthreads();
+  for (int K = k0; K < k1; ++K) {
+    T* cur = lds + ((K - k0) & 1) * TS * S;
+    T* nxt = lds + (((K - k0) & 1) ^ 1) * TS * S;
+    if (K + 1 < k1) {
+      ra.store_lds(nxt);
+      if (K + 2 < k1) ra.load(pa(K + 2));
+    }
+    tile_mma<T>(acc, cur, cur, sign);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool DBUF = false>
 __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc, const T* __restrict__ part,
                                           T* __restrict__ F, int32_t* __restrict__ status,
                                           unsigned char* smem_raw) {
@@ -262,14 +322,18 @@ __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc
   TileAcc<T> acc;
   acc.load(F + tri_index(J, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
-  TileRegs<T> ra;
-  if (kfrom < J) ra.load(F + tri_index(J, kfrom) * TS2);
-  for (int K = kfrom; K < J; ++K) {
-    __syncthreads();
-    ra.store_lds(sA);
-    __syncthreads();
-    if (K + 1 < J) ra.load(F + tri_index(J, K + 1) * TS2);
-    tile_mma<T>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
+  if (DBUF) {
+    syrk_loop_db<T>(acc, kfrom, J, [&](int K) { return F + tri_index(J, K) * TS2; }, sA, T(-1));
+  } else {
+    TileRegs<T> ra;
+    if (kfrom < J) ra.load(F + tri_index(J, kfrom) * TS2);
+    for (int K = kfrom; K < J; ++K) {
+      __syncthreads();
+      ra.store_lds(sA);
+      __syncthreads();
+      if (K + 1 < J) ra.load(F + tri_index(J, K + 1) * TS2);
+      tile_mma<T>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
+    }
   }
   __syncthreads();
   constexpr int PS = Pstride<T>::v;
@@ -303,27 +367,32 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
 
 // Sub-diagonal tile (I, J): A_IJ - sum_{K<J} L_IK L_JK^T (terms K >= kfrom
 // here, the others from nparts partial tiles), times L_JJ^{-T}.
-template <typename T>
+template <typename T, bool DBUF = false>
 __device__ __forceinline__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const T* __restrict__ part,
                            T* __restrict__ F, T* sA, T* sB) {
   TileAcc<T> acc;
   acc.load(F + tri_index(I, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);
-  TileRegs<T> ra, rb;
-  if (kfrom < J) {
-    ra.load(F + tri_index(I, kfrom) * TS2);
-    rb.load(F + tri_index(J, kfrom) * TS2);
-  }
-  for (int K = kfrom; K < J; ++K) {
-    __syncthreads();
-    ra.store_lds(sA);
-    rb.store_lds(sB);
-    __syncthreads();
-    if (K + 1 < J) {
-      ra.load(F + tri_index(I, K + 1) * TS2);
-      rb.load(F + tri_index(J, K + 1) * TS2);
+  if (DBUF) {   // sA: four LDS tiles
+    gemm_loop_db<T>(acc, kfrom, J, [&](int K) { return F + tri_index(I, K) * TS2; },
+                    [&](int K) { return F + tri_index(J, K) * TS2; }, sA, T(-1));
+  } else {
+    TileRegs<T> ra, rb;
+    if (kfrom < J) {
+      ra.load(F + tri_index(I, kfrom) * TS2);
+      rb.load(F + tri_index(J, kfrom) * TS2);
     }
-    tile_mma<T>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+    for (int K = kfrom; K < J; ++K) {
+      __syncthreads();
+      ra.store_lds(sA);
+      rb.store_lds(sB);
+      __syncthreads();
+      if (K + 1 < J) {
+        ra.load(F + tri_index(I, K + 1) * TS2);
+        rb.load(F + tri_index(J, K + 1) * TS2);
+      }
+      tile_mma<T>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+    }
   }
   __syncthreads();
   acc.store_lds(sA);
@@ -358,21 +427,6 @@ __device__ __forceinline__ void partial_tile(int Jn, int I, int c, int k0, int k
   acc.store(part + ((int64_t)I * maxc + c) * TS2);
 }
 
-template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_panel(int J, int kfrom, int nparts, int maxc,
-                                                              const T* __restrict__ part,
-                                                              const int32_t* __restrict__ nt,
-                                                              const int64_t* __restrict__ off,
-                                                              T* __restrict__ fac) {
-  const int b = blockIdx.y;
-  const int I = J + 1 + blockIdx.x;
-  if (I >= nt[b]) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LdsV<T>::v;
-  panel_tile<T>(J, I, kfrom, nparts, maxc, part, fac + off[b] * TS2, sA, sB);
-}
-
 // Whole left-looking factorisation of one matrix per workgroup (batches of
 // many small matrices): column by column, the diagonal tile and then the
 // sub-diagonal tiles, all in this workgroup.  Tiles written here are read
@@ -391,9 +445,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[b] * TS2;
   for (int J = 0; J < ntb; ++J) {
-    diag_tile<T>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
+    diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
     __syncthreads();
-    for (int I = J + 1; I < ntb; ++I) panel_tile<T>(J, I, 0, 0, 0, (const T*)nullptr, F, sA, sB);
+    for (int I = J + 1; I < ntb; ++I) panel_tile<T, true>(J, I, 0, 0, 0, (const T*)nullptr, F, sA, sB);
     __syncthreads();
   }
 }
@@ -448,19 +502,9 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
                      part, nt, off, fac, status);
 }
 template <typename T>
-void launch_potrf_panel(int J, int kfrom, int nparts, int maxc, const T* part, int nb, int max_nt,
-                        const int32_t* nt, const int64_t* off, T* fac, hipStream_t s) {
-  if (max_nt - 1 - J <= 0) return;
-  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
-  static bool once = (allow_lds(k_potrf_panel<T>, sh), true);
-  (void)once;
-  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(max_nt - 1 - J, nb), dim3(TILE_THREADS), sh, s, J, kfrom,
-                     nparts, maxc, part, nt, off, fac);
-}
-template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s) {
-  const size_t sh = diag_lds_bytes<T>();
+  const size_t sh = std::max(diag_lds_bytes<T>(), 4 * (size_t)TS * LdsV<T>::v * sizeof(T));
   static bool once = (allow_lds(k_potrf_full<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_full<T>, dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
@@ -701,8 +745,6 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 #define INST(T)                                                                                    \
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
-  template void launch_potrf_panel<T>(int, int, int, int, const T*, int, int, const int32_t*,      \
-                                      const int64_t*, T*, hipStream_t);                            \
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*,            \
                                      hipStream_t);                                                 \
   template void launch_potrf_step<T>(int, int, int, int, const T*, T*, const int32_t*,             \

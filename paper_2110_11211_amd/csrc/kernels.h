@@ -85,9 +85,6 @@ template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s);
-template <typename T>
-void launch_potrf_panel(int J, int kfrom, int nparts, int maxc, const T* part, int nb, int max_nt,
-                        const int32_t* nt, const int64_t* off, T* fac, hipStream_t s);
 // Whole factorisation, one workgroup per matrix.
 template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
