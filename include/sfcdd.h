@@ -217,6 +217,14 @@ sfcdd_status sfcdd_set_profiling(sfcdd_ctx* ctx, int32_t on);
 sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* ctx, int32_t kind, double* total_ms,
                                    int64_t* launches);
 
+/* Streaming-read rate of the device, for roofline context: reads the device
+ * buffer buf_dev (bytes, a multiple of 16, 16-byte aligned; its contents are
+ * not changed) with a 16-byte-per-lane grid-stride kernel `repeats` times on
+ * hip_stream (NULL = default stream) and returns the shortest time in
+ * *best_ms.  Needs no context.  Synchronous. */
+sfcdd_status sfcdd_read_probe(const void* buf_dev, size_t bytes, void* hip_stream, int32_t repeats,
+                              double* best_ms);
+
 /* Sizes and setup timings of a context. */
 sfcdd_status sfcdd_get_info(sfcdd_ctx* ctx, sfcdd_info* info);
 

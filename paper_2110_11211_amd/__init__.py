@@ -34,8 +34,8 @@ LAYOUT = {"natural": 0, "sfc": 1}
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
            "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
            "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
-           "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_destroy",
-           "sfcdd_last_error"]
+           "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_read_probe",
+           "sfcdd_destroy", "sfcdd_last_error"]
 KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
 
 
@@ -151,6 +151,18 @@ def workspace_size(**kw) -> int:
     n = ctypes.c_size_t()
     _check(lib().sfcdd_workspace_size(ctypes.byref(prm), ctypes.byref(n)))
     return int(n.value)
+
+
+def read_probe(buf, repeats: int = 5) -> float:
+    """Best time (ms) of a streaming read of the device tensor `buf` (whole
+    bytes, 16-byte aligned); bytes / time is the device's streaming-read rate."""
+    import torch
+    nbytes = buf.numel() * buf.element_size()
+    ms = ctypes.c_double()
+    stream = torch.cuda.current_stream(buf.device)
+    _check(lib().sfcdd_read_probe(ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(nbytes),
+                                  ctypes.c_void_p(stream.cuda_stream), int(repeats), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def partition_host(**kw):

@@ -577,6 +577,24 @@ void launch_axpy_scal(const Batch& B, const double* scal, int slot, const int32_
   hipLaunchKernelGGL(k_axpy_scal, dim3(2048), dim3(256), 0, s, B, scal, slot, active, x, z);
 }
 
+// Streaming read of n float4 (grid-stride); the sum is written only under a
+// condition that never holds for the probe's input, so the loads stay.
+__global__ __launch_bounds__(256) void k_read_probe(const float4* __restrict__ a, int64_t n,
+                                                    float* __restrict__ sink) {
+  float s = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = a[i];
+    s += (v.x + v.y) + (v.z + v.w);
+  }
+  if (s == -1.5f && sink) sink[0] = s;
+}
+
+void launch_read_probe(const void* buf, int64_t bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_probe, dim3(2048), dim3(256), 0, s, reinterpret_cast<const float4*>(buf),
+                     bytes / 16, (float*)nullptr);
+}
+
 // gather: out[p] = in[idx[p]];  scatter: out[idx[p]] = in[p].
 __global__ void k_permute(int64_t n, const int32_t* __restrict__ idx, const double* __restrict__ in,
                           double* __restrict__ out, int gather) {

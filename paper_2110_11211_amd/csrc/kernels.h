@@ -154,6 +154,7 @@ void launch_grad_coeff(const GridDesc& g, const double* lam, const double* u, do
 void launch_finalize_vec(int nvals, const double* partials, double* out, hipStream_t s);
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
 void launch_zero(int64_t n, double* a, hipStream_t s);
+void launch_read_probe(const void* buf, int64_t bytes, hipStream_t s);
 
 // Scalar slots of the solver's per-grid device scalars S[g * S_COUNT + slot].
 enum {

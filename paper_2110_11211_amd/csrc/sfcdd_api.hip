@@ -1384,6 +1384,34 @@ sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
   return SFCDD_OK;
 }
 
+sfcdd_status sfcdd_read_probe(const void* buf, size_t bytes, void* hip_stream, int32_t repeats,
+                              double* best_ms) {
+  sfcdd_ctx* c = nullptr;
+  if (!buf || !best_ms || bytes == 0 || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(buf) & 15) != 0 ||
+      repeats < 1)
+    FAIL(c, SFCDD_EINVAL, "read probe: need a 16-byte aligned buffer, bytes a positive multiple of 16, repeats >= 1");
+  const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  double best = 1e300;
+  launch_read_probe(buf, (int64_t)bytes, s);  // warm-up
+  for (int r = 0; r < repeats; ++r) {
+    (void)hipEventRecord(e0, s);
+    launch_read_probe(buf, (int64_t)bytes, s);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = std::min(best, (double)ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(c, hipGetLastError());
+  if (!(best < 1e300)) FAIL(c, SFCDD_EDEVICE, "read probe: timing failed");
+  *best_ms = best;
+  return SFCDD_OK;
+}
+
 sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (!c) return SFCDD_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
