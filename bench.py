@@ -211,6 +211,44 @@ def ct_batch_report(steps, warmup):
             "note": "setup + autotune + solve of all 84 grids to 1e-9 per step"}
 
 
+def adjoint_report(steps, warmup):
+    """The d=6 anisotropic workload as a differentiable solve: forward solve,
+    J = 1/2 ||u||^2, adjoint backward (second solve with the same factors and
+    the coefficient-gradient kernel), FP32 factors, rtol of the workload."""
+    import numpy as np
+    import torch
+    import paper_2110_11211_amd as m
+    from seeded_inputs import workloads
+    from oracle.grid import Grid
+    from oracle import exact, grad as ograd
+    w = workloads()["c3"]
+    f0 = w.rhs()
+    times = []
+    for k in range(warmup + steps):
+        f = torch.tensor(f0, dtype=torch.float64, device="cuda:0").requires_grad_(True)
+        a = torch.tensor(w.coeff, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        u = m.solve_poisson(f, a, w.levels[0], P=w.P, gamma=w.gamma, factor_dtype="fp32", rtol=w.rtol)
+        J = 0.5 * (u * u).sum()
+        J.backward()
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            times.append(e0.elapsed_time(e1))
+    g = Grid(levels=w.levels[0], coeff=w.coeff)
+    u_ref = exact.solve(g, f0)
+    gf_ref, ga_ref = ograd.adjoint_gradient(g, u_ref, u_ref)
+    gf = f.grad.detach().cpu().numpy()
+    ga = a.grad.detach().numpy()
+    return {"workload": w.name, "N": w.N(), "P": w.P, "ms": round(sorted(times)[len(times) // 2], 3),
+            "rel_error_grad_f": float(np.linalg.norm(gf - gf_ref) / np.linalg.norm(gf_ref)),
+            "max_rel_error_grad_a": float(np.max(np.abs(ga - ga_ref) / np.abs(ga_ref))),
+            "note": "setup + forward solve + adjoint solve + coefficient gradient, FP32 factors, rtol 1e-9"}
+
+
 def cpu_baseline(w, iterations, nsample):
     """The oracle (plain FP64 NumPy/SciPy, untuned) on a bounded sample of the
     same workload, extrapolated to one full setup + solve."""
@@ -373,6 +411,7 @@ def main():
                      "note": "FP32 MFMA; runs concurrently with the coarse setup"}
     if not args.no_batch:
         out["ct_batch"] = ct_batch_report(max(2, args.steps // 2), 1)
+        out["adjoint"] = adjoint_report(max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         iters = f64["iterations"] if f64 is not None else head["iterations"]
         out["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_sample)

@@ -44,3 +44,26 @@ def test_adjoint_gradients_small(fdtype):
         um = m.solve_poisson(dvec(f0), torch.tensor(am), levels, P=6, gamma=Fraction(1, 4))
     fd = (0.5 * float((up * up).sum()) - 0.5 * float((um * um).sum())) / (2 * h)
     assert abs(fd - a.grad[0].item()) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("fdtype", ["fp32", "fp64"])
+def test_adjoint_full_size_d6(fdtype):
+    """The d=6 anisotropic-coefficient workload at full size (7^5 x 15 =
+    252,105 unknowns, P = 512, gamma = 1/4, a_j log-uniform): forward solve,
+    adjoint backward, gradients against the exact DST-I adjoint."""
+    from seeded_inputs import workloads
+    w = workloads()["c3"]
+    levels = w.levels[0]
+    announce("adjoint full", levels, fdtype)
+    g = Grid(levels=levels, coeff=w.coeff)
+    f0 = w.rhs()
+    f = dvec(f0).requires_grad_(True)
+    a = torch.tensor(w.coeff, dtype=torch.float64, requires_grad=True)
+    u = m.solve_poisson(f, a, levels, P=w.P, gamma=w.gamma, factor_dtype=fdtype)
+    J = 0.5 * (u * u).sum()
+    J.backward()
+    u_ref = exact.solve(g, f0)
+    gf_ref, ga_ref = ograd.adjoint_gradient(g, u_ref, u_ref)
+    assert relerr(host(u), u_ref) <= 1e-9
+    assert relerr(host(f.grad), gf_ref) <= 1e-9
+    assert np.allclose(a.grad.numpy(), ga_ref, rtol=1e-8, atol=0)
