@@ -46,11 +46,11 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
 // by the first wave: lane i < DB holds block row i in registers, and the
 // factor column of each pivot is read from the pivot lane's registers
 // (readlane).  Writes the factor back to the block (upper part zero), its
-// inverse (row-major, lower) to dinv.  A non-positive pivot sets *status to
-// -6 and is replaced by 1.
+// inverse (lower, upper part zero) to dinv (row stride ldd).  A non-positive
+// pivot sets *status to -6 and is replaced by 1.
 template <typename T>
-__device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, T* __restrict__ colbuf,
-                             int32_t* status) {
+__device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, int ldd,
+                                             int32_t* status) {
   constexpr int PS = Pstride<T>::v;
   const int i = threadIdx.x;
   const bool act = i < DB;
@@ -79,7 +79,6 @@ __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __res
 #pragma unroll
     for (int j = k + 1; j < DB; ++j) a[j] -= l * (colk[j] * rs);
   }
-  (void)colbuf;
   if (act) {
 #pragma unroll
     for (int j = 0; j < DB; ++j) sC[(o + i) * PS + o + j] = a[j];
@@ -96,7 +95,7 @@ __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __res
   }
   if (act) {
 #pragma unroll
-    for (int r = 0; r < DB; ++r) dinv[r * DB + i] = x[r];
+    for (int r = 0; r < DB; ++r) dinv[r * ldd + i] = x[r];
   }
 }
 
@@ -147,16 +146,16 @@ __device__ __forceinline__ typename Acc<T>::type blk_zero() {
 // C_rb,cb -= L_rb,bk L_cb,bk^T, with independent block products issued
 // together.
 template <typename T, int bk>
-__device__ __forceinline__ void factor_column(T* __restrict__ sC, T* __restrict__ dinv,
-                                              T* __restrict__ colbuf, int32_t* status) {
+__device__ __forceinline__ void factor_column(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
   constexpr int PS = Pstride<T>::v;
   constexpr int o = bk * DB;
   constexpr int nr = NDB - 1 - bk;  // blocks below the diagonal
   typedef typename Acc<T>::type AT;
-  factor_block(sC, o, dinv + bk * DB * DB, colbuf, status);
+  T* dinv = sX + o * PS + o;        // L_bk,bk^{-1} is block (bk, bk) of X
+  factor_block(sC, o, dinv, PS, status);
   if constexpr (nr > 0) {
     T fd[DB / 4], fc[nr][DB / 4];
-    frag_load<T>(fd, dinv + bk * DB * DB, DB);                 // B = Dinv^T
+    frag_load<T>(fd, dinv, PS);                                // B = Dinv^T
 #pragma unroll
     for (int q = 0; q < nr; ++q) frag_load<T>(fc[q], sC + (o + DB + q * DB) * PS + o, PS);
     AT pc[nr];
@@ -188,8 +187,7 @@ __device__ __forceinline__ void factor_column(T* __restrict__ sC, T* __restrict_
 // Block row I of X = L^{-1}: X_IJ = -L_II^{-1} sum_{K=J}^{I-1} L_IK X_KJ,
 // J < I (rows above already complete).
 template <typename T, int I>
-__device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restrict__ sX,
-                                            const T* __restrict__ dinv, T* __restrict__ tmp) {
+__device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restrict__ sX) {
   constexpr int PS = Pstride<T>::v;
   typedef typename Acc<T>::type AT;
   AT t[I];
@@ -207,12 +205,13 @@ __device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restr
     }
   }
   T fdi[DB / 4];
-  frag_load<T>(fdi, dinv + I * DB * DB, DB);                   // A = L_II^{-1}
+  frag_load<T>(fdi, sX + (I * DB) * PS + I * DB, PS);          // A = L_II^{-1}
 #pragma unroll
   for (int J = 0; J < I; ++J) {
-    blk_store<T>(t[J], tmp + J * DB * DB, DB, T(1));
+    T* tmp = sX + (J + 1) * DB;                                // free upper block (0, J + 1)
+    blk_store<T>(t[J], tmp, PS, T(1));
     T fb[DB / 4];
-    frag_load_b<T>(fb, tmp + J * DB * DB, DB);
+    frag_load_b<T>(fb, tmp, PS);
     AT xij = blk_zero<T>();
     frag_mma<T>(xij, fdi, fb);
     blk_store<T>(xij, sX + (I * DB) * PS + J * DB, PS, T(-1));
@@ -221,37 +220,29 @@ __device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restr
 
 // Cholesky factorisation and inversion of a TS x TS LDS tile (stride
 // Pstride, lower part read), blocked by DB, all by the first wave.
-// On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).
-// tmp: (NDB - 1) DB x DB blocks plus a DB column buffer.
+// On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).  The
+// inverted diagonal blocks are formed in place in sX, and the free blocks
+// above its diagonal serve as scratch.
 template <typename T>
-__device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, T* __restrict__ dinv,
-                               T* __restrict__ tmp, int32_t* status) {
-  constexpr int PS = Pstride<T>::v;
+__device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
   __syncthreads();
   if (threadIdx.x < 64) {
-    T* colbuf = tmp + (NDB - 1) * DB * DB;
-    factor_column<T, 0>(sC, dinv, colbuf, status);
-    factor_column<T, 1>(sC, dinv, colbuf, status);
-    factor_column<T, 2>(sC, dinv, colbuf, status);
-    factor_column<T, 3>(sC, dinv, colbuf, status);
-    const int lane = threadIdx.x;
-    for (int e = lane; e < NDB * DB * DB; e += 64) {  // X_II = L_II^{-1}
-      const int I = e / (DB * DB), r = (e / DB) % DB, cc = e % DB;
-      sX[(I * DB + r) * PS + I * DB + cc] = dinv[e];
-    }
-    inverse_row<T, 1>(sC, sX, dinv, tmp);
-    inverse_row<T, 2>(sC, sX, dinv, tmp);
-    inverse_row<T, 3>(sC, sX, dinv, tmp);
+    factor_column<T, 0>(sC, sX, status);
+    factor_column<T, 1>(sC, sX, status);
+    factor_column<T, 2>(sC, sX, status);
+    factor_column<T, 3>(sC, sX, status);
+    inverse_row<T, 1>(sC, sX);
+    inverse_row<T, 2>(sC, sX);
+    inverse_row<T, 3>(sC, sX);
   }
   __syncthreads();
 }
 
-// LDS of the diagonal kernel: two Pstride tiles (C, X), the DB x DB block
-// inverses, NDB - 1 scratch blocks and a column buffer.  The GEMM staging (LdsV tiles, the same size) fits in
-// the same space.
+// LDS of the diagonal-tile factorisation: two Pstride tiles (C, X).  The
+// GEMM staging (LdsV tiles, the same size) fits in the same space.
 template <typename T>
 constexpr size_t diag_lds_bytes() {
-  return (2 * (size_t)TS * Pstride<T>::v + NDB * DB * DB + (NDB - 1) * DB * DB + DB) * sizeof(T);
+  return 2 * (size_t)TS * Pstride<T>::v * sizeof(T);
 }
 
 // Left-looking: the tile first receives -sum_{K<J} L_JK L_JK^T.  The terms
@@ -339,12 +330,11 @@ __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc
   constexpr int PS = Pstride<T>::v;
   T* sC = reinterpret_cast<T*>(smem_raw);
   T* sX = sC + TS * PS;
-  T* dinv = sX + TS * PS;
-  T* tmp = dinv + NDB * DB * DB;
+
   for (int a = 0; a < 2; ++a)
     for (int b2 = 0; b2 < 2; ++b2)
       for (int r = 0; r < 4; ++r) sC[TileAcc<T>::row(a, r) * PS + TileAcc<T>::col(b2)] = acc.c[a][b2][r];
-  potrf_inv_tile(sC, sX, dinv, tmp, status);
+  potrf_inv_tile(sC, sX, status);
   T* D = F + tri_index(J, J) * TS2;
   for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
     const int i = e / TS, j = e % TS;
@@ -453,34 +443,57 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
 }
 
 // One matrix (batch of one), look-ahead step after the diagonal tile of
-// column J: the first workgroups form the split-K partial update of column
-// J + 1 from columns K < J (part_out[I][c], I > J, chunks of SPLITK columns),
-// the others finish the sub-diagonal tiles of column J (using the partials of
-// columns K < J - 1 in part_in and forming the K = J - 1 term themselves).
-// Column J + 1 then needs only its own K = J term.
+// column J: workgroups form the split-K partial update of column J + 1 from
+// columns K < J (part_out[I][c], I > J, chunks of SPLITK columns) and finish
+// the sub-diagonal tiles of column J (using the partials of columns K < J - 1
+// in part_in and forming the K = J - 1 term themselves).  The workgroups of
+// row J + 1 come first; the last of them to finish (a device-scope counter,
+// with release/acquire fences around it) goes on to factor and invert the
+// diagonal tile of column J + 1, while the other rows are still in flight.
 template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, int nparts_in,
                                                              const T* __restrict__ part_in,
                                                              T* __restrict__ part_out, int nc_out,
                                                              const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
-                                                             T* __restrict__ fac) {
+                                                             T* __restrict__ fac,
+                                                             int32_t* __restrict__ counter,
+                                                             int32_t* __restrict__ status) {
   const int ntb = nt[0];
   const int m = ntb - 1 - J;  // tiles below the diagonal in column J
   if (m <= 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int last;
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[0] * TS2;
   const int x = blockIdx.x;
-  if (x < m * nc_out) {
-    const int I = J + 1 + x % m, c = x / m;
-    const int k0 = c * SPLITK, k1 = min(J, k0 + SPLITK);
-    partial_tile<T>(J + 1, I, c, k0, k1, maxc, F, part_out, sA, sB);
-  } else if (x < m * nc_out + m) {
-    const int I = J + 1 + (x - m * nc_out);
-    panel_tile<T>(J, I, J > 0 ? J - 1 : 0, nparts_in, maxc, part_in, F, sA, sB);
+  const int kfrom = J > 0 ? J - 1 : 0;
+  int I;
+  if (x <= nc_out) {                       // row J + 1: its partial chunks, then its panel tile
+    I = J + 1;
+    if (x < nc_out) partial_tile<T>(J + 1, I, x, x * SPLITK, min(J, (x + 1) * SPLITK), maxc, F, part_out, sA, sB);
+    else panel_tile<T>(J, I, kfrom, nparts_in, maxc, part_in, F, sA, sB);
+  } else {
+    const int y = x - (nc_out + 1), mr = m - 1;  // rows J + 2 .. ntb - 1
+    if (y < mr * nc_out) {
+      I = J + 2 + y % mr;
+      const int c = y / mr;
+      partial_tile<T>(J + 1, I, c, c * SPLITK, min(J, (c + 1) * SPLITK), maxc, F, part_out, sA, sB);
+    } else {
+      I = J + 2 + (y - mr * nc_out);
+      panel_tile<T>(J, I, kfrom, nparts_in, maxc, part_in, F, sA, sB);
+    }
+    return;
   }
+  // row J + 1 done by this workgroup: publish, and let the last one continue
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter + J, 1) == nc_out);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  diag_tile<T>(J + 1, J, nc_out, maxc, part_out, F, status, smem_raw);
 }
 
 // The FP64 tile kernels stage two 64x65 double tiles (66.5 KB of LDS), above
@@ -511,15 +524,16 @@ void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, in
 }
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part_in, T* part_out,
-                       const int32_t* nt, const int64_t* off, T* fac, hipStream_t s) {
+                       const int32_t* nt, const int64_t* off, T* fac, int32_t* counter,
+                       int32_t* status, hipStream_t s) {
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
   const int nc_out = (J + SPLITK - 1) / SPLITK;
-  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
+  const size_t sh = std::max(2 * TS * LdsV<T>::v * sizeof(T), diag_lds_bytes<T>());
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_step<T>, dim3(m * nc_out + m), dim3(TILE_THREADS), sh, s, J, maxc,
-                     nparts_in, part_in, part_out, nc_out, nt, off, fac);
+                     nparts_in, part_in, part_out, nc_out, nt, off, fac, counter, status);
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -748,7 +762,7 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*,            \
                                      hipStream_t);                                                 \
   template void launch_potrf_step<T>(int, int, int, int, const T*, T*, const int32_t*,             \
-                                     const int64_t*, T*, hipStream_t);                             \
+                                     const int64_t*, T*, int32_t*, int32_t*, hipStream_t);         \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \
