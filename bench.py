@@ -48,11 +48,12 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_kernel=True):
+def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_kernel=True, curve="zorder"):
     """Times `steps` full setup+solve passes; returns a dict of measurements."""
     import torch
     import paper_2110_11211_amd as m
-    kw = dict(levels=list(w.levels[0]), P=w.P, gamma=w.gamma, factor_dtype=fdtype, local_solver=local)
+    kw = dict(levels=list(w.levels[0]), P=w.P, gamma=w.gamma, factor_dtype=fdtype, local_solver=local,
+              curve=curve)
     nbytes = m.workspace_size(**kw)
     key = (fdtype, local)
     if key not in ws_cache:
@@ -329,6 +330,8 @@ def main():
             out["copy_probe_bytes_written"] = 4 * n
         print(json.dumps(out), flush=True)
         return
+    hil = run_path(w, f_dev, "fp32", args.local, max(2, args.steps // 2), args.warmup, ws_cache,
+                   prof_kernel=False, curve="hilbert")
     f64 = None
     if not args.skip_fp64:
         f64 = run_path(w, f_dev, "fp64", args.local, max(2, args.steps // 2), args.warmup, ws_cache)
@@ -402,6 +405,10 @@ def main():
                        "local_solve_gbps": round(b64 / (ms64 / max(n64, 1) * 1e-3) / 1e9, 1),
                        "setup_phases_ms": i64["setup_ms"]}
         out["speedup_fp32_vs_fp64"] = round(f64["ms"] / head["ms"], 3)
+    out["hilbert"] = {"ms": round(hil["ms"], 3), "setup_ms": round(hil["setup_ms"], 3),
+                      "solve_ms": round(hil["solve_ms"], 3), "iterations": hil["iterations"],
+                      "iterations_zorder": head["iterations"],
+                      "note": "same workload with the Hilbert curve (Skilling's construction) instead of Z-order"}
     # MFMA rate of the batched subdomain factorisation (sum N_i^3 / 3 flops)
     _, Ni, _, _ = m.partition_host(levels=list(w.levels[0]), P=w.P, gamma=w.gamma)
     fflops = float(np.sum(Ni.astype(np.float64) ** 3) / 3.0)

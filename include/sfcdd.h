@@ -57,6 +57,10 @@ enum { SFCDD_ADDITIVE = 0, SFCDD_BALANCED = 1 };
 enum { SFCDD_FP64 = 0, SFCDD_FP32 = 1 };
 enum { SFCDD_LOCAL_CHOLESKY = 0, SFCDD_LOCAL_INVERSE = 1 };
 enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
+/* Space-filling curve of the point order (Sec. 3.2, Alg. 1): Z-order
+ * (Morton), or Hilbert (Skilling's construction), both at the resolution of
+ * the finest direction on the scaled coordinates k_j 2^(max l - l_j). */
+enum { SFCDD_CURVE_ZORDER = 0, SFCDD_CURVE_HILBERT = 1 };
 /* Flag OR-ed into the method of sfcdd_solve: start from x0 exactly as given
  * and apply the full balanced operator every iteration (see sfcdd_solve). */
 enum { SFCDD_SOLVE_PLAIN_START = 256 };
@@ -80,6 +84,7 @@ typedef struct {
                                 explicit inverse formed from it, applied as a
                                 symmetric matrix-vector product                        */
   int32_t layout;            /* 0 natural order, 1 curve order                          */
+  int32_t curve;             /* SFCDD_CURVE_ZORDER or SFCDD_CURVE_HILBERT (Sec. 3.2)    */
 } sfcdd_params;
 
 typedef struct {

@@ -31,7 +31,7 @@ WEIGHT_NONE, WEIGHT_OMEGA, WEIGHT_D = "none", "omega", "D"
 class OracleSchwarz:
     def __init__(self, grid: Grid, P: int, gamma, q: Optional[int] = None,
                  weighting: str = WEIGHT_OMEGA, variant: str = "balanced",
-                 factor: bool = True):
+                 factor: bool = True, curve: str = "zorder"):
         self.g = grid
         self.N = grid.N
         self.P = int(P)
@@ -41,7 +41,8 @@ class OracleSchwarz:
         self.q = part.coarse_rule_q(self.N, self.P) if q is None else int(q)
         self.weighting = weighting
         self.variant = variant
-        self.sfc_index, self.pos = sfc_order(grid)
+        self.curve = curve
+        self.sfc_index, self.pos = sfc_order(grid, curve)
         A_nat = grid.matrix()
         perm = self.sfc_index
         self.A_nat = A_nat

@@ -29,6 +29,7 @@ FACTOR_DTYPE = {"fp64": 0, "fp32": 1}
 LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
 METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}
 SOLVE_PLAIN_START = 256
+CURVE = {"zorder": 0, "hilbert": 1}
 LAYOUT = {"natural": 0, "sfc": 1}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
@@ -51,7 +52,7 @@ class Params(ctypes.Structure):
                 ("P", ctypes.c_int32), ("gamma_num", ctypes.c_int64), ("gamma_den", ctypes.c_int64),
                 ("q", ctypes.c_int32), ("weighting", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("factor_dtype", ctypes.c_int32), ("local_solver", ctypes.c_int32),
-                ("layout", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("curve", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -115,7 +116,7 @@ def _check(st: int, ctx=None):
 
 def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q=0,
                 weighting="omega", variant="balanced", factor_dtype="fp64",
-                local_solver="cholesky", layout="natural"):
+                local_solver="cholesky", layout="natural", curve="zorder"):
     """Builds the sfcdd_params struct; returns (struct, keepalive)."""
     g = Fraction(gamma)
     d = len(levels) if levels is not None else len(npts)
@@ -143,6 +144,7 @@ def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q
     prm.factor_dtype = FACTOR_DTYPE[factor_dtype]
     prm.local_solver = LOCAL_SOLVER[local_solver]
     prm.layout = LAYOUT[layout]
+    prm.curve = CURVE[curve]
     return prm, keep
 
 
@@ -190,7 +192,7 @@ class SFCSchwarz:
                  coeff: Optional[Sequence[float]] = None, P: int = 1, gamma=Fraction(1, 2), q: int = 0,
                  weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
                  local_solver: str = "cholesky", layout: str = "natural", device="cuda:0",
-                 workspace=None):
+                 workspace=None, curve: str = "zorder"):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -198,7 +200,7 @@ class SFCSchwarz:
             raise RuntimeError("SFCSchwarz needs a ROCm GPU device")
         self.kw = dict(levels=levels, npts=npts, coeff=coeff, P=P, gamma=gamma, q=q, weighting=weighting,
                        variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
-                       layout=layout)
+                       layout=layout, curve=curve)
         prm, self._keep = make_params(**self.kw)
         n = ctypes.c_size_t()
         _check(lib().sfcdd_workspace_size(ctypes.byref(prm), ctypes.byref(n)))
@@ -311,7 +313,7 @@ class SFCSchwarzBatch(SFCSchwarz):
     """Many independent grids in one context (e.g. one layer of the
     combination technique): every setup phase and solver operator runs as one
     launch over all grids.  `grids` is a list of dicts with the per-grid keys
-    levels / npts, coeff, P, gamma, q; the other options are shared.  Vectors
+    levels / npts, coeff, P, gamma, q, curve; the other options are shared.  Vectors
     concatenate the grids in order (see `offsets`)."""
 
     def __init__(self, grids, weighting: str = "omega", variant: str = "balanced",
@@ -329,7 +331,8 @@ class SFCSchwarzBatch(SFCSchwarz):
             prm, keep = make_params(levels=gk.get("levels"), npts=gk.get("npts"), coeff=gk.get("coeff"),
                                     P=gk["P"], gamma=gk.get("gamma", Fraction(1, 2)), q=gk.get("q", 0),
                                     weighting=weighting, variant=variant, factor_dtype=factor_dtype,
-                                    local_solver=local_solver, layout=layout)
+                                    local_solver=local_solver, layout=layout,
+                                    curve=gk.get("curve", "zorder"))
             arr[k] = prm
             self._keep.append(keep)
         self._arr = arr

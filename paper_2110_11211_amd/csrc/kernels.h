@@ -17,6 +17,7 @@ constexpr int MAXD = 16;
 struct GridDesc {
   int d;
   int nres;                 // curve resolution bits
+  int curve;                // 0 Z-order, 1 Hilbert
   int64_t N;
   int n[MAXD];              // interior points per dimension
   int shift[MAXD];          // coordinate scaling to the finest resolution

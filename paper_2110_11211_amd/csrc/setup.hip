@@ -14,6 +14,68 @@ __device__ __forceinline__ int64_t count_in(int64_t lo, int64_t hi, int n, int s
   return b >= a ? b - a + 1 : 0;
 }
 
+// Hilbert index digit (d bits, dimension 0 most significant) at bit level bi
+// of the point with scaled coordinates Y, by Skilling's transform
+// (transposed Hilbert index): walking the bit levels above bi from the top,
+// axis i with a 1 at that level inverts the lower bits of axis 0, otherwise
+// axes 0 and i exchange their lower bits; after that the bits at levels >= bi
+// are final.  The axes are then Gray-coded in order (axis i XORed with the
+// already coded axis i - 1, i.e. the XOR of axes 0..i), and the digit is
+// their bit at level bi, inverted when the coded last axis has an odd number
+// of ones above bi.  Depends only on the bits of Y at levels >= bi.
+__device__ __forceinline__ int hilbert_digit(const uint64_t* __restrict__ Y, int d, int nres, int bi) {
+  uint64_t X[MAXD];
+  for (int j = 0; j < d; ++j) X[j] = Y[j];
+  for (int lev = nres - 1; lev > bi; --lev) {
+    const uint64_t Q = 1ull << lev, low = Q - 1;
+    for (int i = 0; i < d; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= low;
+      } else {
+        const uint64_t t = (X[0] ^ X[i]) & low;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  uint64_t glast = 0;
+  for (int i = 0; i < d; ++i) glast ^= X[i];
+  const int flip = __popcll(glast >> (bi + 1)) & 1;
+  int digit = 0, acc = 0;
+  for (int i = 0; i < d; ++i) {
+    acc ^= (int)((X[i] >> bi) & 1ull);
+    digit = (digit << 1) | (acc ^ flip);
+  }
+  return digit;
+}
+
+// Hilbert rank: at every bit level, the points of the children of p's cell
+// that the curve visits before p's child (smaller digit) come first; each
+// child is an axis-aligned box, so its interior points are counted as a
+// product of interval counts.
+__device__ int64_t hilbert_rank(const int64_t* C, const GridDesc& g) {
+  uint64_t Y[MAXD];
+  uint64_t Cu[MAXD];
+  for (int j = 0; j < g.d; ++j) Cu[j] = (uint64_t)C[j];
+  int64_t rank = 0;
+  for (int bi = g.nres - 1; bi >= 0; --bi) {
+    const int hp = hilbert_digit(Cu, g.d, g.nres, bi);
+    if (hp == 0) continue;
+    for (int c = 0; c < (1 << g.d); ++c) {
+      for (int j = 0; j < g.d; ++j)
+        Y[j] = ((Cu[j] >> (bi + 1)) << (bi + 1)) | ((uint64_t)((c >> (g.d - 1 - j)) & 1) << bi);
+      if (hilbert_digit(Y, g.d, g.nres, bi) >= hp) continue;
+      int64_t cnt = 1;
+      for (int j = 0; j < g.d && cnt; ++j) {
+        const int64_t lo = (int64_t)Y[j];
+        cnt *= count_in(lo, lo + ((int64_t)1 << bi) - 1, g.n[j], g.shift[j]);
+      }
+      rank += cnt;
+    }
+  }
+  return rank;
+}
+
 // Curve rank of every point without sorting (Sec. 3.2/3.3, Alg. 1 sfc_index):
 // the rank of key K is the number of grid points whose Morton key is smaller.
 // Walking K's bits from the most significant one, each 1-bit contributes the
@@ -33,6 +95,9 @@ __global__ void k_sfc_rank(Batch B, int32_t* __restrict__ pos, int32_t* __restri
     C[j] = k << g.shift[j];
   }
   int64_t rank = 0;
+  if (g.curve == 1) {
+    rank = hilbert_rank(C, g);
+  } else {
   for (int t = g.nres - 1; t >= 0; --t) {
     for (int j = g.d - 1; j >= 0; --j) {
       if (!((C[j] >> t) & 1)) continue;
@@ -53,6 +118,7 @@ __global__ void k_sfc_rank(Batch B, int32_t* __restrict__ pos, int32_t* __restri
       }
       rank += cnt;
     }
+  }
   }
   pos[idx] = (int32_t)(g.goff + rank);
   if (rank < g.N) sfc_index[g.goff + rank] = (int32_t)idx;

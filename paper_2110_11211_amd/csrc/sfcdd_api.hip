@@ -256,6 +256,9 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
   if (p->local_solver != SFCDD_LOCAL_CHOLESKY && p->local_solver != SFCDD_LOCAL_INVERSE)
     GFAIL(SFCDD_EINVAL, "local_solver = %d", p->local_solver);
   if (p->layout != 0 && p->layout != 1) GFAIL(SFCDD_EINVAL, "layout = %d", p->layout);
+  if (p->curve != SFCDD_CURVE_ZORDER && p->curve != SFCDD_CURVE_HILBERT)
+    GFAIL(SFCDD_EINVAL, "curve = %d", p->curve);
+  g.curve = p->curve;
 
   const int P = p->P;
   const int64_t base = N / P, rem = N % P;

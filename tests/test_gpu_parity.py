@@ -44,24 +44,26 @@ def _solver(levels, P, gamma, **kw):
     return m.SFCSchwarz(levels=levels, P=P, gamma=gamma, **kw)
 
 
+@pytest.mark.parametrize("curve", ["zorder", "hilbert"])
 @pytest.mark.parametrize("levels,P,gamma", SMALL)
-def test_sfc_index_and_partition_bit_exact(levels, P, gamma):
-    announce("partition", levels, P, gamma)
-    S = _solver(levels, P, gamma)
+def test_sfc_index_and_partition_bit_exact(levels, P, gamma, curve):
+    announce("partition", levels, P, gamma, curve)
+    S = _solver(levels, P, gamma, curve=curve)
     part = S.partition()
-    O = OracleSchwarz(Grid(levels=levels), P, gamma, factor=False)
+    O = OracleSchwarz(Grid(levels=levels), P, gamma, factor=False, curve=curve)
     assert np.array_equal(part["sfc_index"], O.sfc_index)
     assert np.array_equal(part["ta"], O.ta) and np.array_equal(part["Ni"], O.Ni)
     assert np.array_equal(part["omega"], O.omega) and part["q"] == O.q
 
 
+@pytest.mark.parametrize("curve", ["zorder", "hilbert"])
 @pytest.mark.parametrize("name", ["c2", "c3", "c5"])
-def test_sfc_index_full_size(name):
+def test_sfc_index_full_size(name, curve):
     w = workloads()[name]
-    announce("sfc_index", name)
-    S = _solver(w.levels[0], w.P, w.gamma, factor_dtype="fp32")
+    announce("sfc_index", name, curve)
+    S = _solver(w.levels[0], w.P, w.gamma, factor_dtype="fp32", curve=curve)
     sfc = S.partition()["sfc_index"]
-    ref, _ = sfc_order(Grid(levels=w.levels[0]))
+    ref, _ = sfc_order(Grid(levels=w.levels[0]), curve)
     assert np.array_equal(sfc, ref)
     S.close()
     del S
@@ -92,6 +94,31 @@ def test_apply_fp64(levels, P, gamma, variant, weighting, local):
     r = uniform_pm1(7, g.N)
     h = host(S.apply(dvec(r)))
     assert relerr(h, O.apply(r)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("variant", ["balanced", "additive"])
+@pytest.mark.parametrize("levels,P,gamma", SMALL)
+def test_apply_fp64_hilbert(levels, P, gamma, variant):
+    announce("apply64 hilbert", levels, P, gamma, variant)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma, variant=variant, curve="hilbert")
+    S = _solver(levels, P, gamma, variant=variant, curve="hilbert")
+    r = uniform_pm1(17, g.N)
+    h = host(S.apply(dvec(r)))
+    assert relerr(h, O.apply(r)) <= FP64_TOL
+
+
+def test_pcg_hilbert_iterations_and_solution():
+    levels, P, gamma = (5, 4, 4), 16, Fraction(1, 2)
+    announce("pcg hilbert")
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma, curve="hilbert")
+    f = uniform_pm1(9, g.N)
+    _, it_o, _ = solvers.pcg(O.A_nat, f, O.apply, x0=O.balancing_start(f), rtol=1e-10)
+    S = _solver(levels, P, gamma, curve="hilbert")
+    x, info = S.solve(dvec(f), rtol=1e-10)
+    assert abs(info["iterations"] - it_o) <= 1
+    assert relerr(host(x), exact.solve(g, f)) <= 1e-8
 
 
 @pytest.mark.parametrize("local", ["cholesky", "inverse"])

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle.grid import Grid
-from oracle.sfc import sfc_order, morton_keys
+from oracle.sfc import sfc_order, morton_keys, hilbert_keys, hilbert_transpose
 from oracle import partition as part
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -157,3 +157,54 @@ def test_coarse_rule_values():
     assert part.coarse_rule_q(8258175, 4096) == 4      # rule gives 64, cap 16384/4096
     assert part.coarse_rule_q(6885, 16) == 16 and part.coarse_rule_q(11025, 16) == 32
     assert part.coarse_rule_q(20, 8) == 1
+
+
+def _hilbert_cube_order(d, b):
+    n = 1 << b
+    pts = np.array(np.meshgrid(*[np.arange(n)] * d, indexing="ij")).reshape(d, -1)
+    T = hilbert_transpose([pts[j].astype(np.uint64) for j in range(d)], b)
+    keys = np.zeros(pts.shape[1], dtype=np.uint64)
+    for lev in range(b - 1, -1, -1):
+        for j in range(d):
+            keys = (keys << np.uint64(1)) | ((T[j] >> np.uint64(lev)) & np.uint64(1))
+    return pts, keys
+
+
+@pytest.mark.parametrize("d,b", [(2, 1), (2, 4), (3, 3), (4, 2), (5, 2), (6, 2)])
+def test_hilbert_is_a_continuous_nested_curve(d, b):
+    """Defining properties of a Hilbert curve on the 2^b cube: the index is a
+    bijection onto 0 .. 2^(db) - 1, consecutive cells are face neighbours
+    (the property that sets it apart from Z-order), and every run of 2^(dk)
+    consecutive indices fills one aligned sub-cube of side 2^k."""
+    pts, keys = _hilbert_cube_order(d, b)
+    n = 1 << b
+    assert np.array_equal(np.sort(keys), np.arange(n ** d, dtype=np.uint64))
+    P = pts[:, np.argsort(keys)].astype(np.int64)
+    assert np.all(np.abs(np.diff(P, axis=1)).sum(axis=0) == 1)
+    for k in range(1, b):
+        blocks = P.reshape(d, -1, 1 << (d * k)) >> k
+        assert np.all(blocks == blocks[:, :, :1])
+
+
+def test_hilbert_two_dimensional_level_one_and_two():
+    """The first-order curve visits the four quadrants as a U; the second
+    order curve starts in the corner cell of the first quadrant and ends in the
+    corner of the last one, both on the same edge of the square."""
+    pts, keys = _hilbert_cube_order(2, 1)
+    P = pts[:, np.argsort(keys)].T.tolist()
+    assert P[0] == [0, 0] and P[3] in ([1, 0], [0, 1])
+    assert sorted(map(tuple, P)) == [(0, 0), (0, 1), (1, 0), (1, 1)]
+    pts, keys = _hilbert_cube_order(2, 2)
+    P = pts[:, np.argsort(keys)].T
+    assert P[0].tolist() == [0, 0]
+    end = P[-1].tolist()
+    assert end in ([3, 0], [0, 3])
+
+
+def test_hilbert_grid_keys_unique_and_1d_identity():
+    g = Grid(levels=(4, 3, 5))
+    k = hilbert_keys(g)
+    assert len(np.unique(k)) == g.N
+    g1 = Grid(levels=(6,))
+    sfc_index, _ = sfc_order(g1, "hilbert")
+    assert np.array_equal(sfc_index, np.arange(g1.N))
