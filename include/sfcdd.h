@@ -52,8 +52,15 @@ typedef enum {
   SFCDD_ENOTSPD = -6     /* a local or coarse matrix was not positive definite */
 } sfcdd_status;
 
-enum { SFCDD_WEIGHT_NONE = 0, SFCDD_WEIGHT_OMEGA = 1 };
-enum { SFCDD_ADDITIVE = 0, SFCDD_BALANCED = 1 };
+/* Weights of the one-level sum (eqs. w1levprec, Di, omegai): none, the scalar
+ * omega_i per subdomain, or D_i = diag(1 / multiplicity) per point (a
+ * non-symmetric preconditioner unless every multiplicity agrees: use
+ * SFCDD_FCG). */
+enum { SFCDD_WEIGHT_NONE = 0, SFCDD_WEIGHT_OMEGA = 1, SFCDD_WEIGHT_D = 2 };
+/* Two-level forms: additive C1^{-1} + F (eq. addSW), balanced
+ * G^T C1^{-1} G + F (eq. balSW) and deflated G^T C1^{-1} + F (Sec. 3.1),
+ * F = R_0^T A_0^{-1} R_0, G = I - A F. */
+enum { SFCDD_ADDITIVE = 0, SFCDD_BALANCED = 1, SFCDD_DEFLATED = 2 };
 enum { SFCDD_FP64 = 0, SFCDD_FP32 = 1 };
 enum { SFCDD_LOCAL_CHOLESKY = 0, SFCDD_LOCAL_INVERSE = 1 };
 enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
@@ -76,8 +83,8 @@ typedef struct {
   int64_t gamma_den;         /*   gamma_den >= 1                                       */
   int32_t q;                 /* coarse unknowns per subdomain (eq. restr), 1..floor(N/P);
                                 0 = 2^(floor(log2(N/P)) - 4), capped at qP <= 16384    */
-  int32_t weighting;         /* SFCDD_WEIGHT_NONE or SFCDD_WEIGHT_OMEGA (eq. omegai)   */
-  int32_t variant;           /* SFCDD_ADDITIVE (eq. addSW) or SFCDD_BALANCED (eq. balSW) */
+  int32_t weighting;         /* SFCDD_WEIGHT_NONE, _OMEGA (eq. omegai) or _D (eq. Di)    */
+  int32_t variant;           /* SFCDD_ADDITIVE, SFCDD_BALANCED or SFCDD_DEFLATED         */
   int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves  */
   int32_t local_solver;      /* SFCDD_LOCAL_CHOLESKY: forward/backward substitution
                                 with the Cholesky factor; SFCDD_LOCAL_INVERSE: the
@@ -163,11 +170,12 @@ sfcdd_status sfcdd_matvec(sfcdd_ctx* ctx, const double* x_dev, double* y_dev);
  * for the FP32-factor preconditioner) or SFCDD_RICHARDSON (x += xi C^{-1} r;
  * xi <= 0 estimates xi = 2/(lmin + lmax) from 30 Lanczos steps on the residual
  * of the start).
- * Balanced variant (eq. balSW): unless SFCDD_SOLVE_PLAIN_START is OR-ed into
+ * Balanced and deflated variants: unless SFCDD_SOLVE_PLAIN_START is OR-ed into
  * method, the start is first corrected to x0 + F (b - A x0), F = R_0^T A_0^{-1}
  * R_0.  Its residual, and every later one, satisfies R_0 r = 0, where the
  * balanced operator reduces to (I - F A) C1^{-1}: one coarse solve per
- * iteration instead of two, same iterates as the full operator from that start.
+ * iteration instead of two, same iterates as the full operator from that start
+ * (on such residuals the two variants coincide).
  * info: host, may be NULL. */
 sfcdd_status sfcdd_solve(sfcdd_ctx* ctx, const double* b_dev, double* x_dev, double rtol,
                          int32_t max_iter, int32_t method, double xi, sfcdd_solve_info* info);

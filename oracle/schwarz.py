@@ -8,6 +8,7 @@ Sec. 3.1, 3.3, Alg. 1 and Alg. 2:
   additive         C^{-1} = R_0^T A_0^{-1} R_0 + C1^{-1}      (eq. addSW, Alg. 2)
   balanced         C^{-1} = G^T C1^{-1} G + F,               (eq. balSW)
                    F = R_0^T A_0^{-1} R_0, G = I - A F        (eq. balan)
+  deflated         C^{-1} = G^T C1^{-1} + F                  (Sec. 3.1, after eq. balan)
 The coarse right-hand side in Alg. 2 is read as R_0 g (the input vector).
 Vectors passed in and out are in natural order; internally everything is in
 curve-position order (row p of the permuted matrix is the point sfc_index[p]).
@@ -105,6 +106,11 @@ class OracleSchwarz:
             y = self.fine_s(w)                     # C1^{-1} G g
             s = self.coarse_s(self.A @ y)          # F A y
             return y - s + t                       # G^T y + F g
+        if self.variant == "deflated":
+            t = self.coarse_s(g_s)                 # F g
+            y = self.fine_s(g_s)                   # C1^{-1} g
+            s = self.coarse_s(self.A @ y)          # F A y
+            return y - s + t                       # G^T C1^{-1} g + F g
         if self.variant == "onelevel":
             return self.fine_s(g_s)
         raise ValueError(self.variant)

@@ -23,8 +23,8 @@ LIB_PATH = os.path.join(HERE, "libsfcdd.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EOVERFLOW, ENOTSPD = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTCONV: "ENOTCONV",
            EOVERFLOW: "EOVERFLOW", ENOTSPD: "ENOTSPD"}
-WEIGHTING = {"none": 0, "omega": 1}
-VARIANT = {"additive": 0, "balanced": 1}
+WEIGHTING = {"none": 0, "omega": 1, "D": 2}
+VARIANT = {"additive": 0, "balanced": 1, "deflated": 2}
 FACTOR_DTYPE = {"fp64": 0, "fp32": 1}
 LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
 METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}

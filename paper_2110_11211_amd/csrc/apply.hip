@@ -203,15 +203,17 @@ INST(double)
 // (Alg. 2 last step, eq. w1levprec with D_i = omega_i I), in gather form with
 // a fixed order over i: deterministic, no floating-point atomics.  Only
 // pieces k-F-1 .. k+F+1 around p's piece k can contain p.
-__global__ void k_scatter(Batch B, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
-                          const int64_t* __restrict__ doff, const double* __restrict__ omega,
-                          const double* __restrict__ dbuf, double* __restrict__ h) {
+__global__ void k_scatter(Batch B, int dweight, const int32_t* __restrict__ ta,
+                          const int32_t* __restrict__ Ni, const int64_t* __restrict__ doff,
+                          const double* __restrict__ omega, const double* __restrict__ dbuf,
+                          double* __restrict__ h) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B.Ntot;
        p += (int64_t)gridDim.x * blockDim.x) {
     const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
     const int64_t N = g.N;
     const int64_t pl = p - g.goff;
     double acc = 0.0;
+    int mult = 0;
     const int k = piece_of(pl, g.base, g.rem);
     for (int c = 0; c < g.ncand; ++c) {
       int i = (g.ncand >= g.P) ? c : k - (g.F + 1) + c;
@@ -220,17 +222,22 @@ __global__ void k_scatter(Batch B, const int32_t* __restrict__ ta, const int32_t
       const int ig = g.soff + i;
       int64_t o = pl - ta[ig];
       if (o < 0) o += N;
-      if (o < Ni[ig]) acc += omega[ig] * dbuf[doff[ig] + o];
+      if (o < Ni[ig]) {
+        const double v = dbuf[doff[ig] + o];
+        acc += dweight ? v : omega[ig] * v;
+        ++mult;
+      }
     }
-    h[p] = acc;
+    h[p] = dweight ? acc / (double)mult : acc;  // D_i weighting: 1 / multiplicity of p
   }
 }
 
-void launch_scatter(const Batch& B, const int32_t* ta, const int32_t* Ni, const int64_t* doff,
-                    const double* omega, const double* dbuf, double* h, hipStream_t s) {
+void launch_scatter(const Batch& B, int dweight, const int32_t* ta, const int32_t* Ni,
+                    const int64_t* doff, const double* omega, const double* dbuf, double* h,
+                    hipStream_t s) {
   const int64_t nb = (B.Ntot + 255) / 256;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)(nb < 1048576 ? nb : 1048576)), dim3(256), 0, s, B,
-                     ta, Ni, doff, omega, dbuf, h);
+                     dweight, ta, Ni, doff, omega, dbuf, h);
 }
 
 // ---------------------------------------------------------------------------

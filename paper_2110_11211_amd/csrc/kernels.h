@@ -128,8 +128,11 @@ void launch_symv_reduce(int nb, int max_n, const BatchMeta& bm, const int32_t* n
 template <typename T>
 void launch_gather_local(const Batch& B, int max_nt, const BatchMeta& bm, const int32_t* ta,
                          const int32_t* Ni, const double* w, T* xloc, hipStream_t s);
-void launch_scatter(const Batch& B, const int32_t* ta, const int32_t* Ni, const int64_t* doff,
-                    const double* omega, const double* dbuf, double* h, hipStream_t s);
+// h[p] = sum over the subdomains i containing p of w_i(p) d_i[p - ta_i]:
+// w_i = omega_i, or (dweight) 1 / (number of subdomains containing p).
+void launch_scatter(const Batch& B, int dweight, const int32_t* ta, const int32_t* Ni,
+                    const int64_t* doff, const double* omega, const double* dbuf, double* h,
+                    hipStream_t s);
 void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s);
 // out = X^T (X v) for packed lower-tiled FP64 X (the coarse operator X = L_0^{-1}):
 // v tile-padded at bm.xoff, ytmp the same layout, part the per-(tile, chunk)

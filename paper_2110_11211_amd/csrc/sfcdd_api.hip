@@ -248,9 +248,10 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
   if (p->gamma_den < 1 || p->gamma_den > (int64_t(1) << 30) || p->gamma_num < 0)
     GFAIL(SFCDD_EINVAL, "gamma = %lld/%lld must be >= 0 with 1 <= den <= 2^30",
           (long long)p->gamma_num, (long long)p->gamma_den);
-  if (p->weighting != SFCDD_WEIGHT_NONE && p->weighting != SFCDD_WEIGHT_OMEGA)
+  if (p->weighting != SFCDD_WEIGHT_NONE && p->weighting != SFCDD_WEIGHT_OMEGA && p->weighting != SFCDD_WEIGHT_D)
     GFAIL(SFCDD_EINVAL, "weighting = %d", p->weighting);
-  if (p->variant != SFCDD_ADDITIVE && p->variant != SFCDD_BALANCED) GFAIL(SFCDD_EINVAL, "variant = %d", p->variant);
+  if (p->variant != SFCDD_ADDITIVE && p->variant != SFCDD_BALANCED && p->variant != SFCDD_DEFLATED)
+    GFAIL(SFCDD_EINVAL, "variant = %d", p->variant);
   if (p->factor_dtype != SFCDD_FP64 && p->factor_dtype != SFCDD_FP32)
     GFAIL(SFCDD_EINVAL, "factor_dtype = %d", p->factor_dtype);
   if (p->local_solver != SFCDD_LOCAL_CHOLESKY && p->local_solver != SFCDD_LOCAL_INVERSE)
@@ -632,7 +633,8 @@ void fine_apply(sfcdd_ctx* c, const double* w, double* y, const int32_t* mask = 
     local_solves(c, w, c->trsv_waves, mask);
   }
   ProfScope ps(c, SFCDD_K_SCATTER);
-  launch_scatter(c->batch(), c->d_ta, c->d_Ni, c->d_doff, c->d_omega, c->dbuf, y, c->stream);
+  launch_scatter(c->batch(), c->weighting == SFCDD_WEIGHT_D, c->d_ta, c->d_Ni, c->d_doff, c->d_omega,
+                 c->dbuf, y, c->stream);
 }
 
 void spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, double* partials) {
@@ -655,6 +657,14 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h, const int32_t* mask = nul
     spmv(c, 0, y, v, nullptr, nullptr);                         // v = A y
     coarse_solve(c, v, mask);                                   // d0 = A0^{-1} R0 A y
     launch_combine(B, COMB_BAL_FINAL, c->d0, y, t, h, s);      // h = y - F A y + F g
+  } else if (c->variant == SFCDD_DEFLATED) {
+    double *t = c->vec[V_T], *y = c->vec[V_Y], *v = c->vec[V_V];
+    coarse_solve(c, g, mask);                                   // d0 = A0^{-1} R0 g
+    launch_combine(B, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
+    fine_apply(c, g, y, mask);                                  // y = C1^{-1} g
+    spmv(c, 0, y, v, nullptr, nullptr);                         // v = A y
+    coarse_solve(c, v, mask);                                   // d0 = A0^{-1} R0 A y
+    launch_combine(B, COMB_BAL_FINAL, c->d0, y, t, h, s);      // h = G^T C1^{-1} g + F g
   } else {
     coarse_solve(c, g, mask);
     fine_apply(c, g, h, mask);
@@ -992,7 +1002,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   if (method != SFCDD_PCG && method != SFCDD_FCG && method != SFCDD_RICHARDSON)
     FAIL(c, SFCDD_EINVAL, "method = %d", method);
   // balanced form: coarse-corrected start, then one coarse solve per iteration
-  const bool proj = c->variant == SFCDD_BALANCED && !plain;
+  const bool proj = (c->variant == SFCDD_BALANCED || c->variant == SFCDD_DEFLATED) && !plain;
   // preconditioner inside the iteration: grids that are not updating skip
   // their subdomain and coarse solves
   auto precond = [&](const double* g, double* h) {

@@ -108,6 +108,32 @@ def test_apply_fp64_hilbert(levels, P, gamma, variant):
     assert relerr(h, O.apply(r)) <= FP64_TOL
 
 
+@pytest.mark.parametrize("variant,weighting", [("deflated", "omega"), ("balanced", "D"), ("additive", "D"),
+                                               ("deflated", "D")])
+@pytest.mark.parametrize("levels,P,gamma", SMALL)
+def test_apply_fp64_deflated_and_D_weights(levels, P, gamma, variant, weighting):
+    announce("apply64 variants", levels, P, gamma, variant, weighting)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma, weighting=weighting, variant=variant)
+    S = _solver(levels, P, gamma, weighting=weighting, variant=variant)
+    r = uniform_pm1(19, g.N)
+    h = host(S.apply(dvec(r)))
+    assert relerr(h, O.apply(r)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("variant", ["balanced", "deflated"])
+def test_fcg_with_D_weights_matches_exact(variant):
+    """D_i weights make the preconditioner non-symmetric for gamma = 1/4:
+    flexible CG still converges to the exact solution."""
+    levels, P, gamma = (5, 4, 3), 12, Fraction(1, 4)
+    announce("fcg D", variant)
+    g = Grid(levels=levels)
+    f = uniform_pm1(10, g.N)
+    S = _solver(levels, P, gamma, weighting="D", variant=variant)
+    x, info = S.solve(dvec(f), rtol=1e-12, method="fcg", max_iter=500)
+    assert relerr(host(x), exact.solve(g, f)) <= 1e-9
+
+
 def test_pcg_hilbert_iterations_and_solution():
     levels, P, gamma = (5, 4, 4), 16, Fraction(1, 2)
     announce("pcg hilbert")

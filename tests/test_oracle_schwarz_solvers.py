@@ -112,6 +112,27 @@ def test_balancing_start_keeps_residuals_in_kernel_of_R0(levels, P, gamma, q):
     assert np.allclose(S.apply_s(r), proj, atol=1e-12 * np.abs(proj).max())
 
 
+@pytest.mark.parametrize("levels,P,gamma,q", SMALL)
+def test_two_level_forms_reproduce_the_coarse_residual(levels, P, gamma, q):
+    """R_0 A C^{-1} r = R_0 r for the balanced and the deflated forms
+    (R_0 A G^T = 0 and R_0 A F = R_0), not for the additive one; on r with
+    R_0 r = 0 the balanced and deflated forms coincide."""
+    g = Grid(levels=levels)
+    r = uniform_pm1(8, g.N)
+    ops = {v: OracleSchwarz(g, P, gamma, q=q, variant=v) for v in ("balanced", "deflated", "additive")}
+    for v in ("balanced", "deflated"):
+        S = ops[v]
+        lhs = S.R0 @ (S.A @ S.apply_s(S.to_s(r)))
+        assert np.allclose(lhs, S.R0 @ S.to_s(r), atol=1e-10 * np.abs(S.R0 @ S.to_s(r)).max())
+    Sa = ops["additive"]
+    lhs = Sa.R0 @ (Sa.A @ Sa.apply_s(Sa.to_s(r)))
+    assert not np.allclose(lhs, Sa.R0 @ Sa.to_s(r), atol=1e-6 * np.abs(Sa.R0 @ Sa.to_s(r)).max())
+    Sb, Sd = ops["balanced"], ops["deflated"]
+    v = Sb.to_s(uniform_pm1(9, g.N))
+    r0 = v - Sb.A @ Sb.coarse_s(v)                     # R_0 r0 = 0
+    assert np.allclose(Sb.apply_s(r0), Sd.apply_s(r0), atol=1e-12 * np.abs(Sb.apply_s(r0)).max())
+
+
 def test_single_subdomain_is_exact():
     """P = 1: the only subdomain is the whole grid, so C_bal^{-1} = A^{-1}
     (PCG converges in one step) and additive PCG needs at most two."""
