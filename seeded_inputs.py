@@ -1,8 +1,9 @@
 """Seeded synthetic inputs shared by the oracle and the HIP path.
 
 This module holds input generation only: a counter-based random generator
-(splitmix64, as published by Steele, Lea and Flood, 2014) and the workload
-descriptions (grid levels, subdomain counts, overlap parameters, seeds).  It
+(splitmix64, as published by Steele, Lea and Flood, 2014), the workload
+descriptions (grid levels, subdomain counts, overlap parameters, seeds) and
+the manufactured test problem of the combination-technique study.  It
 contains none of the solver's arithmetic, so the oracle and the library can
 both draw the same right-hand sides and coefficients without sharing any
 method code.
@@ -59,6 +60,23 @@ def ct_levels(d: int, total: int, lmin: int) -> List[Tuple[int, ...]]:
         if sum(l) == total:
             out.append(tuple(l))
     return out
+
+
+def manufactured(x: np.ndarray):
+    """(u, f) of Sec. 4.3 at points x (M, d): u = |x| prod sin(pi x_j),
+    f = -Laplace(u) = -(s (d-1)/r + (2 pi / r) sum_i x_i cos(pi x_i) prod_{j!=i} sin(pi x_j)
+    - d pi^2 r s), r = |x|, s = prod sin(pi x_j)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    d = x.shape[1]
+    r = np.sqrt((x * x).sum(axis=1))
+    sn = np.sin(np.pi * x)
+    s = np.prod(sn, axis=1)
+    grad_term = np.zeros(x.shape[0])
+    for i in range(d):
+        others = np.prod(np.delete(sn, i, axis=1), axis=1) if d > 1 else np.ones(x.shape[0])
+        grad_term += x[:, i] * np.pi * np.cos(np.pi * x[:, i]) * others
+    lap = s * (d - 1) / r + 2.0 * grad_term / r - d * np.pi ** 2 * r * s
+    return r * s, -lap
 
 
 @dataclass
