@@ -230,6 +230,18 @@ sfcdd_status sfcdd_set_profiling(sfcdd_ctx* ctx, int32_t on);
 sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* ctx, int32_t kind, double* total_ms,
                                    int64_t* launches);
 
+/* Combination technique (Sec. 2, eq. combi): out[m] = sum_g weights[g] u_g(x_m)
+ * over the grids of the context (a batch set up with sfcdd_setup_batch, all
+ * of one dimension d <= 10), where u_g is the piecewise multilinear function
+ * of grid g's values (zero on the boundary of [0,1]^d).  weights_dev: device,
+ * ngrids doubles (e.g. (-1)^i binom(d-1, i) for the grids of layer i);
+ * u_dev: device, the concatenated grid vectors in the context's layout (as
+ * sfcdd_solve returns them); x_dev: device, M points of d coordinates,
+ * row-major; out_dev: device, M doubles.  Grids are summed in order, so the
+ * result is reproducible.  Asynchronous on the context stream. */
+sfcdd_status sfcdd_ct_combine(sfcdd_ctx* ctx, const double* weights_dev, const double* u_dev,
+                              const double* x_dev, int64_t M, double* out_dev);
+
 /* Streaming-read rate of the device, for roofline context: reads the device
  * buffer buf_dev (bytes, a multiple of 16, 16-byte aligned; its contents are
  * not changed) with a 16-byte-per-lane grid-stride kernel `repeats` times on

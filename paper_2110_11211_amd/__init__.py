@@ -36,7 +36,7 @@ EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", 
            "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
            "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
            "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_read_probe",
-           "sfcdd_destroy", "sfcdd_last_error"]
+           "sfcdd_ct_combine", "sfcdd_destroy", "sfcdd_last_error"]
 KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
 
 
@@ -408,3 +408,4 @@ def _autotune(self, repeats: int = 5):
 SFCSchwarz.autotune = _autotune
 
 from .autograd import PoissonSolve, solve_poisson  # noqa: E402,F401
+from .ct import CombinationTechnique  # noqa: E402,F401

@@ -584,6 +584,57 @@ void launch_axpy_scal(const Batch& B, const double* scal, int slot, const int32_
   hipLaunchKernelGGL(k_axpy_scal, dim3(2048), dim3(256), 0, s, B, scal, slot, active, x, z);
 }
 
+// Combination technique (Sec. 2, eq. combi): out[m] = sum_g w[g] u_g(x_m),
+// u_g the piecewise multilinear function of grid g's values (zero on the
+// boundary), grids summed in order (deterministic).  x: M points, d
+// coordinates each, row-major.  u in natural order per grid, or in curve
+// order (layout 1) through the position table.
+__global__ void k_ct_combine(Batch B, int layout, const int32_t* __restrict__ pos,
+                             const double* __restrict__ w, const double* __restrict__ u,
+                             const double* __restrict__ x, int64_t M, double* __restrict__ out) {
+  const int d = B.grids[0].d;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
+       m += (int64_t)gridDim.x * blockDim.x) {
+    const double* xm = x + m * d;
+    double acc = 0.0;
+    for (int gi = 0; gi < B.G; ++gi) {
+      const GridDesc& g = B.grids[gi];
+      int64_t k[MAXD];
+      double t[MAXD];
+      for (int j = 0; j < d; ++j) {
+        const double sj = xm[j] * (double)(g.n[j] + 1);
+        int64_t kj = (int64_t)floor(sj);
+        kj = kj < 0 ? 0 : (kj > g.n[j] ? g.n[j] : kj);
+        k[j] = kj;
+        t[j] = sj - (double)kj;
+      }
+      double val = 0.0;
+      for (int corner = 0; corner < (1 << d); ++corner) {
+        double wt = 1.0;
+        int64_t nat = 0;
+        bool inside = true;
+        for (int j = 0; j < d; ++j) {
+          const int b = (corner >> j) & 1;
+          wt *= b ? t[j] : 1.0 - t[j];
+          const int64_t idx = k[j] + b;
+          if (idx < 1 || idx > g.n[j]) inside = false;
+          nat += (idx - 1) * g.stride[j];
+        }
+        if (inside) val += wt * u[layout ? (int64_t)pos[g.goff + nat] : g.goff + nat];
+      }
+      acc += w[gi] * val;
+    }
+    out[m] = acc;
+  }
+}
+
+void launch_ct_combine(const Batch& B, int layout, const int32_t* pos, const double* w, const double* u,
+                       const double* x, int64_t M, double* out, hipStream_t s) {
+  const int64_t nb = (M + 255) / 256;
+  hipLaunchKernelGGL(k_ct_combine, dim3((unsigned)(nb < 65536 ? (nb > 0 ? nb : 1) : 65536)), dim3(256), 0, s,
+                     B, layout, pos, w, u, x, M, out);
+}
+
 // Streaming read of n float4 (grid-stride); the sum is written only under a
 // condition that never holds for the probe's input, so the loads stay.
 __global__ __launch_bounds__(256) void k_read_probe(const float4* __restrict__ a, int64_t n,

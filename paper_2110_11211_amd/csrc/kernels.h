@@ -163,6 +163,8 @@ void launch_finalize_vec(int nvals, const double* partials, double* out, hipStre
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
 void launch_zero(int64_t n, double* a, hipStream_t s);
 void launch_read_probe(const void* buf, int64_t bytes, hipStream_t s);
+void launch_ct_combine(const Batch& B, int layout, const int32_t* pos, const double* w, const double* u,
+                       const double* x, int64_t M, double* out, hipStream_t s);
 
 // Scalar slots of the solver's per-grid device scalars S[g * S_COUNT + slot].
 enum {

@@ -1402,6 +1402,20 @@ sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
   return SFCDD_OK;
 }
 
+sfcdd_status sfcdd_ct_combine(sfcdd_ctx* c, const double* weights, const double* u, const double* x,
+                              int64_t M, double* out) {
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  if (M < 0 || (M > 0 && (!weights || !u || !x || !out))) FAIL(c, SFCDD_EINVAL, "ct_combine: NULL argument");
+  const int d = c->grid[0].desc.d;
+  for (int g = 1; g < c->G; ++g)
+    if (c->grid[g].desc.d != d) FAIL(c, SFCDD_EINVAL, "ct_combine: grids of different dimension");
+  if (d > 10) FAIL(c, SFCDD_EINVAL, "ct_combine: d = %d > 10", d);
+  if (M == 0) return SFCDD_OK;
+  launch_ct_combine(c->batch(), c->layout, c->pos, weights, u, x, M, out, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return SFCDD_OK;
+}
+
 sfcdd_status sfcdd_read_probe(const void* buf, size_t bytes, void* hip_stream, int32_t repeats,
                               double* best_ms) {
   sfcdd_ctx* c = nullptr;

@@ -37,6 +37,8 @@ SMALL = [  # levels, P, gamma
     ((4, 4), 6, Fraction(0)),          # no overlap
     ((2, 3, 2, 2), 9, Fraction(1, 3)),
     ((7, 2), 11, Fraction(1, 2)),      # ragged subdomains (N_i not multiples of 64)
+    ((3, 1, 1), 7, Fraction(1, 4)),    # P = N, one point per piece, level-1 dimensions
+    ((1, 2, 3), 6, Fraction(1, 4)),    # leading level-1 dimension (combination grids)
 ]
 
 
