@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
+# (d, L) of the combination-technique runs (Sec. 4.3 setting, L <= 17 - d)
+CT_RUNS = [(2, 14), (4, 12), (6, 10)]
 
 
 def parse():
@@ -188,40 +190,79 @@ def run_batch(w, fdtype, steps, warmup, sequential=False):
 
 
 def ct_batch_report(steps, warmup):
-    import numpy as np
+    """The 84-grid layer batched (FP32 and FP64 factors) and grid after grid.
+    Returns the report and the solutions, which the oracle leg checks."""
     from seeded_inputs import workloads
-    from oracle.grid import Grid
-    from oracle import exact
     w = workloads()["c4"]
     b32, it32, x32, waves, offs = run_batch(w, "fp32", steps, warmup)
     b64, it64, x64, _, _ = run_batch(w, "fp64", max(1, steps // 2), warmup)
     s32, _, _, _, _ = run_batch(w, "fp32", 1, 1, sequential=True)
-    err32 = err64 = 0.0
-    for g in range(len(w.levels)):
-        ref = exact.solve(Grid(levels=w.levels[g]), w.rhs(g))
-        nr = np.linalg.norm(ref)
-        err32 = max(err32, float(np.linalg.norm(x32[offs[g]:offs[g + 1]] - ref) / nr))
-        err64 = max(err64, float(np.linalg.norm(x64[offs[g]:offs[g + 1]] - ref) / nr))
-    return {"workload": w.name, "grids": len(w.levels), "N_total": int(offs[-1]),
-            "batched_fp32_ms": round(b32, 3), "batched_fp64_ms": round(b64, 3),
-            "sequential_fp32_ms": round(s32, 3),
-            "speedup_batched_vs_sequential": round(s32 / b32, 3),
-            "speedup_fp32_vs_fp64": round(b64 / b32, 3),
-            "max_iterations_fp32": it32, "max_iterations_fp64": it64, "trsv_waves": waves,
-            "max_rel_error_vs_exact_fp32": err32, "max_rel_error_vs_exact_fp64": err64,
-            "note": "setup + autotune + solve of all 84 grids to 1e-9 per step"}
+    rep = {"workload": w.name, "grids": len(w.levels), "N_total": int(offs[-1]),
+           "batched_fp32_ms": round(b32, 3), "batched_fp64_ms": round(b64, 3),
+           "sequential_fp32_ms": round(s32, 3),
+           "speedup_batched_vs_sequential": round(s32 / b32, 3),
+           "speedup_fp32_vs_fp64": round(b64 / b32, 3),
+           "max_iterations_fp32": it32, "max_iterations_fp64": it64, "trsv_waves": waves,
+           "max_rel_error_vs_exact_fp32": None, "max_rel_error_vs_exact_fp64": None,
+           "note": "setup + autotune + solve of all 84 grids to 1e-9 per step"}
+    return rep, {"w": w, "offs": offs, "x32": x32, "x64": x64}
+
+
+def ct_solve_report(d, L, steps, warmup, npts=20000):
+    """The combination-technique experiment of Sec. 4.3 on one GPU: every grid
+    of the level-L combination in d dimensions (Phat = 2^(L-8), so about 2^8
+    points per subdomain; gamma = 1/4; FP32 factors; flexible CG to a relative
+    residual of 1e-8) set up and solved as one batch, then the combined
+    solution evaluated at npts seeded uniform points.  One step = setup +
+    solve + combination; the error is the maximum absolute error against the
+    manufactured solution at the points."""
+    from fractions import Fraction
+    import numpy as np
+    import torch
+    import paper_2110_11211_amd as m
+    from seeded_inputs import manufactured, uniform01
+    phat = 1 << max(0, L - 8)
+    CT = m.CombinationTechnique(d, L, phat=phat, gamma=Fraction(1, 4), factor_dtype="fp32")
+    f = np.concatenate([manufactured(CT.grid_points(g))[1] for g in range(CT.ngrids)])
+    f_dev = torch.tensor(f, dtype=torch.float64, device="cuda:0")
+    X = uniform01(8000 + 10 * d + L, npts * d).reshape(npts, d)
+    x_dev = torch.tensor(X, dtype=torch.float64, device="cuda:0")
+    ws = CT.batch.ws
+    subdomains = sum(CT.batch._arr[g].P for g in range(CT.ngrids))
+    CT.close()
+    times, tcomb, iters = [], [], 0
+    for k in range(warmup + steps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        CT = m.CombinationTechnique(d, L, phat=phat, gamma=Fraction(1, 4), factor_dtype="fp32", workspace=ws)
+        u, _ = CT.solve(f_dev, rtol=1e-8, max_iter=500)
+        e1.record()
+        val = CT.evaluate(u, x_dev)
+        e2.record()
+        torch.cuda.synchronize()
+        its, _ = CT.batch.batch_stats()
+        iters = max(its)
+        CT.close()
+        if k >= warmup:
+            times.append(e0.elapsed_time(e2))
+            tcomb.append(e1.elapsed_time(e2))
+    err = float(np.abs(val.cpu().numpy() - manufactured(X)[0]).max())
+    return {"d": d, "L": L, "phat": phat, "grids": CT.ngrids, "subdomains": subdomains,
+            "N_total": int(f.size), "ms": round(sorted(times)[len(times) // 2], 3),
+            "combine_ms": round(sorted(tcomb)[len(tcomb) // 2], 3),
+            "max_iterations": iters, "max_abs_error_vs_manufactured": err, "points": npts}
 
 
 def adjoint_report(steps, warmup):
     """The d=6 anisotropic workload as a differentiable solve: forward solve,
     J = 1/2 ||u||^2, adjoint backward (second solve with the same factors and
     the coefficient-gradient kernel), FP32 factors, rtol of the workload."""
-    import numpy as np
     import torch
     import paper_2110_11211_amd as m
     from seeded_inputs import workloads
-    from oracle.grid import Grid
-    from oracle import exact, grad as ograd
     w = workloads()["c3"]
     f0 = w.rhs()
     times = []
@@ -239,15 +280,10 @@ def adjoint_report(steps, warmup):
         torch.cuda.synchronize()
         if k >= warmup:
             times.append(e0.elapsed_time(e1))
-    g = Grid(levels=w.levels[0], coeff=w.coeff)
-    u_ref = exact.solve(g, f0)
-    gf_ref, ga_ref = ograd.adjoint_gradient(g, u_ref, u_ref)
-    gf = f.grad.detach().cpu().numpy()
-    ga = a.grad.detach().numpy()
-    return {"workload": w.name, "N": w.N(), "P": w.P, "ms": round(sorted(times)[len(times) // 2], 3),
-            "rel_error_grad_f": float(np.linalg.norm(gf - gf_ref) / np.linalg.norm(gf_ref)),
-            "max_rel_error_grad_a": float(np.max(np.abs(ga - ga_ref) / np.abs(ga_ref))),
-            "note": "setup + forward solve + adjoint solve + coefficient gradient, FP32 factors, rtol 1e-9"}
+    rep = {"workload": w.name, "N": w.N(), "P": w.P, "ms": round(sorted(times)[len(times) // 2], 3),
+           "rel_error_grad_f": None, "max_rel_error_grad_a": None,
+           "note": "setup + forward solve + adjoint solve + coefficient gradient, FP32 factors, rtol 1e-9"}
+    return rep, {"w": w, "f0": f0, "gf": f.grad.detach().cpu().numpy(), "ga": a.grad.detach().numpy()}
 
 
 def cpu_baseline(w, iterations, nsample):
@@ -297,6 +333,35 @@ def cpu_baseline(w, iterations, nsample):
             "setup_s": setup, "per_iteration_s": per_iter}
 
 
+def oracle_checks(w, x_head, ct_raw, adj_raw):
+    """Part of the CPU-baseline leg: errors of the GPU results against the
+    oracle's exact DST-I solutions and adjoint gradients."""
+    import numpy as np
+    from oracle.grid import Grid
+    from oracle import exact, grad as ograd
+    out = {}
+    xs = exact.solve(Grid(levels=w.levels[0]), w.rhs())
+    out["headline_rel_error_vs_exact"] = float(np.linalg.norm(x_head - xs) / np.linalg.norm(xs))
+    if ct_raw is not None:
+        wc, offs = ct_raw["w"], ct_raw["offs"]
+        e32 = e64 = 0.0
+        for g in range(len(wc.levels)):
+            ref = exact.solve(Grid(levels=wc.levels[g]), wc.rhs(g))
+            nr = np.linalg.norm(ref)
+            e32 = max(e32, float(np.linalg.norm(ct_raw["x32"][offs[g]:offs[g + 1]] - ref) / nr))
+            e64 = max(e64, float(np.linalg.norm(ct_raw["x64"][offs[g]:offs[g + 1]] - ref) / nr))
+        out["ct_batch_max_rel_error_fp32"] = e32
+        out["ct_batch_max_rel_error_fp64"] = e64
+    if adj_raw is not None:
+        wa = adj_raw["w"]
+        g = Grid(levels=wa.levels[0], coeff=wa.coeff)
+        u_ref = exact.solve(g, adj_raw["f0"])
+        gf_ref, ga_ref = ograd.adjoint_gradient(g, u_ref, u_ref)
+        out["adjoint_rel_error_grad_f"] = float(np.linalg.norm(adj_raw["gf"] - gf_ref) / np.linalg.norm(gf_ref))
+        out["adjoint_max_rel_error_grad_a"] = float(np.max(np.abs(adj_raw["ga"] - ga_ref) / np.abs(ga_ref)))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -337,12 +402,7 @@ def main():
         f64 = run_path(w, f_dev, "fp64", args.local, max(2, args.steps // 2), args.warmup, ws_cache)
     ws_cache.clear()
 
-    # accuracy of the headline solution against the exact DST-I solution
-    from oracle.grid import Grid
-    from oracle import exact
-    xs = exact.solve(Grid(levels=w.levels[0]), w.rhs())
     xh = head["x"].cpu().numpy()
-    err = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
 
     info = head["info"]
     es = 4
@@ -389,7 +449,7 @@ def main():
         "headline": {"setup_ms": round(head["setup_ms"], 3), "solve_ms": round(head["solve_ms"], 3),
                      "ms_min": round(head["ms_min"], 3), "iterations": head["iterations"],
                      "restarts": head["restarts"], "rel_residual": head["rel_residual"],
-                     "rel_error_vs_exact": err, "setup_phases_ms": info["setup_ms"]},
+                     "rel_error_vs_exact": None, "setup_phases_ms": info["setup_ms"]},
         "gbps": {"schwarz_local_solve": round(gbs_local, 1), "spmv": round(gbs_spmv, 1),
                  "local_solve_avg_ms": avg_local, "spmv_avg_ms": avg_spmv},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in head["kernels"].items()},
@@ -416,12 +476,24 @@ def main():
                      "tflops": round(fflops / (factor_ms * 1e-3) / 1e12, 2), "peak_tflops": FP32_MFMA_PEAK_TFLOPS,
                      "frac": round(fflops / (factor_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
                      "note": "FP32 MFMA; runs concurrently with the coarse setup"}
+    ct_raw = adj_raw = None
     if not args.no_batch:
-        out["ct_batch"] = ct_batch_report(max(2, args.steps // 2), 1)
-        out["adjoint"] = adjoint_report(max(2, args.steps // 2), 1)
+        out["ct_batch"], ct_raw = ct_batch_report(max(2, args.steps // 2), 1)
+        out["adjoint"], adj_raw = adjoint_report(max(2, args.steps // 2), 1)
+        out["combination"] = [ct_solve_report(d, L, max(2, args.steps // 2), 1) for d, L in CT_RUNS]
     if not args.no_cpu_baseline:
+        # the oracle leg: CPU timing of the oracle, then the accuracy checks
         iters = f64["iterations"] if f64 is not None else head["iterations"]
         out["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_sample)
+        chk = oracle_checks(w, xh, ct_raw, adj_raw)
+        out["cpu_baseline"]["accuracy_vs_oracle"] = chk
+        out["headline"]["rel_error_vs_exact"] = chk["headline_rel_error_vs_exact"]
+        if ct_raw is not None:
+            out["ct_batch"]["max_rel_error_vs_exact_fp32"] = chk["ct_batch_max_rel_error_fp32"]
+            out["ct_batch"]["max_rel_error_vs_exact_fp64"] = chk["ct_batch_max_rel_error_fp64"]
+        if adj_raw is not None:
+            out["adjoint"]["rel_error_grad_f"] = chk["adjoint_rel_error_grad_f"]
+            out["adjoint"]["max_rel_error_grad_a"] = chk["adjoint_max_rel_error_grad_a"]
     print(json.dumps(out), flush=True)
 
 

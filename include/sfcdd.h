@@ -49,7 +49,9 @@ typedef enum {
   SFCDD_EDEVICE = -3,    /* a HIP runtime call failed                          */
   SFCDD_ENOTCONV = -4,   /* solve reached max_iter before rtol                 */
   SFCDD_EOVERFLOW = -5,  /* N >= 2^31, or d * max_j l_j > 64 key bits          */
-  SFCDD_ENOTSPD = -6     /* a local or coarse matrix was not positive definite */
+  SFCDD_ENOTSPD = -6,    /* a local or coarse matrix was not positive definite */
+  SFCDD_ESTAGNATED = -7  /* the true residual stopped decreasing above rtol: the
+                            FP64 rounding floor of the grid lies above rtol      */
 } sfcdd_status;
 
 /* Weights of the one-level sum (eqs. w1levprec, Di, omegai): none, the scalar
@@ -68,9 +70,10 @@ enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
  * (Morton), or Hilbert (Skilling's construction), both at the resolution of
  * the finest direction on the scaled coordinates k_j 2^(max l - l_j). */
 enum { SFCDD_CURVE_ZORDER = 0, SFCDD_CURVE_HILBERT = 1 };
-/* Flag OR-ed into the method of sfcdd_solve: start from x0 exactly as given
- * and apply the full balanced operator every iteration (see sfcdd_solve). */
-enum { SFCDD_SOLVE_PLAIN_START = 256 };
+/* Flags OR-ed into the method of sfcdd_solve: start from x0 exactly as given
+ * and apply the full balanced operator every iteration; stop on the recursive
+ * residual alone (see sfcdd_solve). */
+enum { SFCDD_SOLVE_PLAIN_START = 256, SFCDD_SOLVE_RECURSIVE = 512 };
 
 typedef struct {
   int32_t d;                 /* dimension, 1 <= d <= 16                                */
@@ -165,7 +168,15 @@ sfcdd_status sfcdd_matvec(sfcdd_ctx* ctx, const double* x_dev, double* y_dev);
  * x0 = 0), solution on exit; may not alias b_dev.  Stops when the relative
  * residual ||b - A x||_2 / ||b||_2 <= rtol (checked on the recursive residual
  * and confirmed on the true residual, restarting from the current x when they
- * disagree), or after max_iter iterations (ENOTCONV).
+ * disagree), or after max_iter iterations (ENOTCONV).  A grid whose true
+ * residual has not halved since its previous restart has reached the rounding
+ * floor of FP64 for its matrix (about eps ||A|| ||x|| / ||b||, which exceeds
+ * 1e-8 on strongly anisotropic grids with 2^14 points along one direction):
+ * it stops there, and the call returns ESTAGNATED with x the last iterate.
+ * With SFCDD_SOLVE_RECURSIVE OR-ed into method, the stopping test is the
+ * recursive residual of the iteration alone, as in the paper's algorithms
+ * (Sec. 4: ||r_k|| / ||r_0|| with r_0 = b for x0 = 0); info.rel_residual is then
+ * the recursive one.
  * method: SFCDD_PCG, SFCDD_FCG (flexible CG, beta = z'(r_new - r_old)/z'r_old,
  * for the FP32-factor preconditioner) or SFCDD_RICHARDSON (x += xi C^{-1} r;
  * xi <= 0 estimates xi = 2/(lmin + lmax) from 30 Lanczos steps on the residual
@@ -237,8 +248,9 @@ sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* ctx, int32_t kind, double* total_m
  * ngrids doubles (e.g. (-1)^i binom(d-1, i) for the grids of layer i);
  * u_dev: device, the concatenated grid vectors in the context's layout (as
  * sfcdd_solve returns them); x_dev: device, M points of d coordinates,
- * row-major; out_dev: device, M doubles.  Grids are summed in order, so the
- * result is reproducible.  Asynchronous on the context stream. */
+ * row-major (points outside [0,1]^d are extrapolated from the boundary cell);
+ * out_dev: device, M doubles.  The summation order over the grids is fixed, so
+ * the result is reproducible.  Asynchronous on the context stream. */
 sfcdd_status sfcdd_ct_combine(sfcdd_ctx* ctx, const double* weights_dev, const double* u_dev,
                               const double* x_dev, int64_t M, double* out_dev);
 

@@ -20,15 +20,16 @@ from typing import Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsfcdd.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EOVERFLOW, ENOTSPD = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EOVERFLOW, ENOTSPD, ESTAGNATED = 0, -1, -2, -3, -4, -5, -6, -7
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOTCONV: "ENOTCONV",
-           EOVERFLOW: "EOVERFLOW", ENOTSPD: "ENOTSPD"}
+           EOVERFLOW: "EOVERFLOW", ENOTSPD: "ENOTSPD", ESTAGNATED: "ESTAGNATED"}
 WEIGHTING = {"none": 0, "omega": 1, "D": 2}
 VARIANT = {"additive": 0, "balanced": 1, "deflated": 2}
 FACTOR_DTYPE = {"fp64": 0, "fp32": 1}
 LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
 METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}
 SOLVE_PLAIN_START = 256
+SOLVE_RECURSIVE = 512
 CURVE = {"zorder": 0, "hilbert": 1}
 LAYOUT = {"natural": 0, "sfc": 1}
 
@@ -251,15 +252,17 @@ class SFCSchwarz:
         return y
 
     def solve(self, b, x0=None, rtol=1e-9, max_iter=1000, method="pcg", xi=0.0, check=True,
-              plain_start=False):
+              plain_start=False, recursive=False):
         """x with A x = b to relative residual rtol; returns (x, info dict).
         plain_start: balanced variant only, start from x0 as given and apply
         the full balanced operator every iteration (otherwise the start is
-        coarse-corrected and each iteration needs one coarse solve)."""
+        coarse-corrected and each iteration needs one coarse solve).
+        recursive: stop on the recursive residual of the iteration alone
+        (otherwise it is confirmed on the true residual)."""
         torch = self._torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         inf = SolveInfo()
-        code = METHOD[method] | (SOLVE_PLAIN_START if plain_start else 0)
+        code = METHOD[method] | (SOLVE_PLAIN_START if plain_start else 0) | (SOLVE_RECURSIVE if recursive else 0)
         st = lib().sfcdd_solve(self.ctx, self._vec(b, "b"), self._vec(x, "x"), float(rtol), int(max_iter),
                                code, float(xi), ctypes.byref(inf))
         if check:

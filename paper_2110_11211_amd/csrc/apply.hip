@@ -10,6 +10,7 @@ namespace sfcdd {
 // SpMV with the (2d+1)-point FD matrix, vectors in curve order (Alg. 3 A x).
 // MODE 0: y = A x over the whole batch.  MODE 1: y = A x with per-grid
 // partials of x . y.  MODE 2: y = b - A x with per-grid partials of y . y.
+// MODE 3: y = b - A x over the whole batch (no partials).
 // Reductions: block (x, g) covers grid g only; partials[g * rbx + x]; the
 // grid of blocks is fixed, so the sums are deterministic.
 template <int MODE>
@@ -22,7 +23,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
   double acc = 0.0;
   const int64_t Nt = B.Ntot;
   int64_t start, hi;
-  if (MODE == 0) {
+  if (MODE == 0 || MODE == 3) {
     start = 0;
     hi = Nt;
   } else {
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
   }
   for (int64_t p = start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const GridDesc& g = B.grids[MODE == 0 ? grid_of(B, B.gid, p) : (int)blockIdx.y];
+    const GridDesc& g = B.grids[MODE == 0 || MODE == 3 ? grid_of(B, B.gid, p) : (int)blockIdx.y];
     const double xp = x[p];
     double v = g.diag * xp;
     for (int j = 0; j < g.d; ++j) {
@@ -43,12 +44,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
       if (q >= 0) sj += x[q];
       v -= g.c[j] * sj;
     }
-    if (MODE == 2) v = b[p] - v;
+    if (MODE == 2 || MODE == 3) v = b[p] - v;
     y[p] = v;
     if (MODE == 1) acc += xp * v;
     if (MODE == 2) acc += v * v;
   }
-  if (MODE != 0) {
+  if (MODE == 1 || MODE == 2) {
     const double sm = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sm;
   }
@@ -64,8 +65,11 @@ void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, 
                        partials);
   } else {
     const int64_t nb = (B.Ntot + RED_THREADS - 1) / RED_THREADS;
-    hipLaunchKernelGGL(k_spmv<0>, dim3((unsigned)(nb < 65535 * 16 ? nb : 65535 * 16)),
-                       dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
+    const dim3 grid((unsigned)(nb < 65535 * 16 ? nb : 65535 * 16));
+    if (mode == 3)
+      hipLaunchKernelGGL(k_spmv<3>, grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
+    else
+      hipLaunchKernelGGL(k_spmv<0>, grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
   }
 }
 
@@ -292,7 +296,6 @@ __global__ void k_combine(Batch B, const double* __restrict__ d0, const double* 
     if (MODE == COMB_PROLONG) out[p] = t;
     if (MODE == COMB_ADD_PROLONG) out[p] = a[p] + t;
     if (MODE == COMB_BAL_FINAL) out[p] = a[p] - t + b[p];
-    if (MODE == COMB_SUB_PROLONG) out[p] = a[p] - t;
   }
 }
 
@@ -304,10 +307,8 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
     hipLaunchKernelGGL(k_combine<COMB_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
   else if (mode == COMB_ADD_PROLONG)
     hipLaunchKernelGGL(k_combine<COMB_ADD_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
-  else if (mode == COMB_BAL_FINAL)
-    hipLaunchKernelGGL(k_combine<COMB_BAL_FINAL>, grid, dim3(256), 0, s, B, d0, a, b, out);
   else
-    hipLaunchKernelGGL(k_combine<COMB_SUB_PROLONG>, grid, dim3(256), 0, s, B, d0, a, b, out);
+    hipLaunchKernelGGL(k_combine<COMB_BAL_FINAL>, grid, dim3(256), 0, s, B, d0, a, b, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,51 +587,71 @@ void launch_axpy_scal(const Batch& B, const double* scal, int slot, const int32_
 
 // Combination technique (Sec. 2, eq. combi): out[m] = sum_g w[g] u_g(x_m),
 // u_g the piecewise multilinear function of grid g's values (zero on the
-// boundary), grids summed in order (deterministic).  x: M points, d
-// coordinates each, row-major.  u in natural order per grid, or in curve
-// order (layout 1) through the position table.
-__global__ void k_ct_combine(Batch B, int layout, const int32_t* __restrict__ pos,
-                             const double* __restrict__ w, const double* __restrict__ u,
-                             const double* __restrict__ x, int64_t M, double* __restrict__ out) {
+// boundary).  x: M points, d coordinates each, row-major.  u in natural order
+// per grid, or in curve order (layout 1) through the position table.
+// One wave per point: lane l evaluates grids l, l + 64, ... (in order) and
+// the wave sums the 64 lane totals with a fixed butterfly, so the result is
+// deterministic.  Per grid: the cell of the point, then the 2^d corners with
+// an incremental index; corners on the boundary (value zero) are skipped.
+__global__ __launch_bounds__(256) void k_ct_combine(Batch B, int layout, const int32_t* __restrict__ pos,
+                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ x, int64_t M,
+                                                    double* __restrict__ out) {
   const int d = B.grids[0].d;
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
-       m += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t m = wave; m < M; m += nwaves) {
     const double* xm = x + m * d;
+    double xs[MAXD];
+    for (int j = 0; j < d; ++j) xs[j] = xm[j];
     double acc = 0.0;
-    for (int gi = 0; gi < B.G; ++gi) {
+    for (int gi = lane; gi < B.G; gi += 64) {
       const GridDesc& g = B.grids[gi];
-      int64_t k[MAXD];
-      double t[MAXD];
+      // per direction: corner weights wt[j][b], index offsets, and which of
+      // the two corners are interior points
+      double w0[MAXD], w1[MAXD];
+      int64_t base = 0, st[MAXD];
+      unsigned ok0 = 0, ok1 = 0;
       for (int j = 0; j < d; ++j) {
-        const double sj = xm[j] * (double)(g.n[j] + 1);
-        int64_t kj = (int64_t)floor(sj);
-        kj = kj < 0 ? 0 : (kj > g.n[j] ? g.n[j] : kj);
-        k[j] = kj;
-        t[j] = sj - (double)kj;
+        const double sj = xs[j] * (double)(g.n[j] + 1);
+        // cell index clamped to 0..n_j (a NaN coordinate gives cell 0, so
+        // every index stays in range; the weights then carry the NaN)
+        double fl = floor(sj);
+        if (!(fl >= 0.0)) fl = 0.0;
+        if (fl > (double)g.n[j]) fl = (double)g.n[j];
+        const int64_t kj = (int64_t)fl;
+        const double t = sj - fl;
+        w0[j] = 1.0 - t;
+        w1[j] = t;
+        st[j] = g.stride[j];
+        base += (kj - 1) * g.stride[j];
+        if (kj >= 1) ok0 |= 1u << j;
+        if (kj + 1 <= g.n[j]) ok1 |= 1u << j;
       }
       double val = 0.0;
-      for (int corner = 0; corner < (1 << d); ++corner) {
+      for (unsigned corner = 0; corner < (1u << d); ++corner) {
+        if ((~corner & ~ok0 & ((1u << d) - 1)) || (corner & ~ok1)) continue;
         double wt = 1.0;
-        int64_t nat = 0;
-        bool inside = true;
+        int64_t nat = base;
         for (int j = 0; j < d; ++j) {
-          const int b = (corner >> j) & 1;
-          wt *= b ? t[j] : 1.0 - t[j];
-          const int64_t idx = k[j] + b;
-          if (idx < 1 || idx > g.n[j]) inside = false;
-          nat += (idx - 1) * g.stride[j];
+          const bool bj = (corner >> j) & 1u;
+          wt *= bj ? w1[j] : w0[j];
+          nat += bj ? st[j] : 0;
         }
-        if (inside) val += wt * u[layout ? (int64_t)pos[g.goff + nat] : g.goff + nat];
+        val += wt * u[layout ? (int64_t)pos[g.goff + nat] : g.goff + nat];
       }
       acc += w[gi] * val;
     }
-    out[m] = acc;
+    acc = wave_sum(acc);
+    if (lane == 0) out[m] = acc;
   }
 }
 
 void launch_ct_combine(const Batch& B, int layout, const int32_t* pos, const double* w, const double* u,
                        const double* x, int64_t M, double* out, hipStream_t s) {
-  const int64_t nb = (M + 255) / 256;
+  const int64_t nb = (M + 3) / 4;  // four points (waves) per workgroup
   hipLaunchKernelGGL(k_ct_combine, dim3((unsigned)(nb < 65536 ? (nb > 0 ? nb : 1) : 65536)), dim3(256), 0, s,
                      B, layout, pos, w, u, x, M, out);
 }

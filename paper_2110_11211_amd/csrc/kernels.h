@@ -109,7 +109,7 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 
 // ---- per-iteration operators ---------------------------------------------
 // mode 0: y = A x;  1: y = A x, per-grid partials of x.y;  2: y = b - A x,
-// per-grid partials of y.y.
+// per-grid partials of y.y;  3: y = b - A x.
 void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
                  const double* b, double* partials, hipStream_t s);
 // active (nullable): per-grid solver flags; subdomains of grids that are not
@@ -197,8 +197,7 @@ enum {
 enum {
   COMB_PROLONG = 0,          // out = R0^T d0
   COMB_ADD_PROLONG,          // out = a + R0^T d0
-  COMB_BAL_FINAL,            // out = a - R0^T d0 + b      (y - F A y + F g)
-  COMB_SUB_PROLONG           // out = a - R0^T d0          (y - F A y)
+  COMB_BAL_FINAL             // out = a - R0^T d0 + b      (y - F A y + F g)
 };
 
 }  // namespace sfcdd

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <limits>
 
 #include "../../include/sfcdd.h"
 #include "common.h"
@@ -642,6 +643,8 @@ void spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, d
   launch_spmv(c->batch(), mode, c->nbr, x, y, b, partials, c->stream);
 }
 
+void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask);
+
 // h = C^{-1} g in curve order (Alg. 2; balanced form eq. balSW).
 // mask (nullable): solver flags; grids that are not updating may skip the
 // subdomain and coarse solves (their output is then unspecified).
@@ -658,13 +661,7 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h, const int32_t* mask = nul
     coarse_solve(c, v, mask);                                   // d0 = A0^{-1} R0 A y
     launch_combine(B, COMB_BAL_FINAL, c->d0, y, t, h, s);      // h = y - F A y + F g
   } else if (c->variant == SFCDD_DEFLATED) {
-    double *t = c->vec[V_T], *y = c->vec[V_Y], *v = c->vec[V_V];
-    coarse_solve(c, g, mask);                                   // d0 = A0^{-1} R0 g
-    launch_combine(B, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
-    fine_apply(c, g, y, mask);                                  // y = C1^{-1} g
-    spmv(c, 0, y, v, nullptr, nullptr);                         // v = A y
-    coarse_solve(c, v, mask);                                   // d0 = A0^{-1} R0 A y
-    launch_combine(B, COMB_BAL_FINAL, c->d0, y, t, h, s);      // h = G^T C1^{-1} g + F g
+    apply_s_defl(c, g, h, mask);                                // h = G^T C1^{-1} g + F g
   } else {
     coarse_solve(c, g, mask);
     fine_apply(c, g, h, mask);
@@ -672,17 +669,21 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h, const int32_t* mask = nul
   }
 }
 
-// Balanced operator on a residual r with R_0 r = 0 (F r = 0): the terms
-// t = F r and A t of eq. balSW vanish, so h = y - F A y with y = C1^{-1} r.
+// Deflated operator h = G^T C1^{-1} r + F r = y + F (r - A y), y = C1^{-1} r:
+// one coarse solve.  On a residual with R_0 r = 0 (F r = 0) it equals the
+// balanced operator of eq. balSW, whose terms t = F r and A t vanish there.
 // PCG and Richardson keep R_0 r_k = 0 once the start is coarse-corrected,
-// because R_0 A C^{-1} r = R_0 r, so each iteration needs one coarse solve.
-void apply_s_proj(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask = nullptr) {
+// because R_0 A (I - F A) = 0, so the balanced iteration runs on this form.
+// Unlike y - F A y (the same operator in exact arithmetic), it also corrects
+// the coarse component that rounding adds to r_k over the iterations, which
+// would otherwise stall the residual once it reaches that level.
+void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask) {
   const Batch B = c->batch();
   double *y = c->vec[V_Y], *v = c->vec[V_V];
   fine_apply(c, r, y, mask);                                   // y = C1^{-1} r
-  spmv(c, 0, y, v, nullptr, nullptr);                          // v = A y
-  coarse_solve(c, v, mask);                                    // d0 = A0^{-1} R0 A y
-  launch_combine(B, COMB_SUB_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y - F A y
+  spmv(c, 3, y, v, r, nullptr);                                // v = r - A y
+  coarse_solve(c, v, mask);                                    // d0 = A0^{-1} R0 (r - A y)
+  launch_combine(B, COMB_ADD_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y + F (r - A y)
 }
 
 // Copies the per-grid scalars to the pinned host buffer.
@@ -998,7 +999,8 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   if (!b_in || !x_io || b_in == x_io) FAIL(c, SFCDD_EINVAL, "b and x must be distinct non-NULL device vectors");
   if (!(rtol > 0.0) || max_iter < 0) FAIL(c, SFCDD_EINVAL, "need rtol > 0 and max_iter >= 0");
   const bool plain = (method & SFCDD_SOLVE_PLAIN_START) != 0;
-  method &= ~SFCDD_SOLVE_PLAIN_START;
+  const bool recursive = (method & SFCDD_SOLVE_RECURSIVE) != 0;
+  method &= ~(SFCDD_SOLVE_PLAIN_START | SFCDD_SOLVE_RECURSIVE);
   if (method != SFCDD_PCG && method != SFCDD_FCG && method != SFCDD_RICHARDSON)
     FAIL(c, SFCDD_EINVAL, "method = %d", method);
   // balanced form: coarse-corrected start, then one coarse solve per iteration
@@ -1006,7 +1008,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   // preconditioner inside the iteration: grids that are not updating skip
   // their subdomain and coarse solves
   auto precond = [&](const double* g, double* h) {
-    if (proj) apply_s_proj(c, g, h, c->active);
+    if (proj) apply_s_defl(c, g, h, c->active);
     else apply_s(c, g, h, c->active);
   };
   const hipStream_t s = c->stream;
@@ -1037,7 +1039,9 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     bb[g] = hs(c, g, S_BB);
     tol2[g] = rtol * rtol * bb[g];
   }
-  std::vector<int32_t> flags(G, ACT_RUN), its(G, 0);
+  std::vector<int32_t> flags(G, ACT_RUN), its(G, 0), stagnated(G, 0);
+  // true residual at each grid's previous restart (stagnation test)
+  std::vector<double> last_trr(G, std::numeric_limits<double>::infinity());
   sfcdd_solve_info inf{};
   int it = 0, restarts = 0;
   auto n_updating = [&]() {
@@ -1207,9 +1211,15 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
           if (flags[g] == ACT_CAND || (it >= max_iter && act_updating(flags[g]))) check = true;
         }
         c->active_shadow = flags;
-        if (check) {
+        if (check && recursive) {
+          // the recursive residual decides: candidates are done
+          for (int g = 0; g < G; ++g)
+            if (flags[g] == ACT_CAND || (it >= max_iter && act_updating(flags[g]))) flags[g] = ACT_DONE;
+          if ((st = write_active(c, flags))) return st;
+        } else if (check) {
           // confirm on the true residual; a grid whose true residual is still
-          // too large restarts from its current x (residual replacement)
+          // too large restarts from its current x (residual replacement),
+          // unless it has not halved since the grid's previous restart
           spmv(c, 2, x, tmp, b, c->partials);
           launch_finalize(B, FIN_TRR, c->partials, c->scal, nullptr, s);
           if ((st = read_scal(c))) return st;
@@ -1221,7 +1231,11 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
             rr[g] = trr;
             if (trr <= tol2[g]) {
               flags[g] = ACT_DONE;
+            } else if (flags[g] == ACT_CAND && trr > 0.25 * last_trr[g]) {
+              flags[g] = ACT_DONE;  // rounding floor reached
+              stagnated[g] = 1;
             } else if (flags[g] == ACT_CAND && it < max_iter && restarts < 8 * G) {
+              last_trr[g] = trr;
               const GridDesc& gd = c->grid[g].desc;
               launch_copy(gd.N, tmp + gd.goff, r + gd.goff, s);
               flags[g] = ACT_RESTART;
@@ -1252,7 +1266,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   prof_collect(c);
   c->last_iters = its;
   c->last_relres.assign(G, 0.0);
-  bool conv = true;
+  bool conv = true, stag_only = true;
   double worst = 0.0;
   int itmax = 0;
   for (int g = 0; g < G; ++g) {
@@ -1260,12 +1274,18 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     c->last_relres[g] = rel;
     worst = std::max(worst, rel);
     itmax = std::max(itmax, its[g]);
-    if (rr[g] > tol2[g]) conv = false;
+    if (rr[g] > tol2[g]) {
+      conv = false;
+      if (!stagnated[g]) stag_only = false;
+    }
   }
   inf.iterations = itmax;
   inf.restarts = restarts;
   inf.rel_residual = worst;
   if (info) *info = inf;
+  if (!conv && stag_only)
+    FAIL(c, SFCDD_ESTAGNATED, "true residual stagnated at %.3e above rtol %.1e after %d iterations "
+         "(the FP64 rounding floor of the grid)", worst, rtol, itmax);
   if (!conv) FAIL(c, SFCDD_ENOTCONV, "not converged after %d iterations (rel. residual %.3e)", itmax, worst);
   return SFCDD_OK;
 }

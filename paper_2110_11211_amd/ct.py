@@ -70,10 +70,15 @@ class CombinationTechnique:
         mesh = np.meshgrid(*reversed(axes), indexing="ij")
         return np.stack([m.reshape(-1) for m in reversed(mesh)], axis=1)
 
-    def solve(self, f, rtol=1e-9, max_iter=1000, method=None):
+    def solve(self, f, rtol=1e-8, max_iter=1000, method=None, recursive=True):
         """Solutions of all grids for the concatenated right-hand sides f
-        (device tensor, grid after grid, each in the context's layout)."""
-        return self.batch.solve(f, rtol=rtol, max_iter=max_iter, method=method or self.method)
+        (device tensor, grid after grid, each in the context's layout).  The
+        default stopping test is the one of Sec. 4.3, the relative recursive
+        residual of every grid below rtol: on the grids with 2^(L+d-1)
+        points along one axis the true residual has a rounding floor near
+        1e-8 in FP64."""
+        return self.batch.solve(f, rtol=rtol, max_iter=max_iter, method=method or self.method,
+                                recursive=recursive)
 
     def evaluate(self, u, x):
         """u^(c)(x) at the points x (contiguous float64 device tensor (M, d))

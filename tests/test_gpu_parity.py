@@ -368,3 +368,27 @@ def test_batch_ct_layer_84_grids(fdtype, method):
         Sg = _solver(w.levels[g], w.P, w.gamma, factor_dtype=fdtype)
         _, ig = Sg.solve(dvec(w.rhs(g)), rtol=1e-12, method=method, max_iter=400)
         assert abs(ig["iterations"] - its[g]) <= (1 if fdtype == "fp64" else 2), g
+
+
+def test_stagnation_status_and_recursive_criterion():
+    """A (14, 1) grid (16383 points along x_1): the FP64 rounding floor of the
+    true relative residual (about eps ||A|| ||x|| / ||b||, 4e-11 for this
+    right-hand side in the oracle's FP64 PCG) lies above 1e-12.
+    The verified criterion stops there with ESTAGNATED and an accurate x; the
+    recursive criterion of the paper's algorithms reaches rtol."""
+    levels = (14, 1)
+    announce("stagnation", levels)
+    g = Grid(levels=levels)
+    f0 = uniform_pm1(31, g.N)
+    ex = exact.solve(g, f0)
+    S = m.SFCSchwarz(levels=levels, P=128, gamma=Fraction(1, 4), factor_dtype="fp32")
+    with pytest.raises(m.SfcddError) as e:
+        S.solve(dvec(f0), rtol=1e-12, method="fcg", max_iter=400)
+    assert e.value.status == m.ESTAGNATED
+    x, info = S.solve(dvec(f0), rtol=1e-12, method="fcg", max_iter=400, check=False)
+    assert info["status"] == m.ESTAGNATED and info["iterations"] < 400
+    assert relerr(host(x), ex) <= 1e-9
+    x2, info2 = S.solve(dvec(f0), rtol=1e-12, method="fcg", max_iter=400, recursive=True)
+    assert info2["status"] == m.OK and info2["rel_residual"] <= 1e-12
+    assert relerr(host(x2), ex) <= 1e-9
+    S.close()
