@@ -249,60 +249,42 @@ constexpr size_t diag_lds_bytes() {
 // K = kfrom .. J-1 are formed in this workgroup; the terms K < kfrom (single
 // matrix, split-K) were precomputed as nparts partial tiles part[I][c].
 // acc += sign * sum_{K = k0}^{k1 - 1} A_K B_K^T for row-major global tiles
-// A_K = pa(K), B_K = pb(K), with two LDS buffers of two tiles each at lds:
-// the tiles of step K + 1 are staged while the MFMAs of step K run, one
-// barrier per step.
-template <typename T, typename FA, typename FB>
-__device__ __forceinline__ void gemm_loop_db(TileAcc<T>& acc, int k0, int k1, FA pa, FB pb, T* lds, T sign) {
+// A_K = pa(K), B_K = pb(K) (B = A when SYRK), two LDS buffers of two tiles
+// each at lds.  The loads run NPF steps ahead in registers, so a tile has NPF
+// tile products' time to arrive from memory.  Every step issues its loads
+// unconditionally (past the end they repeat the last tile) and the loop runs
+// in whole groups of NPF steps, so the code between a load and its use is
+// the same on every path and the wait before each LDS store covers only the
+// loads of that stage.  One barrier per step: the store into a buffer at
+// step K follows the barrier of step K - 1, which every wave passes only
+// after its products of step K - 2 on that buffer.
+constexpr int FACTOR_PF = 3;
+template <int NPF, bool SYRK, typename T, typename FA, typename FB>
+__device__ __forceinline__ void gemm_loop_pf(TileAcc<T>& acc, int k0, int k1, FA pa, FB pb, T* lds, T sign) {
   constexpr int S = LdsV<T>::v;
   if (k0 >= k1) return;
-  TileRegs<T> ra, rb;
-  ra.load(pa(k0));
-  rb.load(pb(k0));
-  __syncthreads();
-  ra.store_lds(lds);
-  rb.store_lds(lds + TS * S);
-  if (k0 + 1 < k1) {
-    ra.load(pa(k0 + 1));
-    rb.load(pb(k0 + 1));
+  TileRegs<T> ra[NPF], rb[NPF];
+#pragma unroll
+  for (int t = 0; t < NPF; ++t) {
+    const int Kl = min(k0 + t, k1 - 1);
+    ra[t].load(pa(Kl));
+    if (!SYRK) rb[t].load(pb(Kl));
   }
-  __syncthreads();
-  for (int K = k0; K < k1; ++K) {
-    T* cur = lds + ((K - k0) & 1) * 2 * TS * S;
-    T* nxt = lds + (((K - k0) & 1) ^ 1) * 2 * TS * S;
-    if (K + 1 < k1) {
-      ra.store_lds(nxt);
-      rb.store_lds(nxt + TS * S);
-      if (K + 2 < k1) {
-        ra.load(pa(K + 2));
-        rb.load(pb(K + 2));
-      }
+  for (int K = k0; K < k1; K += NPF) {
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) {
+      const int Kc = K + t;
+      T* buf = lds + ((Kc - k0) & 1) * 2 * TS * S;
+      ra[t].store_lds(buf);
+      if (!SYRK) rb[t].store_lds(buf + TS * S);
+      const int Kl = min(Kc + NPF, k1 - 1);
+      ra[t].load(pa(Kl));
+      if (!SYRK) rb[t].load(pb(Kl));
+      __syncthreads();
+      if (Kc < k1) tile_mma<T>(acc, buf, SYRK ? buf : buf + TS * S, sign);
     }
-    tile_mma<T>(acc, cur, cur + TS * S, sign);
-    __syncthreads();
   }
-}
-// Same with A_K = B_K (acc += sign * sum A_K A_K^T), one tile per buffer.
-template <typename T, typename FA>
-__device__ __forceinline__ void syrk_loop_db(TileAcc<T>& acc, int k0, int k1, FA pa, T* lds, T sign) {
-  constexpr int S = LdsV<T>::v;
-  if (k0 >= k1) return;
-  TileRegs<T> ra;
-  ra.load(pa(k0));
   __syncthreads();
-  ra.store_lds(lds);
-  if (k0 + 1 < k1) ra.load(pa(k0 + 1));
-  __syncthreads();
-  for (int K = k0; K < k1; ++K) {
-    T* cur = lds + ((K - k0) & 1) * TS * S;
-    T* nxt = lds + (((K - k0) & 1) ^ 1) * TS * S;
-    if (K + 1 < k1) {
-      ra.store_lds(nxt);
-      if (K + 2 < k1) ra.load(pa(K + 2));
-    }
-    tile_mma<T>(acc, cur, cur, sign);
-    __syncthreads();
-  }
 }
 
 template <typename T, bool DBUF = false>
@@ -314,7 +296,8 @@ __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc
   acc.load(F + tri_index(J, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
   if (DBUF) {
-    syrk_loop_db<T>(acc, kfrom, J, [&](int K) { return F + tri_index(J, K) * TS2; }, sA, T(-1));
+    auto pj = [&](int K) { return F + tri_index(J, K) * TS2; };
+    gemm_loop_pf<FACTOR_PF, true, T>(acc, kfrom, J, pj, pj, sA, T(-1));
   } else {
     TileRegs<T> ra;
     if (kfrom < J) ra.load(F + tri_index(J, kfrom) * TS2);
@@ -364,8 +347,8 @@ __device__ __forceinline__ void panel_tile(int J, int I, int kfrom, int nparts, 
   acc.load(F + tri_index(I, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);
   if (DBUF) {   // sA: four LDS tiles
-    gemm_loop_db<T>(acc, kfrom, J, [&](int K) { return F + tri_index(I, K) * TS2; },
-                    [&](int K) { return F + tri_index(J, K) * TS2; }, sA, T(-1));
+    gemm_loop_pf<FACTOR_PF, false, T>(acc, kfrom, J, [&](int K) { return F + tri_index(I, K) * TS2; },
+                                      [&](int K) { return F + tri_index(J, K) * TS2; }, sA, T(-1));
   } else {
     TileRegs<T> ra, rb;
     if (kfrom < J) {
@@ -417,6 +400,97 @@ __device__ __forceinline__ void partial_tile(int Jn, int I, int c, int k0, int k
   acc.store(part + ((int64_t)I * maxc + c) * TS2);
 }
 
+// Rows per step of the batched panel update: every step loads the L_JK tile
+// once for PANEL_R row tiles L_IK, so the tile products of one step cover the
+// load latency of the next and the L_JK tile is read once per PANEL_R rows.
+template <typename T> struct PanelRows { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
+
+// acc[r] += sign * A_r B^T for r < nr (LDS tiles A_r at sA + r TS S, B at
+// sBt, k-contiguous): tile_mma with the B fragments loaded once per k group.
+template <typename T, int R>
+__device__ __forceinline__ void tile_mma_rows(TileAcc<T> (&acc)[R], int nr, const T* __restrict__ sA,
+                                              const T* __restrict__ sBt, T sign) {
+  constexpr int S = LdsV<T>::v;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i0 = 32 * (w >> 1), j0 = 32 * (w & 1);
+  const int li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < TS / 16; ++t) {
+    const int kb = 16 * t + 4 * lk;
+    T b[2][4];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) load4(b[n], sBt + (j0 + 16 * n + li) * S + kb);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r < nr) {
+        T a[2][4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          load4(a[m], sA + r * TS * S + (i0 + 16 * m + li) * S + kb);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[m][u] *= sign;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[r].c[m][n] = mfma16(a[m][u], b[n][u], acc[r].c[m][n]);
+      }
+    }
+  }
+}
+
+// Sub-diagonal tiles (I0 + r, J), r < nr <= R, of one matrix: A_IJ minus
+// sum_{K<J} L_IK L_JK^T, times L_JJ^{-T}.  LDS: R + 1 tiles at lds.
+template <typename T, int R>
+__device__ __forceinline__ void panel_rows(int J, int I0, int nr, T* __restrict__ F, T* lds) {
+  constexpr int S = LdsV<T>::v;
+  T* sB = lds + R * TS * S;
+  TileAcc<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nr) acc[r].load(F + tri_index(I0 + r, J) * TS2);
+  TileRegs<T> ra[R], rb;
+  if (J > 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) ra[r].load(F + tri_index(I0 + r, 0) * TS2);
+    rb.load(F + tri_index(J, 0) * TS2);
+  }
+  for (int K = 0; K < J; ++K) {
+    __syncthreads();  // the products of step K - 1 have read the tiles
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) ra[r].store_lds(lds + r * TS * S);
+    rb.store_lds(sB);
+    __syncthreads();
+    if (K + 1 < J) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < nr) ra[r].load(F + tri_index(I0 + r, K + 1) * TS2);
+      rb.load(F + tri_index(J, K + 1) * TS2);
+    }
+    tile_mma_rows<T, R>(acc, nr, lds, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nr) acc[r].store_lds(lds + r * TS * S);
+  stage_tile(sB, F + tri_index(J, J) * TS2);  // L_JJ^{-1}
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r < nr) {
+      TileAcc<T> out;
+      out.zero();
+      tile_mma<T>(out, lds + r * TS * S, sB, T(1));  // L_IJ = A_IJ L_JJ^{-T}
+      out.store(F + tri_index(I0 + r, J) * TS2);
+    }
+  }
+  __syncthreads();
+}
+
 // Whole left-looking factorisation of one matrix per workgroup (batches of
 // many small matrices): column by column, the diagonal tile and then the
 // sub-diagonal tiles, all in this workgroup.  Tiles written here are read
@@ -432,12 +506,12 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   const int ntb = nt[b];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[b] * TS2;
   for (int J = 0; J < ntb; ++J) {
     diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
     __syncthreads();
-    for (int I = J + 1; I < ntb; ++I) panel_tile<T, true>(J, I, 0, 0, 0, (const T*)nullptr, F, sA, sB);
+    constexpr int R = PanelRows<T>::v;
+    for (int I = J + 1; I < ntb; I += R) panel_rows<T, R>(J, I, min(R, ntb - I), F, sA);
     __syncthreads();
   }
 }
@@ -517,7 +591,7 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
 template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s) {
-  const size_t sh = std::max(diag_lds_bytes<T>(), 4 * (size_t)TS * LdsV<T>::v * sizeof(T));
+  const size_t sh = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, PanelRows<T>::v + 1) * TS * LdsV<T>::v * sizeof(T));
   static bool once = (allow_lds(k_potrf_full<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_full<T>, dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
