@@ -56,10 +56,14 @@ __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __res
   const bool act = i < DB;
   T a[DB], rd[DB];
   // full symmetric row i from the lower triangle (the stored upper part is
-  // not meaningful)
+  // not meaningful); every lane reads (lanes past DB read row DB - 1 and drop
+  // it), so the reads issue back to back without branches
+  const int ir = act ? i : DB - 1;
 #pragma unroll
-  for (int j = 0; j < DB; ++j)
-    a[j] = act ? (j <= i ? sC[(o + i) * PS + o + j] : sC[(o + j) * PS + o + i]) : T(0);
+  for (int j = 0; j < DB; ++j) {
+    const T v = sC[(j <= ir ? (o + ir) * PS + o + j : (o + j) * PS + o + ir)];
+    a[j] = act ? v : T(0);
+  }
 #pragma unroll
   for (int k = 0; k < DB; ++k) {
     // the trailing block stays symmetric (every lane updates its whole row),
@@ -401,9 +405,12 @@ __device__ __forceinline__ void partial_tile(int Jn, int I, int c, int k0, int k
 }
 
 // Rows per step of the batched panel update: every step loads the L_JK tile
-// once for PANEL_R row tiles L_IK, so the tile products of one step cover the
-// load latency of the next and the L_JK tile is read once per PANEL_R rows.
-template <typename T> struct PanelRows { static constexpr int v = sizeof(T) == 4 ? 4 : 2; };
+// once for R row tiles L_IK, so the tile products of one step cover the load
+// latency of the next and the L_JK tile is read once per R rows.  R = 3 for
+// FP32 keeps the kernel at about 300 registers per lane, so that a workgroup
+// of the coarse factorisation (about 200) still fits beside it on a SIMD and
+// the two setups overlap; R = 4 is faster alone but no longer shares a CU.
+template <typename T> struct PanelRows { static constexpr int v = sizeof(T) == 4 ? 3 : 2; };
 
 // acc[r] += sign * A_r B^T for r < nr (LDS tiles A_r at sA + r TS S, B at
 // sBt, k-contiguous): tile_mma with the B fragments loaded once per k group.
@@ -516,58 +523,52 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   }
 }
 
-// One matrix (batch of one), look-ahead step after the diagonal tile of
-// column J: workgroups form the split-K partial update of column J + 1 from
-// columns K < J (part_out[I][c], I > J, chunks of SPLITK columns) and finish
-// the sub-diagonal tiles of column J (using the partials of columns K < J - 1
-// in part_in and forming the K = J - 1 term themselves).  The workgroups of
-// row J + 1 come first; the last of them to finish (a device-scope counter,
-// with release/acquire fences around it) goes on to factor and invert the
-// diagonal tile of column J + 1, while the other rows are still in flight.
+// One matrix (batch of one), step J after the diagonal tile of column J,
+// with the split-K partial sums two columns ahead.  Slot C mod 3 of `part`
+// holds the partials of column C: part[I][c] = sum of L_IK L_CK^T over the
+// chunk K in [c SPLITK, (c + 1) SPLITK) of K <= C - 3, formed in step C - 2.
+// Workgroups of step J:
+//  - 0: the tile (J + 1, J) (its partials, the direct terms K = J - 2, J - 1,
+//    times L_JJ^{-T}), then in the same workgroup the diagonal tile of
+//    column J + 1 (its partials, K = J - 1 and the tile just formed);
+//  - 1 .. m - 1: the tiles (I, J), I = J + 2 .. ntb - 1, the same way;
+//  - the rest: the partials of column J + 2 over K <= J - 1, rows J + 2 ..
+//    ntb - 1, one chunk each.
+// So the chain from one diagonal tile to the next holds no chunk sums and no
+// cross-workgroup handshake: five tile products and a diagonal
+// factorisation.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, int nparts_in,
-                                                             const T* __restrict__ part_in,
-                                                             T* __restrict__ part_out, int nc_out,
+__global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T* __restrict__ part,
+                                                             int64_t slot_tiles,
                                                              const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
-                                                             int32_t* __restrict__ counter,
                                                              int32_t* __restrict__ status) {
   const int ntb = nt[0];
   const int m = ntb - 1 - J;  // tiles below the diagonal in column J
   if (m <= 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int last;
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[0] * TS2;
   const int x = blockIdx.x;
-  const int kfrom = J > 0 ? J - 1 : 0;
-  int I;
-  if (x <= nc_out) {                       // row J + 1: its partial chunks, then its panel tile
-    I = J + 1;
-    if (x < nc_out) partial_tile<T>(J + 1, I, x, x * SPLITK, min(J, (x + 1) * SPLITK), maxc, F, part_out, sA, sB);
-    else panel_tile<T>(J, I, kfrom, nparts_in, maxc, part_in, F, sA, sB);
-  } else {
-    const int y = x - (nc_out + 1), mr = m - 1;  // rows J + 2 .. ntb - 1
-    if (y < mr * nc_out) {
-      I = J + 2 + y % mr;
-      const int c = y / mr;
-      partial_tile<T>(J + 1, I, c, c * SPLITK, min(J, (c + 1) * SPLITK), maxc, F, part_out, sA, sB);
-    } else {
-      I = J + 2 + (y - mr * nc_out);
-      panel_tile<T>(J, I, kfrom, nparts_in, maxc, part_in, F, sA, sB);
-    }
+  auto slot = [&](int C) { return part + (int64_t)(C % 3) * slot_tiles * TS2; };
+  // column J: partials over K <= J - 3, direct terms from K = max(0, J - 2)
+  const int kd = J >= 2 ? J - 2 : 0;
+  const int nc_j = J >= 3 ? (J - 2 + SPLITK - 1) / SPLITK : 0;
+  if (x < m) {
+    panel_tile<T>(J, J + 1 + x, kd, nc_j, maxc, slot(J), F, sA, sB);
+    if (x > 0) return;
+    __syncthreads();
+    // diagonal tile J + 1: partials over K <= J - 2, direct K = J - 1, J
+    const int nc_d = J >= 2 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
+    diag_tile<T>(J + 1, J >= 1 ? J - 1 : 0, nc_d, maxc, slot(J + 1), F, status, smem_raw);
     return;
   }
-  // row J + 1 done by this workgroup: publish, and let the last one continue
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter + J, 1) == nc_out);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  diag_tile<T>(J + 1, J, nc_out, maxc, part_out, F, status, smem_raw);
+  // partials of column J + 2 over K = 0 .. J - 1, rows J + 2 .. ntb - 1
+  const int y = x - m, mr = m - 1;
+  const int I = J + 2 + y % mr, c = y / mr;
+  partial_tile<T>(J + 2, I, c, c * SPLITK, min(J, (c + 1) * SPLITK), maxc, F, slot(J + 2), sA, sB);
 }
 
 // The FP64 tile kernels stage two 64x65 double tiles (66.5 KB of LDS), above
@@ -597,17 +598,17 @@ void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, in
   hipLaunchKernelGGL(k_potrf_full<T>, dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
 }
 template <typename T>
-void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part_in, T* part_out,
-                       const int32_t* nt, const int64_t* off, T* fac, int32_t* counter,
-                       int32_t* status, hipStream_t s) {
+void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
+                       const int64_t* off, T* fac, int32_t* status, hipStream_t s) {
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
-  const int nc_out = (J + SPLITK - 1) / SPLITK;
+  const int nc = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
+  const int nwg = m + (m > 1 ? (m - 1) * nc : 0);
   const size_t sh = std::max(2 * TS * LdsV<T>::v * sizeof(T), diag_lds_bytes<T>());
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_step<T>, dim3(m * nc_out + m), dim3(TILE_THREADS), sh, s, J, maxc,
-                     nparts_in, part_in, part_out, nc_out, nt, off, fac, counter, status);
+  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg), dim3(TILE_THREADS), sh, s, J, maxc, part, slot_tiles, nt,
+                     off, fac, status);
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -835,8 +836,8 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*,            \
                                      hipStream_t);                                                 \
-  template void launch_potrf_step<T>(int, int, int, int, const T*, T*, const int32_t*,             \
-                                     const int64_t*, T*, int32_t*, int32_t*, hipStream_t);         \
+  template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
+                                     T*, int32_t*, hipStream_t);                                   \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \

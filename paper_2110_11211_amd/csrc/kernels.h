@@ -90,13 +90,12 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
 template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s);
-// One matrix: sub-diagonal tiles of column J, split-K partials of column
-// J + 1, and the diagonal tile of column J + 1 (by the last workgroup of row
-// J + 1; counter[J] must be zero before the launch).
+// One matrix: sub-diagonal tiles of column J, the diagonal tile of column
+// J + 1, and the split-K partials of column J + 2 (three slots of slot_tiles
+// tiles at part, slot C mod 3 for column C).
 template <typename T>
-void launch_potrf_step(int J, int max_nt, int maxc, int nparts_in, const T* part_in, T* part_out,
-                       const int32_t* nt, const int64_t* off, T* fac, int32_t* counter,
-                       int32_t* status, hipStream_t s);
+void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
+                       const int64_t* off, T* fac, int32_t* status, hipStream_t s);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);

@@ -73,7 +73,7 @@ struct sfcdd_ctx {
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
-      r_cmeta, r_cgid, r_ctgid, r_cy, r_ccount, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout;
+      r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // device pointers
@@ -86,7 +86,6 @@ struct sfcdd_ctx {
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
   double* cy = nullptr;  // tile-padded coarse vector X_0 R_0 v between the two products
-  int32_t* ccount = nullptr;  // per-column arrival counters of the coarse factorisation
   double* cpartk = nullptr;  // split-K partial tiles of a single coarse factorisation
   int32_t *dc_nt = nullptr, *dc_n = nullptr;
   int64_t *dc_off = nullptr, *dc_xoff = nullptr, *dc_poff = nullptr, *dc_doff = nullptr;
@@ -479,15 +478,14 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_c0 = pl.take((size_t)c->c0len * 8);
   c->r_d0 = pl.take((size_t)c->N0tot * 8);
   c->r_cpart = pl.take((size_t)c->cparts * 8);
-  // split-K partials of the single-matrix factorisation (two buffers), later
+  // split-K partials of the single-matrix factorisation (three slots), later
   // reused by the triangular inversion
-  const size_t kparts = G == 1 ? 2 * (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) : 0;
+  const size_t kparts = G == 1 ? 3 * (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) : 0;
   c->r_cpartk = pl.take(std::max(kparts, (size_t)c->ctinv) * TS2 * 8);
   c->r_cmeta = pl.take((size_t)G * (5 * 8 + 2 * 4));
   c->r_cgid = pl.take(2 * c->N0tot);
   c->r_ctgid = pl.take(2 * c->ctiles);
   c->r_cy = pl.take((size_t)c->c0len * 8);
-  c->r_ccount = pl.take((size_t)4 * c->max_nt0);
   c->r_dbuf = pl.take((size_t)c->sum_Ni * 8);
   c->r_vec = pl.take((size_t)NVEC * (((size_t)Nt * 8 + 255) & ~size_t(255)));
   c->r_partials = pl.take((size_t)8 * (2 * (size_t)G * c->rbx + (size_t)MAXD * RED_BLOCKS));
@@ -529,7 +527,6 @@ void bind(sfcdd_ctx* c) {
   c->cpart = at<double>(c, c->r_cpart);
   c->cpartk = at<double>(c, c->r_cpartk);
   c->cy = at<double>(c, c->r_cy);
-  c->ccount = at<int32_t>(c, c->r_ccount);
   unsigned char* cm = c->ws + c->r_cmeta.off;
   const int G = c->G;
   c->dc_off = reinterpret_cast<int64_t*>(cm);
@@ -558,24 +555,18 @@ void bind(sfcdd_ctx* c) {
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, bool product, int32_t* status, T* part, T* tbuf,
-                  const int64_t* toff, int32_t* counter, hipStream_t s) {
+                  const int64_t* toff, hipStream_t s) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
-  const int64_t half = (int64_t)max_nt * maxc * TS2;
   if (!part) {
     // batch: one workgroup factors a whole matrix
     launch_potrf_full<T>(nb, nt, off, fac, status, s);
   } else {
-    // one matrix: split-K partials of columns K < J - 1 (double-buffered),
-    // computed by the previous step concurrently with its panel; each step
-    // also factors the next diagonal tile (counter[J] zeroed beforehand)
-    (void)hipMemsetAsync(counter, 0, sizeof(int32_t) * max_nt, s);
+    // one matrix: the first diagonal tile, then one step per column (its
+    // sub-diagonal tiles, the next diagonal tile, split-K partials two
+    // columns ahead in three slots)
     launch_potrf_diag<T>(0, 0, 0, maxc, part, 1, nt, off, fac, status, s);
-    for (int J = 0; J + 1 < max_nt; ++J) {
-      const int np = J > 1 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
-      T* pin = part + (J & 1) * half;
-      T* pout = part + ((J + 1) & 1) * half;
-      launch_potrf_step<T>(J, max_nt, maxc, np, pin, pout, nt, off, fac, counter, status, s);
-    }
+    for (int J = 0; J + 1 < max_nt; ++J)
+      launch_potrf_step<T>(J, max_nt, maxc, part, (int64_t)max_nt * maxc, nt, off, fac, status, s);
   }
   if (invert) {
     if (tbuf) {
@@ -827,7 +818,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
     factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
-                         G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, c->ccount, cs);
+                         G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, cs);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
     HIPCHK(c, hipEventRecord(join, cs));
@@ -848,10 +839,10 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
-                        c->status, (float*)nullptr, (float*)nullptr, nullptr, nullptr, s);
+                        c->status, (float*)nullptr, (float*)nullptr, nullptr, s);
   else
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
-                         c->status, (double*)nullptr, (double*)nullptr, nullptr, nullptr, s);
+                         c->status, (double*)nullptr, (double*)nullptr, nullptr, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
   HIPCHK(c, hipStreamWaitEvent(s, join, 0));
