@@ -7,6 +7,7 @@
 // keep the INVERSE of the diagonal Cholesky block, L_JJ^{-1}, so that both
 // the panel update and the substitution sweeps are tile products.
 #include <algorithm>
+#include <utility>
 
 #include "common.h"
 #include "kernels.h"
@@ -42,64 +43,86 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
   return y * fmaf(-0.5f * x * y, y, 1.5f);
 }
 
+// Lane K of each row of 16 lanes, to every lane of that row (DPP
+// row_newbcast).
+template <int K, typename T>
+__device__ __forceinline__ T row_bcast(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xF, 0xF, false));
+  } else {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + K, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
+// Pivot K of the DB x DB block held by one wave: lane (p, i) = 16 p + i holds
+// a[q] = A[i][p + 4 q].  The trailing block stays symmetric (every lane
+// updates its whole part of its row), so the factor column below the pivot,
+// L[j][K] = A[K][j] / sqrt(A[K][K]), is row K right of the pivot: lane K of
+// each 16-lane row holds the entries of that row's columns (row broadcast),
+// while the lane's own L[i][K] sits in lane (K mod 4, i) (one shuffle).
+template <typename T, int K>
+__device__ __forceinline__ void pivot_step(T (&a)[DB / 4], T (&rd)[DB], int p, int i, int32_t* status) {
+  constexpr int pk = K & 3, qk = K >> 2;
+  T piv = bcast(a[qk], 16 * pk + K);
+  if (!(piv > T(0))) {
+    if ((int)threadIdx.x == 16 * pk + K) atomicExch(status, -6);
+    piv = T(1);
+  }
+  const T rs = rsqrt_nr(piv);
+  rd[K] = rs;
+  const T li = __shfl(a[qk], 16 * pk + i, 64) * rs;
+  T lj[DB / 4];
+#pragma unroll
+  for (int q = 0; q < DB / 4; ++q) lj[q] = row_bcast<K>(a[q]) * rs;
+#pragma unroll
+  for (int q = 0; q < DB / 4; ++q)
+    if (i > K && p + 4 * q > K) a[q] -= li * lj[q];
+  if (p == pk) a[qk] = i > K ? li : (i == K ? piv * rs : T(0));
+}
+template <typename T, int... K>
+__device__ __forceinline__ void pivots(std::integer_sequence<int, K...>, T (&a)[DB / 4], T (&rd)[DB], int p,
+                                       int i, int32_t* status) {
+  (pivot_step<T, K>(a, rd, p, i, status), ...);
+}
+
 // Cholesky factor and inverse of the DB x DB diagonal block at (o, o) of sC,
-// by the first wave: lane i < DB holds block row i in registers, and the
-// factor column of each pivot is read from the pivot lane's registers
-// (readlane).  Writes the factor back to the block (upper part zero), its
-// inverse (lower, upper part zero) to dinv (row stride ldd).  A non-positive
-// pivot sets *status to -6 and is replaced by 1.
+// by the first wave (pivots as in pivot_step, all 64 lanes).  Writes the
+// factor back to the block (upper part zero), its inverse (lower, upper part
+// zero) to dinv (row stride ldd).  A non-positive pivot sets *status to -6
+// and is replaced by 1.
 template <typename T>
 __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __restrict__ dinv, int ldd,
                                              int32_t* status) {
   constexpr int PS = Pstride<T>::v;
-  const int i = threadIdx.x;
-  const bool act = i < DB;
-  T a[DB], rd[DB];
-  // full symmetric row i from the lower triangle (the stored upper part is
-  // not meaningful); every lane reads (lanes past DB read row DB - 1 and drop
-  // it), so the reads issue back to back without branches
-  const int ir = act ? i : DB - 1;
+  const int lane = threadIdx.x, p = lane >> 4, i = lane & 15;
+  T a[DB / 4], rd[DB];
+  // the lane's part of the full symmetric row i, from the lower triangle (the
+  // stored upper part is not meaningful)
 #pragma unroll
-  for (int j = 0; j < DB; ++j) {
-    const T v = sC[(j <= ir ? (o + ir) * PS + o + j : (o + j) * PS + o + ir)];
-    a[j] = act ? v : T(0);
+  for (int q = 0; q < DB / 4; ++q) {
+    const int j = p + 4 * q;
+    a[q] = sC[j <= i ? (o + i) * PS + o + j : (o + j) * PS + o + i];
   }
+  pivots<T>(std::make_integer_sequence<int, DB>{}, a, rd, p, i, status);
 #pragma unroll
-  for (int k = 0; k < DB; ++k) {
-    // the trailing block stays symmetric (every lane updates its whole row),
-    // so column k below the pivot is row k right of it: lane k's registers
-    T piv = bcast(a[k], k);
-    if (!(piv > T(0))) {
-      if (i == k) atomicExch(status, -6);
-      piv = T(1);
-    }
-    T colk[DB];
-#pragma unroll
-    for (int j = k + 1; j < DB; ++j) colk[j] = bcast(a[j], k);
-    const T rs = rsqrt_nr(piv);
-    rd[k] = rs;
-    const T l = (i > k) ? a[k] * rs : (i == k ? piv * rs : T(0));
-    a[k] = l;
-#pragma unroll
-    for (int j = k + 1; j < DB; ++j) a[j] -= l * (colk[j] * rs);
-  }
-  if (act) {
-#pragma unroll
-    for (int j = 0; j < DB; ++j) sC[(o + i) * PS + o + j] = a[j];
-  }
-  // inverse by forward substitution, lane c owning column c; L_rk read back
-  // from the block (same address in every lane), 1/L_rr = rd[r]
+  for (int q = 0; q < DB / 4; ++q) sC[(o + i) * PS + o + p + 4 * q] = a[q];
+  // inverse by forward substitution, lane c < DB owning column c; L_rk read
+  // back from the block (same address in every lane), 1/L_rr = rd[r]
+  const bool act = lane < DB;
   T x[DB];
 #pragma unroll
   for (int r = 0; r < DB; ++r) {
-    T sum = (r == i) ? T(1) : T(0);
+    T sum = (r == lane) ? T(1) : T(0);
 #pragma unroll
     for (int k = 0; k < r; ++k) sum -= sC[(o + r) * PS + o + k] * x[k];
     x[r] = sum * rd[r];
   }
   if (act) {
 #pragma unroll
-    for (int r = 0; r < DB; ++r) dinv[r * ldd + i] = x[r];
+    for (int r = 0; r < DB; ++r) dinv[r * ldd + lane] = x[r];
   }
 }
 
