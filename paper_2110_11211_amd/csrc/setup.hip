@@ -14,63 +14,72 @@ __device__ __forceinline__ int64_t count_in(int64_t lo, int64_t hi, int n, int s
   return b >= a ? b - a + 1 : 0;
 }
 
-// Hilbert index digit (d bits, dimension 0 most significant) at bit level bi
-// of the point with scaled coordinates Y, by Skilling's transform
-// (transposed Hilbert index): walking the bit levels above bi from the top,
+// Hilbert rank by Skilling's transform (transposed Hilbert index), one pass
+// from the top bit level down.  At level lev the transform walks the axes: an
 // axis i with a 1 at that level inverts the lower bits of axis 0, otherwise
-// axes 0 and i exchange their lower bits; after that the bits at levels >= bi
-// are final.  The axes are then Gray-coded in order (axis i XORed with the
-// already coded axis i - 1, i.e. the XOR of axes 0..i), and the digit is
-// their bit at level bi, inverted when the coded last axis has an odd number
-// of ones above bi.  Depends only on the bits of Y at levels >= bi.
-__device__ __forceinline__ int hilbert_digit(const uint64_t* __restrict__ Y, int d, int nres, int bi) {
-  uint64_t X[MAXD];
-  for (int j = 0; j < d; ++j) X[j] = Y[j];
-  for (int lev = nres - 1; lev > bi; --lev) {
-    const uint64_t Q = 1ull << lev, low = Q - 1;
-    for (int i = 0; i < d; ++i) {
-      if (X[i] & Q) {
-        X[0] ^= low;
-      } else {
-        const uint64_t t = (X[0] ^ X[i]) & low;
-        X[0] ^= t;
-        X[i] ^= t;
-      }
-    }
-  }
-  uint64_t glast = 0;
-  for (int i = 0; i < d; ++i) glast ^= X[i];
-  const int flip = __popcll(glast >> (bi + 1)) & 1;
-  int digit = 0, acc = 0;
-  for (int i = 0; i < d; ++i) {
-    acc ^= (int)((X[i] >> bi) & 1ull);
-    digit = (digit << 1) | (acc ^ flip);
-  }
-  return digit;
-}
-
-// Hilbert rank: at every bit level, the points of the children of p's cell
-// that the curve visits before p's child (smaller digit) come first; each
-// child is an axis-aligned box, so its interior points are counted as a
+// axes 0 and i exchange their lower bits.  Those operations reach only the
+// levels below lev and depend only on bits at levels >= lev, so when level bi
+// is reached the bits at bi already hold the transformed digit, and the same
+// operations act on the bit-bi vector of every sibling cell (same bits above
+// bi) as one affine map v[k] = c[perm[k]] ^ mask[k], built up level by level.
+// The digit of a bit-bi vector: the axes Gray-coded in order (axis i XORed
+// with the coded axis i - 1), inverted when the coded last axis has an odd
+// number of ones above bi; axis 0 is its most significant bit.  At every
+// level, the points of the sibling cells with a smaller digit come first;
+// each cell is an axis-aligned box, so its interior points are counted as a
 // product of interval counts.
 __device__ int64_t hilbert_rank(const int64_t* C, const GridDesc& g) {
-  uint64_t Y[MAXD];
-  uint64_t Cu[MAXD];
-  for (int j = 0; j < g.d; ++j) Cu[j] = (uint64_t)C[j];
+  const int d = g.d;
+  uint64_t X[MAXD];
+  int perm[MAXD], mask[MAXD];
+  for (int j = 0; j < d; ++j) {
+    X[j] = (uint64_t)C[j];
+    perm[j] = j;
+    mask[j] = 0;
+  }
   int64_t rank = 0;
   for (int bi = g.nres - 1; bi >= 0; --bi) {
-    const int hp = hilbert_digit(Cu, g.d, g.nres, bi);
-    if (hp == 0) continue;
-    for (int c = 0; c < (1 << g.d); ++c) {
-      for (int j = 0; j < g.d; ++j)
-        Y[j] = ((Cu[j] >> (bi + 1)) << (bi + 1)) | ((uint64_t)((c >> (g.d - 1 - j)) & 1) << bi);
-      if (hilbert_digit(Y, g.d, g.nres, bi) >= hp) continue;
-      int64_t cnt = 1;
-      for (int j = 0; j < g.d && cnt; ++j) {
-        const int64_t lo = (int64_t)Y[j];
-        cnt *= count_in(lo, lo + ((int64_t)1 << bi) - 1, g.n[j], g.shift[j]);
+    uint64_t glast = 0;
+    for (int i = 0; i < d; ++i) glast ^= X[i];
+    const int flip = __popcll(glast >> (bi + 1)) & 1;
+    int hp = 0, acc = 0;
+    for (int i = 0; i < d; ++i) {
+      acc ^= (int)((X[i] >> bi) & 1ull);
+      hp = (hp << 1) | (acc ^ flip);
+    }
+    if (hp > 0) {
+      for (int c = 0; c < (1 << d); ++c) {
+        int dg = 0, ac = 0;
+        for (int k = 0; k < d; ++k) {
+          ac ^= ((c >> (d - 1 - perm[k])) & 1) ^ mask[k];
+          dg = (dg << 1) | (ac ^ flip);
+        }
+        if (dg >= hp) continue;
+        int64_t cnt = 1;
+        for (int j = 0; j < d && cnt; ++j) {
+          const int64_t lo = ((C[j] >> (bi + 1)) << (bi + 1)) | ((int64_t)((c >> (d - 1 - j)) & 1) << bi);
+          cnt *= count_in(lo, lo + ((int64_t)1 << bi) - 1, g.n[j], g.shift[j]);
+        }
+        rank += cnt;
       }
-      rank += cnt;
+    }
+    if (bi > 0) {
+      const uint64_t Q = 1ull << bi, low = Q - 1;
+      for (int i = 0; i < d; ++i) {
+        if (X[i] & Q) {
+          X[0] ^= low;
+          mask[0] ^= 1;
+        } else {
+          const uint64_t t = (X[0] ^ X[i]) & low;
+          X[0] ^= t;
+          X[i] ^= t;
+          const int pt = perm[0], mt = mask[0];
+          perm[0] = perm[i];
+          mask[0] = mask[i];
+          perm[i] = pt;
+          mask[i] = mt;
+        }
+      }
     }
   }
   return rank;
