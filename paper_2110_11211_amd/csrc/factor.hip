@@ -472,9 +472,9 @@ __device__ __forceinline__ void tile_mma_rows(TileAcc<T> (&acc)[R], int nr, cons
 }
 
 // Sub-diagonal tiles (I0 + r, J), r < nr <= R, of one matrix: A_IJ minus
-// sum_{K<J} L_IK L_JK^T, times L_JJ^{-T}.  LDS: R + 1 tiles at lds.
+// sum_{kfrom<=K<J} L_IK L_JK^T, times L_JJ^{-T}.  LDS: R + 1 tiles at lds.
 template <typename T, int R>
-__device__ __forceinline__ void panel_rows(int J, int I0, int nr, T* __restrict__ F, T* lds) {
+__device__ __forceinline__ void panel_rows(int J, int kfrom, int I0, int nr, T* __restrict__ F, T* lds) {
   constexpr int S = LdsV<T>::v;
   T* sB = lds + R * TS * S;
   TileAcc<T> acc[R];
@@ -482,13 +482,13 @@ __device__ __forceinline__ void panel_rows(int J, int I0, int nr, T* __restrict_
   for (int r = 0; r < R; ++r)
     if (r < nr) acc[r].load(F + tri_index(I0 + r, J) * TS2);
   TileRegs<T> ra[R], rb;
-  if (J > 0) {
+  if (kfrom < J) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (r < nr) ra[r].load(F + tri_index(I0 + r, 0) * TS2);
-    rb.load(F + tri_index(J, 0) * TS2);
+      if (r < nr) ra[r].load(F + tri_index(I0 + r, kfrom) * TS2);
+    rb.load(F + tri_index(J, kfrom) * TS2);
   }
-  for (int K = 0; K < J; ++K) {
+  for (int K = kfrom; K < J; ++K) {
     __syncthreads();  // the products of step K - 1 have read the tiles
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -521,13 +521,119 @@ __device__ __forceinline__ void panel_rows(int J, int I0, int nr, T* __restrict_
   __syncthreads();
 }
 
+// acc0[r] += sign A_r B0^T and, where r >= r1, acc1[r] += sign A_r B1^T
+// (LDS tiles A_r at sA + r TS S; B0, B1 k-contiguous): the A fragments are
+// loaded once for both columns.
+template <typename T, int R>
+__device__ __forceinline__ void tile_mma_pair(TileAcc<T> (&acc0)[R], TileAcc<T> (&acc1)[R], int nr, int r1,
+                                              const T* __restrict__ sA, const T* __restrict__ sB0,
+                                              const T* __restrict__ sB1, T sign) {
+  constexpr int S = LdsV<T>::v;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i0 = 32 * (w >> 1), j0 = 32 * (w & 1);
+  const int li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < TS / 16; ++t) {
+    const int kb = 16 * t + 4 * lk;
+    T b0[2][4], b1[2][4];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      load4(b0[n], sB0 + (j0 + 16 * n + li) * S + kb);
+      load4(b1[n], sB1 + (j0 + 16 * n + li) * S + kb);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r < nr) {
+        T a[2][4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          load4(a[m], sA + r * TS * S + (i0 + 16 * m + li) * S + kb);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[m][u] *= sign;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc0[r].c[m][n] = mfma16(a[m][u], b0[n][u], acc0[r].c[m][n]);
+        if (r >= r1) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+              for (int n = 0; n < 2; ++n) acc1[r].c[m][n] = mfma16(a[m][u], b1[n][u], acc1[r].c[m][n]);
+        }
+      }
+    }
+  }
+}
+
+// Columns J and J + 1 of rows I0 + r, r < nr <= R (I0 >= J), updated by
+// the columns K < J: A_IJ -= sum L_IK L_JK^T and, for I > J, A_I,J+1 -=
+// sum L_IK L_J+1,K^T, with each row tile L_IK loaded once for both columns;
+// the updated tiles are written back in place.  LDS: R + 2 tiles at lds.
+template <typename T, int R>
+__device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__ F, T* lds) {
+  constexpr int S = LdsV<T>::v;
+  T* sB0 = lds + R * TS * S;
+  T* sB1 = sB0 + TS * S;
+  const int r1 = I0 > J ? 0 : 1;  // row J has no tile in column J + 1
+  TileAcc<T> acc0[R], acc1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r < nr) {
+      acc0[r].load(F + tri_index(I0 + r, J) * TS2);
+      if (r >= r1) acc1[r].load(F + tri_index(I0 + r, J + 1) * TS2);
+    }
+  }
+  TileRegs<T> ra[R], rb0, rb1;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nr) ra[r].load(F + tri_index(I0 + r, 0) * TS2);
+  rb0.load(F + tri_index(J, 0) * TS2);
+  rb1.load(F + tri_index(J + 1, 0) * TS2);
+  for (int K = 0; K < J; ++K) {
+    __syncthreads();  // the products of step K - 1 have read the tiles
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) ra[r].store_lds(lds + r * TS * S);
+    rb0.store_lds(sB0);
+    rb1.store_lds(sB1);
+    __syncthreads();
+    if (K + 1 < J) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < nr) ra[r].load(F + tri_index(I0 + r, K + 1) * TS2);
+      rb0.load(F + tri_index(J, K + 1) * TS2);
+      rb1.load(F + tri_index(J + 1, K + 1) * TS2);
+    }
+    tile_mma_pair<T, R>(acc0, acc1, nr, r1, lds, sB0, sB1, T(-1));
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r < nr) {
+      acc0[r].store(F + tri_index(I0 + r, J) * TS2);
+      if (r >= r1) acc1[r].store(F + tri_index(I0 + r, J + 1) * TS2);
+    }
+  }
+  __syncthreads();
+}
+
 // Whole left-looking factorisation of one matrix per workgroup (batches of
-// many small matrices): column by column, the diagonal tile and then the
-// sub-diagonal tiles, all in this workgroup.  Tiles written here are read
-// back in later columns only by this workgroup, whose waves share one CU and
-// its vector L1: the workgroup-scope release/acquire of the barrier makes the
+// many small matrices): the diagonal tile and then the sub-diagonal tiles of
+// each column, all in this workgroup.  Tiles written here are read back in
+// later columns only by this workgroup, whose waves share one CU and its
+// vector L1: the workgroup-scope release/acquire of the barrier makes the
 // stores visible.
-template <typename T>
+// PAIR: columns J and J + 1 together (the update by the columns K < J loads
+// each row tile once for both; the two columns are then finished in turn,
+// column J + 1 still taking the term K = J).  About 8% faster alone, but at
+// about 380 registers per lane (FP32) it leaves no room on a SIMD for a
+// workgroup of the single-matrix coarse factorisation, so the launcher takes
+// it only where that does not matter (see launch_potrf_full).
+template <typename T, bool PAIR>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
@@ -537,11 +643,29 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* F = fac + off[b] * TS2;
-  for (int J = 0; J < ntb; ++J) {
-    diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
+  constexpr int R = PanelRows<T>::v;
+  int J = 0;
+  if (!PAIR) {
+    for (; J < ntb; ++J) {
+      diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
+      __syncthreads();
+      for (int I = J + 1; I < ntb; I += R) panel_rows<T, R>(J, 0, I, min(R, ntb - I), F, sA);
+      __syncthreads();
+    }
+    return;
+  }
+  for (; J + 1 < ntb; J += 2) {
+    if (J > 0)
+      for (int I = J; I < ntb; I += R) pair_rows<T, R>(J, I, min(R, ntb - I), F, sA);
+    diag_tile<T, true>(J, J, 0, 0, (const T*)nullptr, F, status, smem_raw);
     __syncthreads();
-    constexpr int R = PanelRows<T>::v;
-    for (int I = J + 1; I < ntb; I += R) panel_rows<T, R>(J, I, min(R, ntb - I), F, sA);
+    for (int I = J + 1; I < ntb; I += R) panel_rows<T, R>(J, J, I, min(R, ntb - I), F, sA);
+    diag_tile<T, true>(J + 1, J, 0, 0, (const T*)nullptr, F, status, smem_raw);
+    __syncthreads();
+    for (int I = J + 2; I < ntb; I += R) panel_rows<T, R>(J + 1, J, I, min(R, ntb - I), F, sA);
+  }
+  if (J < ntb) {  // odd tile count: the last column alone
+    diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
     __syncthreads();
   }
 }
@@ -613,12 +737,16 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
                      part, nt, off, fac, status);
 }
 template <typename T>
-void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
+void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, bool pair,
                        hipStream_t s) {
-  const size_t sh = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, PanelRows<T>::v + 1) * TS * LdsV<T>::v * sizeof(T));
-  static bool once = (allow_lds(k_potrf_full<T>, sh), true);
+  const size_t sh1 = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, PanelRows<T>::v + 1) * TS * LdsV<T>::v * sizeof(T));
+  const size_t sh2 = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, PanelRows<T>::v + 2) * TS * LdsV<T>::v * sizeof(T));
+  static bool once = (allow_lds(k_potrf_full<T, false>, sh1), allow_lds(k_potrf_full<T, true>, sh2), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_full<T>, dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
+  if (pair)
+    hipLaunchKernelGGL((k_potrf_full<T, true>), dim3(nb), dim3(TILE_THREADS), sh2, s, nt, off, fac, status);
+  else
+    hipLaunchKernelGGL((k_potrf_full<T, false>), dim3(nb), dim3(TILE_THREADS), sh1, s, nt, off, fac, status);
 }
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
@@ -857,7 +985,7 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 #define INST(T)                                                                                    \
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
-  template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*,            \
+  template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*, bool,      \
                                      hipStream_t);                                                 \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
                                      T*, int32_t*, hipStream_t);                                   \

@@ -86,9 +86,10 @@ template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
                        hipStream_t s);
-// Whole factorisation, one workgroup per matrix.
+// Whole factorisation, one workgroup per matrix (pair: two columns per
+// step; faster alone, but no room beside it for other workgroups).
 template <typename T>
-void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
+void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, bool pair,
                        hipStream_t s);
 // One matrix: sub-diagonal tiles of column J, the diagonal tile of column
 // J + 1, and the split-K partials of column J + 2 (three slots of slot_tiles

@@ -555,11 +555,11 @@ void bind(sfcdd_ctx* c) {
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, bool product, int32_t* status, T* part, T* tbuf,
-                  const int64_t* toff, hipStream_t s) {
+                  const int64_t* toff, bool pair, hipStream_t s) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   if (!part) {
     // batch: one workgroup factors a whole matrix
-    launch_potrf_full<T>(nb, nt, off, fac, status, s);
+    launch_potrf_full<T>(nb, nt, off, fac, status, pair, s);
   } else {
     // one matrix: the first diagonal tile, then one step per column (its
     // sub-diagonal tiles, the next diagonal tile, split-K partials two
@@ -818,7 +818,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
     factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
-                         G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, cs);
+                         G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
     HIPCHK(c, hipEventRecord(join, cs));
@@ -835,14 +835,22 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[3], s));
 
-  // factor once (Sec. 3.1)
+  // factor once (Sec. 3.1).  The two-column batched kernel is faster alone
+  // but takes the SIMD room that a workgroup of the single-matrix coarse
+  // chain (running beside it) needs; keep the one-column kernel when that
+  // chain is a sizeable share of the setup work (FP32 factors; FP64 leaves
+  // no room either way).
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
+  double fine_work = 0.0;
+  for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
+  const double coarse_work = G == 1 ? std::pow((double)c->N0tot, 3.0) : 0.0;
+  const bool pair = c->fdtype == SFCDD_FP64 || coarse_work < 0.15 * fine_work;
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
-                        c->status, (float*)nullptr, (float*)nullptr, nullptr, s);
+                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s);
   else
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
-                         c->status, (double*)nullptr, (double*)nullptr, nullptr, s);
+                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
   HIPCHK(c, hipStreamWaitEvent(s, join, 0));
