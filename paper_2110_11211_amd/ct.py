@@ -28,6 +28,19 @@ def _layer(d: int, total: int) -> List[Tuple[int, ...]]:
     return out
 
 
+def ct_layout(d: int, L: int, phat: int = 1):
+    """[(level vector, layer i, weight, P)] of the level-L combination in d
+    dimensions: layers |l|_1 = L + d - 1 - i, weight (-1)^i binom(d-1, i),
+    P = Phat 2^(d-1-i) capped at the grid's size."""
+    out = []
+    for i in range(d):
+        w = float((-1) ** i * comb(d - 1, i))
+        for lv in _layer(d, L + d - 1 - i):
+            N = int(np.prod([(1 << l) - 1 for l in lv]))
+            out.append((lv, i, w, max(1, min(phat * (1 << (d - 1 - i)), N))))
+    return out
+
+
 class CombinationTechnique:
     def __init__(self, d: int, L: int, phat: int = 1, gamma=Fraction(1, 4), factor_dtype: str = "fp32",
                  variant: str = "balanced", weighting: str = "omega", curve: str = "zorder",
@@ -38,15 +51,11 @@ class CombinationTechnique:
             raise ValueError("need d >= 1 and L >= 1")
         self.d, self.L = d, L
         self.levels, self.layer, self.weights, grids = [], [], [], []
-        for i in range(d):
-            w = float((-1) ** i * comb(d - 1, i))
-            for lv in _layer(d, L + d - 1 - i):
-                N = int(np.prod([(1 << l) - 1 for l in lv]))
-                P = max(1, min(phat * (1 << (d - 1 - i)), N))
-                self.levels.append(lv)
-                self.layer.append(i)
-                self.weights.append(w)
-                grids.append(dict(levels=list(lv), P=P, gamma=gamma, curve=curve))
+        for lv, i, w, P in ct_layout(d, L, phat):
+            self.levels.append(lv)
+            self.layer.append(i)
+            self.weights.append(w)
+            grids.append(dict(levels=list(lv), P=P, gamma=gamma, curve=curve))
         self.batch = SFCSchwarzBatch(grids, factor_dtype=factor_dtype, variant=variant,
                                      weighting=weighting, layout=layout, device=device,
                                      workspace=workspace)

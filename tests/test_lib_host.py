@@ -95,3 +95,21 @@ def test_workspace_grows_with_factor_precision():
     a = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp32")
     b = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp64")
     assert b > a > 1.9e9
+
+
+def test_ct_layout_against_oracle():
+    """Grids, layers, weights and subdomain counts of the combination-technique
+    binding (host logic) against the oracle's enumeration (eq. combi, eq.
+    Pchoice), and the capped P never exceeds a grid's size."""
+    from paper_2110_11211_amd.ct import ct_layout
+    from oracle import ct as oct
+    from oracle.grid import Grid
+    for d in range(1, 6):
+        for L in range(d, d + 5):
+            for phat in (1, 4):
+                got = ct_layout(d, L, phat)
+                ref = oct.ct_grids(d, L)
+                assert [(lv, i, w) for lv, i, w, _ in got] == ref
+                for lv, i, _, P in got:
+                    N = Grid(levels=lv).N
+                    assert P == min(oct.subdomains_per_grid(d, i, phat), N)
