@@ -110,15 +110,19 @@ __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __res
 #pragma unroll
   for (int q = 0; q < DB / 4; ++q) sC[(o + i) * PS + o + p + 4 * q] = a[q];
   // inverse by forward substitution, lane c < DB owning column c; L_rk read
-  // back from the block (same address in every lane), 1/L_rr = rd[r]
+  // back from the block (same address in every lane), 1/L_rr = rd[r].
+  // Column-oriented: once x_k is known it is subtracted from every later
+  // row, so the dependent chain is one multiply-add per row (each row's sum
+  // still takes its terms in increasing k).
   const bool act = lane < DB;
-  T x[DB];
+  T x[DB], sum[DB];
 #pragma unroll
-  for (int r = 0; r < DB; ++r) {
-    T sum = (r == lane) ? T(1) : T(0);
+  for (int r = 0; r < DB; ++r) sum[r] = (r == lane) ? T(1) : T(0);
 #pragma unroll
-    for (int k = 0; k < r; ++k) sum -= sC[(o + r) * PS + o + k] * x[k];
-    x[r] = sum * rd[r];
+  for (int k = 0; k < DB; ++k) {
+    x[k] = sum[k] * rd[k];
+#pragma unroll
+    for (int r = k + 1; r < DB; ++r) sum[r] -= sC[(o + r) * PS + o + k] * x[k];
   }
   if (act) {
 #pragma unroll
