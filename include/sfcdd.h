@@ -213,10 +213,14 @@ sfcdd_status sfcdd_get_batch_stats(sfcdd_ctx* ctx, int32_t* iterations, double* 
 
 /* Autotuner of the subdomain-solve kernel: times the substitution sweeps with
  * 4, 8 and 16 waves per workgroup on the context's own factors (repeats runs
- * each, events on the context's stream), keeps the fastest for all later
- * applications, and returns its time per application in *best_ms (may be
- * NULL).  With the explicit-inverse local solver there is nothing to tune and
- * only the time is measured.  Synchronous. */
+ * each, 0 = 3, events on the context's stream), keeps the fastest for all
+ * later applications, and returns its time per application in *best_ms (may
+ * be NULL).  The choice is remembered for the process per launch shape
+ * (device, factor precision, local solver, tile count and size of every
+ * subdomain): a later call on a context of the same shape takes it without
+ * timing and returns the time measured then.  A negative repeats times
+ * again (|repeats| runs) regardless.  With the explicit-inverse local solver
+ * there is nothing to tune and only the time is measured.  Synchronous. */
 sfcdd_status sfcdd_autotune(sfcdd_ctx* ctx, int32_t repeats, double* best_ms);
 
 /* The same partition computed on the host alone, before any setup (no GPU

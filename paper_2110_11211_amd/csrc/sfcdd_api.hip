@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 #include <limits>
+#include <map>
+#include <mutex>
 
 #include "../../include/sfcdd.h"
 #include "common.h"
@@ -1360,7 +1362,35 @@ sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, 
 
 sfcdd_status sfcdd_autotune(sfcdd_ctx* c, int32_t repeats, double* best_ms) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
-  if (repeats < 1) repeats = 3;
+  const bool force = repeats < 0;
+  repeats = repeats < 0 ? -repeats : (repeats == 0 ? 3 : repeats);
+  const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
+  // The choice depends only on the launch shapes: the device, the factor
+  // precision and the tile counts and sizes of the subdomains.  It is kept
+  // per shape for the life of the process.
+  static std::mutex mu;
+  static std::map<uint64_t, std::pair<int, double>> tuned;
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+  mix((uint64_t)dev);
+  mix((uint64_t)c->fdtype);
+  mix((uint64_t)c->local_solver);
+  for (int i = 0; i < c->Ptot; ++i) {
+    mix((uint64_t)c->nt[i]);
+    mix((uint64_t)c->Ni[i]);
+  }
+  if (ncand > 1 && !force) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = tuned.find(key);
+    if (it != tuned.end()) {
+      c->trsv_waves = it->second.first;
+      c->info.trsv_waves = c->trsv_waves;
+      if (best_ms) *best_ms = it->second.second;
+      return SFCDD_OK;
+    }
+  }
   const hipStream_t s = c->stream;
   hipEvent_t a, b;
   HIPCHK(c, hipEventCreate(&a));
@@ -1370,7 +1400,6 @@ sfcdd_status sfcdd_autotune(sfcdd_ctx* c, int32_t repeats, double* best_ms) {
   int best = c->trsv_waves;
   double best_t = 1e300;
   const int cand[3] = {4, 8, 16};
-  const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
   for (int k = 0; k < ncand; ++k) {
     local_solves(c, w, cand[k]);  // warm-up
     HIPCHK(c, hipEventRecord(a, s));
@@ -1387,7 +1416,11 @@ sfcdd_status sfcdd_autotune(sfcdd_ctx* c, int32_t repeats, double* best_ms) {
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  if (ncand > 1) c->trsv_waves = best;
+  if (ncand > 1) {
+    c->trsv_waves = best;
+    std::lock_guard<std::mutex> lk(mu);
+    tuned[key] = {best, best_t};
+  }
   c->info.trsv_waves = c->trsv_waves;
   if (best_ms) *best_ms = best_t;
   return SFCDD_OK;

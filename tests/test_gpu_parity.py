@@ -392,3 +392,25 @@ def test_stagnation_status_and_recursive_criterion():
     assert info2["status"] == m.OK and info2["rel_residual"] <= 1e-12
     assert relerr(host(x2), ex) <= 1e-9
     S.close()
+
+
+def test_autotune_choice_kept_per_shape():
+    """The tuner's choice is kept per launch shape: a second context of the
+    same shape gets the same wave count and time without timing again; a
+    negative repeat count times again; the solve is unchanged either way."""
+    announce("autotune cache")
+    kw = dict(levels=(5, 5), P=8, gamma=Fraction(1, 4), factor_dtype="fp32")
+    S1 = m.SFCSchwarz(**kw)
+    t1 = S1.autotune(2)
+    w1 = S1.info()["trsv_waves"]
+    S1.close()
+    S2 = m.SFCSchwarz(**kw)
+    t2 = S2.autotune(2)
+    assert S2.info()["trsv_waves"] == w1 and t2 == t1
+    t3 = S2.autotune(-2)
+    assert t3 > 0 and S2.info()["trsv_waves"] in (4, 8, 16)
+    g = Grid(levels=(5, 5))
+    f0 = uniform_pm1(1, g.N)
+    x, _ = S2.solve(dvec(f0), rtol=1e-12, method="fcg")
+    assert relerr(host(x), exact.solve(g, f0)) <= 1e-9
+    S2.close()
