@@ -449,7 +449,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->ctiles = ctoff;
   c->cparts = cpof;
   c->ctinv = ctt;
-  c->rbx = G == 1 ? RED_BLOCKS : std::max(8, RED_BLOCKS / G);
+  // reduction blocks per grid: one pass of RED_THREADS per point of the
+  // largest grid (so that every point has its own thread), at most RED_BLOCKS
+  int64_t maxN = 1;
+  for (int k = 0; k < G; ++k) maxN = std::max<int64_t>(maxN, c->grid[k].desc.N);
+  c->rbx = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(8, ceil_div(maxN, (int64_t)RED_THREADS)));
 
   // workspace layout
   const size_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
