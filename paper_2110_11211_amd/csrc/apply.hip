@@ -256,23 +256,37 @@ __device__ __forceinline__ void block_range(int I, const GridDesc& g, int64_t* s
   *size = qb + (m < qr ? 1 : 0);
 }
 
-__global__ void k_restrict(Batch B, const double* __restrict__ v, double* __restrict__ c0) {
-  const int64_t Ig = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (Ig >= B.N0tot) return;
-  const GridDesc& g = B.grids[grid_of(B, B.cgid, Ig)];
-  const int I = (int)(Ig - g.c0off);
-  int64_t st, sz;
-  block_range(I, g, &st, &sz);
-  const double* vg = v + g.goff + st;
+// R_0 v: the sum of v over each coarse block (a contiguous curve range), LPU
+// lanes per coarse unknown summing in a fixed order (lane-strided partial
+// sums, then a butterfly within the LPU lanes).
+template <int LPU>
+__global__ __launch_bounds__(256) void k_restrict(Batch B, const double* __restrict__ v, double* __restrict__ c0) {
+  const int64_t Ig = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPU;
+  const int lane = threadIdx.x & (LPU - 1);
+  const bool valid = Ig < B.N0tot;
   double acc = 0.0;
-  for (int64_t e = lane; e < sz; e += 64) acc += vg[e];
-  acc = wave_sum(acc);
-  if (lane == 0) c0[g.c0pad + I] = acc;
+  int64_t I = 0;
+  const GridDesc* gp = nullptr;
+  if (valid) {
+    gp = &B.grids[grid_of(B, B.cgid, Ig)];
+    I = Ig - gp->c0off;
+    int64_t st, sz;
+    block_range((int)I, *gp, &st, &sz);
+    const double* vg = v + gp->goff + st;
+    for (int64_t e = lane; e < sz; e += LPU) acc += vg[e];
+  }
+  for (int o = LPU / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (valid && lane == 0) c0[gp->c0pad + I] = acc;
 }
 
-void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((B.N0tot + 3) / 4)), dim3(256), 0, s, B, v, c0);
+void launch_restrict(const Batch& B, int max_block, const double* v, double* c0, hipStream_t s) {
+  if (max_block <= 48) {
+    const int64_t nb = (B.N0tot * 16 + 255) / 256;
+    hipLaunchKernelGGL(k_restrict<16>, dim3((unsigned)nb), dim3(256), 0, s, B, v, c0);
+  } else {
+    const int64_t nb = (B.N0tot * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_restrict<64>, dim3((unsigned)nb), dim3(256), 0, s, B, v, c0);
+  }
 }
 
 __device__ __forceinline__ int coarse_block_of(int64_t p, const GridDesc& g) {

@@ -133,7 +133,7 @@ void launch_gather_local(const Batch& B, int max_nt, const BatchMeta& bm, const 
 void launch_scatter(const Batch& B, int dweight, const int32_t* ta, const int32_t* Ni,
                     const int64_t* doff, const double* omega, const double* dbuf, double* h,
                     hipStream_t s);
-void launch_restrict(const Batch& B, const double* v, double* c0, hipStream_t s);
+void launch_restrict(const Batch& B, int max_block, const double* v, double* c0, hipStream_t s);
 // out = X^T (X v) for packed lower-tiled FP64 X (the coarse operator X = L_0^{-1}):
 // v tile-padded at bm.xoff, ytmp the same layout, part the per-(tile, chunk)
 // partials at bm.poff, out unpadded at doff (n[b] entries).

@@ -58,6 +58,7 @@ struct sfcdd_ctx {
   int weighting = 1, variant = 1, fdtype = 0, local_solver = 0, layout = 0;
   int64_t Ntot = 0, N0tot = 0;
   int Ptot = 0, dmax = 0, rbx = RED_BLOCKS;
+  int max_cblock = 1;  // largest coarse block (points) of any grid
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // internal, default priority: coarse setup overlaps the fine factorisation
   // per-subdomain (batch-global) host tables
@@ -454,6 +455,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   int64_t maxN = 1;
   for (int k = 0; k < G; ++k) maxN = std::max<int64_t>(maxN, c->grid[k].desc.N);
   c->rbx = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(8, ceil_div(maxN, (int64_t)RED_THREADS)));
+  c->max_cblock = 1;
+  for (int k = 0; k < G; ++k) {
+    const GridDesc& gd = c->grid[k].desc;
+    c->max_cblock = (int)std::max<int64_t>(c->max_cblock, ceil_div(gd.base + 1, gd.q));
+  }
 
   // workspace layout
   const size_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
@@ -590,7 +596,7 @@ void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) 
   ProfScope ps(c, SFCDD_K_COARSE);
   const Batch B = c->batch();
   BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
-  launch_restrict(B, v, c->c0, c->stream);
+  launch_restrict(B, c->max_cblock, v, c->c0, c->stream);
   launch_coarse_apply(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart, c->d0,
                       mask, c->stream);
 }
