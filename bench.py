@@ -62,7 +62,7 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
               curve=curve)
     nbytes = m.workspace_size(**kw)
     key = (fdtype, local)
-    if key not in ws_cache:
+    if key not in ws_cache or ws_cache[key].numel() < nbytes + 256:
         ws_cache.clear()
         torch.cuda.empty_cache()
         ws_cache[key] = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda:0")

@@ -88,7 +88,10 @@ typedef struct {
                                 0 = 2^(floor(log2(N/P)) - 4), capped at qP <= 16384    */
   int32_t weighting;         /* SFCDD_WEIGHT_NONE, _OMEGA (eq. omegai) or _D (eq. Di)    */
   int32_t variant;           /* SFCDD_ADDITIVE, SFCDD_BALANCED or SFCDD_DEFLATED         */
-  int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves  */
+  int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves;
+                                the coarse Cholesky factor is FP64 either way, and
+                                its inverse is kept in the same precision as the
+                                subdomain factors                                      */
   int32_t local_solver;      /* SFCDD_LOCAL_CHOLESKY: forward/backward substitution
                                 with the Cholesky factor; SFCDD_LOCAL_INVERSE: the
                                 explicit inverse formed from it, applied as a

@@ -203,20 +203,13 @@ class SFCSchwarz:
                        variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
                        layout=layout, curve=curve)
         prm, self._keep = make_params(**self.kw)
-        n = ctypes.c_size_t()
-        _check(lib().sfcdd_workspace_size(ctypes.byref(prm), ctypes.byref(n)))
-        self.workspace_bytes = int(n.value)
+        self._prm = prm
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            if workspace is not None:
-                if workspace.device != self.device or workspace.numel() < self.workspace_bytes + 256:
-                    raise ValueError("workspace tensor too small or on the wrong device")
-                self.ws = workspace
-            else:
-                self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            self.ws = self._workspace(workspace)
             ctx = ctypes.c_void_p()
             _check(lib().sfcdd_setup(ctypes.byref(prm), ctypes.c_void_p(self.ws.data_ptr()),
-                                     self.workspace_bytes + 256, ctypes.c_void_p(self.stream.cuda_stream),
+                                     self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream),
                                      ctypes.byref(ctx)), None if not ctx.value else ctx)
         self.ctx = ctx
         inf = Info()
@@ -226,6 +219,30 @@ class SFCSchwarz:
         self._info = inf
 
     # -- helpers -----------------------------------------------------------
+    def _query_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().sfcdd_workspace_size(ctypes.byref(self._prm), ctypes.byref(n)))
+        return int(n.value)
+
+    @property
+    def workspace_bytes(self) -> int:
+        """Workspace bytes the library plans for this problem."""
+        if getattr(self, "_ws_bytes", None) is None:
+            self._ws_bytes = self._query_bytes()
+        return self._ws_bytes
+
+    def _workspace(self, workspace):
+        """The caller's uint8 workspace tensor (its size is checked by the
+        library's setup, which fails with ENOMEM when it is short), else a new
+        one of the planned size."""
+        torch = self._torch
+        if workspace is not None:
+            if not isinstance(workspace, torch.Tensor) or workspace.device != self.device \
+                    or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+                raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device}")
+            return workspace
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+
     def _vec(self, t, name):
         torch = self._torch
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
@@ -339,21 +356,14 @@ class SFCSchwarzBatch(SFCSchwarz):
             arr[k] = prm
             self._keep.append(keep)
         self._arr = arr
+        self.G = G
         self.kw = dict(P=sum(g["P"] for g in grids), weighting=weighting, variant=variant,
                        factor_dtype=factor_dtype, local_solver=local_solver, layout=layout)
-        n = ctypes.c_size_t()
-        _check(lib().sfcdd_workspace_size_batch(G, arr, ctypes.byref(n)))
-        self.workspace_bytes = int(n.value)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            if workspace is not None:
-                if workspace.device != self.device or workspace.numel() < self.workspace_bytes + 256:
-                    raise ValueError("workspace tensor too small or on the wrong device")
-                self.ws = workspace
-            else:
-                self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            self.ws = self._workspace(workspace)
             ctx = ctypes.c_void_p()
-            st = lib().sfcdd_setup_batch(G, arr, ctypes.c_void_p(self.ws.data_ptr()), self.workspace_bytes + 256,
+            st = lib().sfcdd_setup_batch(G, arr, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
             _check(st, None if not ctx.value else ctx)
         self.ctx = ctx
@@ -371,6 +381,11 @@ class SFCSchwarzBatch(SFCSchwarz):
         self.offsets = [0]
         for v in sizes:
             self.offsets.append(self.offsets[-1] + v)
+
+    def _query_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().sfcdd_workspace_size_batch(self.G, self._arr, ctypes.byref(n)))
+        return int(n.value)
 
     def split(self, v):
         """Per-grid views of a concatenated vector."""

@@ -326,18 +326,30 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
 }
 
 // ---------------------------------------------------------------------------
-// Triangular matrix-vector products with a packed lower-tiled FP64 matrix X
-// (the coarse operator keeps X = L_0^{-1}, so A_0^{-1} v = X^T (X v)).
-// Streamed straight from HBM with 16-byte loads, in chunks of TRMV_CH tiles
-// per workgroup; partial results per (tile, chunk) are summed by
-// k_trmv_reduce in a fixed order (no atomics).
+// Triangular matrix-vector products with a packed lower-tiled matrix X (FP64,
+// or FP32 beside FP32 subdomain factors) and FP64 vectors; the coarse
+// operator keeps X = L_0^{-1}, so A_0^{-1} v = X^T (X v).  Streamed straight
+// from HBM with 16-byte loads (VEC entries per lane, LPR lanes per tile row),
+// in chunks of TRMV_CH tiles per workgroup; partial results per (tile, chunk)
+// are summed by k_trmv_reduce in a fixed order (no atomics).  Products and
+// sums are FP64.
 constexpr int TRMV_CH = 8;
 
+template <typename T> struct TrmvLanes {
+  static constexpr int VEC = Vec16<T>::n;   // entries per lane and load
+  static constexpr int LPR = TS / VEC;      // lanes per tile row
+  static constexpr int RPL = 64 / LPR;      // tile rows per wave and load
+  static constexpr int NQ = 16 / RPL;       // loads per wave for its 16 rows
+};
+
 // Rows: part[I][c] = sum_{K in chunk c, K <= I} X_IK v_K.
+template <typename T>
 __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
-                                                   const double* __restrict__ X,
+                                                   const T* __restrict__ X,
                                                    const double* __restrict__ v,
                                                    double* __restrict__ part) {
+  typedef TrmvLanes<T> LN;
+  typedef typename Vec16<T>::type V;
   const int b = blockIdx.y, ntb = bm.nt[b];
   const int I = blockIdx.x / nchx, c = blockIdx.x % nchx;
   const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
@@ -345,36 +357,49 @@ __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const
   if (I >= ntb || c >= nch || k0 > I || (active && !act_updating(active[b]))) return;
   const int k1 = min(I + 1, k0 + TRMV_CH);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lrow = lane >> 5, c0 = (lane & 31) * 2;
-  const double* Xb = X + bm.off[b] * TS2;
+  const int lrow = lane / LN::LPR, c0 = (lane % LN::LPR) * LN::VEC;
+  const T* Xb = X + bm.off[b] * TS2;
   const double* vb = v + bm.xoff[b];
-  double acc[8];
+  double acc[LN::NQ];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int q = 0; q < LN::NQ; ++q) acc[q] = 0.0;
   for (int K = k0; K < k1; ++K) {
-    const double2 vk = *reinterpret_cast<const double2*>(vb + K * TS + c0);
-    const double* tile = Xb + tri_index(I, K) * TS2;
+    double vk[LN::VEC];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = wv * 16 + q * 2 + lrow;
-      const double2 x = *reinterpret_cast<const double2*>(tile + r * TS + c0);
-      acc[q] += x.x * vk.x + x.y * vk.y;
+    for (int e = 0; e < LN::VEC; e += 2) {
+      const double2 t = *reinterpret_cast<const double2*>(vb + K * TS + c0 + e);
+      vk[e] = t.x;
+      vk[e + 1] = t.y;
+    }
+    const T* tile = Xb + tri_index(I, K) * TS2;
+#pragma unroll
+    for (int q = 0; q < LN::NQ; ++q) {
+      const int r = wv * 16 + q * LN::RPL + lrow;
+      const V xv = *reinterpret_cast<const V*>(tile + r * TS + c0);
+      const T* x = reinterpret_cast<const T*>(&xv);
+      double t = (double)x[0] * vk[0];
+#pragma unroll
+      for (int e = 1; e < LN::VEC; ++e) t += (double)x[e] * vk[e];
+      acc[q] += t;
     }
   }
   double* pb = part + bm.poff[b] + ((int64_t)I * nch + c) * TS;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < LN::NQ; ++q) {
     double a = acc[q];
-    for (int o = 16; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-    if ((lane & 31) == 0) pb[wv * 16 + q * 2 + lrow] = a;
+    for (int o = LN::LPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane % LN::LPR == 0) pb[wv * 16 + q * LN::RPL + lrow] = a;
   }
 }
 
 // Columns: part[K][c] = sum_{I in chunk c of [K, nt)} X_IK^T y_I.
+template <typename T>
 __global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
-                                                   const double* __restrict__ X,
+                                                   const T* __restrict__ X,
                                                    const double* __restrict__ y,
                                                    double* __restrict__ part) {
+  typedef TrmvLanes<T> LN;
+  typedef typename Vec16<T>::type V;
   const int b = blockIdx.y, ntb = bm.nt[b];
   const int K = blockIdx.x / nchx, c = blockIdx.x % nchx;
   const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
@@ -383,26 +408,30 @@ __global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const
   const int i1 = min(ntb, i0 + TRMV_CH);
   __shared__ double red[4 * TS];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lrow = lane >> 5, c0 = (lane & 31) * 2;
-  const double* Xb = X + bm.off[b] * TS2;
+  const int lrow = lane / LN::LPR, c0 = (lane % LN::LPR) * LN::VEC;
+  const T* Xb = X + bm.off[b] * TS2;
   const double* yb = y + bm.xoff[b];
-  double a0 = 0.0, a1 = 0.0;
-  for (int I = i0; I < i1; ++I) {
-    const double* tile = Xb + tri_index(I, K) * TS2;
+  double a[LN::VEC];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = wv * 16 + q * 2 + lrow;
-      const double2 x = *reinterpret_cast<const double2*>(tile + r * TS + c0);
+  for (int e = 0; e < LN::VEC; ++e) a[e] = 0.0;
+  for (int I = i0; I < i1; ++I) {
+    const T* tile = Xb + tri_index(I, K) * TS2;
+#pragma unroll
+    for (int q = 0; q < LN::NQ; ++q) {
+      const int r = wv * 16 + q * LN::RPL + lrow;
+      const V xv = *reinterpret_cast<const V*>(tile + r * TS + c0);
+      const T* x = reinterpret_cast<const T*>(&xv);
       const double yr = yb[I * TS + r];
-      a0 += x.x * yr;
-      a1 += x.y * yr;
+#pragma unroll
+      for (int e = 0; e < LN::VEC; ++e) a[e] += (double)x[e] * yr;
     }
   }
-  a0 += __shfl_xor(a0, 32, 64);
-  a1 += __shfl_xor(a1, 32, 64);
-  if (lane < 32) {
-    red[wv * TS + c0] = a0;
-    red[wv * TS + c0 + 1] = a1;
+#pragma unroll
+  for (int e = 0; e < LN::VEC; ++e)
+    for (int o = LN::LPR; o < 64; o <<= 1) a[e] += __shfl_xor(a[e], o, 64);
+  if (lane < LN::LPR) {
+#pragma unroll
+    for (int e = 0; e < LN::VEC; ++e) red[wv * TS + c0 + e] = a[e];
   }
   __syncthreads();
   if (threadIdx.x < TS) {
@@ -436,15 +465,43 @@ __global__ __launch_bounds__(TS) void k_trmv_reduce(BatchMeta bm, const int32_t*
   }
 }
 
+template <typename T>
 void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
-                         const int64_t* doff, const double* X, const double* v, double* ytmp,
+                         const int64_t* doff, const T* X, const double* v, double* ytmp,
                          double* part, double* out, const int32_t* active, hipStream_t s) {
   const int nchx = (max_nt + TRMV_CH - 1) / TRMV_CH;
   const dim3 grid(max_nt * nchx, nb);
-  hipLaunchKernelGGL(k_trmv_rows, grid, dim3(256), 0, s, bm, nchx, active, X, v, part);
+  hipLaunchKernelGGL(k_trmv_rows<T>, grid, dim3(256), 0, s, bm, nchx, active, X, v, part);
   hipLaunchKernelGGL(k_trmv_reduce<0>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, ytmp);
-  hipLaunchKernelGGL(k_trmv_cols, grid, dim3(256), 0, s, bm, nchx, active, X, ytmp, part);
+  hipLaunchKernelGGL(k_trmv_cols<T>, grid, dim3(256), 0, s, bm, nchx, active, X, ytmp, part);
   hipLaunchKernelGGL(k_trmv_reduce<1>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, out);
+}
+
+template void launch_coarse_apply<float>(int, int, const BatchMeta&, const int32_t*, const int64_t*,
+                                         const float*, const double*, double*, double*, double*,
+                                         const int32_t*, hipStream_t);
+template void launch_coarse_apply<double>(int, int, const BatchMeta&, const int32_t*, const int64_t*,
+                                          const double*, const double*, double*, double*, double*,
+                                          const int32_t*, hipStream_t);
+
+// Rounds n FP64 values to FP32 (a coarse factor kept beside FP32 subdomain
+// factors).
+__global__ __launch_bounds__(256) void k_round_f32(int64_t n, const double* __restrict__ src,
+                                                   float* __restrict__ dst) {
+  const int64_t i4 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i4 + 4 <= n) {
+    const double2 a = *reinterpret_cast<const double2*>(src + i4);
+    const double2 b = *reinterpret_cast<const double2*>(src + i4 + 2);
+    *reinterpret_cast<float4*>(dst + i4) = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+  } else {
+    for (int64_t i = i4; i < n; ++i) dst[i] = (float)src[i];
+  }
+}
+
+void launch_round_f32(int64_t n, const double* src, float* dst, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t nb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(k_round_f32, dim3((unsigned)nb), dim3(256), 0, s, n, src, dst);
 }
 
 // ---------------------------------------------------------------------------

@@ -137,9 +137,11 @@ void launch_restrict(const Batch& B, int max_block, const double* v, double* c0,
 // out = X^T (X v) for packed lower-tiled FP64 X (the coarse operator X = L_0^{-1}):
 // v tile-padded at bm.xoff, ytmp the same layout, part the per-(tile, chunk)
 // partials at bm.poff, out unpadded at doff (n[b] entries).
+template <typename T>
 void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
-                         const int64_t* doff, const double* X, const double* v, double* ytmp,
+                         const int64_t* doff, const T* X, const double* v, double* ytmp,
                          double* part, double* out, const int32_t* active, hipStream_t s);
+void launch_round_f32(int64_t n, const double* src, float* dst, hipStream_t s);
 void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
                     double* out, hipStream_t s);
 

@@ -591,14 +591,21 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
 }
 
 // F v = R_0^T A_0^{-1} R_0 v: restriction into c0, then
-// d0 = A_0^{-1} c0 = X_0^T (X_0 c0) with X_0 = L_0^{-1} (per grid).
+// d0 = A_0^{-1} c0 = X_0^T (X_0 c0) with X_0 = L_0^{-1} (per grid; FP32
+// entries in the second half of the X0 region beside FP32 subdomain factors,
+// FP64 otherwise).
 void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) {
   ProfScope ps(c, SFCDD_K_COARSE);
   const Batch B = c->batch();
   BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
   launch_restrict(B, c->max_cblock, v, c->c0, c->stream);
-  launch_coarse_apply(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart, c->d0,
-                      mask, c->stream);
+  if (c->fdtype == SFCDD_FP32)
+    launch_coarse_apply<float>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff,
+                               reinterpret_cast<const float*>(c->X0) + c->ctiles * TS2, c->c0, c->cy,
+                               c->cpart, c->d0, mask, c->stream);
+  else
+    launch_coarse_apply<double>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart,
+                                c->d0, mask, c->stream);
 }
 
 // Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
@@ -829,8 +836,20 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
-    factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
+    // Beside FP32 subdomain factors the inverse is formed and kept in FP32
+    // from the FP64 Cholesky factor: A_0 is an M-matrix (a Galerkin
+    // aggregation of the stencil matrix), so L_0 has non-positive
+    // off-diagonal entries, L_0^{-1} is entrywise non-negative and every sum
+    // that forms it has terms of one sign (no cancellation).
+    const bool x32 = c->fdtype == SFCDD_FP32;
+    factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, !x32, false, c->status + 1,
                          G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
+    if (x32) {
+      float* L32 = reinterpret_cast<float*>(c->X0);
+      launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
+      launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
+                              reinterpret_cast<float*>(c->cpartk), cs);
+    }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
     HIPCHK(c, hipEventRecord(join, cs));

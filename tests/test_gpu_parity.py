@@ -414,3 +414,38 @@ def test_autotune_choice_kept_per_shape():
     x, _ = S2.solve(dvec(f0), rtol=1e-12, method="fcg")
     assert relerr(host(x), exact.solve(g, f0)) <= 1e-9
     S2.close()
+
+
+def test_caller_workspace_sizes():
+    """A caller's workspace of exactly the queried size works at any byte
+    offset within its 256 bytes of slack; a buffer one byte short of the need
+    at an aligned address fails with ENOMEM; a batch context accepts a
+    workspace of its own query."""
+    announce("caller workspace")
+    kw = dict(levels=(5, 4), P=6, gamma=Fraction(1, 2), factor_dtype="fp64")
+    nbytes = m.workspace_size(**kw)
+    buf = torch.empty(nbytes + 512, dtype=torch.uint8, device=DEV)
+    g = Grid(levels=(5, 4))
+    f0 = uniform_pm1(2, g.N)
+    ex = exact.solve(g, f0)
+    base = buf.data_ptr()
+    aligned = (-base) % 256
+    for off in (aligned, aligned + 1, aligned + 255):
+        S = m.SFCSchwarz(workspace=buf[off:off + nbytes], **kw)
+        assert S.workspace_bytes == nbytes
+        x, _ = S.solve(dvec(f0), rtol=1e-12)
+        assert relerr(host(x), ex) <= 1e-9
+        S.close()
+    with pytest.raises(m.SfcddError) as e:
+        m.SFCSchwarz(workspace=buf[aligned:aligned + nbytes - 257], **kw)
+    assert e.value.status == m.ENOMEM
+    with pytest.raises(ValueError):
+        m.SFCSchwarz(workspace=torch.empty(nbytes, dtype=torch.float64, device=DEV), **kw)
+    grids = [dict(levels=[5, 4], P=6), dict(levels=[3, 3], P=2)]
+    B = m.SFCSchwarzBatch(grids, factor_dtype="fp64")
+    want = B.workspace_bytes
+    assert B.ws.numel() == want
+    B.close()
+    B = m.SFCSchwarzBatch(grids, factor_dtype="fp64", workspace=torch.empty(want, dtype=torch.uint8, device=DEV))
+    assert B.workspace_bytes == want
+    B.close()
