@@ -88,10 +88,8 @@ typedef struct {
                                 0 = 2^(floor(log2(N/P)) - 4), capped at qP <= 16384    */
   int32_t weighting;         /* SFCDD_WEIGHT_NONE, _OMEGA (eq. omegai) or _D (eq. Di)    */
   int32_t variant;           /* SFCDD_ADDITIVE, SFCDD_BALANCED or SFCDD_DEFLATED         */
-  int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves;
-                                the coarse Cholesky factor is FP64 either way, and
-                                its inverse is kept in the same precision as the
-                                subdomain factors                                      */
+  int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves
+                                (and coarse inverse; see sfcdd_info.coarse_fp32)       */
   int32_t local_solver;      /* SFCDD_LOCAL_CHOLESKY: forward/backward substitution
                                 with the Cholesky factor; SFCDD_LOCAL_INVERSE: the
                                 explicit inverse formed from it, applied as a
@@ -123,6 +121,11 @@ typedef struct {
                                 total                                                  */
   int32_t ngrids;            /* grids in the context (1 unless set up as a batch)      */
   int32_t trsv_waves;        /* waves per workgroup of the substitution kernel          */
+  int32_t coarse_fp32;       /* 1: the coarse Cholesky factor is FP32 (FP32 subdomain
+                                factors and every coarse matrix well conditioned by
+                                the bound kappa(A) * max block / min block <= 4096);
+                                0: FP64.  Its inverse X_0 = L_0^{-1} is FP32 whenever
+                                the subdomain factors are                              */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1

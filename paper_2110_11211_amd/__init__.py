@@ -68,7 +68,7 @@ class Info(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("sum_Ni", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("factor_algo_bytes", ctypes.c_int64), ("coarse_bytes", ctypes.c_int64),
                 ("setup_ms", ctypes.c_double * 6), ("ngrids", ctypes.c_int32),
-                ("trsv_waves", ctypes.c_int32)]
+                ("trsv_waves", ctypes.c_int32), ("coarse_fp32", ctypes.c_int32)]
 
 
 _lib = None

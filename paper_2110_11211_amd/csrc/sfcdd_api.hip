@@ -59,6 +59,7 @@ struct sfcdd_ctx {
   int64_t Ntot = 0, N0tot = 0;
   int Ptot = 0, dmax = 0, rbx = RED_BLOCKS;
   int max_cblock = 1;  // largest coarse block (points) of any grid
+  bool coarse32 = false;  // FP32 coarse Cholesky factor (see coarse_fp32_ok)
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // internal, default priority: coarse setup overlaps the fine factorisation
   // per-subdomain (batch-global) host tables
@@ -360,6 +361,39 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
 #undef GFAIL
 }
 
+// Bound on the condition number of a coarse matrix: with R_0 R_0^T =
+// diag(block sizes), the Rayleigh quotients of A_0 = R_0 A R_0^T lie in
+// [lambda_min(A) b_min, lambda_max(A) b_max], so kappa(A_0) <= kappa(A)
+// b_max / b_min, with the stencil's extreme eigenvalues
+// sum_j (a_j / h_j^2) 4 sin^2(k pi h_j / 2), k = 1 and n_j.  Pieces of
+// floor(N/P) or that + 1 points are cut into q blocks of near-equal size.
+double coarse_kappa_bound(const GridDesc& gd) {
+  const double pi = 3.14159265358979323846;
+  double lmin = 0.0, lmax = 0.0;
+  for (int j = 0; j < gd.d; ++j) {
+    const double t = pi / (2.0 * (gd.n[j] + 1));
+    lmin += gd.c[j] * 4.0 * std::sin(t) * std::sin(t);
+    lmax += gd.c[j] * 4.0 * std::cos(t) * std::cos(t);
+  }
+  const double bmin = (double)std::max<int64_t>(1, gd.base / gd.q);
+  const double bmax = (double)ceil_div(gd.base + 1, (int64_t)gd.q);
+  return lmax / lmin * bmax / bmin;
+}
+
+// The coarse factorisation may run in FP32 (beside FP32 subdomain factors)
+// when every coarse matrix of the context is well conditioned: solves with
+// an FP32 Cholesky factor are accurate to about kappa * 6e-8, so the bound
+// 4096 keeps them within a few 1e-4 (the 8192 coarse unknowns of the
+// (7,6,5) grid with 256 subdomains: bound 3.0e3, kappa(A_0) = 99, error
+// about 2e-7), an error of the order the FP32 subdomain solves already make
+// (their matrices are principal submatrices of A, kappa(A_i) <= kappa(A)).
+constexpr double COARSE32_KAPPA = 4096.0;
+bool coarse_fp32_ok(const sfcdd_ctx* c) {
+  for (int k = 0; k < c->G; ++k)
+    if (!(coarse_kappa_bound(c->grid[k].desc) <= COARSE32_KAPPA)) return false;
+  return true;
+}
+
 // Plans the whole batch: per-grid partitions, batch placement, workspace.
 sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   if (G < 1 || G > 65535) FAIL(c, SFCDD_EINVAL, "number of grids %d out of range 1..65535", G);
@@ -460,6 +494,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     const GridDesc& gd = c->grid[k].desc;
     c->max_cblock = (int)std::max<int64_t>(c->max_cblock, ceil_div(gd.base + 1, gd.q));
   }
+  c->coarse32 = c->fdtype == SFCDD_FP32 && coarse_fp32_ok(c);
 
   // workspace layout
   const size_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
@@ -836,19 +871,30 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
-    // Beside FP32 subdomain factors the inverse is formed and kept in FP32
-    // from the FP64 Cholesky factor: A_0 is an M-matrix (a Galerkin
-    // aggregation of the stencil matrix), so L_0 has non-positive
-    // off-diagonal entries, L_0^{-1} is entrywise non-negative and every sum
-    // that forms it has terms of one sign (no cancellation).
-    const bool x32 = c->fdtype == SFCDD_FP32;
-    factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, !x32, false, c->status + 1,
-                         G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
-    if (x32) {
+    // Beside FP32 subdomain factors the inverse X_0 = L_0^{-1} is FP32: A_0
+    // is an M-matrix (a Galerkin aggregation of the stencil matrix), so L_0
+    // has non-positive off-diagonal entries, X_0 is entrywise non-negative
+    // and every sum that forms it has terms of one sign (no cancellation).
+    // The factor itself is FP32 as well when the coarse matrices are well
+    // conditioned (coarse_fp32_ok), else FP64 and rounded.  FP32 tiles: L_0
+    // in the first half of the X0 region, X_0 in the second.
+    if (c->fdtype == SFCDD_FP32) {
       float* L32 = reinterpret_cast<float*>(c->X0);
-      launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
-      launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
-                              reinterpret_cast<float*>(c->cpartk), cs);
+      float* part32 = reinterpret_cast<float*>(c->cpartk);
+      if (c->coarse32) {
+        launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
+        factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
+                            c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs);
+      } else {
+        factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, false, false, c->status + 1,
+                             G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
+        launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
+        launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
+                                part32, cs);
+      }
+    } else {
+      factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
+                           G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
@@ -918,6 +964,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.setup_ms[5] = tot;
   I.ngrids = G;
   I.trsv_waves = c->trsv_waves;
+  I.coarse_fp32 = c->coarse32 ? 1 : 0;
 
   int32_t stat[2] = {0, 0};
   HIPCHK(c, hipMemcpy(stat, c->status, 8, hipMemcpyDeviceToHost));

@@ -449,3 +449,19 @@ def test_caller_workspace_sizes():
     B = m.SFCSchwarzBatch(grids, factor_dtype="fp64", workspace=torch.empty(want, dtype=torch.uint8, device=DEV))
     assert B.workspace_bytes == want
     B.close()
+
+
+def test_coarse_factor_precision_choice():
+    """FP32 subdomain factors take an FP32 coarse factor only when the bound
+    kappa(A) b_max / b_min on kappa(A_0) is at most 4096: the (7,6,5) grid
+    with 256 subdomains (bound 3.0e3) does, the (14,1) grid with 128 (bound
+    ~5e7) does not; FP64 factors never do."""
+    announce("coarse precision choice")
+    w = workloads()["c2"]
+    for fdtype, want in (("fp32", 1), ("fp64", 0)):
+        S = _solver(w.levels[0], w.P, w.gamma, factor_dtype=fdtype)
+        assert S.info()["coarse_fp32"] == want, fdtype
+        S.close()
+    S = m.SFCSchwarz(levels=(14, 1), P=128, gamma=Fraction(1, 4), factor_dtype="fp32")
+    assert S.info()["coarse_fp32"] == 0
+    S.close()
