@@ -326,31 +326,46 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
   }
   g.F = (int)std::min<int64_t>(F, P);
   g.ncand = (int)std::min<int64_t>(P, 2 * F + 3);
-  // multiplicities and omega_i = 1 / min_{p in Omega_i} m_p (eq. omegai)
+  // multiplicities and omega_i = 1 / min_{p in Omega_i} m_p (eq. omegai).
+  // m is constant between subdomain ends, so it is kept as at most 2P + 1
+  // runs (start position, value) and each subdomain takes the minimum over
+  // the runs its cyclic range meets: O(P log P + sum of runs met), not O(N).
   h.omega.assign(P, 1.0);
   if (p->weighting == SFCDD_WEIGHT_OMEGA) {
-    std::vector<int32_t> m(N + 1, 0);
+    std::vector<std::pair<int64_t, int32_t>> ev;  // (position, change of m)
+    ev.reserve(4 * (size_t)P + 1);
+    ev.emplace_back(0, 0);
     for (int i = 0; i < P; ++i) {
       const int64_t a = h.ta[i], e = a + h.Ni[i];
+      ev.emplace_back(a, 1);
       if (e <= N) {
-        m[a] += 1;
-        m[e] -= 1;
+        ev.emplace_back(e, -1);
       } else {
-        m[a] += 1;
-        m[N] -= 1;
-        m[0] += 1;
-        m[e - N] -= 1;
+        ev.emplace_back(N, -1);
+        ev.emplace_back(0, 1);
+        ev.emplace_back(e - N, -1);
       }
     }
-    for (int64_t k = 1; k < N; ++k) m[k] += m[k - 1];
+    std::sort(ev.begin(), ev.end());
+    std::vector<int64_t> rs;  // run starts, strictly increasing, rs[0] = 0, all < N
+    std::vector<int32_t> rv;  // m on [rs[k], rs[k + 1])
+    int32_t cur = 0;
+    for (size_t k = 0; k < ev.size();) {
+      const int64_t pos = ev[k].first;
+      for (; k < ev.size() && ev[k].first == pos; ++k) cur += ev[k].second;
+      if (pos >= N) break;
+      rs.push_back(pos);
+      rv.push_back(cur);
+    }
+    auto run_min = [&](int64_t lo, int64_t hi, int32_t mn) {  // min over [lo, hi), 0 <= lo < hi <= N
+      size_t k = (size_t)(std::upper_bound(rs.begin(), rs.end(), lo) - rs.begin()) - 1;
+      for (; k < rs.size() && rs[k] < hi; ++k) mn = std::min(mn, rv[k]);
+      return mn;
+    };
     for (int i = 0; i < P; ++i) {
-      int32_t mn = INT32_MAX;
-      const int64_t a = h.ta[i];
-      for (int64_t s = 0; s < h.Ni[i]; ++s) {
-        int64_t q2 = a + s;
-        if (q2 >= N) q2 -= N;
-        mn = std::min(mn, m[q2]);
-      }
+      const int64_t a = h.ta[i], e = a + h.Ni[i];
+      int32_t mn = run_min(a, std::min<int64_t>(e, N), INT32_MAX);
+      if (e > N) mn = run_min(0, e - N, mn);
       h.omega[i] = 1.0 / (double)mn;
     }
   }

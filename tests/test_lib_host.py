@@ -49,6 +49,23 @@ def test_partition_host_matches_oracle(levels, P, gamma):
     assert np.array_equal(om, oom) and q == oq
 
 
+def test_partition_host_random_small_cases():
+    """Random small grids, P and gamma (including P = N, gamma beyond full
+    overlap, and wrapping subdomains) against the oracle's set construction."""
+    rng = np.random.default_rng(2024)
+    for _ in range(60):
+        d = int(rng.integers(1, 3))
+        levels = tuple(int(v) for v in rng.integers(1, 5, size=d))
+        N = Grid(levels=levels).N
+        P = int(rng.integers(1, N + 1))
+        gamma = Fraction(int(rng.integers(0, 13)), int(rng.integers(1, 5)))
+        ta, Ni, om, q = m.partition_host(levels=levels, P=P, gamma=gamma)
+        ota, oNi, oom, oq = _oracle_partition(levels, P, gamma)
+        case = (levels, P, gamma)
+        assert np.array_equal(ta, ota) and np.array_equal(Ni, oNi), case
+        assert np.array_equal(om, oom) and q == oq, case
+
+
 def test_partition_host_ct_layer():
     w = workloads()["c4"]
     for lv in w.levels[::7]:
