@@ -819,6 +819,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   std::vector<GridDesc> gd(G);
   for (int k = 0; k < G; ++k) gd[k] = c->grid[k].desc;
   std::vector<uint16_t> gid, cgid, ctgid;
+  std::vector<unsigned char> img, cimg;
   if (G > 1) {
     gid.resize(c->Ntot);
     cgid.resize(c->N0tot);
@@ -834,23 +835,25 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->cgid, cgid.data(), 2 * c->N0tot, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->ctgid, ctgid.data(), 2 * c->ctiles, hipMemcpyHostToDevice, s));
   }
-  HIPCHK(c, hipMemcpyAsync(c->d_grids, gd.data(), sizeof(GridDesc) * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_ta, c->ta.data(), 4 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_Ni, c->Ni.data(), 4 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_nt, c->nt.data(), 4 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_off, c->off.data(), 8 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_doff, c->doff.data(), 8 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_xoff, c->xoff.data(), 8 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_poff, c->poff.data(), 8 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_omega, c->omega.data(), 8 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->d_sgid, c->sgid.data(), 2 * Pt, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_off, c->c_off.data(), 8 * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_xoff, c->c_xoff.data(), 8 * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_poff, c->c_poff.data(), 8 * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_doff, c->c_doff.data(), 8 * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_toff, c->c_toff.data(), 8 * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_nt, c->c_nt.data(), 4 * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->dc_n, c->c_n.data(), 4 * G, hipMemcpyHostToDevice, s));
+  // the per-grid and per-subdomain tables (consecutive workspace regions)
+  // and the coarse metadata go up as one host image each
+  {
+    const Region* tabs[] = {&c->r_grids, &c->r_ta, &c->r_Ni, &c->r_nt, &c->r_off, &c->r_doff,
+                            &c->r_xoff, &c->r_poff, &c->r_omega, &c->r_sgid};
+    const void* srcs[] = {gd.data(), c->ta.data(), c->Ni.data(), c->nt.data(), c->off.data(),
+                          c->doff.data(), c->xoff.data(), c->poff.data(), c->omega.data(), c->sgid.data()};
+    const size_t t0 = c->r_grids.off, t1 = c->r_sgid.off + c->r_sgid.bytes;
+    img.assign(t1 - t0, 0);
+    for (int k = 0; k < 10; ++k) std::memcpy(img.data() + (tabs[k]->off - t0), srcs[k], tabs[k]->bytes);
+    HIPCHK(c, hipMemcpyAsync(c->ws + t0, img.data(), t1 - t0, hipMemcpyHostToDevice, s));
+    cimg.assign(c->r_cmeta.bytes, 0);
+    unsigned char* q = cimg.data();
+    const std::vector<int64_t>* c64[] = {&c->c_off, &c->c_xoff, &c->c_poff, &c->c_doff, &c->c_toff};
+    for (auto* v : c64) { std::memcpy(q, v->data(), 8 * (size_t)G); q += 8 * (size_t)G; }
+    std::memcpy(q, c->c_nt.data(), 4 * (size_t)G);
+    std::memcpy(q + 4 * (size_t)G, c->c_n.data(), 4 * (size_t)G);
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->r_cmeta.off, cimg.data(), c->r_cmeta.bytes, hipMemcpyHostToDevice, s));
+  }
   HIPCHK(c, hipMemsetAsync(c->status, 0, 64, s));
   HIPCHK(c, hipStreamSynchronize(s));
 
@@ -927,16 +930,16 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[3], s));
 
-  // factor once (Sec. 3.1).  The two-column batched kernel is faster alone
-  // but takes the SIMD room that a workgroup of the single-matrix coarse
-  // chain (running beside it) needs; keep the one-column kernel when that
-  // chain is a sizeable share of the setup work (FP32 factors; FP64 leaves
-  // no room either way).
+  // factor once (Sec. 3.1).  The two-column batched kernel (380 registers
+  // per lane in FP32) is faster alone but leaves room on a SIMD only for a
+  // workgroup of the FP32 coarse chain (120), not of the FP64 one (196);
+  // keep the one-column kernel (264) beside an FP64 coarse chain that is a
+  // sizeable share of the setup work (FP64 factors leave no room either way).
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   double fine_work = 0.0;
   for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
   const double coarse_work = G == 1 ? std::pow((double)c->N0tot, 3.0) : 0.0;
-  const bool pair = c->fdtype == SFCDD_FP64 || coarse_work < 0.15 * fine_work;
+  const bool pair = c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work;
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
                         c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s);
