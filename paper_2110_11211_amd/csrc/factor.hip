@@ -848,93 +848,131 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_diag_copy(const int32_t*
   for (int e = threadIdx.x; e < TS2 / VEC; e += TILE_THREADS) dst[e] = src[e];
 }
 
-// T_ij = sum_{k = j}^{B0 - 1} L_ik X_kj for i in B, j in A.  Workgroups with
-// the longest sums (small jj) are dispatched first.
-template <typename T>
+// Rows of B per workgroup in the inversion products: the R row tiles share
+// the loads of the other operand (1 + 1/R tile loads per product instead of
+// 2), and at about 110 registers per lane (FP32) a workgroup still fits on a
+// SIMD beside the two-column batched factorisation.
+constexpr int TRTRI_ROWS = 2;
+
+// T_ij = sum_{k = j}^{B0 - 1} L_ik X_kj for i in B, j in A: workgroup (jj, g)
+// forms the R tiles i = B0 + g R + r of column j = A0 + jj (one X_kj per
+// step for all of them).  Workgroups with the longest sums (small jj) are
+// dispatched first.
+template <typename T, int R>
 __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32_t* __restrict__ nt,
                                                               const int64_t* __restrict__ off,
                                                               const int64_t* __restrict__ toff,
                                                               const T* __restrict__ L,
                                                               const T* __restrict__ X,
                                                               T* __restrict__ Tb) {
+  constexpr int S = LdsV<T>::v;
   const int b = blockIdx.z, p = blockIdx.y;
-  const int jj = blockIdx.x / s, ii = blockIdx.x % s;
+  const int ng = (s + R - 1) / R;
+  const int jj = blockIdx.x / ng, g = blockIdx.x % ng;
   const int A0 = 2 * p * s, B0 = A0 + s;
-  const int i = B0 + ii, j = A0 + jj;
-  if (i >= nt[b]) return;
+  const int j = A0 + jj, i0 = B0 + g * R;
+  const int nr = min(R, min(B0 + s, nt[b]) - i0);
+  if (nr <= 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LdsV<T>::v;
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  T* sB = lds + R * TS * S;
   const T* Lb = L + off[b] * TS2;
   const T* Xb = X + off[b] * TS2;
-  TileAcc<T> acc;
-  acc.zero();
-  TileRegs<T> ra, rb;
-  ra.load(Lb + tri_index(i, j) * TS2);
+  TileAcc<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r].zero();
+  TileRegs<T> ra[R], rb;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nr) ra[r].load(Lb + tri_index(i0 + r, j) * TS2);
   rb.load(Xb + tri_index(j, j) * TS2);
   for (int k = j; k < B0; ++k) {
     __syncthreads();
-    ra.store_lds(sA);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) ra[r].store_lds(lds + r * TS * S);
     rb.store_lds_t(sB);
     __syncthreads();
     if (k + 1 < B0) {
-      ra.load(Lb + tri_index(i, k + 1) * TS2);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < nr) ra[r].load(Lb + tri_index(i0 + r, k + 1) * TS2);
       rb.load(Xb + tri_index(k + 1, j) * TS2);
     }
-    tile_mma<T>(acc, sA, sB, T(1));                // T_ij += L_ik X_kj
+    tile_mma_rows<T, R>(acc, nr, lds, sB, T(1));   // T_ij += L_ik X_kj
   }
-  acc.store(Tb + (toff[b] + (int64_t)p * s * s + (int64_t)ii * s + jj) * TS2);
+  T* Tp = Tb + (toff[b] + (int64_t)p * s * s + (int64_t)(g * R) * s + jj) * TS2;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nr) acc[r].store(Tp + (int64_t)r * s * TS2);
 }
 
-// X_ij = -sum_{k = B0}^{i} X_ik T_kj for i in B, j in A (longest sums, large
-// ii, first).
-template <typename T>
+// X_ij = -sum_{k = B0}^{i} X_ik T_kj for i in B, j in A: workgroup (g, jj)
+// forms the R tiles i = i0, i0 - 1, .. (from the top of B down) of column
+// j; row i0 - r leaves the sum after k = i0 - r, so the rows still summing
+// are always the first ones.  Longest sums (large i) first.
+template <typename T, int R>
 __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32_t* __restrict__ nt,
                                                               const int64_t* __restrict__ off,
                                                               const int64_t* __restrict__ toff,
                                                               const T* __restrict__ Tb,
                                                               T* __restrict__ X) {
+  constexpr int S = LdsV<T>::v;
   const int b = blockIdx.z, p = blockIdx.y;
-  const int ii = s - 1 - (int)(blockIdx.x / s), jj = blockIdx.x % s;
+  const int g = blockIdx.x / s, jj = blockIdx.x % s;
   const int A0 = 2 * p * s, B0 = A0 + s;
-  const int i = B0 + ii, j = A0 + jj;
-  if (i >= nt[b]) return;
+  const int top = min(B0 + s, nt[b]) - 1 - B0 - g * R;   // row of B (0-based) of the group's first tile
+  if (top < 0) return;
+  const int nrows = min(R, top + 1);
+  const int i0 = B0 + top, j = A0 + jj;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sA = reinterpret_cast<T*>(smem_raw);
-  T* sB = sA + TS * LdsV<T>::v;
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  T* sB = lds + R * TS * S;
   T* Xb = X + off[b] * TS2;
   const T* Tp = Tb + (toff[b] + (int64_t)p * s * s + jj) * TS2;  // T_kj at Tp + (k - B0) s TS2
-  TileAcc<T> acc;
-  acc.zero();
-  TileRegs<T> ra, rb;
-  ra.load(Xb + tri_index(i, B0) * TS2);
+  TileAcc<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r].zero();
+  TileRegs<T> ra[R], rb;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nrows) ra[r].load(Xb + tri_index(i0 - r, B0) * TS2);
   rb.load(Tp);
-  for (int k = B0; k <= i; ++k) {
+  for (int k = B0; k <= i0; ++k) {
+    const int nr = min(nrows, i0 - k + 1);
     __syncthreads();
-    ra.store_lds(sA);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nr) ra[r].store_lds(lds + r * TS * S);
     rb.store_lds_t(sB);
     __syncthreads();
-    if (k + 1 <= i) {
-      ra.load(Xb + tri_index(i, k + 1) * TS2);
+    if (k + 1 <= i0) {
+      const int nr1 = min(nrows, i0 - k);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r < nr1) ra[r].load(Xb + tri_index(i0 - r, k + 1) * TS2);
       rb.load(Tp + (int64_t)(k + 1 - B0) * s * TS2);
     }
-    tile_mma<T>(acc, sA, sB, T(-1));               // X_ij -= X_ik T_kj
+    tile_mma_rows<T, R>(acc, nr, lds, sB, T(-1));  // X_ij -= X_ik T_kj
   }
-  acc.store(Xb + tri_index(i, j) * TS2);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r < nrows) acc[r].store(Xb + tri_index(i0 - r, j) * TS2);
 }
 
 template <typename T>
 void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
                       const T* L, T* X, T* Tb, hipStream_t st) {
-  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
-  static bool once = (allow_lds(k_trtri_rec_t<T>, sh), allow_lds(k_trtri_rec_x<T>, sh), true);
+  constexpr int R = TRTRI_ROWS;
+  const size_t sh = (R + 1) * TS * LdsV<T>::v * sizeof(T);
+  static bool once = (allow_lds(k_trtri_rec_t<T, R>, sh), allow_lds(k_trtri_rec_x<T, R>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_trtri_diag_copy<T>, dim3(max_nt, nb), dim3(TILE_THREADS), 0, st, nt, off, L, X);
   for (int s = 1; s < max_nt; s *= 2) {
     const int npairs = (max_nt + 2 * s - 1) / (2 * s);
-    const dim3 grid(s * s, npairs, nb);
-    hipLaunchKernelGGL(k_trtri_rec_t<T>, grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, L, X, Tb);
-    hipLaunchKernelGGL(k_trtri_rec_x<T>, grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X);
+    const dim3 grid(s * ((s + R - 1) / R), npairs, nb);
+    hipLaunchKernelGGL((k_trtri_rec_t<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, L, X, Tb);
+    hipLaunchKernelGGL((k_trtri_rec_x<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X);
   }
 }
 
