@@ -266,7 +266,8 @@ sfcdd_status sfcdd_ct_combine(sfcdd_ctx* ctx, const double* weights_dev, const d
 
 /* Streaming-read rate of the device, for roofline context: reads the device
  * buffer buf_dev (bytes, a multiple of 16, 16-byte aligned; its contents are
- * not changed) with a 16-byte-per-lane grid-stride kernel `repeats` times on
+ * not changed) with a 16-byte-per-lane grid-stride kernel (non-temporal
+ * loads, as the substitution kernel streams its factors) `repeats` times on
  * hip_stream (NULL = default stream) and returns the shortest time in
  * *best_ms.  Needs no context.  Synchronous. */
 sfcdd_status sfcdd_read_probe(const void* buf_dev, size_t bytes, void* hip_stream, int32_t repeats,

@@ -116,7 +116,7 @@ void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, 
 // updating (flag not RUN or RESTART) are skipped.
 template <typename T>
 void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                         const int64_t* off, const int64_t* doff, int max_nt, int waves,
+                         const int64_t* off, const int64_t* doff, int max_nt, int waves, bool stream,
                          const T* fac, const double* w, double* dbuf, const int32_t* active,
                          hipStream_t s);
 template <typename T>

@@ -103,6 +103,7 @@ struct sfcdd_ctx {
   hipEvent_t ev_rb = nullptr;  // readback of the per-iteration scalars
   // host copy of the device activity flags (valid after the first upload)
   std::vector<int32_t> active_shadow;
+  std::vector<int64_t> gfac_bytes;  // subdomain factor bytes per grid
   bool active_valid = false, active_in_flight = false;
   std::vector<double> last_relres;
   std::string err;
@@ -443,9 +444,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->c_doff.clear(); c->c_toff.clear();
   int64_t toff = 0, dof = 0, xof = 0, pof = 0, ctoff = 0, cpof = 0, ctt = 0;
   c->max_nt = 0; c->max_Ni = 0; c->min_Ni = INT32_MAX; c->max_nt0 = 0; c->max_N0 = 0;
+  c->gfac_bytes.assign(G, 0);
   for (int k = 0; k < G; ++k) {
     GridHost& h = c->grid[k];
     GridDesc& g = h.desc;
+    const int64_t toff0 = toff;
     g.goff = goff;
     g.soff = soff;
     g.c0off = c0off;
@@ -474,6 +477,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
       c->max_Ni = std::max(c->max_Ni, h.Ni[i]);
       c->min_Ni = std::min(c->min_Ni, h.Ni[i]);
     }
+    c->gfac_bytes[k] = (toff - toff0) * TS2 * (c->fdtype == SFCDD_FP32 ? 4 : 8);
     c->c_nt.push_back(g.nt0);
     c->c_n.push_back(g.N0);
     c->c_off.push_back(ctoff);
@@ -659,15 +663,36 @@ void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) 
 }
 
 // Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
+// Whether the substitution streams its factors with non-temporal loads: only
+// when the factors that one sweep has in flight (about 512 subdomains at a
+// time) exceed the 256 MB last-level cache.  Smaller working sets are read
+// faster without the hint: small subdomains find their tiles again in the
+// caches on the backward sweep, and a few grids still iterating find them
+// there in the next iteration.  "Being solved" means all grids, or those
+// still iterating as of the host's last look.
+constexpr int64_t STREAM_FACTOR_BYTES = int64_t(256) << 20;
+bool stream_factors(const sfcdd_ctx* c, const int32_t* mask) {
+  const bool all = !mask || (int)c->active_shadow.size() != c->G;
+  int64_t bytes = 0, nsub = 0;
+  for (int g = 0; g < c->G; ++g)
+    if (all || act_updating(c->active_shadow[g])) {
+      bytes += c->gfac_bytes[g];
+      nsub += c->grid[g].desc.P;
+    }
+  if (nsub == 0 || bytes <= STREAM_FACTOR_BYTES) return false;
+  return (double)bytes / (double)nsub * (double)std::min<int64_t>(nsub, 512) > (double)STREAM_FACTOR_BYTES;
+}
+
 void local_solves(sfcdd_ctx* c, const double* w, int waves, const int32_t* mask = nullptr) {
   const hipStream_t s = c->stream;
   const Batch B = c->batch();
   if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
+    const bool nt = stream_factors(c, mask);
     if (c->fdtype == SFCDD_FP32)
-      launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves,
+      launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves, nt,
                                  (const float*)c->fac, w, c->dbuf, mask, s);
     else
-      launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves,
+      launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves, nt,
                                   (const double*)c->fac, w, c->dbuf, mask, s);
   } else {
     BatchMeta bm{c->d_nt, c->d_off, c->d_xoff, c->d_poff};
