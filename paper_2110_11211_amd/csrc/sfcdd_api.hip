@@ -98,7 +98,10 @@ struct sfcdd_ctx {
   double* vec[NVEC] = {};
   double *partials = nullptr, *scal = nullptr, *gout = nullptr;
   int32_t *active = nullptr, *status = nullptr;
-  double* host_scal = nullptr;  // pinned, G * S_COUNT + G + 256 doubles
+  double* host_scal = nullptr;  // pinned: an image of the workspace bytes from the scalars
+                                // to the end of the flags (rb_bytes; flags at byte rb_flags),
+                                // then the flag upload buffer (G int32 at byte hb_off)
+  size_t rb_bytes = 0, rb_flags = 0, hb_off = 0;
   std::vector<int32_t> last_iters;
   hipEvent_t ev_rb = nullptr;  // readback of the per-iteration scalars
   // host copy of the device activity flags (valid after the first upload)
@@ -787,7 +790,7 @@ double hs(sfcdd_ctx* c, int g, int slot) { return c->host_scal[(size_t)g * S_COU
 sfcdd_status write_active(sfcdd_ctx* c, const std::vector<int32_t>& act) {
   if (c->active_valid && act == c->active_shadow) return SFCDD_OK;
   if (c->active_in_flight) HIPCHK(c, hipStreamSynchronize(c->stream));
-  int32_t* hb = reinterpret_cast<int32_t*>(c->host_scal + (size_t)c->G * S_COUNT);
+  int32_t* hb = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(c->host_scal) + c->hb_off);
   for (int g = 0; g < c->G; ++g) hb[g] = act[g];
   HIPCHK(c, hipMemcpyAsync(c->active, hb, 4 * c->G, hipMemcpyHostToDevice, c->stream));
   c->active_in_flight = true;
@@ -1037,7 +1040,11 @@ sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev
   c->ws = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(workspace_dev) + 255) & ~uintptr_t(255));
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   bind(c);
-  if (hipHostMalloc((void**)&c->host_scal, sizeof(double) * ((size_t)G * S_COUNT + (size_t)G + 256),
+  // the scalars and the flags are consecutive workspace regions: one copy reads both back
+  c->rb_flags = c->r_active.off - c->r_scal.off;
+  c->rb_bytes = c->rb_flags + 4 * (size_t)G;
+  c->hb_off = (c->rb_bytes + 255) & ~size_t(255);
+  if (hipHostMalloc((void**)&c->host_scal, c->hb_off + 4 * (size_t)G + 8 * MAXD + 256,
                     hipHostMallocDefault) != hipSuccess) {
     g_last_error = "hipHostMalloc failed";
     delete c;
@@ -1185,10 +1192,9 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   // Asynchronous copy of the residual norms and flags of the step just
   // enqueued; the host waits for it while the next preconditioner
   // application (enqueued speculatively) runs.
-  int32_t* hflags = reinterpret_cast<int32_t*>(c->host_scal + (size_t)G * S_COUNT) + G;
+  int32_t* hflags = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(c->host_scal) + c->rb_flags);
   auto enqueue_readback = [&]() -> sfcdd_status {
-    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * G * S_COUNT, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(hflags, c->active, 4 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, c->rb_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipEventRecord(c->ev_rb, s));
     return SFCDD_OK;
   };
