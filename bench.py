@@ -378,8 +378,8 @@ def progress(what):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
-              f"(the solver's sharding across GPUs is design-only).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} was asked for): the solver has no "
+              f"multi-GPU path; its sharding across GPUs is described, not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -2,7 +2,7 @@
 
 Sec. 3.3 (eq. dof): N = prod_j (2^{l_j} - 1) interior points of the grid with
 mesh widths h_j = 2^{-l_j}.  Sec. 4: -div(alpha grad u) = f on [0,1]^d with
-homogeneous Dirichlet data; this build takes alpha = diag(a_1..a_d) constant,
+homogeneous Dirichlet data; here alpha = diag(a_1..a_d) is constant,
 discretised by the (2d+1)-point finite-difference stencil scaled by 1/h_j^2
 (the scaling under which the level (m,1,...,1) grid reduces to the 1-D
 operator plus 8(d-1) I, Sec. 4.2).
