@@ -634,10 +634,10 @@ __device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__
 // stores visible.
 // PAIR: columns J and J + 1 together (the update by the columns K < J loads
 // each row tile once for both; the two columns are then finished in turn,
-// column J + 1 still taking the term K = J).  About 8% faster alone, but at
-// about 380 registers per lane (FP32) it leaves no room on a SIMD for a
-// workgroup of the single-matrix coarse factorisation, so the launcher takes
-// it only where that does not matter (see launch_potrf_full).
+// column J + 1 still taking the term K = J).  About 8% faster alone; at
+// about 380 registers per lane (FP32) it leaves room on a SIMD for a
+// workgroup of the FP32 single-matrix coarse factorisation (120) but not of
+// the FP64 one, and the caller chooses accordingly.
 template <typename T, bool PAIR>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
