@@ -18,10 +18,12 @@ Prints one JSON line (see the design notes for the field definitions).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
 import time
+from fractions import Fraction
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -48,6 +50,7 @@ def parse():
                     help="with --profile-only: also copy a buffer of this many MiB three times "
                          "(the reference kernel that scales the HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 84-grid layer")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the overlap (gamma) sweep")
     return ap.parse_args()
 
 
@@ -412,6 +415,16 @@ def main():
         return
     zo = run_path(w, f_dev, "fp32", args.local, max(2, args.steps // 2), args.warmup, ws_cache, curve="zorder")
     progress("Z-order path")
+    # the overlap axis of Sec. 4.1 on the same grid: gamma = 1/4, 1 and 3/2
+    # beside the headline's 1/2 (more overlap: fewer iterations, larger
+    # subdomain factors)
+    sweep = []
+    if not args.no_sweep:
+        for gam in (Fraction(1, 4), Fraction(1), Fraction(3, 2)):
+            r = run_path(dataclasses.replace(w, gamma=gam), f_dev, "fp32", args.local, max(2, args.steps // 2),
+                         args.warmup, ws_cache)
+            sweep.append((gam, r))
+        progress("overlap sweep")
     f64 = None
     if not args.skip_fp64:
         f64 = run_path(w, f_dev, "fp64", args.local, max(2, args.steps // 2), args.warmup, ws_cache, prof_steps=1)
@@ -481,6 +494,12 @@ def main():
                        "local_solve_gbps": round(b64 / (ms64 / max(n64, 1) * 1e-3) / 1e9, 1),
                        "setup_phases_ms": i64["setup_ms"]}
         out["speedup_fp32_vs_fp64"] = round(f64["ms"] / head["ms"], 3)
+    if sweep:
+        rows = sorted([(w.gamma, head)] + sweep, key=lambda t: t[0])
+        out["overlap_sweep"] = [{"gamma": str(gm), "ms": round(r["ms"], 3), "setup_ms": round(r["setup_ms"], 3),
+                                 "solve_ms": round(r["solve_ms"], 3), "iterations": r["iterations"],
+                                 "max_Ni": r["info"]["max_Ni"], "factor_bytes": r["info"]["factor_algo_bytes"]}
+                                for gm, r in rows]
     out["zorder"] = {"ms": round(zo["ms"], 3), "setup_ms": round(zo["setup_ms"], 3),
                      "solve_ms": round(zo["solve_ms"], 3), "iterations": zo["iterations"],
                      "iterations_hilbert": head["iterations"],
