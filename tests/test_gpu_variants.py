@@ -68,3 +68,23 @@ def test_overlap_sweep_matches_oracle():
         assert abs(it_g - it_o) <= 1, (gamma, it_o, it_g)
         its.append(it_g)
     assert all(a > b for a, b in zip(its, its[1:])), its
+
+
+def test_weak_scaling_counts_level_off():
+    """Sec. 4.1 weak scaling (N/P = 256 fixed, q = 16, balanced omega_i): the
+    GPU counts for P = 64 and 128 equal the oracle's (+-1) and the counts for
+    P = 64 .. 512 stay within one iteration of each other."""
+    its = {}
+    for p in (64, 128, 256, 512):
+        announce("weak scaling", p)
+        g = Grid(npts=[256 * p])
+        b = uniform_pm1(7, g.N)
+        S = m.SFCSchwarz(npts=[256 * p], P=p, gamma=Fraction(1, 2), q=16, factor_dtype="fp64")
+        _, info = S.solve(dvec(b), rtol=RTOL, method="pcg", plain_start=True, recursive=True)
+        S.close()
+        its[p] = info["iterations"]
+        if p <= 128:
+            O = OracleSchwarz(g, p, Fraction(1, 2), q=16)
+            it_o = solvers.pcg(O.A_nat, b, O.apply, rtol=RTOL)[1]
+            assert abs(its[p] - it_o) <= 1, (p, it_o, its[p])
+    assert max(its.values()) - min(its.values()) <= 1, its
