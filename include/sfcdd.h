@@ -73,7 +73,7 @@ enum { SFCDD_CURVE_ZORDER = 0, SFCDD_CURVE_HILBERT = 1 };
 /* Flags OR-ed into the method of sfcdd_solve: start from x0 exactly as given
  * and apply the full balanced operator every iteration; stop on the recursive
  * residual alone (see sfcdd_solve). */
-enum { SFCDD_SOLVE_PLAIN_START = 256, SFCDD_SOLVE_RECURSIVE = 512 };
+enum { SFCDD_SOLVE_PLAIN_START = 256, SFCDD_SOLVE_RECURSIVE = 512, SFCDD_SOLVE_ENERGY = 1024 };
 
 typedef struct {
   int32_t d;                 /* dimension, 1 <= d <= 16                                */
@@ -183,6 +183,12 @@ sfcdd_status sfcdd_matvec(sfcdd_ctx* ctx, const double* x_dev, double* y_dev);
  * recursive residual of the iteration alone, as in the paper's algorithms
  * (Sec. 4: ||r_k|| / ||r_0|| with r_0 = b for x0 = 0); info.rel_residual is then
  * the recursive one.
+ * With SFCDD_SOLVE_ENERGY OR-ed into method (only for b = 0, EINVAL otherwise:
+ * the protocol of the paper's Sec. 4.1 experiments, a homogeneous problem
+ * from a random start), the error is the iterate itself and a grid stops when
+ * its energy norm sqrt(x_k^T A x_k) <= rtol, evaluated as -(x_k . r_k) with
+ * the iteration's residual; the test is on the iteration alone (as with
+ * SFCDD_SOLVE_RECURSIVE) and info.rel_residual is that energy norm.
  * method: SFCDD_PCG, SFCDD_FCG (flexible CG, beta = z'(r_new - r_old)/z'r_old,
  * for the FP32-factor preconditioner) or SFCDD_RICHARDSON (x += xi C^{-1} r;
  * xi <= 0 estimates xi = 2/(lmin + lmax) from 30 Lanczos steps on the residual

@@ -30,6 +30,7 @@ LOCAL_SOLVER = {"cholesky": 0, "inverse": 1}
 METHOD = {"pcg": 0, "fcg": 1, "richardson": 2}
 SOLVE_PLAIN_START = 256
 SOLVE_RECURSIVE = 512
+SOLVE_ENERGY = 1024
 CURVE = {"zorder": 0, "hilbert": 1}
 LAYOUT = {"natural": 0, "sfc": 1}
 
@@ -269,17 +270,20 @@ class SFCSchwarz:
         return y
 
     def solve(self, b, x0=None, rtol=1e-9, max_iter=1000, method="pcg", xi=0.0, check=True,
-              plain_start=False, recursive=False):
+              plain_start=False, recursive=False, energy=False):
         """x with A x = b to relative residual rtol; returns (x, info dict).
         plain_start: balanced variant only, start from x0 as given and apply
         the full balanced operator every iteration (otherwise the start is
         coarse-corrected and each iteration needs one coarse solve).
         recursive: stop on the recursive residual of the iteration alone
-        (otherwise it is confirmed on the true residual)."""
+        (otherwise it is confirmed on the true residual).
+        energy: b must be zero; stop when the energy norm of the iterate (the
+        error) falls below rtol (the Sec. 4.1 protocol)."""
         torch = self._torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         inf = SolveInfo()
-        code = METHOD[method] | (SOLVE_PLAIN_START if plain_start else 0) | (SOLVE_RECURSIVE if recursive else 0)
+        code = METHOD[method] | (SOLVE_PLAIN_START if plain_start else 0) | (SOLVE_RECURSIVE if recursive else 0) \
+            | (SOLVE_ENERGY if energy else 0)
         st = lib().sfcdd_solve(self.ctx, self._vec(b, "b"), self._vec(x, "x"), float(rtol), int(max_iter),
                                code, float(xi), ctypes.byref(inf))
         if check:

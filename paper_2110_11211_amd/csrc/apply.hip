@@ -578,6 +578,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
         if (active && upd && r0 <= S[S_TOL2]) active[gi] = (mode == FIN_RR_CAND) ? ACT_CAND : ACT_DONE;
         break;
       case FIN_TRR: S[S_TRR] = r0; break;
+      case FIN_EN: S[S_RR] = -r0; break;
+      case FIN_EN_CAND:
+      case FIN_EN_DONE:
+        S[S_RR] = -r0;
+        if (active && upd && -r0 <= S[S_TOL2]) active[gi] = (mode == FIN_EN_CAND) ? ACT_CAND : ACT_DONE;
+        break;
     }
   }
 }

@@ -193,7 +193,10 @@ enum {
   FIN_BB,             // S_BB = sum
   FIN_RR_CAND,        // S_RR = sum; updating grid with S_RR <= S_TOL2 -> CAND
   FIN_RR_DONE,        // S_RR = sum; updating grid with S_RR <= S_TOL2 -> DONE
-  FIN_TRR             // S_TRR = sum
+  FIN_TRR,            // S_TRR = sum
+  FIN_EN,             // S_RR = -sum (sum = x . r with b = 0: x^T A x)
+  FIN_EN_CAND,        // S_RR = -sum; updating grid with S_RR <= S_TOL2 -> CAND
+  FIN_EN_DONE         // S_RR = -sum; updating grid with S_RR <= S_TOL2 -> DONE
 };
 // Combine modes of launch_combine.
 enum {

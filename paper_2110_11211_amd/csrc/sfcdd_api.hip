@@ -1126,8 +1126,9 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   if (!b_in || !x_io || b_in == x_io) FAIL(c, SFCDD_EINVAL, "b and x must be distinct non-NULL device vectors");
   if (!(rtol > 0.0) || max_iter < 0) FAIL(c, SFCDD_EINVAL, "need rtol > 0 and max_iter >= 0");
   const bool plain = (method & SFCDD_SOLVE_PLAIN_START) != 0;
-  const bool recursive = (method & SFCDD_SOLVE_RECURSIVE) != 0;
-  method &= ~(SFCDD_SOLVE_PLAIN_START | SFCDD_SOLVE_RECURSIVE);
+  const bool energy = (method & SFCDD_SOLVE_ENERGY) != 0;
+  const bool recursive = (method & SFCDD_SOLVE_RECURSIVE) != 0 || energy;
+  method &= ~(SFCDD_SOLVE_PLAIN_START | SFCDD_SOLVE_RECURSIVE | SFCDD_SOLVE_ENERGY);
   if (method != SFCDD_PCG && method != SFCDD_FCG && method != SFCDD_RICHARDSON)
     FAIL(c, SFCDD_EINVAL, "method = %d", method);
   // balanced form: coarse-corrected start, then one coarse solve per iteration
@@ -1164,8 +1165,19 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   std::vector<double> tol2(G), bb(G), rr(G, 0.0);
   for (int g = 0; g < G; ++g) {
     bb[g] = hs(c, g, S_BB);
-    tol2[g] = rtol * rtol * bb[g];
+    if (energy && bb[g] != 0.0) FAIL(c, SFCDD_EINVAL, "SFCDD_SOLVE_ENERGY needs b = 0 (grid %d)", g);
+    tol2[g] = energy ? rtol * rtol : rtol * rtol * bb[g];
   }
+  // the squared norm a grid's stopping test looks at, from the partials of
+  // the residual's r . r just formed: that norm, or (energy test) -(x . r)
+  auto norm_fin = [&](int rr_mode, int en_mode) {
+    if (energy) {
+      launch_dot(B, x, r, nullptr, c->partials, s);
+      launch_finalize(B, en_mode, c->partials, c->scal, en_mode == FIN_EN ? nullptr : c->active, s);
+    } else {
+      launch_finalize(B, rr_mode, c->partials, c->scal, rr_mode == FIN_RR ? nullptr : c->active, s);
+    }
+  };
   std::vector<int32_t> flags(G, ACT_RUN), its(G, 0), stagnated(G, 0);
   // true residual at each grid's previous restart (stagnation test)
   std::vector<double> last_trr(G, std::numeric_limits<double>::infinity());
@@ -1262,7 +1274,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     inf.xi = xig[0];
     // r = b - A x and its norm; damping and tolerances to the device
     spmv(c, 2, x, r, b, c->partials);
-    launch_finalize(B, FIN_RR, c->partials, c->scal, nullptr, s);
+    norm_fin(FIN_RR, FIN_EN);
     if ((st = read_rr())) return st;
     for (int g = 0; g < G; ++g) {
       c->host_scal[(size_t)g * S_COUNT + S_XI] = xig[g];
@@ -1278,7 +1290,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         const std::vector<int32_t> before = flags;
         launch_axpy_scal(B, c->scal, S_XI, c->active, x, z, s);
         spmv(c, 2, x, r, b, c->partials);
-        launch_finalize(B, FIN_RR_DONE, c->partials, c->scal, c->active, s);
+        norm_fin(FIN_RR_DONE, FIN_EN_DONE);
         if ((st = enqueue_readback())) return st;
         ++it;
         if (it < max_iter) precond(r, z);  // next iteration's, speculatively
@@ -1296,7 +1308,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     const int fin_rz = flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT;
     // r = b - A x
     spmv(c, 2, x, r, b, c->partials);
-    launch_finalize(B, FIN_RR, c->partials, c->scal, nullptr, s);
+    norm_fin(FIN_RR, FIN_EN);
     if ((st = read_rr())) return st;
     for (int g = 0; g < G; ++g) {
       c->host_scal[(size_t)g * S_COUNT + S_TOL2] = tol2[g];
@@ -1317,7 +1329,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         spmv(c, 1, p, q, nullptr, c->partials);
         launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s);
         launch_update_xr(B, c->scal, c->active, x, r, p, q, c->partials, s);
-        launch_finalize(B, FIN_RR_CAND, c->partials, c->scal, c->active, s);
+        norm_fin(FIN_RR_CAND, FIN_EN_CAND);
         if ((st = enqueue_readback())) return st;
         ++it;
         if (it < max_iter) {

@@ -88,3 +88,58 @@ def test_weak_scaling_counts_level_off():
             it_o = solvers.pcg(O.A_nat, b, O.apply, rtol=RTOL)[1]
             assert abs(its[p] - it_o) <= 1, (p, it_o, its[p])
     assert max(its.values()) - min(its.values()) <= 1, its
+
+
+def _paper_pin(key):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_d1_iterations.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#") and line.split()[0] == key:
+            return float(line.split()[1])
+    raise KeyError(key)
+
+
+def _paper_solve(p, variant, method, xi=0.0):
+    """GPU run of the Sec. 4.1 protocol: b = 0, x0 with ||x0||_A = 1 (the
+    oracle's start), stop on the energy norm of the error at 1e-8."""
+    g = Grid(npts=[256 * p])
+    x0 = solvers.paper_start(g.matrix().tocsr(), 11, g.N)
+    S = m.SFCSchwarz(npts=[256 * p], P=p, gamma=Fraction(1, 2), q=16, variant=variant, factor_dtype="fp64")
+    _, info = S.solve(dvec(np.zeros(g.N)), x0=dvec(x0), rtol=1e-8, method=method, xi=xi, max_iter=5000,
+                      plain_start=True, energy=True)
+    S.close()
+    return info
+
+
+def test_paper_protocol_d1():
+    """Sec. 4.1 protocol (b = 0, random x0 with ||x0||_A = 1, energy norm of
+    the error to 1e-8; d = 1, N = 256 P, q = 16, gamma = 1/2, omega_i).
+    Balanced PCG: the GPU count equals the oracle's (+-1) at P = 32 and stays
+    within the paper's bound of 29 up to P = 1024.  Richardson with the
+    oracle's damping: balanced and additive counts equal the oracle's (+-1),
+    and additive needs about 6 times as many (the paper's ratio, within 30%)."""
+    P0 = 32
+    g = Grid(npts=[256 * P0])
+    O = OracleSchwarz(g, P0, Fraction(1, 2), q=16)
+    x0 = solvers.paper_start(O.A_nat, 11, g.N)
+    it_o = solvers.pcg(O.A_nat, np.zeros(g.N), O.apply, x0=x0, energy_tol=1e-8)[1]
+    announce("paper protocol pcg", P0)
+    info = _paper_solve(P0, "balanced", "pcg")
+    assert abs(info["iterations"] - it_o) <= 1, (it_o, info["iterations"])
+    assert info["rel_residual"] <= 1e-8
+    for p in (256, 1024):
+        announce("paper protocol pcg", p)
+        assert _paper_solve(p, "balanced", "pcg")["iterations"] <= _paper_pin("pcg_balanced_omega_max")
+    its = {}
+    for variant in ("balanced", "additive"):
+        Ov = OracleSchwarz(g, P0, Fraction(1, 2), q=16, variant=variant)
+        a, bb = solvers.cg_coefficients(Ov.A_nat, uniform_pm1(99, g.N), Ov.apply, 150)
+        xi, _ = solvers.optimal_damping(*solvers.lanczos_extremes(a, bb))
+        it_r = solvers.richardson(Ov.A_nat, np.zeros(g.N), Ov.apply, xi, x0=x0, energy_tol=1e-8)[1]
+        announce("paper protocol richardson", variant)
+        got = _paper_solve(P0, variant, "richardson", xi=xi)["iterations"]
+        assert abs(got - it_r) <= 1, (variant, it_r, got)
+        its[variant] = got
+    ratio = its["additive"] / its["balanced"]
+    pin = _paper_pin("ratio_richardson_weighted")
+    assert 0.7 * pin <= ratio <= 1.3 * pin, its
