@@ -465,3 +465,21 @@ def test_coarse_factor_precision_choice():
     S = m.SFCSchwarz(levels=(14, 1), P=128, gamma=Fraction(1, 4), factor_dtype="fp32")
     assert S.info()["coarse_fp32"] == 0
     S.close()
+
+
+def test_largest_subdomain_single_piece_is_exact():
+    """P = 1 at the largest subdomain the library takes (the (6, 7) grid:
+    8001 points, 126 tiles): C^{-1} = A^{-1} exactly (the one subdomain is the
+    whole grid), against the exact DST-I solve; PCG then converges in one
+    iteration."""
+    levels = (6, 7)
+    announce("largest subdomain", levels)
+    g = Grid(levels=levels)
+    S = _solver(levels, 1, Fraction(1, 2), factor_dtype="fp64")
+    assert S.info()["max_Ni"] == g.N == 8001
+    r = uniform_pm1(41, g.N)
+    assert relerr(host(S.apply(dvec(r))), exact.solve(g, r)) <= 1e-9
+    x, info = S.solve(dvec(r), rtol=1e-8, method="pcg", plain_start=True, recursive=True)
+    assert info["iterations"] <= 1
+    assert relerr(host(x), exact.solve(g, r)) <= 1e-8
+    S.close()

@@ -101,11 +101,18 @@ def test_partition_host_1d_npts():
     (dict(levels=(3, 3), P=4, gamma=Fraction(-1, 2)), m.EINVAL),
     (dict(levels=(3, 3), P=4, q=20), m.EINVAL), (dict(levels=(11,) * 6, P=4), m.EOVERFLOW),
     (dict(levels=(16, 16), P=4), m.EOVERFLOW), (dict(levels=(0, 3), P=4), m.EINVAL),
-    (dict(levels=(3, 3), P=4, coeff=(1.0, -1.0)), m.EINVAL)])
+    (dict(levels=(3, 3), P=4, coeff=(1.0, -1.0)), m.EINVAL),
+    (dict(npts=[8193], P=1), m.EINVAL),                          # a subdomain above 8192 points
+    (dict(npts=[1 << 18], P=2048, q=128), m.EINVAL)])            # coarse size qP above 131072
 def test_invalid_parameters(kw, code):
     with pytest.raises(m.SfcddError) as e:
         m.workspace_size(**kw)
     assert e.value.status == code
+
+
+def test_size_limits_accepted_at_the_bound():
+    assert m.workspace_size(npts=[8192], P=1) > 8192 * 8192 * 4
+    assert m.workspace_size(npts=[1 << 18], P=2048, q=64) > 0   # qP = 131072
 
 
 def test_workspace_grows_with_factor_precision():
