@@ -206,7 +206,7 @@ def ct_batch_report(steps, warmup):
     from seeded_inputs import workloads
     w = workloads()["c4"]
     b32, it32, x32, waves, offs = run_batch(w, "fp32", steps, warmup)
-    b64, it64, x64, _, _ = run_batch(w, "fp64", max(1, steps // 2), warmup)
+    b64, it64, x64, _, _ = run_batch(w, "fp64", steps, warmup)
     s32, _, _, _, _ = run_batch(w, "fp32", 1, 1, sequential=True)
     rep = {"workload": w.name, "grids": len(w.levels), "N_total": int(offs[-1]),
            "batched_fp32_ms": round(b32, 3), "batched_fp64_ms": round(b64, 3),
