@@ -261,3 +261,26 @@ def test_adjoint_gradient_matches_finite_differences(levels, coeff):
         fd = (grad.objective(Grid(levels=levels, coeff=a_p), f)
               - grad.objective(Grid(levels=levels, coeff=a_m), f)) / (2 * h)
         assert abs(fd - ga[j]) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("levels,P,gamma,q", [((5, 4), 6, Fraction(1, 2), 0), ((4, 3, 3), 9, Fraction(1, 4), 2),
+                                              ((7,), 5, Fraction(1, 3), 3), ((3, 5), 7, Fraction(1), 0)])
+def test_coarse_matrix_is_m_matrix_within_condition_bound(levels, P, gamma, q):
+    """The facts the FP32 coarse path rests on: A_0 = R_0 A R_0^T is an
+    M-matrix (non-positive off-diagonal entries), so L_0^{-1} is entrywise
+    non-negative; and kappa(A_0) <= kappa(A) b_max / b_min (Rayleigh quotients
+    with R_0 R_0^T = diag(block sizes)), kappa(A) from the stencil's extreme
+    sine eigenvalues."""
+    g = Grid(levels=levels)
+    S = OracleSchwarz(g, P, gamma, q=q or None, factor=False)
+    A0 = S.A0
+    off = A0 - np.diag(np.diag(A0))
+    assert off.max() <= 0.0
+    L0 = np.linalg.cholesky(A0)
+    X0 = np.linalg.inv(L0)
+    assert X0.min() >= -1e-12 * np.abs(X0).max()
+    ev = np.linalg.eigvalsh(A0)
+    lam = np.linalg.eigvalsh(g.matrix().toarray())
+    bsz = np.asarray(S.R0.sum(axis=1)).ravel()
+    assert bsz.min() >= 1
+    assert ev[-1] / ev[0] <= (lam[-1] / lam[0]) * bsz.max() / bsz.min() * (1 + 1e-12)
