@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import dataclasses
+import gc
 import json
 import os
 import sys
@@ -375,7 +376,10 @@ def oracle_checks(w, x_head, ct_raw, adj_raw):
 
 
 def progress(what):
+    """Progress line after a section; also collects cyclic garbage there,
+    between the timed regions (automatic collection is paused)."""
     print(f"bench: {what} done", file=sys.stderr, flush=True)
+    gc.collect()
 
 
 def main():
@@ -389,6 +393,13 @@ def main():
     import paper_2110_11211_amd as m
     from seeded_inputs import workloads
     m.lib()
+    # Python's cyclic garbage collector is paused while the GPU paths are
+    # timed: a full collection (tens of milliseconds with torch loaded) would
+    # otherwise land inside some steps.  Reference counting still frees
+    # everything the steps drop; the collector runs again for the CPU leg.
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     w = workloads()["c2"]
     f_dev = torch.tensor(w.rhs(), dtype=torch.float64, device="cuda:0")
     ws_cache = {}
@@ -521,6 +532,7 @@ def main():
         for d, L in CT_RUNS:
             out["combination"].append(ct_solve_report(d, L, max(2, args.steps // 2), 1))
             progress(f"combination d={d} L={L}")
+    gc.enable()
     if not args.no_cpu_baseline:
         # the oracle leg: CPU timing of the oracle, then the accuracy checks
         iters = f64["iterations"] if f64 is not None else head["iterations"]

@@ -61,7 +61,8 @@ struct sfcdd_ctx {
   int max_cblock = 1;  // largest coarse block (points) of any grid
   bool coarse32 = false;  // FP32 coarse Cholesky factor (see coarse_fp32_ok)
   hipStream_t stream = nullptr;
-  hipStream_t side = nullptr;  // internal, default priority: coarse setup overlaps the fine factorisation
+  hipStream_t side = nullptr;  // internal per-device stream (default priority): the coarse setup
+                               // overlaps the fine factorisation; shared by the contexts of a device
   // per-subdomain (batch-global) host tables
   std::vector<int32_t> ta, Ni, nt;
   std::vector<int64_t> off, doff, xoff, poff;
@@ -834,6 +835,27 @@ void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b
 }
 
 // Device setup of a planned context (Alg. 1).
+// The internal side stream of the current device, created on first use and
+// kept for the life of the process: creating and destroying a stream per
+// context now and then stalled a setup by tens of milliseconds.  Contexts of
+// one device share it; their coarse setups then run one after the other on
+// it (each joins the caller's stream before setup returns).
+sfcdd_status device_side_stream(sfcdd_ctx* c, hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t st = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    it = streams.emplace(dev, st).first;
+  }
+  *out = it->second;
+  return SFCDD_OK;
+}
+
 sfcdd_status setup_device(sfcdd_ctx* c) {
   const hipStream_t s = c->stream;
   const int G = c->G;
@@ -901,7 +923,10 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   HIPCHK(c, hipEventCreateWithFlags(&join, hipEventDisableTiming));
   HIPCHK(c, hipEventCreate(&cev0));
   HIPCHK(c, hipEventCreate(&cev1));
-  if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  if (!c->side) {
+    const sfcdd_status st = device_side_stream(c, &c->side);
+    if (st != SFCDD_OK) return st;
+  }
   HIPCHK(c, hipEventRecord(fork, s));
   HIPCHK(c, hipStreamWaitEvent(c->side, fork, 0));
   {
@@ -1639,7 +1664,7 @@ sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   if (c->ev_rb) (void)hipEventDestroy(c->ev_rb);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
-  if (c->side) (void)hipStreamDestroy(c->side);
+
   delete c;
   return SFCDD_OK;
 }
