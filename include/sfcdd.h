@@ -18,9 +18,12 @@
  *    compute calls are caller-owned device buffers of N doubles.  The context
  *    owns only host memory.
  *  - Streams.  All device work is enqueued on the HIP stream given to
- *    sfcdd_setup (NULL = the default stream).  sfcdd_apply_precond and
- *    sfcdd_matvec are asynchronous; sfcdd_setup and sfcdd_solve return after
- *    their work is complete (they synchronise the stream).
+ *    sfcdd_setup (NULL = the default stream), except that sfcdd_setup runs
+ *    the coarse setup on an internal stream of the device (created on first
+ *    use, shared by all contexts of the device, default priority) and joins
+ *    it before returning.  sfcdd_apply_precond and sfcdd_matvec are
+ *    asynchronous; sfcdd_setup and sfcdd_solve return after their work is
+ *    complete (they synchronise the stream).
  *  - Vector order.  Vectors are in natural order (first coordinate fastest,
  *    point k -> sum_j (k_j - 1) prod_{i<j} n_i) unless params.layout = 1, in
  *    which case they are in curve order (entry p = point sfc_index[p]).
