@@ -483,3 +483,34 @@ def test_largest_subdomain_single_piece_is_exact():
     assert info["iterations"] <= 1
     assert relerr(host(x), exact.solve(g, r)) <= 1e-8
     S.close()
+
+
+def test_concurrent_setups_on_two_streams():
+    """Two host threads set up and solve on their own streams at the same
+    time; their coarse setups share the device's internal stream (one after
+    the other) and both solutions are right."""
+    import threading
+    announce("concurrent setups")
+    cases = [((5, 4), 6, 51), ((4, 3, 3), 9, 52)]
+    out = {}
+
+    def work(levels, P, seed):
+        g = Grid(levels=levels)
+        f0 = uniform_pm1(seed, g.N)
+        st = torch.cuda.Stream(device=DEV)
+        with torch.cuda.stream(st):
+            b = torch.tensor(f0, dtype=torch.float64, device=DEV)
+            for _ in range(3):
+                S = _solver(levels, P, Fraction(1, 2), factor_dtype="fp32")
+                x, _ = S.solve(b, rtol=1e-12, method="fcg")
+                S.close()
+            st.synchronize()
+            out[levels] = relerr(host(x), exact.solve(g, f0))
+
+    ts = [threading.Thread(target=work, args=c) for c in cases]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert all(not t.is_alive() for t in ts)
+    assert len(out) == 2 and all(e <= 1e-9 for e in out.values()), out
