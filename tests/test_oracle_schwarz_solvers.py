@@ -284,3 +284,80 @@ def test_coarse_matrix_is_m_matrix_within_condition_bound(levels, P, gamma, q):
     bsz = np.asarray(S.R0.sum(axis=1)).ravel()
     assert bsz.min() >= 1
     assert ev[-1] / ev[0] <= (lam[-1] / lam[0]) * bsz.max() / bsz.min() * (1 + 1e-12)
+
+
+def _recorded_cg(A, b, M, flexible, x0=None, rtol=1e-12, maxit=400):
+    """Runs the oracle's PCG with M wrapped so that every (r, z) pair it
+    applies is kept; the search directions are rebuilt from the z's and the
+    returned beta's (p_0 = z_0, p_k = z_k + beta_{k-1} p_{k-1})."""
+    seen = []
+
+    def Mrec(r):
+        z = M(r)
+        seen.append((r.copy(), z.copy()))
+        return z
+
+    x, it, info = solvers.pcg(A, b, Mrec, x0=x0, rtol=rtol, maxit=maxit, flexible=flexible)
+    ps = [seen[0][1]]
+    for k, beta in enumerate(info["betas"]):
+        ps.append(seen[k + 1][1] + beta * ps[-1])
+    return x, it, seen, ps
+
+
+def _local_a_orthogonality(A, seen, ps):
+    """Largest |p_{k+1}^T A p_k| / (||p_{k+1}||_A ||p_k||_A) and largest
+    |p_k^T r_{k+1}| / (||p_k|| ||r_{k+1}||) over the run."""
+    worst_ap, worst_pr = 0.0, 0.0
+    for k in range(len(ps) - 1):
+        Ap = A @ ps[k]
+        nk = np.sqrt(float(ps[k] @ Ap))
+        nk1 = np.sqrt(float(ps[k + 1] @ (A @ ps[k + 1])))
+        worst_ap = max(worst_ap, abs(float(ps[k + 1] @ Ap)) / (nk * nk1))
+        r1 = seen[k + 1][0]
+        worst_pr = max(worst_pr, abs(float(ps[k] @ r1)) / (np.linalg.norm(ps[k]) * np.linalg.norm(r1)))
+    return worst_ap, worst_pr
+
+
+def test_flexible_cg_keeps_consecutive_directions_a_orthogonal():
+    """Flexible CG (Sec. 3.3, the remedy for a non-symmetric preconditioner):
+    with beta = z_{k+1}^T (r_{k+1} - r_k) / z_k^T r_k every new direction is
+    A-orthogonal to the previous one and every residual is orthogonal to the
+    last direction, for any preconditioner.  With the D_i weights at
+    gamma = 1/4 (non-symmetric) the flexible branch keeps both to rounding,
+    the standard beta does not, and the flexible iteration reaches the exact
+    DST-I solution."""
+    levels, P, gamma = (5, 4, 3), 12, Fraction(1, 4)
+    g = Grid(levels=levels)
+    S = OracleSchwarz(g, P, gamma, weighting="D", variant="balanced")
+    f = uniform_pm1(10, g.N)
+    xs = exact.solve(g, f)
+    x, it, seen, ps = _recorded_cg(S.A_nat, f, S.apply, flexible=True)
+    ap, pr = _local_a_orthogonality(S.A_nat, seen, ps)
+    assert ap <= 1e-9 and pr <= 1e-9, (ap, pr)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+    _, _, seen_s, ps_s = _recorded_cg(S.A_nat, f, S.apply, flexible=False, maxit=15)
+    ap_s, _ = _local_a_orthogonality(S.A_nat, seen_s, ps_s)
+    assert ap_s >= 1e-6, ap_s
+
+
+def test_flexible_cg_equals_pcg_for_a_symmetric_preconditioner():
+    """With a fixed symmetric positive definite preconditioner z_{k+1}^T r_k = 0,
+    so the flexible beta equals the standard one: same iteration count and the
+    same iterate (the d = 2 workload, balanced omega-weighted form, and a d = 3
+    grid from the balancing start)."""
+    w = workloads()["c1"]
+    g = Grid(levels=w.levels[0])
+    S = OracleSchwarz(g, w.P, w.gamma)
+    f = w.rhs()
+    x_p, it_p, _ = solvers.pcg(S.A_nat, f, S.apply, rtol=1e-10)
+    x_f, it_f, _ = solvers.pcg(S.A_nat, f, S.apply, rtol=1e-10, flexible=True)
+    assert it_p == it_f
+    assert np.linalg.norm(x_p - x_f) <= 1e-10 * np.linalg.norm(x_p)
+    g3 = Grid(levels=(4, 3, 3))
+    S3 = OracleSchwarz(g3, 10, Fraction(1, 2))
+    f3 = uniform_pm1(4, g3.N)
+    x0 = S3.balancing_start(f3)
+    x_p, it_p, _ = solvers.pcg(S3.A_nat, f3, S3.apply, x0=x0, rtol=1e-10)
+    x_f, it_f, _ = solvers.pcg(S3.A_nat, f3, S3.apply, x0=x0, rtol=1e-10, flexible=True)
+    assert it_p == it_f
+    assert np.linalg.norm(x_p - x_f) <= 1e-10 * np.linalg.norm(x_p)

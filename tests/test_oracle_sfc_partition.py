@@ -208,3 +208,83 @@ def test_hilbert_grid_keys_unique_and_1d_identity():
     g1 = Grid(levels=(6,))
     sfc_index, _ = sfc_order(g1, "hilbert")
     assert np.array_equal(sfc_index, np.arange(g1.N))
+
+
+def _order_within(keys: np.ndarray) -> np.ndarray:
+    return np.argsort(keys, kind="stable")
+
+
+@pytest.mark.parametrize("levels", [(4, 4), (3, 3, 3), (2, 2, 2, 2), (3, 2, 4), (2, 4, 3), (1, 3), (4, 1, 2)])
+def test_hilbert_keys_follow_the_cube_curve(levels):
+    """hilbert_keys itself on a grid: its order of the interior points equals
+    the order that the property-checked cube curve (bijective, face-continuous,
+    nested; test above) gives to the same points at their scaled coordinates
+    C_j = k_j 2^(nres - l_j), nres = max l_j.  A wrong interleave, bit order or
+    scaling in hilbert_keys changes this order."""
+    g = Grid(levels=levels)
+    nres = max(levels)
+    pts, cube_keys = _hilbert_cube_order(g.d, nres)
+    side = 1 << nres
+    lin = np.zeros(pts.shape[1], dtype=np.int64)
+    for j in range(g.d):
+        lin = lin * side + pts[j]
+    lookup = np.empty(side ** g.d, dtype=np.uint64)
+    lookup[lin] = cube_keys
+    C = g.coords().astype(np.int64) << np.array([nres - l for l in levels], dtype=np.int64)[None, :]
+    lin_g = np.zeros(g.N, dtype=np.int64)
+    for j in range(g.d):
+        lin_g = lin_g * side + C[:, j]
+    want = _order_within(lookup[lin_g])
+    got = _order_within(hilbert_keys(g))
+    assert np.array_equal(got, want)
+
+
+def _classic_hilbert_2d(x: np.ndarray, y: np.ndarray, b: int) -> np.ndarray:
+    """Index along the classic two-dimensional Hilbert curve of side 2^b
+    (the quadrant-by-quadrant construction with a rotation/reflection of the
+    remaining low bits after each level), vectorised: at level s the quadrant
+    digit is 3 rx XOR ry, and the low bits are reflected when (rx, ry) = (1, 0)
+    and transposed whenever ry = 0."""
+    x = x.astype(np.int64).copy()
+    y = y.astype(np.int64).copy()
+    n = 1 << b
+    out = np.zeros_like(x)
+    s = n >> 1
+    while s > 0:
+        rx = (x & s) > 0
+        ry = (y & s) > 0
+        out += s * s * ((3 * rx.astype(np.int64)) ^ ry.astype(np.int64))
+        flip = (~ry) & rx
+        x = np.where(flip, n - 1 - x, x)
+        y = np.where(flip, n - 1 - y, y)
+        x, y = np.where(~ry, y, x), np.where(~ry, x, y)
+        s >>= 1
+    return out
+
+
+def test_hilbert_keys_two_dimensional_are_the_classic_curve():
+    """An independent construction: on the 2^b x 2^b grids (b = 2..6) the
+    order hilbert_keys gives the interior points is the order of the classic
+    two-dimensional Hilbert curve composed with one fixed symmetry of the
+    square (the same symmetry at every b)."""
+    found = None
+    for b in range(6, 1, -1):
+        g = Grid(levels=(b, b))
+        K = g.coords().astype(np.int64)
+        got = _order_within(hilbert_keys(g))
+        n = (1 << b) - 1
+        ok = []
+        for swap in (False, True):
+            for fx in (False, True):
+                for fy in (False, True):
+                    u = n - K[:, 0] if fx else K[:, 0]
+                    v = n - K[:, 1] if fy else K[:, 1]
+                    if swap:
+                        u, v = v, u
+                    if np.array_equal(got, _order_within(_classic_hilbert_2d(u, v, b))):
+                        ok.append((swap, fx, fy))
+        assert ok, b
+        if found is None:
+            assert len(ok) == 1
+            found = ok[0]
+        assert found in ok, (b, ok)
