@@ -34,6 +34,9 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
 # (d, L) of the combination-technique runs (Sec. 4.3 setting, L <= 17 - d)
 CT_RUNS = [(2, 14), (4, 12), (6, 10)]
+# relative residual that brings the headline solve's error against the exact
+# solution below 1e-9 (error / residual is about 1.9 on that grid)
+RTOL_ERROR_1E9 = 5e-10
 
 
 def parse():
@@ -43,7 +46,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--local", default="cholesky", choices=["cholesky", "inverse"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="subdomains in the CPU oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="PCG iterations in the CPU oracle sample")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="run the CPU oracle's PCG to the tolerance instead of a sample of iterations")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="run only the CPU oracle leg (needs no GPU) and print its JSON")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the headline path only (for rocprofv3)")
@@ -52,10 +59,12 @@ def parse():
                          "(the reference kernel that scales the HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 84-grid layer")
     ap.add_argument("--no-sweep", action="store_true", help="skip the overlap (gamma) sweep")
+    ap.add_argument("--no-large", action="store_true", help="skip the large single grid (8.26 M unknowns)")
     return ap.parse_args()
 
 
-def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, curve="hilbert"):
+def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, curve="hilbert",
+             coarse_precision="auto", rtol=None, max_iter=500):
     """Times `steps` full setup+solve passes (after `warmup` untimed ones);
     then, when prof_steps > 0, that many more passes with the library's
     per-kernel HIP events on (they add about 3% to a solve, so the step times
@@ -63,7 +72,8 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
     import torch
     import paper_2110_11211_amd as m
     kw = dict(levels=list(w.levels[0]), P=w.P, gamma=w.gamma, factor_dtype=fdtype, local_solver=local,
-              curve=curve)
+              curve=curve, coarse_precision=coarse_precision)
+    rtol = w.rtol if rtol is None else rtol
     nbytes = m.workspace_size(**kw)
     key = (fdtype, local)
     if key not in ws_cache or ws_cache[key].numel() < nbytes + 256:
@@ -92,7 +102,7 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
         e1.record()
         if prof:
             S.set_profiling(True)
-        x, info = S.solve(f_dev, rtol=w.rtol, max_iter=500, method=method)
+        x, info = S.solve(f_dev, rtol=rtol, max_iter=max_iter, method=method)
         e2.record()
         torch.cuda.synchronize()
         if timed:
@@ -112,6 +122,40 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
             "solve_ms": sorted(solves)[len(solves) // 2], "iterations": iters[-1], "info": sinfo,
             "kernels": ktimes, "prof_steps": prof_steps, "prof_full_launches": sum(piters), "x": x,
             "rel_residual": info["rel_residual"], "restarts": info["restarts"]}
+
+
+def kernel_rates(res, w, local):
+    """Average launch time and algorithmic GB/s of the substitution kernel and
+    of the SpMV from a run with the library's per-kernel events on."""
+    info = res["info"]
+    d = len(w.levels[0])
+    if local == "cholesky":
+        local_bytes = 2 * info["factor_algo_bytes"] + 16 * info["sum_Ni"]   # two sweeps over the triangle
+    else:
+        local_bytes = info["factor_algo_bytes"] + 16 * info["sum_Ni"]       # one pass over the inverse
+    ms_local, n_local = res["kernels"]["local_solve"]
+    # launches that did work: one per iteration (the application enqueued
+    # after the converging step skips every subdomain and its few
+    # microseconds stay in the numerator)
+    avg_local = ms_local / max(min(n_local, res["prof_full_launches"]), 1)
+    ms_spmv, n_spmv = res["kernels"]["spmv"]
+    avg_spmv = ms_spmv / max(n_spmv, 1)
+    spmv_bytes = (16 + 8 * d) * info["N"]
+    return {"local_bytes": local_bytes, "avg_local_ms": avg_local,
+            "local_gbps": local_bytes / (avg_local * 1e-3) / 1e9,
+            "spmv_bytes": spmv_bytes, "avg_spmv_ms": avg_spmv,
+            "spmv_gbps": spmv_bytes / (avg_spmv * 1e-3) / 1e9}
+
+
+def dtype_label(info):
+    """The arithmetic of a run, from the context's precision choices."""
+    if info["coarse_inv_fp32"]:
+        coarse = "f32 coarse factor and inverse" if info["coarse_fp32"] else \
+            "f64 coarse factor rounded to f32, f32 coarse inverse"
+    else:
+        coarse = "f64 coarse factor and inverse"
+    return (f"f32 subdomain factors and solves (MFMA, f32 accumulate), {coarse} (f64 coarse matrix "
+            f"and sums), f64 outer flexible CG, dots and residuals")
 
 
 def hbm_read_probe():
@@ -299,54 +343,75 @@ def adjoint_report(steps, warmup):
     return rep, {"w": w, "f0": f0, "gf": f.grad.detach().cpu().numpy(), "ga": a.grad.detach().numpy()}
 
 
-def cpu_baseline(w, iterations, nsample):
-    """The oracle (plain FP64 NumPy/SciPy, untuned) on a bounded sample of the
-    same workload, extrapolated to one full setup + solve."""
+def cpu_model():
+    """CPU model name of this host (first /proc/cpuinfo entry), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, gpu_iterations, sample_iters, full=False):
+    """The oracle as it stands (plain FP64 NumPy/SciPy, untuned) on the headline
+    workload, in two legs: BLAS/LAPACK on every thread the library uses here,
+    and on one thread (threadpoolctl).  Each leg times the oracle's whole setup
+    (curve order, partition, A and A_0, all P local Cholesky factorisations and
+    the coarse one) and its balanced PCG from the balancing start.  By default
+    the PCG runs `sample_iters` iterations (the bounded sample) and the leg's
+    value is setup + start + gpu_iterations x the measured time per iteration;
+    with full=True it runs to the workload's tolerance and the value is the
+    measured total."""
     import numpy as np
-    import scipy.linalg as sla
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.grid import Grid
     from oracle.schwarz import OracleSchwarz
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    from oracle import solvers
     g = Grid(levels=w.levels[0])
-    t = time.perf_counter()
-    O = OracleSchwarz(g, w.P, w.gamma, factor=False)       # index work, A, A_0 (full)
-    t_index = time.perf_counter() - t
-    t = time.perf_counter()
-    coarse = sla.cho_factor(O.A0, lower=True)                # full coarse factorisation
-    t_coarse = time.perf_counter() - t
-    idx = np.linspace(0, w.P - 1, nsample).astype(int)
-    t = time.perf_counter()
-    facs = {i: sla.cho_factor(O.local_matrix(i), lower=True) for i in idx}
-    t_fac = (time.perf_counter() - t) / nsample
     f = w.rhs()
-    gs = O.to_s(f)
-    t = time.perf_counter()
-    for i in idx:
-        sla.cho_solve(facs[i], gs[O.orders[i]])
-    t_loc = (time.perf_counter() - t) / nsample
-    t = time.perf_counter()
-    for _ in range(4):
-        sla.cho_solve(coarse, O.R0 @ gs)
-    t_csolve = (time.perf_counter() - t) / 4
-    t = time.perf_counter()
-    for _ in range(6):
-        O.A @ gs
-    t_spmv = (time.perf_counter() - t) / 6
-    setup = t_index + t_coarse + w.P * t_fac
-    per_iter = w.P * t_loc + 2 * t_csolve + 3 * t_spmv
-    total_ms = 1e3 * (setup + iterations * per_iter)
-    return {"value": total_ms, "unit": "ms", "cores": int(cores), "kind": "oracle",
-            "sample": f"{nsample} of {w.P} local Cholesky factorisations and solves timed and scaled by "
-                      f"{w.P}; index work, coarse factorisation, coarse solves and SpMV timed in full; "
-                      f"{iterations} balanced-PCG iterations (the GPU FP64 count)",
-            "setup_s": setup, "per_iteration_s": per_iter}
+    legs = {}
+    for name, limit in (("all_threads", None), ("one_thread", 1)):
+        with threadpool_limits(limits=limit):
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+            t = time.perf_counter()
+            O = OracleSchwarz(g, w.P, w.gamma, curve="hilbert")
+            t_setup = time.perf_counter() - t
+            print(f"bench: CPU oracle {name}: setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+            t = time.perf_counter()
+            x0 = O.balancing_start(f)
+            t_start = time.perf_counter() - t
+            t = time.perf_counter()
+            x, its, pinfo = solvers.pcg(O.A_nat, f, O.apply, x0=x0, rtol=w.rtol,
+                                        maxit=1000 if full else sample_iters)
+            t_iter = time.perf_counter() - t
+        per_iter = t_iter / max(its, 1)
+        converged = not pinfo.get("not_converged", False)
+        if full:
+            total = t_setup + t_start + t_iter
+        else:
+            total = t_setup + t_start + gpu_iterations * per_iter
+        legs[name] = {"value": round(1e3 * total, 1), "unit": "ms", "threads": int(threads),
+                      "setup_s": round(t_setup, 3), "start_s": round(t_start, 4),
+                      "per_iteration_s": round(per_iter, 4), "iterations_run": int(its),
+                      "converged": bool(converged and full),
+                      "rel_residual": float(np.linalg.norm(f - O.A_nat @ x) / np.linalg.norm(f)) if full else None}
+        del O
+    allt = legs["all_threads"]
+    if full:
+        sample = (f"full run: the oracle's setup and its balanced PCG to rtol {w.rtol:g} "
+                  f"({allt['iterations_run']} iterations; GPU {gpu_iterations})")
+    else:
+        sample = (f"the oracle's full setup (all {w.P} local factorisations, coarse matrix and factor) timed "
+                  f"in full, then {sample_iters} iterations of its balanced PCG timed and scaled to the "
+                  f"GPU's {gpu_iterations} iterations")
+    return {"value": allt["value"], "unit": "ms", "cores": allt["threads"], "kind": "oracle",
+            "sample": sample, "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model(), "legs": legs}
 
 
-def oracle_checks(w, x_head, ct_raw, adj_raw):
+def oracle_checks(w, x_head, ct_raw, adj_raw, extra=None, big=None):
     """Part of the CPU-baseline leg: errors of the GPU results against the
     oracle's exact DST-I solutions and adjoint gradients."""
     import numpy as np
@@ -355,6 +420,12 @@ def oracle_checks(w, x_head, ct_raw, adj_raw):
     out = {}
     xs = exact.solve(Grid(levels=w.levels[0]), w.rhs())
     out["headline_rel_error_vs_exact"] = float(np.linalg.norm(x_head - xs) / np.linalg.norm(xs))
+    for k, xv in (extra or {}).items():
+        out[k + "_rel_error_vs_exact"] = float(np.linalg.norm(xv - xs) / np.linalg.norm(xs))
+    if big is not None:
+        wl, xl = big
+        xe = exact.solve(Grid(levels=wl.levels[0]), wl.rhs())
+        out["large_grid_rel_error_vs_exact"] = float(np.linalg.norm(xl - xe) / np.linalg.norm(xe))
     if ct_raw is not None:
         wc, offs = ct_raw["w"], ct_raw["offs"]
         e32 = e64 = 0.0
@@ -388,6 +459,11 @@ def main():
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} was asked for): the solver has no "
               f"multi-GPU path; its sharding across GPUs is described, not implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_only:
+        from seeded_inputs import workloads
+        w = workloads()["c2"]
+        print(json.dumps({"cpu_baseline": cpu_baseline(w, 30, args.cpu_sample, full=args.cpu_full)}), flush=True)
+        return
     import numpy as np
     import torch
     import paper_2110_11211_amd as m
@@ -440,30 +516,38 @@ def main():
     if not args.skip_fp64:
         f64 = run_path(w, f_dev, "fp64", args.local, max(2, args.steps // 2), args.warmup, ws_cache, prof_steps=1)
         progress("FP64 path")
+    # FP32 subdomain factors beside an all-FP64 coarse operator
+    c64 = run_path(w, f_dev, "fp32", args.local, max(2, args.steps // 2), args.warmup, ws_cache,
+                   coarse_precision="fp64")
+    progress("FP64-coarse path")
+    # the headline run to an error of 1e-9 against the exact solution rather
+    # than a residual of 1e-9 (on this grid the error is about twice the
+    # relative residual)
+    e9 = run_path(w, f_dev, "fp32", args.local, max(2, args.steps // 2), args.warmup, ws_cache,
+                  rtol=RTOL_ERROR_1E9)
+    progress("error-1e-9 path")
     ws_cache.clear()
+    # the large single grid: 8.26 M unknowns, 4096 subdomains of ~2521 points
+    big = None
+    if not args.no_large:
+        wl = workloads()["c5"]
+        fl_dev = torch.tensor(wl.rhs(), dtype=torch.float64, device="cuda:0")
+        big = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1)
+        big["x"] = big["x"].cpu().numpy()
+        del fl_dev
+        ws_cache.clear()
+        torch.cuda.empty_cache()
+        progress("large grid")
 
     xh = head["x"].cpu().numpy()
 
     info = head["info"]
-    es = 4
     sumN = info["sum_Ni"]
     N = info["N"]
-    d = len(w.levels[0])
-    if args.local == "cholesky":
-        local_bytes = 2 * info["factor_algo_bytes"] + 16 * sumN     # two sweeps over the triangle
-    else:
-        local_bytes = info["factor_algo_bytes"] + 16 * sumN         # one pass over the inverse
-    ms_local, n_local = head["kernels"]["local_solve"]
-    # launches that did work: one per iteration (the initial application plus
-    # one per step; the application enqueued after the converging step skips
-    # every subdomain and its few microseconds stay in the numerator)
-    n_full = head["prof_full_launches"]
-    avg_local = ms_local / max(min(n_local, n_full), 1)
-    ms_spmv, n_spmv = head["kernels"]["spmv"]
-    avg_spmv = ms_spmv / max(n_spmv, 1)
-    spmv_bytes = (16 + 8 * d) * N
-    gbs_local = local_bytes / (avg_local * 1e-3) / 1e9
-    gbs_spmv = spmv_bytes / (avg_spmv * 1e-3) / 1e9
+    kr = kernel_rates(head, w, args.local)
+    local_bytes, avg_local, gbs_local = kr["local_bytes"], kr["avg_local_ms"], kr["local_gbps"]
+    avg_spmv, gbs_spmv = kr["avg_spmv_ms"], kr["spmv_gbps"]
+    ms_local = head["kernels"]["local_solve"][0]
     # the dominant kernel class over a whole step
     solve_local_ms = ms_local / psteps
     factor_ms = info["setup_ms"][3]
@@ -481,7 +565,7 @@ def main():
         "metric": "time-to-1e-9 solve & GB/s of SpMV+Schwarz: FP32-precond vs FP64, 1 GPU",
         "value": round(head["ms"], 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(head["ms"], 3), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 local factors/solves, f64 outer", "data": "synthetic",
+        "vs_baseline": None, "dtype": dtype_label(info), "data": "synthetic",
         "config": {"workload": w.name, "levels": list(w.levels[0]), "N": N, "P": w.P, "curve": "hilbert",
                    "gamma": str(w.gamma), "q": info["q"], "N0": info["N0"], "rtol": w.rtol,
                    "variant": "balanced", "weighting": "omega", "local_solver": args.local,
@@ -491,7 +575,10 @@ def main():
                      "restarts": head["restarts"], "rel_residual": head["rel_residual"],
                      "rel_error_vs_exact": None, "setup_phases_ms": info["setup_ms"]},
         "gbps": {"schwarz_local_solve": round(gbs_local, 1), "spmv": round(gbs_spmv, 1),
-                 "local_solve_avg_ms": avg_local, "spmv_avg_ms": avg_spmv},
+                 "local_solve_avg_ms": avg_local, "spmv_avg_ms": avg_spmv,
+                 "spmv_note": "the SpMV's 9.9 MB working set stays in the caches at this size and a launch "
+                              "lasts a few microseconds (latency-bound); its HBM roofline is measured on the "
+                              "large grid (large_grid.roofline_spmv)"},
         "kernel_ms_per_step": {k: round(v[0] / psteps, 3) for k, v in head["kernels"].items()},
         "kernel_launches_per_step": {k: v[1] // psteps for k, v in head["kernels"].items()},
         "roofline": roofline,
@@ -505,6 +592,35 @@ def main():
                        "local_solve_gbps": round(b64 / (ms64 / max(n64, 1) * 1e-3) / 1e9, 1),
                        "setup_phases_ms": i64["setup_ms"]}
         out["speedup_fp32_vs_fp64"] = round(f64["ms"] / head["ms"], 3)
+    out["fp64_coarse"] = {"ms": round(c64["ms"], 3), "setup_ms": round(c64["setup_ms"], 3),
+                          "solve_ms": round(c64["solve_ms"], 3), "iterations": c64["iterations"],
+                          "dtype": dtype_label(c64["info"]), "rel_error_vs_exact": None,
+                          "note": "headline workload with the coarse factor, inverse and solves in FP64"}
+    out["to_error_1e-9"] = {"ms": round(e9["ms"], 3), "setup_ms": round(e9["setup_ms"], 3),
+                            "solve_ms": round(e9["solve_ms"], 3), "iterations": e9["iterations"],
+                            "rtol": RTOL_ERROR_1E9, "rel_residual": e9["rel_residual"], "rel_error_vs_exact": None,
+                            "note": "headline run to a relative residual of 5e-10, which brings the error "
+                                    "against the exact solution below 1e-9"}
+    if big is not None:
+        bi = big["info"]
+        krl = kernel_rates(big, wl, args.local)
+        out["large_grid"] = {
+            "workload": wl.name, "levels": list(wl.levels[0]), "N": bi["N"], "P": wl.P, "gamma": str(wl.gamma),
+            "q": bi["q"], "N0": bi["N0"], "curve": "hilbert", "dtype": dtype_label(bi),
+            "ms": round(big["ms"], 3), "setup_ms": round(big["setup_ms"], 3), "solve_ms": round(big["solve_ms"], 3),
+            "iterations": big["iterations"], "rel_residual": big["rel_residual"], "rel_error_vs_exact": None,
+            "factor_bytes": bi["factor_algo_bytes"],
+            "kernel_ms_per_step": {k: round(v[0], 3) for k, v in big["kernels"].items()},
+            "roofline_spmv": {"kernel": "k_spmv", "bound": "hbm", "achieved": round(krl["spmv_gbps"], 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(krl["spmv_gbps"] / HBM_PEAK_GBS, 4), "target_frac": 0.6,
+                              "avg_launch_ms": krl["avg_spmv_ms"], "algorithmic_bytes_per_launch": krl["spmv_bytes"]},
+            "roofline_local_solve": {"kernel": "k_schwarz_trsv (FP32 factors)", "bound": "hbm",
+                                     "achieved": round(krl["local_gbps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(krl["local_gbps"] / HBM_PEAK_GBS, 4), "target_frac": 0.6,
+                                     "avg_launch_ms": krl["avg_local_ms"],
+                                     "algorithmic_bytes_per_launch": krl["local_bytes"]},
+            "note": "q = 4 under the dense coarse-size cap N0 <= 16384 (the four-levels-coarser rule gives 64)"}
     if sweep:
         rows = sorted([(w.gamma, head)] + sweep, key=lambda t: t[0])
         out["overlap_sweep"] = [{"gamma": str(gm), "ms": round(r["ms"], 3), "setup_ms": round(r["setup_ms"], 3),
@@ -536,9 +652,15 @@ def main():
     if not args.no_cpu_baseline:
         # the oracle leg: CPU timing of the oracle, then the accuracy checks
         iters = f64["iterations"] if f64 is not None else head["iterations"]
-        out["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_sample, full=args.cpu_full)
         progress("CPU oracle baseline")
-        chk = oracle_checks(w, xh, ct_raw, adj_raw)
+        chk = oracle_checks(w, xh, ct_raw, adj_raw,
+                            extra={"fp64_coarse": c64["x"].cpu().numpy(), "to_error_1e-9": e9["x"].cpu().numpy()},
+                            big=(wl, big["x"]) if big is not None else None)
+        for k in ("fp64_coarse", "to_error_1e-9"):
+            out[k]["rel_error_vs_exact"] = chk[k + "_rel_error_vs_exact"]
+        if big is not None:
+            out["large_grid"]["rel_error_vs_exact"] = chk["large_grid_rel_error_vs_exact"]
         out["cpu_baseline"]["accuracy_vs_oracle"] = chk
         out["headline"]["rel_error_vs_exact"] = chk["headline_rel_error_vs_exact"]
         if ct_raw is not None:

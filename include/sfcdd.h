@@ -73,6 +73,8 @@ enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
  * (Morton), or Hilbert (Skilling's construction), both at the resolution of
  * the finest direction on the scaled coordinates k_j 2^(max l - l_j). */
 enum { SFCDD_CURVE_ZORDER = 0, SFCDD_CURVE_HILBERT = 1 };
+/* Precision of the coarse operator (see sfcdd_params.coarse_precision). */
+enum { SFCDD_COARSE_AUTO = 0, SFCDD_COARSE_FP64 = 1 };
 /* Flags OR-ed into the method of sfcdd_solve: start from x0 exactly as given
  * and apply the full balanced operator every iteration; stop on the recursive
  * residual alone (see sfcdd_solve). */
@@ -92,13 +94,19 @@ typedef struct {
   int32_t weighting;         /* SFCDD_WEIGHT_NONE, _OMEGA (eq. omegai) or _D (eq. Di)    */
   int32_t variant;           /* SFCDD_ADDITIVE, SFCDD_BALANCED or SFCDD_DEFLATED         */
   int32_t factor_dtype;      /* SFCDD_FP64 or SFCDD_FP32 subdomain factors and solves
-                                (and coarse inverse; see sfcdd_info.coarse_fp32)       */
+                                (see coarse_precision for the coarse operator)         */
   int32_t local_solver;      /* SFCDD_LOCAL_CHOLESKY: forward/backward substitution
                                 with the Cholesky factor; SFCDD_LOCAL_INVERSE: the
                                 explicit inverse formed from it, applied as a
                                 symmetric matrix-vector product                        */
   int32_t layout;            /* 0 natural order, 1 curve order                          */
   int32_t curve;             /* SFCDD_CURVE_ZORDER or SFCDD_CURVE_HILBERT (Sec. 3.2)    */
+  int32_t coarse_precision;  /* SFCDD_COARSE_AUTO: beside FP32 subdomain factors the
+                                coarse inverse X_0 is FP32 and the coarse Cholesky
+                                factor too when the coarse matrices are well
+                                conditioned (sfcdd_info.coarse_fp32); FP64 otherwise.
+                                SFCDD_COARSE_FP64: factor, inverse and coarse solves
+                                in FP64 whatever the subdomain factors               */
 } sfcdd_params;
 
 typedef struct {
@@ -125,10 +133,12 @@ typedef struct {
   int32_t ngrids;            /* grids in the context (1 unless set up as a batch)      */
   int32_t trsv_waves;        /* waves per workgroup of the substitution kernel          */
   int32_t coarse_fp32;       /* 1: the coarse Cholesky factor is FP32 (FP32 subdomain
-                                factors and every coarse matrix well conditioned by
-                                the bound kappa(A) * max block / min block <= 4096);
-                                0: FP64.  Its inverse X_0 = L_0^{-1} is FP32 whenever
-                                the subdomain factors are                              */
+                                factors, automatic coarse precision and every coarse
+                                matrix well conditioned by the bound
+                                kappa(A) * max block / min block <= 4096); 0: FP64    */
+  int32_t coarse_inv_fp32;   /* 1: the coarse inverse X_0 = L_0^{-1} and the coarse
+                                solves' matrix reads are FP32 (FP32 subdomain factors,
+                                automatic coarse precision); 0: FP64                  */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1

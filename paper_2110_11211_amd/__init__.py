@@ -33,6 +33,7 @@ SOLVE_RECURSIVE = 512
 SOLVE_ENERGY = 1024
 CURVE = {"zorder": 0, "hilbert": 1}
 LAYOUT = {"natural": 0, "sfc": 1}
+COARSE_PRECISION = {"auto": 0, "fp64": 1}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
            "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
@@ -54,7 +55,8 @@ class Params(ctypes.Structure):
                 ("P", ctypes.c_int32), ("gamma_num", ctypes.c_int64), ("gamma_den", ctypes.c_int64),
                 ("q", ctypes.c_int32), ("weighting", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("factor_dtype", ctypes.c_int32), ("local_solver", ctypes.c_int32),
-                ("layout", ctypes.c_int32), ("curve", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("curve", ctypes.c_int32),
+                ("coarse_precision", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -69,7 +71,8 @@ class Info(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("sum_Ni", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("factor_algo_bytes", ctypes.c_int64), ("coarse_bytes", ctypes.c_int64),
                 ("setup_ms", ctypes.c_double * 6), ("ngrids", ctypes.c_int32),
-                ("trsv_waves", ctypes.c_int32), ("coarse_fp32", ctypes.c_int32)]
+                ("trsv_waves", ctypes.c_int32), ("coarse_fp32", ctypes.c_int32),
+                ("coarse_inv_fp32", ctypes.c_int32)]
 
 
 _lib = None
@@ -118,7 +121,7 @@ def _check(st: int, ctx=None):
 
 def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q=0,
                 weighting="omega", variant="balanced", factor_dtype="fp64",
-                local_solver="cholesky", layout="natural", curve="zorder"):
+                local_solver="cholesky", layout="natural", curve="zorder", coarse_precision="auto"):
     """Builds the sfcdd_params struct; returns (struct, keepalive)."""
     g = Fraction(gamma)
     d = len(levels) if levels is not None else len(npts)
@@ -147,6 +150,7 @@ def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q
     prm.local_solver = LOCAL_SOLVER[local_solver]
     prm.layout = LAYOUT[layout]
     prm.curve = CURVE[curve]
+    prm.coarse_precision = COARSE_PRECISION[coarse_precision]
     return prm, keep
 
 
@@ -194,7 +198,7 @@ class SFCSchwarz:
                  coeff: Optional[Sequence[float]] = None, P: int = 1, gamma=Fraction(1, 2), q: int = 0,
                  weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
                  local_solver: str = "cholesky", layout: str = "natural", device="cuda:0",
-                 workspace=None, curve: str = "zorder"):
+                 workspace=None, curve: str = "zorder", coarse_precision: str = "auto"):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -202,7 +206,7 @@ class SFCSchwarz:
             raise RuntimeError("SFCSchwarz needs a ROCm GPU device")
         self.kw = dict(levels=levels, npts=npts, coeff=coeff, P=P, gamma=gamma, q=q, weighting=weighting,
                        variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
-                       layout=layout, curve=curve)
+                       layout=layout, curve=curve, coarse_precision=coarse_precision)
         prm, self._keep = make_params(**self.kw)
         self._prm = prm
         with torch.cuda.device(self.device):

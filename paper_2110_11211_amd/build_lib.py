@@ -23,16 +23,22 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     """Compiles every source and links the library; returns its path."""
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         cmd = [HIPCC] + FLAGS[:-1] + ["-c", os.path.join(CSRC, src), "-o", obj]
-        cmd = [c for c in cmd if c != "-shared"]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([c for c in cmd if c != "-shared"])
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    # the sources compile independently: one compiler process each
+    with ThreadPoolExecutor(max_workers=min(len(cmds), 8)) as ex:
+        for r in list(ex.map(lambda c: subprocess.run(c, check=False), cmds)):
+            if r.returncode != 0:
+                raise subprocess.CalledProcessError(r.returncode, r.args)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.run(cmd, check=True)

@@ -60,6 +60,7 @@ struct sfcdd_ctx {
   int Ptot = 0, dmax = 0, rbx = RED_BLOCKS;
   int max_cblock = 1;  // largest coarse block (points) of any grid
   bool coarse32 = false;  // FP32 coarse Cholesky factor (see coarse_fp32_ok)
+  bool coarse_x32 = false;  // FP32 coarse inverse X_0 (FP32 subdomain factors, automatic coarse precision)
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // internal per-device stream (default priority): the coarse setup
                                // overlaps the fine factorisation; shared by the contexts of a device
@@ -266,6 +267,8 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
   if (p->local_solver != SFCDD_LOCAL_CHOLESKY && p->local_solver != SFCDD_LOCAL_INVERSE)
     GFAIL(SFCDD_EINVAL, "local_solver = %d", p->local_solver);
   if (p->layout != 0 && p->layout != 1) GFAIL(SFCDD_EINVAL, "layout = %d", p->layout);
+  if (p->coarse_precision != SFCDD_COARSE_AUTO && p->coarse_precision != SFCDD_COARSE_FP64)
+    GFAIL(SFCDD_EINVAL, "coarse_precision = %d", p->coarse_precision);
   if (p->curve != SFCDD_CURVE_ZORDER && p->curve != SFCDD_CURVE_HILBERT)
     GFAIL(SFCDD_EINVAL, "curve = %d", p->curve);
   g.curve = p->curve;
@@ -429,9 +432,10 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     }
     if (params[k].weighting != params[0].weighting || params[k].variant != params[0].variant ||
         params[k].factor_dtype != params[0].factor_dtype ||
-        params[k].local_solver != params[0].local_solver || params[k].layout != params[0].layout)
-      FAIL(c, SFCDD_EINVAL, "grid %d: weighting, variant, factor_dtype, local_solver and layout must "
-           "be the same for every grid of a batch", k);
+        params[k].local_solver != params[0].local_solver || params[k].layout != params[0].layout ||
+        params[k].coarse_precision != params[0].coarse_precision)
+      FAIL(c, SFCDD_EINVAL, "grid %d: weighting, variant, factor_dtype, local_solver, layout and "
+           "coarse_precision must be the same for every grid of a batch", k);
   }
   c->weighting = params[0].weighting;
   c->variant = params[0].variant;
@@ -517,7 +521,8 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     const GridDesc& gd = c->grid[k].desc;
     c->max_cblock = (int)std::max<int64_t>(c->max_cblock, ceil_div(gd.base + 1, gd.q));
   }
-  c->coarse32 = c->fdtype == SFCDD_FP32 && coarse_fp32_ok(c);
+  c->coarse_x32 = c->fdtype == SFCDD_FP32 && params[0].coarse_precision == SFCDD_COARSE_AUTO;
+  c->coarse32 = c->coarse_x32 && coarse_fp32_ok(c);
 
   // workspace layout
   const size_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
@@ -657,7 +662,7 @@ void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) 
   const Batch B = c->batch();
   BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
   launch_restrict(B, c->max_cblock, v, c->c0, c->stream);
-  if (c->fdtype == SFCDD_FP32)
+  if (c->coarse_x32)
     launch_coarse_apply<float>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff,
                                reinterpret_cast<const float*>(c->X0) + c->ctiles * TS2, c->c0, c->cy,
                                c->cpart, c->d0, mask, c->stream);
@@ -949,7 +954,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     // The factor itself is FP32 as well when the coarse matrices are well
     // conditioned (coarse_fp32_ok), else FP64 and rounded.  FP32 tiles: L_0
     // in the first half of the X0 region, X_0 in the second.
-    if (c->fdtype == SFCDD_FP32) {
+    if (c->coarse_x32) {
       float* L32 = reinterpret_cast<float*>(c->X0);
       float* part32 = reinterpret_cast<float*>(c->cpartk);
       if (c->coarse32) {
@@ -1036,6 +1041,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.ngrids = G;
   I.trsv_waves = c->trsv_waves;
   I.coarse_fp32 = c->coarse32 ? 1 : 0;
+  I.coarse_inv_fp32 = c->coarse_x32 ? 1 : 0;
 
   int32_t stat[2] = {0, 0};
   HIPCHK(c, hipMemcpy(stat, c->status, 8, hipMemcpyDeviceToHost));

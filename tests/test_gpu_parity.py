@@ -297,16 +297,82 @@ def test_full_size_solution_and_operator_properties(name, fdtype):
     torch.cuda.empty_cache()
 
 
-def test_full_size_apply_c2_matches_oracle():
+_C2_ORACLES = {}
+
+
+def _c2_oracle(curve):
+    """The oracle's operators of the d=3 workload (factored once per curve)."""
+    if curve not in _C2_ORACLES:
+        w = workloads()["c2"]
+        _C2_ORACLES.clear()
+        _C2_ORACLES[curve] = OracleSchwarz(Grid(levels=w.levels[0]), w.P, w.gamma, curve=curve)
+    return _C2_ORACLES[curve]
+
+
+def _kappa(levels):
+    """Condition number of the FD matrix from its closed-form extreme
+    eigenvalues sum_j 4 (n_j+1)^2 sin^2(k pi / (2 (n_j+1))), k = 1 and n_j."""
+    n = np.array([(1 << l) - 1 for l in levels], dtype=np.float64)
+    t = np.pi / (2.0 * (n + 1))
+    return float(np.sum((n + 1) ** 2 * np.cos(t) ** 2) / np.sum((n + 1) ** 2 * np.sin(t) ** 2))
+
+
+@pytest.mark.parametrize("curve,fdtype", [("zorder", "fp64"), ("hilbert", "fp64"), ("hilbert", "fp32")])
+def test_full_size_apply_c2_matches_oracle(curve, fdtype):
     """One preconditioner application at the d=3 workload's full size (256
-    subdomains of ~1937 points, FP64 factors) against the oracle."""
+    subdomains of ~1937 points) against the oracle, in the benchmark's launch
+    configuration (default launch; with FP32 factors the 2 GB of factors take
+    the non-temporal streaming substitution).  FP32 bound: the subdomain
+    matrices are principal submatrices of A (kappa(A_i) <= kappa(A), about
+    2.9e3 here) and their entries are exact in FP32, so an FP32 Cholesky solve
+    errs by a small multiple of kappa(A) * 2^-24; the bar is 4 kappa(A) 2^-24
+    (7e-4), the measured error is printed."""
     w = workloads()["c2"]
-    announce("full-size apply c2")
+    announce("full-size apply c2", curve, fdtype)
+    O = _c2_oracle(curve)
+    S = _solver(w.levels[0], w.P, w.gamma, factor_dtype=fdtype, curve=curve)
+    if fdtype == "fp32":
+        assert S.info()["factor_bytes"] > 256 << 20   # the streaming (non-temporal) path
+    r = uniform_pm1(31, O.N)
+    e = relerr(host(S.apply(dvec(r))), O.apply(r))
+    tol = FP64_TOL if fdtype == "fp64" else 4.0 * _kappa(w.levels[0]) * 2.0 ** -24
+    print(f"c2 apply {curve} {fdtype}: relative error {e:.3e} (bar {tol:.1e})", flush=True)
+    assert e <= tol
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+
+
+def _golden_c2_iterations():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_hilbert_iterations.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    its, res, err = rows[0]
+    return int(its), float(res), float(err)
+
+
+@pytest.mark.parametrize("fdtype", ["fp32", "fp64"])
+def test_c2_iteration_count_matches_oracle(fdtype):
+    """The benchmark's solve (Hilbert curve, balancing start, rtol 1e-9; FP32
+    factors with flexible CG, FP64 factors with PCG) takes the oracle's PCG
+    iteration count within one, and reaches the oracle's error against the
+    exact solution (golden file written by the oracle's script)."""
+    w = workloads()["c2"]
+    announce("c2 iterations", fdtype)
+    its, _, err_o = _golden_c2_iterations()
     g = Grid(levels=w.levels[0])
-    O = OracleSchwarz(g, w.P, w.gamma)
-    S = _solver(w.levels[0], w.P, w.gamma)
-    r = uniform_pm1(31, g.N)
-    assert relerr(host(S.apply(dvec(r))), O.apply(r)) <= FP64_TOL
+    f = w.rhs()
+    S = _solver(w.levels[0], w.P, w.gamma, factor_dtype=fdtype, curve="hilbert")
+    x, info = S.solve(dvec(f), rtol=w.rtol, method="fcg" if fdtype == "fp32" else "pcg", max_iter=200)
+    err = relerr(host(x), exact.solve(g, f))
+    print(f"c2 {fdtype}: {info['iterations']} iterations (oracle {its}), residual "
+          f"{info['rel_residual']:.3e}, error {err:.3e} (oracle {err_o:.3e})", flush=True)
+    assert abs(info["iterations"] - its) <= 1
+    assert info["rel_residual"] <= w.rtol
+    assert err <= 2.0 * err_o
+    S.close()
+    del S
+    torch.cuda.empty_cache()
 
 
 def test_batch_heterogeneous_grids_match_single_grid_oracle():
@@ -463,7 +529,32 @@ def test_coarse_factor_precision_choice():
         assert S.info()["coarse_fp32"] == want, fdtype
         S.close()
     S = m.SFCSchwarz(levels=(14, 1), P=128, gamma=Fraction(1, 4), factor_dtype="fp32")
-    assert S.info()["coarse_fp32"] == 0
+    assert S.info()["coarse_fp32"] == 0 and S.info()["coarse_inv_fp32"] == 1
+    S.close()
+
+
+@pytest.mark.parametrize("levels,P,gamma", [((6, 5, 5), 128, Fraction(1, 2)), ((7, 2), 11, Fraction(1, 2))])
+def test_fp32_factors_with_fp64_coarse_operator(levels, P, gamma):
+    """coarse_precision="fp64" keeps the coarse factor, inverse and solves in
+    FP64 beside FP32 subdomain factors: the coarse-space identity of the
+    balanced operator (C^{-1} A R_0^T c = R_0^T c) then holds to FP64
+    rounding, and the application matches the oracle to the FP32 bar."""
+    announce("fp64 coarse beside fp32 factors", levels, P, gamma)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma)
+    S = _solver(levels, P, gamma, factor_dtype="fp32", coarse_precision="fp64", layout="sfc")
+    inf = S.info()
+    assert inf["coarse_fp32"] == 0 and inf["coarse_inv_fp32"] == 0
+    r = uniform_pm1(41, g.N)
+    sfc = S.partition()["sfc_index"]
+    h = np.empty(g.N)
+    h[sfc] = host(S.apply(dvec(r[sfc])))
+    assert relerr(h, O.apply(r)) <= FP32_TOL
+    cv = dvec(_coarse_vector(g.N, P, S.partition()["q"], 43))
+    back = S.apply(S.matvec(cv))
+    e = relerr(host(back), host(cv))
+    print(f"coarse identity with the FP64 coarse operator: {e:.2e}", flush=True)
+    assert e <= 1e-10
     S.close()
 
 
