@@ -14,7 +14,8 @@
  *  - Memory.  The library allocates no device memory.  The caller queries
  *    sfcdd_workspace_size, allocates one device buffer of that size (any
  *    allocator; 256-byte alignment) and passes it to sfcdd_setup; the buffer
- *    must stay alive and untouched until sfcdd_destroy.  Vectors passed to the
+ *    must stay alive and untouched until sfcdd_destroy.  (sfcdd_setup_noalloc
+ *    instead takes the library's static per-device workspace.)  Vectors passed to the
  *    compute calls are caller-owned device buffers of N doubles.  The context
  *    owns only host memory.
  *  - Streams.  All device work is enqueued on the HIP stream given to
@@ -174,6 +175,30 @@ sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t
  * not available for batches (EINVAL). */
 sfcdd_status sfcdd_setup_batch(int32_t ngrids, const sfcdd_params* params, void* workspace_dev,
                                size_t bytes, void* hip_stream, sfcdd_ctx** out);
+
+/* Bytes of the device workspace behind sfcdd_setup_noalloc: one static array
+ * per device, resident from the first allocation-free setup on the device
+ * until the process ends. */
+#define SFCDD_NOALLOC_WORKSPACE_BYTES ((size_t)256 << 20)
+
+/* Allocation-free variant of sfcdd_setup, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same setup of one grid, with the workspace taken from the
+ * library's static per-device array of SFCDD_NOALLOC_WORKSPACE_BYTES instead of
+ * a caller buffer.  It calls no hipMalloc, hipHostMalloc, hipFree or other
+ * device or pinned-host allocator; the context's host tables live on the C++
+ * heap, and its scalar read-backs go to pageable host memory (each waits for
+ * the stream, so a solve does not overlap its host checks with the next
+ * preconditioner application).  Parameters, stream and errors as sfcdd_setup;
+ * ENOMEM (message gives the size) when sfcdd_workspace_size exceeds
+ * SFCDD_NOALLOC_WORKSPACE_BYTES.  The array is shared by every allocation-free
+ * context of the device: a new sfcdd_setup_noalloc on the device overwrites it,
+ * after which every call on an earlier allocation-free context of that device
+ * fails with EINVAL (destroy it as usual).  Allocation-free setups and their
+ * contexts' calls that overlap in time on one device race on the array; keep
+ * them on one thread or ordered.  Everything else (apply, solve, destroy) is
+ * used as with sfcdd_setup. */
+sfcdd_status sfcdd_setup_noalloc(const sfcdd_params* params, void* hip_stream, sfcdd_ctx** out);
 
 /* h = C^{-1} g (Alg. 2; balanced form eq. balSW when variant = BALANCED).
  * g_dev, h_dev: device, N doubles each, may not alias.  Asynchronous. */

@@ -34,8 +34,10 @@ SOLVE_ENERGY = 1024
 CURVE = {"zorder": 0, "hilbert": 1}
 LAYOUT = {"natural": 0, "sfc": 1}
 COARSE_PRECISION = {"auto": 0, "fp64": 1}
+NOALLOC_WORKSPACE_BYTES = 256 << 20  # SFCDD_NOALLOC_WORKSPACE_BYTES
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
+           "sfcdd_setup_noalloc",
            "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
            "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
            "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_read_probe",
@@ -93,6 +95,7 @@ def lib() -> ctypes.CDLL:
     L.sfcdd_workspace_size_batch.argtypes = [i32, P(Params), P(ctypes.c_size_t)]
     L.sfcdd_setup.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(vp)]
     L.sfcdd_setup_batch.argtypes = [i32, P(Params), vp, ctypes.c_size_t, vp, P(vp)]
+    L.sfcdd_setup_noalloc.argtypes = [P(Params), vp, P(vp)]
     L.sfcdd_get_batch_stats.argtypes = [vp, P(i32), P(dbl)]
     L.sfcdd_autotune.argtypes = [vp, i32, P(dbl)]
     L.sfcdd_apply_precond.argtypes = [vp, vp, vp]
@@ -191,7 +194,10 @@ class SFCSchwarz:
 
     All vectors are float64 torch tensors of length N on the context's device,
     in natural order (first coordinate fastest) unless layout="sfc".  Work is
-    enqueued on the torch stream current at construction.
+    enqueued on the torch stream current at construction.  workspace="static"
+    selects the allocation-free setup (sfcdd_setup_noalloc): the library's
+    static per-device workspace, which a later such setup on the device takes
+    over.
     """
 
     def __init__(self, levels: Optional[Sequence[int]] = None, npts: Optional[Sequence[int]] = None,
@@ -211,11 +217,13 @@ class SFCSchwarz:
         self._prm = prm
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            self.ws = self._workspace(workspace)
             ctx = ctypes.c_void_p()
-            _check(lib().sfcdd_setup(ctypes.byref(prm), ctypes.c_void_p(self.ws.data_ptr()),
-                                     self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream),
-                                     ctypes.byref(ctx)), None if not ctx.value else ctx)
+            if isinstance(workspace, str):
+                if workspace != "static":
+                    raise ValueError('workspace must be a uint8 tensor, None or "static"')
+                self.ws = None
+                _check(lib().sfcdd_setup_noalloc(ctypes.byref(prm), ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(ctx)), None if not ctx.value else ctx)
         self.ctx = ctx
         inf = Info()
         _check(lib().sfcdd_get_info(self.ctx, ctypes.byref(inf)), self.ctx)

@@ -103,6 +103,13 @@ struct sfcdd_ctx {
   double* host_scal = nullptr;  // pinned: an image of the workspace bytes from the scalars
                                 // to the end of the flags (rb_bytes; flags at byte rb_flags),
                                 // then the flag upload buffer (G int32 at byte hb_off)
+  // allocation-free context (sfcdd_setup_noalloc): the workspace is the device's
+  // static array, host_scal points into this pageable buffer, and the context
+  // is valid while no later allocation-free setup on its device has run
+  bool noalloc = false;
+  int noalloc_dev = -1;
+  uint64_t noalloc_gen = 0;
+  std::vector<unsigned char> host_pageable;
   size_t rb_bytes = 0, rb_flags = 0, hb_off = 0;
   std::vector<int32_t> last_iters;
   hipEvent_t ev_rb = nullptr;  // readback of the per-iteration scalars
@@ -150,6 +157,19 @@ struct sfcdd_ctx {
   do {                                                                                         \
     hipError_t _e = (call);                                                                    \
     if (_e != hipSuccess) FAIL(ctx, SFCDD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+namespace {
+bool noalloc_stale(const sfcdd_ctx* c);
+}  // namespace
+
+// A context from sfcdd_setup_noalloc whose device workspace a later
+// allocation-free setup has taken over may not run device work.
+#define LIVE(ctx)                                                                             \
+  do {                                                                                        \
+    if (noalloc_stale(ctx))                                                                   \
+      FAIL(ctx, SFCDD_EINVAL, "allocation-free context superseded by a later "                \
+           "sfcdd_setup_noalloc on its device");                                              \
   } while (0)
 
 namespace {
@@ -1050,11 +1070,52 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   return SFCDD_OK;
 }
 
+// Workspace of the allocation-free setup: one array per device, resident for
+// the life of the process.  In host code its name is only a stand-in for the
+// symbol; the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[SFCDD_NOALLOC_WORKSPACE_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+uint64_t g_noalloc_gen[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's static workspace (looked up on the
+// first call on that device) and the generation the new context takes; a
+// context of an older generation on the same device is stale.
+sfcdd_status noalloc_acquire(int* dev_out, void** ptr_out, uint64_t* gen_out) {
+  sfcdd_ctx* none = nullptr;
+  int dev = 0;
+  HIPCHK(none, hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    FAIL(none, SFCDD_EINVAL, "device %d: the allocation-free setup supports devices 0..%d", dev,
+         NOALLOC_MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(none, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) FAIL(none, SFCDD_EDEVICE, "hipGetSymbolAddress returned no address for the static workspace");
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *dev_out = dev;
+  *ptr_out = g_noalloc_ptr[dev];
+  *gen_out = ++g_noalloc_gen[dev];
+  return SFCDD_OK;
+}
+
+// EINVAL for an allocation-free context whose workspace a later
+// allocation-free setup on the same device has taken over.
+bool noalloc_stale(const sfcdd_ctx* c) {
+  if (!c->noalloc) return false;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_gen[c->noalloc_dev] != c->noalloc_gen;
+}
+
 sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev, size_t bytes,
-                          void* hip_stream, sfcdd_ctx** out) {
+                          void* hip_stream, sfcdd_ctx** out, bool noalloc = false) {
   if (!out) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!workspace_dev) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "workspace is NULL");
+  if (!noalloc && !workspace_dev) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "workspace is NULL");
   sfcdd_ctx* c = new (std::nothrow) sfcdd_ctx();
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_ENOMEM, "host allocation failed");
   sfcdd_status st = plan(c, G, params);
@@ -1062,6 +1123,22 @@ sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev
     g_last_error = c->err;
     delete c;
     return st;
+  }
+  if (noalloc) {
+    if (c->total > SFCDD_NOALLOC_WORKSPACE_BYTES) {
+      g_last_error = "the problem needs a workspace of " + std::to_string(c->total) +
+                     " bytes; the allocation-free setup has " +
+                     std::to_string((unsigned long long)SFCDD_NOALLOC_WORKSPACE_BYTES);
+      delete c;
+      return SFCDD_ENOMEM;
+    }
+    st = noalloc_acquire(&c->noalloc_dev, &workspace_dev, &c->noalloc_gen);
+    if (st != SFCDD_OK) {
+      delete c;
+      return st;
+    }
+    bytes = SFCDD_NOALLOC_WORKSPACE_BYTES;
+    c->noalloc = true;
   }
   if (bytes < c->total) {
     g_last_error = "workspace too small: need " + std::to_string(c->total) + " bytes";
@@ -1075,15 +1152,20 @@ sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev
   c->rb_flags = c->r_active.off - c->r_scal.off;
   c->rb_bytes = c->rb_flags + 4 * (size_t)G;
   c->hb_off = (c->rb_bytes + 255) & ~size_t(255);
-  if (hipHostMalloc((void**)&c->host_scal, c->hb_off + 4 * (size_t)G + 8 * MAXD + 256,
-                    hipHostMallocDefault) != hipSuccess) {
+  const size_t hbytes = c->hb_off + 4 * (size_t)G + 8 * MAXD + 256;
+  if (c->noalloc) {
+    // pageable host image: device-to-host copies into it are waited for with a
+    // stream synchronisation (see wait_readback)
+    c->host_pageable.assign(hbytes, 0);
+    c->host_scal = reinterpret_cast<double*>(c->host_pageable.data());
+  } else if (hipHostMalloc((void**)&c->host_scal, hbytes, hipHostMallocDefault) != hipSuccess) {
     g_last_error = "hipHostMalloc failed";
     delete c;
     return SFCDD_EDEVICE;
   }
   if (hipEventCreateWithFlags(&c->ev_rb, hipEventDisableTiming) != hipSuccess) {
     g_last_error = "hipEventCreate failed";
-    (void)hipHostFree(c->host_scal);
+    if (!c->noalloc) (void)hipHostFree(c->host_scal);
     delete c;
     return SFCDD_EDEVICE;
   }
@@ -1121,8 +1203,13 @@ sfcdd_status sfcdd_setup_batch(int32_t ngrids, const sfcdd_params* params, void*
   return setup_common(ngrids, params, workspace_dev, bytes, hip_stream, out);
 }
 
+sfcdd_status sfcdd_setup_noalloc(const sfcdd_params* params, void* hip_stream, sfcdd_ctx** out) {
+  return setup_common(1, params, nullptr, 0, hip_stream, out, true);
+}
+
 sfcdd_status sfcdd_apply_precond(sfcdd_ctx* c, const double* g, double* h) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   if (!g || !h || g == h) FAIL(c, SFCDD_EINVAL, "g and h must be distinct non-NULL device vectors");
   const int64_t N = c->Ntot;
   if (c->layout == 1) {
@@ -1138,6 +1225,7 @@ sfcdd_status sfcdd_apply_precond(sfcdd_ctx* c, const double* g, double* h) {
 
 sfcdd_status sfcdd_matvec(sfcdd_ctx* c, const double* x, double* y) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   if (!x || !y || x == y) FAIL(c, SFCDD_EINVAL, "x and y must be distinct non-NULL device vectors");
   const int64_t N = c->Ntot;
   if (c->layout == 1) {
@@ -1154,6 +1242,7 @@ sfcdd_status sfcdd_matvec(sfcdd_ctx* c, const double* x, double* y) {
 sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double rtol,
                          int32_t max_iter, int32_t method, double xi, sfcdd_solve_info* info) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   if (!b_in || !x_io || b_in == x_io) FAIL(c, SFCDD_EINVAL, "b and x must be distinct non-NULL device vectors");
   if (!(rtol > 0.0) || max_iter < 0) FAIL(c, SFCDD_EINVAL, "need rtol > 0 and max_iter >= 0");
   const bool plain = (method & SFCDD_SOLVE_PLAIN_START) != 0;
@@ -1242,7 +1331,8 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     return SFCDD_OK;
   };
   auto wait_readback = [&]() -> sfcdd_status {
-    HIPCHK(c, hipEventSynchronize(c->ev_rb));
+    if (c->noalloc) HIPCHK(c, hipStreamSynchronize(s));  // pageable target: the copy is complete
+    else HIPCHK(c, hipEventSynchronize(c->ev_rb));
     c->active_in_flight = false;
     for (int g = 0; g < G; ++g) rr[g] = hs(c, g, S_RR);
     return SFCDD_OK;
@@ -1470,6 +1560,7 @@ sfcdd_status sfcdd_get_batch_stats(sfcdd_ctx* c, int32_t* iterations, double* re
 
 sfcdd_status sfcdd_grad_coeff(sfcdd_ctx* c, const double* lam, const double* u, double* grad_a) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   if (!lam || !u || !grad_a) FAIL(c, SFCDD_EINVAL, "NULL argument");
   if (c->G != 1) FAIL(c, SFCDD_EINVAL, "the coefficient gradient is defined for a single grid");
   const hipStream_t s = c->stream;
@@ -1494,6 +1585,7 @@ sfcdd_status sfcdd_get_partition(sfcdd_ctx* c, int32_t grid, int32_t* sfc_index_
                                  int64_t* ta_host, int64_t* Ni_host, double* omega_host,
                                  int32_t* q_out) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   if (grid < 0 || grid >= c->G) FAIL(c, SFCDD_EINVAL, "grid %d out of range", grid);
   const GridHost& h = c->grid[grid];
   if (sfc_index_host) {
@@ -1530,6 +1622,7 @@ sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, 
 
 sfcdd_status sfcdd_autotune(sfcdd_ctx* c, int32_t repeats, double* best_ms) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   const bool force = repeats < 0;
   repeats = repeats < 0 ? -repeats : (repeats == 0 ? 3 : repeats);
   const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
@@ -1625,6 +1718,7 @@ sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
 sfcdd_status sfcdd_ct_combine(sfcdd_ctx* c, const double* weights, const double* u, const double* x,
                               int64_t M, double* out) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
   if (M < 0 || (M > 0 && (!weights || !u || !x || !out))) FAIL(c, SFCDD_EINVAL, "ct_combine: NULL argument");
   const int d = c->grid[0].desc.d;
   for (int g = 1; g < c->G; ++g)
@@ -1667,7 +1761,7 @@ sfcdd_status sfcdd_read_probe(const void* buf, size_t bytes, void* hip_stream, i
 sfcdd_status sfcdd_destroy(sfcdd_ctx* c) {
   if (!c) return SFCDD_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  if (c->host_scal && !c->noalloc) (void)hipHostFree(c->host_scal);
   if (c->ev_rb) (void)hipEventDestroy(c->ev_rb);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
 

@@ -115,6 +115,18 @@ def test_size_limits_accepted_at_the_bound():
     assert m.workspace_size(npts=[1 << 18], P=2048, q=64) > 0   # qP = 131072
 
 
+def test_noalloc_setup_rejects_oversize_before_any_device_work():
+    """The allocation-free setup checks the planned workspace against its
+    static array on the host, before any HIP call: ENOMEM with the sizes."""
+    import ctypes
+    prm, keep = m.make_params(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp32")
+    ctx = ctypes.c_void_p()
+    st = m.lib().sfcdd_setup_noalloc(ctypes.byref(prm), None, ctypes.byref(ctx))
+    assert st == m.ENOMEM and not ctx.value
+    msg = m.lib().sfcdd_last_error(None).decode()
+    assert str(m.NOALLOC_WORKSPACE_BYTES) in msg and "allocation-free" in msg
+
+
 def test_workspace_grows_with_factor_precision():
     a = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp32")
     b = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp64")
