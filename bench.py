@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--cpu-only", action="store_true",
                     help="run only the CPU oracle leg (needs no GPU) and print its JSON")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--profile-workload", default="c2", choices=["c2", "c5"],
+                    help="with --profile-only: the workload (c2: the headline grid; c5: the 8.26 M-unknown grid)")
+    ap.add_argument("--profile-coarse", default="dense", choices=["dense", "iterative"],
+                    help="with --profile-only: the coarse solver")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the headline path only (for rocprofv3)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -64,7 +68,7 @@ def parse():
 
 
 def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, curve="hilbert",
-             coarse_precision="auto", rtol=None, max_iter=500):
+             coarse_precision="auto", rtol=None, max_iter=500, coarse_solver="dense"):
     """Times `steps` full setup+solve passes (after `warmup` untimed ones);
     then, when prof_steps > 0, that many more passes with the library's
     per-kernel HIP events on (they add about 3% to a solve, so the step times
@@ -72,7 +76,7 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
     import torch
     import paper_2110_11211_amd as m
     kw = dict(levels=list(w.levels[0]), P=w.P, gamma=w.gamma, factor_dtype=fdtype, local_solver=local,
-              curve=curve, coarse_precision=coarse_precision)
+              curve=curve, coarse_precision=coarse_precision, coarse_solver=coarse_solver)
     rtol = w.rtol if rtol is None else rtol
     nbytes = m.workspace_size(**kw)
     key = (fdtype, local)
@@ -86,6 +90,7 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
     x = None
     ktimes = None
     piters = []
+    csteps = []
     S = None
     for k in range(warmup + steps + prof_steps):
         timed = warmup <= k < warmup + steps
@@ -110,6 +115,8 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
             setups.append(e0.elapsed_time(e1))
             solves.append(e1.elapsed_time(e2))
             iters.append(info["iterations"])
+        if timed:
+            csteps.append(info["coarse_steps"])
         if prof:
             piters.append(info["iterations"] + info["restarts"])
             kt = {kk: S.kernel_time(kk) for kk in ("local_solve", "scatter", "spmv", "coarse")}
@@ -121,7 +128,8 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
     return {"ms": sorted(times)[len(times) // 2], "ms_min": min(times), "setup_ms": sorted(setups)[len(setups) // 2],
             "solve_ms": sorted(solves)[len(solves) // 2], "iterations": iters[-1], "info": sinfo,
             "kernels": ktimes, "prof_steps": prof_steps, "prof_full_launches": sum(piters), "x": x,
-            "rel_residual": info["rel_residual"], "restarts": info["restarts"]}
+            "rel_residual": info["rel_residual"], "restarts": info["restarts"],
+            "coarse_steps": max(csteps) if csteps else 0}
 
 
 def kernel_rates(res, w, local):
@@ -423,9 +431,10 @@ def oracle_checks(w, x_head, ct_raw, adj_raw, extra=None, big=None):
     for k, xv in (extra or {}).items():
         out[k + "_rel_error_vs_exact"] = float(np.linalg.norm(xv - xs) / np.linalg.norm(xs))
     if big is not None:
-        wl, xl = big
+        wl, xl, xli = big
         xe = exact.solve(Grid(levels=wl.levels[0]), wl.rhs())
         out["large_grid_rel_error_vs_exact"] = float(np.linalg.norm(xl - xe) / np.linalg.norm(xe))
+        out["large_grid_iterative_rel_error_vs_exact"] = float(np.linalg.norm(xli - xe) / np.linalg.norm(xe))
     if ct_raw is not None:
         wc, offs = ct_raw["w"], ct_raw["offs"]
         e32 = e64 = 0.0
@@ -476,18 +485,25 @@ def main():
     gc.collect()
     gc.freeze()
     gc.disable()
-    w = workloads()["c2"]
+    w = workloads()["c5" if args.profile_only and args.profile_workload == "c5" else "c2"]
     f_dev = torch.tensor(w.rhs(), dtype=torch.float64, device="cuda:0")
     ws_cache = {}
-    head = run_path(w, f_dev, "fp32", args.local, args.steps, args.warmup, ws_cache, prof_steps=args.steps)
+    head = run_path(w, f_dev, "fp32", args.local, args.steps, args.warmup, ws_cache, prof_steps=args.steps,
+                    coarse_solver=args.profile_coarse if args.profile_only else "dense")
     psteps = head["prof_steps"]
     progress("headline")
     if args.profile_only:
         ms_l, n_l = head["kernels"]["local_solve"]
         n_full = head["prof_full_launches"]
-        out = {"profile_only": True, "ms": head["ms"], "local_solve_launches": n_l,
+        kr = kernel_rates(head, w, args.local)
+        out = {"profile_only": True, "workload": w.name, "ms": head["ms"], "local_solve_launches": n_l,
                "local_solve_full_launches": min(n_l, n_full),
-               "local_solve_avg_ms": ms_l / max(min(n_l, n_full), 1)}
+               "local_solve_avg_ms": ms_l / max(min(n_l, n_full), 1),
+               "local_solve_gbps": kr["local_gbps"], "spmv_launches": head["kernels"]["spmv"][1],
+               "spmv_avg_ms": kr["avg_spmv_ms"], "spmv_gbps": kr["spmv_gbps"],
+               "spmv_algorithmic_bytes": kr["spmv_bytes"], "iterations": head["iterations"],
+               "coarse_ms": head["kernels"]["coarse"][0] / max(psteps, 1), "coarse_steps": head["coarse_steps"],
+               "setup_ms": head["setup_ms"], "solve_ms": head["solve_ms"], "q": head["info"]["q"]}
         if args.copy_probe > 0:
             ws_cache.clear()
             n = args.copy_probe * (1 << 20) // 4
@@ -534,6 +550,11 @@ def main():
         fl_dev = torch.tensor(wl.rhs(), dtype=torch.float64, device="cuda:0")
         big = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1)
         big["x"] = big["x"].cpu().numpy()
+        ws_cache.clear()
+        torch.cuda.empty_cache()
+        # the same grid at the paper's q = 64 (N0 = 262,144) with the iterative coarse solve
+        bigi = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1, coarse_solver="iterative")
+        bigi["x"] = bigi["x"].cpu().numpy()
         del fl_dev
         ws_cache.clear()
         torch.cuda.empty_cache()
@@ -621,6 +642,16 @@ def main():
                                      "avg_launch_ms": krl["avg_local_ms"],
                                      "algorithmic_bytes_per_launch": krl["local_bytes"]},
             "note": "q = 4 under the dense coarse-size cap N0 <= 16384 (the four-levels-coarser rule gives 64)"}
+        ii = bigi["info"]
+        out["large_grid"]["iterative_coarse"] = {
+            "q": ii["q"], "N0": ii["N0"], "N0d": ii["N0d"], "ell_width": ii["ell_width"],
+            "ms": round(bigi["ms"], 3), "setup_ms": round(bigi["setup_ms"], 3),
+            "solve_ms": round(bigi["solve_ms"], 3), "iterations": bigi["iterations"],
+            "inner_steps_max": bigi["coarse_steps"], "inner_budget": ii["coarse_steps"],
+            "rel_residual": bigi["rel_residual"], "rel_error_vs_exact": None,
+            "kernel_ms_per_step": {k: round(v[0], 3) for k, v in bigi["kernels"].items()},
+            "note": "q by the four-levels-coarser rule (64); A_0 kept sparse and solved by an inner FP64 CG "
+                    "to 1e-10 at every coarse solve"}
     if sweep:
         rows = sorted([(w.gamma, head)] + sweep, key=lambda t: t[0])
         out["overlap_sweep"] = [{"gamma": str(gm), "ms": round(r["ms"], 3), "setup_ms": round(r["setup_ms"], 3),
@@ -656,11 +687,12 @@ def main():
         progress("CPU oracle baseline")
         chk = oracle_checks(w, xh, ct_raw, adj_raw,
                             extra={"fp64_coarse": c64["x"].cpu().numpy(), "to_error_1e-9": e9["x"].cpu().numpy()},
-                            big=(wl, big["x"]) if big is not None else None)
+                            big=(wl, big["x"], bigi["x"]) if big is not None else None)
         for k in ("fp64_coarse", "to_error_1e-9"):
             out[k]["rel_error_vs_exact"] = chk[k + "_rel_error_vs_exact"]
         if big is not None:
             out["large_grid"]["rel_error_vs_exact"] = chk["large_grid_rel_error_vs_exact"]
+            out["large_grid"]["iterative_coarse"]["rel_error_vs_exact"] = chk["large_grid_iterative_rel_error_vs_exact"]
         out["cpu_baseline"]["accuracy_vs_oracle"] = chk
         out["headline"]["rel_error_vs_exact"] = chk["headline_rel_error_vs_exact"]
         if ct_raw is not None:

@@ -76,6 +76,8 @@ enum { SFCDD_PCG = 0, SFCDD_FCG = 1, SFCDD_RICHARDSON = 2 };
 enum { SFCDD_CURVE_ZORDER = 0, SFCDD_CURVE_HILBERT = 1 };
 /* Precision of the coarse operator (see sfcdd_params.coarse_precision). */
 enum { SFCDD_COARSE_AUTO = 0, SFCDD_COARSE_FP64 = 1 };
+/* Solver of the coarse problem (see sfcdd_params.coarse_solver). */
+enum { SFCDD_COARSE_DENSE = 0, SFCDD_COARSE_ITERATIVE = 1 };
 /* Flags OR-ed into the method of sfcdd_solve: start from x0 exactly as given
  * and apply the full balanced operator every iteration; stop on the recursive
  * residual alone (see sfcdd_solve). */
@@ -108,6 +110,14 @@ typedef struct {
                                 conditioned (sfcdd_info.coarse_fp32); FP64 otherwise.
                                 SFCDD_COARSE_FP64: factor, inverse and coarse solves
                                 in FP64 whatever the subdomain factors               */
+  int32_t coarse_solver;     /* SFCDD_COARSE_DENSE: A_0 factored and inverted densely;
+                                q = 0 takes the four-levels-coarser rule capped at
+                                qP <= 16384.  SFCDD_COARSE_ITERATIVE (single grids
+                                only): A_0 kept sparse and solved by an inner FP64 CG
+                                at every application (see sfcdd_setup); q = 0 takes
+                                the rule uncapped; qP <= 2^22                          */
+  double coarse_tol;         /* SFCDD_COARSE_ITERATIVE: relative residual of the inner
+                                CG, 0 = 1e-10                                          */
 } sfcdd_params;
 
 typedef struct {
@@ -117,6 +127,11 @@ typedef struct {
   double xi;                 /* Richardson damping used (0 for CG)                     */
   double lambda_min;         /* Lanczos estimates of the extreme eigenvalues of        */
   double lambda_max;         /*   C^{-1} A (Richardson with xi <= 0 only)              */
+  int32_t coarse_steps;      /* iterative coarse solve: most inner CG steps one coarse
+                                solve of this call took (0 with the dense solver)     */
+  int32_t coarse_unconverged; /* iterative coarse solve: coarse solves of this call
+                                whose inner CG stopped at its step budget (each is
+                                followed by a larger budget)                           */
 } sfcdd_solve_info;
 
 typedef struct {
@@ -140,6 +155,12 @@ typedef struct {
   int32_t coarse_inv_fp32;   /* 1: the coarse inverse X_0 = L_0^{-1} and the coarse
                                 solves' matrix reads are FP32 (FP32 subdomain factors,
                                 automatic coarse precision); 0: FP64                  */
+  int32_t coarse_iterative;  /* 1: SFCDD_COARSE_ITERATIVE: then N0d below is the size of
+                                the inner CG's dense second level (the factor and
+                                inverse above belong to it), ell_width the entries
+                                per row kept for A_0, coarse_steps the inner CG's
+                                current step budget                                    */
+  int32_t N0d, ell_width, coarse_steps;
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1
@@ -155,9 +176,21 @@ sfcdd_status sfcdd_workspace_size_batch(int32_t ngrids, const sfcdd_params* para
  * (eq. sloc), overlapping subdomains (eq. enlarge, cyclic), weights
  * (eq. omegai), coarse blocks and A_0 = R_0 A R_0^T (eqs. restr, csm), and a
  * Cholesky factorisation of every A_i = R_i A R_i^T and of A_0 (factor once,
- * Sec. 3.1).  workspace_dev: device buffer of at least the queried size;
- * hip_stream: hipStream_t or NULL.  On success *out receives a new context.
- * ENOTSPD if a factorisation breaks down. */
+ * Sec. 3.1).  With coarse_solver = SFCDD_COARSE_ITERATIVE, A_0 is kept as a
+ * sparse matrix (one row per coarse block: the blocks its points couple to)
+ * and every coarse solve runs an FP64 CG on it to relative residual
+ * coarse_tol, preconditioned by the explicit inverses of its 64 x 64 diagonal
+ * blocks (64 consecutive coarse unknowns) plus a dense correction on the
+ * Galerkin aggregation of A_0 over those blocks; the setup sizes the inner
+ * step budget with one trial solve.  This lifts the dense coarse size limit
+ * (the paper's four-levels-coarser rule, Sec. 4.1, on many subdomains; the
+ * paper leaves the coarse problem's scalable solution open).  The inner solve
+ * makes the preconditioner vary slightly between applications, so sfcdd_solve
+ * uses the flexible CG update for SFCDD_PCG as well.  workspace_dev: device
+ * buffer of at least the queried size; hip_stream: hipStream_t or NULL.  On
+ * success *out receives a new context.  ENOTSPD if a factorisation breaks
+ * down; EINVAL if a coarse row of the iterative solver couples to more blocks
+ * than its table holds. */
 sfcdd_status sfcdd_setup(const sfcdd_params* params, void* workspace_dev, size_t bytes,
                          void* hip_stream, sfcdd_ctx** out);
 
@@ -307,6 +340,19 @@ sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* ctx, int32_t kind, double* total_m
  * the result is reproducible.  Asynchronous on the context stream. */
 sfcdd_status sfcdd_ct_combine(sfcdd_ctx* ctx, const double* weights_dev, const double* u_dev,
                               const double* x_dev, int64_t M, double* out_dev);
+
+/* Grids of the combination technique of level L in d dimensions (Sec. 2,
+ * eq. combi): the anisotropic full grids of the layers |l|_1 = L + d - 1 - i,
+ * l_j >= 1, i = 0 .. d-1, in layer order and lexicographically within a layer
+ * (first entry slowest), each with its combination weight (-1)^i binom(d-1, i)
+ * and its subdomain count P = phat 2^(d-1-i) (eq. Pchoice) capped at the
+ * grid's point count.  Host only, no GPU needed.  *ngrids receives the number
+ * of grids; when any of levels (ngrids * d int32, row-major), layer (int32),
+ * weight (double) or P (int32) is non-NULL, all non-NULL arrays are filled,
+ * which needs capacity >= *ngrids (ENOMEM otherwise, *ngrids still set).
+ * EINVAL for d outside 1..16, L outside 1..60 or phat < 1. */
+sfcdd_status sfcdd_ct_layout(int32_t d, int32_t L, int32_t phat, int32_t capacity, int32_t* ngrids,
+                             int32_t* levels, int32_t* layer, double* weight, int32_t* P);
 
 /* Streaming-read rate of the device, for roofline context: reads the device
  * buffer buf_dev (bytes, a multiple of 16, 16-byte aligned; its contents are

@@ -32,16 +32,17 @@ SOLVE_PLAIN_START = 256
 SOLVE_RECURSIVE = 512
 SOLVE_ENERGY = 1024
 CURVE = {"zorder": 0, "hilbert": 1}
+NOALLOC_WORKSPACE_BYTES = 256 << 20  # SFCDD_NOALLOC_WORKSPACE_BYTES
 LAYOUT = {"natural": 0, "sfc": 1}
 COARSE_PRECISION = {"auto": 0, "fp64": 1}
-NOALLOC_WORKSPACE_BYTES = 256 << 20  # SFCDD_NOALLOC_WORKSPACE_BYTES
+COARSE_SOLVER = {"dense": 0, "iterative": 1}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
            "sfcdd_setup_noalloc",
            "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
            "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
            "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_read_probe",
-           "sfcdd_ct_combine", "sfcdd_destroy", "sfcdd_last_error"]
+           "sfcdd_ct_combine", "sfcdd_ct_layout", "sfcdd_destroy", "sfcdd_last_error"]
 KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
 
 
@@ -58,13 +59,15 @@ class Params(ctypes.Structure):
                 ("q", ctypes.c_int32), ("weighting", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("factor_dtype", ctypes.c_int32), ("local_solver", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("curve", ctypes.c_int32),
-                ("coarse_precision", ctypes.c_int32)]
+                ("coarse_precision", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
+                ("coarse_tol", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("xi", ctypes.c_double),
-                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("coarse_steps", ctypes.c_int32), ("coarse_unconverged", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -74,7 +77,8 @@ class Info(ctypes.Structure):
                 ("factor_algo_bytes", ctypes.c_int64), ("coarse_bytes", ctypes.c_int64),
                 ("setup_ms", ctypes.c_double * 6), ("ngrids", ctypes.c_int32),
                 ("trsv_waves", ctypes.c_int32), ("coarse_fp32", ctypes.c_int32),
-                ("coarse_inv_fp32", ctypes.c_int32)]
+                ("coarse_inv_fp32", ctypes.c_int32), ("coarse_iterative", ctypes.c_int32),
+                ("N0d", ctypes.c_int32), ("ell_width", ctypes.c_int32), ("coarse_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -107,6 +111,7 @@ def lib() -> ctypes.CDLL:
     L.sfcdd_get_info.argtypes = [vp, P(Info)]
     L.sfcdd_set_profiling.argtypes = [vp, i32]
     L.sfcdd_get_kernel_time.argtypes = [vp, i32, P(dbl), P(i64)]
+    L.sfcdd_ct_layout.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32), P(dbl), P(i32)]
     L.sfcdd_destroy.argtypes = [vp]
     L.sfcdd_last_error.argtypes = [vp]
     L.sfcdd_last_error.restype = ctypes.c_char_p
@@ -124,7 +129,8 @@ def _check(st: int, ctx=None):
 
 def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q=0,
                 weighting="omega", variant="balanced", factor_dtype="fp64",
-                local_solver="cholesky", layout="natural", curve="zorder", coarse_precision="auto"):
+                local_solver="cholesky", layout="natural", curve="zorder", coarse_precision="auto",
+                coarse_solver="dense", coarse_tol=0.0):
     """Builds the sfcdd_params struct; returns (struct, keepalive)."""
     g = Fraction(gamma)
     d = len(levels) if levels is not None else len(npts)
@@ -154,6 +160,8 @@ def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q
     prm.layout = LAYOUT[layout]
     prm.curve = CURVE[curve]
     prm.coarse_precision = COARSE_PRECISION[coarse_precision]
+    prm.coarse_solver = COARSE_SOLVER[coarse_solver]
+    prm.coarse_tol = float(coarse_tol)
     return prm, keep
 
 
@@ -204,7 +212,8 @@ class SFCSchwarz:
                  coeff: Optional[Sequence[float]] = None, P: int = 1, gamma=Fraction(1, 2), q: int = 0,
                  weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
                  local_solver: str = "cholesky", layout: str = "natural", device="cuda:0",
-                 workspace=None, curve: str = "zorder", coarse_precision: str = "auto"):
+                 workspace=None, curve: str = "zorder", coarse_precision: str = "auto",
+                 coarse_solver: str = "dense", coarse_tol: float = 0.0):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -212,7 +221,8 @@ class SFCSchwarz:
             raise RuntimeError("SFCSchwarz needs a ROCm GPU device")
         self.kw = dict(levels=levels, npts=npts, coeff=coeff, P=P, gamma=gamma, q=q, weighting=weighting,
                        variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
-                       layout=layout, curve=curve, coarse_precision=coarse_precision)
+                       layout=layout, curve=curve, coarse_precision=coarse_precision,
+                       coarse_solver=coarse_solver, coarse_tol=coarse_tol)
         prm, self._keep = make_params(**self.kw)
         self._prm = prm
         with torch.cuda.device(self.device):
@@ -224,6 +234,11 @@ class SFCSchwarz:
                 self.ws = None
                 _check(lib().sfcdd_setup_noalloc(ctypes.byref(prm), ctypes.c_void_p(self.stream.cuda_stream),
                                                  ctypes.byref(ctx)), None if not ctx.value else ctx)
+            else:
+                self.ws = self._workspace(workspace)
+                _check(lib().sfcdd_setup(ctypes.byref(prm), ctypes.c_void_p(self.ws.data_ptr()),
+                                         self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(ctx)), None if not ctx.value else ctx)
         self.ctx = ctx
         inf = Info()
         _check(lib().sfcdd_get_info(self.ctx, ctypes.byref(inf)), self.ctx)

@@ -1,8 +1,11 @@
 // Per-iteration operators: stencil SpMV in curve order, the subdomain solves
 // of the Schwarz operator (Alg. 2), the weighted scatter-add, the coarse
 // restriction / prolongation, BLAS-1 with deterministic two-stage reductions.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
+#include "coarse_blocks.h"
 
 namespace sfcdd {
 
@@ -13,64 +16,150 @@ namespace sfcdd {
 // MODE 3: y = b - A x over the whole batch (no partials).
 // Reductions: block (x, g) covers grid g only; partials[g * rbx + x]; the
 // grid of blocks is fixed, so the sums are deterministic.
-template <int MODE>
+// D > 0: every grid has dimension D (compile-time neighbour count).  A
+// block takes one contiguous chunk of its range and walks it in windows of
+// SPMV_WIN points: the window's x is staged in LDS (one coalesced read), and
+// a neighbour inside the window (about 90% of them for windows of 2048
+// points of a Hilbert- or Z-ordered grid) is read from there, the rest from
+// memory.  Each thread takes U points of the window per step and issues all
+// their neighbour-index loads before their gathers.  The neighbour table is
+// streamed once per product (non-temporal loads).  The chunks are dealt so
+// that each of the 8 XCDs (which receive the workgroups round-robin) works on
+// a contiguous eighth of the curve, where the neighbours outside a window
+// mostly lie.  D = 0: any mix of dimensions, one point per thread and step,
+// no staging.
+constexpr int SPMV_WIN = 2048;
+
+template <int MODE, int D, int U>
 __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __restrict__ nbr,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const double* __restrict__ b,
                                                       double* __restrict__ partials) {
   __shared__ double sh[16];
+  __shared__ double xw[D > 0 ? SPMV_WIN : 1];
+  constexpr bool PERGRID = MODE == 1 || MODE == 2;
   double acc = 0.0;
-  const int64_t Nt = B.Ntot;
-  int64_t start, hi;
-  if (MODE == 0 || MODE == 3) {
+  const int Nt = (int)B.Ntot;   // < 2^31 (checked at planning)
+  int start, hi;
+  if (!PERGRID) {
     start = 0;
     hi = Nt;
   } else {
     const GridDesc& g = B.grids[blockIdx.y];
-    start = g.goff;
-    hi = g.goff + g.N;
+    start = (int)g.goff;
+    hi = (int)(g.goff + g.N);
   }
-  for (int64_t p = start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < hi;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const GridDesc& g = B.grids[MODE == 0 || MODE == 3 ? grid_of(B, B.gid, p) : (int)blockIdx.y];
-    const double xp = x[p];
-    double v = g.diag * xp;
-    for (int j = 0; j < g.d; ++j) {
-      const int32_t m = nbr[(2 * j) * Nt + p];
-      const int32_t q = nbr[(2 * j + 1) * Nt + p];
-      double sj = 0.0;
-      if (m >= 0) sj += x[m];
-      if (q >= 0) sj += x[q];
-      v -= g.c[j] * sj;
+  const int nbx = gridDim.x;
+  const int lb = (nbx & 7) == 0 ? (int)(blockIdx.x & 7) * (nbx >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  const int chunk = (int)((((int64_t)(hi - start) + nbx - 1) / nbx + 63) & ~int64_t(63));
+  const int c0 = (int)min((int64_t)hi, (int64_t)start + (int64_t)lb * chunk);
+  const int c1 = (int)min((int64_t)hi, (int64_t)c0 + chunk);
+  const int bs = blockDim.x;
+  if (D > 0) {
+    for (int w0 = c0; w0 < c1; w0 += SPMV_WIN) {
+      const int w1 = min(c1, w0 + SPMV_WIN);
+      __syncthreads();  // the previous window's readers are done
+      for (int e = threadIdx.x; e < w1 - w0; e += bs) xw[e] = x[w0 + e];
+      __syncthreads();
+      for (int p0 = w0 + threadIdx.x; p0 < w1; p0 += U * bs) {
+        int32_t nb[U][2 * (D > 0 ? D : 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = p0 + u * bs;
+          const bool ok = p < w1;
+#pragma unroll
+          for (int k = 0; k < 2 * D; ++k)
+            nb[u][k] = ok ? __builtin_nontemporal_load(nbr + (int64_t)k * Nt + p) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = p0 + u * bs;
+          if (p >= w1) break;
+          const GridDesc& g = B.grids[PERGRID ? (int)blockIdx.y : grid_of(B, B.gid, p)];
+          const double xp = xw[p - w0];
+          double v = g.diag * xp;
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            const int32_t m = nb[u][2 * j], q = nb[u][2 * j + 1];
+            double sj = 0.0;
+            if (m >= 0) sj += (m >= w0 && m < w1) ? xw[m - w0] : x[m];
+            if (q >= 0) sj += (q >= w0 && q < w1) ? xw[q - w0] : x[q];
+            v -= g.c[j] * sj;
+          }
+          if (MODE == 2 || MODE == 3) v = b[p] - v;
+          y[p] = v;
+          if (MODE == 1) acc += xp * v;
+          if (MODE == 2) acc += v * v;
+        }
+      }
     }
-    if (MODE == 2 || MODE == 3) v = b[p] - v;
-    y[p] = v;
-    if (MODE == 1) acc += xp * v;
-    if (MODE == 2) acc += v * v;
+  } else {
+    for (int p = c0 + threadIdx.x; p < c1; p += bs) {
+      const GridDesc& g = B.grids[PERGRID ? (int)blockIdx.y : grid_of(B, B.gid, p)];
+      const double xp = x[p];
+      double v = g.diag * xp;
+      for (int j = 0; j < g.d; ++j) {
+        const int32_t m = nbr[(int64_t)(2 * j) * Nt + p];
+        const int32_t q = nbr[(int64_t)(2 * j + 1) * Nt + p];
+        double sj = 0.0;
+        if (m >= 0) sj += x[m];
+        if (q >= 0) sj += x[q];
+        v -= g.c[j] * sj;
+      }
+      if (MODE == 2 || MODE == 3) v = b[p] - v;
+      y[p] = v;
+      if (MODE == 1) acc += xp * v;
+      if (MODE == 2) acc += v * v;
+    }
   }
-  if (MODE == 1 || MODE == 2) {
+  if (PERGRID) {
     const double sm = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + lb] = sm;
+  }
+}
+
+// The whole-batch modes use one window per block (a multiple of 8 blocks),
+// the per-grid modes their fixed block count.
+template <int MODE, int D>
+void spmv_mode(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
+               double* partials, hipStream_t s) {
+  constexpr int UW = D > 0 ? (D <= 4 ? 4 : 2) : 1;
+  if (MODE == 1 || MODE == 2) {
+    hipLaunchKernelGGL((k_spmv<MODE, D, UW>), dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
+                       partials);
+  } else {
+    // windows of up to SPMV_WIN points, but at least 2048 blocks when the
+    // batch is large enough to fill the device
+    int64_t per = RED_THREADS;
+    if (D > 0) per = std::min<int64_t>(SPMV_WIN, std::max<int64_t>(RED_THREADS, ((B.Ntot / 2048) + 63) & ~int64_t(63)));
+    int64_t nb = (B.Ntot + per - 1) / per;
+    nb = std::min<int64_t>((nb + 7) & ~int64_t(7), 65535 * 16);
+    hipLaunchKernelGGL((k_spmv<MODE, D, UW>), dim3((unsigned)nb), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
+                       partials);
+  }
+}
+
+template <int MODE>
+void spmv_dim(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
+              double* partials, hipStream_t s) {
+  switch (B.duni) {
+    case 1: spmv_mode<MODE, 1>(B, nbr, x, y, b, partials, s); break;
+    case 2: spmv_mode<MODE, 2>(B, nbr, x, y, b, partials, s); break;
+    case 3: spmv_mode<MODE, 3>(B, nbr, x, y, b, partials, s); break;
+    case 4: spmv_mode<MODE, 4>(B, nbr, x, y, b, partials, s); break;
+    case 5: spmv_mode<MODE, 5>(B, nbr, x, y, b, partials, s); break;
+    case 6: spmv_mode<MODE, 6>(B, nbr, x, y, b, partials, s); break;
+    default: spmv_mode<MODE, 0>(B, nbr, x, y, b, partials, s); break;
   }
 }
 
 void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
                  const double* b, double* partials, hipStream_t s) {
-  if (mode == 2) {
-    hipLaunchKernelGGL(k_spmv<2>, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
-                       partials);
-  } else if (mode == 1) {
-    hipLaunchKernelGGL(k_spmv<1>, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
-                       partials);
-  } else {
-    const int64_t nb = (B.Ntot + RED_THREADS - 1) / RED_THREADS;
-    const dim3 grid((unsigned)(nb < 65535 * 16 ? nb : 65535 * 16));
-    if (mode == 3)
-      hipLaunchKernelGGL(k_spmv<3>, grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
-    else
-      hipLaunchKernelGGL(k_spmv<0>, grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
-  }
+  if (mode == 2) spmv_dim<2>(B, nbr, x, y, b, partials, s);
+  else if (mode == 1) spmv_dim<1>(B, nbr, x, y, b, partials, s);
+  else if (mode == 3) spmv_dim<3>(B, nbr, x, y, b, partials, s);
+  else spmv_dim<0>(B, nbr, x, y, b, partials, s);
 }
 
 
@@ -248,13 +337,6 @@ void launch_scatter(const Batch& B, int dweight, const int32_t* ta, const int32_
 // Coarse restriction c0 = R_0 v (eq. restr): block (i, m) is a contiguous
 // curve range; one wave per coarse unknown.  c0 is stored per grid padded to
 // whole tiles (offset c0pad).
-__device__ __forceinline__ void block_range(int I, const GridDesc& g, int64_t* start, int64_t* size) {
-  const int i = I / g.q, m = I % g.q;
-  const int64_t sz = g.base + (i < g.rem ? 1 : 0);
-  const int64_t qb = sz / g.q, qr = sz % g.q;
-  *start = piece_start(i, g.base, g.rem) + (m < qr ? m * (qb + 1) : qr * (qb + 1) + (m - qr) * qb);
-  *size = qb + (m < qr ? 1 : 0);
-}
 
 // R_0 v: the sum of v over each coarse block (a contiguous curve range), LPU
 // lanes per coarse unknown summing in a fixed order (lane-strided partial
@@ -289,15 +371,6 @@ void launch_restrict(const Batch& B, int max_block, const double* v, double* c0,
   }
 }
 
-__device__ __forceinline__ int coarse_block_of(int64_t p, const GridDesc& g) {
-  const int i = piece_of(p, g.base, g.rem);
-  const int64_t o = p - piece_start(i, g.base, g.rem);
-  const int64_t sz = g.base + (i < g.rem ? 1 : 0);
-  const int64_t qb = sz / g.q, qr = sz % g.q;
-  const int64_t big = qr * (qb + 1);
-  const int m = o < big ? (int)(o / (qb + 1)) : (int)(qr + (o - big) / qb);
-  return i * g.q + m;
-}
 
 // Prolongation R_0^T d0 fused with the final vector combinations.
 template <int MODE>
@@ -306,7 +379,7 @@ __global__ void k_combine(Batch B, const double* __restrict__ d0, const double* 
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B.Ntot;
        p += (int64_t)gridDim.x * blockDim.x) {
     const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
-    const double t = d0[g.c0off + coarse_block_of(p - g.goff, g)];
+    const double t = d0[g.c0off + coarse_block(p - g.goff, g)];
     if (MODE == COMB_PROLONG) out[p] = t;
     if (MODE == COMB_ADD_PROLONG) out[p] = a[p] + t;
     if (MODE == COMB_BAL_FINAL) out[p] = a[p] - t + b[p];

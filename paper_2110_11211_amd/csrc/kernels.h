@@ -36,6 +36,12 @@ struct GridDesc {
   int64_t c0off;            // first coarse unknown
   int64_t c0pad;            // first entry of the tile-padded coarse vector
   int nt0;                  // coarse tiles per edge
+  // dense coarse level: the coarse matrix itself (agg = 1), or, with the
+  // iterative coarse solve, its Galerkin aggregation over groups of agg = TS
+  // consecutive coarse unknowns (the inner solve's second level)
+  int agg;
+  int N0d;                  // ceil(N0 / agg) dense unknowns
+  int nt0d;                 // dense tiles per edge
 };
 
 // Device view of a batch (passed by value).
@@ -43,6 +49,7 @@ struct Batch {
   const GridDesc* grids;
   int G;
   int dmax;                 // planes of the neighbour table
+  int duni;                 // the dimension of every grid when they all agree, else 0
   int64_t Ntot;             // sum of N
   int Ptot;                 // sum of P
   int64_t N0tot;            // sum of N0
@@ -142,6 +149,22 @@ void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t*
                          const int64_t* doff, const T* X, const double* v, double* ytmp,
                          double* part, double* out, const int32_t* active, hipStream_t s);
 void launch_round_f32(int64_t n, const double* src, float* dst, hipStream_t s);
+
+// ---- iterative coarse solve (single grid) -----------------------------------
+void launch_coarse_ell(const Batch& B, int64_t n0, const int32_t* nbr, int kw, int64_t ld, int32_t* deg,
+                       int32_t* col, double* val, int32_t* status, hipStream_t s);
+void launch_bj_extract(int64_t n0, int64_t ld, const int32_t* deg, const int32_t* col, const double* val,
+                       double* tiles, hipStream_t s);
+void launch_bj_form(int ntiles, const double* X, float* M, hipStream_t s);
+void launch_ic_trial(int64_t n0, int64_t ld, double* b, hipStream_t s);
+void launch_ic_begin(const int32_t* outer, int32_t* flag, double* sc, hipStream_t s);
+void launch_ic_spmv(int64_t ld, const int32_t* deg, const int32_t* col, const double* val, const double* p,
+                    double* q, double* part, const int32_t* flag, hipStream_t s);
+void launch_ic_update(int first, int it, int64_t n0, int nt, int nq, const double* qpart, const double* sc,
+                      const double* b, double* x, double* r, const double* p, const double* q, const float* M,
+                      double* z1, double* cagg, double* part, const int32_t* flag, hipStream_t s);
+void launch_ic_dir(int first, int it, int64_t n0, int nt, double tol2, const double* part, const double* cagg,
+                   const double* dagg, double* sc, const double* z1, double* p, int32_t* flag, hipStream_t s);
 void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
                     double* out, hipStream_t s);
 
@@ -171,7 +194,10 @@ void launch_ct_combine(const Batch& B, int layout, const int32_t* pos, const dou
 // Scalar slots of the solver's per-grid device scalars S[g * S_COUNT + slot].
 enum {
   S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZQ, S_BB, S_XI, S_TMP, S_TOL2, S_TRR,
-  S_COUNT = 16
+  // inner CG of the iterative coarse solve (single grid): r.z of the last two
+  // steps, r.r at the start, steps taken, 1 when converged
+  IC_RZ = 16, IC_RR0 = 18, IC_ITS = 19, IC_CONV = 20,
+  S_COUNT = 24
 };
 // Per-grid solver flags (device array `active`).
 enum {

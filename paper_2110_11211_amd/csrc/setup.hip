@@ -2,6 +2,7 @@
 // coarse assembly, for a batch of grids (one launch covers every grid).
 #include "common.h"
 #include "kernels.h"
+#include "coarse_blocks.h"
 
 namespace sfcdd {
 
@@ -221,20 +222,14 @@ template void launch_assemble_local<double>(const Batch&, const int32_t*, const 
 
 // Coarse unknown (block) of local curve position p of grid g: piece i and its
 // m-th block of eq. (restr), local index i q + m.
-__device__ __forceinline__ int coarse_block(int64_t p, const GridDesc& g) {
-  const int i = piece_of(p, g.base, g.rem);
-  const int64_t o = p - piece_start(i, g.base, g.rem);
-  const int64_t sz = g.base + (i < g.rem ? 1 : 0);
-  const int64_t qb = sz / g.q, qr = sz % g.q;
-  const int64_t big = qr * (qb + 1);
-  const int m = o < big ? (int)(o / (qb + 1)) : (int)(qr + (o - big) / qb);
-  return i * g.q + m;
-}
 
 // Integer coupling counts of dimension j between coarse blocks (eq. csm with
 // A = sum_j c_j L_j): cnt(I, J) = sum_{p in I, p' in J} (L_j)_{p p'} for
 // J <= I, accumulated with integer atomics into the packed lower tiles of
-// each grid's coarse matrix (first tile ctile_off[g]).
+// each grid's dense coarse matrix (first tile ctile_off[g]).  With agg > 1
+// the rows and columns are groups of agg consecutive coarse blocks (the
+// Galerkin aggregation of A_0 that the iterative coarse solve uses as its
+// second level).
 __global__ void k_coarse_counts(Batch B, int j, const int32_t* __restrict__ nbr,
                                 const int64_t* __restrict__ ctile_off, int32_t* __restrict__ cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,12 +238,12 @@ __global__ void k_coarse_counts(Batch B, int j, const int32_t* __restrict__ nbr,
   const GridDesc& g = B.grids[gi];
   if (j >= g.d) return;
   int32_t* C = cnt + ctile_off[gi] * TS2;
-  const int I = coarse_block(p - g.goff, g);
+  const int I = coarse_block(p - g.goff, g) / g.agg;
   atomicAdd(&C[tri_index(I / TS, I / TS) * TS2 + (I % TS) * TS + (I % TS)], 2);
   for (int side = 0; side < 2; ++side) {
     const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
     if (q < 0) continue;
-    const int J = coarse_block(q - g.goff, g);
+    const int J = coarse_block(q - g.goff, g) / g.agg;
     if (J > I) continue;
     atomicAdd(&C[tri_index(I / TS, J / TS) * TS2 + (I % TS) * TS + (J % TS)], -1);
   }
@@ -283,8 +278,8 @@ void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32
 __global__ void k_coarse_pad(Batch B, const int64_t* __restrict__ ctile_off, double* __restrict__ A0) {
   const int gi = blockIdx.y;
   const GridDesc& g = B.grids[gi];
-  const int r = g.N0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= g.nt0 * TS) return;
+  const int r = g.N0d + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.nt0d * TS) return;
   const int I = r / TS;
   A0[(ctile_off[gi] + tri_index(I, I)) * TS2 + (r % TS) * TS + (r % TS)] = 1.0;
 }

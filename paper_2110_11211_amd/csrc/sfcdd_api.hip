@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 #include <limits>
+#include <functional>
 #include <map>
 #include <mutex>
 
@@ -57,10 +58,25 @@ struct sfcdd_ctx {
   std::vector<GridHost> grid;
   int weighting = 1, variant = 1, fdtype = 0, local_solver = 0, layout = 0;
   int64_t Ntot = 0, N0tot = 0;
-  int Ptot = 0, dmax = 0, rbx = RED_BLOCKS;
+  int Ptot = 0, dmax = 0, duni = 0, rbx = RED_BLOCKS;
   int max_cblock = 1;  // largest coarse block (points) of any grid
   bool coarse32 = false;  // FP32 coarse Cholesky factor (see coarse_fp32_ok)
   bool coarse_x32 = false;  // FP32 coarse inverse X_0 (FP32 subdomain factors, automatic coarse precision)
+  // iterative coarse solve (single grid): A_0 in ELL form (ic_kw entries per
+  // row, rows padded to ic_ld = ic_nt 64-blocks), the explicit FP32 inverses of
+  // its diagonal 64-blocks, and the inner CG's vectors; the dense coarse
+  // regions hold the aggregated second level
+  bool coarse_iter = false;
+  double ic_tol2 = 1e-20;
+  int ic_kw = 0, ic_nt = 0, ic_nq = 0;
+  int64_t ic_ld = 0;
+  int ic_k = 0;              // inner step budget of one coarse solve
+  int ic_max_steps = 0, ic_unconv = 0;  // statistics of the current sfcdd_solve
+  int32_t *ideg = nullptr, *icol = nullptr, *ibjnt = nullptr, *iflag = nullptr;
+  int64_t* ibjoff = nullptr;
+  double *ival = nullptr, *ibjt = nullptr, *ir = nullptr, *ip = nullptr, *iq = nullptr, *iz1 = nullptr;
+  double *icagg = nullptr, *idagg = nullptr, *iqpart = nullptr, *ipart = nullptr;
+  float* ibjm = nullptr;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // internal per-device stream (default priority): the coarse setup
                                // overlaps the fine factorisation; shared by the contexts of a device
@@ -79,7 +95,8 @@ struct sfcdd_ctx {
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
-      r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout;
+      r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout,
+      r_ideg, r_icol, r_ival, r_ibjt, r_ibjm, r_ibjnt, r_ibjoff, r_ivec, r_icagg, r_idagg, r_iqpart, r_ipart;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // device pointers
@@ -133,6 +150,7 @@ struct sfcdd_ctx {
     B.grids = d_grids;
     B.G = G;
     B.dmax = dmax;
+    B.duni = duni;
     B.Ntot = Ntot;
     B.Ptot = Ptot;
     B.N0tot = N0tot;
@@ -293,6 +311,11 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
     GFAIL(SFCDD_EINVAL, "curve = %d", p->curve);
   g.curve = p->curve;
 
+  if (p->coarse_solver != SFCDD_COARSE_DENSE && p->coarse_solver != SFCDD_COARSE_ITERATIVE)
+    GFAIL(SFCDD_EINVAL, "coarse_solver = %d", p->coarse_solver);
+  const bool iter = p->coarse_solver == SFCDD_COARSE_ITERATIVE;
+  if (iter && !(p->coarse_tol >= 0.0 && p->coarse_tol < 1.0))
+    GFAIL(SFCDD_EINVAL, "coarse_tol = %g must lie in [0, 1)", p->coarse_tol);
   const int P = p->P;
   const int64_t base = N / P, rem = N % P;
   // coarse points per subdomain
@@ -303,18 +326,25 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
     for (int64_t v = base; v > 1; v >>= 1) ++e;
     if (e < 0) e = 0;
     int64_t qq = int64_t(1) << e;
-    qq = std::min<int64_t>(qq, std::max<int64_t>(1, 16384 / P));
+    if (!iter) qq = std::min<int64_t>(qq, std::max<int64_t>(1, 16384 / P));
     qq = std::min<int64_t>(qq, base);
     q = (int)std::max<int64_t>(1, qq);
   }
   if (q < 1 || q > base) GFAIL(SFCDD_EINVAL, "q = %d must satisfy 1 <= q <= floor(N/P) = %lld", q, (long long)base);
-  if ((int64_t)q * P > (int64_t(1) << 17)) GFAIL(SFCDD_EINVAL, "coarse size qP = %lld exceeds 131072", (long long)q * P);
+  const int64_t n0max = iter ? (int64_t(1) << 22) : (int64_t(1) << 17);
+  if ((int64_t)q * P > n0max)
+    GFAIL(SFCDD_EINVAL, "coarse size qP = %lld exceeds %lld", (long long)q * P, (long long)n0max);
   g.P = P;
   g.q = q;
   g.N0 = q * P;
   g.nt0 = (int)ceil_div(g.N0, TS);
   g.base = base;
   g.rem = rem;
+  // dense coarse level: A_0 itself, or (iterative) its aggregation over
+  // groups of TS consecutive coarse unknowns
+  g.agg = iter ? TS : 1;
+  g.N0d = (int)ceil_div(g.N0, g.agg);
+  g.nt0d = (int)ceil_div(g.N0d, TS);
 
   // overlapping subdomains, eq. (enlarge), cyclic closure
   const int64_t F = p->gamma_num / p->gamma_den;
@@ -456,12 +486,19 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
         params[k].coarse_precision != params[0].coarse_precision)
       FAIL(c, SFCDD_EINVAL, "grid %d: weighting, variant, factor_dtype, local_solver, layout and "
            "coarse_precision must be the same for every grid of a batch", k);
+    if (params[k].coarse_solver == SFCDD_COARSE_ITERATIVE && G > 1)
+      FAIL(c, SFCDD_EINVAL, "grid %d: the iterative coarse solver is for single grids", k);
   }
   c->weighting = params[0].weighting;
   c->variant = params[0].variant;
   c->fdtype = params[0].factor_dtype;
   c->local_solver = params[0].local_solver;
   c->layout = params[0].layout;
+  c->coarse_iter = params[0].coarse_solver == SFCDD_COARSE_ITERATIVE;
+  if (c->coarse_iter) {
+    const double t = params[0].coarse_tol > 0.0 ? params[0].coarse_tol : 1e-10;
+    c->ic_tol2 = t * t;
+  }
   // batch placement
   int64_t goff = 0, c0off = 0, c0pad = 0;
   int soff = 0;
@@ -506,19 +543,23 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
       c->min_Ni = std::min(c->min_Ni, h.Ni[i]);
     }
     c->gfac_bytes[k] = (toff - toff0) * TS2 * (c->fdtype == SFCDD_FP32 ? 4 : 8);
-    c->c_nt.push_back(g.nt0);
-    c->c_n.push_back(g.N0);
+    // the dense coarse level (A_0, or its aggregation for the iterative solve)
+    c->c_nt.push_back(g.nt0d);
+    c->c_n.push_back(g.N0d);
     c->c_off.push_back(ctoff);
     c->c_xoff.push_back(g.c0pad);
     c->c_poff.push_back(cpof);
     c->c_doff.push_back(g.c0off);
     c->c_toff.push_back(ctt);
-    ctt += ((int64_t)g.nt0 * g.nt0 + 3) / 4;
-    ctoff += (int64_t)g.nt0 * (g.nt0 + 1) / 2;
-    cpof += (int64_t)g.nt0 * g.nt0 * TS;
-    c->max_nt0 = std::max(c->max_nt0, g.nt0);
-    c->max_N0 = std::max(c->max_N0, g.N0);
+    ctt += ((int64_t)g.nt0d * g.nt0d + 3) / 4;
+    ctoff += (int64_t)g.nt0d * (g.nt0d + 1) / 2;
+    cpof += (int64_t)g.nt0d * g.nt0d * TS;
+    c->max_nt0 = std::max(c->max_nt0, g.nt0d);
+    c->max_N0 = std::max(c->max_N0, g.N0d);
   }
+  c->duni = c->grid[0].desc.d;
+  for (int k = 1; k < G; ++k)
+    if (c->grid[k].desc.d != c->duni) c->duni = 0;
   c->Ntot = goff;
   if (c->Ntot >= (int64_t(1) << 31)) FAIL(c, SFCDD_EOVERFLOW, "total size of the batch >= 2^31");
   c->Ptot = soff;
@@ -542,7 +583,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     c->max_cblock = (int)std::max<int64_t>(c->max_cblock, ceil_div(gd.base + 1, gd.q));
   }
   c->coarse_x32 = c->fdtype == SFCDD_FP32 && params[0].coarse_precision == SFCDD_COARSE_AUTO;
-  c->coarse32 = c->coarse_x32 && coarse_fp32_ok(c);
+  c->coarse32 = c->coarse_x32 && !c->coarse_iter && coarse_fp32_ok(c);
 
   // workspace layout
   const size_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
@@ -571,7 +612,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_A0 = pl.take((size_t)c->ctiles * TS2 * 8);
   c->r_X0 = pl.take((size_t)c->ctiles * TS2 * 8);
   c->r_c0 = pl.take((size_t)c->c0len * 8);
-  c->r_d0 = pl.take((size_t)c->N0tot * 8);
+  c->r_d0 = pl.take((size_t)std::max<int64_t>(c->N0tot, c->c0len) * 8);
   c->r_cpart = pl.take((size_t)c->cparts * 8);
   // split-K partials of the single-matrix factorisation (three slots), later
   // reused by the triangular inversion
@@ -588,6 +629,27 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_active = pl.take((size_t)4 * G);
   c->r_status = pl.take(64);
   c->r_gout = pl.take(MAXD * 8);
+  if (c->coarse_iter) {
+    const GridDesc& g = c->grid[0].desc;
+    c->ic_nt = g.nt0;
+    c->ic_ld = (int64_t)g.nt0 * TS;
+    c->ic_nq = (int)ceil_div(c->ic_ld, 256);
+    // a row holds the block itself and at most 2 d entries per point
+    c->ic_kw = (int)std::min<int64_t>(std::min<int64_t>(256, 2LL * g.d * c->max_cblock + 1), g.N0);
+    const size_t ld = (size_t)c->ic_ld;
+    c->r_ideg = pl.take(4 * ld);
+    c->r_icol = pl.take(4 * ld * c->ic_kw);
+    c->r_ival = pl.take(8 * ld * c->ic_kw);
+    c->r_ibjt = pl.take((size_t)c->ic_nt * TS2 * 8);
+    c->r_ibjm = pl.take((size_t)c->ic_nt * TS2 * 4);
+    c->r_ibjnt = pl.take((size_t)c->ic_nt * 4);
+    c->r_ibjoff = pl.take((size_t)c->ic_nt * 8);
+    c->r_ivec = pl.take(4 * ld * 8);
+    c->r_icagg = pl.take((size_t)g.nt0d * TS * 8);
+    c->r_idagg = pl.take((size_t)g.nt0d * TS * 8);
+    c->r_iqpart = pl.take((size_t)c->ic_nq * 8);
+    c->r_ipart = pl.take((size_t)c->ic_nt * 2 * 8);
+  }
   c->total = pl.top + 256;
   return SFCDD_OK;
 }
@@ -642,6 +704,25 @@ void bind(sfcdd_ctx* c) {
   c->active = at<int32_t>(c, c->r_active);
   c->status = at<int32_t>(c, c->r_status);
   c->gout = at<double>(c, c->r_gout);
+  if (c->coarse_iter) {
+    c->ideg = at<int32_t>(c, c->r_ideg);
+    c->icol = at<int32_t>(c, c->r_icol);
+    c->ival = at<double>(c, c->r_ival);
+    c->ibjt = at<double>(c, c->r_ibjt);
+    c->ibjm = at<float>(c, c->r_ibjm);
+    c->ibjnt = at<int32_t>(c, c->r_ibjnt);
+    c->ibjoff = at<int64_t>(c, c->r_ibjoff);
+    double* v = at<double>(c, c->r_ivec);
+    c->ir = v;
+    c->ip = v + c->ic_ld;
+    c->iq = v + 2 * c->ic_ld;
+    c->iz1 = v + 3 * c->ic_ld;
+    c->icagg = at<double>(c, c->r_icagg);
+    c->idagg = at<double>(c, c->r_idagg);
+    c->iqpart = at<double>(c, c->r_iqpart);
+    c->ipart = at<double>(c, c->r_ipart);
+    c->iflag = c->status + 4;
+  }
 }
 
 // Batched left-looking factorisation: each workgroup keeps its output tile in
@@ -677,11 +758,50 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
 // d0 = A_0^{-1} c0 = X_0^T (X_0 c0) with X_0 = L_0^{-1} (per grid; FP32
 // entries in the second half of the X0 region beside FP32 subdomain factors,
 // FP64 otherwise).
+// Second level of the inner CG: d = A_agg^{-1} c with the dense aggregated
+// matrix's inverse factor (FP32 beside FP32 subdomain factors).
+void ic_second_level(sfcdd_ctx* c) {
+  BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
+  if (c->coarse_x32)
+    launch_coarse_apply<float>(1, c->max_nt0, bm, c->dc_n, c->dc_doff,
+                               reinterpret_cast<const float*>(c->X0) + c->ctiles * TS2, c->icagg, c->cy,
+                               c->cpart, c->idagg, c->iflag, c->stream);
+  else
+    launch_coarse_apply<double>(1, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->icagg, c->cy, c->cpart,
+                                c->idagg, c->iflag, c->stream);
+}
+
+// Iterative coarse solve d0 = A_0^{-1} b with b in c0 (single grid): inner
+// CG on the sparse A_0, at most `steps` steps after the first direction; the
+// device stops it at relative residual coarse_tol.  mask: the outer grid's
+// flag (a grid that is not updating skips the solve).
+void ic_solve(sfcdd_ctx* c, int steps, const int32_t* mask) {
+  const hipStream_t s = c->stream;
+  const int64_t n0 = c->grid[0].desc.N0;
+  const int nt = c->ic_nt;
+  launch_ic_begin(mask, c->iflag, c->scal, s);
+  launch_ic_update(1, 0, n0, nt, c->ic_nq, c->iqpart, c->scal, c->c0, c->d0, c->ir, c->ip, c->iq, c->ibjm,
+                   c->iz1, c->icagg, c->ipart, c->iflag, s);
+  ic_second_level(c);
+  launch_ic_dir(1, 0, n0, nt, c->ic_tol2, c->ipart, c->icagg, c->idagg, c->scal, c->iz1, c->ip, c->iflag, s);
+  for (int it = 1; it <= steps; ++it) {
+    launch_ic_spmv(c->ic_ld, c->ideg, c->icol, c->ival, c->ip, c->iq, c->iqpart, c->iflag, s);
+    launch_ic_update(0, it, n0, nt, c->ic_nq, c->iqpart, c->scal, c->c0, c->d0, c->ir, c->ip, c->iq, c->ibjm,
+                     c->iz1, c->icagg, c->ipart, c->iflag, s);
+    ic_second_level(c);
+    launch_ic_dir(0, it, n0, nt, c->ic_tol2, c->ipart, c->icagg, c->idagg, c->scal, c->iz1, c->ip, c->iflag, s);
+  }
+}
+
 void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) {
   ProfScope ps(c, SFCDD_K_COARSE);
   const Batch B = c->batch();
   BatchMeta bm{c->dc_nt, c->dc_off, c->dc_xoff, c->dc_poff};
   launch_restrict(B, c->max_cblock, v, c->c0, c->stream);
+  if (c->coarse_iter) {
+    ic_solve(c, c->ic_k, mask);
+    return;
+  }
   if (c->coarse_x32)
     launch_coarse_apply<float>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff,
                                reinterpret_cast<const float*>(c->X0) + c->ctiles * TS2, c->c0, c->cy,
@@ -800,12 +920,28 @@ void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask)
   launch_combine(B, COMB_ADD_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y + F (r - A y)
 }
 
+// Inner step statistics of the latest iterative coarse solve, from the
+// scalars just read back: the most steps seen, and a solve that ran out of
+// its budget doubles the budget of the later ones.
+constexpr int IC_TRIAL_STEPS = 500, IC_MAX_STEPS = 4000;
+void ic_note(sfcdd_ctx* c) {
+  if (!c->coarse_iter) return;
+  const int its = (int)c->host_scal[IC_ITS];
+  const bool conv = c->host_scal[IC_CONV] != 0.0;
+  c->ic_max_steps = std::max(c->ic_max_steps, its);
+  if (!conv && its >= c->ic_k && c->ic_k > 0) {
+    ++c->ic_unconv;
+    c->ic_k = std::min(2 * c->ic_k, IC_MAX_STEPS);
+  }
+}
+
 // Copies the per-grid scalars to the pinned host buffer.
 sfcdd_status read_scal(sfcdd_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal, sizeof(double) * c->G * S_COUNT,
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->active_in_flight = false;
+  ic_note(c);
   return SFCDD_OK;
 }
 double hs(sfcdd_ctx* c, int g, int slot) { return c->host_scal[(size_t)g * S_COUNT + slot]; }
@@ -929,6 +1065,16 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     std::memcpy(q + 4 * (size_t)G, c->c_n.data(), 4 * (size_t)G);
     HIPCHK(c, hipMemcpyAsync(c->ws + c->r_cmeta.off, cimg.data(), c->r_cmeta.bytes, hipMemcpyHostToDevice, s));
   }
+  // block-diagonal part of the iterative coarse solve: ic_nt single-tile matrices
+  std::vector<int32_t> bjnt;
+  std::vector<int64_t> bjoff;
+  if (c->coarse_iter) {
+    bjnt.assign(c->ic_nt, 1);
+    bjoff.resize(c->ic_nt);
+    for (int t = 0; t < c->ic_nt; ++t) bjoff[t] = t;
+    HIPCHK(c, hipMemcpyAsync(c->ibjnt, bjnt.data(), 4 * (size_t)c->ic_nt, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->ibjoff, bjoff.data(), 8 * (size_t)c->ic_nt, hipMemcpyHostToDevice, s));
+  }
   HIPCHK(c, hipMemsetAsync(c->status, 0, 64, s));
   HIPCHK(c, hipStreamSynchronize(s));
 
@@ -992,6 +1138,19 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
                            G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
     }
+    if (c->coarse_iter) {
+      // the sparse rows of A_0 (one workgroup per coarse block), then the
+      // explicit inverses of its diagonal 64-blocks
+      const int64_t n0 = c->grid[0].desc.N0;
+      HIPCHK(c, hipMemsetAsync(c->ideg, 0, c->r_ideg.bytes, cs));
+      launch_coarse_ell(B, n0, c->nbr, c->ic_kw, c->ic_ld, c->ideg, c->icol, c->ival, c->status + 2, cs);
+      HIPCHK(c, hipMemsetAsync(c->ibjt, 0, c->r_ibjt.bytes, cs));
+      launch_bj_extract(n0, c->ic_ld, c->ideg, c->icol, c->ival, c->ibjt, cs);
+      launch_potrf_full<double>(c->ic_nt, c->ibjnt, c->ibjoff, c->ibjt, c->status + 3, false, cs);
+      launch_bj_form(c->ic_nt, c->ibjt, c->ibjm, cs);
+      HIPCHK(c, hipMemsetAsync(c->icagg, 0, c->r_icagg.bytes, cs));
+      HIPCHK(c, hipMemsetAsync(c->idagg, 0, c->r_idagg.bytes, cs));
+    }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(cev1, cs));
     HIPCHK(c, hipEventRecord(join, cs));
@@ -1016,7 +1175,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   double fine_work = 0.0;
   for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
-  const double coarse_work = G == 1 ? std::pow((double)c->N0tot, 3.0) : 0.0;
+  const double coarse_work = G == 1 ? std::pow((double)c->max_N0, 3.0) : 0.0;
   const bool pair = c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work;
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
@@ -1062,11 +1221,30 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.trsv_waves = c->trsv_waves;
   I.coarse_fp32 = c->coarse32 ? 1 : 0;
   I.coarse_inv_fp32 = c->coarse_x32 ? 1 : 0;
+  I.coarse_iterative = c->coarse_iter ? 1 : 0;
+  I.N0d = c->max_N0;
+  I.ell_width = c->ic_kw;
 
-  int32_t stat[2] = {0, 0};
-  HIPCHK(c, hipMemcpy(stat, c->status, 8, hipMemcpyDeviceToHost));
+  int32_t stat[4] = {0, 0, 0, 0};
+  HIPCHK(c, hipMemcpy(stat, c->status, 16, hipMemcpyDeviceToHost));
   if (stat[0] != 0) FAIL(c, SFCDD_ENOTSPD, "a local matrix is not positive definite");
   if (stat[1] != 0) FAIL(c, SFCDD_ENOTSPD, "a coarse matrix is not positive definite");
+  if (stat[2] != 0)
+    FAIL(c, SFCDD_EINVAL, "a coarse block couples to more than %d blocks (iterative coarse solver)", c->ic_kw);
+  if (stat[3] != 0) FAIL(c, SFCDD_ENOTSPD, "a diagonal block of the coarse matrix is not positive definite");
+  if (c->coarse_iter) {
+    // size the inner step budget with a trial solve on a fixed right-hand side
+    const int64_t n0 = c->grid[0].desc.N0;
+    launch_ic_trial(n0, c->ic_ld, c->c0, s);
+    ic_solve(c, IC_TRIAL_STEPS, nullptr);
+    HIPCHK(c, hipGetLastError());
+    double sc[S_COUNT];
+    HIPCHK(c, hipMemcpyAsync(sc, c->scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const int its = (int)sc[IC_ITS];
+    c->ic_k = sc[IC_CONV] != 0.0 ? std::min(IC_MAX_STEPS, its + its / 4 + 4) : IC_TRIAL_STEPS;
+    I.coarse_steps = c->ic_k;
+  }
   return SFCDD_OK;
 }
 
@@ -1245,6 +1423,8 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   LIVE(c);
   if (!b_in || !x_io || b_in == x_io) FAIL(c, SFCDD_EINVAL, "b and x must be distinct non-NULL device vectors");
   if (!(rtol > 0.0) || max_iter < 0) FAIL(c, SFCDD_EINVAL, "need rtol > 0 and max_iter >= 0");
+  c->ic_max_steps = 0;
+  c->ic_unconv = 0;
   const bool plain = (method & SFCDD_SOLVE_PLAIN_START) != 0;
   const bool energy = (method & SFCDD_SOLVE_ENERGY) != 0;
   const bool recursive = (method & SFCDD_SOLVE_RECURSIVE) != 0 || energy;
@@ -1334,6 +1514,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     if (c->noalloc) HIPCHK(c, hipStreamSynchronize(s));  // pageable target: the copy is complete
     else HIPCHK(c, hipEventSynchronize(c->ev_rb));
     c->active_in_flight = false;
+    ic_note(c);
     for (int g = 0; g < G; ++g) rr[g] = hs(c, g, S_RR);
     return SFCDD_OK;
   };
@@ -1425,7 +1606,9 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       }
     }
   } else {
-    const bool flex = method == SFCDD_FCG;
+    // an iterative coarse solve varies the preconditioner slightly between
+    // applications: the flexible update keeps the directions conjugate
+    const bool flex = method == SFCDD_FCG || c->coarse_iter;
     const int fin_rz = flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT;
     // r = b - A x
     spmv(c, 2, x, r, b, c->partials);
@@ -1541,6 +1724,8 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   inf.iterations = itmax;
   inf.restarts = restarts;
   inf.rel_residual = worst;
+  inf.coarse_steps = c->ic_max_steps;
+  inf.coarse_unconverged = c->ic_unconv;
   if (info) *info = inf;
   if (!conv && stag_only)
     FAIL(c, SFCDD_ESTAGNATED, "true residual stagnated at %.3e above rtol %.1e after %d iterations "
@@ -1617,6 +1802,64 @@ sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, 
     if (omega_host) omega_host[i] = h.omega[i];
   }
   if (q_out) *q_out = h.desc.q;
+  return SFCDD_OK;
+}
+
+sfcdd_status sfcdd_ct_layout(int32_t d, int32_t L, int32_t phat, int32_t capacity, int32_t* ngrids,
+                             int32_t* levels, int32_t* layer, double* weight, int32_t* P) {
+  sfcdd_ctx* none = nullptr;
+  if (!ngrids) FAIL(none, SFCDD_EINVAL, "ngrids is NULL");
+  if (d < 1 || d > MAXD) FAIL(none, SFCDD_EINVAL, "d = %d out of range 1..%d", d, MAXD);
+  if (L < 1 || L > 60) FAIL(none, SFCDD_EINVAL, "L = %d out of range 1..60", L);
+  if (phat < 1) FAIL(none, SFCDD_EINVAL, "phat = %d must be >= 1", phat);
+  // layer i: the level vectors with l_j >= 1 and |l|_1 = L + d - 1 - i, in
+  // lexicographic order (first entry slowest)
+  std::vector<int32_t> lv;
+  std::vector<int32_t> lay;
+  std::vector<int32_t> cur(d);
+  for (int i = 0; i < d; ++i) {
+    const int total = L + d - 1 - i;
+    // odometer over the first d - 1 entries; the last takes the rest
+    std::function<void(int, int)> rec = [&](int k, int left) {
+      if (k == d - 1) {
+        if (left >= 1) {
+          cur[k] = left;
+          lv.insert(lv.end(), cur.begin(), cur.end());
+          lay.push_back(i);
+        }
+        return;
+      }
+      for (int v = 1; v <= left - (d - 1 - k); ++v) {
+        cur[k] = v;
+        rec(k + 1, left - v);
+      }
+    };
+    rec(0, total);
+  }
+  const int64_t n = (int64_t)lay.size();
+  if (n > INT32_MAX) FAIL(none, SFCDD_EOVERFLOW, "more than 2^31 grids");
+  *ngrids = (int32_t)n;
+  if (!levels && !layer && !weight && !P) return SFCDD_OK;
+  if (capacity < n) FAIL(none, SFCDD_ENOMEM, "capacity %d < %lld grids", capacity, (long long)n);
+  for (int64_t k = 0; k < n; ++k) {
+    const int i = lay[k];
+    // binom(d - 1, i) exactly, then the sign of the layer
+    double b = 1.0;
+    for (int t = 1; t <= i; ++t) b = b * (double)(d - t) / (double)t;
+    const double w = (i % 2 ? -1.0 : 1.0) * std::round(b);
+    // P = phat 2^(d-1-i) (eq. Pchoice), at most the grid's point count
+    int64_t Pk = (int64_t)phat << (d - 1 - i);
+    int64_t N = 1;
+    for (int j = 0; j < d; ++j) {
+      const int64_t nj = (int64_t(1) << lv[k * d + j]) - 1;
+      N = N > INT64_MAX / nj ? INT64_MAX : N * nj;
+    }
+    Pk = std::min<int64_t>(std::min<int64_t>(Pk, N), INT32_MAX);
+    if (levels) std::memcpy(levels + k * d, lv.data() + k * d, sizeof(int32_t) * d);
+    if (layer) layer[k] = i;
+    if (weight) weight[k] = w;
+    if (P) P[k] = (int32_t)std::max<int64_t>(1, Pk);
+  }
   return SFCDD_OK;
 }
 
@@ -1712,6 +1955,7 @@ sfcdd_status sfcdd_get_kernel_time(sfcdd_ctx* c, int32_t kind, double* total_ms,
 sfcdd_status sfcdd_get_info(sfcdd_ctx* c, sfcdd_info* info) {
   if (!c || !info) FAIL(c, SFCDD_EINVAL, "NULL argument");
   *info = c->info;
+  info->coarse_steps = c->ic_k;
   return SFCDD_OK;
 }
 

@@ -6,39 +6,33 @@ i = 0 .. d-1) get P = Phat 2^(d-1-i) subdomains (eq. Pchoice; at most the
 grid's size) and the weight (-1)^i binom(d-1, i) (eq. combi).  The grids are
 independent, so one setup and one solve cover all of them; the combined
 solution is evaluated at arbitrary points by the library's combination
-kernel (multilinear evaluation of every grid, summed in a fixed order).
+kernel (multilinear evaluation of every grid, summed in a fixed order).  The
+layout (level vectors, layers, weights, subdomain counts) comes from the
+library's sfcdd_ct_layout; this module only marshals.
 """
 from __future__ import annotations
 
 import ctypes
 from fractions import Fraction
-from math import comb
-from typing import List, Tuple
 
 import numpy as np
 
 
-def _layer(d: int, total: int) -> List[Tuple[int, ...]]:
-    """Level vectors with l_j >= 1 and |l|_1 = total, lexicographic."""
-    if d == 1:
-        return [(total,)] if total >= 1 else []
-    out = []
-    for v in range(1, total - (d - 1) + 1):
-        out.extend((v,) + rest for rest in _layer(d - 1, total - v))
-    return out
-
-
 def ct_layout(d: int, L: int, phat: int = 1):
     """[(level vector, layer i, weight, P)] of the level-L combination in d
-    dimensions: layers |l|_1 = L + d - 1 - i, weight (-1)^i binom(d-1, i),
-    P = Phat 2^(d-1-i) capped at the grid's size."""
-    out = []
-    for i in range(d):
-        w = float((-1) ** i * comb(d - 1, i))
-        for lv in _layer(d, L + d - 1 - i):
-            N = int(np.prod([(1 << l) - 1 for l in lv]))
-            out.append((lv, i, w, max(1, min(phat * (1 << (d - 1 - i)), N))))
-    return out
+    dimensions, from the library's sfcdd_ct_layout (layers |l|_1 = L + d - 1 - i,
+    weight (-1)^i binom(d-1, i), P = Phat 2^(d-1-i) capped at the grid's
+    size)."""
+    from . import _check, lib
+    n = ctypes.c_int32()
+    _check(lib().sfcdd_ct_layout(int(d), int(L), int(phat), 0, ctypes.byref(n), None, None, None, None))
+    G = n.value
+    lv = (ctypes.c_int32 * (G * d))()
+    lay = (ctypes.c_int32 * G)()
+    w = (ctypes.c_double * G)()
+    P = (ctypes.c_int32 * G)()
+    _check(lib().sfcdd_ct_layout(int(d), int(L), int(phat), G, ctypes.byref(n), lv, lay, w, P))
+    return [(tuple(lv[k * d:(k + 1) * d]), int(lay[k]), float(w[k]), int(P[k])) for k in range(G)]
 
 
 class CombinationTechnique:

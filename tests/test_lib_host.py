@@ -127,6 +127,32 @@ def test_noalloc_setup_rejects_oversize_before_any_device_work():
     assert str(m.NOALLOC_WORKSPACE_BYTES) in msg and "allocation-free" in msg
 
 
+def test_iterative_coarse_rule_and_validation():
+    """The iterative coarse solver keeps the four-levels-coarser rule uncapped
+    (q = 64 on the 8.26 M-unknown grid with 4096 subdomains, where the dense
+    solver caps it at 4), allows coarse sizes up to 2^22, validates its
+    tolerance, and is refused for batches."""
+    import ctypes
+    kw = dict(levels=(8, 8, 7), P=4096, gamma=Fraction(1, 8))
+    assert m.partition_host(**kw)[3] == 4
+    assert m.partition_host(coarse_solver="iterative", **kw)[3] == 64
+    assert m.partition_host(levels=(10, 10), P=1024, gamma=Fraction(1, 4), coarse_solver="iterative")[3] == 32
+    with pytest.raises(m.SfcddError) as e:
+        m.workspace_size(coarse_solver="iterative", coarse_tol=1.5, **kw)
+    assert e.value.status == m.EINVAL
+    with pytest.raises(m.SfcddError) as e:        # dense coarse size limit
+        m.workspace_size(levels=(8, 8, 7), P=4096, gamma=Fraction(1, 8), q=64)
+    assert e.value.status == m.EINVAL
+    arr = (m.Params * 2)()
+    keep = []
+    for k in range(2):
+        prm, kp = m.make_params(levels=(5, 5), P=8, gamma=Fraction(1, 4), coarse_solver="iterative")
+        arr[k] = prm
+        keep.append(kp)
+    n = ctypes.c_size_t()
+    assert m.lib().sfcdd_workspace_size_batch(2, arr, ctypes.byref(n)) == m.EINVAL
+
+
 def test_workspace_grows_with_factor_precision():
     a = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp32")
     b = m.workspace_size(levels=(7, 6, 5), P=256, gamma=Fraction(1, 2), factor_dtype="fp64")
