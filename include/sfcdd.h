@@ -117,7 +117,9 @@ typedef struct {
                                 at every application (see sfcdd_setup); q = 0 takes
                                 the rule uncapped; qP <= 2^22                          */
   double coarse_tol;         /* SFCDD_COARSE_ITERATIVE: relative residual of the inner
-                                CG, 0 = 1e-10                                          */
+                                CG, 0 = 1e-6 (the outer flexible CG absorbs the rest:
+                                on the 8.26 M-unknown grid 1e-4 .. 1e-10 all take the
+                                same outer iteration count)                            */
 } sfcdd_params;
 
 typedef struct {

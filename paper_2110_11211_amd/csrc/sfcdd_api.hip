@@ -496,7 +496,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->layout = params[0].layout;
   c->coarse_iter = params[0].coarse_solver == SFCDD_COARSE_ITERATIVE;
   if (c->coarse_iter) {
-    const double t = params[0].coarse_tol > 0.0 ? params[0].coarse_tol : 1e-10;
+    const double t = params[0].coarse_tol > 0.0 ? params[0].coarse_tol : 1e-6;
     c->ic_tol2 = t * t;
   }
   // batch placement
