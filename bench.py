@@ -189,6 +189,39 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+def factor_digest():
+    """Digest of the sources of the batched factorisation (its stored counter
+    summary is only valid for the code it was measured on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("factor.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2110_11211_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_mfma(kernel_file):
+    """MFMA-busy fraction and rates from the committed counter summary, or None
+    when it is missing or was taken on other factorisation sources."""
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != factor_digest():
+        return None
+    try:
+        return {"mfma_busy": float(vals["mfma_busy"]), "executed_tflops": float(vals["executed_tflops"]),
+                "useful_tflops": float(vals["useful_tflops"]),
+                "lds_conflict_fraction": float(vals["lds_conflict_fraction"]), "source": kernel_file}
+    except (KeyError, ValueError):
+        return None
+
+
 def stored_traffic(kernel_file):
     """HBM bytes per launch from the committed counter summary, or None when
     the summary is missing or was taken on other kernel sources."""
@@ -668,7 +701,8 @@ def main():
     out["factor"] = {"flops": fflops, "ms": round(factor_ms, 3),
                      "tflops": round(fflops / (factor_ms * 1e-3) / 1e12, 2), "peak_tflops": FP32_MFMA_PEAK_TFLOPS,
                      "frac": round(fflops / (factor_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
-                     "note": "FP32 MFMA; runs concurrently with the coarse setup"}
+                     "note": "FP32 MFMA; runs concurrently with the coarse setup",
+                     "counters": stored_mfma("k_potrf_full_fp32_d3_l7x6x5_P256_mfma.txt")}
     ct_raw = adj_raw = None
     if not args.no_batch:
         out["ct_batch"], ct_raw = ct_batch_report(max(2, args.steps // 2), 1)
