@@ -163,6 +163,10 @@ typedef struct {
                                 per row kept for A_0, coarse_steps the inner CG's
                                 current step budget                                    */
   int32_t N0d, ell_width, coarse_steps;
+  int32_t factor_rows;       /* launch shape of the batched factorisation: row tiles  */
+  int32_t factor_pair;       /*   per panel step, and 1 for two columns per step      */
+  int32_t spmv_points;       /* launch shape of the SpMV: points per thread and step, */
+  int32_t spmv_window;       /*   and points of x staged in LDS per window            */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1
@@ -296,17 +300,45 @@ sfcdd_status sfcdd_get_partition(sfcdd_ctx* ctx, int32_t grid, int32_t* sfc_inde
  * sfcdd_solve (host arrays of ngrids entries, each may be NULL). */
 sfcdd_status sfcdd_get_batch_stats(sfcdd_ctx* ctx, int32_t* iterations, double* rel_residual);
 
-/* Autotuner of the subdomain-solve kernel: times the substitution sweeps with
- * 4, 8 and 16 waves per workgroup on the context's own factors (repeats runs
- * each, 0 = 3, events on the context's stream), keeps the fastest for all
- * later applications, and returns its time per application in *best_ms (may
- * be NULL).  The choice is remembered for the process per launch shape
- * (device, factor precision, local solver, tile count and size of every
- * subdomain): a later call on a context of the same shape takes it without
- * timing and returns the time measured then.  A negative repeats times
- * again (|repeats| runs) regardless.  With the explicit-inverse local solver
- * there is nothing to tune and only the time is measured.  Synchronous. */
+/* The substitution-kernel part of sfcdd_tune (SFCDD_TUNE_TRSV): times the
+ * substitution sweeps with 4, 8 and 16 waves per workgroup on the context's
+ * own factors, keeps the fastest, and returns its time per application in
+ * *best_ms (may be NULL).  Repeats and the per-shape record as in sfcdd_tune.
+ * With the explicit-inverse local solver there is nothing to tune and only
+ * the time is measured.  Synchronous. */
 sfcdd_status sfcdd_autotune(sfcdd_ctx* ctx, int32_t repeats, double* best_ms);
+
+/* Launch shapes chosen by sfcdd_tune and their times (ms) against the default
+ * shapes on the context's own data. */
+typedef struct {
+  int32_t trsv_waves;        /* waves per workgroup of the substitution kernel (4, 8, 16) */
+  int32_t spmv_points;       /* SpMV points per thread and step (1, 2)                    */
+  int32_t spmv_window;       /* SpMV LDS window (256, 512, 1024, 2048 points)             */
+  int32_t factor_rows;       /* row tiles per step of the batched factorisation (2..4)    */
+  int32_t factor_pair;       /* 1: two columns per step                                   */
+  int32_t tuned;             /* SFCDD_TUNE_* bits that were timed now (the rest came
+                                from the per-shape record of earlier tunings, or were
+                                not asked for)                                           */
+  double trsv_ms, trsv_default_ms;    /* one application of the subdomain solves        */
+  double spmv_ms, spmv_default_ms;    /* one SpMV y = A x                               */
+  double setup_ms, setup_default_ms;  /* one whole setup (Alg. 1 and the factorisations) */
+} sfcdd_tuning;
+enum { SFCDD_TUNE_TRSV = 1, SFCDD_TUNE_SPMV = 2, SFCDD_TUNE_SETUP = 4, SFCDD_TUNE_ALL = 7 };
+
+/* Autotuner of the launch shapes (the `what` bits): the substitution kernel's
+ * waves per workgroup (4, 8, 16); the SpMV's points per thread and LDS window
+ * (2 x 4 shapes); and the batched factorisation's row tiles per panel step
+ * (2, 3, 4; 2, 3 with FP64 factors) with one or two columns per step, each
+ * candidate timed with events on the context's stream (repeats runs each,
+ * 0 = 3; the factorisation shapes by repeating the whole setup of this
+ * context, which is left set up with the winner).  The fastest shapes are used
+ * by this context from then on and recorded for the process per launch shape
+ * (device, precision, grid sizes, subdomain sizes): every later setup of the
+ * same shape starts from them, and a later sfcdd_tune call on such a context
+ * returns the recorded choice and times without timing again.  A negative
+ * repeats times again (|repeats| runs) regardless.  report: host, may be
+ * NULL.  Synchronous. */
+sfcdd_status sfcdd_tune(sfcdd_ctx* ctx, int32_t repeats, int32_t what, sfcdd_tuning* report);
 
 /* The same partition computed on the host alone, before any setup (no GPU
  * needed): ta[P], Ni[P], omega[P] and q_out as in sfcdd_get_partition, each

@@ -42,7 +42,7 @@ EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", 
            "sfcdd_apply_precond", "sfcdd_matvec", "sfcdd_solve", "sfcdd_grad_coeff",
            "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
            "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_read_probe",
-           "sfcdd_ct_combine", "sfcdd_ct_layout", "sfcdd_destroy", "sfcdd_last_error"]
+           "sfcdd_ct_combine", "sfcdd_ct_layout", "sfcdd_tune", "sfcdd_destroy", "sfcdd_last_error"]
 KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
 
 
@@ -78,7 +78,21 @@ class Info(ctypes.Structure):
                 ("setup_ms", ctypes.c_double * 6), ("ngrids", ctypes.c_int32),
                 ("trsv_waves", ctypes.c_int32), ("coarse_fp32", ctypes.c_int32),
                 ("coarse_inv_fp32", ctypes.c_int32), ("coarse_iterative", ctypes.c_int32),
-                ("N0d", ctypes.c_int32), ("ell_width", ctypes.c_int32), ("coarse_steps", ctypes.c_int32)]
+                ("N0d", ctypes.c_int32), ("ell_width", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
+                ("factor_rows", ctypes.c_int32), ("factor_pair", ctypes.c_int32),
+                ("spmv_points", ctypes.c_int32), ("spmv_window", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("trsv_waves", ctypes.c_int32), ("spmv_points", ctypes.c_int32),
+                ("spmv_window", ctypes.c_int32), ("factor_rows", ctypes.c_int32),
+                ("factor_pair", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("trsv_ms", ctypes.c_double), ("trsv_default_ms", ctypes.c_double),
+                ("spmv_ms", ctypes.c_double), ("spmv_default_ms", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("setup_default_ms", ctypes.c_double)]
+
+
+TUNE = {"trsv": 1, "spmv": 2, "setup": 4, "all": 7}
 
 
 _lib = None
@@ -102,6 +116,7 @@ def lib() -> ctypes.CDLL:
     L.sfcdd_setup_noalloc.argtypes = [P(Params), vp, P(vp)]
     L.sfcdd_get_batch_stats.argtypes = [vp, P(i32), P(dbl)]
     L.sfcdd_autotune.argtypes = [vp, i32, P(dbl)]
+    L.sfcdd_tune.argtypes = [vp, i32, i32, P(Tuning)]
     L.sfcdd_apply_precond.argtypes = [vp, vp, vp]
     L.sfcdd_matvec.argtypes = [vp, vp, vp]
     L.sfcdd_solve.argtypes = [vp, vp, vp, dbl, i32, i32, dbl, P(SolveInfo)]
@@ -455,6 +470,22 @@ def _autotune(self, repeats: int = 5):
 
 
 SFCSchwarz.autotune = _autotune
+
+
+def _tune(self, what="all", repeats: int = 3) -> dict:
+    """Autotunes the launch shapes (sfcdd_tune; what: "trsv", "spmv", "setup",
+    "all" or a list of them) on this context; returns the chosen shapes and
+    their times against the defaults (ms)."""
+    bits = TUNE[what] if isinstance(what, str) else sum(TUNE[w] for w in what)
+    rep = Tuning()
+    _check(lib().sfcdd_tune(self.ctx, int(repeats), int(bits), ctypes.byref(rep)), self.ctx)
+    inf = Info()
+    _check(lib().sfcdd_get_info(self.ctx, ctypes.byref(inf)), self.ctx)
+    self._info = inf
+    return {k: getattr(rep, k) for k, _ in Tuning._fields_}
+
+
+SFCSchwarz.tune = _tune
 
 from .autograd import PoissonSolve, solve_poisson  # noqa: E402,F401
 from .ct import CombinationTechnique  # noqa: E402,F401

@@ -18,16 +18,18 @@ namespace sfcdd {
 // grid of blocks is fixed, so the sums are deterministic.
 // D > 0: every grid has dimension D (compile-time neighbour count).  A
 // block takes one contiguous chunk of its range and walks it in windows of
-// SPMV_WIN points: the window's x is staged in LDS (one coalesced read), and
-// a neighbour inside the window (about 90% of them for windows of 2048
-// points of a Hilbert- or Z-ordered grid) is read from there, the rest from
-// memory.  Each thread takes U points of the window per step and issues all
-// their neighbour-index loads before their gathers.  The neighbour table is
-// streamed once per product (non-temporal loads).  The chunks are dealt so
-// that each of the 8 XCDs (which receive the workgroups round-robin) works on
-// a contiguous eighth of the curve, where the neighbours outside a window
-// mostly lie.  D = 0: any mix of dimensions, one point per thread and step,
-// no staging.
+// `win` points (at most SPMV_WIN): the window's x is staged in LDS (one
+// coalesced read), and a neighbour inside the window (80-90% of them for
+// windows of 256-2048 points of a Hilbert- or Z-ordered grid) is read from
+// there, the rest from memory.  Each thread takes U points of the window per
+// step and issues all their neighbour-index loads before their gathers.  The
+// neighbour table is streamed once per product (non-temporal loads).  The
+// chunks are dealt so that each of the 8 XCDs (which receive the workgroups
+// round-robin) works on a contiguous eighth of the curve, where the
+// neighbours outside a window mostly lie.  U and the window are launch
+// shapes of the autotuner (2 and 512 by default: the fastest measured on
+// the 8.26 M-unknown grid).  D = 0: any mix of dimensions, one point per
+// thread and step, no staging.
 constexpr int SPMV_WIN = 2048;
 
 template <int MODE, int D, int U>
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const double* __restrict__ b,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ partials, int win) {
   __shared__ double sh[16];
   __shared__ double xw[D > 0 ? SPMV_WIN : 1];
   constexpr bool PERGRID = MODE == 1 || MODE == 2;
@@ -57,8 +59,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
   const int c1 = (int)min((int64_t)hi, (int64_t)c0 + chunk);
   const int bs = blockDim.x;
   if (D > 0) {
-    for (int w0 = c0; w0 < c1; w0 += SPMV_WIN) {
-      const int w1 = min(c1, w0 + SPMV_WIN);
+    for (int w0 = c0; w0 < c1; w0 += win) {
+      const int w1 = min(c1, w0 + win);
       __syncthreads();  // the previous window's readers are done
       for (int e = threadIdx.x; e < w1 - w0; e += bs) xw[e] = x[w0 + e];
       __syncthreads();
@@ -119,25 +121,26 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
   }
 }
 
-// The whole-batch modes use one window per block (a multiple of 8 blocks),
-// the per-grid modes their fixed block count.
+// The whole-batch modes use one window per block (a multiple of 8 blocks, at
+// least 2048 of them when the batch is large enough to fill the device), the
+// per-grid modes their fixed block count.
 template <int MODE, int D>
 void spmv_mode(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
                double* partials, hipStream_t s) {
-  constexpr int UW = D > 0 ? (D <= 4 ? 4 : 2) : 1;
-  if (MODE == 1 || MODE == 2) {
-    hipLaunchKernelGGL((k_spmv<MODE, D, UW>), dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
-                       partials);
-  } else {
-    // windows of up to SPMV_WIN points, but at least 2048 blocks when the
-    // batch is large enough to fill the device
+  const int win = D > 0 ? std::max(64, std::min(SPMV_WIN, B.spmv_win > 0 ? B.spmv_win : 512)) & ~63 : 1;
+  const bool two = D > 0 && B.spmv_u != 1;
+  dim3 grid(B.rbx, B.G);
+  if (MODE == 0 || MODE == 3) {
     int64_t per = RED_THREADS;
-    if (D > 0) per = std::min<int64_t>(SPMV_WIN, std::max<int64_t>(RED_THREADS, ((B.Ntot / 2048) + 63) & ~int64_t(63)));
+    if (D > 0) per = std::min<int64_t>(win, std::max<int64_t>(RED_THREADS, ((B.Ntot / 2048) + 63) & ~int64_t(63)));
     int64_t nb = (B.Ntot + per - 1) / per;
     nb = std::min<int64_t>((nb + 7) & ~int64_t(7), 65535 * 16);
-    hipLaunchKernelGGL((k_spmv<MODE, D, UW>), dim3((unsigned)nb), dim3(RED_THREADS), 0, s, B, nbr, x, y, b,
-                       partials);
+    grid = dim3((unsigned)nb);
   }
+  if (two)
+    hipLaunchKernelGGL((k_spmv<MODE, D, 2>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials, win);
+  else
+    hipLaunchKernelGGL((k_spmv<MODE, D, 1>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials, win);
 }
 
 template <int MODE>

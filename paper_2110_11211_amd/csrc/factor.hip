@@ -638,7 +638,9 @@ __device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__
 // about 380 registers per lane (FP32) it leaves room on a SIMD for a
 // workgroup of the FP32 single-matrix coarse factorisation (120) but not of
 // the FP64 one, and the caller chooses accordingly.
-template <typename T, bool PAIR>
+// R: row tiles per step of the panel and pair updates (the autotuner picks
+// it per launch shape; PanelRows by default).
+template <typename T, bool PAIR, int R>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
@@ -648,7 +650,6 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* F = fac + off[b] * TS2;
-  constexpr int R = PanelRows<T>::v;
   int J = 0;
   if (!PAIR) {
     for (; J < ntb; ++J) {
@@ -747,17 +748,32 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
   hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, kfrom, nparts, maxc,
                      part, nt, off, fac, status);
 }
+template <typename T, bool PAIR, int R>
+static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, hipStream_t s) {
+  const size_t sh = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, R + (PAIR ? 2 : 1)) * TS * LdsV<T>::v * sizeof(T));
+  static bool once = (allow_lds(k_potrf_full<T, PAIR, R>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL((k_potrf_full<T, PAIR, R>), dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
+}
+
+// Largest row count whose LDS staging (rows + 1 or + 2 tiles, at least four)
+// fits the 160 KB of a CU: 4 FP32; FP64 3 for one column, 2 for pairs.
+int potrf_full_max_rows(bool fp64, bool pair) { return fp64 ? (pair ? 2 : 3) : 4; }
+
 template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, bool pair,
-                       hipStream_t s) {
-  const size_t sh1 = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, PanelRows<T>::v + 1) * TS * LdsV<T>::v * sizeof(T));
-  const size_t sh2 = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, PanelRows<T>::v + 2) * TS * LdsV<T>::v * sizeof(T));
-  static bool once = (allow_lds(k_potrf_full<T, false>, sh1), allow_lds(k_potrf_full<T, true>, sh2), true);
-  (void)once;
-  if (pair)
-    hipLaunchKernelGGL((k_potrf_full<T, true>), dim3(nb), dim3(TILE_THREADS), sh2, s, nt, off, fac, status);
-  else
-    hipLaunchKernelGGL((k_potrf_full<T, false>), dim3(nb), dim3(TILE_THREADS), sh1, s, nt, off, fac, status);
+                       hipStream_t s, int rows) {
+  if (rows <= 0) rows = PanelRows<T>::v;
+  rows = std::max(2, std::min(rows, potrf_full_max_rows(sizeof(T) == 8, pair)));
+  if (pair) {
+    if (rows == 2) potrf_full_rows<T, true, 2>(nb, nt, off, fac, status, s);
+    else if (rows == 3) potrf_full_rows<T, true, 3>(nb, nt, off, fac, status, s);
+    else if constexpr (sizeof(T) == 4) potrf_full_rows<T, true, 4>(nb, nt, off, fac, status, s);
+  } else {
+    if (rows == 2) potrf_full_rows<T, false, 2>(nb, nt, off, fac, status, s);
+    else if (rows == 3) potrf_full_rows<T, false, 3>(nb, nt, off, fac, status, s);
+    else if constexpr (sizeof(T) == 4) potrf_full_rows<T, false, 4>(nb, nt, off, fac, status, s);
+  }
 }
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
@@ -1035,7 +1051,7 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*, bool,      \
-                                     hipStream_t);                                                 \
+                                     hipStream_t, int);                                            \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
                                      T*, int32_t*, hipStream_t);                                   \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \

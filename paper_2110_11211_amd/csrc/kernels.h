@@ -58,6 +58,7 @@ struct Batch {
   const uint16_t* cgid;     // grid of each coarse unknown
   const uint16_t* ctgid;    // grid of each coarse tile
   int rbx;                  // reduction blocks per grid
+  int spmv_u, spmv_win;     // SpMV launch shape: points per thread and step, LDS window
 };
 
 __device__ __forceinline__ int grid_of(const Batch& B, const uint16_t* ids, int64_t i) {
@@ -95,9 +96,12 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
                        hipStream_t s);
 // Whole factorisation, one workgroup per matrix (pair: two columns per
 // step; faster alone, but no room beside it for other workgroups).
+// rows: row tiles per step of the panel updates (2 .. potrf_full_max_rows;
+// 0 = the default 3 FP32, 2 FP64).
+int potrf_full_max_rows(bool fp64, bool pair);
 template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, bool pair,
-                       hipStream_t s);
+                       hipStream_t s, int rows = 0);
 // One matrix: sub-diagonal tiles of column J, the diagonal tile of column
 // J + 1, and the split-K partials of column J + 2 (three slots of slot_tiles
 // tiles at part, slot C mod 3 for column C).

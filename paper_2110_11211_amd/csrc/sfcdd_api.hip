@@ -92,6 +92,8 @@ struct sfcdd_ctx {
   int64_t sum_Ni = 0, tiles = 0, parts = 0, xlen = 0, ctiles = 0, cparts = 0, c0len = 0;
   int64_t ctinv = 0;  // tiles of the coarse inversion workspace (all grids)
   int trsv_waves = 16;
+  int spmv_u = 2, spmv_win = 512;   // SpMV launch shape (autotuned)
+  int factor_rows = 0, factor_pair = -1;  // batched factorisation shape (0 / -1: rules)
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
@@ -159,6 +161,8 @@ struct sfcdd_ctx {
     B.cgid = cgid;
     B.ctgid = ctgid;
     B.rbx = rbx;
+    B.spmv_u = spmv_u;
+    B.spmv_win = spmv_win;
     return B;
   }
 };
@@ -731,11 +735,11 @@ void bind(sfcdd_ctx* c) {
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, bool product, int32_t* status, T* part, T* tbuf,
-                  const int64_t* toff, bool pair, hipStream_t s) {
+                  const int64_t* toff, bool pair, hipStream_t s, int rows = 0) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   if (!part) {
     // batch: one workgroup factors a whole matrix
-    launch_potrf_full<T>(nb, nt, off, fac, status, pair, s);
+    launch_potrf_full<T>(nb, nt, off, fac, status, pair, s, rows);
   } else {
     // one matrix: the first diagonal tile, then one step per column (its
     // sub-diagonal tiles, the next diagonal tile, split-K partials two
@@ -1176,13 +1180,16 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   double fine_work = 0.0;
   for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
   const double coarse_work = G == 1 ? std::pow((double)c->max_N0, 3.0) : 0.0;
-  const bool pair = c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work;
+  const bool pair = c->factor_pair >= 0 ? c->factor_pair != 0
+                                         : (c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work);
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
-                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s);
+                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s, c->factor_rows);
   else
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
-                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s);
+                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s, c->factor_rows);
+  c->info.factor_pair = pair ? 1 : 0;
+  c->info.factor_rows = c->factor_rows > 0 ? c->factor_rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
   HIPCHK(c, hipStreamWaitEvent(s, join, 0));
@@ -1222,6 +1229,8 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.coarse_fp32 = c->coarse32 ? 1 : 0;
   I.coarse_inv_fp32 = c->coarse_x32 ? 1 : 0;
   I.coarse_iterative = c->coarse_iter ? 1 : 0;
+  I.spmv_points = c->spmv_u;
+  I.spmv_window = c->spmv_win;
   I.N0d = c->max_N0;
   I.ell_width = c->ic_kw;
 
@@ -1245,6 +1254,246 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     c->ic_k = sc[IC_CONV] != 0.0 ? std::min(IC_MAX_STEPS, its + its / 4 + 4) : IC_TRIAL_STEPS;
     I.coarse_steps = c->ic_k;
   }
+  return SFCDD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the launch shapes.  Each choice depends only on the launch
+// shape it serves and is recorded for the process under a key of that shape:
+// the substitution kernel's waves (device, precision, local solver, tile
+// count and size of every subdomain), the SpMV's points per step and window
+// (device, grid sizes and curves), the batched factorisation's rows per step
+// and column pairing (device, precisions, coarse solver, subdomain sizes and
+// coarse sizes; it is timed as a whole setup, since the factorisation shares
+// the device with the concurrent coarse setup).
+struct TuneRecord {
+  int a = 0, b = 0;
+  double t = 0.0, t_default = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<uint64_t, TuneRecord> g_tune_trsv, g_tune_spmv, g_tune_setup;
+
+struct KeyMix {
+  uint64_t key = 1469598103934665603ull;
+  void operator()(uint64_t v) { key = (key ^ v) * 1099511628211ull; }
+};
+
+uint64_t key_trsv(const sfcdd_ctx* c, int dev) {
+  KeyMix m;
+  m((uint64_t)dev);
+  m((uint64_t)c->fdtype);
+  m((uint64_t)c->local_solver);
+  for (int i = 0; i < c->Ptot; ++i) {
+    m((uint64_t)c->nt[i]);
+    m((uint64_t)c->Ni[i]);
+  }
+  return m.key;
+}
+uint64_t key_spmv(const sfcdd_ctx* c, int dev) {
+  KeyMix m;
+  m((uint64_t)dev);
+  m((uint64_t)c->G);
+  for (int k = 0; k < c->G; ++k) {
+    const GridDesc& g = c->grid[k].desc;
+    m((uint64_t)g.d);
+    m((uint64_t)g.curve);
+    for (int j = 0; j < g.d; ++j) m((uint64_t)g.n[j]);
+  }
+  return m.key;
+}
+uint64_t key_setup(const sfcdd_ctx* c, int dev) {
+  KeyMix m;
+  m(key_trsv(c, dev));
+  m((uint64_t)c->coarse_iter);
+  m((uint64_t)c->coarse_x32);
+  m((uint64_t)c->coarse32);
+  for (int k = 0; k < c->G; ++k) {
+    m((uint64_t)c->grid[k].desc.N0);
+    m((uint64_t)c->grid[k].desc.N0d);
+  }
+  return m.key;
+}
+
+// Shapes recorded by earlier tunings of the same launch shapes (applied at
+// setup, before the factorisation).
+void apply_recorded_shapes(sfcdd_ctx* c) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto t = g_tune_trsv.find(key_trsv(c, dev));
+  if (t != g_tune_trsv.end()) c->trsv_waves = t->second.a;
+  auto v = g_tune_spmv.find(key_spmv(c, dev));
+  if (v != g_tune_spmv.end()) {
+    c->spmv_u = v->second.a;
+    c->spmv_win = v->second.b;
+  }
+  auto f = g_tune_setup.find(key_setup(c, dev));
+  if (f != g_tune_setup.end()) {
+    c->factor_rows = f->second.a;
+    c->factor_pair = f->second.b;
+  }
+}
+
+sfcdd_status setup_device(sfcdd_ctx* c);
+void local_solves(sfcdd_ctx* c, const double* w, int waves, const int32_t* mask);
+
+sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuning* r) {
+  const bool force = repeats < 0;
+  repeats = repeats < 0 ? -repeats : (repeats == 0 ? 3 : repeats);
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  const hipStream_t s = c->stream;
+  hipEvent_t a, b;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  // mean time (ms) of `repeats` runs of f after one warm-up run
+  auto timed = [&](auto&& f, double* ms) -> sfcdd_status {
+    f();
+    HIPCHK(c, hipEventRecord(a, s));
+    for (int k = 0; k < repeats; ++k) f();
+    HIPCHK(c, hipEventRecord(b, s));
+    HIPCHK(c, hipEventSynchronize(b));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, a, b));
+    *ms = t / repeats;
+    return SFCDD_OK;
+  };
+  sfcdd_status st = SFCDD_OK;
+  r->tuned = 0;
+  double* w = c->vec[V_TMP];
+  double* y = c->vec[V_Y];
+  launch_zero(c->Ntot, w, s);
+  // substitution kernel: waves per workgroup
+  if (what & SFCDD_TUNE_TRSV) {
+    const uint64_t key = key_trsv(c, dev);
+    TuneRecord rec;
+    bool have = false;
+    if (!force) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_trsv.find(key);
+      if (it != g_tune_trsv.end()) { rec = it->second; have = true; }
+    }
+    if (!have) {
+      const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
+      const int cand[3] = {16, 8, 4};
+      rec.a = c->trsv_waves;
+      rec.t = 1e300;
+      for (int k = 0; k < ncand && st == SFCDD_OK; ++k) {
+        double ms = 0.0;
+        st = timed([&] { local_solves(c, w, cand[k], nullptr); }, &ms);
+        if (k == 0) rec.t_default = ms;
+        if (ms < rec.t) { rec.t = ms; rec.a = ncand > 1 ? cand[k] : c->trsv_waves; }
+      }
+      if (st == SFCDD_OK) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_trsv[key] = rec;
+      }
+      r->tuned |= SFCDD_TUNE_TRSV;
+    }
+    c->trsv_waves = rec.a;
+    r->trsv_ms = rec.t;
+    r->trsv_default_ms = rec.t_default;
+  }
+  // SpMV: points per thread and step, LDS window
+  if (st == SFCDD_OK && (what & SFCDD_TUNE_SPMV)) {
+    const uint64_t key = key_spmv(c, dev);
+    TuneRecord rec;
+    bool have = false;
+    if (!force) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_spmv.find(key);
+      if (it != g_tune_spmv.end()) { rec = it->second; have = true; }
+    }
+    if (!have) {
+      const int us[2] = {2, 1}, wins[4] = {512, 256, 1024, 2048};
+      rec.t = 1e300;
+      for (int i = 0; i < 2 && st == SFCDD_OK; ++i)
+        for (int j = 0; j < 4 && st == SFCDD_OK; ++j) {
+          Batch B = c->batch();
+          B.spmv_u = us[i];
+          B.spmv_win = wins[j];
+          double ms = 0.0;
+          st = timed([&] { launch_spmv(B, 0, c->nbr, w, y, nullptr, nullptr, s); }, &ms);
+          if (i == 0 && j == 0) rec.t_default = ms;
+          if (ms < rec.t) { rec.t = ms; rec.a = us[i]; rec.b = wins[j]; }
+        }
+      if (st == SFCDD_OK) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_spmv[key] = rec;
+      }
+      r->tuned |= SFCDD_TUNE_SPMV;
+    }
+    c->spmv_u = rec.a;
+    c->spmv_win = rec.b;
+    r->spmv_ms = rec.t;
+    r->spmv_default_ms = rec.t_default;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != SFCDD_OK) return st;
+  // batched factorisation: rows per panel step and column pairing, timed as
+  // whole setups of this context (which ends set up with the winner)
+  if (what & SFCDD_TUNE_SETUP) {
+    const uint64_t key = key_setup(c, dev);
+    TuneRecord rec;
+    bool have = false;
+    if (!force) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_setup.find(key);
+      if (it != g_tune_setup.end()) { rec = it->second; have = true; }
+    }
+    if (!have) {
+      const int saved_rows = c->factor_rows, saved_pair = c->factor_pair;
+      // the default shape (the rules) first, then every explicit one
+      std::vector<std::pair<int, int>> cand{{0, -1}};
+      for (int pr = 0; pr <= 1; ++pr)
+        for (int rw = 2; rw <= potrf_full_max_rows(c->fdtype == SFCDD_FP64, pr != 0); ++rw)
+          cand.emplace_back(rw, pr);
+      rec.t = 1e300;
+      int last = -1;
+      for (size_t k = 0; k < cand.size(); ++k) {
+        c->factor_rows = cand[k].first;
+        c->factor_pair = cand[k].second;
+        double best_k = 1e300;
+        for (int rpt = 0; rpt < std::max(1, std::min(repeats, 2)); ++rpt) {
+          if ((st = setup_device(c)) != SFCDD_OK) {
+            c->factor_rows = saved_rows;
+            c->factor_pair = saved_pair;
+            return st;
+          }
+          best_k = std::min(best_k, c->info.setup_ms[5]);
+        }
+        last = (int)k;
+        if (k == 0) rec.t_default = best_k;
+        // the explicit shape of the default is the one setup_device reports
+        const int rw = k == 0 ? c->info.factor_rows : cand[k].first;
+        const int pr = k == 0 ? c->info.factor_pair : cand[k].second;
+        if (best_k < rec.t) { rec.t = best_k; rec.a = rw; rec.b = pr; }
+      }
+      c->factor_rows = rec.a;
+      c->factor_pair = rec.b;
+      if (last < 0 || !(cand[last].first == rec.a && cand[last].second == rec.b))
+        if ((st = setup_device(c)) != SFCDD_OK) return st;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_setup[key] = rec;
+      }
+      r->tuned |= SFCDD_TUNE_SETUP;
+    } else {
+      c->factor_rows = rec.a;
+      c->factor_pair = rec.b;
+    }
+    r->setup_ms = rec.t;
+    r->setup_default_ms = rec.t_default;
+  }
+  r->trsv_waves = c->trsv_waves;
+  r->spmv_points = c->spmv_u;
+  r->spmv_window = c->spmv_win;
+  r->factor_rows = c->factor_rows > 0 ? c->factor_rows : c->info.factor_rows;
+  r->factor_pair = c->factor_pair >= 0 ? c->factor_pair : c->info.factor_pair;
+  c->info.trsv_waves = c->trsv_waves;
+  c->info.spmv_points = c->spmv_u;
+  c->info.spmv_window = c->spmv_win;
   return SFCDD_OK;
 }
 
@@ -1348,6 +1597,7 @@ sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev
     return SFCDD_EDEVICE;
   }
   *out = c;
+  apply_recorded_shapes(c);
   return setup_device(c);
 }
 
@@ -1866,67 +2116,21 @@ sfcdd_status sfcdd_ct_layout(int32_t d, int32_t L, int32_t phat, int32_t capacit
 sfcdd_status sfcdd_autotune(sfcdd_ctx* c, int32_t repeats, double* best_ms) {
   if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
   LIVE(c);
-  const bool force = repeats < 0;
-  repeats = repeats < 0 ? -repeats : (repeats == 0 ? 3 : repeats);
-  const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
-  // The choice depends only on the launch shapes: the device, the factor
-  // precision and the tile counts and sizes of the subdomains.  It is kept
-  // per shape for the life of the process.
-  static std::mutex mu;
-  static std::map<uint64_t, std::pair<int, double>> tuned;
-  int dev = 0;
-  HIPCHK(c, hipGetDevice(&dev));
-  uint64_t key = 1469598103934665603ull;
-  auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
-  mix((uint64_t)dev);
-  mix((uint64_t)c->fdtype);
-  mix((uint64_t)c->local_solver);
-  for (int i = 0; i < c->Ptot; ++i) {
-    mix((uint64_t)c->nt[i]);
-    mix((uint64_t)c->Ni[i]);
-  }
-  if (ncand > 1 && !force) {
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = tuned.find(key);
-    if (it != tuned.end()) {
-      c->trsv_waves = it->second.first;
-      c->info.trsv_waves = c->trsv_waves;
-      if (best_ms) *best_ms = it->second.second;
-      return SFCDD_OK;
-    }
-  }
-  const hipStream_t s = c->stream;
-  hipEvent_t a, b;
-  HIPCHK(c, hipEventCreate(&a));
-  HIPCHK(c, hipEventCreate(&b));
-  double* w = c->vec[V_TMP];
-  launch_zero(c->Ntot, w, s);
-  int best = c->trsv_waves;
-  double best_t = 1e300;
-  const int cand[3] = {4, 8, 16};
-  for (int k = 0; k < ncand; ++k) {
-    local_solves(c, w, cand[k]);  // warm-up
-    HIPCHK(c, hipEventRecord(a, s));
-    for (int rpt = 0; rpt < repeats; ++rpt) local_solves(c, w, cand[k]);
-    HIPCHK(c, hipEventRecord(b, s));
-    HIPCHK(c, hipEventSynchronize(b));
-    float ms;
-    HIPCHK(c, hipEventElapsedTime(&ms, a, b));
-    const double t = ms / repeats;
-    if (t < best_t) {
-      best_t = t;
-      best = cand[k];
-    }
-  }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  if (ncand > 1) {
-    c->trsv_waves = best;
-    std::lock_guard<std::mutex> lk(mu);
-    tuned[key] = {best, best_t};
-  }
-  c->info.trsv_waves = c->trsv_waves;
-  if (best_ms) *best_ms = best_t;
+  sfcdd_tuning r{};
+  const sfcdd_status st = tune_shapes(c, repeats, SFCDD_TUNE_TRSV, &r);
+  if (st != SFCDD_OK) return st;
+  if (best_ms) *best_ms = r.trsv_ms;
+  return SFCDD_OK;
+}
+
+sfcdd_status sfcdd_tune(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuning* report) {
+  if (!c) FAIL((sfcdd_ctx*)nullptr, SFCDD_EINVAL, "ctx is NULL");
+  LIVE(c);
+  if (what & ~SFCDD_TUNE_ALL) FAIL(c, SFCDD_EINVAL, "what = %d", what);
+  sfcdd_tuning r{};
+  const sfcdd_status st = tune_shapes(c, repeats, what, &r);
+  if (st != SFCDD_OK) return st;
+  if (report) *report = r;
   return SFCDD_OK;
 }
 

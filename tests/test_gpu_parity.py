@@ -482,6 +482,46 @@ def test_autotune_choice_kept_per_shape():
     S2.close()
 
 
+@pytest.mark.parametrize("fdtype", ["fp32", "fp64"])
+def test_tune_launch_shapes_keeps_parity(fdtype):
+    """sfcdd_tune over all launch shapes (substitution waves, SpMV points and
+    window, factorisation rows and column pairing): the choices lie in the
+    candidate sets, the context is left set up with the winning factorisation
+    shape and still matches the oracle, and a second context of the same shape
+    starts from the recorded shapes and gets the recorded times without timing."""
+    levels, P, gamma = (6, 5, 5), 128, Fraction(1, 2)
+    announce("tune", fdtype)
+    kw = dict(levels=levels, P=P, gamma=gamma, factor_dtype=fdtype, curve="hilbert")
+    S1 = m.SFCSchwarz(**kw)
+    rep = S1.tune("all", -2)
+    print(f"tuning {fdtype}: {rep}", flush=True)
+    assert rep["tuned"] == 7
+    assert rep["trsv_waves"] in (4, 8, 16)
+    assert rep["spmv_points"] in (1, 2) and rep["spmv_window"] in (256, 512, 1024, 2048)
+    assert rep["factor_pair"] in (0, 1)
+    assert rep["factor_rows"] in ((2, 3, 4) if fdtype == "fp32" else ((2, 3) if rep["factor_pair"] == 0 else (2,)))
+    for k in ("trsv", "spmv", "setup"):
+        assert 0 < rep[k + "_ms"] <= rep[k + "_default_ms"] * 1.0000001
+    inf = S1.info()
+    assert (inf["factor_rows"], inf["factor_pair"]) == (rep["factor_rows"], rep["factor_pair"])
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma, curve="hilbert")
+    r = uniform_pm1(71, g.N)
+    tol = FP64_TOL if fdtype == "fp64" else FP32_TOL
+    assert relerr(host(S1.apply(dvec(r))), O.apply(r)) <= tol
+    S1.close()
+    S2 = m.SFCSchwarz(**kw)
+    inf2 = S2.info()
+    assert (inf2["factor_rows"], inf2["factor_pair"]) == (rep["factor_rows"], rep["factor_pair"])
+    assert (inf2["spmv_points"], inf2["spmv_window"]) == (rep["spmv_points"], rep["spmv_window"])
+    rep2 = S2.tune("all", 2)
+    assert rep2["tuned"] == 0 and rep2["setup_ms"] == rep["setup_ms"] and rep2["spmv_ms"] == rep["spmv_ms"]
+    f0 = uniform_pm1(72, g.N)
+    x, _ = S2.solve(dvec(f0), rtol=1e-12, method="fcg" if fdtype == "fp32" else "pcg")
+    assert relerr(host(x), exact.solve(g, f0)) <= 1e-9
+    S2.close()
+
+
 def test_caller_workspace_sizes():
     """A caller's workspace of exactly the queried size works at any byte
     offset within its 256 bytes of slack; a buffer one byte short of the need
