@@ -188,12 +188,12 @@ def hbm_read_probe():
     return 4.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
-def source_digest():
-    """Digest of the sources of the substitution kernel: a stored HBM byte
-    count is only valid for the code it was measured on."""
+def source_digest(files=("trsv.hip",)):
+    """Digest of the given kernel sources: a stored HBM byte count is only
+    valid for the code it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("trsv.hip",):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2110_11211_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -202,17 +202,10 @@ def source_digest():
 def factor_digest():
     """Digest of the sources of the batched factorisation (its stored counter
     summary is only valid for the code it was measured on)."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("factor.hip", "common.h"):
-        with open(os.path.join(ROOT, "paper_2110_11211_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return source_digest(("factor.hip", "common.h"))
 
 
-def stored_mfma(kernel_file):
-    """MFMA-busy fraction and rates from the committed counter summary, or None
-    when it is missing or was taken on other factorisation sources."""
+def _profile_fields(kernel_file):
     path = os.path.join(ROOT, "profiles", kernel_file)
     if not os.path.exists(path):
         return None
@@ -222,7 +215,14 @@ def stored_mfma(kernel_file):
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_digest") != factor_digest():
+    return vals
+
+
+def stored_mfma(kernel_file):
+    """MFMA-busy fraction and rates from the committed counter summary, or None
+    when it is missing or was taken on other factorisation sources."""
+    vals = _profile_fields(kernel_file)
+    if vals is None or vals.get("source_digest") != factor_digest():
         return None
     try:
         return {"mfma_busy": float(vals["mfma_busy"]), "executed_tflops": float(vals["executed_tflops"]),
@@ -232,22 +232,18 @@ def stored_mfma(kernel_file):
         return None
 
 
-def stored_traffic(kernel_file):
+LARGE_TRAFFIC = "k_spmv_trsv_fp32_d3_l8x8x7_P4096_traffic.txt"
+
+
+def stored_traffic(kernel_file, key="traffic_bytes_per_launch", digest_key="source_digest",
+                   sources=("trsv.hip",)):
     """HBM bytes per launch from the committed counter summary, or None when
     the summary is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", kernel_file)
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith(" "):
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-    if vals.get("source_digest") != source_digest():
+    vals = _profile_fields(kernel_file)
+    if vals is None or vals.get(digest_key) != source_digest(sources):
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -682,12 +678,15 @@ def main():
             "roofline_spmv": {"kernel": "k_spmv", "bound": "hbm", "achieved": round(krl["spmv_gbps"], 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(krl["spmv_gbps"] / HBM_PEAK_GBS, 4), "target_frac": 0.6,
-                              "avg_launch_ms": krl["avg_spmv_ms"], "algorithmic_bytes_per_launch": krl["spmv_bytes"]},
+                              "avg_launch_ms": krl["avg_spmv_ms"], "algorithmic_bytes_per_launch": krl["spmv_bytes"],
+                              "traffic": stored_traffic(LARGE_TRAFFIC, sources=("apply.hip",))},
             "roofline_local_solve": {"kernel": "k_schwarz_trsv (FP32 factors)", "bound": "hbm",
                                      "achieved": round(krl["local_gbps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": round(krl["local_gbps"] / HBM_PEAK_GBS, 4), "target_frac": 0.6,
                                      "avg_launch_ms": krl["avg_local_ms"],
-                                     "algorithmic_bytes_per_launch": krl["local_bytes"]},
+                                     "algorithmic_bytes_per_launch": krl["local_bytes"],
+                                     "traffic": stored_traffic(LARGE_TRAFFIC, key="trsv_traffic_bytes_per_launch",
+                                                               digest_key="trsv_source_digest")},
             "note": "q = 4 under the dense coarse-size cap N0 <= 16384 (the four-levels-coarser rule gives 64)"}
         ii = bigi["info"]
         out["large_grid"]["iterative_coarse"] = {
