@@ -78,6 +78,8 @@ enum { SFCDD_CURVE_ZORDER = 0, SFCDD_CURVE_HILBERT = 1 };
 enum { SFCDD_COARSE_AUTO = 0, SFCDD_COARSE_FP64 = 1 };
 /* Solver of the coarse problem (see sfcdd_params.coarse_solver). */
 enum { SFCDD_COARSE_DENSE = 0, SFCDD_COARSE_ITERATIVE = 1 };
+/* Elimination order of the subdomain matrices (see sfcdd_params.local_order). */
+enum { SFCDD_ORDER_DIAGONAL = 0, SFCDD_ORDER_CURVE = 1, SFCDD_ORDER_DENSE = 2 };
 /* Flags OR-ed into the method of sfcdd_solve: start from x0 exactly as given
  * and apply the full balanced operator every iteration; stop on the recursive
  * residual alone (see sfcdd_solve). */
@@ -120,6 +122,17 @@ typedef struct {
                                 CG, 0 = 1e-6 (the outer flexible CG absorbs the rest:
                                 on the 8.26 M-unknown grid 1e-4 .. 1e-10 all take the
                                 same outer iteration count)                            */
+  int32_t local_order;       /* elimination order of the subdomain matrices for the
+                                direct solves (Sec. 3.1; A_i^{-1} does not depend on it).
+                                SFCDD_ORDER_DIAGONAL: the points of each subdomain
+                                sorted by a coordinate diagonal sum_j s_j x_j (signs
+                                chosen per subdomain for the narrowest level), ties
+                                in curve order; SFCDD_ORDER_CURVE: curve order.  Both
+                                store and stream only the tile envelope of the factor
+                                (Cholesky creates no entries left of the first
+                                nonzero of a row).  SFCDD_ORDER_DENSE: curve order,
+                                the whole packed triangle.  The explicit-inverse
+                                local solver always uses the last.                    */
 } sfcdd_params;
 
 typedef struct {
@@ -142,8 +155,13 @@ typedef struct {
   int32_t max_Ni, min_Ni;    /* largest / smallest overlapping subdomain               */
   int32_t tile;              /* tile edge of the packed factor layout                  */
   int64_t sum_Ni;            /* sum_i N_i                                              */
-  int64_t factor_bytes;      /* bytes of all subdomain factor tiles                    */
-  int64_t factor_algo_bytes; /* sum_i N_i (N_i + 1) / 2 * sizeof(factor element)      */
+  int64_t factor_bytes;      /* bytes of the subdomain factor tiles stored (the tile
+                                envelopes; the workspace reserves the packed triangles) */
+  int64_t factor_algo_bytes; /* bytes of factor entries one substitution sweep reads:
+                                the off-diagonal envelope tiles and the lower triangles
+                                of the diagonal tiles, padding rows excluded
+                                (sum_i N_i (N_i + 1) / 2 entries with
+                                SFCDD_ORDER_DENSE) times sizeof(factor element)       */
   int64_t coarse_bytes;      /* bytes of the coarse operator tiles                     */
   double setup_ms[6];        /* sfc rank, neighbours, assembly, subdomain factorisation,
                                 coarse setup (runs concurrently with the factorisation),
@@ -167,6 +185,7 @@ typedef struct {
   int32_t factor_pair;       /*   per panel step, and 1 for two columns per step      */
   int32_t spmv_points;       /* launch shape of the SpMV: points per thread and step, */
   int32_t spmv_window;       /*   and points of x staged in LDS per window            */
+  int32_t local_order;       /* elimination order of the subdomain matrices in use      */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1

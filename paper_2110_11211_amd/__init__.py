@@ -36,6 +36,7 @@ NOALLOC_WORKSPACE_BYTES = 256 << 20  # SFCDD_NOALLOC_WORKSPACE_BYTES
 LAYOUT = {"natural": 0, "sfc": 1}
 COARSE_PRECISION = {"auto": 0, "fp64": 1}
 COARSE_SOLVER = {"dense": 0, "iterative": 1}
+LOCAL_ORDER = {"diagonal": 0, "curve": 1, "dense": 2}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
            "sfcdd_setup_noalloc",
@@ -60,7 +61,7 @@ class Params(ctypes.Structure):
                 ("factor_dtype", ctypes.c_int32), ("local_solver", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("curve", ctypes.c_int32),
                 ("coarse_precision", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
-                ("coarse_tol", ctypes.c_double)]
+                ("coarse_tol", ctypes.c_double), ("local_order", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -80,7 +81,8 @@ class Info(ctypes.Structure):
                 ("coarse_inv_fp32", ctypes.c_int32), ("coarse_iterative", ctypes.c_int32),
                 ("N0d", ctypes.c_int32), ("ell_width", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
                 ("factor_rows", ctypes.c_int32), ("factor_pair", ctypes.c_int32),
-                ("spmv_points", ctypes.c_int32), ("spmv_window", ctypes.c_int32)]
+                ("spmv_points", ctypes.c_int32), ("spmv_window", ctypes.c_int32),
+                ("local_order", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -145,7 +147,7 @@ def _check(st: int, ctx=None):
 def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q=0,
                 weighting="omega", variant="balanced", factor_dtype="fp64",
                 local_solver="cholesky", layout="natural", curve="zorder", coarse_precision="auto",
-                coarse_solver="dense", coarse_tol=0.0):
+                coarse_solver="dense", coarse_tol=0.0, local_order="diagonal"):
     """Builds the sfcdd_params struct; returns (struct, keepalive)."""
     g = Fraction(gamma)
     d = len(levels) if levels is not None else len(npts)
@@ -177,6 +179,7 @@ def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q
     prm.coarse_precision = COARSE_PRECISION[coarse_precision]
     prm.coarse_solver = COARSE_SOLVER[coarse_solver]
     prm.coarse_tol = float(coarse_tol)
+    prm.local_order = LOCAL_ORDER[local_order]
     return prm, keep
 
 
@@ -228,7 +231,7 @@ class SFCSchwarz:
                  weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
                  local_solver: str = "cholesky", layout: str = "natural", device="cuda:0",
                  workspace=None, curve: str = "zorder", coarse_precision: str = "auto",
-                 coarse_solver: str = "dense", coarse_tol: float = 0.0):
+                 coarse_solver: str = "dense", coarse_tol: float = 0.0, local_order: str = "diagonal"):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -237,7 +240,7 @@ class SFCSchwarz:
         self.kw = dict(levels=levels, npts=npts, coeff=coeff, P=P, gamma=gamma, q=q, weighting=weighting,
                        variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
                        layout=layout, curve=curve, coarse_precision=coarse_precision,
-                       coarse_solver=coarse_solver, coarse_tol=coarse_tol)
+                       coarse_solver=coarse_solver, coarse_tol=coarse_tol, local_order=local_order)
         prm, self._keep = make_params(**self.kw)
         self._prm = prm
         with torch.cuda.device(self.device):
@@ -384,7 +387,7 @@ class SFCSchwarzBatch(SFCSchwarz):
 
     def __init__(self, grids, weighting: str = "omega", variant: str = "balanced",
                  factor_dtype: str = "fp64", local_solver: str = "cholesky", layout: str = "natural",
-                 device="cuda:0", workspace=None):
+                 device="cuda:0", workspace=None, local_order: str = "diagonal"):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -398,13 +401,14 @@ class SFCSchwarzBatch(SFCSchwarz):
                                     P=gk["P"], gamma=gk.get("gamma", Fraction(1, 2)), q=gk.get("q", 0),
                                     weighting=weighting, variant=variant, factor_dtype=factor_dtype,
                                     local_solver=local_solver, layout=layout,
-                                    curve=gk.get("curve", "zorder"))
+                                    curve=gk.get("curve", "zorder"), local_order=local_order)
             arr[k] = prm
             self._keep.append(keep)
         self._arr = arr
         self.G = G
         self.kw = dict(P=sum(g["P"] for g in grids), weighting=weighting, variant=variant,
-                       factor_dtype=factor_dtype, local_solver=local_solver, layout=layout)
+                       factor_dtype=factor_dtype, local_solver=local_solver, layout=layout,
+                       local_order=local_order)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             self.ws = self._workspace(workspace)

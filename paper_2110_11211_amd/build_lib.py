@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfcdd.so")
-SOURCES = ["setup.hip", "factor.hip", "trsv.hip", "apply.hip", "coarse_iter.hip", "sfcdd_api.hip"]
+SOURCES = ["setup.hip", "order.hip", "factor.hip", "trsv.hip", "apply.hip", "coarse_iter.hip", "sfcdd_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -276,6 +276,32 @@ constexpr size_t diag_lds_bytes() {
   return 2 * (size_t)TS * Pstride<T>::v * sizeof(T);
 }
 
+// Tile addressing of a factor: the packed lower triangle (Tri), or the tile
+// envelope of a subdomain factor (Env: tile row I holds the tiles J = lo[I]
+// .. I at rb[I] + J, lo non-decreasing; every tile left of lo[I] is zero in
+// the matrix and in its Cholesky factor).
+struct Tri {
+  __device__ __forceinline__ int64_t operator()(int I, int J) const { return tri_index(I, J); }
+  __device__ __forceinline__ int first(int) const { return 0; }
+  __device__ __forceinline__ int last(int, int ntb) const { return ntb - 1; }
+};
+// Null tables: the packed triangle.
+struct Env {
+  const int32_t* lo;
+  const int32_t* rb;
+  __device__ __forceinline__ int64_t operator()(int I, int J) const {
+    return rb ? (int64_t)rb[I] + J : tri_index(I, J);
+  }
+  __device__ __forceinline__ int first(int I) const { return lo ? lo[I] : 0; }
+  // last tile row with a tile in column J
+  __device__ __forceinline__ int last(int J, int ntb) const {
+    if (!lo) return ntb - 1;
+    int h = J;
+    while (h + 1 < ntb && lo[h + 1] <= J) ++h;
+    return h;
+  }
+};
+
 // Left-looking: the tile first receives -sum_{K<J} L_JK L_JK^T.  The terms
 // K = kfrom .. J-1 are formed in this workgroup; the terms K < kfrom (single
 // matrix, split-K) were precomputed as nparts partial tiles part[I][c].
@@ -318,25 +344,26 @@ __device__ __forceinline__ void gemm_loop_pf(TileAcc<T>& acc, int k0, int k1, FA
   __syncthreads();
 }
 
-template <typename T, bool DBUF = false>
+template <typename T, bool DBUF = false, typename IX = Tri>
 __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc, const T* __restrict__ part,
                                           T* __restrict__ F, int32_t* __restrict__ status,
-                                          unsigned char* smem_raw) {
+                                          unsigned char* smem_raw, IX ix = IX()) {
   T* sA = reinterpret_cast<T*>(smem_raw);
+  kfrom = max(kfrom, ix.first(J));
   TileAcc<T> acc;
-  acc.load(F + tri_index(J, J) * TS2);
+  acc.load(F + ix(J, J) * TS2);
   for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
   if (DBUF) {
-    auto pj = [&](int K) { return F + tri_index(J, K) * TS2; };
+    auto pj = [&](int K) { return F + ix(J, K) * TS2; };
     gemm_loop_pf<FACTOR_PF, true, T>(acc, kfrom, J, pj, pj, sA, T(-1));
   } else {
     TileRegs<T> ra;
-    if (kfrom < J) ra.load(F + tri_index(J, kfrom) * TS2);
+    if (kfrom < J) ra.load(F + ix(J, kfrom) * TS2);
     for (int K = kfrom; K < J; ++K) {
       __syncthreads();
       ra.store_lds(sA);
       __syncthreads();
-      if (K + 1 < J) ra.load(F + tri_index(J, K + 1) * TS2);
+      if (K + 1 < J) ra.load(F + ix(J, K + 1) * TS2);
       tile_mma<T>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
     }
   }
@@ -349,7 +376,7 @@ __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc
     for (int b2 = 0; b2 < 2; ++b2)
       for (int r = 0; r < 4; ++r) sC[TileAcc<T>::row(a, r) * PS + TileAcc<T>::col(b2)] = acc.c[a][b2][r];
   potrf_inv_tile(sC, sX, status);
-  T* D = F + tri_index(J, J) * TS2;
+  T* D = F + ix(J, J) * TS2;
   for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
     const int i = e / TS, j = e % TS;
     D[e] = j <= i ? sX[i * PS + j] : T(0);
@@ -476,43 +503,61 @@ __device__ __forceinline__ void tile_mma_rows(TileAcc<T> (&acc)[R], int nr, cons
   }
 }
 
+// Rows r < R (of nr) whose first tile column lo[I0 + r] is at most K: a
+// prefix, since lo does not decrease.
+template <int R>
+__device__ __forceinline__ int rows_upto(const int (&lor)[R], int nr, int K) {
+  int n = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) n += (r < nr && lor[r] <= K) ? 1 : 0;
+  return n;
+}
+
 // Sub-diagonal tiles (I0 + r, J), r < nr <= R, of one matrix: A_IJ minus
-// sum_{kfrom<=K<J} L_IK L_JK^T, times L_JJ^{-T}.  LDS: R + 1 tiles at lds.
-template <typename T, int R>
-__device__ __forceinline__ void panel_rows(int J, int kfrom, int I0, int nr, T* __restrict__ F, T* lds) {
+// sum_{kfrom<=K<J} L_IK L_JK^T, times L_JJ^{-T}.  Row I takes the terms
+// K >= lo[I] only (its tiles left of that are zero).  LDS: R + 1 tiles at lds.
+template <typename T, int R, typename IX>
+__device__ __forceinline__ void panel_rows(int J, int kfrom, int I0, int nr, T* __restrict__ F, T* lds, IX ix) {
   constexpr int S = LdsV<T>::v;
   T* sB = lds + R * TS * S;
+  int lor[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) lor[r] = r < nr ? ix.first(I0 + r) : J;
   TileAcc<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (r < nr) acc[r].load(F + tri_index(I0 + r, J) * TS2);
+    if (r < nr) acc[r].load(F + ix(I0 + r, J) * TS2);
+  const int k0 = max(kfrom, lor[0]);
   TileRegs<T> ra[R], rb;
-  if (kfrom < J) {
+  if (k0 < J) {
+    const int n1 = rows_upto<R>(lor, nr, k0);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (r < nr) ra[r].load(F + tri_index(I0 + r, kfrom) * TS2);
-    rb.load(F + tri_index(J, kfrom) * TS2);
+      if (r < n1) ra[r].load(F + ix(I0 + r, k0) * TS2);
+    rb.load(F + ix(J, k0) * TS2);
   }
-  for (int K = kfrom; K < J; ++K) {
+  for (int K = k0; K < J; ++K) {
+    const int nk = rows_upto<R>(lor, nr, K);
     __syncthreads();  // the products of step K - 1 have read the tiles
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (r < nr) ra[r].store_lds(lds + r * TS * S);
+      if (r < nk) ra[r].store_lds(lds + r * TS * S);
     rb.store_lds(sB);
     __syncthreads();
     if (K + 1 < J) {
+      const int n1 = rows_upto<R>(lor, nr, K + 1);
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (r < nr) ra[r].load(F + tri_index(I0 + r, K + 1) * TS2);
-      rb.load(F + tri_index(J, K + 1) * TS2);
+        if (r < n1) ra[r].load(F + ix(I0 + r, K + 1) * TS2);
+      rb.load(F + ix(J, K + 1) * TS2);
     }
-    tile_mma_rows<T, R>(acc, nr, lds, sB, T(-1));  // A_IJ -= L_IK L_JK^T
+    tile_mma_rows<T, R>(acc, nk, lds, sB, T(-1));  // A_IJ -= L_IK L_JK^T
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r < nr) acc[r].store_lds(lds + r * TS * S);
-  stage_tile(sB, F + tri_index(J, J) * TS2);  // L_JJ^{-1}
+  stage_tile(sB, F + ix(J, J) * TS2);  // L_JJ^{-1}
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -520,7 +565,7 @@ __device__ __forceinline__ void panel_rows(int J, int kfrom, int I0, int nr, T* 
       TileAcc<T> out;
       out.zero();
       tile_mma<T>(out, lds + r * TS * S, sB, T(1));  // L_IJ = A_IJ L_JJ^{-T}
-      out.store(F + tri_index(I0 + r, J) * TS2);
+      out.store(F + ix(I0 + r, J) * TS2);
     }
   }
   __syncthreads();
@@ -578,49 +623,64 @@ __device__ __forceinline__ void tile_mma_pair(TileAcc<T> (&acc0)[R], TileAcc<T> 
 // Columns J and J + 1 of rows I0 + r, r < nr <= R (I0 >= J), updated by
 // the columns K < J: A_IJ -= sum L_IK L_JK^T and, for I > J, A_I,J+1 -=
 // sum L_IK L_J+1,K^T, with each row tile L_IK loaded once for both columns;
-// the updated tiles are written back in place.  LDS: R + 2 tiles at lds.
-template <typename T, int R>
-__device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__ F, T* lds) {
+// the updated tiles are written back in place.  Row I takes the terms
+// K >= lo[I]; a row with lo[I] > J has no tile in column J.  LDS: R + 2
+// tiles at lds.
+template <typename T, int R, typename IX>
+__device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__ F, T* lds, IX ix) {
   constexpr int S = LdsV<T>::v;
   T* sB0 = lds + R * TS * S;
   T* sB1 = sB0 + TS * S;
+  int lor[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) lor[r] = r < nr ? ix.first(I0 + r) : J;
+  const int k0 = lor[0];
+  if (k0 >= J) return;  // no row of the group has a term K < J
   const int r1 = I0 > J ? 0 : 1;  // row J has no tile in column J + 1
+  const int lo1 = ix.first(J + 1);
   TileAcc<T> acc0[R], acc1[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r < nr) {
-      acc0[r].load(F + tri_index(I0 + r, J) * TS2);
-      if (r >= r1) acc1[r].load(F + tri_index(I0 + r, J + 1) * TS2);
+      if (lor[r] <= J) acc0[r].load(F + ix(I0 + r, J) * TS2);
+      if (r >= r1) acc1[r].load(F + ix(I0 + r, J + 1) * TS2);
     }
   }
   TileRegs<T> ra[R], rb0, rb1;
+  {
+    const int n1 = rows_upto<R>(lor, nr, k0);
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (r < nr) ra[r].load(F + tri_index(I0 + r, 0) * TS2);
-  rb0.load(F + tri_index(J, 0) * TS2);
-  rb1.load(F + tri_index(J + 1, 0) * TS2);
-  for (int K = 0; K < J; ++K) {
+    for (int r = 0; r < R; ++r)
+      if (r < n1) ra[r].load(F + ix(I0 + r, k0) * TS2);
+    rb0.load(F + ix(J, k0) * TS2);
+    if (k0 >= lo1) rb1.load(F + ix(J + 1, k0) * TS2);
+  }
+  for (int K = k0; K < J; ++K) {
+    const int nk = rows_upto<R>(lor, nr, K);
     __syncthreads();  // the products of step K - 1 have read the tiles
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (r < nr) ra[r].store_lds(lds + r * TS * S);
+      if (r < nk) ra[r].store_lds(lds + r * TS * S);
     rb0.store_lds(sB0);
-    rb1.store_lds(sB1);
+    if (K >= lo1) rb1.store_lds(sB1);
     __syncthreads();
     if (K + 1 < J) {
+      const int n1 = rows_upto<R>(lor, nr, K + 1);
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (r < nr) ra[r].load(F + tri_index(I0 + r, K + 1) * TS2);
-      rb0.load(F + tri_index(J, K + 1) * TS2);
-      rb1.load(F + tri_index(J + 1, K + 1) * TS2);
+        if (r < n1) ra[r].load(F + ix(I0 + r, K + 1) * TS2);
+      rb0.load(F + ix(J, K + 1) * TS2);
+      if (K + 1 >= lo1) rb1.load(F + ix(J + 1, K + 1) * TS2);
     }
-    tile_mma_pair<T, R>(acc0, acc1, nr, r1, lds, sB0, sB1, T(-1));
+    // an active row r >= r1 has lo <= K, and lo[J + 1] <= lo of that row, so
+    // the tile L_J+1,K it takes is one that was loaded
+    tile_mma_pair<T, R>(acc0, acc1, nk, r1, lds, sB0, sB1, T(-1));
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r < nr) {
-      acc0[r].store(F + tri_index(I0 + r, J) * TS2);
-      if (r >= r1) acc1[r].store(F + tri_index(I0 + r, J + 1) * TS2);
+      if (lor[r] <= J) acc0[r].store(F + ix(I0 + r, J) * TS2);
+      if (r >= r1) acc1[r].store(F + ix(I0 + r, J + 1) * TS2);
     }
   }
   __syncthreads();
@@ -643,6 +703,9 @@ __device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__
 template <typename T, bool PAIR, int R>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
+                                                             const int64_t* __restrict__ xoff,
+                                                             const int32_t* __restrict__ tlo,
+                                                             const int32_t* __restrict__ trb,
                                                              T* __restrict__ fac,
                                                              int32_t* __restrict__ status) {
   const int b = blockIdx.x;
@@ -650,28 +713,32 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* F = fac + off[b] * TS2;
+  const int64_t trow = tlo ? xoff[b] / TS : 0;
+  const Env ix{tlo ? tlo + trow : nullptr, tlo ? trb + trow : nullptr};
   int J = 0;
   if (!PAIR) {
     for (; J < ntb; ++J) {
-      diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
+      diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
       __syncthreads();
-      for (int I = J + 1; I < ntb; I += R) panel_rows<T, R>(J, 0, I, min(R, ntb - I), F, sA);
+      const int h = ix.last(J, ntb);
+      for (int I = J + 1; I <= h; I += R) panel_rows<T, R>(J, 0, I, min(R, h + 1 - I), F, sA, ix);
       __syncthreads();
     }
     return;
   }
   for (; J + 1 < ntb; J += 2) {
+    const int h0 = ix.last(J, ntb), h1 = ix.last(J + 1, ntb);
     if (J > 0)
-      for (int I = J; I < ntb; I += R) pair_rows<T, R>(J, I, min(R, ntb - I), F, sA);
-    diag_tile<T, true>(J, J, 0, 0, (const T*)nullptr, F, status, smem_raw);
+      for (int I = J; I <= h1; I += R) pair_rows<T, R>(J, I, min(R, h1 + 1 - I), F, sA, ix);
+    diag_tile<T, true>(J, J, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
     __syncthreads();
-    for (int I = J + 1; I < ntb; I += R) panel_rows<T, R>(J, J, I, min(R, ntb - I), F, sA);
-    diag_tile<T, true>(J + 1, J, 0, 0, (const T*)nullptr, F, status, smem_raw);
+    for (int I = J + 1; I <= h0; I += R) panel_rows<T, R>(J, J, I, min(R, h0 + 1 - I), F, sA, ix);
+    diag_tile<T, true>(J + 1, J, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
     __syncthreads();
-    for (int I = J + 2; I < ntb; I += R) panel_rows<T, R>(J + 1, J, I, min(R, ntb - I), F, sA);
+    for (int I = J + 2; I <= h1; I += R) panel_rows<T, R>(J + 1, J, I, min(R, h1 + 1 - I), F, sA, ix);
   }
   if (J < ntb) {  // odd tile count: the last column alone
-    diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw);
+    diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
     __syncthreads();
   }
 }
@@ -749,11 +816,13 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
                      part, nt, off, fac, status);
 }
 template <typename T, bool PAIR, int R>
-static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, hipStream_t s) {
+static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
+                            const int32_t* trb, T* fac, int32_t* status, hipStream_t s) {
   const size_t sh = std::max(diag_lds_bytes<T>(), (size_t)std::max(4, R + (PAIR ? 2 : 1)) * TS * LdsV<T>::v * sizeof(T));
   static bool once = (allow_lds(k_potrf_full<T, PAIR, R>, sh), true);
   (void)once;
-  hipLaunchKernelGGL((k_potrf_full<T, PAIR, R>), dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, fac, status);
+  hipLaunchKernelGGL((k_potrf_full<T, PAIR, R>), dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, xoff, tlo, trb, fac,
+                     status);
 }
 
 // Largest row count whose LDS staging (rows + 1 or + 2 tiles, at least four)
@@ -761,18 +830,19 @@ static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, T* fa
 int potrf_full_max_rows(bool fp64, bool pair) { return fp64 ? (pair ? 2 : 3) : 4; }
 
 template <typename T>
-void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, bool pair,
+void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
+                       const int32_t* trb, T* fac, int32_t* status, bool pair,
                        hipStream_t s, int rows) {
   if (rows <= 0) rows = PanelRows<T>::v;
   rows = std::max(2, std::min(rows, potrf_full_max_rows(sizeof(T) == 8, pair)));
   if (pair) {
-    if (rows == 2) potrf_full_rows<T, true, 2>(nb, nt, off, fac, status, s);
-    else if (rows == 3) potrf_full_rows<T, true, 3>(nb, nt, off, fac, status, s);
-    else if constexpr (sizeof(T) == 4) potrf_full_rows<T, true, 4>(nb, nt, off, fac, status, s);
+    if (rows == 2) potrf_full_rows<T, true, 2>(nb, nt, off, xoff, tlo, trb, fac, status, s);
+    else if (rows == 3) potrf_full_rows<T, true, 3>(nb, nt, off, xoff, tlo, trb, fac, status, s);
+    else if constexpr (sizeof(T) == 4) potrf_full_rows<T, true, 4>(nb, nt, off, xoff, tlo, trb, fac, status, s);
   } else {
-    if (rows == 2) potrf_full_rows<T, false, 2>(nb, nt, off, fac, status, s);
-    else if (rows == 3) potrf_full_rows<T, false, 3>(nb, nt, off, fac, status, s);
-    else if constexpr (sizeof(T) == 4) potrf_full_rows<T, false, 4>(nb, nt, off, fac, status, s);
+    if (rows == 2) potrf_full_rows<T, false, 2>(nb, nt, off, xoff, tlo, trb, fac, status, s);
+    else if (rows == 3) potrf_full_rows<T, false, 3>(nb, nt, off, xoff, tlo, trb, fac, status, s);
+    else if constexpr (sizeof(T) == 4) potrf_full_rows<T, false, 4>(nb, nt, off, xoff, tlo, trb, fac, status, s);
   }
 }
 template <typename T>
@@ -1050,7 +1120,8 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 #define INST(T)                                                                                    \
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
-  template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, T*, int32_t*, bool,      \
+  template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, const int64_t*,          \
+                                     const int32_t*, const int32_t*, T*, int32_t*, bool,           \
                                      hipStream_t, int);                                            \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
                                      T*, int32_t*, hipStream_t);                                   \

@@ -78,10 +78,24 @@ struct BatchMeta {
 void launch_sfc_rank(const Batch& B, int32_t* pos, int32_t* sfc_index, hipStream_t s);
 void launch_build_nbr(const Batch& B, const int32_t* pos, const int32_t* sfc_index, int32_t* nbr,
                       hipStream_t s);
+// Local elimination order and tile envelope of every subdomain matrix
+// (mode 0: curve order, packed triangle; 1: curve order, envelope; 2:
+// diagonal-level order, envelope).  lperm (per local row, at xoff) and
+// liperm (per subdomain offset, at doff) map local rows to subdomain offsets
+// and back; tlo / trb (per tile row, at xoff / TS) hold the first tile column
+// and the packed row base; gtiles[2 g] += tiles stored for grid g's
+// subdomains, gtiles[2 g + 1] += factor entries one substitution sweep reads.
+constexpr int ORDER_MAX_KEYS = 16384;
+void launch_local_order(const Batch& B, int mode, int max_nt, const int32_t* ta, const int32_t* Ni,
+                        const int32_t* nt, const int64_t* xoff, const int64_t* doff, const int32_t* sfc_index,
+                        const int32_t* nbr, int32_t* lperm, int32_t* liperm, int32_t* tlo, int32_t* trb,
+                        unsigned long long* gtiles, hipStream_t s);
+// Envelope tiles of the local matrices (cleared and assembled).
 template <typename T>
 void launch_assemble_local(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                           const int64_t* fac_off, const int32_t* nbr, int max_nt, T* fac,
-                           hipStream_t s);
+                           const int64_t* fac_off, const int64_t* xoff, const int64_t* doff,
+                           const int32_t* lperm, const int32_t* liperm, const int32_t* tlo, const int32_t* trb,
+                           const int32_t* nbr, int max_nt, T* fac, hipStream_t s);
 void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
                           int32_t* cnt, hipStream_t s);
 void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
@@ -99,9 +113,11 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
 // rows: row tiles per step of the panel updates (2 .. potrf_full_max_rows;
 // 0 = the default 3 FP32, 2 FP64).
 int potrf_full_max_rows(bool fp64, bool pair);
+// With tlo / trb (and xoff) the matrices are stored as tile envelopes (see
+// launch_local_order); with null tables as packed triangles.
 template <typename T>
-void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, T* fac, int32_t* status, bool pair,
-                       hipStream_t s, int rows = 0);
+void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
+                       const int32_t* trb, T* fac, int32_t* status, bool pair, hipStream_t s, int rows = 0);
 // One matrix: sub-diagonal tiles of column J, the diagonal tile of column
 // J + 1, and the split-K partials of column J + 2 (three slots of slot_tiles
 // tiles at part, slot C mod 3 for column C).
@@ -125,9 +141,16 @@ void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, 
                  const double* b, double* partials, hipStream_t s);
 // active (nullable): per-grid solver flags; subdomains of grids that are not
 // updating (flag not RUN or RESTART) are skipped.
+// Whether the substitution kernel's LDS (the subdomain's right-hand side and
+// the tile-row tables) fits a CU for subdomains of max_nt tile rows at this
+// many waves per workgroup.  The launcher lowers the waves until it does.
+bool trsv_fits(int max_nt, int elem_bytes, int waves);
+// Factors stored as tile envelopes in the local order lperm (see
+// launch_local_order).
 template <typename T>
 void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                         const int64_t* off, const int64_t* doff, int max_nt, int waves, bool stream,
+                         const int64_t* off, const int64_t* doff, const int64_t* xoff, const int32_t* lperm,
+                         const int32_t* tlo, const int32_t* trb, int max_nt, int waves, bool stream,
                          const T* fac, const double* w, double* dbuf, const int32_t* active,
                          hipStream_t s);
 template <typename T>

@@ -169,56 +169,88 @@ void launch_build_nbr(const Batch& B, const int32_t* pos, const int32_t* sfc_ind
                      nbr);
 }
 
-// Local matrices A_i = R_i A R_i^T (Sec. 3.1) written as packed lower tiles:
-// row s of subdomain b (grid g) is curve position (ta_b + s) mod N of grid g.
-// Rows past N_b are padding with a unit diagonal.  The tiles must be zeroed
-// beforehand.
+// Local matrices A_i = R_i A R_i^T (Sec. 3.1) in the local elimination
+// order, written as the envelope tiles of the packed lower factor: local row
+// t of subdomain b (grid g) is curve position (ta_b + lperm[t]) mod N of grid
+// g, and tile (I, J), lo[I] <= J <= I, is tile off_b + rb[I] + J.  One
+// workgroup per tile row: it clears the row's tiles (consecutive in memory)
+// and then writes the diagonal and the stencil couplings left of it.  Rows
+// past N_b are padding with a unit diagonal.
 template <typename T>
-__global__ void k_assemble_local(Batch B, const int32_t* __restrict__ ta,
-                                 const int32_t* __restrict__ Ni, const int32_t* __restrict__ nt,
-                                 const int64_t* __restrict__ fac_off,
-                                 const int32_t* __restrict__ nbr, T* __restrict__ fac) {
-  const int b = blockIdx.y;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_assemble_local(Batch B, const int32_t* __restrict__ ta,
+                                                        const int32_t* __restrict__ Ni,
+                                                        const int32_t* __restrict__ nt,
+                                                        const int64_t* __restrict__ fac_off,
+                                                        const int64_t* __restrict__ xoff,
+                                                        const int64_t* __restrict__ doff,
+                                                        const int32_t* __restrict__ lperm,
+                                                        const int32_t* __restrict__ liperm,
+                                                        const int32_t* __restrict__ tlo,
+                                                        const int32_t* __restrict__ trb,
+                                                        const int32_t* __restrict__ nbr, T* __restrict__ fac) {
+  const int b = blockIdx.y, I = blockIdx.x;
   const int ntb = nt[b];
-  if (s >= ntb * TS) return;
+  if (I >= ntb) return;
   const GridDesc& g = B.grids[grid_of(B, B.sgid, b)];
+  const int64_t trow = xoff[b] / TS + I;
+  const int lo = tlo[trow];
+  const int64_t rb = trb[trow];
   T* F = fac + fac_off[b] * TS2;
-  const int I = s / TS, r = s % TS;
+  {
+    typedef typename Vec16<T>::type V;
+    constexpr int VEC = Vec16<T>::n;
+    V* row = reinterpret_cast<V*>(F + (rb + lo) * TS2);
+    const int64_t nv = (int64_t)(I - lo + 1) * TS2 / VEC;
+    V z;
+    if constexpr (VEC == 4) z = make_float4(0.f, 0.f, 0.f, 0.f);
+    else z = make_double2(0.0, 0.0);
+    for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) row[e] = z;
+  }
+  __syncthreads();
+  const int r = threadIdx.x;
+  if (r >= TS) return;
+  const int t = I * TS + r;
   const int n = Ni[b];
-  if (s >= n) {
-    F[tri_index(I, I) * TS2 + r * TS + r] = T(1);
+  T* D = F + (rb + I) * TS2;
+  if (t >= n) {
+    D[r * TS + r] = T(1);
     return;
   }
-  F[tri_index(I, I) * TS2 + r * TS + r] = (T)g.diag;
-  const int64_t p = g.goff + ((int64_t)ta[b] + s) % g.N;
+  D[r * TS + r] = (T)g.diag;
+  const int64_t t0 = ta[b];
+  int64_t p = t0 + lperm[xoff[b] + t];
+  if (p >= g.N) p -= g.N;
+  p += g.goff;
+  const int32_t* ip = liperm + doff[b];
   for (int j = 0; j < g.d; ++j) {
     for (int side = 0; side < 2; ++side) {
       const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
       if (q < 0) continue;
-      const int64_t t = ((q - g.goff - ta[b]) % g.N + g.N) % g.N;
-      if (t < n && t < s) {
-        const int J = (int)(t / TS), c = (int)(t % TS);
-        F[tri_index(I, J) * TS2 + r * TS + c] = (T)(-g.c[j]);
-      }
+      int64_t u = q - g.goff - t0;
+      if (u < 0) u += g.N;
+      if (u >= n) continue;
+      const int tc = ip[u];
+      if (tc < t) F[(rb + tc / TS) * TS2 + r * TS + tc % TS] = (T)(-g.c[j]);
     }
   }
 }
 
 template <typename T>
 void launch_assemble_local(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                           const int64_t* fac_off, const int32_t* nbr, int max_nt, T* fac,
-                           hipStream_t s) {
-  const int th = 256;
-  dim3 grid((max_nt * TS + th - 1) / th, B.Ptot);
-  hipLaunchKernelGGL(k_assemble_local<T>, grid, dim3(th), 0, s, B, ta, Ni, nt, fac_off, nbr, fac);
+                           const int64_t* fac_off, const int64_t* xoff, const int64_t* doff,
+                           const int32_t* lperm, const int32_t* liperm, const int32_t* tlo, const int32_t* trb,
+                           const int32_t* nbr, int max_nt, T* fac, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble_local<T>, dim3(max_nt, B.Ptot), dim3(256), 0, s, B, ta, Ni, nt, fac_off, xoff,
+                     doff, lperm, liperm, tlo, trb, nbr, fac);
 }
-template void launch_assemble_local<float>(const Batch&, const int32_t*, const int32_t*,
-                                           const int32_t*, const int64_t*, const int32_t*, int,
-                                           float*, hipStream_t);
-template void launch_assemble_local<double>(const Batch&, const int32_t*, const int32_t*,
-                                            const int32_t*, const int64_t*, const int32_t*, int,
-                                            double*, hipStream_t);
+#define INST(T)                                                                                         \
+  template void launch_assemble_local<T>(const Batch&, const int32_t*, const int32_t*, const int32_t*, \
+                                         const int64_t*, const int64_t*, const int64_t*, const int32_t*, \
+                                         const int32_t*, const int32_t*, const int32_t*, const int32_t*, \
+                                         int, T*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
 
 // Coarse unknown (block) of local curve position p of grid g: piece i and its
 // m-th block of eq. (restr), local index i q + m.

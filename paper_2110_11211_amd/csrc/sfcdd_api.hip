@@ -57,6 +57,7 @@ struct sfcdd_ctx {
   int G = 0;
   std::vector<GridHost> grid;
   int weighting = 1, variant = 1, fdtype = 0, local_solver = 0, layout = 0;
+  int local_order = SFCDD_ORDER_DIAGONAL;  // elimination order of the subdomain matrices
   int64_t Ntot = 0, N0tot = 0;
   int Ptot = 0, dmax = 0, duni = 0, rbx = RED_BLOCKS;
   int max_cblock = 1;  // largest coarse block (points) of any grid
@@ -98,7 +99,8 @@ struct sfcdd_ctx {
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
       r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout,
-      r_ideg, r_icol, r_ival, r_ibjt, r_ibjm, r_ibjnt, r_ibjoff, r_ivec, r_icagg, r_idagg, r_iqpart, r_ipart;
+      r_ideg, r_icol, r_ival, r_ibjt, r_ibjm, r_ibjnt, r_ibjoff, r_ivec, r_icagg, r_idagg, r_iqpart, r_ipart,
+      r_lperm, r_liperm, r_tlo, r_trb, r_gtiles;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // device pointers
@@ -108,6 +110,9 @@ struct sfcdd_ctx {
   int32_t *d_ta = nullptr, *d_Ni = nullptr, *d_nt = nullptr;
   int64_t *d_off = nullptr, *d_doff = nullptr, *d_xoff = nullptr, *d_poff = nullptr;
   double* d_omega = nullptr;
+  // local elimination order and tile envelopes of the subdomain factors
+  int32_t *lperm = nullptr, *liperm = nullptr, *tlo = nullptr, *trb = nullptr;
+  unsigned long long* gtiles = nullptr;   // per grid: tiles stored, entries per sweep
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
   double* cy = nullptr;  // tile-padded coarse vector X_0 R_0 v between the two products
@@ -313,6 +318,9 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
     GFAIL(SFCDD_EINVAL, "coarse_precision = %d", p->coarse_precision);
   if (p->curve != SFCDD_CURVE_ZORDER && p->curve != SFCDD_CURVE_HILBERT)
     GFAIL(SFCDD_EINVAL, "curve = %d", p->curve);
+  if (p->local_order != SFCDD_ORDER_DIAGONAL && p->local_order != SFCDD_ORDER_CURVE &&
+      p->local_order != SFCDD_ORDER_DENSE)
+    GFAIL(SFCDD_EINVAL, "local_order = %d", p->local_order);
   g.curve = p->curve;
 
   if (p->coarse_solver != SFCDD_COARSE_DENSE && p->coarse_solver != SFCDD_COARSE_ITERATIVE)
@@ -487,8 +495,9 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     if (params[k].weighting != params[0].weighting || params[k].variant != params[0].variant ||
         params[k].factor_dtype != params[0].factor_dtype ||
         params[k].local_solver != params[0].local_solver || params[k].layout != params[0].layout ||
-        params[k].coarse_precision != params[0].coarse_precision)
-      FAIL(c, SFCDD_EINVAL, "grid %d: weighting, variant, factor_dtype, local_solver, layout and "
+        params[k].coarse_precision != params[0].coarse_precision ||
+        params[k].local_order != params[0].local_order)
+      FAIL(c, SFCDD_EINVAL, "grid %d: weighting, variant, factor_dtype, local_solver, layout, local_order and "
            "coarse_precision must be the same for every grid of a batch", k);
     if (params[k].coarse_solver == SFCDD_COARSE_ITERATIVE && G > 1)
       FAIL(c, SFCDD_EINVAL, "grid %d: the iterative coarse solver is for single grids", k);
@@ -497,6 +506,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->variant = params[0].variant;
   c->fdtype = params[0].factor_dtype;
   c->local_solver = params[0].local_solver;
+  c->local_order = c->local_solver == SFCDD_LOCAL_INVERSE ? SFCDD_ORDER_DENSE : params[0].local_order;
   c->layout = params[0].layout;
   c->coarse_iter = params[0].coarse_solver == SFCDD_COARSE_ITERATIVE;
   if (c->coarse_iter) {
@@ -546,7 +556,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
       c->max_Ni = std::max(c->max_Ni, h.Ni[i]);
       c->min_Ni = std::min(c->min_Ni, h.Ni[i]);
     }
-    c->gfac_bytes[k] = (toff - toff0) * TS2 * (c->fdtype == SFCDD_FP32 ? 4 : 8);
+    c->gfac_bytes[k] = (toff - toff0) * TS2 * (c->fdtype == SFCDD_FP32 ? 4 : 8);  // until the envelopes are known
     // the dense coarse level (A_0, or its aggregation for the iterative solve)
     c->c_nt.push_back(g.nt0d);
     c->c_n.push_back(g.N0d);
@@ -561,6 +571,10 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
     c->max_nt0 = std::max(c->max_nt0, g.nt0d);
     c->max_N0 = std::max(c->max_N0, g.N0d);
   }
+  // the substitution kernel stages the subdomain's right-hand side in LDS
+  if (c->local_solver == SFCDD_LOCAL_CHOLESKY && !trsv_fits(c->max_nt, c->fdtype == SFCDD_FP32 ? 4 : 8, 4))
+    FAIL(c, SFCDD_EINVAL, "a subdomain of %d points is too large for the substitution kernel (%s factors)",
+         c->max_Ni, c->fdtype == SFCDD_FP32 ? "FP32" : "FP64");
   c->duni = c->grid[0].desc.d;
   for (int k = 1; k < G; ++k)
     if (c->grid[k].desc.d != c->duni) c->duni = 0;
@@ -633,6 +647,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_active = pl.take((size_t)4 * G);
   c->r_status = pl.take(64);
   c->r_gout = pl.take(MAXD * 8);
+  c->r_lperm = pl.take(4 * (size_t)c->xlen);
+  c->r_liperm = pl.take(4 * (size_t)c->sum_Ni);
+  c->r_tlo = pl.take(4 * (size_t)(c->xlen / TS));
+  c->r_trb = pl.take(4 * (size_t)(c->xlen / TS));
+  c->r_gtiles = pl.take(16 * (size_t)G);
   if (c->coarse_iter) {
     const GridDesc& g = c->grid[0].desc;
     c->ic_nt = g.nt0;
@@ -708,6 +727,11 @@ void bind(sfcdd_ctx* c) {
   c->active = at<int32_t>(c, c->r_active);
   c->status = at<int32_t>(c, c->r_status);
   c->gout = at<double>(c, c->r_gout);
+  c->lperm = at<int32_t>(c, c->r_lperm);
+  c->liperm = at<int32_t>(c, c->r_liperm);
+  c->tlo = at<int32_t>(c, c->r_tlo);
+  c->trb = at<int32_t>(c, c->r_trb);
+  c->gtiles = at<unsigned long long>(c, c->r_gtiles);
   if (c->coarse_iter) {
     c->ideg = at<int32_t>(c, c->r_ideg);
     c->icol = at<int32_t>(c, c->r_icol);
@@ -732,14 +756,16 @@ void bind(sfcdd_ctx* c) {
 // Batched left-looking factorisation: each workgroup keeps its output tile in
 // registers across the K loop.  A single matrix (part != nullptr) uses the
 // split-K form instead, so that every column step runs on many workgroups.
+// xoff / tlo / trb (batch only): the matrices are stored as tile envelopes.
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, bool product, int32_t* status, T* part, T* tbuf,
-                  const int64_t* toff, bool pair, hipStream_t s, int rows = 0) {
+                  const int64_t* toff, bool pair, hipStream_t s, int rows = 0,
+                  const int64_t* xoff = nullptr, const int32_t* tlo = nullptr, const int32_t* trb = nullptr) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   if (!part) {
     // batch: one workgroup factors a whole matrix
-    launch_potrf_full<T>(nb, nt, off, fac, status, pair, s, rows);
+    launch_potrf_full<T>(nb, nt, off, xoff, tlo, trb, fac, status, pair, s, rows);
   } else {
     // one matrix: the first diagonal tile, then one step per column (its
     // sub-diagonal tiles, the next diagonal tile, split-K partials two
@@ -842,10 +868,12 @@ void local_solves(sfcdd_ctx* c, const double* w, int waves, const int32_t* mask 
   if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
     const bool nt = stream_factors(c, mask);
     if (c->fdtype == SFCDD_FP32)
-      launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves, nt,
+      launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->d_xoff, c->lperm, c->tlo,
+                                 c->trb, c->max_nt, waves, nt,
                                  (const float*)c->fac, w, c->dbuf, mask, s);
     else
-      launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->max_nt, waves, nt,
+      launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->d_xoff, c->lperm, c->tlo,
+                                  c->trb, c->max_nt, waves, nt,
                                   (const double*)c->fac, w, c->dbuf, mask, s);
   } else {
     BatchMeta bm{c->d_nt, c->d_off, c->d_xoff, c->d_poff};
@@ -1150,7 +1178,8 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       launch_coarse_ell(B, n0, c->nbr, c->ic_kw, c->ic_ld, c->ideg, c->icol, c->ival, c->status + 2, cs);
       HIPCHK(c, hipMemsetAsync(c->ibjt, 0, c->r_ibjt.bytes, cs));
       launch_bj_extract(n0, c->ic_ld, c->ideg, c->icol, c->ival, c->ibjt, cs);
-      launch_potrf_full<double>(c->ic_nt, c->ibjnt, c->ibjoff, c->ibjt, c->status + 3, false, cs);
+      launch_potrf_full<double>(c->ic_nt, c->ibjnt, c->ibjoff, nullptr, nullptr, nullptr, c->ibjt, c->status + 3,
+                                false, cs);
       launch_bj_form(c->ic_nt, c->ibjt, c->ibjm, cs);
       HIPCHK(c, hipMemsetAsync(c->icagg, 0, c->r_icagg.bytes, cs));
       HIPCHK(c, hipMemsetAsync(c->idagg, 0, c->r_idagg.bytes, cs));
@@ -1160,14 +1189,18 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     HIPCHK(c, hipEventRecord(join, cs));
   }
 
-  // local matrices A_i = R_i A R_i^T
-  HIPCHK(c, hipMemsetAsync(c->fac, 0, c->r_fac.bytes, s));
+  // local elimination order and tile envelopes, then the local matrices
+  // A_i = R_i A R_i^T in that order (only the envelope tiles are written)
+  HIPCHK(c, hipMemsetAsync(c->gtiles, 0, c->r_gtiles.bytes, s));
+  const int omode = c->local_order == SFCDD_ORDER_DIAGONAL ? 2 : c->local_order == SFCDD_ORDER_CURVE ? 1 : 0;
+  launch_local_order(B, omode, c->max_nt, c->d_ta, c->d_Ni, c->d_nt, c->d_xoff, c->d_doff, c->sfc_index, c->nbr,
+                     c->lperm, c->liperm, c->tlo, c->trb, c->gtiles, s);
   if (c->fdtype == SFCDD_FP32)
-    launch_assemble_local<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->nbr, c->max_nt,
-                                 (float*)c->fac, s);
+    launch_assemble_local<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm, c->liperm,
+                                 c->tlo, c->trb, c->nbr, c->max_nt, (float*)c->fac, s);
   else
-    launch_assemble_local<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->nbr, c->max_nt,
-                                  (double*)c->fac, s);
+    launch_assemble_local<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm,
+                                  c->liperm, c->tlo, c->trb, c->nbr, c->max_nt, (double*)c->fac, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[3], s));
 
@@ -1184,10 +1217,12 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
                                          : (c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work);
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
-                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s, c->factor_rows);
+                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s, c->factor_rows,
+                        c->d_xoff, c->tlo, c->trb);
   else
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
-                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s, c->factor_rows);
+                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s, c->factor_rows,
+                         c->d_xoff, c->tlo, c->trb);
   c->info.factor_pair = pair ? 1 : 0;
   c->info.factor_rows = c->factor_rows > 0 ? c->factor_rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
   HIPCHK(c, hipGetLastError());
@@ -1217,10 +1252,19 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.tile = TS;
   I.sum_Ni = c->sum_Ni;
   const int64_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
-  I.factor_bytes = c->tiles * TS2 * es;
-  int64_t algo = 0;
-  for (int i = 0; i < Pt; ++i) algo += (int64_t)c->Ni[i] * (c->Ni[i] + 1) / 2;
-  I.factor_algo_bytes = algo * es;
+  {
+    std::vector<unsigned long long> gt(2 * (size_t)G);
+    HIPCHK(c, hipMemcpy(gt.data(), c->gtiles, 16 * (size_t)G, hipMemcpyDeviceToHost));
+    int64_t tiles = 0, entries = 0;
+    for (int k = 0; k < G; ++k) {
+      c->gfac_bytes[k] = (int64_t)gt[2 * k] * TS2 * es;
+      tiles += (int64_t)gt[2 * k];
+      entries += (int64_t)gt[2 * k + 1];
+    }
+    I.factor_bytes = tiles * TS2 * es;
+    I.factor_algo_bytes = entries * es;
+  }
+  I.local_order = c->local_order;
   I.coarse_bytes = (int64_t)c->r_A0.bytes;
   for (int k = 0; k < 5; ++k) I.setup_ms[k] = ms[k];
   I.setup_ms[5] = tot;
@@ -1260,8 +1304,8 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
 // ---------------------------------------------------------------------------
 // Autotuning of the launch shapes.  Each choice depends only on the launch
 // shape it serves and is recorded for the process under a key of that shape:
-// the substitution kernel's waves (device, precision, local solver, tile
-// count and size of every subdomain), the SpMV's points per step and window
+// the substitution kernel's waves (device, precision, local solver and
+// order, tile count and size of every subdomain, grid sizes and curves), the SpMV's points per step and window
 // (device, grid sizes and curves), the batched factorisation's rows per step
 // and column pairing (device, precisions, coarse solver, subdomain sizes and
 // coarse sizes; it is timed as a whole setup, since the factorisation shares
@@ -1283,9 +1327,16 @@ uint64_t key_trsv(const sfcdd_ctx* c, int dev) {
   m((uint64_t)dev);
   m((uint64_t)c->fdtype);
   m((uint64_t)c->local_solver);
+  m((uint64_t)c->local_order);
   for (int i = 0; i < c->Ptot; ++i) {
     m((uint64_t)c->nt[i]);
     m((uint64_t)c->Ni[i]);
+  }
+  // the tile envelopes follow from the grid's geometry and curve
+  for (int k = 0; k < c->G; ++k) {
+    const GridDesc& g = c->grid[k].desc;
+    m((uint64_t)g.curve);
+    for (int j = 0; j < g.d; ++j) m((uint64_t)g.n[j]);
   }
   return m.key;
 }

@@ -1,6 +1,6 @@
 // Subdomain solves of the fine Schwarz level: forward and backward
-// substitution with the packed tiled Cholesky factors, one workgroup per
-// subdomain.
+// substitution with the tiled Cholesky factors (tile envelopes in the local
+// elimination order), one workgroup per subdomain.
 #include "common.h"
 #include "kernels.h"
 
@@ -10,7 +10,8 @@ namespace sfcdd {
 // Subdomain solves d_i = A_i^{-1} R_i w by forward and backward substitution
 // with the packed tiled Cholesky factor (Sec. 3.1: factor once, then only
 // forward/backward steps; Alg. 2 first two steps).  One workgroup per
-// subdomain; R_i w (a cyclic contiguous curve range) is staged in LDS.
+// subdomain; R_i w (a cyclic contiguous curve range, permuted to the local
+// order) is staged in LDS.
 // Diagonal tiles hold L_II^{-1}, so every step is a tile matrix-vector product.
 // Each wave streams whole 16-byte-per-lane row groups of the tiles.
 
@@ -63,19 +64,39 @@ __device__ __forceinline__ typename Vec16<T>::type load_fac(const T* p) {
   return *reinterpret_cast<const typename Vec16<T>::type*>(p);
 }
 
+template <typename T>
+__device__ __forceinline__ typename Vec16<T>::type vzero();
+template <>
+__device__ __forceinline__ float4 vzero<float>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <>
+__device__ __forceinline__ double2 vzero<double>() { return make_double2(0.0, 0.0); }
+
+// The factor of subdomain b is stored as its tile envelope in the local
+// elimination order: local row t is subdomain offset lperm[t], tile row I
+// holds the tiles J = lo[I] .. I at rb[I] + J (lo non-decreasing), and every
+// tile outside is zero.  So the forward step of row I reads the tiles lo[I]
+// .. I, and the backward step of column I the tiles (K, I), K = I + 1 ..
+// hi[I], hi[I] the last row whose envelope reaches column I.
+// Each wave owns G row groups of every tile; the first PF tiles of the next
+// row (column) and its diagonal tile are loaded into registers before the
+// current one is reduced, so their latency overlaps the reductions and the
+// barriers of the step.
 // NT: factor loads with the non-temporal hint (chosen by the caller when the
 // factors being swept are larger than the last-level cache).
 template <typename T, int W, bool NT>
 __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     Batch B, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
     const int32_t* __restrict__ nt, const int64_t* __restrict__ off,
-    const int64_t* __restrict__ doff, const T* __restrict__ fac, const double* __restrict__ w,
-    double* __restrict__ dbuf, const int32_t* __restrict__ active) {
+    const int64_t* __restrict__ doff, const int64_t* __restrict__ xoff, const int32_t* __restrict__ lperm,
+    const int32_t* __restrict__ tlo, const int32_t* __restrict__ trb, const T* __restrict__ fac,
+    const double* __restrict__ w, double* __restrict__ dbuf, const int32_t* __restrict__ active) {
   typedef typename Vec16<T>::type V;
   constexpr int VEC = Vec16<T>::n;          // elements per lane per load
   constexpr int LPR = TS / VEC;             // lanes per tile row
   constexpr int RPI = 64 / LPR;             // rows per wave load
   constexpr int NGRP = TS / RPI;            // row groups per tile
+  constexpr int G = NGRP / W;               // row groups per wave
+  constexpr int PF = G >= 8 ? 1 : 8 / G;    // prefetched tiles per row group
   const int b = blockIdx.x;
   const int ntb = nt[b], n = Ni[b];
   const int64_t t0 = ta[b];
@@ -88,33 +109,94 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   T* y = reinterpret_cast<T*>(smem_raw);    // ntb * TS
   T* sS = y + ntb * TS;                     // TS
   T* red = sS + TS;                         // W * TS
+  int* slo = reinterpret_cast<int*>(red + W * TS);  // ntb
+  int* shi = slo + ntb;                     // ntb
+  int* srb = shi + ntb;                     // ntb
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int lrow = lane / LPR, c0 = (lane % LPR) * VEC;
   const T* F = fac + off[b] * TS2;
+  const int64_t xb = xoff[b];
+  const int32_t* __restrict__ perm = lperm + xb;
 
+  for (int I = tid; I < ntb; I += W * 64) {
+    slo[I] = tlo[xb / TS + I];
+    srb[I] = trb[xb / TS + I];
+  }
   for (int s = tid; s < ntb * TS; s += W * 64) {
     T v = T(0);
     if (s < n) {
-      int64_t p = t0 + s;
+      int64_t p = t0 + perm[s];
       if (p >= N) p -= N;
       v = (T)wg[p];
     }
     y[s] = v;
   }
   __syncthreads();
+  for (int J = tid; J < ntb; J += W * 64) {
+    int h = J;
+    while (h + 1 < ntb && slo[h + 1] <= J) ++h;
+    shi[J] = h;
+  }
+  __syncthreads();
 
   // Rows at or past n are padding (unit diagonal, zero right-hand side, zero
-  // solution): their tile rows and columns are never read.  Chunks of the
-  // diagonal-tile inverses right of the diagonal are zero and not read either.
-  // forward: y_I <- L_II^{-1} (g_I - sum_{J<I} L_IJ y_J)
+  // solution): their tile rows are never read.  Chunks of the diagonal-tile
+  // inverses right of the diagonal are zero and not read either.
+  V cur[G][PF + 1], nxt[G][PF + 1];
+  auto load_fwd = [&](int I, V (&buf)[G][PF + 1]) {
+    const int lo = slo[I];
+    const T* rowI = F + (int64_t)srb[I] * TS2;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int r = (wv + W * gg) * RPI + lrow;
+      const bool live = I * TS + r < n;
+#pragma unroll
+      for (int k = 0; k < PF; ++k)
+        buf[gg][k] = (live && lo + k < I) ? load_fac<T, NT>(rowI + (int64_t)(lo + k) * TS2 + r * TS + c0)
+                                          : vzero<T>();
+      buf[gg][PF] = (live && c0 <= r) ? load_fac<T, NT>(rowI + (int64_t)I * TS2 + r * TS + c0) : vzero<T>();
+    }
+  };
+  auto load_bwd = [&](int I, V (&buf)[G][PF + 1]) {
+    const int hi = shi[I];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int r = (wv + W * gg) * RPI + lrow;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int K = I + 1 + k;
+        buf[gg][k] = (K <= hi && K * TS + r < n)
+                         ? load_fac<T, NT>(F + ((int64_t)srb[K] + I) * TS2 + r * TS + c0)
+                         : vzero<T>();
+      }
+      buf[gg][PF] = (c0 <= r && I * TS + r < n)
+                        ? load_fac<T, NT>(F + ((int64_t)srb[I] + I) * TS2 + r * TS + c0)
+                        : vzero<T>();
+    }
+  };
+  auto advance = [&]() {
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+      for (int k = 0; k <= PF; ++k) cur[gg][k] = nxt[gg][k];
+  };
+
+  // forward: y_I <- L_II^{-1} (g_I - sum_{lo_I <= J < I} L_IJ y_J)
+  load_fwd(0, cur);
   for (int I = 0; I < ntb; ++I) {
-    const T* rowI = F + tri_index(I, 0) * TS2;
-    for (int grp = wv; grp < NGRP; grp += W) {
-      const int r = grp * RPI + lrow;
+    if (I + 1 < ntb) load_fwd(I + 1, nxt);
+    else load_bwd(ntb - 1, nxt);
+    const int lo = slo[I];
+    const T* rowI = F + (int64_t)srb[I] * TS2;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int r = (wv + W * gg) * RPI + lrow;
       T acc = T(0);
       if (I * TS + r < n) {
-#pragma unroll 4
-        for (int J = 0; J < I; ++J) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+          if (lo + k < I) acc += dotv<T>(cur[gg][k], y + (lo + k) * TS + c0);
+        for (int J = lo + PF; J < I; ++J) {
           const V v = load_fac<T, NT>(rowI + (int64_t)J * TS2 + r * TS + c0);
           acc += dotv<T>(v, y + J * TS + c0);
         }
@@ -123,35 +205,37 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
       if ((lane % LPR) == 0) sS[r] = y[I * TS + r] - acc;
     }
     __syncthreads();
-    const T* D = rowI + (int64_t)I * TS2;
-    for (int grp = wv; grp < NGRP; grp += W) {
-      const int r = grp * RPI + lrow;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int r = (wv + W * gg) * RPI + lrow;
       T acc = T(0);
-      if (c0 <= r && I * TS + r < n) {
-        const V v = load_fac<T, NT>(D + r * TS + c0);
-        acc = dotv<T>(v, sS + c0);
-      }
+      if (c0 <= r && I * TS + r < n) acc = dotv<T>(cur[gg][PF], sS + c0);
       for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if ((lane % LPR) == 0) y[I * TS + r] = acc;
     }
     __syncthreads();
+    advance();
   }
 
-  // backward: x_I <- L_II^{-T} (y_I - sum_{K>I} L_KI^T x_K), x overwrites y
+  // backward: x_I <- L_II^{-T} (y_I - sum_{I < K <= hi_I} L_KI^T x_K), x overwrites y
   for (int I = ntb - 1; I >= 0; --I) {
+    if (I > 0) load_bwd(I - 1, nxt);
+    const int hi = shi[I];
     T accv[VEC];
     for (int e = 0; e < VEC; ++e) accv[e] = T(0);
-    for (int grp = wv; grp < NGRP; grp += W) {
-      const int r = grp * RPI + lrow;
-      const int Kend = ntb - 1;  // the last tile row may hold padding rows
-#pragma unroll 4
-      for (int K = I + 1; K < Kend; ++K) {
-        const V v = load_fac<T, NT>(F + tri_index(K, I) * TS2 + r * TS + c0);
-        axpyv<T>(accv, v, y[K * TS + r]);
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int r = (wv + W * gg) * RPI + lrow;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int K = I + 1 + k;
+        if (K <= hi && K * TS + r < n) axpyv<T>(accv, cur[gg][k], y[K * TS + r]);
       }
-      if (I < Kend && Kend * TS + r < n) {
-        const V v = load_fac<T, NT>(F + tri_index(Kend, I) * TS2 + r * TS + c0);
-        axpyv<T>(accv, v, y[Kend * TS + r]);
+      for (int K = I + 1 + PF; K <= hi; ++K) {
+        if (K * TS + r < n) {
+          const V v = load_fac<T, NT>(F + ((int64_t)srb[K] + I) * TS2 + r * TS + c0);
+          axpyv<T>(accv, v, y[K * TS + r]);
+        }
       }
     }
     for (int e = 0; e < VEC; ++e)
@@ -166,13 +250,10 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
     }
     __syncthreads();
     for (int e = 0; e < VEC; ++e) accv[e] = T(0);
-    const T* D = F + tri_index(I, I) * TS2;
-    for (int grp = wv; grp < NGRP; grp += W) {
-      const int r = grp * RPI + lrow;
-      if (c0 <= r && I * TS + r < n) {
-        const V v = load_fac<T, NT>(D + r * TS + c0);
-        axpyv<T>(accv, v, sS[r]);
-      }
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int r = (wv + W * gg) * RPI + lrow;
+      if (c0 <= r && I * TS + r < n) axpyv<T>(accv, cur[gg][PF], sS[r]);
     }
     for (int e = 0; e < VEC; ++e)
       for (int o = LPR; o < 64; o <<= 1) accv[e] += __shfl_xor(accv[e], o, 64);
@@ -185,45 +266,66 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
       y[I * TS + tid] = s;
     }
     __syncthreads();
+    advance();
   }
 
   double* out = dbuf + doff[b];
-  for (int s = tid; s < n; s += W * 64) out[s] = (double)y[s];
+  for (int s = tid; s < n; s += W * 64) out[perm[s]] = (double)y[s];
+}
+
+static size_t trsv_lds(int max_nt, size_t es, int W) {
+  return ((size_t)max_nt * TS + TS + (size_t)W * TS) * es + 3 * (size_t)max_nt * sizeof(int);
+}
+bool trsv_fits(int max_nt, int elem_bytes, int waves) {
+  return trsv_lds(max_nt, (size_t)elem_bytes, waves) <= (size_t)160 * 1024;
 }
 
 // Waves per workgroup of the substitution kernel: 4, 8 or 16 (a tuning knob).
 template <typename T, int W, bool NT>
 static void trsv_w(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                   const int64_t* off, const int64_t* doff, int max_nt, const T* fac,
+                   const int64_t* off, const int64_t* doff, const int64_t* xoff, const int32_t* lperm,
+                   const int32_t* tlo, const int32_t* trb, int max_nt, const T* fac,
                    const double* w, double* dbuf, const int32_t* active, hipStream_t s) {
-  const size_t sh = ((size_t)max_nt * TS + TS + (size_t)W * TS) * sizeof(T);
+  const size_t sh = trsv_lds(max_nt, sizeof(T), W);
+  if (sh > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_schwarz_trsv<T, W, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   hipLaunchKernelGGL((k_schwarz_trsv<T, W, NT>), dim3(B.Ptot), dim3(W * 64), sh, s, B, ta, Ni, nt, off,
-                     doff, fac, w, dbuf, active);
+                     doff, xoff, lperm, tlo, trb, fac, w, dbuf, active);
 }
 
 template <typename T, bool NT>
 static void trsv_nt(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                    const int64_t* off, const int64_t* doff, int max_nt, int waves, const T* fac,
+                    const int64_t* off, const int64_t* doff, const int64_t* xoff, const int32_t* lperm,
+                    const int32_t* tlo, const int32_t* trb, int max_nt, int waves, const T* fac,
                     const double* w, double* dbuf, const int32_t* active, hipStream_t s) {
-  if (waves <= 4) trsv_w<T, 4, NT>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, active, s);
-  else if (waves <= 8) trsv_w<T, 8, NT>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, active, s);
-  else trsv_w<T, 16, NT>(B, ta, Ni, nt, off, doff, max_nt, fac, w, dbuf, active, s);
+  while (waves > 4 && !trsv_fits(max_nt, (int)sizeof(T), waves)) waves /= 2;
+  if (waves <= 4)
+    trsv_w<T, 4, NT>(B, ta, Ni, nt, off, doff, xoff, lperm, tlo, trb, max_nt, fac, w, dbuf, active, s);
+  else if (waves <= 8)
+    trsv_w<T, 8, NT>(B, ta, Ni, nt, off, doff, xoff, lperm, tlo, trb, max_nt, fac, w, dbuf, active, s);
+  else
+    trsv_w<T, 16, NT>(B, ta, Ni, nt, off, doff, xoff, lperm, tlo, trb, max_nt, fac, w, dbuf, active, s);
 }
 
 template <typename T>
 void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
-                         const int64_t* off, const int64_t* doff, int max_nt, int waves, bool stream,
+                         const int64_t* off, const int64_t* doff, const int64_t* xoff, const int32_t* lperm,
+                         const int32_t* tlo, const int32_t* trb, int max_nt, int waves, bool stream,
                          const T* fac, const double* w, double* dbuf, const int32_t* active,
                          hipStream_t s) {
-  if (stream) trsv_nt<T, true>(B, ta, Ni, nt, off, doff, max_nt, waves, fac, w, dbuf, active, s);
-  else trsv_nt<T, false>(B, ta, Ni, nt, off, doff, max_nt, waves, fac, w, dbuf, active, s);
+  if (stream)
+    trsv_nt<T, true>(B, ta, Ni, nt, off, doff, xoff, lperm, tlo, trb, max_nt, waves, fac, w, dbuf, active, s);
+  else
+    trsv_nt<T, false>(B, ta, Ni, nt, off, doff, xoff, lperm, tlo, trb, max_nt, waves, fac, w, dbuf, active, s);
 }
 
 #define INST(T)                                                                                    \
   template void launch_schwarz_trsv<T>(const Batch&, const int32_t*, const int32_t*,              \
-                                       const int32_t*, const int64_t*, const int64_t*, int, int,   \
-                                       bool, const T*, const double*, double*, const int32_t*,     \
-                                       hipStream_t);
+                                       const int32_t*, const int64_t*, const int64_t*,             \
+                                       const int64_t*, const int32_t*, const int32_t*,             \
+                                       const int32_t*, int, int, bool, const T*, const double*,    \
+                                       double*, const int32_t*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST
