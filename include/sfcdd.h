@@ -186,6 +186,9 @@ typedef struct {
   int32_t spmv_points;       /* launch shape of the SpMV: points per thread and step, */
   int32_t spmv_window;       /*   and points of x staged in LDS per window            */
   int32_t local_order;       /* elimination order of the subdomain matrices in use      */
+  double factor_flops;       /* floating-point operations of the subdomain
+                                factorisation: 2 TS^3 per tile product and 2 TS^3 / 3
+                                per diagonal tile (its Cholesky factor and inverse)     */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1
@@ -320,8 +323,9 @@ sfcdd_status sfcdd_get_partition(sfcdd_ctx* ctx, int32_t grid, int32_t* sfc_inde
 sfcdd_status sfcdd_get_batch_stats(sfcdd_ctx* ctx, int32_t* iterations, double* rel_residual);
 
 /* The substitution-kernel part of sfcdd_tune (SFCDD_TUNE_TRSV): times the
- * substitution sweeps with 4, 8 and 16 waves per workgroup on the context's
- * own factors, keeps the fastest, and returns its time per application in
+ * substitution sweeps with 4, 8 and 16 waves per workgroup, each with and
+ * without the non-temporal hint on the factor loads, on the context's own
+ * factors, keeps the fastest, and returns its time per application in
  * *best_ms (may be NULL).  Repeats and the per-shape record as in sfcdd_tune.
  * With the explicit-inverse local solver there is nothing to tune and only
  * the time is measured.  Synchronous. */
@@ -341,11 +345,13 @@ typedef struct {
   double trsv_ms, trsv_default_ms;    /* one application of the subdomain solves        */
   double spmv_ms, spmv_default_ms;    /* one SpMV y = A x                               */
   double setup_ms, setup_default_ms;  /* one whole setup (Alg. 1 and the factorisations) */
+  int32_t trsv_stream;       /* non-temporal hint on the substitution kernel's factor
+                                loads: 1 on, 0 off, -1 the default (off)                 */
 } sfcdd_tuning;
 enum { SFCDD_TUNE_TRSV = 1, SFCDD_TUNE_SPMV = 2, SFCDD_TUNE_SETUP = 4, SFCDD_TUNE_ALL = 7 };
 
 /* Autotuner of the launch shapes (the `what` bits): the substitution kernel's
- * waves per workgroup (4, 8, 16); the SpMV's points per thread and LDS window
+ * waves per workgroup (4, 8, 16) with and without the non-temporal hint; the SpMV's points per thread and LDS window
  * (2 x 4 shapes); and the batched factorisation's row tiles per panel step
  * (2, 3, 4; 2, 3 with FP64 factors) with one or two columns per step, each
  * candidate timed with events on the context's stream (repeats runs each,

@@ -82,7 +82,7 @@ class Info(ctypes.Structure):
                 ("N0d", ctypes.c_int32), ("ell_width", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
                 ("factor_rows", ctypes.c_int32), ("factor_pair", ctypes.c_int32),
                 ("spmv_points", ctypes.c_int32), ("spmv_window", ctypes.c_int32),
-                ("local_order", ctypes.c_int32)]
+                ("local_order", ctypes.c_int32), ("factor_flops", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -91,7 +91,8 @@ class Tuning(ctypes.Structure):
                 ("factor_pair", ctypes.c_int32), ("tuned", ctypes.c_int32),
                 ("trsv_ms", ctypes.c_double), ("trsv_default_ms", ctypes.c_double),
                 ("spmv_ms", ctypes.c_double), ("spmv_default_ms", ctypes.c_double),
-                ("setup_ms", ctypes.c_double), ("setup_default_ms", ctypes.c_double)]
+                ("setup_ms", ctypes.c_double), ("setup_default_ms", ctypes.c_double),
+                ("trsv_stream", ctypes.c_int32)]
 
 
 TUNE = {"trsv": 1, "spmv": 2, "setup": 4, "all": 7}

@@ -805,6 +805,50 @@ static void allow_lds(K kernel, size_t bytes) {
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Off-diagonal tiles of the subdomain factors rescaled to the unit
+// block-lower form U_IJ = L_IJ L_JJ^{-1}: with Delta the diagonal blocks of
+// the Cholesky factor L, A = U Delta Delta^T U^T, so the substitution sweeps
+// take the diagonal blocks off their dependent chain (forward and backward
+// with the unit factor U, the block-diagonal solve in between).  Run after
+// the factorisation is complete; the diagonal tiles (holding L_JJ^{-1}) are
+// read, not changed.  One workgroup per tile row.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_unit_lower(const int32_t* __restrict__ nt,
+                                                             const int64_t* __restrict__ off,
+                                                             const int64_t* __restrict__ xoff,
+                                                             const int32_t* __restrict__ tlo,
+                                                             const int32_t* __restrict__ trb,
+                                                             T* __restrict__ fac) {
+  const int b = blockIdx.y, I = blockIdx.x;
+  if (I >= nt[b]) return;
+  constexpr int S = LdsV<T>::v;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * S;
+  const int64_t trow = xoff[b] / TS;
+  const Env ix{tlo + trow, trb + trow};
+  T* F = fac + off[b] * TS2;
+  for (int J = ix.first(I); J < I; ++J) {
+    __syncthreads();
+    stage_tile(sA, F + ix(I, J) * TS2);      // L_IJ
+    stage_tile_t(sB, F + ix(J, J) * TS2);    // (L_JJ^{-1})^T
+    __syncthreads();
+    TileAcc<T> out;
+    out.zero();
+    tile_mma<T>(out, sA, sB, T(1));          // L_IJ L_JJ^{-1}
+    out.store(F + ix(I, J) * TS2);
+  }
+}
+
+template <typename T>
+void launch_unit_lower(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* xoff,
+                       const int32_t* tlo, const int32_t* trb, T* fac, hipStream_t s) {
+  const size_t sh = 2 * (size_t)TS * LdsV<T>::v * sizeof(T);
+  static bool once = (allow_lds(k_unit_lower<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_unit_lower<T>, dim3(max_nt, nb), dim3(TILE_THREADS), sh, s, nt, off, xoff, tlo, trb, fac);
+}
+
 template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
@@ -1118,6 +1162,8 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 }
 
 #define INST(T)                                                                                    \
+  template void launch_unit_lower<T>(int, int, const int32_t*, const int64_t*, const int64_t*,     \
+                                     const int32_t*, const int32_t*, T*, hipStream_t);              \
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
                                      const int64_t*, T*, int32_t*, hipStream_t);                   \
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, const int64_t*,          \

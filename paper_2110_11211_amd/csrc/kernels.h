@@ -83,10 +83,13 @@ void launch_build_nbr(const Batch& B, const int32_t* pos, const int32_t* sfc_ind
 // diagonal-level order, envelope).  lperm (per local row, at xoff) and
 // liperm (per subdomain offset, at doff) map local rows to subdomain offsets
 // and back; tlo / trb (per tile row, at xoff / TS) hold the first tile column
-// and the packed row base; gtiles[2 g] += tiles stored for grid g's
-// subdomains, gtiles[2 g + 1] += factor entries one substitution sweep reads.
+// and the packed row base; gtiles[3 g] += tiles stored for grid g's
+// subdomains, gtiles[3 g + 1] += factor entries one substitution sweep reads,
+// gtiles[3 g + 2] += tile products of their factorisation.  kcap: the
+// diagonal key levels a subdomain may span (at most ORDER_MAX_KEYS; wider
+// subdomains keep the curve order).
 constexpr int ORDER_MAX_KEYS = 16384;
-void launch_local_order(const Batch& B, int mode, int max_nt, const int32_t* ta, const int32_t* Ni,
+void launch_local_order(const Batch& B, int mode, int kcap, int max_nt, const int32_t* ta, const int32_t* Ni,
                         const int32_t* nt, const int64_t* xoff, const int64_t* doff, const int32_t* sfc_index,
                         const int32_t* nbr, int32_t* lperm, int32_t* liperm, int32_t* tlo, int32_t* trb,
                         unsigned long long* gtiles, hipStream_t s);
@@ -118,6 +121,12 @@ int potrf_full_max_rows(bool fp64, bool pair);
 template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
                        const int32_t* trb, T* fac, int32_t* status, bool pair, hipStream_t s, int rows = 0);
+// Rescales the off-diagonal envelope tiles of factored subdomain matrices to
+// U_IJ = L_IJ L_JJ^{-1} (the unit block-lower factor the substitution kernel
+// uses).
+template <typename T>
+void launch_unit_lower(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* xoff,
+                       const int32_t* tlo, const int32_t* trb, T* fac, hipStream_t s);
 // One matrix: sub-diagonal tiles of column J, the diagonal tile of column
 // J + 1, and the split-K partials of column J + 2 (three slots of slot_tiles
 // tiles at part, slot C mod 3 for column C).
@@ -146,12 +155,13 @@ void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, 
 // many waves per workgroup.  The launcher lowers the waves until it does.
 bool trsv_fits(int max_nt, int elem_bytes, int waves);
 // Factors stored as tile envelopes in the local order lperm (see
-// launch_local_order).
+// launch_local_order), off-diagonal tiles in the unit block-lower form (see
+// launch_unit_lower); ztile: a TS x TS tile of zeros.
 template <typename T>
 void launch_schwarz_trsv(const Batch& B, const int32_t* ta, const int32_t* Ni, const int32_t* nt,
                          const int64_t* off, const int64_t* doff, const int64_t* xoff, const int32_t* lperm,
                          const int32_t* tlo, const int32_t* trb, int max_nt, int waves, bool stream,
-                         const T* fac, const double* w, double* dbuf, const int32_t* active,
+                         const T* fac, const T* ztile, const double* w, double* dbuf, const int32_t* active,
                          hipStream_t s);
 template <typename T>
 void launch_symv_tiles(int nb, int max_nt, const BatchMeta& bm, const T* M, const T* xloc, T* part,

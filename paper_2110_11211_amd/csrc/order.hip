@@ -20,14 +20,15 @@
 //  4. first nonzero column of every local row from the stencil neighbours,
 //     the first tile column lo[I] of every tile row (made non-decreasing),
 //     and the packed row bases rb[I]: tile (I, J), lo[I] <= J <= I, is tile
-//     rb[I] + J of the subdomain's factor; gtiles[2 g] and gtiles[2 g + 1]
-//     of its grid g accumulate the tiles stored and the factor entries one
-//     substitution sweep reads (the off-diagonal tiles and the lower
-//     triangles of the diagonal tiles, padding rows excluded).
+//     rb[I] + J of the subdomain's factor; gtiles[3 g .. 3 g + 2] of its grid
+//     g accumulate the tiles stored, the factor entries one substitution
+//     sweep reads (the off-diagonal tiles and the lower triangles of the
+//     diagonal tiles, padding rows excluded) and the tile products of the
+//     factorisation.
 // mode 0 keeps the curve order and every tile (lo = 0: the packed triangle),
 // mode 1 the curve order with its envelope, mode 2 the diagonal order with
-// its envelope (curve order when d = 1 or the key range exceeds
-// ORDER_MAX_KEYS).
+// its envelope (curve order when d = 1, for subdomains of one tile row, or
+// when the key range exceeds kcap).
 #include "common.h"
 #include "kernels.h"
 
@@ -54,7 +55,7 @@ __device__ __forceinline__ int order_key(const GridDesc& g, int nat, const int* 
 }
 
 __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
-    Batch B, int mode, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
+    Batch B, int mode, int kcap, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
     const int32_t* __restrict__ nt, const int64_t* __restrict__ xoff, const int64_t* __restrict__ doff,
     const int32_t* __restrict__ sfc_index, const int32_t* __restrict__ nbr, int32_t* __restrict__ lperm,
     int32_t* __restrict__ liperm, int32_t* __restrict__ tlo, int32_t* __restrict__ trb,
@@ -71,10 +72,11 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
   const int tid = threadIdx.x, lane = tid & 63;
   __shared__ int bmin[MAXD], bmax[MAXD];
   __shared__ int s_best, s_bestw, s_range, s_red[ORDER_THREADS / 64];
-  extern __shared__ int hist[];         // ORDER_MAX_KEYS counters, then ntb tile-row minima
-  int* tmin = hist + ORDER_MAX_KEYS;
+  extern __shared__ int hist[];         // kcap level counters, then ntb tile-row minima
+  int* tmin = hist + kcap;
 
-  bool diag = mode == 2 && g.d >= 2 && n > 1;
+  // a subdomain of one tile row has nothing to gain from reordering
+  bool diag = mode == 2 && g.d >= 2 && ntb > 1;
   if (diag) {
     if (tid < g.d) {
       bmin[tid] = INT32_MAX;
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
       s_bestw = INT32_MAX;
     }
     __syncthreads();
-    diag = s_range <= ORDER_MAX_KEYS;
+    diag = s_range <= kcap;
   }
   if (diag) {
     const int R = s_range;
@@ -201,28 +203,34 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
       lo = min(lo, tmin[I]);
       tmin[I] = lo;
     }
-    int64_t start = 0, entries = 0;
+    int64_t start = 0, entries = 0, products = 0;
     for (int I = 0; I < ntb; ++I) {
       tlo[trow + I] = tmin[I];
       trb[trow + I] = (int32_t)(start - tmin[I]);
       start += I - tmin[I] + 1;
       const int64_t rows = min(TS, n - I * TS);   // rows of the tile row that are not padding
       entries += rows * TS * (I - tmin[I]) + rows * (rows + 1) / 2;
+      // tile products of the left-looking factorisation: the diagonal tile
+      // takes I - lo[I] updates; a tile (I, J) takes J - lo[I] updates and
+      // the product with L_JJ^{-T}
+      products += I - tmin[I];
+      for (int J = tmin[I]; J < I; ++J) products += J - tmin[I] + 1;
     }
-    atomicAdd(&gtiles[2 * gi], (unsigned long long)start);
-    atomicAdd(&gtiles[2 * gi + 1], (unsigned long long)entries);
+    atomicAdd(&gtiles[3 * gi], (unsigned long long)start);
+    atomicAdd(&gtiles[3 * gi + 1], (unsigned long long)entries);
+    atomicAdd(&gtiles[3 * gi + 2], (unsigned long long)products);
   }
 }
 
-void launch_local_order(const Batch& B, int mode, int max_nt, const int32_t* ta, const int32_t* Ni,
+void launch_local_order(const Batch& B, int mode, int kcap, int max_nt, const int32_t* ta, const int32_t* Ni,
                         const int32_t* nt, const int64_t* xoff, const int64_t* doff, const int32_t* sfc_index,
                         const int32_t* nbr, int32_t* lperm, int32_t* liperm, int32_t* tlo, int32_t* trb,
                         unsigned long long* gtiles, hipStream_t s) {
-  const size_t sh = ((size_t)ORDER_MAX_KEYS + (size_t)max_nt) * sizeof(int);
+  const size_t sh = ((size_t)kcap + (size_t)max_nt) * sizeof(int);
   if (sh > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_local_order),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL(k_local_order, dim3(B.Ptot), dim3(ORDER_THREADS), sh, s, B, mode, ta, Ni, nt, xoff, doff,
+  hipLaunchKernelGGL(k_local_order, dim3(B.Ptot), dim3(ORDER_THREADS), sh, s, B, mode, kcap, ta, Ni, nt, xoff, doff,
                      sfc_index, nbr, lperm, liperm, tlo, trb, gtiles);
 }
 

@@ -93,6 +93,7 @@ struct sfcdd_ctx {
   int64_t sum_Ni = 0, tiles = 0, parts = 0, xlen = 0, ctiles = 0, cparts = 0, c0len = 0;
   int64_t ctinv = 0;  // tiles of the coarse inversion workspace (all grids)
   int trsv_waves = 16;
+  int trsv_stream = -1;  // non-temporal factor loads: -1 by the size rule, 0 off, 1 on (autotuned)
   int spmv_u = 2, spmv_win = 512;   // SpMV launch shape (autotuned)
   int factor_rows = 0, factor_pair = -1;  // batched factorisation shape (0 / -1: rules)
   // workspace regions
@@ -100,7 +101,7 @@ struct sfcdd_ctx {
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
       r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout,
       r_ideg, r_icol, r_ival, r_ibjt, r_ibjm, r_ibjnt, r_ibjoff, r_ivec, r_icagg, r_idagg, r_iqpart, r_ipart,
-      r_lperm, r_liperm, r_tlo, r_trb, r_gtiles;
+      r_lperm, r_liperm, r_tlo, r_trb, r_gtiles, r_ztile;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // device pointers
@@ -112,7 +113,8 @@ struct sfcdd_ctx {
   double* d_omega = nullptr;
   // local elimination order and tile envelopes of the subdomain factors
   int32_t *lperm = nullptr, *liperm = nullptr, *tlo = nullptr, *trb = nullptr;
-  unsigned long long* gtiles = nullptr;   // per grid: tiles stored, entries per sweep
+  unsigned long long* gtiles = nullptr;   // per grid: tiles stored, entries per sweep, tile products
+  void* ztile = nullptr;                  // a tile of zeros (the substitution kernel's unused slots)
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
   double* cy = nullptr;  // tile-padded coarse vector X_0 R_0 v between the two products
@@ -651,7 +653,8 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_liperm = pl.take(4 * (size_t)c->sum_Ni);
   c->r_tlo = pl.take(4 * (size_t)(c->xlen / TS));
   c->r_trb = pl.take(4 * (size_t)(c->xlen / TS));
-  c->r_gtiles = pl.take(16 * (size_t)G);
+  c->r_gtiles = pl.take(24 * (size_t)G);
+  c->r_ztile = pl.take((size_t)TS2 * 8);
   if (c->coarse_iter) {
     const GridDesc& g = c->grid[0].desc;
     c->ic_nt = g.nt0;
@@ -732,6 +735,7 @@ void bind(sfcdd_ctx* c) {
   c->tlo = at<int32_t>(c, c->r_tlo);
   c->trb = at<int32_t>(c, c->r_trb);
   c->gtiles = at<unsigned long long>(c, c->r_gtiles);
+  c->ztile = at<void>(c, c->r_ztile);
   if (c->coarse_iter) {
     c->ideg = at<int32_t>(c, c->r_ideg);
     c->icol = at<int32_t>(c, c->r_icol);
@@ -842,39 +846,26 @@ void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) 
 }
 
 // Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
-// Whether the substitution streams its factors with non-temporal loads: only
-// when the factors that one sweep has in flight (about 512 subdomains at a
-// time) exceed the 256 MB last-level cache.  Smaller working sets are read
-// faster without the hint: small subdomains find their tiles again in the
-// caches on the backward sweep, and a few grids still iterating find them
-// there in the next iteration.  "Being solved" means all grids, or those
-// still iterating as of the host's last look.
-constexpr int64_t STREAM_FACTOR_BYTES = int64_t(256) << 20;
-bool stream_factors(const sfcdd_ctx* c, const int32_t* mask) {
-  const bool all = !mask || (int)c->active_shadow.size() != c->G;
-  int64_t bytes = 0, nsub = 0;
-  for (int g = 0; g < c->G; ++g)
-    if (all || act_updating(c->active_shadow[g])) {
-      bytes += c->gfac_bytes[g];
-      nsub += c->grid[g].desc.P;
-    }
-  if (nsub == 0 || bytes <= STREAM_FACTOR_BYTES) return false;
-  return (double)bytes / (double)nsub * (double)std::min<int64_t>(nsub, 512) > (double)STREAM_FACTOR_BYTES;
-}
+// Whether the substitution kernel reads its factors with the non-temporal
+// hint: off unless the tuner found it faster.  The tile envelopes are read
+// faster without it both at a few hundred MB (the backward sweep finds the
+// tiles of the forward sweep's last rows again in the last-level cache) and
+// at several GB.
+bool stream_factors(const sfcdd_ctx* c) { return c->trsv_stream > 0; }
 
 void local_solves(sfcdd_ctx* c, const double* w, int waves, const int32_t* mask = nullptr) {
   const hipStream_t s = c->stream;
   const Batch B = c->batch();
   if (c->local_solver == SFCDD_LOCAL_CHOLESKY) {
-    const bool nt = stream_factors(c, mask);
+    const bool nt = stream_factors(c);
     if (c->fdtype == SFCDD_FP32)
       launch_schwarz_trsv<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->d_xoff, c->lperm, c->tlo,
                                  c->trb, c->max_nt, waves, nt,
-                                 (const float*)c->fac, w, c->dbuf, mask, s);
+                                 (const float*)c->fac, (const float*)c->ztile, w, c->dbuf, mask, s);
     else
       launch_schwarz_trsv<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_doff, c->d_xoff, c->lperm, c->tlo,
                                   c->trb, c->max_nt, waves, nt,
-                                  (const double*)c->fac, w, c->dbuf, mask, s);
+                                  (const double*)c->fac, (const double*)c->ztile, w, c->dbuf, mask, s);
   } else {
     BatchMeta bm{c->d_nt, c->d_off, c->d_xoff, c->d_poff};
     if (c->fdtype == SFCDD_FP32) {
@@ -1192,8 +1183,16 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   // local elimination order and tile envelopes, then the local matrices
   // A_i = R_i A R_i^T in that order (only the envelope tiles are written)
   HIPCHK(c, hipMemsetAsync(c->gtiles, 0, c->r_gtiles.bytes, s));
+  HIPCHK(c, hipMemsetAsync(c->ztile, 0, c->r_ztile.bytes, s));
   const int omode = c->local_order == SFCDD_ORDER_DIAGONAL ? 2 : c->local_order == SFCDD_ORDER_CURVE ? 1 : 0;
-  launch_local_order(B, omode, c->max_nt, c->d_ta, c->d_Ni, c->d_nt, c->d_xoff, c->d_doff, c->sfc_index, c->nbr,
+  // key levels: at most the sum of the grid extents of the widest grid
+  int kcap = 1;
+  for (int k = 0; k < G; ++k) {
+    int r = 1;
+    for (int j = 0; j < c->grid[k].desc.d; ++j) r += c->grid[k].desc.n[j] - 1;
+    kcap = std::max(kcap, std::min(r, ORDER_MAX_KEYS));
+  }
+  launch_local_order(B, omode, kcap, c->max_nt, c->d_ta, c->d_Ni, c->d_nt, c->d_xoff, c->d_doff, c->sfc_index, c->nbr,
                      c->lperm, c->liperm, c->tlo, c->trb, c->gtiles, s);
   if (c->fdtype == SFCDD_FP32)
     launch_assemble_local<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm, c->liperm,
@@ -1223,6 +1222,13 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
                          c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s, c->factor_rows,
                          c->d_xoff, c->tlo, c->trb);
+  // the substitution kernel sweeps with the unit block-lower factor
+  if (!inv) {
+    if (c->fdtype == SFCDD_FP32)
+      launch_unit_lower<float>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (float*)c->fac, s);
+    else
+      launch_unit_lower<double>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (double*)c->fac, s);
+  }
   c->info.factor_pair = pair ? 1 : 0;
   c->info.factor_rows = c->factor_rows > 0 ? c->factor_rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
   HIPCHK(c, hipGetLastError());
@@ -1253,16 +1259,22 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.sum_Ni = c->sum_Ni;
   const int64_t es = c->fdtype == SFCDD_FP32 ? 4 : 8;
   {
-    std::vector<unsigned long long> gt(2 * (size_t)G);
-    HIPCHK(c, hipMemcpy(gt.data(), c->gtiles, 16 * (size_t)G, hipMemcpyDeviceToHost));
-    int64_t tiles = 0, entries = 0;
+    std::vector<unsigned long long> gt(3 * (size_t)G);
+    HIPCHK(c, hipMemcpy(gt.data(), c->gtiles, 24 * (size_t)G, hipMemcpyDeviceToHost));
+    int64_t tiles = 0, entries = 0, diag = 0;
+    double products = 0.0;
     for (int k = 0; k < G; ++k) {
-      c->gfac_bytes[k] = (int64_t)gt[2 * k] * TS2 * es;
-      tiles += (int64_t)gt[2 * k];
-      entries += (int64_t)gt[2 * k + 1];
+      c->gfac_bytes[k] = (int64_t)gt[3 * k] * TS2 * es;
+      tiles += (int64_t)gt[3 * k];
+      entries += (int64_t)gt[3 * k + 1];
+      products += (double)gt[3 * k + 2];
     }
+    for (int i = 0; i < Pt; ++i) diag += c->nt[i];
     I.factor_bytes = tiles * TS2 * es;
     I.factor_algo_bytes = entries * es;
+    // every tile product 2 TS^3; a diagonal tile's Cholesky and inversion
+    // TS^3 / 3 each
+    I.factor_flops = products * 2.0 * TS * TS * TS + (double)diag * 2.0 * TS * TS * TS / 3.0;
   }
   I.local_order = c->local_order;
   I.coarse_bytes = (int64_t)c->r_A0.bytes;
@@ -1372,7 +1384,10 @@ void apply_recorded_shapes(sfcdd_ctx* c) {
   if (hipGetDevice(&dev) != hipSuccess) return;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto t = g_tune_trsv.find(key_trsv(c, dev));
-  if (t != g_tune_trsv.end()) c->trsv_waves = t->second.a;
+  if (t != g_tune_trsv.end()) {
+    c->trsv_waves = t->second.a;
+    c->trsv_stream = t->second.b;
+  }
   auto v = g_tune_spmv.find(key_spmv(c, dev));
   if (v != g_tune_spmv.end()) {
     c->spmv_u = v->second.a;
@@ -1425,16 +1440,32 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
       if (it != g_tune_trsv.end()) { rec = it->second; have = true; }
     }
     if (!have) {
-      const int ncand = c->local_solver == SFCDD_LOCAL_CHOLESKY ? 3 : 1;
+      // waves per workgroup, and the non-temporal hint on the factor loads
+      // (factors a little larger than the last-level cache can still be
+      // re-read from it by the backward sweep)
+      const bool chol = c->local_solver == SFCDD_LOCAL_CHOLESKY;
+      const int ncand = chol ? 3 : 1;
       const int cand[3] = {16, 8, 4};
+      const int keep_stream = c->trsv_stream;
+      c->trsv_stream = -1;
+      const int rule = stream_factors(c) ? 1 : 0;
       rec.a = c->trsv_waves;
+      rec.b = -1;
       rec.t = 1e300;
-      for (int k = 0; k < ncand && st == SFCDD_OK; ++k) {
-        double ms = 0.0;
-        st = timed([&] { local_solves(c, w, cand[k], nullptr); }, &ms);
-        if (k == 0) rec.t_default = ms;
-        if (ms < rec.t) { rec.t = ms; rec.a = ncand > 1 ? cand[k] : c->trsv_waves; }
+      for (int h = 0; h < (chol ? 2 : 1) && st == SFCDD_OK; ++h) {
+        c->trsv_stream = h == 0 ? rule : 1 - rule;
+        for (int k = 0; k < ncand && st == SFCDD_OK; ++k) {
+          double ms = 0.0;
+          st = timed([&] { local_solves(c, w, cand[k], nullptr); }, &ms);
+          if (h == 0 && k == 0) rec.t_default = ms;
+          if (ms < rec.t) {
+            rec.t = ms;
+            rec.a = ncand > 1 ? cand[k] : c->trsv_waves;
+            rec.b = chol ? c->trsv_stream : -1;
+          }
+        }
       }
+      c->trsv_stream = keep_stream;
       if (st == SFCDD_OK) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_trsv[key] = rec;
@@ -1442,6 +1473,7 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
       r->tuned |= SFCDD_TUNE_TRSV;
     }
     c->trsv_waves = rec.a;
+    c->trsv_stream = rec.b;
     r->trsv_ms = rec.t;
     r->trsv_default_ms = rec.t_default;
   }
@@ -1538,6 +1570,7 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
     r->setup_default_ms = rec.t_default;
   }
   r->trsv_waves = c->trsv_waves;
+  r->trsv_stream = c->trsv_stream;
   r->spmv_points = c->spmv_u;
   r->spmv_window = c->spmv_win;
   r->factor_rows = c->factor_rows > 0 ? c->factor_rows : c->info.factor_rows;

@@ -320,9 +320,9 @@ def _kappa(levels):
 @pytest.mark.parametrize("curve,fdtype", [("zorder", "fp64"), ("hilbert", "fp64"), ("hilbert", "fp32")])
 def test_full_size_apply_c2_matches_oracle(curve, fdtype):
     """One preconditioner application at the d=3 workload's full size (256
-    subdomains of ~1937 points) against the oracle, in the benchmark's launch
-    configuration (default launch; with FP32 factors the 2 GB of factors take
-    the non-temporal streaming substitution).  FP32 bound: the subdomain
+    subdomains of ~1937 points) against the oracle, in the default launch
+    configuration (tile envelopes in the diagonal order, unit block-lower
+    substitution, 16 waves).  FP32 bound: the subdomain
     matrices are principal submatrices of A (kappa(A_i) <= kappa(A), about
     2.9e3 here) and their entries are exact in FP32, so an FP32 Cholesky solve
     errs by a small multiple of kappa(A) * 2^-24; the bar is 4 kappa(A) 2^-24
@@ -331,8 +331,6 @@ def test_full_size_apply_c2_matches_oracle(curve, fdtype):
     announce("full-size apply c2", curve, fdtype)
     O = _c2_oracle(curve)
     S = _solver(w.levels[0], w.P, w.gamma, factor_dtype=fdtype, curve=curve)
-    if fdtype == "fp32":
-        assert S.info()["factor_bytes"] > 256 << 20   # the streaming (non-temporal) path
     r = uniform_pm1(31, O.N)
     e = relerr(host(S.apply(dvec(r))), O.apply(r))
     tol = FP64_TOL if fdtype == "fp64" else 4.0 * _kappa(w.levels[0]) * 2.0 ** -24
