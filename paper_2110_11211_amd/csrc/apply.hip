@@ -339,7 +339,8 @@ void launch_scatter(const Batch& B, int dweight, const int32_t* ta, const int32_
 // ---------------------------------------------------------------------------
 // Coarse restriction c0 = R_0 v (eq. restr): block (i, m) is a contiguous
 // curve range; one wave per coarse unknown.  c0 is stored per grid padded to
-// whole tiles (offset c0pad).
+// whole tiles (offset c0pad), in the coarse elimination order (block k at
+// position cperm[k]).
 
 // R_0 v: the sum of v over each coarse block (a contiguous curve range), LPU
 // lanes per coarse unknown summing in a fixed order (lane-strided partial
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(256) void k_restrict(Batch B, const double* __restr
     for (int64_t e = lane; e < sz; e += LPU) acc += vg[e];
   }
   for (int o = LPU / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (valid && lane == 0) c0[gp->c0pad + I] = acc;
+  if (valid && lane == 0) c0[gp->c0pad + B.cperm[Ig]] = acc;
 }
 
 void launch_restrict(const Batch& B, int max_block, const double* v, double* c0, hipStream_t s) {
@@ -382,7 +383,7 @@ __global__ void k_combine(Batch B, const double* __restrict__ d0, const double* 
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < B.Ntot;
        p += (int64_t)gridDim.x * blockDim.x) {
     const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
-    const double t = d0[g.c0off + coarse_block(p - g.goff, g)];
+    const double t = d0[g.c0off + B.cperm[g.c0off + coarse_block(p - g.goff, g)]];
     if (MODE == COMB_PROLONG) out[p] = t;
     if (MODE == COMB_ADD_PROLONG) out[p] = a[p] + t;
     if (MODE == COMB_BAL_FINAL) out[p] = a[p] - t + b[p];

@@ -193,6 +193,45 @@ __device__ __forceinline__ void tile_mma(TileAcc<T>& acc, const T* __restrict__ 
   }
 }
 
+// acc -= the n row-major tiles at base + c stride, c < n: the loads of four
+// tiles are issued before their subtractions, so their latencies overlap.
+template <typename T>
+__device__ __forceinline__ void sub_tiles(TileAcc<T>& acc, const T* __restrict__ base, int64_t stride, int n) {
+  int c = 0;
+  for (; c + 4 <= n; c += 4) {
+    T t[4][2][2][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            t[q][a][b][r] = base[(c + q) * stride + TileAcc<T>::row(a, r) * TS + TileAcc<T>::col(b)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc.c[a][b][r] -= t[q][a][b][r];
+  }
+  for (; c < n; ++c) acc.sub(base + c * stride);
+}
+
+// Workgroup barrier that orders the LDS accesses only.  A plain
+// __syncthreads also waits for every outstanding global load (loads and
+// stores share one counter on this architecture), which would drain register
+// prefetches; this one is for barriers that guard LDS reuse alone, with no
+// global store before it that another wave reads after it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Wave-level sum (all 64 lanes receive the result).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

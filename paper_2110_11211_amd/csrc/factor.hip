@@ -256,7 +256,7 @@ __device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restr
 // above its diagonal serve as scratch.
 template <typename T>
 __device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x < 64) {
     factor_column<T, 0>(sC, sX, status);
     factor_column<T, 1>(sC, sX, status);
@@ -266,7 +266,7 @@ __device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict
     inverse_row<T, 2>(sC, sX);
     inverse_row<T, 3>(sC, sX);
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // LDS of the diagonal-tile factorisation: two Pstride tiles (C, X).  The
@@ -337,11 +337,11 @@ __device__ __forceinline__ void gemm_loop_pf(TileAcc<T>& acc, int k0, int k1, FA
       const int Kl = min(Kc + NPF, k1 - 1);
       ra[t].load(pa(Kl));
       if (!SYRK) rb[t].load(pb(Kl));
-      __syncthreads();
+      lds_barrier();
       if (Kc < k1) tile_mma<T>(acc, buf, SYRK ? buf : buf + TS * S, sign);
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 template <typename T, bool DBUF = false, typename IX = Tri>
@@ -352,7 +352,10 @@ __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc
   kfrom = max(kfrom, ix.first(J));
   TileAcc<T> acc;
   acc.load(F + ix(J, J) * TS2);
-  for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)J * maxc + c) * TS2);
+  {
+    const int c0 = min(nparts, ix.first(J) / SPLITK);   // chunks left of the envelope were not formed
+    sub_tiles(acc, part + ((int64_t)J * maxc + c0) * TS2, TS2, nparts - c0);
+  }
   if (DBUF) {
     auto pj = [&](int K) { return F + ix(J, K) * TS2; };
     gemm_loop_pf<FACTOR_PF, true, T>(acc, kfrom, J, pj, pj, sA, T(-1));
@@ -360,14 +363,14 @@ __device__ __forceinline__ void diag_tile(int J, int kfrom, int nparts, int maxc
     TileRegs<T> ra;
     if (kfrom < J) ra.load(F + ix(J, kfrom) * TS2);
     for (int K = kfrom; K < J; ++K) {
-      __syncthreads();
+      lds_barrier();
       ra.store_lds(sA);
-      __syncthreads();
+      lds_barrier();
       if (K + 1 < J) ra.load(F + ix(J, K + 1) * TS2);
       tile_mma<T>(acc, sA, sA, T(-1));  // A_JJ -= L_JK L_JK^T
     }
   }
-  __syncthreads();
+  lds_barrier();
   constexpr int PS = Pstride<T>::v;
   T* sC = reinterpret_cast<T*>(smem_raw);
   T* sX = sC + TS * PS;
@@ -389,70 +392,80 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
                                                              const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
-                                                             int32_t* __restrict__ status) {
+                                                             int32_t* __restrict__ status,
+                                                             const int32_t* __restrict__ tlo,
+                                                             const int32_t* __restrict__ trb) {
   __builtin_amdgcn_s_setprio(3);  // head of the same chain as k_potrf_step
   const int b = blockIdx.x;
   if (J >= nt[b]) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  diag_tile<T>(J, kfrom, nparts, maxc, part, fac + off[b] * TS2, status, smem_raw);
+  diag_tile<T, false, Env>(J, kfrom, nparts, maxc, part, fac + off[b] * TS2, status, smem_raw, Env{tlo, trb});
 }
 
 // Sub-diagonal tile (I, J): A_IJ - sum_{K<J} L_IK L_JK^T (terms K >= kfrom
-// here, the others from nparts partial tiles), times L_JJ^{-T}.
-template <typename T, bool DBUF = false>
+// here, the others from nparts partial tiles), times L_JJ^{-T}.  Row I takes
+// the terms K >= lo[I] only (and the partial chunks from lo[I] / SPLITK).
+template <typename T, bool DBUF = false, typename IX = Tri>
 __device__ __forceinline__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const T* __restrict__ part,
-                           T* __restrict__ F, T* sA, T* sB) {
+                           T* __restrict__ F, T* sA, T* sB, IX ix = IX()) {
+  kfrom = max(kfrom, ix.first(I));
   TileAcc<T> acc;
-  acc.load(F + tri_index(I, J) * TS2);
-  for (int c = 0; c < nparts; ++c) acc.sub(part + ((int64_t)I * maxc + c) * TS2);
+  acc.load(F + ix(I, J) * TS2);
+  {
+    const int c0 = min(nparts, ix.first(I) / SPLITK);
+    sub_tiles(acc, part + ((int64_t)I * maxc + c0) * TS2, TS2, nparts - c0);
+  }
   if (DBUF) {   // sA: four LDS tiles
-    gemm_loop_pf<FACTOR_PF, false, T>(acc, kfrom, J, [&](int K) { return F + tri_index(I, K) * TS2; },
-                                      [&](int K) { return F + tri_index(J, K) * TS2; }, sA, T(-1));
+    gemm_loop_pf<FACTOR_PF, false, T>(acc, kfrom, J, [&](int K) { return F + ix(I, K) * TS2; },
+                                      [&](int K) { return F + ix(J, K) * TS2; }, sA, T(-1));
   } else {
     TileRegs<T> ra, rb;
     if (kfrom < J) {
-      ra.load(F + tri_index(I, kfrom) * TS2);
-      rb.load(F + tri_index(J, kfrom) * TS2);
+      ra.load(F + ix(I, kfrom) * TS2);
+      rb.load(F + ix(J, kfrom) * TS2);
     }
     for (int K = kfrom; K < J; ++K) {
-      __syncthreads();
+      lds_barrier();
       ra.store_lds(sA);
       rb.store_lds(sB);
-      __syncthreads();
+      lds_barrier();
       if (K + 1 < J) {
-        ra.load(F + tri_index(I, K + 1) * TS2);
-        rb.load(F + tri_index(J, K + 1) * TS2);
+        ra.load(F + ix(I, K + 1) * TS2);
+        rb.load(F + ix(J, K + 1) * TS2);
       }
       tile_mma<T>(acc, sA, sB, T(-1));  // A_IJ -= L_IK L_JK^T
     }
   }
-  __syncthreads();
+  lds_barrier();
   acc.store_lds(sA);
-  stage_tile(sB, F + tri_index(J, J) * TS2);      // L_JJ^{-1}
-  __syncthreads();
+  stage_tile(sB, F + ix(J, J) * TS2);      // L_JJ^{-1}
+  lds_barrier();
   TileAcc<T> out;
   out.zero();
   tile_mma<T>(out, sA, sB, T(1));     // L_IJ = A_IJ L_JJ^{-T}
-  out.store(F + tri_index(I, J) * TS2);
+  out.store(F + ix(I, J) * TS2);
 }
 
-// Partial update of column Jn: part[I][c] = sum_{K = k0}^{k1 - 1} L_IK L_JnK^T.
-template <typename T>
+// Partial update of column Jn: part[I][c] = sum_{K = k0}^{k1 - 1} L_IK L_JnK^T
+// (zero when the range is empty).
+template <typename T, typename IX = Tri>
 __device__ __forceinline__ void partial_tile(int Jn, int I, int c, int k0, int k1, int maxc, const T* __restrict__ F,
-                             T* __restrict__ part, T* sA, T* sB) {
+                             T* __restrict__ part, T* sA, T* sB, IX ix = IX()) {
   TileAcc<T> acc;
   acc.zero();
   TileRegs<T> ra, rb;
-  ra.load(F + tri_index(I, k0) * TS2);
-  rb.load(F + tri_index(Jn, k0) * TS2);
+  if (k0 < k1) {
+    ra.load(F + ix(I, k0) * TS2);
+    rb.load(F + ix(Jn, k0) * TS2);
+  }
   for (int K = k0; K < k1; ++K) {
-    __syncthreads();
+    lds_barrier();
     ra.store_lds(sA);
     rb.store_lds(sB);
-    __syncthreads();
+    lds_barrier();
     if (K + 1 < k1) {
-      ra.load(F + tri_index(I, K + 1) * TS2);
-      rb.load(F + tri_index(Jn, K + 1) * TS2);
+      ra.load(F + ix(I, K + 1) * TS2);
+      rb.load(F + ix(Jn, K + 1) * TS2);
     }
     tile_mma<T>(acc, sA, sB, T(1));
   }
@@ -538,12 +551,12 @@ __device__ __forceinline__ void panel_rows(int J, int kfrom, int I0, int nr, T* 
   }
   for (int K = k0; K < J; ++K) {
     const int nk = rows_upto<R>(lor, nr, K);
-    __syncthreads();  // the products of step K - 1 have read the tiles
+    lds_barrier();  // the products of step K - 1 have read the tiles
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (r < nk) ra[r].store_lds(lds + r * TS * S);
     rb.store_lds(sB);
-    __syncthreads();
+    lds_barrier();
     if (K + 1 < J) {
       const int n1 = rows_upto<R>(lor, nr, K + 1);
 #pragma unroll
@@ -553,12 +566,12 @@ __device__ __forceinline__ void panel_rows(int J, int kfrom, int I0, int nr, T* 
     }
     tile_mma_rows<T, R>(acc, nk, lds, sB, T(-1));  // A_IJ -= L_IK L_JK^T
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (r < nr) acc[r].store_lds(lds + r * TS * S);
   stage_tile(sB, F + ix(J, J) * TS2);  // L_JJ^{-1}
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r < nr) {
@@ -657,13 +670,13 @@ __device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__
   }
   for (int K = k0; K < J; ++K) {
     const int nk = rows_upto<R>(lor, nr, K);
-    __syncthreads();  // the products of step K - 1 have read the tiles
+    lds_barrier();  // the products of step K - 1 have read the tiles
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (r < nk) ra[r].store_lds(lds + r * TS * S);
     rb0.store_lds(sB0);
     if (K >= lo1) rb1.store_lds(sB1);
-    __syncthreads();
+    lds_barrier();
     if (K + 1 < J) {
       const int n1 = rows_upto<R>(lor, nr, K + 1);
 #pragma unroll
@@ -763,7 +776,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
                                                              const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              T* __restrict__ fac,
-                                                             int32_t* __restrict__ status) {
+                                                             int32_t* __restrict__ status,
+                                                             const int32_t* __restrict__ tlo,
+                                                             const int32_t* __restrict__ trb) {
   // The steps form a chain of dependent launches that runs beside the
   // throughput-bound batched factorisation of the subdomains; the highest
   // wave priority lets its instructions issue first on the shared SIMDs
@@ -773,6 +788,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
   const int ntb = nt[0];
   const int m = ntb - 1 - J;  // tiles below the diagonal in column J
   if (m <= 0) return;
+  const Env ix{tlo, trb};
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LdsV<T>::v;
@@ -783,18 +799,25 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
   const int kd = J >= 2 ? J - 2 : 0;
   const int nc_j = J >= 3 ? (J - 2 + SPLITK - 1) / SPLITK : 0;
   if (x < m) {
-    panel_tile<T>(J, J + 1 + x, kd, nc_j, maxc, slot(J), F, sA, sB);
+    const int I = J + 1 + x;
+    // rows whose envelope starts right of column J have no tile in it
+    if (ix.first(I) <= J) panel_tile<T, false, Env>(J, I, kd, nc_j, maxc, slot(J), F, sA, sB, ix);
     if (x > 0) return;
     __syncthreads();
     // diagonal tile J + 1: partials over K <= J - 2, direct K = J - 1, J
     const int nc_d = J >= 2 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
-    diag_tile<T>(J + 1, J >= 1 ? J - 1 : 0, nc_d, maxc, slot(J + 1), F, status, smem_raw);
+    diag_tile<T, false, Env>(J + 1, J >= 1 ? J - 1 : 0, nc_d, maxc, slot(J + 1), F, status, smem_raw, ix);
     return;
   }
-  // partials of column J + 2 over K = 0 .. J - 1, rows J + 2 .. ntb - 1
+  // partials of column J + 2 over K = 0 .. J - 1, rows J + 2 .. ntb - 1; a
+  // row takes the chunks from lo[I] / SPLITK on (its terms K >= lo[I]), and
+  // rows with no tile in column J + 2 none
   const int y = x - m, mr = m - 1;
   const int I = J + 2 + y % mr, c = y / mr;
-  partial_tile<T>(J + 2, I, c, c * SPLITK, min(J, (c + 1) * SPLITK), maxc, F, slot(J + 2), sA, sB);
+  const int lo = ix.first(I);
+  if (lo > J + 2 || c < lo / SPLITK) return;
+  partial_tile<T, Env>(J + 2, I, c, max(c * SPLITK, lo), min(J, (c + 1) * SPLITK), maxc, F, slot(J + 2), sA, sB,
+                       ix);
 }
 
 // The FP64 tile kernels stage two 64x65 double tiles (66.5 KB of LDS), above
@@ -829,10 +852,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_unit_lower(const int32_t* __re
   const Env ix{tlo + trow, trb + trow};
   T* F = fac + off[b] * TS2;
   for (int J = ix.first(I); J < I; ++J) {
-    __syncthreads();
+    lds_barrier();
     stage_tile(sA, F + ix(I, J) * TS2);      // L_IJ
     stage_tile_t(sB, F + ix(J, J) * TS2);    // (L_JJ^{-1})^T
-    __syncthreads();
+    lds_barrier();
     TileAcc<T> out;
     out.zero();
     tile_mma<T>(out, sA, sB, T(1));          // L_IJ L_JJ^{-1}
@@ -852,12 +875,12 @@ void launch_unit_lower(int nb, int max_nt, const int32_t* nt, const int64_t* off
 template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
-                       hipStream_t s) {
+                       hipStream_t s, const int32_t* tlo, const int32_t* trb) {
   const size_t sh = diag_lds_bytes<T>();
   static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, kfrom, nparts, maxc,
-                     part, nt, off, fac, status);
+                     part, nt, off, fac, status, tlo, trb);
 }
 template <typename T, bool PAIR, int R>
 static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
@@ -891,7 +914,8 @@ void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int6
 }
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
-                       const int64_t* off, T* fac, int32_t* status, hipStream_t s) {
+                       const int64_t* off, T* fac, int32_t* status, hipStream_t s, const int32_t* tlo,
+                       const int32_t* trb) {
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
   const int nc = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
@@ -900,7 +924,7 @@ void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles,
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg), dim3(TILE_THREADS), sh, s, J, maxc, part, slot_tiles, nt,
-                     off, fac, status);
+                     off, fac, status, tlo, trb);
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -932,20 +956,20 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_col(int J, const int32_t
   ra.load(Xb + tri_index(I, J + 1) * TS2);
   rb.load(Lb + tri_index(J + 1, J) * TS2);
   for (int K = J + 1; K <= I; ++K) {
-    __syncthreads();
+    lds_barrier();
     ra.store_lds(sA);
     rb.store_lds_t(sB);
-    __syncthreads();
+    lds_barrier();
     if (K + 1 <= I) {
       ra.load(Xb + tri_index(I, K + 1) * TS2);
       rb.load(Lb + tri_index(K + 1, J) * TS2);
     }
     tile_mma<T>(acc, sA, sB, T(1));                // acc += X_IK L_KJ
   }
-  __syncthreads();
+  lds_barrier();
   acc.store_lds(sA);
   stage_tile_t(sB, Lb + tri_index(J, J) * TS2);
-  __syncthreads();
+  lds_barrier();
   TileAcc<T> out;
   out.zero();
   tile_mma<T>(out, sA, sB, T(-1));                 // X_IJ = -acc L_JJ^{-1}
@@ -994,14 +1018,17 @@ constexpr int TRTRI_ROWS = 2;
 // T_ij = sum_{k = j}^{B0 - 1} L_ik X_kj for i in B, j in A: workgroup (jj, g)
 // forms the R tiles i = B0 + g R + r of column j = A0 + jj (one X_kj per
 // step for all of them).  Workgroups with the longest sums (small jj) are
-// dispatched first.
+// dispatched first.  With an envelope (tlo), row i takes the terms
+// k >= lo[i] only; rows whose envelope starts in B get T_ij = 0.
 template <typename T, int R>
 __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32_t* __restrict__ nt,
                                                               const int64_t* __restrict__ off,
                                                               const int64_t* __restrict__ toff,
                                                               const T* __restrict__ L,
                                                               const T* __restrict__ X,
-                                                              T* __restrict__ Tb) {
+                                                              T* __restrict__ Tb,
+                                                              const int64_t* __restrict__ xoff,
+                                                              const int32_t* __restrict__ tlo) {
   constexpr int S = LdsV<T>::v;
   const int b = blockIdx.z, p = blockIdx.y;
   const int ng = (s + R - 1) / R;
@@ -1015,28 +1042,38 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32
   T* sB = lds + R * TS * S;
   const T* Lb = L + off[b] * TS2;
   const T* Xb = X + off[b] * TS2;
+  const int32_t* lo = tlo ? tlo + xoff[b] / TS : nullptr;
+  int lor[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) lor[r] = r < nr && lo ? lo[i0 + r] : 0;
+  const int k0 = max(j, lor[0]);
   TileAcc<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r].zero();
   TileRegs<T> ra[R], rb;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (r < nr) ra[r].load(Lb + tri_index(i0 + r, j) * TS2);
-  rb.load(Xb + tri_index(j, j) * TS2);
-  for (int k = j; k < B0; ++k) {
-    __syncthreads();
+  if (k0 < B0) {
+    const int n1 = rows_upto<R>(lor, nr, k0);
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (r < nr) ra[r].store_lds(lds + r * TS * S);
+      if (r < n1) ra[r].load(Lb + tri_index(i0 + r, k0) * TS2);
+    rb.load(Xb + tri_index(k0, j) * TS2);
+  }
+  for (int k = k0; k < B0; ++k) {
+    const int nk = rows_upto<R>(lor, nr, k);
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r < nk) ra[r].store_lds(lds + r * TS * S);
     rb.store_lds_t(sB);
-    __syncthreads();
+    lds_barrier();
     if (k + 1 < B0) {
+      const int n1 = rows_upto<R>(lor, nr, k + 1);
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (r < nr) ra[r].load(Lb + tri_index(i0 + r, k + 1) * TS2);
+        if (r < n1) ra[r].load(Lb + tri_index(i0 + r, k + 1) * TS2);
       rb.load(Xb + tri_index(k + 1, j) * TS2);
     }
-    tile_mma_rows<T, R>(acc, nr, lds, sB, T(1));   // T_ij += L_ik X_kj
+    tile_mma_rows<T, R>(acc, nk, lds, sB, T(1));   // T_ij += L_ik X_kj
   }
   T* Tp = Tb + (toff[b] + (int64_t)p * s * s + (int64_t)(g * R) * s + jj) * TS2;
 #pragma unroll
@@ -1047,13 +1084,17 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32
 // X_ij = -sum_{k = B0}^{i} X_ik T_kj for i in B, j in A: workgroup (g, jj)
 // forms the R tiles i = i0, i0 - 1, .. (from the top of B down) of column
 // j; row i0 - r leaves the sum after k = i0 - r, so the rows still summing
-// are always the first ones.  Longest sums (large i) first.
+// are always the first ones.  Longest sums (large i) first.  With an
+// envelope (tlo), T_kj = 0 for the rows k of B past the last one whose
+// envelope reaches into A, and the sums stop there.
 template <typename T, int R>
 __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32_t* __restrict__ nt,
                                                               const int64_t* __restrict__ off,
                                                               const int64_t* __restrict__ toff,
                                                               const T* __restrict__ Tb,
-                                                              T* __restrict__ X) {
+                                                              T* __restrict__ X,
+                                                              const int64_t* __restrict__ xoff,
+                                                              const int32_t* __restrict__ tlo) {
   constexpr int S = LdsV<T>::v;
   const int b = blockIdx.z, p = blockIdx.y;
   const int g = blockIdx.x / s, jj = blockIdx.x % s;
@@ -1067,23 +1108,34 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
   T* sB = lds + R * TS * S;
   T* Xb = X + off[b] * TS2;
   const T* Tp = Tb + (toff[b] + (int64_t)p * s * s + jj) * TS2;  // T_kj at Tp + (k - B0) s TS2
+  // last row of B with nonzero T (its envelope reaches into A)
+  int kend = i0;
+  if (tlo) {
+    const int32_t* lo = tlo + xoff[b] / TS;
+    const int bend = min(B0 + s, nt[b]);
+    int kz = B0 - 1;
+    while (kz + 1 < bend && lo[kz + 1] < B0) ++kz;
+    kend = min(i0, kz);
+  }
   TileAcc<T> acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r].zero();
   TileRegs<T> ra[R], rb;
+  if (B0 <= kend) {
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (r < nrows) ra[r].load(Xb + tri_index(i0 - r, B0) * TS2);
-  rb.load(Tp);
-  for (int k = B0; k <= i0; ++k) {
+    for (int r = 0; r < R; ++r)
+      if (r < nrows) ra[r].load(Xb + tri_index(i0 - r, B0) * TS2);
+    rb.load(Tp);
+  }
+  for (int k = B0; k <= kend; ++k) {
     const int nr = min(nrows, i0 - k + 1);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (r < nr) ra[r].store_lds(lds + r * TS * S);
     rb.store_lds_t(sB);
-    __syncthreads();
-    if (k + 1 <= i0) {
+    lds_barrier();
+    if (k + 1 <= kend) {
       const int nr1 = min(nrows, i0 - k);
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -1099,7 +1151,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
 
 template <typename T>
 void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
-                      const T* L, T* X, T* Tb, hipStream_t st) {
+                      const T* L, T* X, T* Tb, hipStream_t st, const int64_t* xoff, const int32_t* tlo) {
   constexpr int R = TRTRI_ROWS;
   const size_t sh = (R + 1) * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_trtri_rec_t<T, R>, sh), allow_lds(k_trtri_rec_x<T, R>, sh), true);
@@ -1108,8 +1160,9 @@ void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off,
   for (int s = 1; s < max_nt; s *= 2) {
     const int npairs = (max_nt + 2 * s - 1) / (2 * s);
     const dim3 grid(s * ((s + R - 1) / R), npairs, nb);
-    hipLaunchKernelGGL((k_trtri_rec_t<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, L, X, Tb);
-    hipLaunchKernelGGL((k_trtri_rec_x<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X);
+    hipLaunchKernelGGL((k_trtri_rec_t<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, L, X, Tb, xoff,
+                       tlo);
+    hipLaunchKernelGGL((k_trtri_rec_x<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X, xoff, tlo);
   }
 }
 
@@ -1138,10 +1191,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_lauum(const int32_t* __restric
   ra.load(Xb + tri_index(I, I) * TS2);
   rb.load(Xb + tri_index(I, J) * TS2);
   for (int K = I; K < ntb; ++K) {
-    __syncthreads();
+    lds_barrier();
     ra.store_lds_t(sA);
     rb.store_lds_t(sB);
-    __syncthreads();
+    lds_barrier();
     if (K + 1 < ntb) {
       ra.load(Xb + tri_index(K + 1, I) * TS2);
       rb.load(Xb + tri_index(K + 1, J) * TS2);
@@ -1165,17 +1218,18 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
   template void launch_unit_lower<T>(int, int, const int32_t*, const int64_t*, const int64_t*,     \
                                      const int32_t*, const int32_t*, T*, hipStream_t);              \
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
-                                     const int64_t*, T*, int32_t*, hipStream_t);                   \
+                                     const int64_t*, T*, int32_t*, hipStream_t, const int32_t*,    \
+                                     const int32_t*);                                              \
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, const int64_t*,          \
                                      const int32_t*, const int32_t*, T*, int32_t*, bool,           \
                                      hipStream_t, int);                                            \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
-                                     T*, int32_t*, hipStream_t);                                   \
+                                     T*, int32_t*, hipStream_t, const int32_t*, const int32_t*);   \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \
   template void launch_trtri_rec<T>(int, int, const int32_t*, const int64_t*, const int64_t*,     \
-                                    const T*, T*, T*, hipStream_t);
+                                    const T*, T*, T*, hipStream_t, const int64_t*, const int32_t*);
 INST(float)
 INST(double)
 #undef INST

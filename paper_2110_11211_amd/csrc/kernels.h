@@ -59,6 +59,7 @@ struct Batch {
   const uint16_t* ctgid;    // grid of each coarse tile
   int rbx;                  // reduction blocks per grid
   int spmv_u, spmv_win;     // SpMV launch shape: points per thread and step, LDS window
+  const int32_t* cperm;     // position of every coarse block in its grid's coarse numbering
 };
 
 __device__ __forceinline__ int grid_of(const Batch& B, const uint16_t* ids, int64_t i) {
@@ -99,18 +100,31 @@ void launch_assemble_local(const Batch& B, const int32_t* ta, const int32_t* Ni,
                            const int64_t* fac_off, const int64_t* xoff, const int64_t* doff,
                            const int32_t* lperm, const int32_t* liperm, const int32_t* tlo, const int32_t* trb,
                            const int32_t* nbr, int max_nt, T* fac, hipStream_t s);
+// Coarse elimination order (see k_coarse_order): ccen scratch of N0tot * dmax
+// int32, cperm (N0tot), cfnz (tile-padded coarse rows, initialised to the
+// row index).
+void launch_coarse_order(const Batch& B, int kcap, int max_n0, const int32_t* sfc_index, int32_t* ccen,
+                         int32_t* cperm, int32_t* cfnz, hipStream_t s);
+// Integer coupling counts of dimension j in the permuted coarse numbering;
+// cfnz[c0pad + r] is lowered to the first nonzero column of row r.
 void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
-                          int32_t* cnt, hipStream_t s);
+                          int32_t* cnt, int32_t* cfnz, hipStream_t s);
+// Envelope tables of the dense coarse matrices (per tile row at c0pad / TS):
+// first tile column clo (non-decreasing) and packed-triangle row base crb.
+void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb,
+                       hipStream_t s);
 void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
                               hipStream_t s);
 void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, double* A0,
                        hipStream_t s);
 
 // ---- batched tiled Cholesky, inversion ----------------------------------
+// The single-matrix kernels (diag, step) take the envelope tables of matrix 0
+// (tlo / trb at its first tile row; null: every tile).
 template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
-                       hipStream_t s);
+                       hipStream_t s, const int32_t* tlo = nullptr, const int32_t* trb = nullptr);
 // Whole factorisation, one workgroup per matrix (pair: two columns per
 // step; faster alone, but no room beside it for other workgroups).
 // rows: row tiles per step of the panel updates (2 .. potrf_full_max_rows;
@@ -132,13 +146,17 @@ void launch_unit_lower(int nb, int max_nt, const int32_t* nt, const int64_t* off
 // tiles at part, slot C mod 3 for column C).
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
-                       const int64_t* off, T* fac, int32_t* status, hipStream_t s);
+                       const int64_t* off, T* fac, int32_t* status, hipStream_t s,
+                       const int32_t* tlo = nullptr, const int32_t* trb = nullptr);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);
+// xoff / tlo (nullable): envelope of each L (first tile column per tile row
+// at xoff[b] / TS); the tile sums skip the zero tiles left of it.
 template <typename T>
 void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
-                      const T* L, T* X, T* Tb, hipStream_t s);
+                      const T* L, T* X, T* Tb, hipStream_t s, const int64_t* xoff = nullptr,
+                      const int32_t* tlo = nullptr);
 template <typename T>
 void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* X, T* M,
                   hipStream_t s);

@@ -31,11 +31,44 @@
 // when the key range exceeds kcap).
 #include "common.h"
 #include "kernels.h"
+#include "coarse_blocks.h"
 
 namespace sfcdd {
 
 constexpr int ORDER_THREADS = 256;
+constexpr size_t ORDER_LDS_BYTES = 144 * 1024;   // dynamic LDS the ordering kernels may take
 constexpr int ORDER_MAX_PATTERNS = 64;
+
+// Ascending sort of the np (a power of two) values at srt by the whole
+// workgroup (bitonic network; np / 2 compare-exchanges per stage).
+__device__ void bitonic_sort(uint32_t* srt, int np) {
+  for (int k = 2; k <= np; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint32_t a = srt[i], b = srt[l];
+          if ((a > b) == ((i & k) == 0)) {
+            srt[i] = b;
+            srt[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Bits of an index below np (a power of two).
+__device__ __forceinline__ int index_bits(int np) { return 31 - __clz(np); }
 
 __device__ __forceinline__ int64_t sub_pos(const GridDesc& g, int64_t t0, int s) {
   int64_t p = t0 + s;
@@ -55,7 +88,7 @@ __device__ __forceinline__ int order_key(const GridDesc& g, int nat, const int* 
 }
 
 __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
-    Batch B, int mode, int kcap, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
+    Batch B, int mode, int kcap, int npmax, const int32_t* __restrict__ ta, const int32_t* __restrict__ Ni,
     const int32_t* __restrict__ nt, const int64_t* __restrict__ xoff, const int64_t* __restrict__ doff,
     const int32_t* __restrict__ sfc_index, const int32_t* __restrict__ nbr, int32_t* __restrict__ lperm,
     int32_t* __restrict__ liperm, int32_t* __restrict__ tlo, int32_t* __restrict__ trb,
@@ -72,8 +105,9 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
   const int tid = threadIdx.x, lane = tid & 63;
   __shared__ int bmin[MAXD], bmax[MAXD];
   __shared__ int s_best, s_bestw, s_range, s_red[ORDER_THREADS / 64];
-  extern __shared__ int hist[];         // kcap level counters, then ntb tile-row minima
-  int* tmin = hist + kcap;
+  extern __shared__ int hist[];         // kcap level counters, npmax sort keys, ntb tile-row minima
+  uint32_t* srt = reinterpret_cast<uint32_t*>(hist + kcap);
+  int* tmin = reinterpret_cast<int*>(srt + npmax);
 
   // a subdomain of one tile row has nothing to gain from reordering
   bool diag = mode == 2 && g.d >= 2 && ntb > 1;
@@ -83,12 +117,18 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
       bmax[tid] = -1;
     }
     __syncthreads();
-    for (int s = tid; s < n; s += ORDER_THREADS) {
-      const int nat = (int)(sfc_index[sub_pos(g, t0, s)] - g.goff);
-      for (int j = 0; j < g.d; ++j) {
-        const int x = nat / (int)g.stride[j] % g.n[j];
-        atomicMin(&bmin[j], x);
-        atomicMax(&bmax[j], x);
+    for (int j = 0; j < g.d; ++j) {
+      int lo = INT32_MAX, hi = -1;
+      for (int s = tid; s < n; s += ORDER_THREADS) {
+        const int x = (int)(sfc_index[sub_pos(g, t0, s)] - g.goff) / (int)g.stride[j] % g.n[j];
+        lo = min(lo, x);
+        hi = max(hi, x);
+      }
+      lo = wave_min(lo);
+      hi = wave_max(hi);
+      if (lane == 0) {
+        atomicMin(&bmin[j], lo);
+        atomicMax(&bmax[j], hi);
       }
     }
     __syncthreads();
@@ -128,6 +168,23 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
       __syncthreads();
     }
     const int sg = s_best;
+    if (npmax > 0) {
+      // sort of the unique values key << IB | s: by key, ties in curve order
+      int np = 1;
+      while (np < n) np <<= 1;
+      const int IB = index_bits(np);
+      for (int s = tid; s < np; s += ORDER_THREADS)
+        srt[s] = s < n ? ((uint32_t)order_key(g, (int)(sfc_index[sub_pos(g, t0, s)] - g.goff), bmin, bmax, sg) << IB) |
+                             (uint32_t)s
+                       : 0xFFFFFFFFu;
+      __syncthreads();
+      bitonic_sort(srt, np);
+      for (int t = tid; t < n; t += ORDER_THREADS) {
+        const int s = (int)(srt[t] & ((1u << IB) - 1u));
+        perm[t] = s;
+        iperm[s] = t;
+      }
+    } else {
     for (int k = tid; k < R; k += ORDER_THREADS) hist[k] = 0;
     __syncthreads();
     for (int s = tid; s < n; s += ORDER_THREADS)
@@ -165,6 +222,7 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
           iperm[s] = t;
         }
       }
+    }
     }
   } else {
     for (int s = tid; s < n; s += ORDER_THREADS) {
@@ -222,16 +280,254 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_local_order(
   }
 }
 
+// Elimination order of the dense coarse matrices (agg = 1; the iterative
+// coarse solve's aggregated level keeps its order).  A_0 couples the coarse
+// blocks of neighbouring curve segments; in block (curve) order its
+// Cholesky factor is nearly full, while ordered by level sets of a
+// coordinate diagonal of the blocks' centroids it is banded (at the (7,6,5)
+// workload about a fifth of the 64 x 64 tiles), which shortens the
+// factorisation's columns and the inversion's sums.  The centroids (4 x the
+// mean coordinate, rounded) come from k_coarse_centroid; then one workgroup
+// per grid: sign pattern
+// with the narrowest widest level (as for the subdomains), stable counting
+// sort of the blocks by key (ties in block order).  cperm[c0off + k] = the
+// position of block k; cfnz[c0pad + r] = r for every row of the padded
+// matrix (the first-nonzero columns k_coarse_counts lowers).  Keys spanning
+// more than kcap levels keep the block order.
+// 4 x the mean coordinate of every coarse block (rounded), for all blocks of
+// the batch: ccen[Ig * dmax + j].
+__global__ void k_coarse_centroid(Batch B, const int32_t* __restrict__ sfc_index, int32_t* __restrict__ ccen) {
+  const int64_t Ig = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (Ig >= B.N0tot) return;
+  const GridDesc& g = B.grids[grid_of(B, B.cgid, Ig)];
+  int64_t st, sz;
+  block_range((int)(Ig - g.c0off), g, &st, &sz);
+  int64_t sum[MAXD];
+  for (int j = 0; j < g.d; ++j) sum[j] = 0;
+  for (int64_t e = 0; e < sz; ++e) {
+    const int nat = (int)(sfc_index[g.goff + st + e] - g.goff);
+    for (int j = 0; j < g.d; ++j) sum[j] += nat / (int)g.stride[j] % g.n[j];
+  }
+  for (int j = 0; j < g.d; ++j) ccen[Ig * B.dmax + j] = (int32_t)((4 * sum[j] + sz / 2) / sz);
+}
+
+__device__ __forceinline__ int centroid_key(const GridDesc& g, const int32_t* __restrict__ cen, const int* cmin,
+                                            const int* cmax, int sg) {
+  int key = 0;
+  for (int j = 0; j < g.d; ++j) {
+    const int c = cen[j];
+    key += (j > 0 && ((sg >> (j - 1)) & 1)) ? cmax[j] - c : c - cmin[j];
+  }
+  return key;
+}
+
+constexpr int CORDER_THREADS = 1024;
+__global__ __launch_bounds__(CORDER_THREADS) void k_coarse_order(Batch B, int kcap, int npmax, int hcap,
+                                                                const int32_t* __restrict__ ccen,
+                                                                int32_t* __restrict__ cperm,
+                                                                int32_t* __restrict__ cfnz) {
+  const GridDesc& g = B.grids[blockIdx.x];
+  const int n = g.N0, tid = threadIdx.x, lane = tid & 63;
+  int32_t* perm = cperm + g.c0off;
+  for (int r = tid; r < g.nt0d * TS; r += CORDER_THREADS) cfnz[g.c0pad + r] = r;
+  __shared__ int cmin[MAXD], cmax[MAXD];
+  __shared__ int s_best, s_bestw, s_range, s_red[CORDER_THREADS / 64];
+  extern __shared__ int hist[];
+  bool diag = g.agg == 1 && g.d >= 2 && g.nt0d > 1;
+  if (diag) {
+    if (tid < g.d) {
+      cmin[tid] = INT32_MAX;
+      cmax[tid] = -1;
+    }
+    __syncthreads();
+    for (int j = 0; j < g.d; ++j) {
+      int lo = INT32_MAX, hi = -1;
+      for (int k = tid; k < n; k += CORDER_THREADS) {
+        const int c = ccen[(g.c0off + k) * B.dmax + j];
+        lo = min(lo, c);
+        hi = max(hi, c);
+      }
+      lo = wave_min(lo);
+      hi = wave_max(hi);
+      if (lane == 0) {
+        atomicMin(&cmin[j], lo);
+        atomicMax(&cmax[j], hi);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int r = 1;
+      for (int j = 0; j < g.d; ++j) r += cmax[j] - cmin[j];
+      s_range = r;
+      s_best = 0;
+      s_bestw = INT32_MAX;
+    }
+    __syncthreads();
+    diag = s_range <= kcap;
+  }
+  if (!diag) {
+    for (int k = tid; k < n; k += CORDER_THREADS) perm[k] = k;
+    return;
+  }
+  const int R = s_range;
+  const int npat = g.d - 1 >= 6 ? ORDER_MAX_PATTERNS : 1 << (g.d - 1);
+  if (npat * R <= hcap) {
+    // every pattern's level sizes in one pass over the blocks
+    for (int k = tid; k < npat * R; k += CORDER_THREADS) hist[k] = 0;
+    __syncthreads();
+    for (int k = tid; k < n; k += CORDER_THREADS)
+      for (int sg = 0; sg < npat; ++sg)
+        atomicAdd(&hist[sg * R + centroid_key(g, ccen + (g.c0off + k) * B.dmax, cmin, cmax, sg)], 1);
+    __syncthreads();
+    for (int sg = 0; sg < npat; ++sg) {
+      int m = 0;
+      for (int k = tid; k < R; k += CORDER_THREADS) m = max(m, hist[sg * R + k]);
+      m = wave_max(m);
+      if (lane == 0) s_red[tid >> 6] = m;
+      __syncthreads();
+      if (tid == 0) {
+        int w = 0;
+        for (int q = 0; q < CORDER_THREADS / 64; ++q) w = max(w, s_red[q]);
+        if (w < s_bestw) {
+          s_bestw = w;
+          s_best = sg;
+        }
+      }
+      __syncthreads();
+    }
+  } else
+  for (int sg = 0; sg < npat; ++sg) {
+    for (int k = tid; k < R; k += CORDER_THREADS) hist[k] = 0;
+    __syncthreads();
+    for (int k = tid; k < n; k += CORDER_THREADS) atomicAdd(&hist[centroid_key(g, ccen + (g.c0off + k) * B.dmax, cmin, cmax, sg)], 1);
+    __syncthreads();
+    int m = 0;
+    for (int k = tid; k < R; k += CORDER_THREADS) m = max(m, hist[k]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if (lane == 0) s_red[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+      int w = 0;
+      for (int q = 0; q < CORDER_THREADS / 64; ++q) w = max(w, s_red[q]);
+      if (w < s_bestw) {
+        s_bestw = w;
+        s_best = sg;
+      }
+    }
+    __syncthreads();
+  }
+  const int sg = s_best;
+  if (npmax >= n) {
+    // sort of the unique values key << IB | k: by key, ties in block order
+    uint32_t* srt = reinterpret_cast<uint32_t*>(hist + hcap);
+    int np = 1;
+    while (np < n) np <<= 1;
+    const int IB = index_bits(np);
+    for (int k = tid; k < np; k += CORDER_THREADS)
+      srt[k] = k < n ? ((uint32_t)centroid_key(g, ccen + (g.c0off + k) * B.dmax, cmin, cmax, sg) << IB) | (uint32_t)k
+                     : 0xFFFFFFFFu;
+    __syncthreads();
+    bitonic_sort(srt, np);
+    for (int t = tid; t < n; t += CORDER_THREADS) perm[srt[t] & ((1u << IB) - 1u)] = t;
+    return;
+  }
+  for (int k = tid; k < R; k += CORDER_THREADS) hist[k] = 0;
+  __syncthreads();
+  for (int k = tid; k < n; k += CORDER_THREADS) atomicAdd(&hist[centroid_key(g, ccen + (g.c0off + k) * B.dmax, cmin, cmax, sg)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int k = 0; k < R; ++k) {
+      const int c = hist[k];
+      hist[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    for (int k0 = 0; k0 < n; k0 += 64) {
+      const int k = k0 + lane;
+      const bool v = k < n;
+      const int key = v ? centroid_key(g, ccen + (g.c0off + k) * B.dmax, cmin, cmax, sg) : -1;
+      uint64_t rem = __ballot(v);
+      int t = 0;
+      while (rem) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int kk = __shfl(key, leader, 64);
+        const uint64_t mk = __ballot(v && key == kk);
+        if (v && key == kk) t = hist[kk] + __popcll(mk & ((1ull << lane) - 1ull));
+        if (lane == leader) hist[kk] += __popcll(mk);
+        rem &= ~mk;
+      }
+      if (v) perm[k] = t;
+    }
+  }
+}
+
+void launch_coarse_order(const Batch& B, int kcap, int max_n0, const int32_t* sfc_index, int32_t* ccen,
+                         int32_t* cperm, int32_t* cfnz, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_centroid, dim3((unsigned)((B.N0tot + 255) / 256)), dim3(256), 0, s, B, sfc_index, ccen);
+  // sort keys in LDS when they fit (else the wave-serial placement)
+  int npmax = 1;
+  while (npmax < max_n0) npmax <<= 1;
+  if (((size_t)kcap + (size_t)npmax) * sizeof(int) > ORDER_LDS_BYTES) npmax = 0;
+  // level counters: every sign pattern at once when they fit beside the sort keys
+  const int npat = B.dmax - 1 >= 6 ? ORDER_MAX_PATTERNS : 1 << (B.dmax > 0 ? B.dmax - 1 : 0);
+  int hcap = kcap;
+  if (((size_t)npat * kcap + (size_t)npmax) * sizeof(int) <= ORDER_LDS_BYTES) hcap = npat * kcap;
+  const size_t sh = ((size_t)hcap + (size_t)npmax) * sizeof(int);
+  if (sh > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse_order),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL(k_coarse_order, dim3(B.G), dim3(CORDER_THREADS), sh, s, B, kcap, npmax, hcap, ccen, cperm,
+                     cfnz);
+}
+
+// First tile column of every tile row of the (permuted) dense coarse
+// matrices from the rows' first nonzero columns, made non-decreasing, and the
+// row bases of the packed triangle (the matrices stay stored as full packed
+// triangles; only the factorisation and inversion skip the zero tiles).  One
+// workgroup per grid.
+__global__ __launch_bounds__(ORDER_THREADS) void k_coarse_env(Batch B, const int32_t* __restrict__ cfnz,
+                                                              int32_t* __restrict__ clo,
+                                                              int32_t* __restrict__ crb) {
+  const GridDesc& g = B.grids[blockIdx.x];
+  const int nt = g.nt0d;
+  const int64_t trow = g.c0pad / TS;
+  extern __shared__ int tmin[];
+  for (int I = threadIdx.x; I < nt; I += ORDER_THREADS) tmin[I] = I;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nt * TS; r += ORDER_THREADS) atomicMin(&tmin[r / TS], cfnz[g.c0pad + r] / TS);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int lo = nt;
+    for (int I = nt - 1; I >= 0; --I) {
+      lo = min(lo, tmin[I]);
+      clo[trow + I] = lo;
+      crb[trow + I] = I * (I + 1) / 2;
+    }
+  }
+}
+
+void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb, hipStream_t s) {
+  const size_t sh = (size_t)max_nt0 * sizeof(int);
+  hipLaunchKernelGGL(k_coarse_env, dim3(B.G), dim3(ORDER_THREADS), sh, s, B, cfnz, clo, crb);
+}
+
 void launch_local_order(const Batch& B, int mode, int kcap, int max_nt, const int32_t* ta, const int32_t* Ni,
                         const int32_t* nt, const int64_t* xoff, const int64_t* doff, const int32_t* sfc_index,
                         const int32_t* nbr, int32_t* lperm, int32_t* liperm, int32_t* tlo, int32_t* trb,
                         unsigned long long* gtiles, hipStream_t s) {
-  const size_t sh = ((size_t)kcap + (size_t)max_nt) * sizeof(int);
+  // sort keys in LDS when they fit (else the wave-serial placement)
+  int npmax = 1;
+  while (npmax < max_nt * TS) npmax <<= 1;
+  if (((size_t)kcap + (size_t)npmax + (size_t)max_nt) * sizeof(int) > ORDER_LDS_BYTES) npmax = 0;
+  const size_t sh = ((size_t)kcap + (size_t)npmax + (size_t)max_nt) * sizeof(int);
   if (sh > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_local_order),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL(k_local_order, dim3(B.Ptot), dim3(ORDER_THREADS), sh, s, B, mode, kcap, ta, Ni, nt, xoff, doff,
-                     sfc_index, nbr, lperm, liperm, tlo, trb, gtiles);
+  hipLaunchKernelGGL(k_local_order, dim3(B.Ptot), dim3(ORDER_THREADS), sh, s, B, mode, kcap, npmax, ta, Ni, nt, xoff,
+                     doff, sfc_index, nbr, lperm, liperm, tlo, trb, gtiles);
 }
 
 }  // namespace sfcdd

@@ -258,34 +258,42 @@ INST(double)
 // Integer coupling counts of dimension j between coarse blocks (eq. csm with
 // A = sum_j c_j L_j): cnt(I, J) = sum_{p in I, p' in J} (L_j)_{p p'} for
 // J <= I, accumulated with integer atomics into the packed lower tiles of
-// each grid's dense coarse matrix (first tile ctile_off[g]).  With agg > 1
-// the rows and columns are groups of agg consecutive coarse blocks (the
-// Galerkin aggregation of A_0 that the iterative coarse solve uses as its
-// second level).
+// each grid's dense coarse matrix (first tile ctile_off[g]), in the permuted
+// coarse numbering (block k at position cperm[k]); cfnz[c0pad + I] is
+// lowered to the first nonzero column of row I.  With agg > 1 the rows and
+// columns are groups of agg consecutive coarse blocks (the Galerkin
+// aggregation of A_0 that the iterative coarse solve uses as its second
+// level), not permuted.
 __global__ void k_coarse_counts(Batch B, int j, const int32_t* __restrict__ nbr,
-                                const int64_t* __restrict__ ctile_off, int32_t* __restrict__ cnt) {
+                                const int64_t* __restrict__ ctile_off, int32_t* __restrict__ cnt,
+                                int32_t* __restrict__ cfnz) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= B.Ntot) return;
   const int gi = grid_of(B, B.gid, p);
   const GridDesc& g = B.grids[gi];
   if (j >= g.d) return;
   int32_t* C = cnt + ctile_off[gi] * TS2;
-  const int I = coarse_block(p - g.goff, g) / g.agg;
+  auto pos = [&](int64_t q) {
+    const int k = coarse_block(q - g.goff, g);
+    return g.agg == 1 ? B.cperm[g.c0off + k] : k / g.agg;
+  };
+  const int I = pos(p);
   atomicAdd(&C[tri_index(I / TS, I / TS) * TS2 + (I % TS) * TS + (I % TS)], 2);
   for (int side = 0; side < 2; ++side) {
     const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
     if (q < 0) continue;
-    const int J = coarse_block(q - g.goff, g) / g.agg;
+    const int J = pos(q);
     if (J > I) continue;
     atomicAdd(&C[tri_index(I / TS, J / TS) * TS2 + (I % TS) * TS + (J % TS)], -1);
+    if (J < I) atomicMin(&cfnz[g.c0pad + I], J);
   }
 }
 
 void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
-                          int32_t* cnt, hipStream_t s) {
+                          int32_t* cnt, int32_t* cfnz, hipStream_t s) {
   const int th = 256;
   hipLaunchKernelGGL(k_coarse_counts, dim3((B.Ntot + th - 1) / th), dim3(th), 0, s, B, j, nbr,
-                     ctile_off, cnt);
+                     ctile_off, cnt, cfnz);
 }
 
 // A_0 += c_j E_j for every coarse tile element (the grid of a tile from ctgid).

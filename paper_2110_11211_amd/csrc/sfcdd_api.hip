@@ -101,7 +101,7 @@ struct sfcdd_ctx {
       r_omega, r_sgid, r_fac, r_facX, r_xloc, r_fpart, r_A0, r_X0, r_c0, r_d0, r_cpart, r_cpartk,
       r_cmeta, r_cgid, r_ctgid, r_cy, r_dbuf, r_vec, r_partials, r_scal, r_active, r_status, r_gout,
       r_ideg, r_icol, r_ival, r_ibjt, r_ibjm, r_ibjnt, r_ibjoff, r_ivec, r_icagg, r_idagg, r_iqpart, r_ipart,
-      r_lperm, r_liperm, r_tlo, r_trb, r_gtiles, r_ztile;
+      r_lperm, r_liperm, r_tlo, r_trb, r_gtiles, r_ztile, r_cperm, r_ccen, r_cfnz, r_clo, r_crb;
   size_t total = 0;
   unsigned char* ws = nullptr;
   // device pointers
@@ -115,6 +115,8 @@ struct sfcdd_ctx {
   int32_t *lperm = nullptr, *liperm = nullptr, *tlo = nullptr, *trb = nullptr;
   unsigned long long* gtiles = nullptr;   // per grid: tiles stored, entries per sweep, tile products
   void* ztile = nullptr;                  // a tile of zeros (the substitution kernel's unused slots)
+  // coarse elimination order and the envelopes of the dense coarse factors
+  int32_t *cperm = nullptr, *ccen = nullptr, *cfnz = nullptr, *clo = nullptr, *crb = nullptr;
   void *fac = nullptr, *facX = nullptr, *xloc = nullptr, *fpart = nullptr;
   double *A0 = nullptr, *X0 = nullptr, *c0 = nullptr, *d0 = nullptr, *cpart = nullptr;
   double* cy = nullptr;  // tile-padded coarse vector X_0 R_0 v between the two products
@@ -170,6 +172,7 @@ struct sfcdd_ctx {
     B.rbx = rbx;
     B.spmv_u = spmv_u;
     B.spmv_win = spmv_win;
+    B.cperm = cperm;
     return B;
   }
 };
@@ -655,6 +658,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_trb = pl.take(4 * (size_t)(c->xlen / TS));
   c->r_gtiles = pl.take(24 * (size_t)G);
   c->r_ztile = pl.take((size_t)TS2 * 8);
+  c->r_cperm = pl.take(4 * (size_t)c->N0tot);
+  c->r_ccen = pl.take(4 * (size_t)c->N0tot * c->dmax);
+  c->r_cfnz = pl.take(4 * (size_t)c->c0len);
+  c->r_clo = pl.take(4 * (size_t)(c->c0len / TS));
+  c->r_crb = pl.take(4 * (size_t)(c->c0len / TS));
   if (c->coarse_iter) {
     const GridDesc& g = c->grid[0].desc;
     c->ic_nt = g.nt0;
@@ -736,6 +744,11 @@ void bind(sfcdd_ctx* c) {
   c->trb = at<int32_t>(c, c->r_trb);
   c->gtiles = at<unsigned long long>(c, c->r_gtiles);
   c->ztile = at<void>(c, c->r_ztile);
+  c->cperm = at<int32_t>(c, c->r_cperm);
+  c->ccen = at<int32_t>(c, c->r_ccen);
+  c->cfnz = at<int32_t>(c, c->r_cfnz);
+  c->clo = at<int32_t>(c, c->r_clo);
+  c->crb = at<int32_t>(c, c->r_crb);
   if (c->coarse_iter) {
     c->ideg = at<int32_t>(c, c->r_ideg);
     c->icol = at<int32_t>(c, c->r_icol);
@@ -760,7 +773,9 @@ void bind(sfcdd_ctx* c) {
 // Batched left-looking factorisation: each workgroup keeps its output tile in
 // registers across the K loop.  A single matrix (part != nullptr) uses the
 // split-K form instead, so that every column step runs on many workgroups.
-// xoff / tlo / trb (batch only): the matrices are stored as tile envelopes.
+// xoff / tlo / trb: the envelope tables of the matrices (first tile column and
+// row base per tile row at xoff[b] / TS; a single matrix uses those of
+// matrix 0 at tlo / trb).
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, bool product, int32_t* status, T* part, T* tbuf,
@@ -774,13 +789,13 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
     // one matrix: the first diagonal tile, then one step per column (its
     // sub-diagonal tiles, the next diagonal tile, split-K partials two
     // columns ahead in three slots)
-    launch_potrf_diag<T>(0, 0, 0, maxc, part, 1, nt, off, fac, status, s);
+    launch_potrf_diag<T>(0, 0, 0, maxc, part, 1, nt, off, fac, status, s, tlo, trb);
     for (int J = 0; J + 1 < max_nt; ++J)
-      launch_potrf_step<T>(J, max_nt, maxc, part, (int64_t)max_nt * maxc, nt, off, fac, status, s);
+      launch_potrf_step<T>(J, max_nt, maxc, part, (int64_t)max_nt * maxc, nt, off, fac, status, s, tlo, trb);
   }
   if (invert) {
     if (tbuf) {
-      launch_trtri_rec<T>(nb, max_nt, nt, off, toff, fac, X, tbuf, s);
+      launch_trtri_rec<T>(nb, max_nt, nt, off, toff, fac, X, tbuf, s, xoff, tlo);
     } else {
       for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
     }
@@ -1129,13 +1144,24 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     // coarse matrices A_0 = R_0 A R_0^T = sum_j c_j E_j (eq. csm), then A_0^{-1}
     HIPCHK(c, hipMemsetAsync(c->A0, 0, c->r_A0.bytes, cs));
     HIPCHK(c, hipMemsetAsync(c->c0, 0, c->r_c0.bytes, cs));
+    // coarse elimination order (key levels: 4 x the sum of the grid extents)
+    int ckcap = 1;
+    for (int k = 0; k < G; ++k) {
+      int r = 1;
+      for (int j = 0; j < c->grid[k].desc.d; ++j) r += 4 * (c->grid[k].desc.n[j] - 1);
+      ckcap = std::max(ckcap, std::min(r, ORDER_MAX_KEYS));
+    }
+    int max_n0 = 1;
+    for (int k = 0; k < G; ++k) max_n0 = std::max(max_n0, c->grid[k].desc.N0);
+    launch_coarse_order(B, ckcap, max_n0, c->sfc_index, c->ccen, c->cperm, c->cfnz, cs);
     const int64_t celems = c->ctiles * TS2;
     for (int j = 0; j < c->dmax; ++j) {
       HIPCHK(c, hipMemsetAsync(c->X0, 0, (size_t)celems * 4, cs));
-      launch_coarse_counts(B, j, c->nbr, c->dc_off, (int32_t*)c->X0, cs);
+      launch_coarse_counts(B, j, c->nbr, c->dc_off, (int32_t*)c->X0, c->cfnz, cs);
       launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
+    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, cs);
     // Beside FP32 subdomain factors the inverse X_0 = L_0^{-1} is FP32: A_0
     // is an M-matrix (a Galerkin aggregation of the stencil matrix), so L_0
     // has non-positive off-diagonal entries, X_0 is entrywise non-negative
@@ -1149,17 +1175,20 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       if (c->coarse32) {
         launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
         factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
-                            c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs);
+                            c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs, 0,
+                            c->dc_xoff, c->clo, c->crb);
       } else {
         factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, false, false, c->status + 1,
-                             G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
+                             G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
+                             c->dc_xoff, c->clo, c->crb);
         launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
         launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
-                                part32, cs);
+                                part32, cs, c->dc_xoff, c->clo);
       }
     } else {
       factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
-                           G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs);
+                           G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
+                           c->dc_xoff, c->clo, c->crb);
     }
     if (c->coarse_iter) {
       // the sparse rows of A_0 (one workgroup per coarse block), then the

@@ -120,17 +120,6 @@ __device__ __forceinline__ T sum_col_lanes(T v) {
   return swap32_add(v);
 }
 
-// Workgroup barrier that orders the LDS accesses only.  (A plain
-// __syncthreads also waits for every outstanding global load, since loads
-// and stores share one counter on this architecture: it would drain the
-// factor prefetches at every step.)  The kernel stores nothing to global
-// memory before its last barrier, so no global ordering is needed.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 template <typename T>
 __device__ __forceinline__ typename Vec16<T>::type vzero();
 template <>
