@@ -337,7 +337,8 @@ typedef struct {
   int32_t trsv_waves;        /* waves per workgroup of the substitution kernel (4, 8, 16) */
   int32_t spmv_points;       /* SpMV points per thread and step (1, 2)                    */
   int32_t spmv_window;       /* SpMV LDS window (256, 512, 1024, 2048 points)             */
-  int32_t factor_rows;       /* row tiles per step of the batched factorisation (2..4)    */
+  int32_t factor_rows;       /* row tiles per step of the batched factorisation (1..4;
+                                1: the light kernel for matrices of a few tile rows)     */
   int32_t factor_pair;       /* 1: two columns per step                                   */
   int32_t tuned;             /* SFCDD_TUNE_* bits that were timed now (the rest came
                                 from the per-shape record of earlier tunings, or were

@@ -57,12 +57,35 @@ __device__ __forceinline__ T row_bcast(T v) {
   }
 }
 
+// Row PK of 16 lanes copied to all four rows (lane 16 p + i receives lane
+// 16 PK + i) with the gfx950 permlane swaps: the 16-lane swap pairs rows
+// (0, 1) and (2, 3), its first result holding rows (0, 0, 2, 2) and its
+// second (1, 1, 3, 3); the 32-lane swap of either gives the lower pair
+// (first result) or the upper pair (second) in both halves.
+template <int PK>
+__device__ __forceinline__ unsigned row_to_all(unsigned v) {
+  const auto x = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  const unsigned w = (PK & 1) ? x[1] : x[0];
+  const auto z = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return (PK & 2) ? z[1] : z[0];
+}
+template <int PK>
+__device__ __forceinline__ float row_to_all(float v) {
+  return __uint_as_float(row_to_all<PK>(__float_as_uint(v)));
+}
+template <int PK>
+__device__ __forceinline__ double row_to_all(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = row_to_all<PK>((unsigned)b), hi = row_to_all<PK>((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Pivot K of the DB x DB block held by one wave: lane (p, i) = 16 p + i holds
 // a[q] = A[i][p + 4 q].  The trailing block stays symmetric (every lane
 // updates its whole part of its row), so the factor column below the pivot,
 // L[j][K] = A[K][j] / sqrt(A[K][K]), is row K right of the pivot: lane K of
 // each 16-lane row holds the entries of that row's columns (row broadcast),
-// while the lane's own L[i][K] sits in lane (K mod 4, i) (one shuffle).
+// while the lane's own L[i][K] sits in lane (K mod 4, i) (row_to_all).
 template <typename T, int K>
 __device__ __forceinline__ void pivot_step(T (&a)[DB / 4], T (&rd)[DB], int p, int i, int32_t* status) {
   constexpr int pk = K & 3, qk = K >> 2;
@@ -73,7 +96,7 @@ __device__ __forceinline__ void pivot_step(T (&a)[DB / 4], T (&rd)[DB], int p, i
   }
   const T rs = rsqrt_nr(piv);
   rd[K] = rs;
-  const T li = __shfl(a[qk], 16 * pk + i, 64) * rs;
+  const T li = row_to_all<pk>(a[qk]) * rs;
   T lj[DB / 4];
 #pragma unroll
   for (int q = 0; q < DB / 4; ++q) lj[q] = row_bcast<K>(a[q]) * rs;
@@ -713,7 +736,7 @@ __device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__
 // the FP64 one, and the caller chooses accordingly.
 // R: row tiles per step of the panel and pair updates (the autotuner picks
 // it per launch shape; PanelRows by default).
-template <typename T, bool PAIR, int R>
+template <typename T, bool PAIR, int R, bool DBUF = true>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __restrict__ nt,
                                                              const int64_t* __restrict__ off,
                                                              const int64_t* __restrict__ xoff,
@@ -731,7 +754,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
   int J = 0;
   if (!PAIR) {
     for (; J < ntb; ++J) {
-      diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
+      diag_tile<T, DBUF>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
       __syncthreads();
       const int h = ix.last(J, ntb);
       for (int I = J + 1; I <= h; I += R) panel_rows<T, R>(J, 0, I, min(R, h + 1 - I), F, sA, ix);
@@ -743,15 +766,15 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
     const int h0 = ix.last(J, ntb), h1 = ix.last(J + 1, ntb);
     if (J > 0)
       for (int I = J; I <= h1; I += R) pair_rows<T, R>(J, I, min(R, h1 + 1 - I), F, sA, ix);
-    diag_tile<T, true>(J, J, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
+    diag_tile<T, DBUF>(J, J, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
     __syncthreads();
     for (int I = J + 1; I <= h0; I += R) panel_rows<T, R>(J, J, I, min(R, h0 + 1 - I), F, sA, ix);
-    diag_tile<T, true>(J + 1, J, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
+    diag_tile<T, DBUF>(J + 1, J, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
     __syncthreads();
     for (int I = J + 2; I <= h1; I += R) panel_rows<T, R>(J + 1, J, I, min(R, h1 + 1 - I), F, sA, ix);
   }
   if (J < ntb) {  // odd tile count: the last column alone
-    diag_tile<T, true>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
+    diag_tile<T, DBUF>(J, 0, 0, 0, (const T*)nullptr, F, status, smem_raw, ix);
     __syncthreads();
   }
 }
@@ -892,6 +915,19 @@ static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, const
                      status);
 }
 
+// Small matrices (a few tile rows): the diagonal update without the
+// double-buffered prefetch and one row per panel step, so that the staging
+// (35 KB FP32) lets four workgroups share a CU.
+template <typename T>
+static void potrf_full_light(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
+                             const int32_t* trb, T* fac, int32_t* status, hipStream_t s) {
+  const size_t sh = std::max(diag_lds_bytes<T>(), (size_t)2 * TS * LdsV<T>::v * sizeof(T));
+  static bool once = (allow_lds(k_potrf_full<T, false, 1, false>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL((k_potrf_full<T, false, 1, false>), dim3(nb), dim3(TILE_THREADS), sh, s, nt, off, xoff, tlo, trb,
+                     fac, status);
+}
+
 // Largest row count whose LDS staging (rows + 1 or + 2 tiles, at least four)
 // fits the 160 KB of a CU: 4 FP32; FP64 3 for one column, 2 for pairs.
 int potrf_full_max_rows(bool fp64, bool pair) { return fp64 ? (pair ? 2 : 3) : 4; }
@@ -900,6 +936,10 @@ template <typename T>
 void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
                        const int32_t* trb, T* fac, int32_t* status, bool pair,
                        hipStream_t s, int rows) {
+  if (rows == 1) {
+    potrf_full_light<T>(nb, nt, off, xoff, tlo, trb, fac, status, s);
+    return;
+  }
   if (rows <= 0) rows = PanelRows<T>::v;
   rows = std::max(2, std::min(rows, potrf_full_max_rows(sizeof(T) == 8, pair)));
   if (pair) {

@@ -128,7 +128,9 @@ void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, in
 // Whole factorisation, one workgroup per matrix (pair: two columns per
 // step; faster alone, but no room beside it for other workgroups).
 // rows: row tiles per step of the panel updates (2 .. potrf_full_max_rows;
-// 0 = the default 3 FP32, 2 FP64).
+// 0 = the default 3 FP32, 2 FP64; 1 = the light kernel for matrices of a
+// few tile rows: one row per step, no double-buffered prefetch, 35 KB of LDS
+// in FP32; pair is then ignored).
 int potrf_full_max_rows(bool fp64, bool pair);
 // With tlo / trb (and xoff) the matrices are stored as tile envelopes (see
 // launch_local_order); with null tables as packed triangles.

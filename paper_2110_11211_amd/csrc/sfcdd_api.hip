@@ -580,6 +580,9 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   if (c->local_solver == SFCDD_LOCAL_CHOLESKY && !trsv_fits(c->max_nt, c->fdtype == SFCDD_FP32 ? 4 : 8, 4))
     FAIL(c, SFCDD_EINVAL, "a subdomain of %d points is too large for the substitution kernel (%s factors)",
          c->max_Ni, c->fdtype == SFCDD_FP32 ? "FP32" : "FP64");
+  // subdomains of at most eight tile rows: four waves per workgroup (a wider
+  // workgroup splits too short a row of tiles and idles most of its waves)
+  c->trsv_waves = c->max_nt <= 8 ? 4 : 16;
   c->duni = c->grid[0].desc.d;
   for (int k = 1; k < G; ++k)
     if (c->grid[k].desc.d != c->duni) c->duni = 0;
@@ -1243,13 +1246,17 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   const double coarse_work = G == 1 ? std::pow((double)c->max_N0, 3.0) : 0.0;
   const bool pair = c->factor_pair >= 0 ? c->factor_pair != 0
                                          : (c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work);
+  // matrices of at most four tile rows: the light kernel (one row per panel
+  // step, no prefetch in the diagonal update), whose small LDS staging lets
+  // several workgroups share a CU
+  const int rows = c->factor_rows > 0 ? c->factor_rows : (c->max_nt <= 4 ? 1 : 0);
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
-                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair, s, c->factor_rows,
+                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair && rows != 1, s, rows,
                         c->d_xoff, c->tlo, c->trb);
   else
     factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
-                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair, s, c->factor_rows,
+                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair && rows != 1, s, rows,
                          c->d_xoff, c->tlo, c->trb);
   // the substitution kernel sweeps with the unit block-lower factor
   if (!inv) {
@@ -1258,8 +1265,8 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     else
       launch_unit_lower<double>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (double*)c->fac, s);
   }
-  c->info.factor_pair = pair ? 1 : 0;
-  c->info.factor_rows = c->factor_rows > 0 ? c->factor_rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
+  c->info.factor_pair = pair && rows != 1 ? 1 : 0;
+  c->info.factor_rows = rows > 0 ? rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(ev[4], s));
   HIPCHK(c, hipStreamWaitEvent(s, join, 0));
@@ -1474,7 +1481,8 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
       // re-read from it by the backward sweep)
       const bool chol = c->local_solver == SFCDD_LOCAL_CHOLESKY;
       const int ncand = chol ? 3 : 1;
-      const int cand[3] = {16, 8, 4};
+      // the default first
+      const int cand[3] = {c->max_nt <= 8 ? 4 : 16, 8, c->max_nt <= 8 ? 16 : 4};
       const int keep_stream = c->trsv_stream;
       c->trsv_stream = -1;
       const int rule = stream_factors(c) ? 1 : 0;
@@ -1557,7 +1565,7 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
     if (!have) {
       const int saved_rows = c->factor_rows, saved_pair = c->factor_pair;
       // the default shape (the rules) first, then every explicit one
-      std::vector<std::pair<int, int>> cand{{0, -1}};
+      std::vector<std::pair<int, int>> cand{{0, -1}, {1, 0}};
       for (int pr = 0; pr <= 1; ++pr)
         for (int rw = 2; rw <= potrf_full_max_rows(c->fdtype == SFCDD_FP64, pr != 0); ++rw)
           cand.emplace_back(rw, pr);

@@ -141,7 +141,8 @@ __device__ __forceinline__ double2 vzero<double>() { return make_double2(0.0, 0.
 // chains hold only the off-diagonal tiles: one barrier per forward step, two
 // per backward step (the column sums of the waves are combined in LDS).
 // Each wave owns G row groups of every tile.  The off-diagonal tiles of a
-// chain step (at most PF per row group) are loaded into one of NSET
+// chain step (at most PF per row group: 4, or 2 for the 4-wave shape meant
+// for small subdomains) are loaded into one of NSET
 // register sets NSET - 1 steps ahead, so that their latency overlaps the
 // steps before.  When every row and column of the envelope holds at most PF
 // off-diagonal tiles (the diagonal order keeps 2 to 4), a step issues
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   constexpr int RPI = 64 / LPR;             // rows per wave load
   constexpr int NGRP = TS / RPI;            // row groups per tile
   constexpr int G = NGRP / W;               // row groups per wave
-  constexpr int PF = TRSV_PF;               // prefetched tiles per row group
+  constexpr int PF = G >= 4 ? TRSV_PF / 2 : TRSV_PF;  // prefetched tiles per row group
   constexpr int NSET = G * PF * 4 <= 16 ? 3 : 2;  // register sets in flight (16 bytes = 4 VGPRs a slot)
   const int b = blockIdx.x;
   const int ntb = nt[b], n = Ni[b];
@@ -318,18 +319,27 @@ __global__ __launch_bounds__(W * 64) void k_schwarz_trsv(
   // diagonal blocks, every tile row independently: wave wv takes the rows
   // I = wv, wv + W, ..; t = D_I w_I row by row, and v = D_I^T t accumulated
   // over the rows of the tile; the wave reads and then writes only y_I
+  // All row groups' loads are issued before their products (chunks right of
+  // the diagonal read the zero tile; padding rows carry zeros of y).
+  // groups per batch of loads: 64 VGPRs of chunks where the prefetch sets are
+  // small (one row group per wave), 16 beside larger sets
+  constexpr int HB = (G == 1 ? 64 : 16) / 4 < NGRP ? (G == 1 ? 64 : 16) / 4 : NGRP;
   for (int I = wv; I < ntb; I += W) {
     const T* D = F + ((int64_t)srb[I] + I) * TS2;
     T accv[VEC];
     for (int e = 0; e < VEC; ++e) accv[e] = T(0);
-#pragma unroll 4
-    for (int grp = 0; grp < NGRP; ++grp) {
-      const int r = grp * RPI + lrow;
-      const bool live = c0 <= r && I * TS + r < n;
-      const V d = live ? load_fac<T, NT>(D + r * TS + c0) : vzero<T>();
-      T t = live ? dotv<T>(d, y + I * TS + c0) : T(0);
-      t = sum_row_lanes<LPR>(t);
-      axpyv<T>(accv, d, t);
+    for (int h = 0; h < NGRP; h += HB) {
+      V d[HB];
+#pragma unroll
+      for (int k = 0; k < HB; ++k) {
+        const int r = (h + k) * RPI + lrow;
+        d[k] = load_fac<T, NT>((c0 <= r ? D : ztile) + r * TS + c0);
+      }
+#pragma unroll
+      for (int k = 0; k < HB; ++k) {
+        T t = sum_row_lanes<LPR>(dotv<T>(d[k], y + I * TS + c0));
+        axpyv<T>(accv, d[k], t);
+      }
     }
     for (int e = 0; e < VEC; ++e) accv[e] = sum_col_lanes<LPR>(accv[e]);
     if (lane < LPR)

@@ -497,7 +497,9 @@ def test_tune_launch_shapes_keeps_parity(fdtype):
     assert rep["trsv_waves"] in (4, 8, 16)
     assert rep["spmv_points"] in (1, 2) and rep["spmv_window"] in (256, 512, 1024, 2048)
     assert rep["factor_pair"] in (0, 1)
-    assert rep["factor_rows"] in ((2, 3, 4) if fdtype == "fp32" else ((2, 3) if rep["factor_pair"] == 0 else (2,)))
+    # rows 1: the light kernel, one column per step
+    assert rep["factor_rows"] in ((1, 2, 3, 4) if fdtype == "fp32" else ((1, 2, 3) if rep["factor_pair"] == 0 else (2,)))
+    assert rep["factor_rows"] != 1 or rep["factor_pair"] == 0
     for k in ("trsv", "spmv", "setup"):
         assert 0 < rep[k + "_ms"] <= rep[k + "_default_ms"] * 1.0000001
     inf = S1.info()
