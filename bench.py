@@ -129,7 +129,7 @@ def run_path(w, f_dev, fdtype, local, steps, warmup, ws_cache, prof_steps=0, cur
             csteps.append(info["coarse_steps"])
         if prof:
             piters.append(info["iterations"] + info["restarts"])
-            kt = {kk: S.kernel_time(kk) for kk in ("local_solve", "scatter", "spmv", "coarse")}
+            kt = {kk: S.kernel_time(kk) for kk in ("local_solve", "scatter", "spmv", "spmv_b", "coarse")}
             ktimes = kt if ktimes is None else {kk: (ktimes[kk][0] + kt[kk][0], ktimes[kk][1] + kt[kk][1])
                                                for kk in kt}
             S.set_profiling(False)
@@ -156,13 +156,24 @@ def kernel_rates(res, w, local):
     # after the converging step skips every subdomain and its few
     # microseconds stay in the numerator)
     avg_local = ms_local / max(min(n_local, res["prof_full_launches"]), 1)
-    ms_spmv, n_spmv = res["kernels"]["spmv"]
+    # y = A x reads x and 2d int32 neighbour indices and writes y; y = b - A x
+    # also reads b
+    ms_ax, n_ax = res["kernels"]["spmv"]
+    ms_bx, n_bx = res["kernels"]["spmv_b"]
+    bytes_ax = (16 + 8 * d) * info["N"]
+    bytes_bx = (24 + 8 * d) * info["N"]
+    ms_spmv, n_spmv = ms_ax + ms_bx, n_ax + n_bx
     avg_spmv = ms_spmv / max(n_spmv, 1)
-    spmv_bytes = (16 + 8 * d) * info["N"]
+    spmv_bytes = (n_ax * bytes_ax + n_bx * bytes_bx) / max(n_spmv, 1)   # per launch, averaged
+    rate = lambda b, ms, n: b / (ms / max(n, 1) * 1e-3) / 1e9 if n else None
     return {"local_bytes": local_bytes, "avg_local_ms": avg_local,
             "local_gbps": local_bytes / (avg_local * 1e-3) / 1e9,
             "spmv_bytes": spmv_bytes, "avg_spmv_ms": avg_spmv,
-            "spmv_gbps": spmv_bytes / (avg_spmv * 1e-3) / 1e9}
+            "spmv_gbps": spmv_bytes / (avg_spmv * 1e-3) / 1e9,
+            "spmv_modes": {"ax": {"launches": n_ax, "avg_ms": ms_ax / max(n_ax, 1), "bytes": bytes_ax,
+                                  "gbps": rate(bytes_ax, ms_ax, n_ax)},
+                           "b_minus_ax": {"launches": n_bx, "avg_ms": ms_bx / max(n_bx, 1), "bytes": bytes_bx,
+                                          "gbps": rate(bytes_bx, ms_bx, n_bx)}}}
 
 
 def dtype_label(info):
@@ -540,7 +551,8 @@ def main():
         out = {"profile_only": True, "workload": w.name, "ms": head["ms"], "local_solve_launches": n_l,
                "local_solve_full_launches": min(n_l, n_full),
                "local_solve_avg_ms": ms_l / max(min(n_l, n_full), 1),
-               "local_solve_gbps": kr["local_gbps"], "spmv_launches": head["kernels"]["spmv"][1],
+               "local_solve_gbps": kr["local_gbps"],
+               "spmv_launches": head["kernels"]["spmv"][1] + head["kernels"]["spmv_b"][1],
                "spmv_avg_ms": kr["avg_spmv_ms"], "spmv_gbps": kr["spmv_gbps"],
                "spmv_algorithmic_bytes": kr["spmv_bytes"], "iterations": head["iterations"],
                "coarse_ms": head["kernels"]["coarse"][0] / max(psteps, 1), "coarse_steps": head["coarse_steps"],
@@ -589,7 +601,8 @@ def main():
     if not args.no_large:
         wl = workloads()["c5"]
         fl_dev = torch.tensor(wl.rhs(), dtype=torch.float64, device="cuda:0")
-        big = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1)
+        big = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1,
+                       tune=None if args.no_tune else 1)
         big["x"] = big["x"].cpu().numpy()
         ws_cache.clear()
         torch.cuda.empty_cache()
@@ -673,12 +686,17 @@ def main():
             "q": bi["q"], "N0": bi["N0"], "curve": "hilbert", "dtype": dtype_label(bi),
             "ms": round(big["ms"], 3), "setup_ms": round(big["setup_ms"], 3), "solve_ms": round(big["solve_ms"], 3),
             "iterations": big["iterations"], "rel_residual": big["rel_residual"], "rel_error_vs_exact": None,
-            "factor_bytes": bi["factor_algo_bytes"],
+            "factor_bytes": bi["factor_algo_bytes"], "tuning": big["tuning"],
             "kernel_ms_per_step": {k: round(v[0], 3) for k, v in big["kernels"].items()},
             "roofline_spmv": {"kernel": "k_spmv", "bound": "hbm", "achieved": round(krl["spmv_gbps"], 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(krl["spmv_gbps"] / HBM_PEAK_GBS, 4), "target_frac": 0.6,
                               "avg_launch_ms": krl["avg_spmv_ms"], "algorithmic_bytes_per_launch": krl["spmv_bytes"],
+                              "modes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                                        for k, v in krl["spmv_modes"].items()},
+                              "note": "both forms of the solve's SpMV, y = A x with the x . y partials and "
+                                      "y = b - A x (which also reads b), launch-weighted; traffic: the "
+                                      "counters of y = A x",
                               "traffic": stored_traffic(LARGE_TRAFFIC, sources=("apply.hip",))},
             "roofline_local_solve": {"kernel": "k_schwarz_trsv (FP32 factors)", "bound": "hbm",
                                      "achieved": round(krl["local_gbps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -183,8 +183,8 @@ typedef struct {
   int32_t N0d, ell_width, coarse_steps;
   int32_t factor_rows;       /* launch shape of the batched factorisation: row tiles  */
   int32_t factor_pair;       /*   per panel step, and 1 for two columns per step      */
-  int32_t spmv_points;       /* launch shape of the SpMV: points per thread and step, */
-  int32_t spmv_window;       /*   and points of x staged in LDS per window            */
+  int32_t spmv_points;       /* launch shape of the SpMV: points per thread,          */
+  int32_t spmv_window;       /*   and points of x staged in LDS per workgroup (256 u) */
   int32_t local_order;       /* elimination order of the subdomain matrices in use      */
   double factor_flops;       /* floating-point operations of the subdomain
                                 factorisation: 2 TS^3 per tile product and 2 TS^3 / 3
@@ -335,8 +335,8 @@ sfcdd_status sfcdd_autotune(sfcdd_ctx* ctx, int32_t repeats, double* best_ms);
  * shapes on the context's own data. */
 typedef struct {
   int32_t trsv_waves;        /* waves per workgroup of the substitution kernel (4, 8, 16) */
-  int32_t spmv_points;       /* SpMV points per thread and step (1, 2)                    */
-  int32_t spmv_window;       /* SpMV LDS window (256, 512, 1024, 2048 points)             */
+  int32_t spmv_points;       /* SpMV points per thread (1, 2, 4)                          */
+  int32_t spmv_window;       /* SpMV LDS window per workgroup: 256 spmv_points            */
   int32_t factor_rows;       /* row tiles per step of the batched factorisation (1..4;
                                 1: the light kernel for matrices of a few tile rows)     */
   int32_t factor_pair;       /* 1: two columns per step                                   */
@@ -352,9 +352,11 @@ typedef struct {
 enum { SFCDD_TUNE_TRSV = 1, SFCDD_TUNE_SPMV = 2, SFCDD_TUNE_SETUP = 4, SFCDD_TUNE_ALL = 7 };
 
 /* Autotuner of the launch shapes (the `what` bits): the substitution kernel's
- * waves per workgroup (4, 8, 16) with and without the non-temporal hint; the SpMV's points per thread and LDS window
- * (2 x 4 shapes); and the batched factorisation's row tiles per panel step
- * (2, 3, 4; 2, 3 with FP64 factors) with one or two columns per step, each
+ * waves per workgroup (4, 8, 16) with and without the non-temporal hint; the
+ * SpMV's points per thread (1, 2, 4; the LDS window is 256 of them); and the
+ * batched factorisation's shape: the light kernel for small matrices, or row
+ * tiles per panel step (2, 3, 4; 2, 3 with FP64 factors) with one or two
+ * columns per step, each
  * candidate timed with events on the context's stream (repeats runs each,
  * 0 = 3; the factorisation shapes by repeating the whole setup of this
  * context, which is left set up with the winner).  The fastest shapes are used
@@ -372,9 +374,11 @@ sfcdd_status sfcdd_tune(sfcdd_ctx* ctx, int32_t repeats, int32_t what, sfcdd_tun
 sfcdd_status sfcdd_partition_host(const sfcdd_params* params, int64_t* ta_host, int64_t* Ni_host,
                                   double* omega_host, int32_t* q_out);
 
-/* Kernel classes timed by the profiling counters. */
+/* Kernel classes timed by the profiling counters: the subdomain solves, the
+ * weighted sum, the SpMV y = A x (with or without the x . y partials), the
+ * coarse solve, and the SpMV y = b - A x (which also reads b). */
 enum { SFCDD_K_LOCAL_SOLVE = 0, SFCDD_K_SCATTER = 1, SFCDD_K_SPMV = 2, SFCDD_K_COARSE = 3,
-       SFCDD_K_COUNT = 4 };
+       SFCDD_K_SPMV_B = 4, SFCDD_K_COUNT = 5 };
 
 /* Turns per-kernel timing on (1) or off (0) and clears the counters.  When on,
  * every launch of a timed kernel class is bracketed by HIP events on the

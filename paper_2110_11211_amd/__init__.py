@@ -44,7 +44,7 @@ EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", 
            "sfcdd_get_partition", "sfcdd_get_batch_stats", "sfcdd_partition_host", "sfcdd_autotune",
            "sfcdd_get_info", "sfcdd_set_profiling", "sfcdd_get_kernel_time", "sfcdd_read_probe",
            "sfcdd_ct_combine", "sfcdd_ct_layout", "sfcdd_tune", "sfcdd_destroy", "sfcdd_last_error"]
-KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3}
+KERNELS = {"local_solve": 0, "scatter": 1, "spmv": 2, "coarse": 3, "spmv_b": 4}
 
 
 class SfcddError(RuntimeError):

@@ -14,32 +14,32 @@ namespace sfcdd {
 // MODE 0: y = A x over the whole batch.  MODE 1: y = A x with per-grid
 // partials of x . y.  MODE 2: y = b - A x with per-grid partials of y . y.
 // MODE 3: y = b - A x over the whole batch (no partials).
-// Reductions: block (x, g) covers grid g only; partials[g * rbx + x]; the
-// grid of blocks is fixed, so the sums are deterministic.
-// D > 0: every grid has dimension D (compile-time neighbour count).  A
-// block takes one contiguous chunk of its range and walks it in windows of
-// `win` points (at most SPMV_WIN): the window's x is staged in LDS (one
-// coalesced read), and a neighbour inside the window (80-90% of them for
-// windows of 256-2048 points of a Hilbert- or Z-ordered grid) is read from
-// there, the rest from memory.  Each thread takes U points of the window per
-// step and issues all their neighbour-index loads before their gathers.  The
-// neighbour table is streamed once per product (non-temporal loads).  The
-// chunks are dealt so that each of the 8 XCDs (which receive the workgroups
-// round-robin) works on a contiguous eighth of the curve, where the
-// neighbours outside a window mostly lie.  U and the window are launch
-// shapes of the autotuner (2 and 512 by default: the fastest measured on
-// the 8.26 M-unknown grid).  D = 0: any mix of dimensions, one point per
-// thread and step, no staging.
-constexpr int SPMV_WIN = 2048;
-
+// D > 0: every grid has dimension D (compile-time neighbour count).  Each
+// block takes one window of U * RED_THREADS consecutive points (of one grid
+// in the per-grid modes): its x is staged in LDS with one coalesced read, and
+// a neighbour inside the window (80-90% of them for windows of 256-1024
+// points of a Hilbert- or Z-ordered grid) is read from there, the rest from
+// memory.  The neighbour indices (streamed with non-temporal loads) and b
+// are requested before the staging barrier, and every gather of a thread is
+// issued before any is used (the memory reads masked to the lanes whose
+// neighbour lies outside the window), so no gather waits for another.  One
+// window per block (rather
+// than a block walking a chunk of windows) keeps enough blocks resident to
+// cover the gathers' latency.  The windows are dealt so that each of the 8
+// XCDs (which receive the workgroups round-robin) works on a contiguous
+// eighth of the range, where the neighbours outside a window mostly lie.
+// Per-grid partials: one per block, partials[g * nbx + x] for the nbx blocks
+// of a grid (launch_spmv returns nbx; k_finalize takes that count).
+// D = 0: any mix of dimensions, one point per thread, no staging, a fixed
+// grid of rbx blocks per grid.
 template <int MODE, int D, int U>
 __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __restrict__ nbr,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const double* __restrict__ b,
-                                                      double* __restrict__ partials, int win) {
+                                                      double* __restrict__ partials) {
   __shared__ double sh[16];
-  __shared__ double xw[D > 0 ? SPMV_WIN : 1];
+  __shared__ double xw[D > 0 ? U * RED_THREADS : 1];
   constexpr bool PERGRID = MODE == 1 || MODE == 2;
   double acc = 0.0;
   const int Nt = (int)B.Ntot;   // < 2^31 (checked at planning)
@@ -54,50 +54,73 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
   }
   const int nbx = gridDim.x;
   const int lb = (nbx & 7) == 0 ? (int)(blockIdx.x & 7) * (nbx >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
-  const int chunk = (int)((((int64_t)(hi - start) + nbx - 1) / nbx + 63) & ~int64_t(63));
-  const int c0 = (int)min((int64_t)hi, (int64_t)start + (int64_t)lb * chunk);
-  const int c1 = (int)min((int64_t)hi, (int64_t)c0 + chunk);
-  const int bs = blockDim.x;
   if (D > 0) {
-    for (int w0 = c0; w0 < c1; w0 += win) {
-      const int w1 = min(c1, w0 + win);
-      __syncthreads();  // the previous window's readers are done
-      for (int e = threadIdx.x; e < w1 - w0; e += bs) xw[e] = x[w0 + e];
-      __syncthreads();
-      for (int p0 = w0 + threadIdx.x; p0 < w1; p0 += U * bs) {
-        int32_t nb[U][2 * (D > 0 ? D : 1)];
+    constexpr int W = U * RED_THREADS;
+    const int w0 = (int)min((int64_t)hi, (int64_t)start + (int64_t)lb * W);
+    const int w1 = min(hi, w0 + W);
+    const int t = threadIdx.x;
+    int32_t nb[U][2 * (D > 0 ? D : 1)];
+    double bp[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int p = p0 + u * bs;
-          const bool ok = p < w1;
+    for (int u = 0; u < U; ++u) {
+      const int p = w0 + t + u * RED_THREADS;
+      const bool ok = p < w1;
 #pragma unroll
-          for (int k = 0; k < 2 * D; ++k)
-            nb[u][k] = ok ? __builtin_nontemporal_load(nbr + (int64_t)k * Nt + p) : -1;
-        }
+      for (int k = 0; k < 2 * D; ++k) nb[u][k] = ok ? __builtin_nontemporal_load(nbr + (int64_t)k * Nt + p) : -1;
+      if (MODE == 2 || MODE == 3) bp[u] = ok ? b[p] : 0.0;
+    }
+    double xp[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int p = p0 + u * bs;
-          if (p >= w1) break;
-          const GridDesc& g = B.grids[PERGRID ? (int)blockIdx.y : grid_of(B, B.gid, p)];
-          const double xp = xw[p - w0];
-          double v = g.diag * xp;
+    for (int u = 0; u < U; ++u) {
+      const int p = w0 + t + u * RED_THREADS;
+      xp[u] = p < w1 ? x[p] : 0.0;
+      xw[t + u * RED_THREADS] = xp[u];
+    }
+    __syncthreads();
+    const unsigned wlen = (unsigned)(w1 - w0);
+    double gv[U][2 * (D > 0 ? D : 1)], lv[U][2 * (D > 0 ? D : 1)];
 #pragma unroll
-          for (int j = 0; j < D; ++j) {
-            const int32_t m = nb[u][2 * j], q = nb[u][2 * j + 1];
-            double sj = 0.0;
-            if (m >= 0) sj += (m >= w0 && m < w1) ? xw[m - w0] : x[m];
-            if (q >= 0) sj += (q >= w0 && q < w1) ? xw[q - w0] : x[q];
-            v -= g.c[j] * sj;
-          }
-          if (MODE == 2 || MODE == 3) v = b[p] - v;
-          y[p] = v;
-          if (MODE == 1) acc += xp * v;
-          if (MODE == 2) acc += v * v;
-        }
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int k = 0; k < 2 * D; ++k) {
+        const int a = nb[u][k];
+        const bool in = (unsigned)(a - w0) < wlen;
+        gv[u][k] = 0.0;
+        if (a >= 0 && !in) gv[u][k] = x[a];   // masked: no value is used before all are issued
+        lv[u][k] = xw[in ? a - w0 : 0];
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = w0 + t + u * RED_THREADS;
+      const GridDesc& g = B.grids[PERGRID ? (int)blockIdx.y : (p < w1 ? grid_of(B, B.gid, p) : 0)];
+      double v = g.diag * xp[u];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double sj = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int a = nb[u][2 * j + h];
+          if (a >= 0) sj += (unsigned)(a - w0) < wlen ? lv[u][2 * j + h] : gv[u][2 * j + h];
+        }
+        v -= g.c[j] * sj;
+      }
+      if (MODE == 2 || MODE == 3) v = bp[u] - v;
+      if (p < w1) {
+        y[p] = v;
+        if (MODE == 1) acc += xp[u] * v;
+        if (MODE == 2) acc += v * v;
+      }
+    }
+    if (PERGRID) {
+      const double sm = block_sum(acc, sh);
+      if (t == 0) partials[(int64_t)blockIdx.y * nbx + lb] = sm;
+    }
   } else {
-    for (int p = c0 + threadIdx.x; p < c1; p += bs) {
+    const int chunk = (int)((((int64_t)(hi - start) + nbx - 1) / nbx + 63) & ~int64_t(63));
+    const int c0 = (int)min((int64_t)hi, (int64_t)start + (int64_t)lb * chunk);
+    const int c1 = (int)min((int64_t)hi, (int64_t)c0 + chunk);
+    for (int p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
       const GridDesc& g = B.grids[PERGRID ? (int)blockIdx.y : grid_of(B, B.gid, p)];
       const double xp = x[p];
       double v = g.diag * xp;
@@ -114,57 +137,63 @@ __global__ __launch_bounds__(RED_THREADS) void k_spmv(Batch B, const int32_t* __
       if (MODE == 1) acc += xp * v;
       if (MODE == 2) acc += v * v;
     }
-  }
-  if (PERGRID) {
-    const double sm = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + lb] = sm;
+    if (PERGRID) {
+      const double sm = block_sum(acc, sh);
+      if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + lb] = sm;
+    }
   }
 }
 
-// The whole-batch modes use one window per block (a multiple of 8 blocks, at
-// least 2048 of them when the batch is large enough to fill the device), the
-// per-grid modes their fixed block count.
+// Blocks per grid of the windowed SpMV (per-grid modes; a multiple of 8 for
+// the XCD dealing), for the largest grid of a batch.
+int spmv_blocks(int64_t maxN, int u) {
+  const int64_t w = (int64_t)u * RED_THREADS;
+  return (int)((((maxN + w - 1) / w) + 7) & ~int64_t(7));
+}
+
 template <int MODE, int D>
-void spmv_mode(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
-               double* partials, hipStream_t s) {
-  const int win = D > 0 ? std::max(64, std::min(SPMV_WIN, B.spmv_win > 0 ? B.spmv_win : 512)) & ~63 : 1;
-  const bool two = D > 0 && B.spmv_u != 1;
+int spmv_mode(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
+              double* partials, hipStream_t s) {
+  const int u = B.spmv_u == 4 ? 4 : B.spmv_u == 2 ? 2 : 1;
   dim3 grid(B.rbx, B.G);
-  if (MODE == 0 || MODE == 3) {
-    int64_t per = RED_THREADS;
-    if (D > 0) per = std::min<int64_t>(win, std::max<int64_t>(RED_THREADS, ((B.Ntot / 2048) + 63) & ~int64_t(63)));
-    int64_t nb = (B.Ntot + per - 1) / per;
+  if (D > 0) {
+    if (MODE == 0 || MODE == 3) grid = dim3((unsigned)spmv_blocks(B.Ntot, u));
+    else grid = dim3((unsigned)spmv_blocks(B.maxN, u), B.G);
+  } else if (MODE == 0 || MODE == 3) {
+    int64_t nb = (B.Ntot + RED_THREADS - 1) / RED_THREADS;
     nb = std::min<int64_t>((nb + 7) & ~int64_t(7), 65535 * 16);
     grid = dim3((unsigned)nb);
   }
-  if (two)
-    hipLaunchKernelGGL((k_spmv<MODE, D, 2>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials, win);
+  if (D > 0 && u == 4)
+    hipLaunchKernelGGL((k_spmv<MODE, D, 4>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
+  else if (D > 0 && u == 2)
+    hipLaunchKernelGGL((k_spmv<MODE, D, 2>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
   else
-    hipLaunchKernelGGL((k_spmv<MODE, D, 1>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials, win);
+    hipLaunchKernelGGL((k_spmv<MODE, D, 1>), grid, dim3(RED_THREADS), 0, s, B, nbr, x, y, b, partials);
+  return (MODE == 1 || MODE == 2) ? (int)grid.x : 0;
 }
 
 template <int MODE>
-void spmv_dim(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
-              double* partials, hipStream_t s) {
+int spmv_dim(const Batch& B, const int32_t* nbr, const double* x, double* y, const double* b,
+             double* partials, hipStream_t s) {
   switch (B.duni) {
-    case 1: spmv_mode<MODE, 1>(B, nbr, x, y, b, partials, s); break;
-    case 2: spmv_mode<MODE, 2>(B, nbr, x, y, b, partials, s); break;
-    case 3: spmv_mode<MODE, 3>(B, nbr, x, y, b, partials, s); break;
-    case 4: spmv_mode<MODE, 4>(B, nbr, x, y, b, partials, s); break;
-    case 5: spmv_mode<MODE, 5>(B, nbr, x, y, b, partials, s); break;
-    case 6: spmv_mode<MODE, 6>(B, nbr, x, y, b, partials, s); break;
-    default: spmv_mode<MODE, 0>(B, nbr, x, y, b, partials, s); break;
+    case 1: return spmv_mode<MODE, 1>(B, nbr, x, y, b, partials, s);
+    case 2: return spmv_mode<MODE, 2>(B, nbr, x, y, b, partials, s);
+    case 3: return spmv_mode<MODE, 3>(B, nbr, x, y, b, partials, s);
+    case 4: return spmv_mode<MODE, 4>(B, nbr, x, y, b, partials, s);
+    case 5: return spmv_mode<MODE, 5>(B, nbr, x, y, b, partials, s);
+    case 6: return spmv_mode<MODE, 6>(B, nbr, x, y, b, partials, s);
+    default: return spmv_mode<MODE, 0>(B, nbr, x, y, b, partials, s);
   }
 }
 
-void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
-                 const double* b, double* partials, hipStream_t s) {
-  if (mode == 2) spmv_dim<2>(B, nbr, x, y, b, partials, s);
-  else if (mode == 1) spmv_dim<1>(B, nbr, x, y, b, partials, s);
-  else if (mode == 3) spmv_dim<3>(B, nbr, x, y, b, partials, s);
-  else spmv_dim<0>(B, nbr, x, y, b, partials, s);
+int launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
+                const double* b, double* partials, hipStream_t s) {
+  if (mode == 2) return spmv_dim<2>(B, nbr, x, y, b, partials, s);
+  if (mode == 1) return spmv_dim<1>(B, nbr, x, y, b, partials, s);
+  if (mode == 3) return spmv_dim<3>(B, nbr, x, y, b, partials, s);
+  return spmv_dim<0>(B, nbr, x, y, b, partials, s);
 }
-
 
 // ---------------------------------------------------------------------------
 // Symmetric matrix-vector product with a packed lower-tiled symmetric matrix
@@ -614,15 +643,26 @@ void launch_dot(const Batch& B, const double* a, const double* b, const double* 
 
 // Second reduction stage plus the scalar recurrences of CG, one block per grid.
 __global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
-                                                          const double* __restrict__ partials,
+                                                          const double* __restrict__ partials, int np,
                                                           double* __restrict__ Sall,
                                                           int32_t* __restrict__ active) {
   __shared__ double sh[16];
   const int gi = blockIdx.x;
-  const double* pp = partials + (int64_t)gi * B.rbx;
-  const double* pp2 = partials + (int64_t)B.G * B.rbx + (int64_t)gi * B.rbx;
+  const double* pp = partials + (int64_t)gi * np;
+  const double* pp2 = partials + (int64_t)B.G * np + (int64_t)gi * np;
   double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < B.rbx; i += blockDim.x) {
+  // four independent loads in flight per thread (the per-block partials of
+  // a large grid's SpMV number up to one per 256 points)
+  int i = threadIdx.x;
+  for (; i + 3 * RED_THREADS < np; i += 4 * RED_THREADS) {
+    const double a0 = pp[i], a1 = pp[i + RED_THREADS], a2 = pp[i + 2 * RED_THREADS], a3 = pp[i + 3 * RED_THREADS];
+    s0 += a0; s0 += a1; s0 += a2; s0 += a3;
+    if (mode == FIN_RZ_NEXT_FLEX) {
+      const double b0 = pp2[i], b1 = pp2[i + RED_THREADS], b2 = pp2[i + 2 * RED_THREADS], b3 = pp2[i + 3 * RED_THREADS];
+      s1 += b0; s1 += b1; s1 += b2; s1 += b3;
+    }
+  }
+  for (; i < np; i += RED_THREADS) {
     s0 += pp[i];
     if (mode == FIN_RZ_NEXT_FLEX) s1 += pp2[i];
   }
@@ -666,8 +706,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
 }
 
 void launch_finalize(const Batch& B, int mode, const double* partials, double* scal,
-                     int32_t* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(B.G), dim3(RED_THREADS), 0, s, B, mode, partials, scal, active);
+                     int32_t* active, hipStream_t s, int nparts) {
+  hipLaunchKernelGGL(k_finalize, dim3(B.G), dim3(RED_THREADS), 0, s, B, mode, partials,
+                     nparts > 0 ? nparts : B.rbx, scal, active);
 }
 
 // x += alpha_g p, r -= alpha_g q on active grids; per-grid partials of r . r.

@@ -58,7 +58,8 @@ struct Batch {
   const uint16_t* cgid;     // grid of each coarse unknown
   const uint16_t* ctgid;    // grid of each coarse tile
   int rbx;                  // reduction blocks per grid
-  int spmv_u, spmv_win;     // SpMV launch shape: points per thread and step, LDS window
+  int spmv_u;               // SpMV launch shape: points per thread (window of 256 u points)
+  int64_t maxN;             // points of the largest grid
   const int32_t* cperm;     // position of every coarse block in its grid's coarse numbering
 };
 
@@ -164,9 +165,12 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
                   hipStream_t s);
 
 // ---- per-iteration operators ---------------------------------------------
+// Blocks per grid of the windowed SpMV for grids of up to maxN points.
+int spmv_blocks(int64_t maxN, int u);
 // mode 0: y = A x;  1: y = A x, per-grid partials of x.y;  2: y = b - A x,
-// per-grid partials of y.y;  3: y = b - A x.
-void launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
+// per-grid partials of y.y;  3: y = b - A x.  Returns the partials written
+// per grid (0 for modes 0 and 3), the count launch_finalize then takes.
+int launch_spmv(const Batch& B, int mode, const int32_t* nbr, const double* x, double* y,
                  const double* b, double* partials, hipStream_t s);
 // active (nullable): per-grid solver flags; subdomains of grids that are not
 // updating (flag not RUN or RESTART) are skipped.
@@ -228,8 +232,9 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
 // ---- BLAS-1 and scalars (per grid) -----------------------------------------
 void launch_dot(const Batch& B, const double* a, const double* b, const double* c,
                 double* partials, hipStream_t s);
+// nparts: partials per grid (0: rbx, the BLAS-1 reductions' count).
 void launch_finalize(const Batch& B, int mode, const double* partials, double* scal,
-                     int32_t* active, hipStream_t s);
+                     int32_t* active, hipStream_t s, int nparts = 0);
 void launch_update_xr(const Batch& B, const double* scal, const int32_t* active, double* x,
                       double* r, const double* p, const double* q, double* partials,
                       hipStream_t s);

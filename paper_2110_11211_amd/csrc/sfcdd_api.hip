@@ -90,11 +90,12 @@ struct sfcdd_ctx {
   std::vector<int32_t> c_nt, c_n;
   std::vector<int64_t> c_off, c_xoff, c_poff, c_doff, c_toff;
   int max_nt = 0, max_Ni = 0, min_Ni = 0, max_nt0 = 0, max_N0 = 0;
+  int64_t maxN = 1;  // points of the largest grid
   int64_t sum_Ni = 0, tiles = 0, parts = 0, xlen = 0, ctiles = 0, cparts = 0, c0len = 0;
   int64_t ctinv = 0;  // tiles of the coarse inversion workspace (all grids)
   int trsv_waves = 16;
   int trsv_stream = -1;  // non-temporal factor loads: -1 by the size rule, 0 off, 1 on (autotuned)
-  int spmv_u = 2, spmv_win = 512;   // SpMV launch shape (autotuned)
+  int spmv_u = 2, spmv_win = 512;   // SpMV launch shape: points per thread, window 256 u (autotuned)
   int factor_rows = 0, factor_pair = -1;  // batched factorisation shape (0 / -1: rules)
   // workspace regions
   Region r_sfc, r_pos, r_nbr, r_gid, r_grids, r_ta, r_Ni, r_nt, r_off, r_doff, r_xoff, r_poff,
@@ -171,7 +172,7 @@ struct sfcdd_ctx {
     B.ctgid = ctgid;
     B.rbx = rbx;
     B.spmv_u = spmv_u;
-    B.spmv_win = spmv_win;
+    B.maxN = maxN;
     B.cperm = cperm;
     return B;
   }
@@ -603,6 +604,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   int64_t maxN = 1;
   for (int k = 0; k < G; ++k) maxN = std::max<int64_t>(maxN, c->grid[k].desc.N);
   c->rbx = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(8, ceil_div(maxN, (int64_t)RED_THREADS)));
+  c->maxN = maxN;
   c->max_cblock = 1;
   for (int k = 0; k < G; ++k) {
     const GridDesc& gd = c->grid[k].desc;
@@ -650,7 +652,9 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_cy = pl.take((size_t)c->c0len * 8);
   c->r_dbuf = pl.take((size_t)c->sum_Ni * 8);
   c->r_vec = pl.take((size_t)NVEC * (((size_t)Nt * 8 + 255) & ~size_t(255)));
-  c->r_partials = pl.take((size_t)8 * (2 * (size_t)G * c->rbx + (size_t)MAXD * RED_BLOCKS));
+  // reductions: rbx partials per grid (two sums), or one per SpMV block
+  c->r_partials = pl.take((size_t)8 * (2 * (size_t)G * std::max(c->rbx, spmv_blocks(maxN, 1)) +
+                                      (size_t)MAXD * RED_BLOCKS));
   c->r_scal = pl.take((size_t)8 * G * S_COUNT);
   c->r_active = pl.take((size_t)4 * G);
   c->r_status = pl.take(64);
@@ -913,9 +917,10 @@ void fine_apply(sfcdd_ctx* c, const double* w, double* y, const int32_t* mask = 
                  c->dbuf, y, c->stream);
 }
 
-void spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, double* partials) {
-  ProfScope ps(c, SFCDD_K_SPMV);
-  launch_spmv(c->batch(), mode, c->nbr, x, y, b, partials, c->stream);
+// Returns the per-grid partials written (modes 1 and 2), for the finalize.
+int spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, double* partials) {
+  ProfScope ps(c, mode >= 2 ? SFCDD_K_SPMV_B : SFCDD_K_SPMV);
+  return launch_spmv(c->batch(), mode, c->nbr, x, y, b, partials, c->stream);
 }
 
 void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask);
@@ -930,7 +935,7 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h, const int32_t* mask = nul
     double *t = c->vec[V_T], *w = c->vec[V_W], *y = c->vec[V_Y], *v = c->vec[V_V];
     coarse_solve(c, g, mask);                                   // d0 = A0^{-1} R0 g
     launch_combine(B, COMB_PROLONG, c->d0, nullptr, nullptr, t, s);  // t = F g
-    spmv(c, 2, t, w, g, c->partials);                           // w = g - A t = G g
+    spmv(c, 3, t, w, g, nullptr);                               // w = g - A t = G g
     fine_apply(c, w, y, mask);                                  // y = C1^{-1} G g
     spmv(c, 0, y, v, nullptr, nullptr);                         // v = A y
     coarse_solve(c, v, mask);                                   // d0 = A0^{-1} R0 A y
@@ -1514,7 +1519,7 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
     r->trsv_ms = rec.t;
     r->trsv_default_ms = rec.t_default;
   }
-  // SpMV: points per thread and step, LDS window
+  // SpMV: points per thread (and window)
   if (st == SFCDD_OK && (what & SFCDD_TUNE_SPMV)) {
     const uint64_t key = key_spmv(c, dev);
     TuneRecord rec;
@@ -1525,18 +1530,18 @@ sfcdd_status tune_shapes(sfcdd_ctx* c, int32_t repeats, int32_t what, sfcdd_tuni
       if (it != g_tune_spmv.end()) { rec = it->second; have = true; }
     }
     if (!have) {
-      const int us[2] = {2, 1}, wins[4] = {512, 256, 1024, 2048};
+      // points per thread (the window is 256 of them per thread); the
+      // default first
+      const int us[3] = {2, 1, 4};
       rec.t = 1e300;
-      for (int i = 0; i < 2 && st == SFCDD_OK; ++i)
-        for (int j = 0; j < 4 && st == SFCDD_OK; ++j) {
-          Batch B = c->batch();
-          B.spmv_u = us[i];
-          B.spmv_win = wins[j];
-          double ms = 0.0;
-          st = timed([&] { launch_spmv(B, 0, c->nbr, w, y, nullptr, nullptr, s); }, &ms);
-          if (i == 0 && j == 0) rec.t_default = ms;
-          if (ms < rec.t) { rec.t = ms; rec.a = us[i]; rec.b = wins[j]; }
-        }
+      for (int i = 0; i < 3 && st == SFCDD_OK; ++i) {
+        Batch B = c->batch();
+        B.spmv_u = us[i];
+        double ms = 0.0;
+        st = timed([&] { launch_spmv(B, 0, c->nbr, w, y, nullptr, nullptr, s); }, &ms);
+        if (i == 0) rec.t_default = ms;
+        if (ms < rec.t) { rec.t = ms; rec.a = us[i]; rec.b = RED_THREADS * us[i]; }
+      }
       if (st == SFCDD_OK) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_spmv[key] = rec;
@@ -1825,7 +1830,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   }
   if (proj) {
     // x <- x + F (b - A x), so that R_0 (b - A x) = 0 (balancing start)
-    spmv(c, 2, x, tmp, b, c->partials);
+    spmv(c, 3, x, tmp, b, nullptr);
     coarse_solve(c, tmp);
     launch_combine(B, COMB_ADD_PROLONG, c->d0, x, nullptr, x, s);
   }
@@ -1841,12 +1846,13 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
   }
   // the squared norm a grid's stopping test looks at, from the partials of
   // the residual's r . r just formed: that norm, or (energy test) -(x . r)
-  auto norm_fin = [&](int rr_mode, int en_mode) {
+  // (np: the partials' count per grid, from the SpMV that formed them, or 0)
+  auto norm_fin = [&](int rr_mode, int en_mode, int np) {
     if (energy) {
       launch_dot(B, x, r, nullptr, c->partials, s);
       launch_finalize(B, en_mode, c->partials, c->scal, en_mode == FIN_EN ? nullptr : c->active, s);
     } else {
-      launch_finalize(B, rr_mode, c->partials, c->scal, rr_mode == FIN_RR ? nullptr : c->active, s);
+      launch_finalize(B, rr_mode, c->partials, c->scal, rr_mode == FIN_RR ? nullptr : c->active, s, np);
     }
   };
   std::vector<int32_t> flags(G, ACT_RUN), its(G, 0), stagnated(G, 0);
@@ -1898,14 +1904,14 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       std::vector<int32_t> ok(G, ACT_RUN);
       if ((st = write_active(c, ok))) return st;
       launch_zero(N, z, s);  // z is the iterate of the estimation run (on the residual of x)
-      spmv(c, 2, x, r, b, c->partials);
+      spmv(c, 3, x, r, b, nullptr);
       precond(r, q);
       launch_copy(N, q, p, s);
       launch_dot(B, r, q, nullptr, c->partials, s);
       launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, c->active, s);
       for (int k = 0; k < 30; ++k) {
-        spmv(c, 1, p, tmp, nullptr, c->partials);
-        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s);
+        const int np = spmv(c, 1, p, tmp, nullptr, c->partials);
+        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s, np);
         launch_update_xr(B, c->scal, c->active, z, r, p, tmp, c->partials, s);
         if ((st = read_scal(c))) return st;
         for (int g = 0; g < G; ++g) {
@@ -1946,8 +1952,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     }
     inf.xi = xig[0];
     // r = b - A x and its norm; damping and tolerances to the device
-    spmv(c, 2, x, r, b, c->partials);
-    norm_fin(FIN_RR, FIN_EN);
+    norm_fin(FIN_RR, FIN_EN, spmv(c, 2, x, r, b, c->partials));
     if ((st = read_rr())) return st;
     for (int g = 0; g < G; ++g) {
       c->host_scal[(size_t)g * S_COUNT + S_XI] = xig[g];
@@ -1962,8 +1967,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         // x += xi C^{-1} r; r = b - A x; a grid below tolerance stops (DONE)
         const std::vector<int32_t> before = flags;
         launch_axpy_scal(B, c->scal, S_XI, c->active, x, z, s);
-        spmv(c, 2, x, r, b, c->partials);
-        norm_fin(FIN_RR_DONE, FIN_EN_DONE);
+        norm_fin(FIN_RR_DONE, FIN_EN_DONE, spmv(c, 2, x, r, b, c->partials));
         if ((st = enqueue_readback())) return st;
         ++it;
         if (it < max_iter) precond(r, z);  // next iteration's, speculatively
@@ -1982,8 +1986,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     const bool flex = method == SFCDD_FCG || c->coarse_iter;
     const int fin_rz = flex ? FIN_RZ_NEXT_FLEX : FIN_RZ_NEXT;
     // r = b - A x
-    spmv(c, 2, x, r, b, c->partials);
-    norm_fin(FIN_RR, FIN_EN);
+    norm_fin(FIN_RR, FIN_EN, spmv(c, 2, x, r, b, c->partials));
     if ((st = read_rr())) return st;
     for (int g = 0; g < G; ++g) {
       c->host_scal[(size_t)g * S_COUNT + S_TOL2] = tol2[g];
@@ -2001,10 +2004,10 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         // step: x += alpha p, r -= alpha q; a grid whose recursive residual is
         // below tolerance is frozen (CAND) until its true residual is checked
         const std::vector<int32_t> before = flags;
-        spmv(c, 1, p, q, nullptr, c->partials);
-        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s);
+        const int np = spmv(c, 1, p, q, nullptr, c->partials);
+        launch_finalize(B, FIN_PQ_ALPHA, c->partials, c->scal, c->active, s, np);
         launch_update_xr(B, c->scal, c->active, x, r, p, q, c->partials, s);
-        norm_fin(FIN_RR_CAND, FIN_EN_CAND);
+        norm_fin(FIN_RR_CAND, FIN_EN_CAND, 0);
         if ((st = enqueue_readback())) return st;
         ++it;
         if (it < max_iter) {
@@ -2033,8 +2036,8 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
           // confirm on the true residual; a grid whose true residual is still
           // too large restarts from its current x (residual replacement),
           // unless it has not halved since the grid's previous restart
-          spmv(c, 2, x, tmp, b, c->partials);
-          launch_finalize(B, FIN_TRR, c->partials, c->scal, nullptr, s);
+          const int np = spmv(c, 2, x, tmp, b, c->partials);
+          launch_finalize(B, FIN_TRR, c->partials, c->scal, nullptr, s, np);
           if ((st = read_scal(c))) return st;
           std::vector<int32_t> pass(G, ACT_SKIP);
           bool any_restart = false;

@@ -495,7 +495,7 @@ def test_tune_launch_shapes_keeps_parity(fdtype):
     print(f"tuning {fdtype}: {rep}", flush=True)
     assert rep["tuned"] == 7
     assert rep["trsv_waves"] in (4, 8, 16)
-    assert rep["spmv_points"] in (1, 2) and rep["spmv_window"] in (256, 512, 1024, 2048)
+    assert rep["spmv_points"] in (1, 2, 4) and rep["spmv_window"] == 256 * rep["spmv_points"]
     assert rep["factor_pair"] in (0, 1)
     # rows 1: the light kernel, one column per step
     assert rep["factor_rows"] in ((1, 2, 3, 4) if fdtype == "fp32" else ((1, 2, 3) if rep["factor_pair"] == 0 else (2,)))
