@@ -602,13 +602,13 @@ def main():
         wl = workloads()["c5"]
         fl_dev = torch.tensor(wl.rhs(), dtype=torch.float64, device="cuda:0")
         big = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1,
-                       tune=None if args.no_tune else 1)
+                       tune=None if args.no_tune else 2)
         big["x"] = big["x"].cpu().numpy()
         ws_cache.clear()
         torch.cuda.empty_cache()
         # the same grid at the paper's q = 64 (N0 = 262,144) with the iterative coarse solve
         bigi = run_path(wl, fl_dev, "fp32", args.local, 2, 1, ws_cache, prof_steps=1, coarse_solver="iterative",
-                        tune=None if args.no_tune else 1)
+                        tune=None if args.no_tune else 2)
         bigi["x"] = bigi["x"].cpu().numpy()
         del fl_dev
         ws_cache.clear()

@@ -147,6 +147,12 @@ template <typename T> struct TileAcc {
       for (int b = 0; b < 2; ++b)
         for (int r = 0; r < 4; ++r) s[row(a, r) * S + col(b)] = c[a][b][r];
   }
+  __device__ __forceinline__ void store_lds_t(T* __restrict__ s) const {  // transposed, stride LdsV
+    constexpr int S = LdsV<T>::v;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int r = 0; r < 4; ++r) s[col(b) * S + row(a, r)] = c[a][b][r];
+  }
 };
 
 // acc += sign * A Bt^T for LDS tiles sA[i][k] and sBt[j][k] (both

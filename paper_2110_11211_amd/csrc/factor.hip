@@ -793,6 +793,72 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
 // So the chain from one diagonal tile to the next holds no chunk sums and no
 // cross-workgroup handshake: five tile products and a diagonal
 // factorisation.
+// Tile (J, C), C <= J, of X = L^{-1} for a single matrix, formed row by row
+// as the factorisation proceeds (L X = I):
+//   X_JJ = L_JJ^{-1},  X_JC = -L_JJ^{-1} sum_{max(C, lo[J]) <= K < J} L_JK X_KC.
+// Row J of L is complete once column J - 1 is factored, and the rows of X
+// above it were formed earlier, so row J of X is formed by extra workgroups
+// of the column step J (the chain itself does not wait for them), and the
+// inversion no longer follows the factorisation on the setup's critical
+// path.  X is a packed lower-triangular tile matrix at X.  A row takes up to
+// (row width of the envelope) tile products in one workgroup: for envelopes
+// wider than XROW_MAXW tiles (the device-side width *wide) the rows would
+// outlast the column steps, and the recursive inversion after the
+// factorisation (whose kernels skip otherwise) is used instead.
+template <typename T, typename IX>
+__device__ __forceinline__ void xrow_tile(int J, int C, const T* __restrict__ F, T* __restrict__ X, T* sA,
+                                          T* sB, IX ix) {
+  T* XD = X + tri_index(J, C) * TS2;
+  if (C == J) {
+    typedef typename Vec16<T>::type V;
+    const V* src = reinterpret_cast<const V*>(F + ix(J, J) * TS2);
+    V* dst = reinterpret_cast<V*>(XD);
+    for (int e = threadIdx.x; e < TS2 / Vec16<T>::n; e += TILE_THREADS) dst[e] = src[e];
+    return;
+  }
+  const int k0 = max(C, ix.first(J));
+  TileAcc<T> acc;
+  acc.zero();
+  TileRegs<T> ra, rb;
+  if (k0 < J) {
+    ra.load(F + ix(J, k0) * TS2);
+    rb.load(X + tri_index(k0, C) * TS2);
+  }
+  for (int K = k0; K < J; ++K) {
+    lds_barrier();
+    ra.store_lds(sA);
+    rb.store_lds_t(sB);
+    lds_barrier();
+    if (K + 1 < J) {
+      ra.load(F + ix(J, K + 1) * TS2);
+      rb.load(X + tri_index(K + 1, C) * TS2);
+    }
+    tile_mma<T>(acc, sA, sB, T(1));  // sum L_JK X_KC
+  }
+  lds_barrier();
+  acc.store_lds_t(sB);
+  stage_tile(sA, F + ix(J, J) * TS2);  // L_JJ^{-1}
+  lds_barrier();
+  TileAcc<T> out;
+  out.zero();
+  tile_mma<T>(out, sA, sB, T(-1));
+  out.store(XD);
+}
+
+// The last row of X (after the last column step).
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_xrow(int J, const int64_t* __restrict__ off,
+                                                       const T* __restrict__ fac, T* __restrict__ X,
+                                                       const int32_t* __restrict__ tlo,
+                                                       const int32_t* __restrict__ trb,
+                                                       const int32_t* __restrict__ wide) {
+  if (wide && *wide > XROW_MAXW) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LdsV<T>::v;
+  xrow_tile<T, Env>(J, (int)blockIdx.x, fac + off[0] * TS2, X + off[0] * TS2, sA, sB, Env{tlo, trb});
+}
+
 template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T* __restrict__ part,
                                                              int64_t slot_tiles,
@@ -801,13 +867,14 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
                                                              T* __restrict__ fac,
                                                              int32_t* __restrict__ status,
                                                              const int32_t* __restrict__ tlo,
-                                                             const int32_t* __restrict__ trb) {
+                                                             const int32_t* __restrict__ trb,
+                                                             T* __restrict__ X, int nwg,
+                                                             const int32_t* __restrict__ wide) {
   // The steps form a chain of dependent launches that runs beside the
   // throughput-bound batched factorisation of the subdomains; the highest
   // wave priority lets its instructions issue first on the shared SIMDs
   // (the 127 steps of the 8192-unknown coarse matrix: 10.4 -> 8.5 ms beside
   // it, the batched factorisation 9.9 -> 10.5 ms).
-  __builtin_amdgcn_s_setprio(3);
   const int ntb = nt[0];
   const int m = ntb - 1 - J;  // tiles below the diagonal in column J
   if (m <= 0) return;
@@ -817,6 +884,12 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
   T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[0] * TS2;
   const int x = blockIdx.x;
+  if (x >= nwg) {  // row J of the inverse (normal priority: off the chain)
+    if (wide && *wide > XROW_MAXW) return;
+    xrow_tile<T, Env>(J, x - nwg, F, X + off[0] * TS2, sA, sB, ix);
+    return;
+  }
+  __builtin_amdgcn_s_setprio(3);
   auto slot = [&](int C) { return part + (int64_t)(C % 3) * slot_tiles * TS2; };
   // column J: partials over K <= J - 3, direct terms from K = max(0, J - 2)
   const int kd = J >= 2 ? J - 2 : 0;
@@ -955,7 +1028,7 @@ void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int6
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
                        const int64_t* off, T* fac, int32_t* status, hipStream_t s, const int32_t* tlo,
-                       const int32_t* trb) {
+                       const int32_t* trb, T* X, const int32_t* wide) {
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
   const int nc = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
@@ -963,8 +1036,17 @@ void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles,
   const size_t sh = std::max(2 * TS * LdsV<T>::v * sizeof(T), diag_lds_bytes<T>());
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg), dim3(TILE_THREADS), sh, s, J, maxc, part, slot_tiles, nt,
-                     off, fac, status, tlo, trb);
+  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg + (X ? J + 1 : 0)), dim3(TILE_THREADS), sh, s, J, maxc, part,
+                     slot_tiles, nt, off, fac, status, tlo, trb, X, nwg, wide);
+}
+
+template <typename T>
+void launch_xrow(int J, const int64_t* off, const T* fac, T* X, hipStream_t s, const int32_t* tlo,
+                 const int32_t* trb, const int32_t* wide) {
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
+  static bool once = (allow_lds(k_xrow<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_xrow<T>, dim3(J + 1), dim3(TILE_THREADS), sh, s, J, off, fac, X, tlo, trb, wide);
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -1039,7 +1121,9 @@ template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_trtri_diag_copy(const int32_t* __restrict__ nt,
                                                                   const int64_t* __restrict__ off,
                                                                   const T* __restrict__ L,
-                                                                  T* __restrict__ X) {
+                                                                  T* __restrict__ X,
+                                                                  const int32_t* __restrict__ wide) {
+  if (wide && *wide <= XROW_MAXW) return;
   const int b = blockIdx.y, k = blockIdx.x;
   if (k >= nt[b]) return;
   typedef typename Vec16<T>::type V;
@@ -1068,7 +1152,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_t(int s, const int32
                                                               const T* __restrict__ X,
                                                               T* __restrict__ Tb,
                                                               const int64_t* __restrict__ xoff,
-                                                              const int32_t* __restrict__ tlo) {
+                                                              const int32_t* __restrict__ tlo,
+                                                              const int32_t* __restrict__ wide) {
+  if (wide && *wide <= XROW_MAXW) return;  // inverted beside the factorisation
   constexpr int S = LdsV<T>::v;
   const int b = blockIdx.z, p = blockIdx.y;
   const int ng = (s + R - 1) / R;
@@ -1134,7 +1220,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
                                                               const T* __restrict__ Tb,
                                                               T* __restrict__ X,
                                                               const int64_t* __restrict__ xoff,
-                                                              const int32_t* __restrict__ tlo) {
+                                                              const int32_t* __restrict__ tlo,
+                                                              const int32_t* __restrict__ wide) {
+  if (wide && *wide <= XROW_MAXW) return;  // inverted beside the factorisation
   constexpr int S = LdsV<T>::v;
   const int b = blockIdx.z, p = blockIdx.y;
   const int g = blockIdx.x / s, jj = blockIdx.x % s;
@@ -1191,18 +1279,20 @@ __global__ __launch_bounds__(TILE_THREADS) void k_trtri_rec_x(int s, const int32
 
 template <typename T>
 void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
-                      const T* L, T* X, T* Tb, hipStream_t st, const int64_t* xoff, const int32_t* tlo) {
+                      const T* L, T* X, T* Tb, hipStream_t st, const int64_t* xoff, const int32_t* tlo,
+                      const int32_t* wide) {
   constexpr int R = TRTRI_ROWS;
   const size_t sh = (R + 1) * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_trtri_rec_t<T, R>, sh), allow_lds(k_trtri_rec_x<T, R>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_trtri_diag_copy<T>, dim3(max_nt, nb), dim3(TILE_THREADS), 0, st, nt, off, L, X);
+  hipLaunchKernelGGL(k_trtri_diag_copy<T>, dim3(max_nt, nb), dim3(TILE_THREADS), 0, st, nt, off, L, X, wide);
   for (int s = 1; s < max_nt; s *= 2) {
     const int npairs = (max_nt + 2 * s - 1) / (2 * s);
     const dim3 grid(s * ((s + R - 1) / R), npairs, nb);
     hipLaunchKernelGGL((k_trtri_rec_t<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, L, X, Tb, xoff,
-                       tlo);
-    hipLaunchKernelGGL((k_trtri_rec_x<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X, xoff, tlo);
+                       tlo, wide);
+    hipLaunchKernelGGL((k_trtri_rec_x<T, R>), grid, dim3(TILE_THREADS), sh, st, s, nt, off, toff, Tb, X, xoff, tlo,
+                       wide);
   }
 }
 
@@ -1264,12 +1354,16 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
                                      const int32_t*, const int32_t*, T*, int32_t*, bool,           \
                                      hipStream_t, int);                                            \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
-                                     T*, int32_t*, hipStream_t, const int32_t*, const int32_t*);   \
+                                     T*, int32_t*, hipStream_t, const int32_t*, const int32_t*, T*, \
+                                     const int32_t*);                                              \
+  template void launch_xrow<T>(int, const int64_t*, const T*, T*, hipStream_t, const int32_t*,     \
+                               const int32_t*, const int32_t*);                                    \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \
   template void launch_trtri_rec<T>(int, int, const int32_t*, const int64_t*, const int64_t*,     \
-                                    const T*, T*, T*, hipStream_t, const int64_t*, const int32_t*);
+                                    const T*, T*, T*, hipStream_t, const int64_t*, const int32_t*,  \
+                                    const int32_t*);
 INST(float)
 INST(double)
 #undef INST

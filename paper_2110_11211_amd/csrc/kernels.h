@@ -111,9 +111,11 @@ void launch_coarse_order(const Batch& B, int kcap, int max_n0, const int32_t* sf
 void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
                           int32_t* cnt, int32_t* cfnz, hipStream_t s);
 // Envelope tables of the dense coarse matrices (per tile row at c0pad / TS):
-// first tile column clo (non-decreasing) and packed-triangle row base crb.
+// first tile column clo (non-decreasing) and packed-triangle row base crb;
+// wide[0] (nullable): the envelope width of grid 0's matrix (the most tile
+// columns left of the diagonal in a tile row).
 void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb,
-                       hipStream_t s);
+                       int32_t* wide, hipStream_t s);
 void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
                               hipStream_t s);
 void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, double* A0,
@@ -144,22 +146,34 @@ void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int6
 template <typename T>
 void launch_unit_lower(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* xoff,
                        const int32_t* tlo, const int32_t* trb, T* fac, hipStream_t s);
+// Widest envelope (tile columns left of the diagonal, over the tile rows)
+// for which the column steps also form the rows of the inverse.
+constexpr int XROW_MAXW = 24;
 // One matrix: sub-diagonal tiles of column J, the diagonal tile of column
 // J + 1, and the split-K partials of column J + 2 (three slots of slot_tiles
-// tiles at part, slot C mod 3 for column C).
+// tiles at part, slot C mod 3 for column C).  X (nullable): also row J of
+// the inverse X = L^{-1} (packed lower tiles at X + off[0] tiles), whose
+// last row launch_xrow forms after the last step, when the device-side
+// envelope width *wide is at most XROW_MAXW.
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
                        const int64_t* off, T* fac, int32_t* status, hipStream_t s,
-                       const int32_t* tlo = nullptr, const int32_t* trb = nullptr);
+                       const int32_t* tlo = nullptr, const int32_t* trb = nullptr, T* X = nullptr,
+                       const int32_t* wide = nullptr);
+template <typename T>
+void launch_xrow(int J, const int64_t* off, const T* fac, T* X, hipStream_t s, const int32_t* tlo,
+                 const int32_t* trb, const int32_t* wide);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);
 // xoff / tlo (nullable): envelope of each L (first tile column per tile row
-// at xoff[b] / TS); the tile sums skip the zero tiles left of it.
+// at xoff[b] / TS); the tile sums skip the zero tiles left of it.  wide
+// (nullable): the device-side envelope width of a single matrix; at most
+// XROW_MAXW, the column steps formed X and these kernels return at once.
 template <typename T>
 void launch_trtri_rec(int nb, int max_nt, const int32_t* nt, const int64_t* off, const int64_t* toff,
                       const T* L, T* X, T* Tb, hipStream_t s, const int64_t* xoff = nullptr,
-                      const int32_t* tlo = nullptr);
+                      const int32_t* tlo = nullptr, const int32_t* wide = nullptr);
 template <typename T>
 void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, const T* X, T* M,
                   hipStream_t s);

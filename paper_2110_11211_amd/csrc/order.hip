@@ -490,7 +490,8 @@ void launch_coarse_order(const Batch& B, int kcap, int max_n0, const int32_t* sf
 // workgroup per grid.
 __global__ __launch_bounds__(ORDER_THREADS) void k_coarse_env(Batch B, const int32_t* __restrict__ cfnz,
                                                               int32_t* __restrict__ clo,
-                                                              int32_t* __restrict__ crb) {
+                                                              int32_t* __restrict__ crb,
+                                                              int32_t* __restrict__ wide) {
   const GridDesc& g = B.grids[blockIdx.x];
   const int nt = g.nt0d;
   const int64_t trow = g.c0pad / TS;
@@ -500,18 +501,21 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_coarse_env(Batch B, const int
   for (int r = threadIdx.x; r < nt * TS; r += ORDER_THREADS) atomicMin(&tmin[r / TS], cfnz[g.c0pad + r] / TS);
   __syncthreads();
   if (threadIdx.x == 0) {
-    int lo = nt;
+    int lo = nt, w = 0;
     for (int I = nt - 1; I >= 0; --I) {
       lo = min(lo, tmin[I]);
       clo[trow + I] = lo;
       crb[trow + I] = I * (I + 1) / 2;
+      w = max(w, I - lo);
     }
+    if (wide && blockIdx.x == 0) wide[0] = w;
   }
 }
 
-void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb, hipStream_t s) {
+void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb,
+                       int32_t* wide, hipStream_t s) {
   const size_t sh = (size_t)max_nt0 * sizeof(int);
-  hipLaunchKernelGGL(k_coarse_env, dim3(B.G), dim3(ORDER_THREADS), sh, s, B, cfnz, clo, crb);
+  hipLaunchKernelGGL(k_coarse_env, dim3(B.G), dim3(ORDER_THREADS), sh, s, B, cfnz, clo, crb, wide);
 }
 
 void launch_local_order(const Batch& B, int mode, int kcap, int max_nt, const int32_t* ta, const int32_t* Ni,

@@ -783,11 +783,14 @@ void bind(sfcdd_ctx* c) {
 // xoff / tlo / trb: the envelope tables of the matrices (first tile column and
 // row base per tile row at xoff[b] / TS; a single matrix uses those of
 // matrix 0 at tlo / trb).
+// wide (single matrix): device-side envelope width, which picks the inversion
+// beside the column steps (narrow envelopes) or after them.
 template <typename T>
 void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* fac, T* X,
                   bool invert, bool product, int32_t* status, T* part, T* tbuf,
                   const int64_t* toff, bool pair, hipStream_t s, int rows = 0,
-                  const int64_t* xoff = nullptr, const int32_t* tlo = nullptr, const int32_t* trb = nullptr) {
+                  const int64_t* xoff = nullptr, const int32_t* tlo = nullptr, const int32_t* trb = nullptr,
+                  const int32_t* wide = nullptr) {
   const int maxc = (max_nt + SPLITK - 1) / SPLITK;
   if (!part) {
     // batch: one workgroup factors a whole matrix
@@ -796,13 +799,17 @@ void factor_batch(int nb, int max_nt, const int32_t* nt, const int64_t* off, T* 
     // one matrix: the first diagonal tile, then one step per column (its
     // sub-diagonal tiles, the next diagonal tile, split-K partials two
     // columns ahead in three slots)
+    // (inverting a narrow envelope: row J of X = L^{-1} formed in step J
+    // beside the chain; the recursive inversion below then skips)
     launch_potrf_diag<T>(0, 0, 0, maxc, part, 1, nt, off, fac, status, s, tlo, trb);
     for (int J = 0; J + 1 < max_nt; ++J)
-      launch_potrf_step<T>(J, max_nt, maxc, part, (int64_t)max_nt * maxc, nt, off, fac, status, s, tlo, trb);
+      launch_potrf_step<T>(J, max_nt, maxc, part, (int64_t)max_nt * maxc, nt, off, fac, status, s, tlo, trb,
+                           invert && wide ? X : nullptr, wide);
+    if (invert && wide) launch_xrow<T>(max_nt - 1, off, fac, X, s, tlo, trb, wide);
   }
   if (invert) {
     if (tbuf) {
-      launch_trtri_rec<T>(nb, max_nt, nt, off, toff, fac, X, tbuf, s, xoff, tlo);
+      launch_trtri_rec<T>(nb, max_nt, nt, off, toff, fac, X, tbuf, s, xoff, tlo, part ? wide : nullptr);
     } else {
       for (int J = max_nt - 1; J >= 0; --J) launch_trtri_col<T>(J, nb, max_nt, nt, off, fac, X, s);
     }
@@ -1169,7 +1176,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
-    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, cs);
+    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, cs);
     // Beside FP32 subdomain factors the inverse X_0 = L_0^{-1} is FP32: A_0
     // is an M-matrix (a Galerkin aggregation of the stencil matrix), so L_0
     // has non-positive off-diagonal entries, X_0 is entrywise non-negative
@@ -1184,7 +1191,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
         launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
         factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
                             c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs, 0,
-                            c->dc_xoff, c->clo, c->crb);
+                            c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
       } else {
         factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, false, false, c->status + 1,
                              G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
@@ -1196,7 +1203,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     } else {
       factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
                            G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
-                           c->dc_xoff, c->clo, c->crb);
+                           c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
     }
     if (c->coarse_iter) {
       // the sparse rows of A_0 (one workgroup per coarse block), then the
