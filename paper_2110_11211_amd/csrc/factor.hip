@@ -793,6 +793,93 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
 // So the chain from one diagonal tile to the next holds no chunk sums and no
 // cross-workgroup handshake: five tile products and a diagonal
 // factorisation.
+// Head of the column step J of a single matrix (FP32): the tile (I, J), I =
+// J + 1, and the diagonal tile I, fused so that every input comes from
+// memory in one round.  Both tiles' operands other than L_IJ itself are
+// final when the step starts: A_IJ and A_II, their split-K partials over K
+// <= J - 3 and K <= J - 2 (slots of columns J and I), the direct terms'
+// tiles L_I,J-2, L_J,J-2, L_I,J-1, L_J,J-1 and L_JJ^{-1}.  Then
+//   L_IJ = (A_IJ - sum_K L_IK L_JK^T) L_JJ^{-T}
+//   A_II - sum_{K < J} L_IK L_IK^T - L_IJ L_IJ^T -> factor and inverse,
+// with L_IJ handed to the diagonal update through LDS.  Rows take the
+// terms K >= lo[I] only (a row whose envelope starts right of J has no tile
+// (I, J)).
+template <typename IX>
+__device__ __forceinline__ void chain_head(int J, int maxc, const float* __restrict__ partJ,
+                                           const float* __restrict__ partI, float* __restrict__ F,
+                                           int32_t* __restrict__ status, unsigned char* smem_raw, IX ix) {
+  typedef float T;
+  constexpr int S = LdsV<T>::v;
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * S;
+  const int I = J + 1;
+  const int lo = ix.first(I);
+  const bool hasp = lo <= J;
+  const int kp0 = max(J - 2, lo);      // direct terms of the panel tile: K = kp0 .. J - 1
+  const int kd0 = max(J - 1, lo);      // direct terms of the diagonal tile from memory: K = kd0 .. J - 1
+  TileRegs<T> rI[2], rJ[2], rD;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int K = J - 2 + t;
+    if (K >= 0 && K >= lo) {
+      rI[t].load(F + ix(I, K) * TS2);
+      if (K >= kp0) rJ[t].load(F + ix(J, K) * TS2);
+    }
+  }
+  if (hasp) rD.load(F + ix(J, J) * TS2);
+  TileAcc<T> ap, ad;
+  if (hasp) ap.load(F + ix(I, J) * TS2);
+  ad.load(F + ix(I, I) * TS2);
+  if (hasp) {
+    const int nc = J >= 3 ? (J - 2 + SPLITK - 1) / SPLITK : 0;
+    const int c0 = min(nc, lo / SPLITK);
+    sub_tiles(ap, partJ + ((int64_t)I * maxc + c0) * TS2, TS2, nc - c0);
+  }
+  {
+    const int nc = J >= 2 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
+    const int c0 = min(nc, lo / SPLITK);
+    sub_tiles(ad, partI + ((int64_t)I * maxc + c0) * TS2, TS2, nc - c0);
+  }
+  if (hasp) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int K = J - 2 + t;
+      if (K < kp0) continue;
+      lds_barrier();
+      rI[t].store_lds(sA);
+      rJ[t].store_lds(sB);
+      lds_barrier();
+      tile_mma<T>(ap, sA, sB, T(-1));    // A_IJ -= L_IK L_JK^T
+      if (K >= kd0) tile_mma<T>(ad, sA, sA, T(-1));  // A_II -= L_IK L_IK^T (K = J - 1)
+    }
+    lds_barrier();
+    ap.store_lds(sA);
+    rD.store_lds(sB);                     // L_JJ^{-1}
+    lds_barrier();
+    TileAcc<T> out;
+    out.zero();
+    tile_mma<T>(out, sA, sB, T(1));       // L_IJ = A_IJ L_JJ^{-T}
+    out.store(F + ix(I, J) * TS2);
+    lds_barrier();
+    out.store_lds(sA);
+    lds_barrier();
+    tile_mma<T>(ad, sA, sA, T(-1));       // A_II -= L_IJ L_IJ^T
+  }
+  lds_barrier();
+  constexpr int PS = Pstride<T>::v;
+  T* sC = reinterpret_cast<T*>(smem_raw);
+  T* sX = sC + TS * PS;
+  for (int a = 0; a < 2; ++a)
+    for (int b2 = 0; b2 < 2; ++b2)
+      for (int r = 0; r < 4; ++r) sC[TileAcc<T>::row(a, r) * PS + TileAcc<T>::col(b2)] = ad.c[a][b2][r];
+  potrf_inv_tile(sC, sX, status);
+  T* D = F + ix(I, I) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += TILE_THREADS) {
+    const int i = e / TS, j = e % TS;
+    D[e] = j <= i ? sX[i * PS + j] : T(0);
+  }
+}
+
 // Tile (J, C), C <= J, of X = L^{-1} for a single matrix, formed row by row
 // as the factorisation proceeds (L X = I):
 //   X_JJ = L_JJ^{-1},  X_JC = -L_JJ^{-1} sum_{max(C, lo[J]) <= K < J} L_JK X_KC.
@@ -895,6 +982,12 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
   const int kd = J >= 2 ? J - 2 : 0;
   const int nc_j = J >= 3 ? (J - 2 + SPLITK - 1) / SPLITK : 0;
   if (x < m) {
+    if constexpr (sizeof(T) == 4) {
+      if (x == 0) {
+        chain_head<Env>(J, maxc, slot(J), slot(J + 1), F, status, smem_raw, ix);
+        return;
+      }
+    }
     const int I = J + 1 + x;
     // rows whose envelope starts right of column J have no tile in it
     if (ix.first(I) <= J) panel_tile<T, false, Env>(J, I, kd, nc_j, maxc, slot(J), F, sA, sB, ix);
