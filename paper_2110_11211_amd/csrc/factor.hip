@@ -81,34 +81,38 @@ __device__ __forceinline__ double row_to_all(double v) {
 }
 
 // Pivot K of the DB x DB block held by one wave: lane (p, i) = 16 p + i holds
-// a[q] = A[i][p + 4 q].  The trailing block stays symmetric (every lane
-// updates its whole part of its row), so the factor column below the pivot,
-// L[j][K] = A[K][j] / sqrt(A[K][K]), is row K right of the pivot: lane K of
-// each 16-lane row holds the entries of that row's columns (row broadcast),
-// while the lane's own L[i][K] sits in lane (K mod 4, i) (row_to_all).
+// w[q] = W[i][p + 4 q] of the working matrix (symmetric, both triangles).
+// The factor column is l = W[:, K] / sqrt(W[K][K]): the lane's own l_i sits
+// in lane (K mod 4, i) (row_to_all), and l_j for its columns j = p + 4 q is
+// row K right of the pivot, in lane K of each 16-lane row (row broadcast).
+// The whole block takes W -= l l^T without masks: rows and columns already
+// eliminated hold only rounding residues, which the update moves among
+// themselves (an active entry W[i][j], i, j >= K, is changed by l_i l_j with
+// both from the active part), so no branch or lane mask sits on the
+// dependent chain.  The factor column goes to lo[] in the lanes of column K
+// (its entries above the diagonal are residues and are dropped when the
+// lower triangle is written).  A non-positive pivot is replaced by 1 and
+// flagged in bad.
 template <typename T, int K>
-__device__ __forceinline__ void pivot_step(T (&a)[DB / 4], T (&rd)[DB], int p, int i, int32_t* status) {
+__device__ __forceinline__ void pivot_step(T (&w)[DB / 4], T (&lo)[DB / 4], T (&rd)[DB], int p, bool& bad) {
   constexpr int pk = K & 3, qk = K >> 2;
-  T piv = bcast(a[qk], 16 * pk + K);
-  if (!(piv > T(0))) {
-    if ((int)threadIdx.x == 16 * pk + K) atomicExch(status, -6);
-    piv = T(1);
-  }
+  T piv = bcast(w[qk], 16 * pk + K);   // W[K][K] (through an SGPR)
+  bad |= !(piv > T(0));
+  piv = piv > T(0) ? piv : T(1);
   const T rs = rsqrt_nr(piv);
   rd[K] = rs;
-  const T li = row_to_all<pk>(a[qk]) * rs;
+  const T li = row_to_all<pk>(w[qk]) * rs;
   T lj[DB / 4];
 #pragma unroll
-  for (int q = 0; q < DB / 4; ++q) lj[q] = row_bcast<K>(a[q]) * rs;
+  for (int q = 0; q < DB / 4; ++q) lj[q] = row_bcast<K>(w[q]) * rs;
 #pragma unroll
-  for (int q = 0; q < DB / 4; ++q)
-    if (i > K && p + 4 * q > K) a[q] -= li * lj[q];
-  if (p == pk) a[qk] = i > K ? li : (i == K ? piv * rs : T(0));
+  for (int q = 0; q < DB / 4; ++q) w[q] = fma(-li, lj[q], w[q]);
+  if (p == pk) lo[qk] = li;
 }
 template <typename T, int... K>
-__device__ __forceinline__ void pivots(std::integer_sequence<int, K...>, T (&a)[DB / 4], T (&rd)[DB], int p,
-                                       int i, int32_t* status) {
-  (pivot_step<T, K>(a, rd, p, i, status), ...);
+__device__ __forceinline__ void pivots(std::integer_sequence<int, K...>, T (&w)[DB / 4], T (&lo)[DB / 4],
+                                       T (&rd)[DB], int p, bool& bad) {
+  (pivot_step<T, K>(w, lo, rd, p, bad), ...);
 }
 
 // Cholesky factor and inverse of the DB x DB diagonal block at (o, o) of sC,
@@ -121,17 +125,20 @@ __device__ __forceinline__ void factor_block(T* __restrict__ sC, int o, T* __res
                                              int32_t* status) {
   constexpr int PS = Pstride<T>::v;
   const int lane = threadIdx.x, p = lane >> 4, i = lane & 15;
-  T a[DB / 4], rd[DB];
+  T w[DB / 4], lo[DB / 4], rd[DB];
   // the lane's part of the full symmetric row i, from the lower triangle (the
   // stored upper part is not meaningful)
 #pragma unroll
   for (int q = 0; q < DB / 4; ++q) {
     const int j = p + 4 * q;
-    a[q] = sC[j <= i ? (o + i) * PS + o + j : (o + j) * PS + o + i];
+    w[q] = sC[j <= i ? (o + i) * PS + o + j : (o + j) * PS + o + i];
+    lo[q] = T(0);
   }
-  pivots<T>(std::make_integer_sequence<int, DB>{}, a, rd, p, i, status);
+  bool bad = false;
+  pivots<T>(std::make_integer_sequence<int, DB>{}, w, lo, rd, p, bad);
+  if (bad && lane == 0) atomicExch(status, -6);
 #pragma unroll
-  for (int q = 0; q < DB / 4; ++q) sC[(o + i) * PS + o + p + 4 * q] = a[q];
+  for (int q = 0; q < DB / 4; ++q) sC[(o + i) * PS + o + p + 4 * q] = p + 4 * q <= i ? lo[q] : T(0);
   // inverse by forward substitution, lane c < DB owning column c; L_rk read
   // back from the block (same address in every lane), 1/L_rr = rd[r].
   // Column-oriented: once x_k is known it is subtracted from every later

@@ -1248,20 +1248,22 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   HIPCHK(c, hipEventRecord(ev[3], s));
 
   // factor once (Sec. 3.1).  The two-column batched kernel (380 registers
-  // per lane in FP32) is faster alone but leaves room on a SIMD only for a
-  // workgroup of the FP32 coarse chain (120), not of the FP64 one (196);
-  // keep the one-column kernel (264) beside an FP64 coarse chain that is a
-  // sizeable share of the setup work (FP64 factors leave no room either way).
+  // per lane in FP32) is the fastest alone; the one-column kernel (264)
+  // leaves more room on the SIMDs for the concurrent coarse setup.
   const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
   double fine_work = 0.0;
   for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
   const double coarse_work = G == 1 ? std::pow((double)c->max_N0, 3.0) : 0.0;
   const bool pair = c->factor_pair >= 0 ? c->factor_pair != 0
                                          : (c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work);
-  // matrices of at most four tile rows: the light kernel (one row per panel
-  // step, no prefetch in the diagonal update), whose small LDS staging lets
-  // several workgroups share a CU
-  const int rows = c->factor_rows > 0 ? c->factor_rows : (c->max_nt <= 4 ? 1 : 0);
+  // The light kernel (one row per panel step, no prefetch in the diagonal
+  // update) for matrices of at most four tile rows, whose small LDS staging
+  // lets several workgroups share a CU, and beside a single grid's coarse
+  // chain at least twice as long as a subdomain's: its registers and LDS
+  // leave room on every CU for the chain's workgroups, which set the
+  // setup's critical path.
+  const bool chain_bound = G == 1 && !c->coarse_iter && c->max_nt0 >= 2 * c->max_nt;
+  const int rows = c->factor_rows > 0 ? c->factor_rows : ((c->max_nt <= 4 || chain_bound) ? 1 : 0);
   if (c->fdtype == SFCDD_FP32)
     factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
                         c->status, (float*)nullptr, (float*)nullptr, nullptr, pair && rows != 1, s, rows,
