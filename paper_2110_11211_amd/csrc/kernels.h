@@ -224,6 +224,10 @@ void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t*
                          const int64_t* doff, const T* X, const double* v, double* ytmp,
                          double* part, double* out, const int32_t* active, hipStream_t s);
 void launch_round_f32(int64_t n, const double* src, float* dst, hipStream_t s);
+// Rounds the tiles inside the envelopes of the dense coarse matrices (tile
+// row I of grid g: clo[c0pad / TS + I] .. I, packed triangle at off[g]).
+void launch_round_env(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, const double* src,
+                      float* dst, hipStream_t s);
 
 // ---- iterative coarse solve (single grid) -----------------------------------
 void launch_coarse_ell(const Batch& B, int64_t n0, const int32_t* nbr, int kw, int64_t ld, int32_t* deg,

@@ -1188,7 +1188,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
       float* L32 = reinterpret_cast<float*>(c->X0);
       float* part32 = reinterpret_cast<float*>(c->cpartk);
       if (c->coarse32) {
-        launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
+        launch_round_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, L32, cs);
         factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
                             c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs, 0,
                             c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
@@ -1196,7 +1196,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
         factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, false, false, c->status + 1,
                              G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
                              c->dc_xoff, c->clo, c->crb);
-        launch_round_f32(c->ctiles * TS2, c->A0, L32, cs);
+        launch_round_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, L32, cs);
         launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
                                 part32, cs, c->dc_xoff, c->clo);
       }
