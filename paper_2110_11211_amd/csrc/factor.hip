@@ -202,101 +202,95 @@ __device__ __forceinline__ typename Acc<T>::type blk_zero() {
   return c;
 }
 
-// One column block bk of the blocked factorisation (first wave): diagonal
-// block, panel L_rb,bk = C_rb,bk L_bk,bk^{-T} and trailing update
-// C_rb,cb -= L_rb,bk L_cb,bk^T, with independent block products issued
-// together.
+// One column block bk of the blocked factorisation: the diagonal block by the
+// first wave (its pivots are one dependent chain), then the panel
+// L_rb,bk = C_rb,bk L_bk,bk^{-T} and the trailing update
+// C_rb,cb -= L_rb,bk L_cb,bk^T with their 16x16 block products dealt over
+// the four waves.
 template <typename T, int bk>
 __device__ __forceinline__ void factor_column(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
   constexpr int PS = Pstride<T>::v;
   constexpr int o = bk * DB;
   constexpr int nr = NDB - 1 - bk;  // blocks below the diagonal
   typedef typename Acc<T>::type AT;
+  const int wv = threadIdx.x >> 6;
   T* dinv = sX + o * PS + o;        // L_bk,bk^{-1} is block (bk, bk) of X
-  factor_block(sC, o, dinv, PS, status);
+  if (wv == 0) factor_block(sC, o, dinv, PS, status);
+  lds_barrier();
   if constexpr (nr > 0) {
-    T fd[DB / 4], fc[nr][DB / 4];
-    frag_load<T>(fd, dinv, PS);                                // B = Dinv^T
-#pragma unroll
-    for (int q = 0; q < nr; ++q) frag_load<T>(fc[q], sC + (o + DB + q * DB) * PS + o, PS);
-    AT pc[nr];
-#pragma unroll
-    for (int q = 0; q < nr; ++q) {
-      pc[q] = blk_zero<T>();
-      frag_mma<T>(pc[q], fc[q], fd);
+    if (wv < nr) {                  // panel block row bk + 1 + wv
+      T fd[DB / 4], fc[DB / 4];
+      frag_load<T>(fd, dinv, PS);                                   // B = Dinv^T
+      T* C = sC + (o + DB + wv * DB) * PS + o;
+      frag_load<T>(fc, C, PS);
+      AT pc = blk_zero<T>();
+      frag_mma<T>(pc, fc, fd);
+      blk_store<T>(pc, C, PS, T(1));
     }
-#pragma unroll
-    for (int q = 0; q < nr; ++q) blk_store<T>(pc[q], sC + (o + DB + q * DB) * PS + o, PS, T(1));
-    T fl[nr][DB / 4];
-#pragma unroll
-    for (int q = 0; q < nr; ++q) frag_load<T>(fl[q], sC + (o + DB + q * DB) * PS + o, PS);
-#pragma unroll
-    for (int q = 0; q < nr; ++q)
-#pragma unroll
-      for (int u = 0; u <= q; ++u) {                              // block (rb, cb) = (bk+1+q, bk+1+u)
-        T* D = sC + (o + DB + q * DB) * PS + o + DB + u * DB;
-        AT cc;
-        blk_load<T>(cc, D, PS);
-        AT up = blk_zero<T>();
-        frag_mma<T>(up, fl[q], fl[u]);
-        cc -= up;
-        blk_store<T>(cc, D, PS, T(1));
-      }
+    lds_barrier();
+    // trailing blocks (bk + 1 + q, bk + 1 + u), u <= q, numbered q (q + 1) / 2 + u
+    for (int t = wv; t < nr * (nr + 1) / 2; t += 4) {
+      const int q = t >= 3 ? 2 : (t >= 1 ? 1 : 0);
+      const int u = t - q * (q + 1) / 2;
+      T fq[DB / 4], fu[DB / 4];
+      frag_load<T>(fq, sC + (o + DB + q * DB) * PS + o, PS);
+      frag_load<T>(fu, sC + (o + DB + u * DB) * PS + o, PS);
+      T* D = sC + (o + DB + q * DB) * PS + o + DB + u * DB;
+      AT cc;
+      blk_load<T>(cc, D, PS);
+      AT up = blk_zero<T>();
+      frag_mma<T>(up, fq, fu);
+      cc -= up;
+      blk_store<T>(cc, D, PS, T(1));
+    }
+    lds_barrier();
   }
 }
 
 // Block row I of X = L^{-1}: X_IJ = -L_II^{-1} sum_{K=J}^{I-1} L_IK X_KJ,
-// J < I (rows above already complete).
+// J < I (rows above already complete), one block J per wave.
 template <typename T, int I>
 __device__ __forceinline__ void inverse_row(const T* __restrict__ sC, T* __restrict__ sX) {
   constexpr int PS = Pstride<T>::v;
   typedef typename Acc<T>::type AT;
-  AT t[I];
-#pragma unroll
-  for (int J = 0; J < I; ++J) t[J] = blk_zero<T>();
-#pragma unroll
-  for (int K = 0; K < I; ++K) {
-    T fa[DB / 4];
-    frag_load<T>(fa, sC + (I * DB) * PS + K * DB, PS);         // A = L_IK
-#pragma unroll
-    for (int J = 0; J <= K; ++J) {
-      T fb[DB / 4];
-      frag_load_b<T>(fb, sX + (K * DB) * PS + J * DB, PS);     // B = X_KJ
-      frag_mma<T>(t[J], fa, fb);
+  const int J = threadIdx.x >> 6;
+  if (J < I) {
+    AT t = blk_zero<T>();
+    for (int K = J; K < I; ++K) {
+      T fa[DB / 4], fb[DB / 4];
+      frag_load<T>(fa, sC + (I * DB) * PS + K * DB, PS);         // A = L_IK
+      frag_load_b<T>(fb, sX + (K * DB) * PS + J * DB, PS);       // B = X_KJ
+      frag_mma<T>(t, fa, fb);
     }
-  }
-  T fdi[DB / 4];
-  frag_load<T>(fdi, sX + (I * DB) * PS + I * DB, PS);          // A = L_II^{-1}
-#pragma unroll
-  for (int J = 0; J < I; ++J) {
-    T* tmp = sX + (J + 1) * DB;                                // free upper block (0, J + 1)
-    blk_store<T>(t[J], tmp, PS, T(1));
+    T fdi[DB / 4];
+    frag_load<T>(fdi, sX + (I * DB) * PS + I * DB, PS);          // A = L_II^{-1}
+    T* tmp = sX + (J + 1) * DB;                                  // free upper block (0, J + 1)
+    blk_store<T>(t, tmp, PS, T(1));
     T fb[DB / 4];
     frag_load_b<T>(fb, tmp, PS);
     AT xij = blk_zero<T>();
     frag_mma<T>(xij, fdi, fb);
     blk_store<T>(xij, sX + (I * DB) * PS + J * DB, PS, T(-1));
   }
+  lds_barrier();
 }
 
 // Cholesky factorisation and inversion of a TS x TS LDS tile (stride
-// Pstride, lower part read), blocked by DB, all by the first wave.
+// Pstride, lower part read), blocked by DB, by the four waves of the
+// workgroup (the pivots of each diagonal block by the first).
 // On exit sX holds L^{-1} (lower; stride Pstride); sC holds L (lower).  The
 // inverted diagonal blocks are formed in place in sX, and the free blocks
 // above its diagonal serve as scratch.
 template <typename T>
 __device__ __forceinline__ void potrf_inv_tile(T* __restrict__ sC, T* __restrict__ sX, int32_t* status) {
   lds_barrier();
-  if (threadIdx.x < 64) {
-    factor_column<T, 0>(sC, sX, status);
-    factor_column<T, 1>(sC, sX, status);
-    factor_column<T, 2>(sC, sX, status);
-    factor_column<T, 3>(sC, sX, status);
-    inverse_row<T, 1>(sC, sX);
-    inverse_row<T, 2>(sC, sX);
-    inverse_row<T, 3>(sC, sX);
-  }
-  lds_barrier();
+  factor_column<T, 0>(sC, sX, status);
+  factor_column<T, 1>(sC, sX, status);
+  factor_column<T, 2>(sC, sX, status);
+  factor_column<T, 3>(sC, sX, status);
+  inverse_row<T, 1>(sC, sX);
+  inverse_row<T, 2>(sC, sX);
+  inverse_row<T, 3>(sC, sX);
 }
 
 // LDS of the diagonal-tile factorisation: two Pstride tiles (C, X).  The
