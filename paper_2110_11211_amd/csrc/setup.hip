@@ -314,6 +314,30 @@ void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32
   hipLaunchKernelGGL(k_coarse_accumulate, dim3(2048), dim3(256), 0, s, B, nelems, j, cnt, A0);
 }
 
+// Rounds to FP32 the tiles inside the envelopes of the dense coarse matrices
+// (packed triangles at off[g] tiles; tile row I of grid g holds the tiles
+// clo[c0pad / TS + I] .. I): the factorisation and the inversion read no
+// other tile.  One workgroup per (tile row, grid).
+__global__ __launch_bounds__(256) void k_round_env(Batch B, const int64_t* __restrict__ off,
+                                                   const int32_t* __restrict__ clo,
+                                                   const double* __restrict__ src, float* __restrict__ dst) {
+  const GridDesc& g = B.grids[blockIdx.y];
+  const int I = blockIdx.x;
+  if (I >= g.nt0d) return;
+  const int lo = clo[g.c0pad / TS + I];
+  const int64_t row = (off[blockIdx.y] + tri_index(I, 0)) * TS2;   // tiles of row I are contiguous
+  for (int64_t e = row + (int64_t)lo * TS2 + 4 * threadIdx.x; e < row + (int64_t)(I + 1) * TS2; e += 4 * 256) {
+    const double2 a = *reinterpret_cast<const double2*>(src + e);
+    const double2 b = *reinterpret_cast<const double2*>(src + e + 2);
+    *reinterpret_cast<float4*>(dst + e) = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+  }
+}
+
+void launch_round_env(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, const double* src,
+                      float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_env, dim3(max_nt0, B.G), dim3(256), 0, s, B, off, clo, src, dst);
+}
+
 // Unit diagonal on the padding rows N0 .. nt0*TS-1 of each coarse matrix.
 __global__ void k_coarse_pad(Batch B, const int64_t* __restrict__ ctile_off, double* __restrict__ A0) {
   const int gi = blockIdx.y;
