@@ -499,9 +499,8 @@ __device__ __forceinline__ void partial_tile(int Jn, int I, int c, int k0, int k
 // Rows per step of the batched panel update: every step loads the L_JK tile
 // once for R row tiles L_IK, so the tile products of one step cover the load
 // latency of the next and the L_JK tile is read once per R rows.  R = 3 for
-// FP32 keeps the kernel at about 300 registers per lane, so that a workgroup
-// of the coarse factorisation (about 200) still fits beside it on a SIMD and
-// the two setups overlap; R = 4 is faster alone but no longer shares a CU.
+// FP32 (about 300 registers per lane) is the default shape; R = 4 is faster
+// alone but leaves less room on a SIMD for the concurrent coarse setup.
 template <typename T> struct PanelRows { static constexpr int v = sizeof(T) == 4 ? 3 : 2; };
 
 // acc[r] += sign * A_r B^T for r < nr (LDS tiles A_r at sA + r TS S, B at
@@ -731,10 +730,9 @@ __device__ __forceinline__ void pair_rows(int J, int I0, int nr, T* __restrict__
 // stores visible.
 // PAIR: columns J and J + 1 together (the update by the columns K < J loads
 // each row tile once for both; the two columns are then finished in turn,
-// column J + 1 still taking the term K = J).  About 8% faster alone; at
-// about 380 registers per lane (FP32) it leaves room on a SIMD for a
-// workgroup of the FP32 single-matrix coarse factorisation (120) but not of
-// the FP64 one, and the caller chooses accordingly.
+// column J + 1 still taking the term K = J).  About 8% faster alone, at
+// about 380 registers per lane (FP32); the caller weighs that against the
+// room the concurrent coarse setup needs on the SIMDs.
 // R: row tiles per step of the panel and pair updates (the autotuner picks
 // it per launch shape; PanelRows by default).
 template <typename T, bool PAIR, int R, bool DBUF = true>
