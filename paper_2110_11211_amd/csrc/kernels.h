@@ -106,18 +106,25 @@ void launch_assemble_local(const Batch& B, const int32_t* ta, const int32_t* Ni,
 // row index).
 void launch_coarse_order(const Batch& B, int kcap, int max_n0, const int32_t* sfc_index, int32_t* ccen,
                          int32_t* cperm, int32_t* cfnz, hipStream_t s);
-// Integer coupling counts of dimension j in the permuted coarse numbering;
-// cfnz[c0pad + r] is lowered to the first nonzero column of row r.
+// First nonzero column of every row of the dense coarse matrices (lowers
+// cfnz[c0pad + r] over the couplings of every dimension).
+void launch_coarse_fnz(const Batch& B, const int32_t* nbr, int32_t* cfnz, hipStream_t s);
+// Integer coupling counts of dimension j in the permuted coarse numbering
+// (inside the envelope tiles, cleared beforehand).
 void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
-                          int32_t* cnt, int32_t* cfnz, hipStream_t s);
+                          int32_t* cnt, hipStream_t s);
+// Zero the envelope tiles of the dense coarse matrices and of the counts.
+void launch_coarse_zero_env(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, double* A0,
+                            int32_t* cnt, hipStream_t s);
 // Envelope tables of the dense coarse matrices (per tile row at c0pad / TS):
 // first tile column clo (non-decreasing) and packed-triangle row base crb;
 // wide[0] (nullable): the envelope width of grid 0's matrix (the most tile
 // columns left of the diagonal in a tile row).
 void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb,
                        int32_t* wide, hipStream_t s);
-void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
-                              hipStream_t s);
+// A_0 += c_j E_j over the envelope tiles; the counts are cleared as read.
+void launch_coarse_accumulate(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, int j,
+                              int32_t* cnt, double* A0, hipStream_t s);
 void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, double* A0,
                        hipStream_t s);
 

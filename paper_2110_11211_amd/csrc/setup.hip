@@ -252,90 +252,149 @@ INST(float)
 INST(double)
 #undef INST
 
-// Coarse unknown (block) of local curve position p of grid g: piece i and its
-// m-th block of eq. (restr), local index i q + m.
+// Position of a point's coarse block in its grid's dense coarse matrix: the
+// permuted block (agg = 1), or its group of agg consecutive blocks (the
+// Galerkin aggregation of A_0 that the iterative coarse solve uses as its
+// second level, not permuted).
+__device__ __forceinline__ int coarse_pos(const Batch& B, const GridDesc& g, int64_t q) {
+  const int k = coarse_block(q - g.goff, g);
+  return g.agg == 1 ? B.cperm[g.c0off + k] : k / g.agg;
+}
+
+// First nonzero column of every row of the dense coarse matrices: row I's
+// cfnz[c0pad + I] is lowered to the smallest block coupled to it in any
+// dimension (one atomic per point).
+__global__ void k_coarse_fnz(Batch B, const int32_t* __restrict__ nbr, int32_t* __restrict__ cfnz) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B.Ntot) return;
+  const GridDesc& g = B.grids[grid_of(B, B.gid, p)];
+  const int I = coarse_pos(B, g, p);
+  int m = I;
+  for (int j = 0; j < g.d; ++j)
+    for (int side = 0; side < 2; ++side) {
+      const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
+      if (q >= 0) m = min(m, coarse_pos(B, g, q));
+    }
+  if (m < I) atomicMin(&cfnz[g.c0pad + I], m);
+}
+
+void launch_coarse_fnz(const Batch& B, const int32_t* nbr, int32_t* cfnz, hipStream_t s) {
+  const int th = 256;
+  hipLaunchKernelGGL(k_coarse_fnz, dim3((B.Ntot + th - 1) / th), dim3(th), 0, s, B, nbr, cfnz);
+}
 
 // Integer coupling counts of dimension j between coarse blocks (eq. csm with
 // A = sum_j c_j L_j): cnt(I, J) = sum_{p in I, p' in J} (L_j)_{p p'} for
 // J <= I, accumulated with integer atomics into the packed lower tiles of
 // each grid's dense coarse matrix (first tile ctile_off[g]), in the permuted
-// coarse numbering (block k at position cperm[k]); cfnz[c0pad + I] is
-// lowered to the first nonzero column of row I.  With agg > 1 the rows and
-// columns are groups of agg consecutive coarse blocks (the Galerkin
-// aggregation of A_0 that the iterative coarse solve uses as its second
-// level), not permuted.
+// coarse numbering (block k at position cperm[k]).  Every count lies inside
+// the envelope (k_coarse_fnz, k_coarse_env), whose tiles k_coarse_zero_env
+// cleared.
 __global__ void k_coarse_counts(Batch B, int j, const int32_t* __restrict__ nbr,
-                                const int64_t* __restrict__ ctile_off, int32_t* __restrict__ cnt,
-                                int32_t* __restrict__ cfnz) {
+                                const int64_t* __restrict__ ctile_off, int32_t* __restrict__ cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= B.Ntot) return;
   const int gi = grid_of(B, B.gid, p);
   const GridDesc& g = B.grids[gi];
   if (j >= g.d) return;
   int32_t* C = cnt + ctile_off[gi] * TS2;
-  auto pos = [&](int64_t q) {
-    const int k = coarse_block(q - g.goff, g);
-    return g.agg == 1 ? B.cperm[g.c0off + k] : k / g.agg;
-  };
-  const int I = pos(p);
+  const int I = coarse_pos(B, g, p);
   atomicAdd(&C[tri_index(I / TS, I / TS) * TS2 + (I % TS) * TS + (I % TS)], 2);
   for (int side = 0; side < 2; ++side) {
     const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
     if (q < 0) continue;
-    const int J = pos(q);
+    const int J = coarse_pos(B, g, q);
     if (J > I) continue;
     atomicAdd(&C[tri_index(I / TS, J / TS) * TS2 + (I % TS) * TS + (J % TS)], -1);
-    if (J < I) atomicMin(&cfnz[g.c0pad + I], J);
   }
 }
 
 void launch_coarse_counts(const Batch& B, int j, const int32_t* nbr, const int64_t* ctile_off,
-                          int32_t* cnt, int32_t* cfnz, hipStream_t s) {
+                          int32_t* cnt, hipStream_t s) {
   const int th = 256;
   hipLaunchKernelGGL(k_coarse_counts, dim3((B.Ntot + th - 1) / th), dim3(th), 0, s, B, j, nbr,
-                     ctile_off, cnt, cfnz);
+                     ctile_off, cnt);
 }
 
-// A_0 += c_j E_j for every coarse tile element (the grid of a tile from ctgid).
-__global__ void k_coarse_accumulate(Batch B, int64_t n, int j, const int32_t* __restrict__ cnt,
-                                    double* __restrict__ A0) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = cnt[e];
-    if (v) {
-      const GridDesc& g = B.grids[grid_of(B, B.ctgid, e / TS2)];
-      if (j < g.d) A0[e] += g.c[j] * (double)v;
+// Tile (I, J) = (blockIdx.x, blockIdx.y) of grid blockIdx.z when it lies inside
+// the envelope of that grid's dense coarse matrix: its first element, else -1.
+__device__ __forceinline__ int64_t env_tile(const Batch& B, const int64_t* __restrict__ off,
+                                            const int32_t* __restrict__ clo, const GridDesc*& gp) {
+  const GridDesc& g = B.grids[blockIdx.z];
+  gp = &g;
+  const int I = blockIdx.x, J = blockIdx.y;
+  if (I >= g.nt0d || J > I || J < clo[g.c0pad / TS + I]) return -1;
+  return (off[blockIdx.z] + tri_index(I, J)) * TS2;
+}
+
+// Zero the envelope tiles of the coarse matrices and of the count scratch.
+__global__ __launch_bounds__(256) void k_coarse_zero_env(Batch B, const int64_t* __restrict__ off,
+                                                         const int32_t* __restrict__ clo, double* __restrict__ A0,
+                                                         int32_t* __restrict__ cnt) {
+  const GridDesc* g;
+  const int64_t t = env_tile(B, off, clo, g);
+  if (t < 0) return;
+  for (int e = 4 * threadIdx.x; e < TS2; e += 4 * 256) {
+    *reinterpret_cast<double2*>(A0 + t + e) = make_double2(0.0, 0.0);
+    *reinterpret_cast<double2*>(A0 + t + e + 2) = make_double2(0.0, 0.0);
+    *reinterpret_cast<int4*>(cnt + t + e) = make_int4(0, 0, 0, 0);
+  }
+}
+
+// A_0 += c_j E_j over the envelope tiles, clearing the counts for the next
+// dimension (the sum over j runs in j order).
+__global__ __launch_bounds__(256) void k_coarse_accumulate(Batch B, const int64_t* __restrict__ off,
+                                                           const int32_t* __restrict__ clo, int j,
+                                                           int32_t* __restrict__ cnt, double* __restrict__ A0) {
+  const GridDesc* g;
+  const int64_t t = env_tile(B, off, clo, g);
+  if (t < 0 || j >= g->d) return;
+  const double cj = g->c[j];
+  for (int e = 4 * threadIdx.x; e < TS2; e += 4 * 256) {
+    const int4 v = *reinterpret_cast<const int4*>(cnt + t + e);
+    if (v.x | v.y | v.z | v.w) {
+      double2 a = *reinterpret_cast<const double2*>(A0 + t + e);
+      double2 b = *reinterpret_cast<const double2*>(A0 + t + e + 2);
+      if (v.x) a.x += cj * (double)v.x;
+      if (v.y) a.y += cj * (double)v.y;
+      if (v.z) b.x += cj * (double)v.z;
+      if (v.w) b.y += cj * (double)v.w;
+      *reinterpret_cast<double2*>(A0 + t + e) = a;
+      *reinterpret_cast<double2*>(A0 + t + e + 2) = b;
+      *reinterpret_cast<int4*>(cnt + t + e) = make_int4(0, 0, 0, 0);
     }
   }
 }
 
-void launch_coarse_accumulate(const Batch& B, int64_t nelems, int j, const int32_t* cnt, double* A0,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_accumulate, dim3(2048), dim3(256), 0, s, B, nelems, j, cnt, A0);
+void launch_coarse_zero_env(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, double* A0,
+                            int32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_zero_env, dim3(max_nt0, max_nt0, B.G), dim3(256), 0, s, B, off, clo, A0, cnt);
+}
+
+void launch_coarse_accumulate(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, int j,
+                              int32_t* cnt, double* A0, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_accumulate, dim3(max_nt0, max_nt0, B.G), dim3(256), 0, s, B, off, clo, j, cnt, A0);
 }
 
 // Rounds to FP32 the tiles inside the envelopes of the dense coarse matrices
-// (packed triangles at off[g] tiles; tile row I of grid g holds the tiles
-// clo[c0pad / TS + I] .. I): the factorisation and the inversion read no
-// other tile.  One workgroup per (tile row, grid).
+// (packed triangles at off[g] tiles): the factorisation and the inversion
+// read no other tile.  One workgroup per tile.
 __global__ __launch_bounds__(256) void k_round_env(Batch B, const int64_t* __restrict__ off,
                                                    const int32_t* __restrict__ clo,
                                                    const double* __restrict__ src, float* __restrict__ dst) {
-  const GridDesc& g = B.grids[blockIdx.y];
-  const int I = blockIdx.x;
-  if (I >= g.nt0d) return;
-  const int lo = clo[g.c0pad / TS + I];
-  const int64_t row = (off[blockIdx.y] + tri_index(I, 0)) * TS2;   // tiles of row I are contiguous
-  for (int64_t e = row + (int64_t)lo * TS2 + 4 * threadIdx.x; e < row + (int64_t)(I + 1) * TS2; e += 4 * 256) {
-    const double2 a = *reinterpret_cast<const double2*>(src + e);
-    const double2 b = *reinterpret_cast<const double2*>(src + e + 2);
-    *reinterpret_cast<float4*>(dst + e) = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+  const GridDesc* g;
+  const int64_t t = env_tile(B, off, clo, g);
+  if (t < 0) return;
+  for (int e = 4 * threadIdx.x; e < TS2; e += 4 * 256) {
+    const double2 a = *reinterpret_cast<const double2*>(src + t + e);
+    const double2 b = *reinterpret_cast<const double2*>(src + t + e + 2);
+    *reinterpret_cast<float4*>(dst + t + e) = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
   }
 }
 
 void launch_round_env(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, const double* src,
                       float* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_round_env, dim3(max_nt0, B.G), dim3(256), 0, s, B, off, clo, src, dst);
+  hipLaunchKernelGGL(k_round_env, dim3(max_nt0, max_nt0, B.G), dim3(256), 0, s, B, off, clo, src, dst);
 }
 
 // Unit diagonal on the padding rows N0 .. nt0*TS-1 of each coarse matrix.

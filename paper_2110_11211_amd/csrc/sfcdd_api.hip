@@ -1157,7 +1157,6 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     const hipStream_t cs = c->side;
     HIPCHK(c, hipEventRecord(cev0, cs));
     // coarse matrices A_0 = R_0 A R_0^T = sum_j c_j E_j (eq. csm), then A_0^{-1}
-    HIPCHK(c, hipMemsetAsync(c->A0, 0, c->r_A0.bytes, cs));
     HIPCHK(c, hipMemsetAsync(c->c0, 0, c->r_c0.bytes, cs));
     // coarse elimination order (key levels: 4 x the sum of the grid extents)
     int ckcap = 1;
@@ -1169,14 +1168,16 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     int max_n0 = 1;
     for (int k = 0; k < G; ++k) max_n0 = std::max(max_n0, c->grid[k].desc.N0);
     launch_coarse_order(B, ckcap, max_n0, c->sfc_index, c->ccen, c->cperm, c->cfnz, cs);
-    const int64_t celems = c->ctiles * TS2;
+    // the envelopes first (only their tiles are cleared, assembled and read)
+    launch_coarse_fnz(B, c->nbr, c->cfnz, cs);
+    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, cs);
+    int32_t* cnt = reinterpret_cast<int32_t*>(c->X0);   // count scratch (the inverse comes later)
+    launch_coarse_zero_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, cnt, cs);
     for (int j = 0; j < c->dmax; ++j) {
-      HIPCHK(c, hipMemsetAsync(c->X0, 0, (size_t)celems * 4, cs));
-      launch_coarse_counts(B, j, c->nbr, c->dc_off, (int32_t*)c->X0, c->cfnz, cs);
-      launch_coarse_accumulate(B, celems, j, (const int32_t*)c->X0, c->A0, cs);
+      launch_coarse_counts(B, j, c->nbr, c->dc_off, cnt, cs);
+      launch_coarse_accumulate(B, c->max_nt0, c->dc_off, c->clo, j, cnt, c->A0, cs);
     }
     launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
-    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, cs);
     // Beside FP32 subdomain factors the inverse X_0 = L_0^{-1} is FP32: A_0
     // is an M-matrix (a Galerkin aggregation of the stencil matrix), so L_0
     // has non-positive off-diagonal entries, X_0 is entrywise non-negative
