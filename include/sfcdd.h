@@ -80,6 +80,8 @@ enum { SFCDD_COARSE_AUTO = 0, SFCDD_COARSE_FP64 = 1 };
 enum { SFCDD_COARSE_DENSE = 0, SFCDD_COARSE_ITERATIVE = 1 };
 /* Elimination order of the subdomain matrices (see sfcdd_params.local_order). */
 enum { SFCDD_ORDER_DIAGONAL = 0, SFCDD_ORDER_CURVE = 1, SFCDD_ORDER_DENSE = 2 };
+/* Dissection of the dense coarse matrix (see sfcdd_params.coarse_split). */
+enum { SFCDD_SPLIT_AUTO = 0, SFCDD_SPLIT_OFF = 1 };
 /* Flags OR-ed into the method of sfcdd_solve: start from x0 exactly as given
  * and apply the full balanced operator every iteration; stop on the recursive
  * residual alone (see sfcdd_solve). */
@@ -133,6 +135,22 @@ typedef struct {
                                 nonzero of a row).  SFCDD_ORDER_DENSE: curve order,
                                 the whole packed triangle.  The explicit-inverse
                                 local solver always uses the last.                    */
+  int32_t coarse_split;      /* elimination order of the dense coarse matrix (any
+                                symmetric order gives the same A_0^{-1}).
+                                SFCDD_SPLIT_AUTO: for a single grid with FP32 coarse
+                                factor and inverse, one level of nested dissection
+                                when it pays: the coarse blocks of the two halves of
+                                the curve, each in the centroid-diagonal order, then
+                                the separator (the first half's blocks with a
+                                neighbour in the second).  The halves factor as two
+                                concurrent chains of column steps, and X_0 = L_0^{-1}
+                                has no tiles coupling them, so the coarse solves
+                                read fewer tiles (sfcdd_info.coarse_split).  It is
+                                used when both halves have at least two 64-row tiles
+                                and the separator at most an eighth of the tile rows,
+                                and the halves' envelopes are at most 24 tiles wide;
+                                otherwise, and with SFCDD_SPLIT_OFF, the
+                                centroid-diagonal order alone                         */
 } sfcdd_params;
 
 typedef struct {
@@ -189,6 +207,9 @@ typedef struct {
   double factor_flops;       /* floating-point operations of the subdomain
                                 factorisation: 2 TS^3 per tile product and 2 TS^3 / 3
                                 per diagonal tile (its Cholesky factor and inverse)     */
+  int32_t coarse_split[3];   /* dissected coarse matrix: 64-row tiles of its first
+                                half, second half and separator (zeros when not
+                                dissected)                                             */
 } sfcdd_info;
 
 /* Workspace bytes that sfcdd_setup needs for these parameters (Alg. 1

@@ -37,6 +37,7 @@ LAYOUT = {"natural": 0, "sfc": 1}
 COARSE_PRECISION = {"auto": 0, "fp64": 1}
 COARSE_SOLVER = {"dense": 0, "iterative": 1}
 LOCAL_ORDER = {"diagonal": 0, "curve": 1, "dense": 2}
+COARSE_SPLIT = {"auto": 0, "off": 1}
 
 EXPORTS = ["sfcdd_workspace_size", "sfcdd_workspace_size_batch", "sfcdd_setup", "sfcdd_setup_batch",
            "sfcdd_setup_noalloc",
@@ -61,7 +62,8 @@ class Params(ctypes.Structure):
                 ("factor_dtype", ctypes.c_int32), ("local_solver", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("curve", ctypes.c_int32),
                 ("coarse_precision", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
-                ("coarse_tol", ctypes.c_double), ("local_order", ctypes.c_int32)]
+                ("coarse_tol", ctypes.c_double), ("local_order", ctypes.c_int32),
+                ("coarse_split", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -82,7 +84,8 @@ class Info(ctypes.Structure):
                 ("N0d", ctypes.c_int32), ("ell_width", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
                 ("factor_rows", ctypes.c_int32), ("factor_pair", ctypes.c_int32),
                 ("spmv_points", ctypes.c_int32), ("spmv_window", ctypes.c_int32),
-                ("local_order", ctypes.c_int32), ("factor_flops", ctypes.c_double)]
+                ("local_order", ctypes.c_int32), ("factor_flops", ctypes.c_double),
+                ("coarse_split", ctypes.c_int32 * 3)]
 
 
 class Tuning(ctypes.Structure):
@@ -148,7 +151,7 @@ def _check(st: int, ctx=None):
 def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q=0,
                 weighting="omega", variant="balanced", factor_dtype="fp64",
                 local_solver="cholesky", layout="natural", curve="zorder", coarse_precision="auto",
-                coarse_solver="dense", coarse_tol=0.0, local_order="diagonal"):
+                coarse_solver="dense", coarse_tol=0.0, local_order="diagonal", coarse_split="auto"):
     """Builds the sfcdd_params struct; returns (struct, keepalive)."""
     g = Fraction(gamma)
     d = len(levels) if levels is not None else len(npts)
@@ -181,6 +184,7 @@ def make_params(levels=None, npts=None, coeff=None, P=1, gamma=Fraction(1, 2), q
     prm.coarse_solver = COARSE_SOLVER[coarse_solver]
     prm.coarse_tol = float(coarse_tol)
     prm.local_order = LOCAL_ORDER[local_order]
+    prm.coarse_split = COARSE_SPLIT[coarse_split]
     return prm, keep
 
 
@@ -232,7 +236,8 @@ class SFCSchwarz:
                  weighting: str = "omega", variant: str = "balanced", factor_dtype: str = "fp64",
                  local_solver: str = "cholesky", layout: str = "natural", device="cuda:0",
                  workspace=None, curve: str = "zorder", coarse_precision: str = "auto",
-                 coarse_solver: str = "dense", coarse_tol: float = 0.0, local_order: str = "diagonal"):
+                 coarse_solver: str = "dense", coarse_tol: float = 0.0, local_order: str = "diagonal",
+                 coarse_split: str = "auto"):
         import torch
         self._torch = torch
         self.device = torch.device(device)
@@ -241,7 +246,8 @@ class SFCSchwarz:
         self.kw = dict(levels=levels, npts=npts, coeff=coeff, P=P, gamma=gamma, q=q, weighting=weighting,
                        variant=variant, factor_dtype=factor_dtype, local_solver=local_solver,
                        layout=layout, curve=curve, coarse_precision=coarse_precision,
-                       coarse_solver=coarse_solver, coarse_tol=coarse_tol, local_order=local_order)
+                       coarse_solver=coarse_solver, coarse_tol=coarse_tol, local_order=local_order,
+                       coarse_split=coarse_split)
         prm, self._keep = make_params(**self.kw)
         self._prm = prm
         with torch.cuda.device(self.device):
@@ -299,7 +305,8 @@ class SFCSchwarz:
 
     def info(self) -> dict:
         i = self._info
-        return {k: (list(getattr(i, k)) if k == "setup_ms" else getattr(i, k)) for k, _ in Info._fields_}
+        return {k: (list(getattr(i, k)) if k in ("setup_ms", "coarse_split") else getattr(i, k))
+                for k, _ in Info._fields_}
 
     # -- operators ---------------------------------------------------------
     def apply(self, g, out=None):

@@ -438,7 +438,9 @@ void launch_combine(const Batch& B, int mode, const double* d0, const double* a,
 // from HBM with 16-byte loads (VEC entries per lane, LPR lanes per tile row),
 // in chunks of TRMV_CH tiles per workgroup; partial results per (tile, chunk)
 // are summed by k_trmv_reduce in a fixed order (no atomics).  Products and
-// sums are FP64.
+// sums are FP64.  nd (nullable, single grid): with a dissected coarse matrix
+// ({ta, tb, ts}, ts > 0) the tiles of X in the second half's rows left of it
+// (tile rows ta .. ta + tb - 1, columns < ta) are zero and are not read.
 constexpr int TRMV_CH = 8;
 
 template <typename T> struct TrmvLanes {
@@ -453,7 +455,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
                                                    const T* __restrict__ X,
                                                    const double* __restrict__ v,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, const int32_t* __restrict__ nd) {
   typedef TrmvLanes<T> LN;
   typedef typename Vec16<T>::type V;
   const int b = blockIdx.y, ntb = bm.nt[b];
@@ -462,6 +464,8 @@ __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const
   const int k0 = c * TRMV_CH;
   if (I >= ntb || c >= nch || k0 > I || (active && !act_updating(active[b]))) return;
   const int k1 = min(I + 1, k0 + TRMV_CH);
+  // second half of a dissected matrix: no tiles left of column ta
+  const int kz = (nd && nd[2] > 0 && I >= nd[0] && I < nd[0] + nd[1]) ? nd[0] : 0;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane / LN::LPR, c0 = (lane % LN::LPR) * LN::VEC;
   const T* Xb = X + bm.off[b] * TS2;
@@ -469,7 +473,7 @@ __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const
   double acc[LN::NQ];
 #pragma unroll
   for (int q = 0; q < LN::NQ; ++q) acc[q] = 0.0;
-  for (int K = k0; K < k1; ++K) {
+  for (int K = max(k0, kz); K < k1; ++K) {
     double vk[LN::VEC];
 #pragma unroll
     for (int e = 0; e < LN::VEC; e += 2) {
@@ -503,7 +507,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
                                                    const T* __restrict__ X,
                                                    const double* __restrict__ y,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, const int32_t* __restrict__ nd) {
   typedef TrmvLanes<T> LN;
   typedef typename Vec16<T>::type V;
   const int b = blockIdx.y, ntb = bm.nt[b];
@@ -512,6 +516,12 @@ __global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const
   const int i0 = K + c * TRMV_CH;
   if (K >= ntb || c >= nch || i0 >= ntb || (active && !act_updating(active[b]))) return;
   const int i1 = min(ntb, i0 + TRMV_CH);
+  // first half's columns of a dissected matrix: no tiles in the second half's rows
+  int za = ntb, zb = ntb;
+  if (nd && nd[2] > 0 && K < nd[0]) {
+    za = nd[0];
+    zb = nd[0] + nd[1];
+  }
   __shared__ double red[4 * TS];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane / LN::LPR, c0 = (lane % LN::LPR) * LN::VEC;
@@ -521,6 +531,8 @@ __global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const
 #pragma unroll
   for (int e = 0; e < LN::VEC; ++e) a[e] = 0.0;
   for (int I = i0; I < i1; ++I) {
+    if (I >= za && I < zb) I = zb;
+    if (I >= i1) break;
     const T* tile = Xb + tri_index(I, K) * TS2;
 #pragma unroll
     for (int q = 0; q < LN::NQ; ++q) {
@@ -574,21 +586,21 @@ __global__ __launch_bounds__(TS) void k_trmv_reduce(BatchMeta bm, const int32_t*
 template <typename T>
 void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
                          const int64_t* doff, const T* X, const double* v, double* ytmp,
-                         double* part, double* out, const int32_t* active, hipStream_t s) {
+                         double* part, double* out, const int32_t* active, hipStream_t s, const int32_t* nd) {
   const int nchx = (max_nt + TRMV_CH - 1) / TRMV_CH;
   const dim3 grid(max_nt * nchx, nb);
-  hipLaunchKernelGGL(k_trmv_rows<T>, grid, dim3(256), 0, s, bm, nchx, active, X, v, part);
+  hipLaunchKernelGGL(k_trmv_rows<T>, grid, dim3(256), 0, s, bm, nchx, active, X, v, part, nd);
   hipLaunchKernelGGL(k_trmv_reduce<0>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, ytmp);
-  hipLaunchKernelGGL(k_trmv_cols<T>, grid, dim3(256), 0, s, bm, nchx, active, X, ytmp, part);
+  hipLaunchKernelGGL(k_trmv_cols<T>, grid, dim3(256), 0, s, bm, nchx, active, X, ytmp, part, nd);
   hipLaunchKernelGGL(k_trmv_reduce<1>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, out);
 }
 
 template void launch_coarse_apply<float>(int, int, const BatchMeta&, const int32_t*, const int64_t*,
                                          const float*, const double*, double*, double*, double*,
-                                         const int32_t*, hipStream_t);
+                                         const int32_t*, hipStream_t, const int32_t*);
 template void launch_coarse_apply<double>(int, int, const BatchMeta&, const int32_t*, const int64_t*,
                                           const double*, const double*, double*, double*, double*,
-                                          const int32_t*, hipStream_t);
+                                          const int32_t*, hipStream_t, const int32_t*);
 
 // Rounds n FP64 values to FP32 (a coarse factor kept beside FP32 subdomain
 // factors).

@@ -418,21 +418,32 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_diag(int J, int kfrom, i
                                                              T* __restrict__ fac,
                                                              int32_t* __restrict__ status,
                                                              const int32_t* __restrict__ tlo,
-                                                             const int32_t* __restrict__ trb) {
+                                                             const int32_t* __restrict__ trb,
+                                                             const int32_t* __restrict__ vinfo, int vstride) {
   __builtin_amdgcn_s_setprio(3);  // head of the same chain as k_potrf_step
-  const int b = blockIdx.x;
-  if (J >= nt[b]) return;
+  const int b = vinfo ? 0 : blockIdx.x;
+  if (vinfo) {  // views of a dissected matrix (see k_potrf_step), view blockIdx.x
+    const int v = blockIdx.x;
+    if (J >= vinfo[3 * v + 1]) return;
+    tlo += v * vstride;
+    trb += v * vstride;
+  } else if (J >= nt[b]) {
+    return;
+  }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   diag_tile<T, false, Env>(J, kfrom, nparts, maxc, part, fac + off[b] * TS2, status, smem_raw, Env{tlo, trb});
 }
 
 // Sub-diagonal tile (I, J): A_IJ - sum_{K<J} L_IK L_JK^T (terms K >= kfrom
 // here, the others from nparts partial tiles), times L_JJ^{-T}.  Row I takes
-// the terms K >= lo[I] only (and the partial chunks from lo[I] / SPLITK).
+// the terms K >= max(lo[I], lo[J]) only (and the partial chunks from lo[I] /
+// SPLITK); lo[J] <= lo[I] unless the envelope is non-decreasing only within
+// parts (a dissected coarse matrix, whose separator rows reach further left
+// than the rows above them).
 template <typename T, bool DBUF = false, typename IX = Tri>
 __device__ __forceinline__ void panel_tile(int J, int I, int kfrom, int nparts, int maxc, const T* __restrict__ part,
                            T* __restrict__ F, T* sA, T* sB, IX ix = IX()) {
-  kfrom = max(kfrom, ix.first(I));
+  kfrom = max(kfrom, max(ix.first(I), ix.first(J)));
   TileAcc<T> acc;
   acc.load(F + ix(I, J) * TS2);
   {
@@ -802,7 +813,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_full(const int32_t* __re
 //   A_II - sum_{K < J} L_IK L_IK^T - L_IJ L_IJ^T -> factor and inverse,
 // with L_IJ handed to the diagonal update through LDS.  Rows take the
 // terms K >= lo[I] only (a row whose envelope starts right of J has no tile
-// (I, J)).
+// (I, J)), the panel's terms K >= lo[J] too.
 template <typename IX>
 __device__ __forceinline__ void chain_head(int J, int maxc, const float* __restrict__ partJ,
                                            const float* __restrict__ partI, float* __restrict__ F,
@@ -814,7 +825,7 @@ __device__ __forceinline__ void chain_head(int J, int maxc, const float* __restr
   const int I = J + 1;
   const int lo = ix.first(I);
   const bool hasp = lo <= J;
-  const int kp0 = max(J - 2, lo);      // direct terms of the panel tile: K = kp0 .. J - 1
+  const int kp0 = max(J - 2, max(lo, ix.first(J)));  // direct terms of the panel tile: K = kp0 .. J - 1
   const int kd0 = max(J - 1, lo);      // direct terms of the diagonal tile from memory: K = kd0 .. J - 1
   TileRegs<T> rI[2], rJ[2], rD;
 #pragma unroll
@@ -886,15 +897,17 @@ __device__ __forceinline__ void chain_head(int J, int maxc, const float* __restr
 // above it were formed earlier, so row J of X is formed by extra workgroups
 // of the column step J (the chain itself does not wait for them), and the
 // inversion no longer follows the factorisation on the setup's critical
-// path.  X is a packed lower-triangular tile matrix at X.  A row takes up to
+// path.  X is a packed lower-triangular tile matrix at X (a chain over one
+// part of a dissected matrix writes its local tile (J, C) at (xo + J, xo +
+// C)).  A row takes up to
 // (row width of the envelope) tile products in one workgroup: for envelopes
 // wider than XROW_MAXW tiles (the device-side width *wide) the rows would
 // outlast the column steps, and the recursive inversion after the
 // factorisation (whose kernels skip otherwise) is used instead.
 template <typename T, typename IX>
 __device__ __forceinline__ void xrow_tile(int J, int C, const T* __restrict__ F, T* __restrict__ X, T* sA,
-                                          T* sB, IX ix) {
-  T* XD = X + tri_index(J, C) * TS2;
+                                          T* sB, IX ix, int xo = 0) {
+  T* XD = X + tri_index(xo + J, xo + C) * TS2;
   if (C == J) {
     typedef typename Vec16<T>::type V;
     const V* src = reinterpret_cast<const V*>(F + ix(J, J) * TS2);
@@ -908,7 +921,7 @@ __device__ __forceinline__ void xrow_tile(int J, int C, const T* __restrict__ F,
   TileRegs<T> ra, rb;
   if (k0 < J) {
     ra.load(F + ix(J, k0) * TS2);
-    rb.load(X + tri_index(k0, C) * TS2);
+    rb.load(X + tri_index(xo + k0, xo + C) * TS2);
   }
   for (int K = k0; K < J; ++K) {
     lds_barrier();
@@ -917,7 +930,7 @@ __device__ __forceinline__ void xrow_tile(int J, int C, const T* __restrict__ F,
     lds_barrier();
     if (K + 1 < J) {
       ra.load(F + ix(J, K + 1) * TS2);
-      rb.load(X + tri_index(K + 1, C) * TS2);
+      rb.load(X + tri_index(xo + K + 1, xo + C) * TS2);
     }
     tile_mma<T>(acc, sA, sB, T(1));  // sum L_JK X_KC
   }
@@ -937,14 +950,21 @@ __global__ __launch_bounds__(TILE_THREADS) void k_xrow(int J, const int64_t* __r
                                                        const T* __restrict__ fac, T* __restrict__ X,
                                                        const int32_t* __restrict__ tlo,
                                                        const int32_t* __restrict__ trb,
-                                                       const int32_t* __restrict__ wide) {
+                                                       const int32_t* __restrict__ wide, int xo) {
   if (wide && *wide > XROW_MAXW) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
   T* sB = sA + TS * LdsV<T>::v;
-  xrow_tile<T, Env>(J, (int)blockIdx.x, fac + off[0] * TS2, X + off[0] * TS2, sA, sB, Env{tlo, trb});
+  xrow_tile<T, Env>(J, (int)blockIdx.x, fac + off[0] * TS2, X + off[0] * TS2, sA, sB, Env{tlo, trb}, xo);
 }
 
+// Column step J of one chain.  Views (vinfo non-null; the chains of a
+// dissected coarse matrix, view blockIdx.y): vinfo[3 v ..] = {tile rows,
+// columns the chain factors, X tile offset}, row tables at tlo / trb + v *
+// vstride, split-K slots at part + 3 v slot_tiles tiles.  The chain of view
+// v factors its first nc columns only: its last step forms the tiles below
+// them (the separator's rows) but neither the next diagonal tile nor
+// partials of columns >= nc.
 template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T* __restrict__ part,
                                                              int64_t slot_tiles,
@@ -954,16 +974,28 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
                                                              int32_t* __restrict__ status,
                                                              const int32_t* __restrict__ tlo,
                                                              const int32_t* __restrict__ trb,
-                                                             T* __restrict__ X, int nwg,
-                                                             const int32_t* __restrict__ wide) {
+                                                             T* __restrict__ X,
+                                                             const int32_t* __restrict__ wide,
+                                                             const int32_t* __restrict__ vinfo, int vstride) {
   // The steps form a chain of dependent launches that runs beside the
   // throughput-bound batched factorisation of the subdomains; the highest
   // wave priority lets its instructions issue first on the shared SIMDs
   // (the 127 steps of the 8192-unknown coarse matrix: 10.4 -> 8.5 ms beside
   // it, the batched factorisation 9.9 -> 10.5 ms).
-  const int ntb = nt[0];
+  int ntb = nt[0], ncol = ntb, xo = 0;
+  if (vinfo) {
+    const int v = blockIdx.y;
+    ntb = vinfo[3 * v];
+    ncol = vinfo[3 * v + 1];
+    xo = vinfo[3 * v + 2];
+    tlo += v * vstride;
+    trb += v * vstride;
+    part += 3 * v * slot_tiles * TS2;
+  }
   const int m = ntb - 1 - J;  // tiles below the diagonal in column J
-  if (m <= 0) return;
+  if (m <= 0 || J >= ncol) return;
+  const int ncj = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
+  const int nwg = m + (m > 1 ? (m - 1) * ncj : 0);
   const Env ix{tlo, trb};
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sA = reinterpret_cast<T*>(smem_raw);
@@ -971,18 +1003,19 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
   T* F = fac + off[0] * TS2;
   const int x = blockIdx.x;
   if (x >= nwg) {  // row J of the inverse (normal priority: off the chain)
-    if (wide && *wide > XROW_MAXW) return;
-    xrow_tile<T, Env>(J, x - nwg, F, X + off[0] * TS2, sA, sB, ix);
+    if (!X || x - nwg > J || (wide && *wide > XROW_MAXW)) return;
+    xrow_tile<T, Env>(J, x - nwg, F, X + off[0] * TS2, sA, sB, ix, xo);
     return;
   }
   __builtin_amdgcn_s_setprio(3);
   auto slot = [&](int C) { return part + (int64_t)(C % 3) * slot_tiles * TS2; };
+  const bool next = J + 1 < ncol;   // the chain factors column J + 1
   // column J: partials over K <= J - 3, direct terms from K = max(0, J - 2)
   const int kd = J >= 2 ? J - 2 : 0;
   const int nc_j = J >= 3 ? (J - 2 + SPLITK - 1) / SPLITK : 0;
   if (x < m) {
     if constexpr (sizeof(T) == 4) {
-      if (x == 0) {
+      if (x == 0 && next) {
         chain_head<Env>(J, maxc, slot(J), slot(J + 1), F, status, smem_raw, ix);
         return;
       }
@@ -990,7 +1023,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
     const int I = J + 1 + x;
     // rows whose envelope starts right of column J have no tile in it
     if (ix.first(I) <= J) panel_tile<T, false, Env>(J, I, kd, nc_j, maxc, slot(J), F, sA, sB, ix);
-    if (x > 0) return;
+    if (x > 0 || !next) return;
     __syncthreads();
     // diagonal tile J + 1: partials over K <= J - 2, direct K = J - 1, J
     const int nc_d = J >= 2 ? (J - 1 + SPLITK - 1) / SPLITK : 0;
@@ -998,14 +1031,15 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
     return;
   }
   // partials of column J + 2 over K = 0 .. J - 1, rows J + 2 .. ntb - 1; a
-  // row takes the chunks from lo[I] / SPLITK on (its terms K >= lo[I]), and
-  // rows with no tile in column J + 2 none
+  // row takes the chunks from lo[I] / SPLITK on (its terms K >= lo[I] and
+  // K >= lo[J + 2]), and rows with no tile in column J + 2 none
+  if (J + 2 >= ncol) return;
   const int y = x - m, mr = m - 1;
   const int I = J + 2 + y % mr, c = y / mr;
   const int lo = ix.first(I);
   if (lo > J + 2 || c < lo / SPLITK) return;
-  partial_tile<T, Env>(J + 2, I, c, max(c * SPLITK, lo), min(J, (c + 1) * SPLITK), maxc, F, slot(J + 2), sA, sB,
-                       ix);
+  partial_tile<T, Env>(J + 2, I, c, max(c * SPLITK, max(lo, ix.first(J + 2))), min(J, (c + 1) * SPLITK), maxc, F,
+                       slot(J + 2), sA, sB, ix);
 }
 
 // The FP64 tile kernels stage two 64x65 double tiles (66.5 KB of LDS), above
@@ -1063,12 +1097,13 @@ void launch_unit_lower(int nb, int max_nt, const int32_t* nt, const int64_t* off
 template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
-                       hipStream_t s, const int32_t* tlo, const int32_t* trb) {
+                       hipStream_t s, const int32_t* tlo, const int32_t* trb, const int32_t* vinfo,
+                       int vstride) {
   const size_t sh = diag_lds_bytes<T>();
   static bool once = (allow_lds(k_potrf_diag<T>, sh), true);
   (void)once;
   hipLaunchKernelGGL(k_potrf_diag<T>, dim3(nb), dim3(TILE_THREADS), sh, s, J, kfrom, nparts, maxc,
-                     part, nt, off, fac, status, tlo, trb);
+                     part, nt, off, fac, status, tlo, trb, vinfo, vstride);
 }
 template <typename T, bool PAIR, int R>
 static void potrf_full_rows(int nb, const int32_t* nt, const int64_t* off, const int64_t* xoff, const int32_t* tlo,
@@ -1120,7 +1155,8 @@ void launch_potrf_full(int nb, const int32_t* nt, const int64_t* off, const int6
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
                        const int64_t* off, T* fac, int32_t* status, hipStream_t s, const int32_t* tlo,
-                       const int32_t* trb, T* X, const int32_t* wide) {
+                       const int32_t* trb, T* X, const int32_t* wide, const int32_t* vinfo, int vstride,
+                       int nviews) {
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
   const int nc = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
@@ -1128,17 +1164,17 @@ void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles,
   const size_t sh = std::max(2 * TS * LdsV<T>::v * sizeof(T), diag_lds_bytes<T>());
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg + (X ? J + 1 : 0)), dim3(TILE_THREADS), sh, s, J, maxc, part,
-                     slot_tiles, nt, off, fac, status, tlo, trb, X, nwg, wide);
+  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg + (X ? J + 1 : 0), nviews), dim3(TILE_THREADS), sh, s, J, maxc,
+                     part, slot_tiles, nt, off, fac, status, tlo, trb, X, wide, vinfo, vstride);
 }
 
 template <typename T>
 void launch_xrow(int J, const int64_t* off, const T* fac, T* X, hipStream_t s, const int32_t* tlo,
-                 const int32_t* trb, const int32_t* wide) {
+                 const int32_t* trb, const int32_t* wide, int xo) {
   const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_xrow<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_xrow<T>, dim3(J + 1), dim3(TILE_THREADS), sh, s, J, off, fac, X, tlo, trb, wide);
+  hipLaunchKernelGGL(k_xrow<T>, dim3(J + 1), dim3(TILE_THREADS), sh, s, J, off, fac, X, tlo, trb, wide, xo);
 }
 
 // Column J of X = L^{-1} from the columns right of it (X L = I):
@@ -1436,20 +1472,187 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
   hipLaunchKernelGGL(k_lauum<T>, dim3(ntiles, nb), dim3(TILE_THREADS), sh, s, nt, off, X, M);
 }
 
+// ---------------------------------------------------------------------------
+// The separator of a dissected coarse matrix (tile rows s0 = ta + tb .. nt - 1
+// of the packed triangle; the first half's rows 0 .. ta - 1, the second
+// half's ta .. s0 - 1, with no tiles coupling the halves).  Once the chains
+// of both halves have formed the separator's tiles L_IK, K < s0, and the
+// rows of X = L^{-1} of both halves, the block form of L X = I gives
+//   S = A_SS - L_S,half L_S,half^T (both halves)  ->  L_SS, X_SS = L_SS^{-1}
+//   X_S,half = -X_SS L_S,half X_half,half,
+// formed as V_IC = sum_{K in C's half, K >= max(C, lo[I])} L_IK X_KC for
+// every separator row I and column C < s0 (independent tile sums), then
+// X_IC = -sum_{s0 <= I' <= I} X_II' V_I'C.
+
+// Blocks [0, npair nck): split-K partials of the Schur complement, tile pair
+// p = i (i + 1) / 2 + j (j <= i, separator-local) and chunk c of K < s0,
+// spart[p nck + c] = sum_K L_IK L_JK^T; then one block per tile V_IC,
+// vbuf[i s0 + C].
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_nd_sv(int ta, int tb, int ts, const int64_t* __restrict__ off,
+                                                        const T* __restrict__ fac, const T* __restrict__ X,
+                                                        const int32_t* __restrict__ clo, T* __restrict__ spart,
+                                                        T* __restrict__ vbuf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LdsV<T>::v;
+  const int s0 = ta + tb, nck = (s0 + SPLITK - 1) / SPLITK;
+  const int nsp = ts * (ts + 1) / 2 * nck;
+  const T* F = fac + off[0] * TS2;
+  const T* Xb = X + off[0] * TS2;
+  const int x = blockIdx.x;
+  TileAcc<T> acc;
+  acc.zero();
+  TileRegs<T> ra, rb;
+  if (x < nsp) {
+    const int p = x / nck, c = x % nck;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= p) ++i;
+    const int I = s0 + i, J = s0 + (p - i * (i + 1) / 2);
+    const int k0 = max(c * SPLITK, max(clo[I], clo[J])), k1 = min((c + 1) * SPLITK, s0);
+    if (k0 < k1) {
+      ra.load(F + tri_index(I, k0) * TS2);
+      rb.load(F + tri_index(J, k0) * TS2);
+    }
+    for (int K = k0; K < k1; ++K) {
+      lds_barrier();
+      ra.store_lds(sA);
+      rb.store_lds(sB);
+      lds_barrier();
+      if (K + 1 < k1) {
+        ra.load(F + tri_index(I, K + 1) * TS2);
+        rb.load(F + tri_index(J, K + 1) * TS2);
+      }
+      tile_mma<T>(acc, sA, sB, T(1));   // L_IK L_JK^T
+    }
+    acc.store(spart + (int64_t)x * TS2);
+    return;
+  }
+  const int y = x - nsp;
+  const int i = y / s0, C = y % s0;
+  if (i >= ts) return;
+  const int I = s0 + i;
+  const int k0 = max(C, clo[I]), k1 = C < ta ? ta : s0;
+  if (k0 < k1) {
+    ra.load(F + tri_index(I, k0) * TS2);
+    rb.load(Xb + tri_index(k0, C) * TS2);
+  }
+  for (int K = k0; K < k1; ++K) {
+    lds_barrier();
+    ra.store_lds(sA);
+    rb.store_lds_t(sB);
+    lds_barrier();
+    if (K + 1 < k1) {
+      ra.load(F + tri_index(I, K + 1) * TS2);
+      rb.load(Xb + tri_index(K + 1, C) * TS2);
+    }
+    tile_mma<T>(acc, sA, sB, T(1));     // L_IK X_KC
+  }
+  acc.store(vbuf + (int64_t)y * TS2);
+}
+
+// The Schur complement into the separator's tiles of the factor storage (a
+// tile left of the row's envelope starts from zero: it was never assembled).
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_nd_schur(int ta, int tb, const int64_t* __restrict__ off,
+                                                           T* __restrict__ fac, const int32_t* __restrict__ clo,
+                                                           const T* __restrict__ spart) {
+  const int s0 = ta + tb, nck = (s0 + SPLITK - 1) / SPLITK;
+  const int p = blockIdx.x;
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= p) ++i;
+  const int I = s0 + i, J = s0 + (p - i * (i + 1) / 2);
+  T* D = fac + (off[0] + tri_index(I, J)) * TS2;
+  TileAcc<T> acc;
+  if (J >= clo[I]) acc.load(D);
+  else acc.zero();
+  sub_tiles(acc, spart + (int64_t)p * nck * TS2, TS2, nck);
+  acc.store(D);
+}
+
+// X_IC = -sum_{s0 <= I' <= I} X_II' V_I'C for the separator's rows, C < s0.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS) void k_nd_xs(int ta, int tb, const int64_t* __restrict__ off,
+                                                        T* __restrict__ X, const T* __restrict__ vbuf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);
+  T* sB = sA + TS * LdsV<T>::v;
+  const int s0 = ta + tb;
+  const int i = blockIdx.x / s0, C = blockIdx.x % s0;
+  const int I = s0 + i;
+  T* Xb = X + off[0] * TS2;
+  TileAcc<T> acc;
+  acc.zero();
+  TileRegs<T> ra, rb;
+  ra.load(Xb + tri_index(I, s0) * TS2);
+  rb.load(vbuf + (int64_t)C * TS2);
+  for (int u = 0; u <= i; ++u) {
+    lds_barrier();
+    ra.store_lds(sA);
+    rb.store_lds_t(sB);
+    lds_barrier();
+    if (u < i) {
+      ra.load(Xb + tri_index(I, s0 + u + 1) * TS2);
+      rb.load(vbuf + ((int64_t)(u + 1) * s0 + C) * TS2);
+    }
+    tile_mma<T>(acc, sA, sB, T(-1));    // -X_II' V_I'C
+  }
+  acc.store(Xb + tri_index(I, C) * TS2);
+}
+
+// Factorisation and inverse X = L^{-1} of a dissected coarse matrix (single
+// grid; nd tiles ta, tb, ts; views from launch_nd_views with vstride entries
+// per view): the chains of the two halves in the same launches (views 0 and
+// 1, the rows of X formed beside the steps), the separator's Schur
+// complement and V, the separator's chain (view 2, whose split-K slots reuse
+// view 0's, free by then), X_SS's last row, then X_S,half.  part holds six
+// slots of vstride * maxc tiles; V takes view 1's.
+template <typename T>
+void factor_nd(int ta, int tb, int ts, int maxc, T* part, const int64_t* off, T* fac, T* X, int32_t* status,
+               const int32_t* nt, const int32_t* clo, const int32_t* vinfo, const int32_t* vlo, const int32_t* vrb,
+               int vstride, hipStream_t s) {
+  const int s0 = ta + tb;
+  const int64_t slot_tiles = (int64_t)vstride * maxc;
+  launch_potrf_diag<T>(0, 0, 0, maxc, part, 2, nt, off, fac, status, s, vlo, vrb, vinfo, vstride);
+  for (int J = 0; J < std::max(ta, tb); ++J)
+    launch_potrf_step<T>(J, std::max(ta, tb) + ts, maxc, part, slot_tiles, nt, off, fac, status, s, vlo, vrb, X,
+                         nullptr, vinfo, vstride, 2);
+  T* vbuf = part + 3 * slot_tiles * TS2;
+  const int nck = (s0 + SPLITK - 1) / SPLITK;
+  const int npair = ts * (ts + 1) / 2;
+  const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
+  static bool once = (allow_lds(k_nd_sv<T>, sh), allow_lds(k_nd_xs<T>, sh), true);
+  (void)once;
+  hipLaunchKernelGGL(k_nd_sv<T>, dim3(npair * nck + ts * s0), dim3(TILE_THREADS), sh, s, ta, tb, ts, off, fac, X,
+                     clo, part, vbuf);
+  hipLaunchKernelGGL(k_nd_schur<T>, dim3(npair), dim3(TILE_THREADS), 0, s, ta, tb, off, fac, clo, part);
+  const int32_t* slo = vlo + 2 * vstride;
+  const int32_t* srb = vrb + 2 * vstride;
+  launch_potrf_diag<T>(0, 0, 0, maxc, part, 1, nt, off, fac, status, s, slo, srb, vinfo + 6, vstride);
+  for (int J = 0; J + 1 < ts; ++J)
+    launch_potrf_step<T>(J, ts, maxc, part, slot_tiles, nt, off, fac, status, s, slo, srb, X, nullptr, vinfo + 6,
+                         vstride, 1);
+  launch_xrow<T>(ts - 1, off, fac, X, s, slo, srb, nullptr, s0);
+  hipLaunchKernelGGL(k_nd_xs<T>, dim3(ts * s0), dim3(TILE_THREADS), sh, s, ta, tb, off, X, vbuf);
+}
+
 #define INST(T)                                                                                    \
   template void launch_unit_lower<T>(int, int, const int32_t*, const int64_t*, const int64_t*,     \
                                      const int32_t*, const int32_t*, T*, hipStream_t);              \
   template void launch_potrf_diag<T>(int, int, int, int, const T*, int, const int32_t*,            \
                                      const int64_t*, T*, int32_t*, hipStream_t, const int32_t*,    \
-                                     const int32_t*);                                              \
+                                     const int32_t*, const int32_t*, int);                         \
   template void launch_potrf_full<T>(int, const int32_t*, const int64_t*, const int64_t*,          \
                                      const int32_t*, const int32_t*, T*, int32_t*, bool,           \
                                      hipStream_t, int);                                            \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
                                      T*, int32_t*, hipStream_t, const int32_t*, const int32_t*, T*, \
-                                     const int32_t*);                                              \
+                                     const int32_t*, const int32_t*, int, int);                    \
   template void launch_xrow<T>(int, const int64_t*, const T*, T*, hipStream_t, const int32_t*,     \
-                               const int32_t*, const int32_t*);                                    \
+                               const int32_t*, const int32_t*, int);                               \
+  template void factor_nd<T>(int, int, int, int, T*, const int64_t*, T*, T*, int32_t*,             \
+                             const int32_t*, const int32_t*, const int32_t*, const int32_t*,       \
+                             const int32_t*, int, hipStream_t);                                    \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \

@@ -121,7 +121,17 @@ void launch_coarse_zero_env(const Batch& B, int max_nt0, const int64_t* off, con
 // wide[0] (nullable): the envelope width of grid 0's matrix (the most tile
 // columns left of the diagonal in a tile row).
 void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb,
-                       int32_t* wide, hipStream_t s);
+                       int32_t* wide, const int32_t* nd, hipStream_t s);
+// One-level dissection of a single grid's coarse matrix (halves of the
+// curve, separator last): separator marks (sep cleared beforehand) and the
+// dissected order (nd = {ta, tb, ts} tiles, or zeros when it does not pay),
+// the previous order kept in backup; its undo; the three chains' row tables.
+void launch_nd_order(const Batch& B, const int32_t* nbr, int32_t* sep, int32_t* backup, int32_t* cperm,
+                     int32_t* nd, int n0, hipStream_t s);
+void launch_nd_undo(const Batch& B, const int32_t* backup, int32_t* cperm, int32_t* cfnz, int32_t* nd,
+                    int nrows, hipStream_t s);
+void launch_nd_views(const int32_t* nd, const int32_t* clo, int stride, int32_t* vinfo, int32_t* vlo, int32_t* vrb,
+                     hipStream_t s);
 // A_0 += c_j E_j over the envelope tiles; the counts are cleared as read.
 void launch_coarse_accumulate(const Batch& B, int max_nt0, const int64_t* off, const int32_t* clo, int j,
                               int32_t* cnt, double* A0, hipStream_t s);
@@ -134,7 +144,8 @@ void launch_coarse_pad(const Batch& B, int max_nt0, const int64_t* ctile_off, do
 template <typename T>
 void launch_potrf_diag(int J, int kfrom, int nparts, int maxc, const T* part, int nb,
                        const int32_t* nt, const int64_t* off, T* fac, int32_t* status,
-                       hipStream_t s, const int32_t* tlo = nullptr, const int32_t* trb = nullptr);
+                       hipStream_t s, const int32_t* tlo = nullptr, const int32_t* trb = nullptr,
+                       const int32_t* vinfo = nullptr, int vstride = 0);
 // Whole factorisation, one workgroup per matrix (pair: two columns per
 // step; faster alone, but no room beside it for other workgroups).
 // rows: row tiles per step of the panel updates (2 .. potrf_full_max_rows;
@@ -161,15 +172,26 @@ constexpr int XROW_MAXW = 24;
 // tiles at part, slot C mod 3 for column C).  X (nullable): also row J of
 // the inverse X = L^{-1} (packed lower tiles at X + off[0] tiles), whose
 // last row launch_xrow forms after the last step, when the device-side
-// envelope width *wide is at most XROW_MAXW.
+// envelope width *wide is at most XROW_MAXW.  vinfo (nullable): nviews
+// chains over the parts of a dissected matrix in the same launches (see
+// factor_nd); max_nt is then the most tile rows of a view.
 template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
                        const int64_t* off, T* fac, int32_t* status, hipStream_t s,
                        const int32_t* tlo = nullptr, const int32_t* trb = nullptr, T* X = nullptr,
-                       const int32_t* wide = nullptr);
+                       const int32_t* wide = nullptr, const int32_t* vinfo = nullptr, int vstride = 0,
+                       int nviews = 1);
+// Row J of X (tile offset xo: local tile (J, C) at (xo + J, xo + C)).
 template <typename T>
 void launch_xrow(int J, const int64_t* off, const T* fac, T* X, hipStream_t s, const int32_t* tlo,
-                 const int32_t* trb, const int32_t* wide);
+                 const int32_t* trb, const int32_t* wide, int xo = 0);
+// Factor and inverse of a dissected single coarse matrix (launch_nd_order,
+// launch_nd_views): the two halves' chains concurrently, then the
+// separator.  part: six slots of vstride * maxc tiles.
+template <typename T>
+void factor_nd(int ta, int tb, int ts, int maxc, T* part, const int64_t* off, T* fac, T* X, int32_t* status,
+               const int32_t* nt, const int32_t* clo, const int32_t* vinfo, const int32_t* vlo, const int32_t* vrb,
+               int vstride, hipStream_t s);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);
@@ -229,7 +251,8 @@ void launch_restrict(const Batch& B, int max_block, const double* v, double* c0,
 template <typename T>
 void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t* n,
                          const int64_t* doff, const T* X, const double* v, double* ytmp,
-                         double* part, double* out, const int32_t* active, hipStream_t s);
+                         double* part, double* out, const int32_t* active, hipStream_t s,
+                         const int32_t* nd = nullptr);
 void launch_round_f32(int64_t n, const double* src, float* dst, hipStream_t s);
 // Rounds the tiles inside the envelopes of the dense coarse matrices (tile
 // row I of grid g: clo[c0pad / TS + I] .. I, packed triangle at off[g]).

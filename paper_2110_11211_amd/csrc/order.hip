@@ -487,11 +487,18 @@ void launch_coarse_order(const Batch& B, int kcap, int max_n0, const int32_t* sf
 // matrices from the rows' first nonzero columns, made non-decreasing, and the
 // row bases of the packed triangle (the matrices stay stored as full packed
 // triangles; only the factorisation and inversion skip the zero tiles).  One
-// workgroup per grid.
+// workgroup per grid.  With the one-level dissection of a single grid (nd =
+// {ta, tb, ts}, ts > 0: tile rows [0, ta) of the first half, [ta, ta + tb) of
+// the second, the separator after them) lo is non-decreasing within each of
+// the three parts only: the rows of the second half start right of the first
+// half, which the separator's rows reach.  wide = the largest I - lo[I] over
+// the rows whose inverse rows the column steps form (all rows, or the two
+// halves with the dissection).
 __global__ __launch_bounds__(ORDER_THREADS) void k_coarse_env(Batch B, const int32_t* __restrict__ cfnz,
                                                               int32_t* __restrict__ clo,
                                                               int32_t* __restrict__ crb,
-                                                              int32_t* __restrict__ wide) {
+                                                              int32_t* __restrict__ wide,
+                                                              const int32_t* __restrict__ nd) {
   const GridDesc& g = B.grids[blockIdx.x];
   const int nt = g.nt0d;
   const int64_t trow = g.c0pad / TS;
@@ -501,21 +508,193 @@ __global__ __launch_bounds__(ORDER_THREADS) void k_coarse_env(Batch B, const int
   for (int r = threadIdx.x; r < nt * TS; r += ORDER_THREADS) atomicMin(&tmin[r / TS], cfnz[g.c0pad + r] / TS);
   __syncthreads();
   if (threadIdx.x == 0) {
+    const bool split = nd && nd[2] > 0;
+    const int ta = split ? nd[0] : 0, tab = split ? nd[0] + nd[1] : nt;
     int lo = nt, w = 0;
     for (int I = nt - 1; I >= 0; --I) {
+      if (split && (I == tab - 1 || I == ta - 1)) lo = nt;   // the part below is another one
       lo = min(lo, tmin[I]);
       clo[trow + I] = lo;
       crb[trow + I] = I * (I + 1) / 2;
-      w = max(w, I - lo);
+      if (I < tab) w = max(w, I - lo);
     }
     if (wide && blockIdx.x == 0) wide[0] = w;
   }
 }
 
 void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t* clo, int32_t* crb,
-                       int32_t* wide, hipStream_t s) {
+                       int32_t* wide, const int32_t* nd, hipStream_t s) {
   const size_t sh = (size_t)max_nt0 * sizeof(int);
-  hipLaunchKernelGGL(k_coarse_env, dim3(B.G), dim3(ORDER_THREADS), sh, s, B, cfnz, clo, crb, wide);
+  hipLaunchKernelGGL(k_coarse_env, dim3(B.G), dim3(ORDER_THREADS), sh, s, B, cfnz, clo, crb, wide, nd);
+}
+
+// ---------------------------------------------------------------------------
+// One-level nested dissection of a single grid's coarse matrix.
+//
+// The coarse blocks of the first half of the curve (block index < N0 / 2) and
+// those of the second half couple only through the blocks of the first half
+// that have a stencil neighbour in the second (the separator).  Ordered as
+// [first half | second half | separator], the Cholesky factor has no tiles
+// coupling the halves, so the two halves factor as independent chains of
+// column steps, and the separator's rows follow: about half the dependent
+// steps of one chain over the whole matrix.  X_0 = L_0^{-1} keeps the block
+// structure (no tiles in the rows of the second half left of it), so the
+// coarse solves read only the nonzero tiles.  Within each part the blocks
+// keep the centroid-diagonal order.  The halves are trimmed to whole tiles:
+// the blocks past the last whole tile of a half go to the separator.
+
+// sep[k] = 1 for every block k of the first half with a neighbour in the
+// second (sep cleared beforehand).  Every writer stores the same value.
+__global__ __launch_bounds__(256) void k_nd_mark(Batch B, const int32_t* __restrict__ nbr,
+                                                 int32_t* __restrict__ sep) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= B.Ntot) return;
+  const GridDesc& g = B.grids[0];
+  const int half = g.N0 / 2;
+  const int k = coarse_block(p - g.goff, g);
+  if (k >= half) return;
+  for (int j = 0; j < g.d; ++j)
+    for (int side = 0; side < 2; ++side) {
+      const int64_t q = nbr[(2 * j + side) * B.Ntot + p];
+      if (q >= 0 && coarse_block(q - g.goff, g) >= half) {
+        sep[k] = 1;
+        return;
+      }
+    }
+}
+
+// The dissected order from the centroid-diagonal one (cperm): each part in
+// that order, the halves' remainders (past their last whole tile) ahead of
+// the separator's own blocks.  nd = {ta, tb, ts} tiles of the two halves and
+// the separator, or {0, 0, 0} (order unchanged) unless both halves have at
+// least two tiles and the separator at most an eighth of the tile rows.
+// backup[k] keeps the previous position of block k.  One workgroup; LDS:
+// the inverse permutation (N0 ints).
+constexpr int ND_THREADS = 1024;
+__global__ __launch_bounds__(ND_THREADS) void k_nd_order(Batch B, int32_t* __restrict__ cperm,
+                                                         const int32_t* __restrict__ sep,
+                                                         int32_t* __restrict__ backup, int32_t* __restrict__ nd) {
+  const GridDesc& g = B.grids[0];
+  const int n0 = g.N0, nt = g.nt0d, half = n0 / 2;
+  extern __shared__ int inv[];
+  __shared__ int wsum[3][ND_THREADS / 64 + 1];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int k = t; k < n0; k += ND_THREADS) inv[cperm[g.c0off + k]] = k;
+  __syncthreads();
+  auto part = [&](int k) { return sep[k] ? 2 : (k < half ? 0 : 1); };
+  const int seg = (n0 + ND_THREADS - 1) / ND_THREADS;
+  const int p0 = min(n0, t * seg), p1 = min(n0, p0 + seg);
+  int c[3] = {0, 0, 0};
+  for (int pos = p0; pos < p1; ++pos) ++c[part(inv[pos])];
+  // exclusive prefix of the segment counts over the threads (wave scans,
+  // then the wave totals)
+  int x[3];
+  for (int q = 0; q < 3; ++q) {
+    int v = c[q];
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o, 64);
+      if (lane >= o) v += u;
+    }
+    x[q] = v - c[q];
+    if (lane == 63) wsum[q][wv + 1] = v;
+  }
+  __syncthreads();
+  if (t < 3) {
+    wsum[t][0] = 0;
+    for (int u = 1; u <= ND_THREADS / 64; ++u) wsum[t][u] += wsum[t][u - 1];
+  }
+  __syncthreads();
+  for (int q = 0; q < 3; ++q) x[q] += wsum[q][wv];
+  const int na = wsum[0][ND_THREADS / 64], nb = wsum[1][ND_THREADS / 64];
+  const int ta = na / TS, tb = nb / TS, ra = na % TS, rb = nb % TS;
+  const int ts = nt - ta - tb;
+  const bool ok = ta >= 2 && tb >= 2 && ts >= 1 && 8 * ts <= nt;
+  if (t == 0) {
+    nd[0] = ok ? ta : 0;
+    nd[1] = ok ? tb : 0;
+    nd[2] = ok ? ts : 0;
+  }
+  if (!ok) return;
+  const int sa = TS * ta, sb = TS * tb, s0 = sa + sb;
+  int r[3] = {x[0], x[1], x[2]};
+  for (int pos = p0; pos < p1; ++pos) {
+    const int k = inv[pos];
+    const int q = part(k);
+    const int rk = r[q]++;
+    int np;
+    if (q == 0) np = rk < sa ? rk : s0 + (rk - sa);
+    else if (q == 1) np = rk < sb ? sa + rk : s0 + ra + (rk - sb);
+    else np = s0 + ra + rb + rk;
+    backup[k] = pos;
+    cperm[g.c0off + k] = np;
+  }
+}
+
+// Back to the order before the dissection (its halves' envelopes turned out
+// too wide for the inverse rows beside the column steps), with the
+// first-nonzero columns reset for k_coarse_fnz.
+__global__ __launch_bounds__(256) void k_nd_undo(Batch B, const int32_t* __restrict__ backup,
+                                                 int32_t* __restrict__ cperm, int32_t* __restrict__ cfnz,
+                                                 int32_t* __restrict__ nd) {
+  const GridDesc& g = B.grids[0];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < g.N0) cperm[g.c0off + i] = backup[i];
+  if (i < g.nt0d * TS) cfnz[g.c0pad + i] = i;
+  if (i < 3) nd[i] = 0;
+}
+
+void launch_nd_order(const Batch& B, const int32_t* nbr, int32_t* sep, int32_t* backup, int32_t* cperm,
+                     int32_t* nd, int n0, hipStream_t s) {
+  hipLaunchKernelGGL(k_nd_mark, dim3((unsigned)((B.Ntot + 255) / 256)), dim3(256), 0, s, B, nbr, sep);
+  const size_t sh = (size_t)n0 * sizeof(int);
+  if (sh > 32768)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_nd_order),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL(k_nd_order, dim3(1), dim3(ND_THREADS), sh, s, B, cperm, sep, backup, nd);
+}
+
+void launch_nd_undo(const Batch& B, const int32_t* backup, int32_t* cperm, int32_t* cfnz, int32_t* nd,
+                    int nrows, hipStream_t s) {
+  hipLaunchKernelGGL(k_nd_undo, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, B, backup, cperm, cfnz, nd);
+}
+
+// Row tables of the three chains of a dissected coarse matrix (views): view 0
+// the first half's tile rows then the separator's, view 1 the second half's
+// then the separator's, view 2 the separator's alone.  Per view v:
+// vinfo[3 v ..] = {rows, columns factored by its chain, first tile column},
+// and for its local tile row i: vlo[v * stride + i] = first local tile column
+// (the separator's own chain treats its block as dense), vrb[v * stride + i]
+// = packed index of global tile (row, first column), so that local tile
+// (i, j) is packed tile vrb[i] + j.
+__global__ __launch_bounds__(256) void k_nd_views(const int32_t* __restrict__ nd, const int32_t* __restrict__ clo,
+                                                  int stride, int32_t* __restrict__ vinfo,
+                                                  int32_t* __restrict__ vlo, int32_t* __restrict__ vrb) {
+  const int ta = nd[0], tb = nd[1], ts = nd[2], s0 = ta + tb;
+  if (threadIdx.x == 0) {
+    vinfo[0] = ta + ts; vinfo[1] = ta; vinfo[2] = 0;
+    vinfo[3] = tb + ts; vinfo[4] = tb; vinfo[5] = ta;
+    vinfo[6] = ts;      vinfo[7] = ts; vinfo[8] = s0;
+  }
+  for (int i = threadIdx.x; i < ta + ts; i += 256) {
+    const int I = i < ta ? i : s0 + (i - ta);
+    vlo[i] = clo[I];
+    vrb[i] = I * (I + 1) / 2;
+  }
+  for (int i = threadIdx.x; i < tb + ts; i += 256) {
+    const int I = i < tb ? ta + i : s0 + (i - tb);
+    vlo[stride + i] = max(clo[I] - ta, 0);
+    vrb[stride + i] = I * (I + 1) / 2 + ta;
+  }
+  for (int i = threadIdx.x; i < ts; i += 256) {
+    const int I = s0 + i;
+    vlo[2 * stride + i] = 0;
+    vrb[2 * stride + i] = I * (I + 1) / 2 + s0;
+  }
+}
+
+void launch_nd_views(const int32_t* nd, const int32_t* clo, int stride, int32_t* vinfo, int32_t* vlo, int32_t* vrb,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_nd_views, dim3(1), dim3(256), 0, s, nd, clo, stride, vinfo, vlo, vrb);
 }
 
 void launch_local_order(const Batch& B, int mode, int kcap, int max_nt, const int32_t* ta, const int32_t* Ni,

@@ -58,6 +58,8 @@ struct sfcdd_ctx {
   std::vector<GridHost> grid;
   int weighting = 1, variant = 1, fdtype = 0, local_solver = 0, layout = 0;
   int local_order = SFCDD_ORDER_DIAGONAL;  // elimination order of the subdomain matrices
+  int coarse_split = SFCDD_SPLIT_AUTO;     // dissection of a single dense coarse matrix
+  int nd[3] = {0, 0, 0};                   // its tiles: first half, second half, separator
   int64_t Ntot = 0, N0tot = 0;
   int Ptot = 0, dmax = 0, duni = 0, rbx = RED_BLOCKS;
   int max_cblock = 1;  // largest coarse block (points) of any grid
@@ -140,6 +142,7 @@ struct sfcdd_ctx {
   uint64_t noalloc_gen = 0;
   std::vector<unsigned char> host_pageable;
   size_t rb_bytes = 0, rb_flags = 0, hb_off = 0;
+  size_t hnd_off = 0;  // byte offset in host_scal of the coarse dissection readback (4 int32)
   std::vector<int32_t> last_iters;
   hipEvent_t ev_rb = nullptr;  // readback of the per-iteration scalars
   // host copy of the device activity flags (valid after the first upload)
@@ -327,6 +330,8 @@ sfcdd_status plan_grid(GridHost& h, const sfcdd_params* p, std::string& err) {
   if (p->local_order != SFCDD_ORDER_DIAGONAL && p->local_order != SFCDD_ORDER_CURVE &&
       p->local_order != SFCDD_ORDER_DENSE)
     GFAIL(SFCDD_EINVAL, "local_order = %d", p->local_order);
+  if (p->coarse_split != SFCDD_SPLIT_AUTO && p->coarse_split != SFCDD_SPLIT_OFF)
+    GFAIL(SFCDD_EINVAL, "coarse_split = %d", p->coarse_split);
   g.curve = p->curve;
 
   if (p->coarse_solver != SFCDD_COARSE_DENSE && p->coarse_solver != SFCDD_COARSE_ITERATIVE)
@@ -513,6 +518,7 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->fdtype = params[0].factor_dtype;
   c->local_solver = params[0].local_solver;
   c->local_order = c->local_solver == SFCDD_LOCAL_INVERSE ? SFCDD_ORDER_DENSE : params[0].local_order;
+  c->coarse_split = params[0].coarse_split;
   c->layout = params[0].layout;
   c->coarse_iter = params[0].coarse_solver == SFCDD_COARSE_ITERATIVE;
   if (c->coarse_iter) {
@@ -868,7 +874,7 @@ void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) 
   if (c->coarse_x32)
     launch_coarse_apply<float>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff,
                                reinterpret_cast<const float*>(c->X0) + c->ctiles * TS2, c->c0, c->cy,
-                               c->cpart, c->d0, mask, c->stream);
+                               c->cpart, c->d0, mask, c->stream, c->nd[2] > 0 ? c->status + 13 : nullptr);
   else
     launch_coarse_apply<double>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart,
                                 c->d0, mask, c->stream);
@@ -1153,6 +1159,14 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   }
   HIPCHK(c, hipEventRecord(fork, s));
   HIPCHK(c, hipStreamWaitEvent(c->side, fork, 0));
+  // One-level dissection of a single dense coarse matrix with FP32 factor and
+  // inverse (the chains' split-K slots then hold two views' worth of FP32
+  // tiles in the FP64-sized region).
+  const int n0s = c->grid[0].desc.N0;
+  const bool nd_try = G == 1 && !c->coarse_iter && c->coarse_x32 && c->coarse32 &&
+                      c->coarse_split == SFCDD_SPLIT_AUTO && c->max_nt0 >= 16;
+  int32_t* const nd_sep = reinterpret_cast<int32_t*>(c->cy);
+  c->nd[0] = c->nd[1] = c->nd[2] = 0;
   {
     const hipStream_t cs = c->side;
     HIPCHK(c, hipEventRecord(cev0, cs));
@@ -1168,61 +1182,22 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     int max_n0 = 1;
     for (int k = 0; k < G; ++k) max_n0 = std::max(max_n0, c->grid[k].desc.N0);
     launch_coarse_order(B, ckcap, max_n0, c->sfc_index, c->ccen, c->cperm, c->cfnz, cs);
+    if (nd_try) {
+      // one-level dissection (halves of the curve, separator last); its
+      // scratch: the separator marks and the previous order in cy
+      HIPCHK(c, hipMemsetAsync(nd_sep, 0, 4 * (size_t)n0s, cs));
+      launch_nd_order(B, c->nbr, nd_sep, nd_sep + n0s, c->cperm, c->status + 13, n0s, cs);
+    }
     // the envelopes first (only their tiles are cleared, assembled and read)
     launch_coarse_fnz(B, c->nbr, c->cfnz, cs);
-    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, cs);
-    int32_t* cnt = reinterpret_cast<int32_t*>(c->X0);   // count scratch (the inverse comes later)
-    launch_coarse_zero_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, cnt, cs);
-    for (int j = 0; j < c->dmax; ++j) {
-      launch_coarse_counts(B, j, c->nbr, c->dc_off, cnt, cs);
-      launch_coarse_accumulate(B, c->max_nt0, c->dc_off, c->clo, j, cnt, c->A0, cs);
-    }
-    launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
-    // Beside FP32 subdomain factors the inverse X_0 = L_0^{-1} is FP32: A_0
-    // is an M-matrix (a Galerkin aggregation of the stencil matrix), so L_0
-    // has non-positive off-diagonal entries, X_0 is entrywise non-negative
-    // and every sum that forms it has terms of one sign (no cancellation).
-    // The factor itself is FP32 as well when the coarse matrices are well
-    // conditioned (coarse_fp32_ok), else FP64 and rounded.  FP32 tiles: L_0
-    // in the first half of the X0 region, X_0 in the second.
-    if (c->coarse_x32) {
-      float* L32 = reinterpret_cast<float*>(c->X0);
-      float* part32 = reinterpret_cast<float*>(c->cpartk);
-      if (c->coarse32) {
-        launch_round_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, L32, cs);
-        factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
-                            c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs, 0,
-                            c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
-      } else {
-        factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, false, false, c->status + 1,
-                             G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
-                             c->dc_xoff, c->clo, c->crb);
-        launch_round_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, L32, cs);
-        launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
-                                part32, cs, c->dc_xoff, c->clo);
-      }
-    } else {
-      factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
-                           G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
-                           c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
-    }
-    if (c->coarse_iter) {
-      // the sparse rows of A_0 (one workgroup per coarse block), then the
-      // explicit inverses of its diagonal 64-blocks
-      const int64_t n0 = c->grid[0].desc.N0;
-      HIPCHK(c, hipMemsetAsync(c->ideg, 0, c->r_ideg.bytes, cs));
-      launch_coarse_ell(B, n0, c->nbr, c->ic_kw, c->ic_ld, c->ideg, c->icol, c->ival, c->status + 2, cs);
-      HIPCHK(c, hipMemsetAsync(c->ibjt, 0, c->r_ibjt.bytes, cs));
-      launch_bj_extract(n0, c->ic_ld, c->ideg, c->icol, c->ival, c->ibjt, cs);
-      launch_potrf_full<double>(c->ic_nt, c->ibjnt, c->ibjoff, nullptr, nullptr, nullptr, c->ibjt, c->status + 3,
-                                false, cs);
-      launch_bj_form(c->ic_nt, c->ibjt, c->ibjm, cs);
-      HIPCHK(c, hipMemsetAsync(c->icagg, 0, c->r_icagg.bytes, cs));
-      HIPCHK(c, hipMemsetAsync(c->idagg, 0, c->r_idagg.bytes, cs));
-    }
+    launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, nd_try ? c->status + 13 : nullptr,
+                      cs);
+    // the dissection's tiles and the halves' envelope width, read back once
+    // the subdomain side is enqueued
+    if (nd_try)
+      HIPCHK(c, hipMemcpyAsync(reinterpret_cast<unsigned char*>(c->host_scal) + c->hnd_off, c->status + 12, 16,
+                               hipMemcpyDeviceToHost, cs));
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipEventRecord(cev1, cs));
-    HIPCHK(c, hipEventRecord(join, cs));
   }
 
   // local elimination order and tile envelopes, then the local matrices
@@ -1280,6 +1255,90 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     else
       launch_unit_lower<double>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (double*)c->fac, s);
   }
+  {
+    const hipStream_t cs = c->side;
+    if (nd_try) {
+      HIPCHK(c, hipStreamSynchronize(cs));
+      const int32_t* h = reinterpret_cast<const int32_t*>(reinterpret_cast<const unsigned char*>(c->host_scal) +
+                                                          c->hnd_off);
+      const int wide = h[0];
+      if (h[3] > 0 && wide <= XROW_MAXW) {
+        c->nd[0] = h[1];
+        c->nd[1] = h[2];
+        c->nd[2] = h[3];
+      } else if (h[3] > 0) {
+        // the halves' envelopes are too wide for the inverse rows beside the
+        // column steps: back to the undissected order
+        launch_nd_undo(B, nd_sep + n0s, c->cperm, c->cfnz, c->status + 13, c->max_nt0 * TS, cs);
+        launch_coarse_fnz(B, c->nbr, c->cfnz, cs);
+        launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, nullptr, cs);
+      }
+    }
+    int32_t* cnt = reinterpret_cast<int32_t*>(c->X0);   // count scratch (the inverse comes later)
+    launch_coarse_zero_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, cnt, cs);
+    for (int j = 0; j < c->dmax; ++j) {
+      launch_coarse_counts(B, j, c->nbr, c->dc_off, cnt, cs);
+      launch_coarse_accumulate(B, c->max_nt0, c->dc_off, c->clo, j, cnt, c->A0, cs);
+    }
+    launch_coarse_pad(B, c->max_nt0, c->dc_off, c->A0, cs);
+    // Beside FP32 subdomain factors the inverse X_0 = L_0^{-1} is FP32: A_0
+    // is an M-matrix (a Galerkin aggregation of the stencil matrix), so L_0
+    // has non-positive off-diagonal entries, X_0 is entrywise non-negative
+    // and every sum that forms it has terms of one sign (no cancellation).
+    // The factor itself is FP32 as well when the coarse matrices are well
+    // conditioned (coarse_fp32_ok), else FP64 and rounded.  FP32 tiles: L_0
+    // in the first half of the X0 region, X_0 in the second.
+    if (c->coarse_x32) {
+      float* L32 = reinterpret_cast<float*>(c->X0);
+      float* part32 = reinterpret_cast<float*>(c->cpartk);
+      if (c->coarse32) {
+        launch_round_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, L32, cs);
+        if (c->nd[2] > 0) {
+          // the three chains' row tables in d0 (free until the solves)
+          int32_t* vinfo = reinterpret_cast<int32_t*>(c->d0);
+          int32_t* vlo = vinfo + 16;
+          int32_t* vrb = vlo + 3 * c->max_nt0;
+          launch_nd_views(c->status + 13, c->clo, c->max_nt0, vinfo, vlo, vrb, cs);
+          factor_nd<float>(c->nd[0], c->nd[1], c->nd[2], (int)ceil_div(c->max_nt0, SPLITK), part32, c->dc_off,
+                           L32, L32 + c->ctiles * TS2, c->status + 1, c->dc_nt, c->clo, vinfo, vlo, vrb,
+                           c->max_nt0, cs);
+        } else {
+          factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
+                              c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs, 0,
+                              c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
+        }
+      } else {
+        factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, false, false, c->status + 1,
+                             G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
+                             c->dc_xoff, c->clo, c->crb);
+        launch_round_env(B, c->max_nt0, c->dc_off, c->clo, c->A0, L32, cs);
+        launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
+                                part32, cs, c->dc_xoff, c->clo);
+      }
+    } else {
+      factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
+                           G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,
+                           c->dc_xoff, c->clo, c->crb, G == 1 ? c->status + 12 : nullptr);
+    }
+    if (c->coarse_iter) {
+      // the sparse rows of A_0 (one workgroup per coarse block), then the
+      // explicit inverses of its diagonal 64-blocks
+      const int64_t n0 = c->grid[0].desc.N0;
+      HIPCHK(c, hipMemsetAsync(c->ideg, 0, c->r_ideg.bytes, cs));
+      launch_coarse_ell(B, n0, c->nbr, c->ic_kw, c->ic_ld, c->ideg, c->icol, c->ival, c->status + 2, cs);
+      HIPCHK(c, hipMemsetAsync(c->ibjt, 0, c->r_ibjt.bytes, cs));
+      launch_bj_extract(n0, c->ic_ld, c->ideg, c->icol, c->ival, c->ibjt, cs);
+      launch_potrf_full<double>(c->ic_nt, c->ibjnt, c->ibjoff, nullptr, nullptr, nullptr, c->ibjt, c->status + 3,
+                                false, cs);
+      launch_bj_form(c->ic_nt, c->ibjt, c->ibjm, cs);
+      HIPCHK(c, hipMemsetAsync(c->icagg, 0, c->r_icagg.bytes, cs));
+      HIPCHK(c, hipMemsetAsync(c->idagg, 0, c->r_idagg.bytes, cs));
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(cev1, cs));
+    HIPCHK(c, hipEventRecord(join, cs));
+  }
+
   c->info.factor_pair = pair && rows != 1 ? 1 : 0;
   c->info.factor_rows = rows > 0 ? rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
   HIPCHK(c, hipGetLastError());
@@ -1340,6 +1399,7 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   I.spmv_window = c->spmv_win;
   I.N0d = c->max_N0;
   I.ell_width = c->ic_kw;
+  for (int k = 0; k < 3; ++k) I.coarse_split[k] = c->nd[k];
 
   int32_t stat[4] = {0, 0, 0, 0};
   HIPCHK(c, hipMemcpy(stat, c->status, 16, hipMemcpyDeviceToHost));
@@ -1391,6 +1451,7 @@ uint64_t key_trsv(const sfcdd_ctx* c, int dev) {
   m((uint64_t)c->fdtype);
   m((uint64_t)c->local_solver);
   m((uint64_t)c->local_order);
+  m((uint64_t)c->coarse_split);
   for (int i = 0; i < c->Ptot; ++i) {
     m((uint64_t)c->nt[i]);
     m((uint64_t)c->Ni[i]);
@@ -1715,7 +1776,8 @@ sfcdd_status setup_common(int G, const sfcdd_params* params, void* workspace_dev
   c->rb_flags = c->r_active.off - c->r_scal.off;
   c->rb_bytes = c->rb_flags + 4 * (size_t)G;
   c->hb_off = (c->rb_bytes + 255) & ~size_t(255);
-  const size_t hbytes = c->hb_off + 4 * (size_t)G + 8 * MAXD + 256;
+  c->hnd_off = c->hb_off + 4 * (size_t)G + 8 * MAXD + 256;
+  const size_t hbytes = c->hnd_off + 16;
   if (c->noalloc) {
     // pageable host image: device-to-host copies into it are waited for with a
     // stream synchronisation (see wait_readback)
