@@ -958,13 +958,39 @@ __global__ __launch_bounds__(TILE_THREADS) void k_xrow(int J, const int64_t* __r
   xrow_tile<T, Env>(J, (int)blockIdx.x, fac + off[0] * TS2, X + off[0] * TS2, sA, sB, Env{tlo, trb}, xo);
 }
 
+// One term of V_IC = sum_K L_IK X_KC for the separator rows of a view (local
+// rows nc .. ntb - 1; the separator's row i at V + (i s0 + xo + C) tiles):
+// V_IC += L_IK X_KC for every such row I whose envelope reaches column K.
+template <typename T, typename IX>
+__device__ __forceinline__ void nd_vterm(int K, int C, int nc, int ntb, int xo, int s0, const T* __restrict__ F,
+                                         const T* __restrict__ X, T* __restrict__ V, T* sA, T* sB, IX ix) {
+  TileRegs<T> ra, rb;
+  rb.load(X + tri_index(xo + K, xo + C) * TS2);
+  rb.store_lds_t(sB);   // X_KC^T
+  for (int I = nc; I < ntb; ++I) {
+    if (ix.first(I) > K) continue;
+    T* Vt = V + ((int64_t)(I - nc) * s0 + xo + C) * TS2;
+    TileAcc<T> acc;
+    acc.load(Vt);
+    ra.load(F + ix(I, K) * TS2);
+    lds_barrier();
+    ra.store_lds(sA);
+    lds_barrier();
+    tile_mma<T>(acc, sA, sB, T(1));
+    acc.store(Vt);
+  }
+}
+
 // Column step J of one chain.  Views (vinfo non-null; the chains of a
 // dissected coarse matrix, view blockIdx.y): vinfo[3 v ..] = {tile rows,
 // columns the chain factors, X tile offset}, row tables at tlo / trb + v *
 // vstride, split-K slots at part + 3 v slot_tiles tiles.  The chain of view
 // v factors its first nc columns only: its last step forms the tiles below
 // them (the separator's rows) but neither the next diagonal tile nor
-// partials of columns >= nc.
+// partials of columns >= nc.  V (nullable, views): the step also adds the
+// term K = J - 1 of the separator rows' V = L_S,half X_half,half (row J - 1
+// of X and column J - 1 of L are final by then; s0 = vinfo[9]), J
+// workgroups after the rows of X.
 template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T* __restrict__ part,
                                                              int64_t slot_tiles,
@@ -976,7 +1002,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
                                                              const int32_t* __restrict__ trb,
                                                              T* __restrict__ X,
                                                              const int32_t* __restrict__ wide,
-                                                             const int32_t* __restrict__ vinfo, int vstride) {
+                                                             const int32_t* __restrict__ vinfo, int vstride,
+                                                             T* __restrict__ V) {
   // The steps form a chain of dependent launches that runs beside the
   // throughput-bound batched factorisation of the subdomains; the highest
   // wave priority lets its instructions issue first on the shared SIMDs
@@ -1002,9 +1029,15 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
   T* sB = sA + TS * LdsV<T>::v;
   T* F = fac + off[0] * TS2;
   const int x = blockIdx.x;
-  if (x >= nwg) {  // row J of the inverse (normal priority: off the chain)
-    if (!X || x - nwg > J || (wide && *wide > XROW_MAXW)) return;
-    xrow_tile<T, Env>(J, x - nwg, F, X + off[0] * TS2, sA, sB, ix, xo);
+  if (x >= nwg) {  // row J of the inverse, terms of V (normal priority: off the chain)
+    if (!X) return;
+    const int xr = x - nwg;
+    if (xr <= J) {
+      if (!(wide && *wide > XROW_MAXW)) xrow_tile<T, Env>(J, xr, F, X + off[0] * TS2, sA, sB, ix, xo);
+      return;
+    }
+    if (V && xr - (J + 1) < J)
+      nd_vterm<T, Env>(J - 1, xr - (J + 1), ncol, ntb, xo, vinfo[9], F, X + off[0] * TS2, V, sA, sB, ix);
     return;
   }
   __builtin_amdgcn_s_setprio(3);
@@ -1156,7 +1189,7 @@ template <typename T>
 void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles, const int32_t* nt,
                        const int64_t* off, T* fac, int32_t* status, hipStream_t s, const int32_t* tlo,
                        const int32_t* trb, T* X, const int32_t* wide, const int32_t* vinfo, int vstride,
-                       int nviews) {
+                       int nviews, T* V) {
   const int m = max_nt - 1 - J;
   if (m <= 0) return;
   const int nc = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
@@ -1164,8 +1197,8 @@ void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles,
   const size_t sh = std::max(2 * TS * LdsV<T>::v * sizeof(T), diag_lds_bytes<T>());
   static bool once = (allow_lds(k_potrf_step<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg + (X ? J + 1 : 0), nviews), dim3(TILE_THREADS), sh, s, J, maxc,
-                     part, slot_tiles, nt, off, fac, status, tlo, trb, X, wide, vinfo, vstride);
+  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg + (X ? J + 1 : 0) + (X && V ? J : 0), nviews), dim3(TILE_THREADS),
+                     sh, s, J, maxc, part, slot_tiles, nt, off, fac, status, tlo, trb, X, wide, vinfo, vstride, V);
 }
 
 template <typename T>
@@ -1481,13 +1514,15 @@ void launch_lauum(int nb, int max_nt, const int32_t* nt, const int64_t* off, con
 //   S = A_SS - L_S,half L_S,half^T (both halves)  ->  L_SS, X_SS = L_SS^{-1}
 //   X_S,half = -X_SS L_S,half X_half,half,
 // formed as V_IC = sum_{K in C's half, K >= max(C, lo[I])} L_IK X_KC for
-// every separator row I and column C < s0 (independent tile sums), then
+// every separator row I and column C < s0 (the column step K + 1 of C's
+// half adds term K, one product per tile beside the chain), then
 // X_IC = -sum_{s0 <= I' <= I} X_II' V_I'C.
 
 // Blocks [0, npair nck): split-K partials of the Schur complement, tile pair
 // p = i (i + 1) / 2 + j (j <= i, separator-local) and chunk c of K < s0,
-// spart[p nck + c] = sum_K L_IK L_JK^T; then one block per tile V_IC,
-// vbuf[i s0 + C].
+// spart[p nck + c] = sum_K L_IK L_JK^T; then one block per column C < s0
+// adding the last term of V_IC (vbuf[i s0 + C], the other terms added by the
+// column steps) for every separator row i.
 template <typename T>
 __global__ __launch_bounds__(TILE_THREADS) void k_nd_sv(int ta, int tb, int ts, const int64_t* __restrict__ off,
                                                         const T* __restrict__ fac, const T* __restrict__ X,
@@ -1528,27 +1563,26 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nd_sv(int ta, int tb, int ts, 
     acc.store(spart + (int64_t)x * TS2);
     return;
   }
-  const int y = x - nsp;
-  const int i = y / s0, C = y % s0;
-  if (i >= ts) return;
-  const int I = s0 + i;
-  const int k0 = max(C, clo[I]), k1 = C < ta ? ta : s0;
-  if (k0 < k1) {
-    ra.load(F + tri_index(I, k0) * TS2);
-    rb.load(Xb + tri_index(k0, C) * TS2);
-  }
-  for (int K = k0; K < k1; ++K) {
+  // the last term of V (K = the last column of C's half), whose row of X the
+  // chain's last step formed
+  const int C = x - nsp;
+  if (C >= s0) return;
+  const int K = C < ta ? ta - 1 : s0 - 1;
+  rb.load(Xb + tri_index(K, C) * TS2);
+  rb.store_lds_t(sB);   // X_KC^T
+  for (int i = 0; i < ts; ++i) {
+    const int I = s0 + i;
+    if (clo[I] > K) continue;
+    T* Vt = vbuf + ((int64_t)i * s0 + C) * TS2;
+    TileAcc<T> v;
+    v.load(Vt);
+    ra.load(F + tri_index(I, K) * TS2);
     lds_barrier();
     ra.store_lds(sA);
-    rb.store_lds_t(sB);
     lds_barrier();
-    if (K + 1 < k1) {
-      ra.load(F + tri_index(I, K + 1) * TS2);
-      rb.load(Xb + tri_index(K + 1, C) * TS2);
-    }
-    tile_mma<T>(acc, sA, sB, T(1));     // L_IK X_KC
+    tile_mma<T>(v, sA, sB, T(1));      // V_IC += L_IK X_KC
+    v.store(Vt);
   }
-  acc.store(vbuf + (int64_t)y * TS2);
 }
 
 // The Schur complement into the separator's tiles of the factor storage (a
@@ -1604,26 +1638,27 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nd_xs(int ta, int tb, const in
 // grid; nd tiles ta, tb, ts; views from launch_nd_views with vstride entries
 // per view): the chains of the two halves in the same launches (views 0 and
 // 1, the rows of X formed beside the steps), the separator's Schur
-// complement and V, the separator's chain (view 2, whose split-K slots reuse
-// view 0's, free by then), X_SS's last row, then X_S,half.  part holds six
-// slots of vstride * maxc tiles; V takes view 1's.
+// complement and the last terms of V, the separator's chain (view 2, whose
+// split-K slots reuse view 0's, free by then), X_SS's last row, then
+// X_S,half.  part holds six slots of vstride * maxc tiles; vbuf ts * s0
+// tiles (cleared here).
 template <typename T>
 void factor_nd(int ta, int tb, int ts, int maxc, T* part, const int64_t* off, T* fac, T* X, int32_t* status,
                const int32_t* nt, const int32_t* clo, const int32_t* vinfo, const int32_t* vlo, const int32_t* vrb,
-               int vstride, hipStream_t s) {
+               int vstride, T* vbuf, hipStream_t s) {
   const int s0 = ta + tb;
   const int64_t slot_tiles = (int64_t)vstride * maxc;
+  (void)hipMemsetAsync(vbuf, 0, (size_t)ts * s0 * TS2 * sizeof(T), s);
   launch_potrf_diag<T>(0, 0, 0, maxc, part, 2, nt, off, fac, status, s, vlo, vrb, vinfo, vstride);
   for (int J = 0; J < std::max(ta, tb); ++J)
     launch_potrf_step<T>(J, std::max(ta, tb) + ts, maxc, part, slot_tiles, nt, off, fac, status, s, vlo, vrb, X,
-                         nullptr, vinfo, vstride, 2);
-  T* vbuf = part + 3 * slot_tiles * TS2;
+                         nullptr, vinfo, vstride, 2, vbuf);
   const int nck = (s0 + SPLITK - 1) / SPLITK;
   const int npair = ts * (ts + 1) / 2;
   const size_t sh = 2 * TS * LdsV<T>::v * sizeof(T);
   static bool once = (allow_lds(k_nd_sv<T>, sh), allow_lds(k_nd_xs<T>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_nd_sv<T>, dim3(npair * nck + ts * s0), dim3(TILE_THREADS), sh, s, ta, tb, ts, off, fac, X,
+  hipLaunchKernelGGL(k_nd_sv<T>, dim3(npair * nck + s0), dim3(TILE_THREADS), sh, s, ta, tb, ts, off, fac, X,
                      clo, part, vbuf);
   hipLaunchKernelGGL(k_nd_schur<T>, dim3(npair), dim3(TILE_THREADS), 0, s, ta, tb, off, fac, clo, part);
   const int32_t* slo = vlo + 2 * vstride;
@@ -1647,12 +1682,12 @@ void factor_nd(int ta, int tb, int ts, int maxc, T* part, const int64_t* off, T*
                                      hipStream_t, int);                                            \
   template void launch_potrf_step<T>(int, int, int, T*, int64_t, const int32_t*, const int64_t*,    \
                                      T*, int32_t*, hipStream_t, const int32_t*, const int32_t*, T*, \
-                                     const int32_t*, const int32_t*, int, int);                    \
+                                     const int32_t*, const int32_t*, int, int, T*);                \
   template void launch_xrow<T>(int, const int64_t*, const T*, T*, hipStream_t, const int32_t*,     \
                                const int32_t*, const int32_t*, int);                               \
   template void factor_nd<T>(int, int, int, int, T*, const int64_t*, T*, T*, int32_t*,             \
                              const int32_t*, const int32_t*, const int32_t*, const int32_t*,       \
-                             const int32_t*, int, hipStream_t);                                    \
+                             const int32_t*, int, T*, hipStream_t);                                \
   template void launch_trtri_col<T>(int, int, int, const int32_t*, const int64_t*, const T*, T*,   \
                                     hipStream_t);                                                  \
   template void launch_lauum<T>(int, int, const int32_t*, const int64_t*, const T*, T*, hipStream_t); \

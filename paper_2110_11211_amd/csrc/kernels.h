@@ -180,18 +180,19 @@ void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles,
                        const int64_t* off, T* fac, int32_t* status, hipStream_t s,
                        const int32_t* tlo = nullptr, const int32_t* trb = nullptr, T* X = nullptr,
                        const int32_t* wide = nullptr, const int32_t* vinfo = nullptr, int vstride = 0,
-                       int nviews = 1);
+                       int nviews = 1, T* V = nullptr);
 // Row J of X (tile offset xo: local tile (J, C) at (xo + J, xo + C)).
 template <typename T>
 void launch_xrow(int J, const int64_t* off, const T* fac, T* X, hipStream_t s, const int32_t* tlo,
                  const int32_t* trb, const int32_t* wide, int xo = 0);
 // Factor and inverse of a dissected single coarse matrix (launch_nd_order,
 // launch_nd_views): the two halves' chains concurrently, then the
-// separator.  part: six slots of vstride * maxc tiles.
+// separator.  part: six slots of vstride * maxc tiles; vbuf: ts (ta + tb)
+// tiles of V = L_S,half X_half,half.
 template <typename T>
 void factor_nd(int ta, int tb, int ts, int maxc, T* part, const int64_t* off, T* fac, T* X, int32_t* status,
                const int32_t* nt, const int32_t* clo, const int32_t* vinfo, const int32_t* vlo, const int32_t* vrb,
-               int vstride, hipStream_t s);
+               int vstride, T* vbuf, hipStream_t s);
 template <typename T>
 void launch_trtri_col(int J, int nb, int max_nt, const int32_t* nt, const int64_t* off,
                       const T* L, T* X, hipStream_t s);

@@ -533,7 +533,10 @@ void launch_coarse_env(const Batch& B, int max_nt0, const int32_t* cfnz, int32_t
 //
 // The coarse blocks of the first half of the curve (block index < N0 / 2) and
 // those of the second half couple only through the blocks of the first half
-// that have a stencil neighbour in the second (the separator).  Ordered as
+// that have a stencil neighbour in the second (the separator).  The curve's
+// midpoint splits the grid along a plane (both curves halve the bounding
+// box there); a split elsewhere leaves a ragged interface and a larger
+// separator, so the first half's chain is the shorter one.  Ordered as
 // [first half | second half | separator], the Cholesky factor has no tiles
 // coupling the halves, so the two halves factor as independent chains of
 // column steps, and the separator's rows follow: about half the dependent
@@ -662,6 +665,7 @@ void launch_nd_undo(const Batch& B, const int32_t* backup, int32_t* cperm, int32
 // the first half's tile rows then the separator's, view 1 the second half's
 // then the separator's, view 2 the separator's alone.  Per view v:
 // vinfo[3 v ..] = {rows, columns factored by its chain, first tile column},
+// vinfo[9] = ta + tb,
 // and for its local tile row i: vlo[v * stride + i] = first local tile column
 // (the separator's own chain treats its block as dense), vrb[v * stride + i]
 // = packed index of global tile (row, first column), so that local tile
@@ -674,6 +678,7 @@ __global__ __launch_bounds__(256) void k_nd_views(const int32_t* __restrict__ nd
     vinfo[0] = ta + ts; vinfo[1] = ta; vinfo[2] = 0;
     vinfo[3] = tb + ts; vinfo[4] = tb; vinfo[5] = ta;
     vinfo[6] = ts;      vinfo[7] = ts; vinfo[8] = s0;
+    vinfo[9] = s0;      // columns of the two halves
   }
   for (int i = threadIdx.x; i < ta + ts; i += 256) {
     const int I = i < ta ? i : s0 + (i - ta);

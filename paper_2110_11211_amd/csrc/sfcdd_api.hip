@@ -1299,9 +1299,11 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
           int32_t* vlo = vinfo + 16;
           int32_t* vrb = vlo + 3 * c->max_nt0;
           launch_nd_views(c->status + 13, c->clo, c->max_nt0, vinfo, vlo, vrb, cs);
+          // V = L_S,half X_half,half in the FP64 coarse matrix's region (read
+          // only by the rounding above)
           factor_nd<float>(c->nd[0], c->nd[1], c->nd[2], (int)ceil_div(c->max_nt0, SPLITK), part32, c->dc_off,
                            L32, L32 + c->ctiles * TS2, c->status + 1, c->dc_nt, c->clo, vinfo, vlo, vrb,
-                           c->max_nt0, cs);
+                           c->max_nt0, reinterpret_cast<float*>(c->A0), cs);
         } else {
           factor_batch<float>(G, c->max_nt0, c->dc_nt, c->dc_off, L32, L32 + c->ctiles * TS2, true, false,
                               c->status + 1, G == 1 ? part32 : (float*)nullptr, part32, c->dc_toff, false, cs, 0,
