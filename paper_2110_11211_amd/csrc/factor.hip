@@ -990,8 +990,10 @@ __device__ __forceinline__ void nd_vterm(int K, int C, int nc, int ntb, int xo, 
 // partials of columns >= nc.  V (nullable, views): the step also adds the
 // term K = J - 1 of the separator rows' V = L_S,half X_half,half (row J - 1
 // of X and column J - 1 of L are final by then; s0 = vinfo[9]), J
-// workgroups after the rows of X.
-template <typename T>
+// workgroups after the rows of X; that code is in the VT instantiation only
+// (present in the other one, it slowed the large grid's setup by 6 ms beside
+// the batched factorisation although never executed).
+template <typename T, bool VT>
 __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T* __restrict__ part,
                                                              int64_t slot_tiles,
                                                              const int32_t* __restrict__ nt,
@@ -1036,8 +1038,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_potrf_step(int J, int maxc, T*
       if (!(wide && *wide > XROW_MAXW)) xrow_tile<T, Env>(J, xr, F, X + off[0] * TS2, sA, sB, ix, xo);
       return;
     }
-    if (V && xr - (J + 1) < J)
-      nd_vterm<T, Env>(J - 1, xr - (J + 1), ncol, ntb, xo, vinfo[9], F, X + off[0] * TS2, V, sA, sB, ix);
+    if constexpr (VT) {
+      if (xr - (J + 1) < J)
+        nd_vterm<T, Env>(J - 1, xr - (J + 1), ncol, ntb, xo, vinfo[9], F, X + off[0] * TS2, V, sA, sB, ix);
+    }
     return;
   }
   __builtin_amdgcn_s_setprio(3);
@@ -1195,10 +1199,15 @@ void launch_potrf_step(int J, int max_nt, int maxc, T* part, int64_t slot_tiles,
   const int nc = (J + SPLITK - 1) / SPLITK;   // chunks of column J + 2
   const int nwg = m + (m > 1 ? (m - 1) * nc : 0);
   const size_t sh = std::max(2 * TS * LdsV<T>::v * sizeof(T), diag_lds_bytes<T>());
-  static bool once = (allow_lds(k_potrf_step<T>, sh), true);
+  static bool once = (allow_lds(k_potrf_step<T, false>, sh), allow_lds(k_potrf_step<T, true>, sh), true);
   (void)once;
-  hipLaunchKernelGGL(k_potrf_step<T>, dim3(nwg + (X ? J + 1 : 0) + (X && V ? J : 0), nviews), dim3(TILE_THREADS),
-                     sh, s, J, maxc, part, slot_tiles, nt, off, fac, status, tlo, trb, X, wide, vinfo, vstride, V);
+  const dim3 grid(nwg + (X ? J + 1 : 0) + (X && V ? J : 0), nviews);
+  if (X && V)
+    hipLaunchKernelGGL((k_potrf_step<T, true>), grid, dim3(TILE_THREADS), sh, s, J, maxc, part, slot_tiles, nt, off,
+                       fac, status, tlo, trb, X, wide, vinfo, vstride, V);
+  else
+    hipLaunchKernelGGL((k_potrf_step<T, false>), grid, dim3(TILE_THREADS), sh, s, J, maxc, part, slot_tiles, nt, off,
+                       fac, status, tlo, trb, X, wide, vinfo, vstride, (T*)nullptr);
 }
 
 template <typename T>

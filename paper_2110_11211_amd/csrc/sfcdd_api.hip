@@ -1192,68 +1192,82 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     launch_coarse_fnz(B, c->nbr, c->cfnz, cs);
     launch_coarse_env(B, c->max_nt0, c->cfnz, c->clo, c->crb, c->status + 12, nd_try ? c->status + 13 : nullptr,
                       cs);
-    // the dissection's tiles and the halves' envelope width, read back once
-    // the subdomain side is enqueued
+    // the dissection's tiles and the halves' envelope width, read back before
+    // the rest of the coarse setup is enqueued (the subdomain side follows it:
+    // enqueued first, a batched factorisation that fills every CU would hold
+    // back the coarse chain's first steps)
     if (nd_try)
       HIPCHK(c, hipMemcpyAsync(reinterpret_cast<unsigned char*>(c->host_scal) + c->hnd_off, c->status + 12, 16,
                                hipMemcpyDeviceToHost, cs));
     HIPCHK(c, hipGetLastError());
   }
 
-  // local elimination order and tile envelopes, then the local matrices
-  // A_i = R_i A R_i^T in that order (only the envelope tiles are written)
-  HIPCHK(c, hipMemsetAsync(c->gtiles, 0, c->r_gtiles.bytes, s));
-  HIPCHK(c, hipMemsetAsync(c->ztile, 0, c->r_ztile.bytes, s));
-  const int omode = c->local_order == SFCDD_ORDER_DIAGONAL ? 2 : c->local_order == SFCDD_ORDER_CURVE ? 1 : 0;
-  // key levels: at most the sum of the grid extents of the widest grid
-  int kcap = 1;
-  for (int k = 0; k < G; ++k) {
-    int r = 1;
-    for (int j = 0; j < c->grid[k].desc.d; ++j) r += c->grid[k].desc.n[j] - 1;
-    kcap = std::max(kcap, std::min(r, ORDER_MAX_KEYS));
-  }
-  launch_local_order(B, omode, kcap, c->max_nt, c->d_ta, c->d_Ni, c->d_nt, c->d_xoff, c->d_doff, c->sfc_index, c->nbr,
-                     c->lperm, c->liperm, c->tlo, c->trb, c->gtiles, s);
-  if (c->fdtype == SFCDD_FP32)
-    launch_assemble_local<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm, c->liperm,
-                                 c->tlo, c->trb, c->nbr, c->max_nt, (float*)c->fac, s);
-  else
-    launch_assemble_local<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm,
-                                  c->liperm, c->tlo, c->trb, c->nbr, c->max_nt, (double*)c->fac, s);
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipEventRecord(ev[3], s));
-
-  // factor once (Sec. 3.1).  The two-column batched kernel (380 registers
-  // per lane in FP32) is the fastest alone; the one-column kernel (264)
-  // leaves more room on the SIMDs for the concurrent coarse setup.
-  const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
-  double fine_work = 0.0;
-  for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
-  const double coarse_work = G == 1 ? std::pow((double)c->max_N0, 3.0) : 0.0;
-  const bool pair = c->factor_pair >= 0 ? c->factor_pair != 0
-                                         : (c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work);
-  // The light kernel (one row per panel step, no prefetch in the diagonal
-  // update) for matrices of at most four tile rows, whose small LDS staging
-  // lets several workgroups share a CU, and beside a single grid's coarse
-  // chain at least twice as long as a subdomain's: its registers and LDS
-  // leave room on every CU for the chain's workgroups, which set the
-  // setup's critical path.
-  const bool chain_bound = G == 1 && !c->coarse_iter && c->max_nt0 >= 2 * c->max_nt;
-  const int rows = c->factor_rows > 0 ? c->factor_rows : ((c->max_nt <= 4 || chain_bound) ? 1 : 0);
-  if (c->fdtype == SFCDD_FP32)
-    factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
-                        c->status, (float*)nullptr, (float*)nullptr, nullptr, pair && rows != 1, s, rows,
-                        c->d_xoff, c->tlo, c->trb);
-  else
-    factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
-                         c->status, (double*)nullptr, (double*)nullptr, nullptr, pair && rows != 1, s, rows,
-                         c->d_xoff, c->tlo, c->trb);
-  // the substitution kernel sweeps with the unit block-lower factor
-  if (!inv) {
+  // The subdomain side: enqueued before the coarse chain (whose first steps a
+  // batched factorisation filling every CU would otherwise hold back), or,
+  // while the dissection's readback is awaited, before that wait.
+  bool pair = false;
+  int rows = 0;
+  auto enqueue_fine = [&]() -> sfcdd_status {
+    // local elimination order and tile envelopes, then the local matrices
+    // A_i = R_i A R_i^T in that order (only the envelope tiles are written)
+    HIPCHK(c, hipMemsetAsync(c->gtiles, 0, c->r_gtiles.bytes, s));
+    HIPCHK(c, hipMemsetAsync(c->ztile, 0, c->r_ztile.bytes, s));
+    const int omode = c->local_order == SFCDD_ORDER_DIAGONAL ? 2 : c->local_order == SFCDD_ORDER_CURVE ? 1 : 0;
+    // key levels: at most the sum of the grid extents of the widest grid
+    int kcap = 1;
+    for (int k = 0; k < G; ++k) {
+      int r = 1;
+      for (int j = 0; j < c->grid[k].desc.d; ++j) r += c->grid[k].desc.n[j] - 1;
+      kcap = std::max(kcap, std::min(r, ORDER_MAX_KEYS));
+    }
+    launch_local_order(B, omode, kcap, c->max_nt, c->d_ta, c->d_Ni, c->d_nt, c->d_xoff, c->d_doff, c->sfc_index, c->nbr,
+                       c->lperm, c->liperm, c->tlo, c->trb, c->gtiles, s);
     if (c->fdtype == SFCDD_FP32)
-      launch_unit_lower<float>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (float*)c->fac, s);
+      launch_assemble_local<float>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm, c->liperm,
+                                   c->tlo, c->trb, c->nbr, c->max_nt, (float*)c->fac, s);
     else
-      launch_unit_lower<double>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (double*)c->fac, s);
+      launch_assemble_local<double>(B, c->d_ta, c->d_Ni, c->d_nt, c->d_off, c->d_xoff, c->d_doff, c->lperm,
+                                    c->liperm, c->tlo, c->trb, c->nbr, c->max_nt, (double*)c->fac, s);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(ev[3], s));
+
+    // factor once (Sec. 3.1).  The two-column batched kernel (380 registers
+    // per lane in FP32) is the fastest alone; the one-column kernel (264)
+    // leaves more room on the SIMDs for the concurrent coarse setup.
+    const bool inv = c->local_solver == SFCDD_LOCAL_INVERSE;
+    double fine_work = 0.0;
+    for (int i = 0; i < Pt; ++i) fine_work += std::pow((double)c->Ni[i], 3.0);
+    const double coarse_work = G == 1 ? std::pow((double)c->max_N0, 3.0) : 0.0;
+    pair = c->factor_pair >= 0 ? c->factor_pair != 0
+                               : (c->fdtype == SFCDD_FP64 || c->coarse32 || coarse_work < 0.15 * fine_work);
+    // The light kernel (one row per panel step, no prefetch in the diagonal
+    // update) for matrices of at most four tile rows, whose small LDS staging
+    // lets several workgroups share a CU, and beside a single grid's coarse
+    // chain at least twice as long as a subdomain's: its registers and LDS
+    // leave room on every CU for the chain's workgroups, which set the
+    // setup's critical path.
+    const bool chain_bound = G == 1 && !c->coarse_iter && c->max_nt0 >= 2 * c->max_nt;
+    rows = c->factor_rows > 0 ? c->factor_rows : ((c->max_nt <= 4 || chain_bound) ? 1 : 0);
+    if (c->fdtype == SFCDD_FP32)
+      factor_batch<float>(Pt, c->max_nt, c->d_nt, c->d_off, (float*)c->fac, (float*)c->facX, inv, inv,
+                          c->status, (float*)nullptr, (float*)nullptr, nullptr, pair && rows != 1, s, rows,
+                          c->d_xoff, c->tlo, c->trb);
+    else
+      factor_batch<double>(Pt, c->max_nt, c->d_nt, c->d_off, (double*)c->fac, (double*)c->facX, inv, inv,
+                           c->status, (double*)nullptr, (double*)nullptr, nullptr, pair && rows != 1, s, rows,
+                           c->d_xoff, c->tlo, c->trb);
+    // the substitution kernel sweeps with the unit block-lower factor
+    if (!inv) {
+      if (c->fdtype == SFCDD_FP32)
+        launch_unit_lower<float>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (float*)c->fac, s);
+      else
+        launch_unit_lower<double>(Pt, c->max_nt, c->d_nt, c->d_off, c->d_xoff, c->tlo, c->trb, (double*)c->fac, s);
+    }
+    return SFCDD_OK;
+  };
+  if (nd_try) {
+    const sfcdd_status fst = enqueue_fine();
+    if (fst != SFCDD_OK) return fst;
   }
   {
     const hipStream_t cs = c->side;
@@ -1341,6 +1355,11 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
     HIPCHK(c, hipEventRecord(join, cs));
   }
 
+
+  if (!nd_try) {
+    const sfcdd_status fst = enqueue_fine();
+    if (fst != SFCDD_OK) return fst;
+  }
   c->info.factor_pair = pair && rows != 1 ? 1 : 0;
   c->info.factor_rows = rows > 0 ? rows : (c->fdtype == SFCDD_FP32 ? 3 : 2);
   HIPCHK(c, hipGetLastError());
