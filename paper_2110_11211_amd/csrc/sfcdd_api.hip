@@ -649,8 +649,11 @@ sfcdd_status plan(sfcdd_ctx* c, int G, const sfcdd_params* params) {
   c->r_d0 = pl.take((size_t)std::max<int64_t>(c->N0tot, c->c0len) * 8);
   c->r_cpart = pl.take((size_t)c->cparts * 8);
   // split-K partials of the single-matrix factorisation (three slots), later
-  // reused by the triangular inversion
-  const size_t kparts = G == 1 ? 3 * (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) : 0;
+  // reused by the triangular inversion; a dissected coarse matrix takes six
+  // (three per half's chain) and V (at most nt0^2 / 8 tiles) after them
+  const size_t kparts = G == 1 ? 6 * (size_t)c->max_nt0 * ceil_div(c->max_nt0, SPLITK) +
+                                     ceil_div((int64_t)c->max_nt0 * c->max_nt0, 8)
+                               : 0;
   c->r_cpartk = pl.take(std::max(kparts, (size_t)c->ctinv) * TS2 * 8);
   c->r_cmeta = pl.take((size_t)G * (5 * 8 + 2 * 4));
   c->r_cgid = pl.take(2 * c->N0tot);
@@ -877,7 +880,7 @@ void coarse_solve(sfcdd_ctx* c, const double* v, const int32_t* mask = nullptr) 
                                c->cpart, c->d0, mask, c->stream, c->nd[2] > 0 ? c->status + 13 : nullptr);
   else
     launch_coarse_apply<double>(c->G, c->max_nt0, bm, c->dc_n, c->dc_doff, c->X0, c->c0, c->cy, c->cpart,
-                                c->d0, mask, c->stream);
+                                c->d0, mask, c->stream, c->nd[2] > 0 ? c->status + 13 : nullptr);
 }
 
 // Subdomain solves d_i = A_i^{-1} R_i w into dbuf (Alg. 2, first two steps).
@@ -1159,11 +1162,12 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
   }
   HIPCHK(c, hipEventRecord(fork, s));
   HIPCHK(c, hipStreamWaitEvent(c->side, fork, 0));
-  // One-level dissection of a single dense coarse matrix with FP32 factor and
-  // inverse (the chains' split-K slots then hold two views' worth of FP32
-  // tiles in the FP64-sized region).
+  // One-level dissection of a single dense coarse matrix whose factor and
+  // inverse have the same precision (FP32 beside FP32 subdomain factors when
+  // the coarse matrix is well conditioned, else FP64 throughout; not the FP64
+  // factor rounded to an FP32 inverse).
   const int n0s = c->grid[0].desc.N0;
-  const bool nd_try = G == 1 && !c->coarse_iter && c->coarse_x32 && c->coarse32 &&
+  const bool nd_try = G == 1 && !c->coarse_iter && (!c->coarse_x32 || c->coarse32) &&
                       c->coarse_split == SFCDD_SPLIT_AUTO && c->max_nt0 >= 16;
   int32_t* const nd_sep = reinterpret_cast<int32_t*>(c->cy);
   c->nd[0] = c->nd[1] = c->nd[2] = 0;
@@ -1331,6 +1335,15 @@ sfcdd_status setup_device(sfcdd_ctx* c) {
         launch_trtri_rec<float>(G, c->max_nt0, c->dc_nt, c->dc_off, c->dc_toff, L32, L32 + c->ctiles * TS2,
                                 part32, cs, c->dc_xoff, c->clo);
       }
+    } else if (c->nd[2] > 0) {
+      int32_t* vinfo = reinterpret_cast<int32_t*>(c->d0);
+      int32_t* vlo = vinfo + 16;
+      int32_t* vrb = vlo + 3 * c->max_nt0;
+      launch_nd_views(c->status + 13, c->clo, c->max_nt0, vinfo, vlo, vrb, cs);
+      const int maxc = (int)ceil_div(c->max_nt0, SPLITK);
+      factor_nd<double>(c->nd[0], c->nd[1], c->nd[2], maxc, c->cpartk, c->dc_off, c->A0, c->X0, c->status + 1,
+                        c->dc_nt, c->clo, vinfo, vlo, vrb, c->max_nt0,
+                        c->cpartk + 6 * (int64_t)c->max_nt0 * maxc * TS2, cs);
     } else {
       factor_batch<double>(G, c->max_nt0, c->dc_nt, c->dc_off, c->A0, c->X0, true, false, c->status + 1,
                            G == 1 ? c->cpartk : (double*)nullptr, c->cpartk, c->dc_toff, false, cs, 0,

@@ -51,7 +51,8 @@ def test_split_apply_matches_oracle(levels, P, gamma, q, variant):
     O = OracleSchwarz(g, P, gamma, q=q, variant=variant, curve="hilbert")
     r = uniform_pm1(41, g.N)
     out = {}
-    for name, kw in [("split", {}), ("off", {"coarse_split": "off"}), ("fp64", {"coarse_precision": "fp64"})]:
+    for name, kw in [("split", {}), ("off", {"coarse_split": "off"}),
+                     ("fp64", {"coarse_precision": "fp64", "coarse_split": "off"})]:
         S = _solver(levels, P, gamma, q, variant=variant, **kw)
         split = S.info()["coarse_split"]
         if name == "split":
@@ -93,10 +94,31 @@ def test_split_solve(levels, P, gamma, q):
     torch.cuda.empty_cache()
 
 
-def test_split_off_with_fp64_factors():
-    """The dissection is for single grids with FP32 coarse factor and inverse:
-    FP64 factors keep the undissected order."""
-    announce("coarse split fp64")
-    S = m.SFCSchwarz(levels=(6, 5, 5), P=256, gamma=Fraction(1, 2), q=4, factor_dtype="fp64", curve="hilbert")
-    assert S.info()["coarse_split"] == [0, 0, 0]
-    S.close()
+FP64_TOL = 1e-12
+
+
+@pytest.mark.parametrize("variant", ["additive", "balanced"])
+@pytest.mark.parametrize("levels,P,gamma,q", CASES)
+def test_split_fp64_matches_oracle(levels, P, gamma, q, variant):
+    """With FP64 factors the coarse matrix is dissected as well, and then the
+    dissected factorisation, the separator's Schur complement and the block
+    inverse are checked to FP64 rounding: the application matches the
+    oracle's, and the undissected one, to 1e-12."""
+    announce("coarse split fp64", levels, P, gamma, q, variant)
+    g = Grid(levels=levels)
+    O = OracleSchwarz(g, P, gamma, q=q, variant=variant, curve="hilbert")
+    r = uniform_pm1(47, g.N)
+    out = {}
+    for name, split in [("split", "auto"), ("off", "off")]:
+        S = m.SFCSchwarz(levels=levels, P=P, gamma=gamma, q=q, factor_dtype="fp64", curve="hilbert",
+                         variant=variant, coarse_split=split)
+        got = S.info()["coarse_split"]
+        assert (got[2] > 0) if split == "auto" else got == [0, 0, 0], got
+        out[name] = host(S.apply(dvec(r)))
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    e = relerr(out["split"], O.apply(r))
+    d = relerr(out["split"], out["off"])
+    print(f"coarse split fp64 {levels} {variant}: vs oracle {e:.2e}, vs undissected {d:.2e}", flush=True)
+    assert e <= FP64_TOL and d <= FP64_TOL
