@@ -653,6 +653,40 @@ void launch_dot(const Batch& B, const double* a, const double* b, const double* 
   hipLaunchKernelGGL(k_dot, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, a, b, c, partials);
 }
 
+// out = a + R_0^T d0 (the deflated operator's last step) fused with the dot
+// products that follow it in CG, out . b and (c non-null) out . c, with
+// k_dot's launch shape, traversal and partials: the same sums, bit for bit,
+// one launch fewer per iteration.
+__global__ __launch_bounds__(RED_THREADS) void k_combine_dot(Batch B, const double* __restrict__ d0,
+                                                             const double* __restrict__ a,
+                                                             double* __restrict__ out,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ c,
+                                                             double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const GridDesc& g = B.grids[blockIdx.y];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = g.goff + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.goff + g.N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double h = a[i] + d0[g.c0off + B.cperm[g.c0off + coarse_block(i - g.goff, g)]];
+    out[i] = h;
+    s0 += h * b[i];
+    if (c) s1 += h * c[i];
+  }
+  const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const double r0 = block_sum(s0, sh);
+  if (threadIdx.x == 0) partials[slot] = r0;
+  if (c) {
+    const double r1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) partials[(int64_t)B.G * gridDim.x + slot] = r1;
+  }
+}
+
+void launch_combine_dot(const Batch& B, const double* d0, const double* a, double* out, const double* b,
+                        const double* c, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine_dot, dim3(B.rbx, B.G), dim3(RED_THREADS), 0, s, B, d0, a, out, b, c, partials);
+}
+
 // Second reduction stage plus the scalar recurrences of CG, one block per grid.
 __global__ __launch_bounds__(RED_THREADS) void k_finalize(Batch B, int mode,
                                                           const double* __restrict__ partials, int np,

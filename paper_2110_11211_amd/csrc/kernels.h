@@ -277,6 +277,10 @@ void launch_ic_dir(int first, int it, int64_t n0, int nt, double tol2, const dou
                    const double* dagg, double* sc, const double* z1, double* p, int32_t* flag, hipStream_t s);
 void launch_combine(const Batch& B, int mode, const double* d0, const double* a, const double* b,
                     double* out, hipStream_t s);
+// out = a + R_0^T d0 and the partials of out . b (and out . c, c non-null)
+// in launch_dot's layout.
+void launch_combine_dot(const Batch& B, const double* d0, const double* a, double* out, const double* b,
+                        const double* c, double* partials, hipStream_t s);
 
 // ---- BLAS-1 and scalars (per grid) -----------------------------------------
 void launch_dot(const Batch& B, const double* a, const double* b, const double* c,

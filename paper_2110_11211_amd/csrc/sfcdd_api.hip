@@ -939,7 +939,8 @@ int spmv(sfcdd_ctx* c, int mode, const double* x, double* y, const double* b, do
   return launch_spmv(c->batch(), mode, c->nbr, x, y, b, partials, c->stream);
 }
 
-void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask);
+void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask, const double* db = nullptr,
+                  const double* dc = nullptr);
 
 // h = C^{-1} g in curve order (Alg. 2; balanced form eq. balSW).
 // mask (nullable): solver flags; grids that are not updating may skip the
@@ -972,14 +973,20 @@ void apply_s(sfcdd_ctx* c, const double* g, double* h, const int32_t* mask = nul
 // because R_0 A (I - F A) = 0, so the balanced iteration runs on this form.
 // Unlike y - F A y (the same operator in exact arithmetic), it also corrects
 // the coarse component that rounding adds to r_k over the iterations, which
-// would otherwise stall the residual once it reaches that level.
-void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask) {
+// would otherwise stall the residual once it reaches that level.  db
+// (nullable): the last step also forms the partials of h . db and h . dc
+// (launch_dot's layout).
+void apply_s_defl(sfcdd_ctx* c, const double* r, double* h, const int32_t* mask, const double* db,
+                  const double* dc) {
   const Batch B = c->batch();
   double *y = c->vec[V_Y], *v = c->vec[V_V];
   fine_apply(c, r, y, mask);                                   // y = C1^{-1} r
   spmv(c, 3, y, v, r, nullptr);                                // v = r - A y
   coarse_solve(c, v, mask);                                    // d0 = A0^{-1} R0 (r - A y)
-  launch_combine(B, COMB_ADD_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y + F (r - A y)
+  if (db)  // h = y + F (r - A y), with the partials of h . db (and h . dc)
+    launch_combine_dot(B, c->d0, y, h, db, dc, c->partials, c->stream);
+  else
+    launch_combine(B, COMB_ADD_PROLONG, c->d0, y, nullptr, h, c->stream);  // h = y + F (r - A y)
 }
 
 // Inner step statistics of the latest iterative coarse solve, from the
@@ -1921,6 +1928,16 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
     if (proj) apply_s_defl(c, g, h, c->active);
     else apply_s(c, g, h, c->active);
   };
+  // h = C^{-1} g and the partials of h . db (and h . dc): the deflated
+  // operator forms them in its last launch
+  auto precond_dot = [&](const double* g, double* h, const double* db, const double* dc) {
+    if (proj) {
+      apply_s_defl(c, g, h, c->active, db, dc);
+    } else {
+      apply_s(c, g, h, c->active);
+      launch_dot(c->batch(), h, db, dc, c->partials, c->stream);
+    }
+  };
   const hipStream_t s = c->stream;
   const int64_t N = c->Ntot;
   const int G = c->G;
@@ -2102,8 +2119,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
       if ((st = upload_scal())) return st;
       if ((st = write_active(c, flags))) return st;
       // z = C^{-1} r, p = z
-      precond(r, z);
-      launch_dot(B, r, z, nullptr, c->partials, s);
+      precond_dot(r, z, r, nullptr);
       launch_finalize(B, FIN_RZ_INIT, c->partials, c->scal, c->active, s);
       launch_copy(N, z, p, s);
       for (;;) {
@@ -2118,8 +2134,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
         ++it;
         if (it < max_iter) {
           // next direction, enqueued before the host has seen the residuals
-          precond(r, z);
-          launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
+          precond_dot(r, z, r, flex ? q : nullptr);
           launch_finalize(B, fin_rz, c->partials, c->scal, c->active, s);
           launch_update_p(B, c->scal, c->active, p, z, s);
         }
@@ -2171,8 +2186,7 @@ sfcdd_status sfcdd_solve(sfcdd_ctx* c, const double* b_in, double* x_io, double 
           if (any_restart) {
             // z = C^{-1} r and p = z for the restarted grids only
             if ((st = write_active(c, pass))) return st;
-            precond(r, z);
-            launch_dot(B, z, r, flex ? q : nullptr, c->partials, s);
+            precond_dot(r, z, r, flex ? q : nullptr);
             launch_finalize(B, fin_rz, c->partials, c->scal, c->active, s);
             launch_update_p(B, c->scal, c->active, p, z, s);
           }
