@@ -450,6 +450,21 @@ template <typename T> struct TrmvLanes {
   static constexpr int NQ = 16 / RPL;       // loads per wave for its 16 rows
 };
 
+// Workgroup index -> (tile T, chunk c) over only the chunks that exist: tile
+// T has T / TRMV_CH + 1 of them (rows: chunks left of the diagonal; columns,
+// with T = nt - 1 - K: chunks below it).  Tiles come in groups of TRMV_CH
+// sharing a chunk count g + 1; 4 g (g + 1) workgroups (TRMV_CH = 8) precede
+// group g.
+static_assert(TRMV_CH == 8, "trmv_chunk assumes groups of eight tiles");
+__device__ __forceinline__ void trmv_chunk(int idx, int& T, int& c) {
+  int g = (int)((sqrtf(1.0f + (float)idx) - 1.0f) * 0.5f);
+  while (4 * (g + 1) * (g + 2) <= idx) ++g;
+  while (g > 0 && 4 * g * (g + 1) > idx) --g;
+  const int rem = idx - 4 * g * (g + 1);
+  T = TRMV_CH * g + rem / (g + 1);
+  c = rem % (g + 1);
+}
+
 // Rows: part[I][c] = sum_{K in chunk c, K <= I} X_IK v_K.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const int32_t* __restrict__ active,
@@ -459,7 +474,8 @@ __global__ __launch_bounds__(256) void k_trmv_rows(BatchMeta bm, int nchx, const
   typedef TrmvLanes<T> LN;
   typedef typename Vec16<T>::type V;
   const int b = blockIdx.y, ntb = bm.nt[b];
-  const int I = blockIdx.x / nchx, c = blockIdx.x % nchx;
+  int I, c;
+  trmv_chunk(blockIdx.x, I, c);
   const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
   const int k0 = c * TRMV_CH;
   if (I >= ntb || c >= nch || k0 > I || (active && !act_updating(active[b]))) return;
@@ -511,7 +527,9 @@ __global__ __launch_bounds__(256) void k_trmv_cols(BatchMeta bm, int nchx, const
   typedef TrmvLanes<T> LN;
   typedef typename Vec16<T>::type V;
   const int b = blockIdx.y, ntb = bm.nt[b];
-  const int K = blockIdx.x / nchx, c = blockIdx.x % nchx;
+  int Kr, c;
+  trmv_chunk(blockIdx.x, Kr, c);
+  const int K = nchx * TRMV_CH - 1 - Kr;  // nchx * TRMV_CH >= every grid's nt
   const int nch = (ntb + TRMV_CH - 1) / TRMV_CH;
   const int i0 = K + c * TRMV_CH;
   if (K >= ntb || c >= nch || i0 >= ntb || (active && !act_updating(active[b]))) return;
@@ -588,7 +606,8 @@ void launch_coarse_apply(int nb, int max_nt, const BatchMeta& bm, const int32_t*
                          const int64_t* doff, const T* X, const double* v, double* ytmp,
                          double* part, double* out, const int32_t* active, hipStream_t s, const int32_t* nd) {
   const int nchx = (max_nt + TRMV_CH - 1) / TRMV_CH;
-  const dim3 grid(max_nt * nchx, nb);
+  // the existing chunks of nchx groups of TRMV_CH tiles (trmv_chunk)
+  const dim3 grid(4 * nchx * (nchx + 1), nb);
   hipLaunchKernelGGL(k_trmv_rows<T>, grid, dim3(256), 0, s, bm, nchx, active, X, v, part, nd);
   hipLaunchKernelGGL(k_trmv_reduce<0>, dim3(max_nt, nb), dim3(TS), 0, s, bm, n, doff, part, ytmp);
   hipLaunchKernelGGL(k_trmv_cols<T>, grid, dim3(256), 0, s, bm, nchx, active, X, ytmp, part, nd);
